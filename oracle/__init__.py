@@ -67,7 +67,7 @@ def _load():
         lib.oracle_inner.argtypes = [dp, dp, ctypes.c_int, dp]
         lib.oracle_expval_pauli.argtypes = [dp, ctypes.c_int, ctypes.c_char_p, ip, ctypes.c_int, dp]
         for f in ("oracle_apply_matrix", "oracle_move_x", "oracle_move_swap", "oracle_inner",
-                  "oracle_expval_pauli", "oracle_version"):
+                  "oracle_expval_pauli", "oracle_version", "oracle_num_threads"):
             getattr(lib, f).restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -93,7 +93,7 @@ def _check(rc: int, what: str):
 # ---------------------------------------------------------------------------
 # gate definitions
 # ---------------------------------------------------------------------------
-_R2 = 1.0 / math.sqrt(2.0)
+_R2 = math.sqrt(0.5)  # correctly rounded 2^(-1/2), the H entry
 
 
 def gate_matrix(name: str, params: Sequence[float] = (), matrix=None) -> np.ndarray:
@@ -143,6 +143,11 @@ def n_targets(name: str, matrix=None) -> int:
 # ---------------------------------------------------------------------------
 # state operations
 # ---------------------------------------------------------------------------
+def num_threads() -> int:
+    """OpenMP threads the oracle's group loops use."""
+    return int(_load().oracle_num_threads())
+
+
 def zero_state(n: int) -> np.ndarray:
     psi = np.zeros(1 << n, dtype=np.complex128)
     psi[0] = 1.0

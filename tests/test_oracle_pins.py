@@ -273,7 +273,7 @@ def test_norm_preserved_random_circuits():
 def test_ghz_bit_exact(n):
     psi = oracle.run_circuit(oracle.zero_state(n), W.ghz_ops(n))
     ref = np.zeros(1 << n, dtype=np.complex128)
-    ref[0] = ref[-1] = 1.0 / math.sqrt(2.0)
+    ref[0] = ref[-1] = math.sqrt(0.5)  # fl(2^(-1/2)): H entries times exact 1s and 0s
     assert np.array_equal(psi, ref)
 
 
