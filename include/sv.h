@@ -1,0 +1,254 @@
+/*
+ * sv.h -- C ABI of libsv, a state-vector gate engine for AMD Instinct MI355X
+ * (gfx950).
+ *
+ * Method: Kang & Ryu, "PennyLane-Lightning MPI: a massively scalable quantum
+ * circuit simulator based on distributed computing in CPU clusters"
+ * (arXiv 2508.13615).  Sec. 2 states the problem this library solves on one
+ * device: an N-qubit state is 2^N complex amplitudes, gates are small logic
+ * matrices (at most 8x8) "conducted to" qubit indices, and only the non-zero
+ * elements of a gate's matrix are used, so each gate gets its own index- and
+ * gate-specific routine: permutation gates move amplitudes, diagonal gates
+ * multiply a subset in place, a control bit only selects where a gate acts.
+ * Sec. 3.1 compares such routines with the "general approach", a dense
+ * matrix-vector product, which is exported here as sv_apply_general.
+ *
+ * Conventions for every entry point:
+ *   - Qubit q is bit q (weight 2^q) of the amplitude index (Sec. 2 numbers
+ *     qubits from zero; the first L are the local ones of a block partition,
+ *     i.e. the low bits).
+ *   - Amplitudes are interleaved (re, im): complex128 = two doubles,
+ *     complex64 = two floats, contiguous, 2^N of them.
+ *   - A k-qubit matrix argument is a HOST array of 2 * 4^k doubles: row-major
+ *     2^k x 2^k, interleaved complex, with row/column index
+ *     r = sum_j bit_{targets[j]} * 2^(k-1-j) (the first-listed target is the
+ *     most significant bit).  For a complex64 state it is rounded to float
+ *     once, on the host.
+ *   - Controls are 1-controls: the gate acts only where every control bit is 1.
+ *   - Rotations are exp(-i th P / 2) for P in {X, Y, Z}; PHASE(phi) is
+ *     diag(1, e^{i phi}).
+ *   - Host arrays passed in are read during the call only; the library keeps
+ *     no pointer to them.
+ *   - Every call validates its arguments on the host before any device work.
+ *     On a validation failure nothing is launched and nothing is modified;
+ *     the status says why and sv_last_error() returns a message.
+ *   - Device work is queued on the state's HIP stream and is asynchronous
+ *     unless the entry point returns a host value (then it synchronises that
+ *     stream).  A fault in a queued kernel is reported as SV_ERR_HIP by the
+ *     next synchronising call.
+ *   - Calls on one state are not thread-safe with respect to each other;
+ *     sv_last_error() is per thread.
+ */
+#ifndef SV_ABI_H_INCLUDED
+#define SV_ABI_H_INCLUDED
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SV_MAX_QUBITS 40   /* validation limit; allocation fails earlier if HBM is short */
+#define SV_MAX_CONTROLS 8
+#define SV_MAX_GENERAL_K 3 /* dense baseline: up to 8x8 (Sec. 2: logic matrices up to 8x8) */
+#define SV_OP_MAX_QUBITS 10
+
+typedef struct sv_state_s* sv_state;
+typedef struct sv_circuit_s* sv_circuit;
+typedef struct sv_batch_s* sv_batch;
+
+typedef enum { SV_C64 = 1, SV_C128 = 2 } sv_dtype;
+
+typedef enum {
+    SV_OK = 0,
+    SV_ERR_ARG = 1,         /* malformed argument (null pointer, bad size, bad enum) */
+    SV_ERR_QUBIT = 2,       /* qubit index out of range or repeated */
+    SV_ERR_OOM = 3,         /* device allocation failed */
+    SV_ERR_HIP = 4,         /* HIP runtime error (launch or earlier asynchronous fault) */
+    SV_ERR_UNSUPPORTED = 5, /* valid request this build does not implement */
+    SV_ERR_HANDLE = 6       /* null or freed handle */
+} sv_status;
+
+typedef enum {
+    SV_I = 0,
+    SV_X = 1,     /* permutation: with 0/1/2 controls = X / CNOT / Toffoli */
+    SV_Y = 2,
+    SV_Z = 3,     /* diagonal; with controls = CZ, CCZ ... */
+    SV_H = 4,
+    SV_S = 5,
+    SV_T = 6,
+    SV_RX = 7,    /* params[0] = theta */
+    SV_RY = 8,
+    SV_RZ = 9,
+    SV_PHASE = 10, /* params[0] = phi; with one control = controlled phase (QFT) */
+    SV_SWAP = 11, /* two targets; permutation */
+    SV_U2 = 12,   /* matrix gate, one target */
+    SV_U4 = 13    /* matrix gate, two targets */
+} sv_gate;
+
+/* ------------------------------------------------------------------------
+ * State lifecycle and data movement
+ * ------------------------------------------------------------------------ */
+
+/* Allocate a 2^n_qubits state in device memory and set it to |0...0>.
+ * stream: a hipStream_t (NULL = the null stream) on which all work on this
+ * state is queued.  The library owns the memory; release with sv_free.
+ * Errors: SV_ERR_ARG (n_qubits outside [1, SV_MAX_QUBITS], bad dtype, null
+ * out), SV_ERR_OOM (device allocation failed). */
+sv_status sv_alloc(int n_qubits, sv_dtype dtype, void* stream, sv_state* out);
+
+/* Wrap caller-owned device memory (e.g. a torch tensor) holding 2^n_qubits
+ * amplitudes of `dtype`, 16-byte aligned.  The contents are left as they are;
+ * sv_free releases only the handle, never dev_ptr. */
+sv_status sv_wrap(void* dev_ptr, int n_qubits, sv_dtype dtype, void* stream, sv_state* out);
+
+/* Release a handle (and its memory if sv_alloc made it).  Synchronises the
+ * state's stream first.  Later use of the handle returns SV_ERR_HANDLE. */
+sv_status sv_free(sv_state st);
+
+sv_status sv_set_stream(sv_state st, void* stream);
+sv_status sv_get_info(sv_state st, int* n_qubits, int* dtype, void** dev_ptr);
+size_t sv_state_bytes(int n_qubits, sv_dtype dtype); /* 2^n * (8 or 16); 0 if invalid */
+
+/* Set the state to the computational basis state |index>. */
+sv_status sv_set_basis(sv_state st, uint64_t index);
+
+/* Copy the whole state to / from host memory of exactly sv_state_bytes bytes.
+ * Synchronous. */
+sv_status sv_copy_to_host(sv_state st, void* host, size_t bytes);
+sv_status sv_copy_from_host(sv_state st, const void* host, size_t bytes);
+
+/* Device-to-device copy of a whole state (same size and dtype). */
+sv_status sv_copy_state(sv_state dst, sv_state src);
+
+/* Wait for all work queued on the state's stream; reports queued faults. */
+sv_status sv_synchronize(sv_state st);
+
+/* ------------------------------------------------------------------------
+ * Gates (Sec. 2; gate-specific routines)
+ * ------------------------------------------------------------------------ */
+
+/* Apply a named gate to `targets` (1 target, or 2 for SV_SWAP / SV_U4).
+ * params: host array, params[0] read for SV_RX/RY/RZ/PHASE, else may be NULL.
+ * matrix: host 2x2 (SV_U2) or 4x4 (SV_U4) complex matrix, else NULL.
+ * adjoint != 0 applies the gate's inverse (conjugate transpose).
+ * The gate is dispatched by class: X/SWAP are pure amplitude moves
+ * (bit-exact), Z/S/T/PHASE multiply only the amplitudes whose target bit is 1,
+ * RZ is an element-wise phase, H/RX/RY/Y/U2 are paired updates, U4 is a
+ * 4-amplitude update.
+ * Errors: SV_ERR_HANDLE, SV_ERR_ARG (bad gate, nt, missing params/matrix),
+ * SV_ERR_QUBIT (index out of range or repeated). */
+sv_status sv_apply_gate(sv_state st, sv_gate gate, const int* targets, int nt,
+                        const double* params, const double* matrix, int adjoint);
+
+/* As sv_apply_gate, restricted to the amplitudes whose `controls` bits are
+ * all 1 (nc in [0, SV_MAX_CONTROLS]); the work covers only that subset
+ * (Sec. 2: a control only decides which part of the state the gate acts
+ * on).  CNOT = SV_X with one control, Toffoli = SV_X with two, controlled
+ * phase = SV_PHASE with one. */
+sv_status sv_apply_controlled(sv_state st, sv_gate gate, const int* controls, int nc,
+                              const int* targets, int nt, const double* params,
+                              const double* matrix, int adjoint);
+
+/* The general approach of Sec. 3.1: a dense 2^k x 2^k matrix-vector product
+ * on every group of 2^k amplitudes that differ only in `qubits`, k in [1, 3],
+ * with no use of the matrix's structure (CNOT as 4x4, Toffoli as 8x8).  The
+ * baseline the gate-specific routines are measured against. */
+sv_status sv_apply_general(sv_state st, const int* qubits, int k, const double* matrix);
+
+/* ------------------------------------------------------------------------
+ * Measurement (Sec. 2: routines for "measurement processes"; Listing 1 takes
+ * the expectation of a Hamiltonian).  All sums use fp64 with a fixed
+ * two-stage order, so repeated calls return bit-identical values.
+ * ------------------------------------------------------------------------ */
+
+/* <psi|psi> into *out (host).  Synchronous. */
+sv_status sv_norm2(sv_state st, double* out);
+
+/* <psi|P|psi> of one Pauli string: paulis[j] in "IXYZ" acts on qubits[j],
+ * n letters, distinct qubits.  Real part into *out (host).  Synchronous. */
+sv_status sv_expval_pauli(sv_state st, const char* paulis, const int* qubits, int n, double* out);
+
+/* A Pauli-sum observable sum_k coeffs[k] * P_k.  Term k is given by bit masks
+ * over qubits: xmask[k] has the X and Y positions, zmask[k] the Z and Y
+ * positions.  All three arrays are host arrays of n_terms entries.
+ * Diagonal terms (xmask = 0) are evaluated together in one pass; the closed
+ * forms sum_i Z_i and sum_i Z_i Z_{i+1} (unit coefficients) are recognised. */
+typedef struct {
+    int n_terms;
+    const double* coeffs;
+    const uint64_t* xmask;
+    const uint64_t* zmask;
+} sv_obs;
+
+/* sum_k c_k <psi|P_k|psi> into *out (host).  Synchronous. */
+sv_status sv_expval_obs(sv_state st, const sv_obs* obs, double* out);
+
+/* Same value written to device memory out_dev (one double); asynchronous on
+ * the state's stream. */
+sv_status sv_expval_obs_dev(sv_state st, const sv_obs* obs, double* out_dev);
+
+/* ------------------------------------------------------------------------
+ * Circuits and adjoint differentiation (a project addition beyond the
+ * paper, whose Listing 1 differentiates a circuit through autograd without
+ * naming the method).  Method: Jones & Gacon 2020 (arXiv 2009.02823).
+ * ------------------------------------------------------------------------ */
+
+/* One operation of a circuit.  qubits[0 .. n_controls-1] are the controls,
+ * the next n_targets entries the targets.  A rotation / PHASE angle is
+ * params[param_index] when param_index >= 0, else `value`.  matrix: host
+ * pointer for SV_U2 / SV_U4 (read when the circuit is created), else NULL. */
+typedef struct {
+    int32_t gate;
+    int32_t n_controls;
+    int32_t n_targets;
+    int32_t param_index;
+    int32_t qubits[SV_OP_MAX_QUBITS];
+    double value;
+    const double* matrix;
+} sv_op;
+
+/* Validate and copy an op list (matrices included) into a circuit object for
+ * states of n_qubits.  Parameters are bound later, per run.  The circuit
+ * holds a small device table of per-op gate coefficients. */
+sv_status sv_circuit_create(int n_qubits, const sv_op* ops, int n_ops, int n_params, sv_circuit* out);
+sv_status sv_circuit_free(sv_circuit c);
+
+/* Apply the circuit to st (in place) with host parameters params[n_params]. */
+sv_status sv_circuit_apply(sv_circuit c, sv_state st, const double* params);
+
+/* Adjoint gradient of E(th) = <psi(th)|O|psi(th)>, psi(th) = U(th)|psi_in>.
+ * On entry psi holds |psi_in> (not modified in the end beyond rounding: the
+ * reverse sweep un-applies every gate).  lam is a work state of the same size
+ * and dtype (its contents are overwritten).  E goes to *expval_out and
+ * dE/dparams[j] to grad_out[j] (host arrays, n_params entries; parameters used
+ * by several ops get the sum).  The gradient of an op with generator G
+ * (U = exp(-i th G / 2)) is Im <lambda|G|phi> at that op, as in the reference
+ * method; PHASE uses its projector generator.  Synchronous.
+ * Errors: as sv_circuit_apply, plus SV_ERR_ARG for a mismatched lam. */
+sv_status sv_adjoint_grad(sv_circuit c, sv_state psi, sv_state lam, const double* params,
+                          const sv_obs* obs, double* expval_out, double* grad_out);
+
+/* ------------------------------------------------------------------------
+ * Launch shapes.  Kernel classes: 0 paired (permutation / butterfly),
+ * 1 subset phase, 2 element-wise diagonal, 3 two-target, 4 general.  Tier by
+ * the lowest qubit a gate touches: 0 (< 3), 1 (< 6), 2 (>= 6).  block is a
+ * multiple of 64 in [64, 1024]; unroll (groups per thread) is 1, 2, 4 or 8.
+ * The table is process-wide; set it from one thread before launching work.
+ * Errors: SV_ERR_ARG for a bad key or shape.
+ * ------------------------------------------------------------------------ */
+sv_status sv_tune_set(int kernel_class, int dtype, int tier, int block, int unroll);
+sv_status sv_tune_get(int kernel_class, int dtype, int tier, int* block, int* unroll);
+
+/* ------------------------------------------------------------------------
+ * Diagnostics
+ * ------------------------------------------------------------------------ */
+const char* sv_last_error(void);
+const char* sv_status_string(sv_status s);
+int sv_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SV_ABI_H_INCLUDED */

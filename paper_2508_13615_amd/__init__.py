@@ -1,0 +1,247 @@
+"""MI355X-native state-vector gate engine: Python binding over libsv (HIP).
+
+Argument marshalling only: every step of gate application, measurement and
+differentiation runs in libsv's HIP kernels (include/sv.h).  torch provides the
+device memory (states are torch tensors wrapped by ``sv_wrap``) and the stream
+(the current torch stream at wrap time).  There is no CPU fallback: importing
+this package fails if libsv.so is not built, and every call on a machine
+without a GPU reports SV_ERR_HIP.
+
+Conventions (Kang & Ryu, arXiv 2508.13615, Sec. 2): qubit q is bit q of the
+amplitude index; controls are 1-controls; matrices put the first-listed target
+in the most significant bit of their index.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Iterable, List, Optional, Sequence, Tuple
+
+import numpy as np
+import torch
+
+from ._lib import (GATES, OP_MAX_QUBITS, SV_C64, SV_C128, SvBatchCircuit, SvError, SvObs, SvOp, check, lib)
+
+__all__ = ["State", "Circuit", "Observable", "AdjointExpval", "SvError", "lib", "tune_set", "tune_get",
+           "sv_version"]
+
+_TORCH_DT = {"c128": torch.complex128, "c64": torch.complex64}
+_SV_DT = {"c128": SV_C128, "c64": SV_C64}
+
+
+def _ints(seq: Sequence[int]):
+    return (ctypes.c_int * max(1, len(seq)))(*[int(q) for q in seq])
+
+
+def _dbl(seq):
+    arr = np.ascontiguousarray(np.asarray(seq, dtype=np.float64).reshape(-1))
+    return arr, arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _matrix(m):
+    if m is None:
+        return None, None
+    a = np.ascontiguousarray(np.asarray(m, dtype=np.complex128))
+    flat = a.view(np.float64).reshape(-1).copy()
+    return flat, flat.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def sv_version() -> int:
+    return int(lib.sv_version())
+
+
+def tune_set(kernel_class: int, dtype: str, tier: int, block: int, unroll: int) -> None:
+    check(lib.sv_tune_set(kernel_class, _SV_DT[dtype], tier, block, unroll))
+
+
+def tune_get(kernel_class: int, dtype: str, tier: int) -> Tuple[int, int]:
+    b, u = ctypes.c_int(), ctypes.c_int()
+    check(lib.sv_tune_get(kernel_class, _SV_DT[dtype], tier, ctypes.byref(b), ctypes.byref(u)))
+    return b.value, u.value
+
+
+class Observable:
+    """Pauli sum sum_k c_k P_k, terms given as (coeff, letters, qubits); marshalled
+    into the sv_obs bit-mask form (X/Y positions in xmask, Z/Y in zmask)."""
+
+    def __init__(self, terms: Iterable[Tuple[float, str, Sequence[int]]]):
+        terms = list(terms)
+        self.coeffs = np.array([float(t[0]) for t in terms] or [0.0], dtype=np.float64)
+        xm, zm = [], []
+        for _, letters, qubits in terms:
+            x = z = 0
+            for p, q in zip(letters, qubits):
+                if p not in "IXYZ":
+                    raise ValueError(f"bad Pauli letter {p!r}")
+                if p in "XY":
+                    x |= 1 << int(q)
+                if p in "ZY":
+                    z |= 1 << int(q)
+            xm.append(x)
+            zm.append(z)
+        self.xmask = np.array(xm or [0], dtype=np.uint64)
+        self.zmask = np.array(zm or [0], dtype=np.uint64)
+        self.c = SvObs(len(terms), self.coeffs.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                       self.xmask.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                       self.zmask.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)))
+
+
+class State:
+    """A 2^n state vector in a torch tensor on the current GPU, wrapped by libsv."""
+
+    def __init__(self, n: int, dtype: str = "c128", tensor: Optional[torch.Tensor] = None,
+                 stream: Optional[torch.cuda.Stream] = None, basis: Optional[int] = 0):
+        if dtype not in _TORCH_DT:
+            raise ValueError("dtype must be 'c128' or 'c64'")
+        self.n, self.dtype = int(n), dtype
+        if tensor is None:
+            tensor = torch.empty(1 << self.n, dtype=_TORCH_DT[dtype], device="cuda")
+        elif tensor.dtype != _TORCH_DT[dtype] or tensor.numel() != (1 << self.n) or not tensor.is_contiguous():
+            raise ValueError("tensor must be a contiguous 2^n vector of the state dtype")
+        self.tensor = tensor
+        self.stream = stream if stream is not None else torch.cuda.current_stream(tensor.device)
+        h = ctypes.c_void_p()
+        check(lib.sv_wrap(ctypes.c_void_p(tensor.data_ptr()), self.n, _SV_DT[dtype],
+                          ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
+        self.handle = h
+        if basis is not None:
+            self.set_basis(basis)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            lib.sv_free(h)
+            self.handle = None
+
+    # ---- data movement ---------------------------------------------------
+    def set_basis(self, index: int) -> "State":
+        check(lib.sv_set_basis(self.handle, int(index)))
+        return self
+
+    def load(self, host: np.ndarray) -> "State":
+        a = np.ascontiguousarray(host, dtype=np.complex128 if self.dtype == "c128" else np.complex64)
+        check(lib.sv_copy_from_host(self.handle, ctypes.c_void_p(a.ctypes.data), a.nbytes))
+        return self
+
+    def numpy(self) -> np.ndarray:
+        out = np.empty(1 << self.n, dtype=np.complex128 if self.dtype == "c128" else np.complex64)
+        check(lib.sv_copy_to_host(self.handle, ctypes.c_void_p(out.ctypes.data), out.nbytes))
+        return out
+
+    def copy_from(self, other: "State") -> "State":
+        check(lib.sv_copy_state(self.handle, other.handle))
+        return self
+
+    def synchronize(self) -> None:
+        check(lib.sv_synchronize(self.handle))
+
+    # ---- gates -------------------------------------------------------------
+    def apply(self, gate: str, targets: Sequence[int], controls: Sequence[int] = (),
+              params: Sequence[float] = (), matrix=None, adjoint: bool = False) -> "State":
+        p, pp = _dbl(list(params) or [0.0])
+        m, mp = _matrix(matrix)
+        check(lib.sv_apply_controlled(self.handle, GATES[gate], _ints(controls), len(controls), _ints(targets),
+                                      len(targets), pp, mp, int(bool(adjoint))))
+        return self
+
+    def apply_general(self, qubits: Sequence[int], matrix) -> "State":
+        m, mp = _matrix(matrix)
+        check(lib.sv_apply_general(self.handle, _ints(qubits), len(qubits), mp))
+        return self
+
+    # ---- measurement -------------------------------------------------------
+    def norm2(self) -> float:
+        out = ctypes.c_double()
+        check(lib.sv_norm2(self.handle, ctypes.byref(out)))
+        return out.value
+
+    def expval_pauli(self, paulis: str, qubits: Sequence[int]) -> float:
+        out = ctypes.c_double()
+        check(lib.sv_expval_pauli(self.handle, paulis.encode(), _ints(qubits), len(qubits), ctypes.byref(out)))
+        return out.value
+
+    def expval(self, obs) -> float:
+        obs = obs if isinstance(obs, Observable) else Observable(obs)
+        out = ctypes.c_double()
+        check(lib.sv_expval_obs(self.handle, ctypes.byref(obs.c), ctypes.byref(out)))
+        return out.value
+
+    def expval_dev(self, obs, out: torch.Tensor) -> None:
+        obs = obs if isinstance(obs, Observable) else Observable(obs)
+        check(lib.sv_expval_obs_dev(self.handle, ctypes.byref(obs.c), ctypes.c_void_p(out.data_ptr())))
+
+
+def _sv_op(op) -> Tuple[SvOp, Optional[np.ndarray]]:
+    """workloads.Op -> sv_op (matrix kept alive by the caller)."""
+    qs = list(op.controls) + list(op.targets)
+    if len(qs) > OP_MAX_QUBITS:
+        raise ValueError("too many qubits in one op")
+    s = SvOp()
+    s.gate = GATES[op.gate]
+    s.n_controls = len(op.controls)
+    s.n_targets = len(op.targets)
+    s.param_index = int(op.pidx)
+    for j, q in enumerate(qs):
+        s.qubits[j] = int(q)
+    s.value = float(op.value)
+    keep = None
+    if op.matrix is not None:
+        keep, mp = _matrix(op.matrix)
+        s.matrix = mp
+    return s, keep
+
+
+class Circuit:
+    """An op list bound into libsv (sv_circuit_create)."""
+
+    def __init__(self, n: int, ops, n_params: int = 0):
+        ops = list(ops)
+        self.n, self.n_params = int(n), int(n_params)
+        arr = (SvOp * max(1, len(ops)))()
+        keep = []
+        for i, op in enumerate(ops):
+            arr[i], k = _sv_op(op)
+            keep.append(k)
+        h = ctypes.c_void_p()
+        check(lib.sv_circuit_create(self.n, arr, len(ops), self.n_params, ctypes.byref(h)))
+        self.handle = h
+        self.n_ops = len(ops)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            lib.sv_circuit_free(h)
+            self.handle = None
+
+    def apply(self, state: State, params=()) -> State:
+        p, pp = _dbl(list(params) if len(params) else [0.0])
+        check(lib.sv_circuit_apply(self.handle, state.handle, pp))
+        return state
+
+    def adjoint_grad(self, psi: State, lam: State, params, obs) -> Tuple[float, np.ndarray]:
+        """Returns (E, dE/dparams); psi holds the input state on entry and again
+        (up to rounding) on exit."""
+        obs = obs if isinstance(obs, Observable) else Observable(obs)
+        p, pp = _dbl(list(params) if len(params) else [0.0])
+        g = np.zeros(max(1, self.n_params), dtype=np.float64)
+        e = ctypes.c_double()
+        check(lib.sv_adjoint_grad(self.handle, psi.handle, lam.handle, pp, ctypes.byref(obs.c), ctypes.byref(e),
+                                  g.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return e.value, g[: self.n_params]
+
+
+class AdjointExpval(torch.autograd.Function):
+    """E(params) = <psi|O|psi> with psi = U(params)|0...0>, differentiated by the
+    adjoint kernel.  The gradient is produced together with E (the adjoint sweep
+    needs the forward state) and returned by backward scaled by dL/dE."""
+
+    @staticmethod
+    def forward(ctx, params: torch.Tensor, circuit: Circuit, psi: State, lam: State, obs):
+        psi.set_basis(0)
+        e, g = circuit.adjoint_grad(psi, lam, params.detach().cpu().double().numpy(), obs)
+        ctx.save_for_backward(torch.from_numpy(g).to(params.device, params.dtype))
+        return torch.tensor(e, dtype=params.dtype, device=params.device)
+
+    @staticmethod
+    def backward(ctx, grad_e):
+        (g,) = ctx.saved_tensors
+        return grad_e * g, None, None, None, None

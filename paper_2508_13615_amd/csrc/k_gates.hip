@@ -1,0 +1,429 @@
+// k_gates.hip -- gate kernels for gfx950 (MI355X).
+//
+// Sec. 2 of the paper: each gate is applied only through the non-zero
+// elements of its logic matrix, and a control only selects where it acts.
+// The kernels below are the GPU form of that rule, one per gate class:
+//   k_pair    two members per group (base + o0, base + o1): permutations
+//             (X, CNOT, Toffoli, SWAP: pure moves) and butterflies (H, RX,
+//             RY, Y, U2 and their controlled forms);
+//   k_one     one member per group: phase on the |1..1> subspace of the
+//             gate's qubits (Z, S, T, PHASE, CZ, controlled phase);
+//   k_diag    element-wise diagonal over the control subspace (RZ);
+//   k_quad    four members per group (U4 on two targets);
+//   k_general the dense 2^K x 2^K product with no structure used (the
+//             "general approach" of Sec. 3.1, the baseline).
+//
+// All kernels are HBM-bound streams.  Each thread owns U groups spaced one
+// block apart, so every load instruction of a wavefront reads consecutive
+// groups; when the lowest inserted bit is >= 3 (complex128) those are whole
+// 128-byte lines, below that the U loads of a wave together cover every line
+// they touch.  All U groups are loaded before any is written, which keeps
+// 2*U independent 16-byte loads in flight per lane.
+#include "sv_core.h"
+
+namespace svk {
+
+template <typename V, typename T>
+__device__ __forceinline__ V cmul(T ur, T ui, V a)
+{
+    V r;
+    r.x = ur * a.x - ui * a.y;
+    r.y = ur * a.y + ui * a.x;
+    return r;
+}
+
+template <typename V, typename T>
+__device__ __forceinline__ V cmad2(T ar_, T ai_, V a, T br_, T bi_, V b)
+{
+    V r;
+    r.x = (ar_ * a.x - ai_ * a.y) + (br_ * b.x - bi_ * b.y);
+    r.y = (ar_ * a.y + ai_ * a.x) + (br_ * b.y + bi_ * b.x);
+    return r;
+}
+
+template <int OP, typename T, typename V>
+__device__ __forceinline__ void pair_apply(const V a0, const V a1, const Coef2<T>& c, V& r0, V& r1)
+{
+    if constexpr (OP == PAIR_SWAP) {
+        r0 = a1;
+        r1 = a0;
+    } else if constexpr (OP == PAIR_Y) {
+        r0.x = a1.y;
+        r0.y = -a1.x;
+        r1.x = -a0.y;
+        r1.y = a0.x;
+    } else if constexpr (OP == PAIR_REAL) {
+        r0.x = c.m[0] * a0.x + c.m[2] * a1.x;
+        r0.y = c.m[0] * a0.y + c.m[2] * a1.y;
+        r1.x = c.m[4] * a0.x + c.m[6] * a1.x;
+        r1.y = c.m[4] * a0.y + c.m[6] * a1.y;
+    } else if constexpr (OP == PAIR_RX) {
+        const T cc = c.m[0], s = -c.m[3];  // m01 = -i s
+        r0.x = cc * a0.x + s * a1.y;
+        r0.y = cc * a0.y - s * a1.x;
+        r1.x = cc * a1.x + s * a0.y;
+        r1.y = cc * a1.y - s * a0.x;
+    } else {
+        r0 = cmad2<V, T>(c.m[0], c.m[1], a0, c.m[2], c.m[3], a1);
+        r1 = cmad2<V, T>(c.m[4], c.m[5], a0, c.m[6], c.m[7], a1);
+    }
+}
+
+template <typename T, int OP, int U>
+__global__ void __launch_bounds__(1024)
+k_pair(typename Vec2<T>::type* __restrict__ psi, GroupSpec gs, uint64_t o0, uint64_t o1, Coef2<T> c)
+{
+    using V = typename Vec2<T>::type;
+    const uint64_t per_block = (uint64_t)blockDim.x * U;
+    const uint64_t stride = (uint64_t)gridDim.x * per_block;
+    for (uint64_t g0 = (uint64_t)blockIdx.x * per_block + threadIdx.x; g0 < gs.n_groups + threadIdx.x;
+         g0 += stride) {
+        uint64_t b[U];
+        V a0[U], a1[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const uint64_t g = g0 + (uint64_t)j * blockDim.x;
+            if (g < gs.n_groups) {
+                b[j] = group_base(g, gs);
+                a0[j] = psi[b[j] + o0];
+                a1[j] = psi[b[j] + o1];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const uint64_t g = g0 + (uint64_t)j * blockDim.x;
+            if (g < gs.n_groups) {
+                V r0, r1;
+                pair_apply<OP, T, V>(a0[j], a1[j], c, r0, r1);
+                psi[b[j] + o0] = r0;
+                psi[b[j] + o1] = r1;
+            }
+        }
+    }
+}
+
+template <typename T, int OP, int U>
+__global__ void __launch_bounds__(1024)
+k_one(typename Vec2<T>::type* __restrict__ psi, GroupSpec gs, T zr, T zi)
+{
+    using V = typename Vec2<T>::type;
+    const uint64_t per_block = (uint64_t)blockDim.x * U;
+    const uint64_t stride = (uint64_t)gridDim.x * per_block;
+    for (uint64_t g0 = (uint64_t)blockIdx.x * per_block + threadIdx.x; g0 < gs.n_groups + threadIdx.x;
+         g0 += stride) {
+        uint64_t b[U];
+        V a[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const uint64_t g = g0 + (uint64_t)j * blockDim.x;
+            if (g < gs.n_groups) {
+                b[j] = group_base(g, gs);
+                a[j] = psi[b[j]];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const uint64_t g = g0 + (uint64_t)j * blockDim.x;
+            if (g < gs.n_groups) {
+                V r;
+                if constexpr (OP == ONE_NEG) {
+                    r.x = -a[j].x;
+                    r.y = -a[j].y;
+                } else if constexpr (OP == ONE_MULI) {
+                    // zr = +1: i*a = (-a.y, a.x); zr = -1: -i*a = (a.y, -a.x)
+                    r.x = zr > T(0) ? -a[j].y : a[j].y;
+                    r.y = zr > T(0) ? a[j].x : -a[j].x;
+                } else {
+                    r = cmul<V, T>(zr, zi, a[j]);
+                }
+                psi[b[j]] = r;
+            }
+        }
+    }
+}
+
+template <typename T, int U>
+__global__ void __launch_bounds__(1024)
+k_diag(typename Vec2<T>::type* __restrict__ psi, GroupSpec gs, DiagSpec<T> d)
+{
+    using V = typename Vec2<T>::type;
+    const uint64_t per_block = (uint64_t)blockDim.x * U;
+    const uint64_t stride = (uint64_t)gridDim.x * per_block;
+    const int ne = 1 << d.k;
+    for (uint64_t g0 = (uint64_t)blockIdx.x * per_block + threadIdx.x; g0 < gs.n_groups + threadIdx.x;
+         g0 += stride) {
+        uint64_t b[U];
+        V a[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const uint64_t g = g0 + (uint64_t)j * blockDim.x;
+            if (g < gs.n_groups) {
+                b[j] = group_base(g, gs);
+                a[j] = psi[b[j]];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const uint64_t g = g0 + (uint64_t)j * blockDim.x;
+            if (g < gs.n_groups) {
+                int e = 0;
+                for (int q = 0; q < d.k; ++q) e = (e << 1) | (int)((b[j] >> d.tq[q]) & 1ull);
+                T zr = d.d[0], zi = d.d[1];
+                for (int i = 1; i < ne; ++i) {
+                    zr = (e == i) ? d.d[2 * i] : zr;
+                    zi = (e == i) ? d.d[2 * i + 1] : zi;
+                }
+                psi[b[j]] = cmul<V, T>(zr, zi, a[j]);
+            }
+        }
+    }
+}
+
+template <typename T, int U>
+__global__ void __launch_bounds__(1024)
+k_quad(typename Vec2<T>::type* __restrict__ psi, GroupSpec gs, uint64_t o1, uint64_t o2, uint64_t o3,
+       Coef4<T> c)
+{
+    using V = typename Vec2<T>::type;
+    const uint64_t per_block = (uint64_t)blockDim.x * U;
+    const uint64_t stride = (uint64_t)gridDim.x * per_block;
+    for (uint64_t g0 = (uint64_t)blockIdx.x * per_block + threadIdx.x; g0 < gs.n_groups + threadIdx.x;
+         g0 += stride) {
+        uint64_t b[U];
+        V a[U][4];
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const uint64_t g = g0 + (uint64_t)j * blockDim.x;
+            if (g < gs.n_groups) {
+                b[j] = group_base(g, gs);
+                a[j][0] = psi[b[j]];
+                a[j][1] = psi[b[j] + o1];
+                a[j][2] = psi[b[j] + o2];
+                a[j][3] = psi[b[j] + o3];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const uint64_t g = g0 + (uint64_t)j * blockDim.x;
+            if (g < gs.n_groups) {
+                V r[4];
+#pragma unroll
+                for (int row = 0; row < 4; ++row) {
+                    T sr = T(0), si = T(0);
+#pragma unroll
+                    for (int col = 0; col < 4; ++col) {
+                        const T ur = c.m[2 * (4 * row + col)], ui = c.m[2 * (4 * row + col) + 1];
+                        sr += ur * a[j][col].x - ui * a[j][col].y;
+                        si += ur * a[j][col].y + ui * a[j][col].x;
+                    }
+                    r[row].x = sr;
+                    r[row].y = si;
+                }
+                psi[b[j]] = r[0];
+                psi[b[j] + o1] = r[1];
+                psi[b[j] + o2] = r[2];
+                psi[b[j] + o3] = r[3];
+            }
+        }
+    }
+}
+
+template <typename T, int K, int U>
+__global__ void __launch_bounds__(1024)
+k_general(typename Vec2<T>::type* __restrict__ psi, GroupSpec gs, GeneralSpec<T, K> sp)
+{
+    using V = typename Vec2<T>::type;
+    constexpr int M = 1 << K;
+    const uint64_t per_block = (uint64_t)blockDim.x * U;
+    const uint64_t stride = (uint64_t)gridDim.x * per_block;
+    for (uint64_t g0 = (uint64_t)blockIdx.x * per_block + threadIdx.x; g0 < gs.n_groups + threadIdx.x;
+         g0 += stride) {
+        uint64_t b[U];
+        V a[U][M];
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const uint64_t g = g0 + (uint64_t)j * blockDim.x;
+            if (g < gs.n_groups) {
+                b[j] = group_base(g, gs);
+#pragma unroll
+                for (int r = 0; r < M; ++r) a[j][r] = psi[b[j] + sp.off[r]];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const uint64_t g = g0 + (uint64_t)j * blockDim.x;
+            if (g < gs.n_groups) {
+#pragma unroll
+                for (int row = 0; row < M; ++row) {
+                    T sr = T(0), si = T(0);
+#pragma unroll
+                    for (int col = 0; col < M; ++col) {
+                        const T ur = sp.m[2 * (M * row + col)], ui = sp.m[2 * (M * row + col) + 1];
+                        sr += ur * a[j][col].x - ui * a[j][col].y;
+                        si += ur * a[j][col].y + ui * a[j][col].x;
+                    }
+                    V r;
+                    r.x = sr;
+                    r.y = si;
+                    psi[b[j] + sp.off[row]] = r;
+                }
+            }
+        }
+    }
+}
+
+template <typename T>
+__global__ void k_set_basis(typename Vec2<T>::type* __restrict__ psi, uint64_t n_amps, uint64_t index)
+{
+    using V = typename Vec2<T>::type;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n_amps; x += stride) {
+        V v;
+        v.x = x == index ? T(1) : T(0);
+        v.y = T(0);
+        psi[x] = v;
+    }
+}
+
+// --------------------------------------------------------------------------
+// launchers
+// --------------------------------------------------------------------------
+static dim3 grid_for(uint64_t n_groups, int block, int unroll)
+{
+    const uint64_t per = (uint64_t)block * (uint64_t)unroll;
+    uint64_t nb = (n_groups + per - 1) / per;
+    if (nb < 1) nb = 1;
+    if (nb > (1ull << 30)) nb = 1ull << 30;  // grid-stride loop covers the rest
+    return dim3((unsigned)nb);
+}
+
+#define SV_UNROLL_SWITCH(lc, ...)                         \
+    switch ((lc).unroll) {                                \
+    case 1: { constexpr int UU = 1; __VA_ARGS__; } break; \
+    case 2: { constexpr int UU = 2; __VA_ARGS__; } break; \
+    case 8: { constexpr int UU = 8; __VA_ARGS__; } break; \
+    default: { constexpr int UU = 4; __VA_ARGS__; } break; \
+    }
+
+template <typename T>
+hipError_t launch_pair(void* psi, const GroupSpec& gs, uint64_t o0, uint64_t o1, int op, const Coef2<T>& c,
+                       hipStream_t s, Launch lc)
+{
+    using V = typename Vec2<T>::type;
+    if (gs.n_groups == 0) return hipSuccess;
+    V* p = (V*)psi;
+    SV_UNROLL_SWITCH(lc, {
+        const dim3 grid = grid_for(gs.n_groups, lc.block, UU);
+        switch (op) {
+        case PAIR_SWAP: hipLaunchKernelGGL((k_pair<T, PAIR_SWAP, UU>), grid, dim3(lc.block), 0, s, p, gs, o0, o1, c); break;
+        case PAIR_Y: hipLaunchKernelGGL((k_pair<T, PAIR_Y, UU>), grid, dim3(lc.block), 0, s, p, gs, o0, o1, c); break;
+        case PAIR_REAL: hipLaunchKernelGGL((k_pair<T, PAIR_REAL, UU>), grid, dim3(lc.block), 0, s, p, gs, o0, o1, c); break;
+        case PAIR_RX: hipLaunchKernelGGL((k_pair<T, PAIR_RX, UU>), grid, dim3(lc.block), 0, s, p, gs, o0, o1, c); break;
+        default: hipLaunchKernelGGL((k_pair<T, PAIR_DENSE, UU>), grid, dim3(lc.block), 0, s, p, gs, o0, o1, c); break;
+        }
+    });
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_one(void* psi, const GroupSpec& gs, int op, T zr, T zi, hipStream_t s, Launch lc)
+{
+    using V = typename Vec2<T>::type;
+    if (gs.n_groups == 0) return hipSuccess;
+    V* p = (V*)psi;
+    SV_UNROLL_SWITCH(lc, {
+        const dim3 grid = grid_for(gs.n_groups, lc.block, UU);
+        switch (op) {
+        case ONE_NEG: hipLaunchKernelGGL((k_one<T, ONE_NEG, UU>), grid, dim3(lc.block), 0, s, p, gs, zr, zi); break;
+        case ONE_MULI: hipLaunchKernelGGL((k_one<T, ONE_MULI, UU>), grid, dim3(lc.block), 0, s, p, gs, zr, zi); break;
+        default: hipLaunchKernelGGL((k_one<T, ONE_MUL, UU>), grid, dim3(lc.block), 0, s, p, gs, zr, zi); break;
+        }
+    });
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_diag(void* psi, const GroupSpec& gs, const DiagSpec<T>& d, hipStream_t s, Launch lc)
+{
+    using V = typename Vec2<T>::type;
+    if (gs.n_groups == 0) return hipSuccess;
+    V* p = (V*)psi;
+    SV_UNROLL_SWITCH(lc, {
+        const dim3 grid = grid_for(gs.n_groups, lc.block, UU);
+        hipLaunchKernelGGL((k_diag<T, UU>), grid, dim3(lc.block), 0, s, p, gs, d);
+    });
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_quad(void* psi, const GroupSpec& gs, const uint64_t off[4], const Coef4<T>& c, hipStream_t s,
+                       Launch lc)
+{
+    using V = typename Vec2<T>::type;
+    if (gs.n_groups == 0) return hipSuccess;
+    V* p = (V*)psi;
+    SV_UNROLL_SWITCH(lc, {
+        const dim3 grid = grid_for(gs.n_groups, lc.block, UU);
+        hipLaunchKernelGGL((k_quad<T, UU>), grid, dim3(lc.block), 0, s, p, gs, off[1], off[2], off[3], c);
+    });
+    return hipGetLastError();
+}
+
+template <typename T, int K>
+static hipError_t launch_general_k(typename Vec2<T>::type* p, const GroupSpec& gs, const uint64_t* off,
+                                   const T* m, hipStream_t s, Launch lc)
+{
+    GeneralSpec<T, K> sp;
+    for (int r = 0; r < (1 << K); ++r) sp.off[r] = off[r];
+    for (int i = 0; i < 2 * (1 << K) * (1 << K); ++i) sp.m[i] = m[i];
+    // the 8x8 form keeps 2 groups per thread at most: its 8 loaded members
+    // per group already give 8 loads in flight per lane
+    const int u = K == 3 ? (lc.unroll > 2 ? 2 : lc.unroll) : lc.unroll;
+    switch (u) {
+    case 1: hipLaunchKernelGGL((k_general<T, K, 1>), grid_for(gs.n_groups, lc.block, 1), dim3(lc.block), 0, s, p, gs, sp); break;
+    case 2: hipLaunchKernelGGL((k_general<T, K, 2>), grid_for(gs.n_groups, lc.block, 2), dim3(lc.block), 0, s, p, gs, sp); break;
+    default: hipLaunchKernelGGL((k_general<T, K, 4>), grid_for(gs.n_groups, lc.block, 4), dim3(lc.block), 0, s, p, gs, sp); break;
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_general(void* psi, const GroupSpec& gs, int k, const uint64_t* off, const T* m, hipStream_t s,
+                          Launch lc)
+{
+    using V = typename Vec2<T>::type;
+    if (gs.n_groups == 0) return hipSuccess;
+    V* p = (V*)psi;
+    switch (k) {
+    case 1: return launch_general_k<T, 1>(p, gs, off, m, s, lc);
+    case 2: return launch_general_k<T, 2>(p, gs, off, m, s, lc);
+    case 3: return launch_general_k<T, 3>(p, gs, off, m, s, lc);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T>
+hipError_t launch_set_basis(void* psi, uint64_t n_amps, uint64_t index, hipStream_t s)
+{
+    using V = typename Vec2<T>::type;
+    uint64_t nb = (n_amps + 255) / 256;
+    if (nb > 65536) nb = 65536;
+    hipLaunchKernelGGL((k_set_basis<T>), dim3((unsigned)nb), dim3(256), 0, s, (V*)psi, n_amps, index);
+    return hipGetLastError();
+}
+
+#define SV_INSTANTIATE(T)                                                                                   \
+    template hipError_t launch_pair<T>(void*, const GroupSpec&, uint64_t, uint64_t, int, const Coef2<T>&,   \
+                                       hipStream_t, Launch);                                                \
+    template hipError_t launch_one<T>(void*, const GroupSpec&, int, T, T, hipStream_t, Launch);             \
+    template hipError_t launch_diag<T>(void*, const GroupSpec&, const DiagSpec<T>&, hipStream_t, Launch);   \
+    template hipError_t launch_quad<T>(void*, const GroupSpec&, const uint64_t[4], const Coef4<T>&,         \
+                                       hipStream_t, Launch);                                                \
+    template hipError_t launch_general<T>(void*, const GroupSpec&, int, const uint64_t*, const T*,          \
+                                          hipStream_t, Launch);                                             \
+    template hipError_t launch_set_basis<T>(void*, uint64_t, uint64_t, hipStream_t);
+
+SV_INSTANTIATE(double)
+SV_INSTANTIATE(float)
+
+}  // namespace svk

@@ -1,0 +1,1064 @@
+// sv_api.hip -- the C ABI of libsv (include/sv.h): validation, gate
+// classification and dispatch, measurements, circuits and the adjoint sweep.
+//
+// Gate classification follows Sec. 2 of the paper: only a gate's non-zero
+// matrix elements are used, so each named gate maps to the cheapest kernel
+// class that realises it exactly:
+//   permutation  X / CNOT / Toffoli / SWAP (any controls)  -> k_pair (moves)
+//   subset phase Z, S, T, PHASE and their controlled forms -> k_one on the
+//                |1..1> subspace of controls + target
+//   diagonal     RZ (any controls)                          -> k_diag
+//   butterfly    H, RY (real), RX, Y, U2 (any controls)     -> k_pair
+//   two-target   U4 (any controls)                          -> k_quad
+// A control never adds work: it is a fixed 1-bit inserted into the group
+// index, so the kernel visits only the controlled subspace.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <mutex>
+#include <string>
+#include <unordered_set>
+#include <vector>
+
+#include "sv_core.h"
+
+namespace svk {
+
+static thread_local std::string g_last_error;
+
+sv_status set_error(sv_status st, const std::string& msg)
+{
+    g_last_error = msg;
+    return st;
+}
+
+}  // namespace svk
+
+using namespace svk;
+
+// ---------------------------------------------------------------------------
+// handles
+// ---------------------------------------------------------------------------
+struct sv_state_s {
+    int n;
+    int dtype;
+    void* data;
+    bool owned;
+    hipStream_t stream;
+    double* work;        // stage-1 partials + results
+    size_t work_doubles;
+};
+
+struct OpRec {
+    int gate;
+    int nc, nt;
+    int q[SV_OP_MAX_QUBITS];
+    int pidx;
+    double value;
+    std::vector<double> matrix;
+};
+
+struct sv_circuit_s {
+    int n;
+    int n_params;
+    std::vector<OpRec> ops;
+    // adjoint workspace (device)
+    int n_slots;
+    int seg;
+    double* d_partials;
+    double* d_slot_val;
+    double* d_slot_scale;
+    int* d_slot_param;
+    double* d_grad;
+    double* d_misc;  // [0] = E, then inner-product partials
+    size_t misc_doubles;
+};
+
+static std::mutex g_mu;
+static std::unordered_set<const void*> g_live;
+
+static void reg(const void* h)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_live.insert(h);
+}
+static bool live(const void* h)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    return h && g_live.count(h);
+}
+static void unreg(const void* h)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_live.erase(h);
+}
+
+#define SV_CHECK_STATE(st)                                                  \
+    do {                                                                    \
+        if (!live(st)) return set_error(SV_ERR_HANDLE, "invalid state handle"); \
+    } while (0)
+
+static sv_status hip_status(hipError_t e, const char* where)
+{
+    if (e == hipSuccess) return SV_OK;
+    char buf[256];
+    snprintf(buf, sizeof buf, "%s: %s", where, hipGetErrorString(e));
+    return set_error(SV_ERR_HIP, buf);
+}
+
+static size_t elem_bytes(int dtype) { return dtype == SV_C128 ? 16 : 8; }
+
+// ---------------------------------------------------------------------------
+// launch-shape table (filled by defaults, overridable by the autotuner)
+// ---------------------------------------------------------------------------
+enum KClass { KC_PAIR = 0, KC_ONE = 1, KC_DIAG = 2, KC_QUAD = 3, KC_GENERAL = 4, KC_COUNT = 5 };
+constexpr int kTiers = 3;  // lowest touched qubit: < 3, < 6, >= 6
+static Launch g_tune[KC_COUNT][2][kTiers];
+static bool g_tune_init = false;
+
+static void tune_defaults()
+{
+    for (int c = 0; c < KC_COUNT; ++c)
+        for (int d = 0; d < 2; ++d)
+            for (int t = 0; t < kTiers; ++t) g_tune[c][d][t] = Launch{256, c == KC_QUAD || c == KC_GENERAL ? 2 : 4};
+    g_tune_init = true;
+}
+
+static Launch tune_get(int kc, int dtype, int low_qubit)
+{
+    if (!g_tune_init) tune_defaults();
+    const int tier = low_qubit < 3 ? 0 : (low_qubit < 6 ? 1 : 2);
+    return g_tune[kc][dtype == SV_C128 ? 1 : 0][tier];
+}
+
+// ---------------------------------------------------------------------------
+// validation
+// ---------------------------------------------------------------------------
+static sv_status check_qubits(int n, const int* ctrl, int nc, const int* tgt, int nt)
+{
+    if (nc < 0 || nc > SV_MAX_CONTROLS) return set_error(SV_ERR_ARG, "number of controls out of range");
+    if (nt < 0) return set_error(SV_ERR_ARG, "negative number of targets");
+    if ((nc > 0 && !ctrl) || (nt > 0 && !tgt)) return set_error(SV_ERR_ARG, "null qubit array");
+    uint64_t seen = 0;
+    for (int j = 0; j < nc + nt; ++j) {
+        const int q = j < nc ? ctrl[j] : tgt[j - nc];
+        if (q < 0 || q >= n) return set_error(SV_ERR_QUBIT, "qubit index " + std::to_string(q) + " out of range");
+        if (seen & (1ull << q)) return set_error(SV_ERR_QUBIT, "qubit index " + std::to_string(q) + " repeated");
+        seen |= 1ull << q;
+    }
+    return SV_OK;
+}
+
+static int gate_targets(int gate)
+{
+    switch (gate) {
+    case SV_SWAP:
+    case SV_U4: return 2;
+    default: return 1;
+    }
+}
+
+static bool gate_has_param(int gate)
+{
+    return gate == SV_RX || gate == SV_RY || gate == SV_RZ || gate == SV_PHASE;
+}
+
+// ---------------------------------------------------------------------------
+// plans: a gate classified into a kernel class with its index spec
+// ---------------------------------------------------------------------------
+enum PlanKind { PK_NOP = 0, PK_PAIR, PK_ONE, PK_DIAG, PK_QUAD };
+
+struct Plan {
+    int kind;
+    int kc;
+    int low;  // lowest touched qubit (launch-shape tier)
+    GroupSpec gs;
+    uint64_t off[4];
+    int op;
+    double m[32];
+    int dk;
+    int dtq[3];
+};
+
+static GroupSpec make_groups(int n, const int* ins, int nins, uint64_t set_mask)
+{
+    GroupSpec gs{};
+    int p[kMaxIns];
+    for (int i = 0; i < nins; ++i) p[i] = ins[i];
+    std::sort(p, p + nins);
+    gs.nins = nins;
+    for (int i = 0; i < nins; ++i) gs.pos[i] = p[i];
+    gs.n_groups = 1ull << (n - nins);
+    gs.set_mask = set_mask;
+    return gs;
+}
+
+static void conj_transpose2(double* m)
+{
+    double t[8];
+    // (r, c) -> conj of (c, r)
+    for (int r = 0; r < 2; ++r)
+        for (int c = 0; c < 2; ++c) {
+            t[2 * (2 * r + c)] = m[2 * (2 * c + r)];
+            t[2 * (2 * r + c) + 1] = -m[2 * (2 * c + r) + 1];
+        }
+    memcpy(m, t, sizeof t);
+}
+
+static sv_status build_plan(int n, int gate, const int* ctrl, int nc, const int* tgt, int nt, const double* params,
+                            const double* matrix, int adjoint, Plan* pl)
+{
+    if (gate < SV_I || gate > SV_U4) return set_error(SV_ERR_ARG, "unknown gate");
+    if (nt != gate_targets(gate)) return set_error(SV_ERR_ARG, "wrong number of targets for gate");
+    sv_status st = check_qubits(n, ctrl, nc, tgt, nt);
+    if (st) return st;
+    if (gate_has_param(gate) && !params) return set_error(SV_ERR_ARG, "gate needs params[0]");
+    if ((gate == SV_U2 || gate == SV_U4) && !matrix) return set_error(SV_ERR_ARG, "gate needs a matrix");
+    if (nc + nt > kMaxIns) return set_error(SV_ERR_ARG, "too many qubits");
+
+    memset(pl, 0, sizeof *pl);
+    uint64_t cmask = 0;
+    int ins[kMaxIns];
+    int low = 64;
+    for (int j = 0; j < nc; ++j) {
+        cmask |= 1ull << ctrl[j];
+        ins[j] = ctrl[j];
+        low = std::min(low, ctrl[j]);
+    }
+    for (int j = 0; j < nt; ++j) low = std::min(low, tgt[j]);
+    pl->low = low;
+    const int t = tgt[0];
+    const double sgn = adjoint ? -1.0 : 1.0;
+
+    switch (gate) {
+    case SV_I: pl->kind = PK_NOP; return SV_OK;
+    case SV_X:
+    case SV_Y:
+    case SV_H:
+    case SV_RX:
+    case SV_RY:
+    case SV_U2: {
+        ins[nc] = t;
+        pl->kind = PK_PAIR;
+        pl->kc = KC_PAIR;
+        pl->gs = make_groups(n, ins, nc + 1, cmask);
+        pl->off[0] = 0;
+        pl->off[1] = 1ull << t;
+        if (gate == SV_X) {
+            pl->op = PAIR_SWAP;
+        } else if (gate == SV_Y) {
+            pl->op = PAIR_Y;
+        } else if (gate == SV_H) {
+            const double r = M_SQRT1_2;  // correctly rounded 2^(-1/2)
+            pl->op = PAIR_REAL;
+            double m[8] = {r, 0, r, 0, r, 0, -r, 0};
+            memcpy(pl->m, m, sizeof m);
+        } else if (gate == SV_RY) {
+            const double c = cos(params[0] / 2), s = sgn * sin(params[0] / 2);
+            pl->op = PAIR_REAL;
+            double m[8] = {c, 0, -s, 0, s, 0, c, 0};
+            memcpy(pl->m, m, sizeof m);
+        } else if (gate == SV_RX) {
+            const double c = cos(params[0] / 2), s = sgn * sin(params[0] / 2);
+            pl->op = PAIR_RX;
+            double m[8] = {c, 0, 0, -s, 0, -s, c, 0};
+            memcpy(pl->m, m, sizeof m);
+        } else {
+            pl->op = PAIR_DENSE;
+            memcpy(pl->m, matrix, 8 * sizeof(double));
+            if (adjoint) conj_transpose2(pl->m);
+        }
+        return SV_OK;
+    }
+    case SV_SWAP: {
+        ins[nc] = tgt[0];
+        ins[nc + 1] = tgt[1];
+        pl->kind = PK_PAIR;
+        pl->kc = KC_PAIR;
+        pl->op = PAIR_SWAP;
+        pl->gs = make_groups(n, ins, nc + 2, cmask);
+        pl->off[0] = 1ull << tgt[0];
+        pl->off[1] = 1ull << tgt[1];
+        return SV_OK;
+    }
+    case SV_Z:
+    case SV_S:
+    case SV_T:
+    case SV_PHASE: {
+        ins[nc] = t;
+        pl->kind = PK_ONE;
+        pl->kc = KC_ONE;
+        pl->gs = make_groups(n, ins, nc + 1, cmask | (1ull << t));
+        if (gate == SV_Z) {
+            pl->op = ONE_NEG;
+        } else if (gate == SV_S) {
+            pl->op = ONE_MULI;
+            pl->m[0] = sgn;
+        } else {
+            const double ph = gate == SV_T ? M_PI / 4 : params[0];
+            pl->op = ONE_MUL;
+            pl->m[0] = cos(ph);
+            pl->m[1] = sgn * sin(ph);
+        }
+        return SV_OK;
+    }
+    case SV_RZ: {
+        pl->kind = PK_DIAG;
+        pl->kc = KC_DIAG;
+        pl->gs = make_groups(n, ins, nc, cmask);
+        pl->dk = 1;
+        pl->dtq[0] = t;
+        const double c = cos(params[0] / 2), s = sgn * sin(params[0] / 2);
+        pl->m[0] = c;
+        pl->m[1] = -s;
+        pl->m[2] = c;
+        pl->m[3] = s;
+        return SV_OK;
+    }
+    case SV_U4: {
+        const int a = tgt[0], b = tgt[1];  // a = most significant matrix bit
+        ins[nc] = a;
+        ins[nc + 1] = b;
+        pl->kind = PK_QUAD;
+        pl->kc = KC_QUAD;
+        pl->gs = make_groups(n, ins, nc + 2, cmask);
+        pl->off[0] = 0;
+        pl->off[1] = 1ull << b;
+        pl->off[2] = 1ull << a;
+        pl->off[3] = (1ull << a) | (1ull << b);
+        for (int r = 0; r < 4; ++r)
+            for (int c = 0; c < 4; ++c) {
+                const int src = adjoint ? (4 * c + r) : (4 * r + c);
+                pl->m[2 * (4 * r + c)] = matrix[2 * src];
+                pl->m[2 * (4 * r + c) + 1] = adjoint ? -matrix[2 * src + 1] : matrix[2 * src + 1];
+            }
+        return SV_OK;
+    }
+    }
+    return set_error(SV_ERR_ARG, "unknown gate");
+}
+
+template <typename T>
+static hipError_t run_plan_t(const Plan& pl, void* psi, hipStream_t s, int dtype)
+{
+    const Launch lc = tune_get(pl.kc, dtype, pl.low);
+    switch (pl.kind) {
+    case PK_NOP: return hipSuccess;
+    case PK_PAIR: {
+        Coef2<T> c;
+        for (int i = 0; i < 8; ++i) c.m[i] = (T)pl.m[i];
+        return launch_pair<T>(psi, pl.gs, pl.off[0], pl.off[1], pl.op, c, s, lc);
+    }
+    case PK_ONE: return launch_one<T>(psi, pl.gs, pl.op, (T)pl.m[0], (T)pl.m[1], s, lc);
+    case PK_DIAG: {
+        DiagSpec<T> d{};
+        d.k = pl.dk;
+        for (int i = 0; i < pl.dk; ++i) d.tq[i] = pl.dtq[i];
+        for (int i = 0; i < 2 * (1 << pl.dk); ++i) d.d[i] = (T)pl.m[i];
+        return launch_diag<T>(psi, pl.gs, d, s, lc);
+    }
+    case PK_QUAD: {
+        Coef4<T> c;
+        for (int i = 0; i < 32; ++i) c.m[i] = (T)pl.m[i];
+        return launch_quad<T>(psi, pl.gs, pl.off, c, s, lc);
+    }
+    }
+    return hipErrorInvalidValue;
+}
+
+static sv_status run_plan(const Plan& pl, sv_state st, void* psi)
+{
+    const hipError_t e = st->dtype == SV_C128 ? run_plan_t<double>(pl, psi, st->stream, st->dtype)
+                                              : run_plan_t<float>(pl, psi, st->stream, st->dtype);
+    return hip_status(e, "gate launch");
+}
+
+// ---------------------------------------------------------------------------
+// workspace
+// ---------------------------------------------------------------------------
+// Workspace layout: doubles [0, 8) hold results, [8, ...) stage-1 partials.
+constexpr size_t kWorkHead = 8;
+static sv_status ensure_work(sv_state st, size_t partial_doubles)
+{
+    const size_t doubles = kWorkHead + partial_doubles;
+    if (st->work_doubles >= doubles) return SV_OK;
+    if (st->work) {
+        (void)hipStreamSynchronize(st->stream);
+        (void)hipFree(st->work);
+        st->work = nullptr;
+        st->work_doubles = 0;
+    }
+    if (hipMalloc((void**)&st->work, doubles * sizeof(double)) != hipSuccess) {
+        st->work = nullptr;
+        return set_error(SV_ERR_OOM, "workspace allocation failed");
+    }
+    st->work_doubles = doubles;
+    return SV_OK;
+}
+
+// Entry points: sv.h declares each of them extern "C", so these definitions
+// have C linkage.
+
+// ---------------------------------------------------------------------------
+// lifecycle
+// ---------------------------------------------------------------------------
+size_t sv_state_bytes(int n_qubits, sv_dtype dtype)
+{
+    if (n_qubits < 1 || n_qubits > SV_MAX_QUBITS) return 0;
+    if (dtype != SV_C64 && dtype != SV_C128) return 0;
+    return (size_t(1) << n_qubits) * elem_bytes(dtype);
+}
+
+static sv_status make_state(void* ptr, bool owned, int n, sv_dtype dtype, void* stream, sv_state* out)
+{
+    sv_state st = new sv_state_s{};
+    st->n = n;
+    st->dtype = dtype;
+    st->data = ptr;
+    st->owned = owned;
+    st->stream = (hipStream_t)stream;
+    st->work = nullptr;  // reduction workspace is allocated on first use
+    st->work_doubles = 0;
+    reg(st);
+    *out = st;
+    return SV_OK;
+}
+
+sv_status sv_alloc(int n_qubits, sv_dtype dtype, void* stream, sv_state* out)
+{
+    if (!out) return set_error(SV_ERR_ARG, "null output handle");
+    const size_t bytes = sv_state_bytes(n_qubits, dtype);
+    if (!bytes) return set_error(SV_ERR_ARG, "n_qubits or dtype out of range");
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess || !p) {
+        (void)hipGetLastError();
+        return set_error(SV_ERR_OOM, "state allocation of " + std::to_string(bytes) + " bytes failed");
+    }
+    sv_status rc = make_state(p, true, n_qubits, dtype, stream, out);
+    if (rc) {
+        (void)hipFree(p);
+        return rc;
+    }
+    return sv_set_basis(*out, 0);
+}
+
+sv_status sv_wrap(void* dev_ptr, int n_qubits, sv_dtype dtype, void* stream, sv_state* out)
+{
+    if (!out) return set_error(SV_ERR_ARG, "null output handle");
+    if (!dev_ptr) return set_error(SV_ERR_ARG, "null device pointer");
+    if (((uintptr_t)dev_ptr) % 16) return set_error(SV_ERR_ARG, "device pointer must be 16-byte aligned");
+    if (!sv_state_bytes(n_qubits, dtype)) return set_error(SV_ERR_ARG, "n_qubits or dtype out of range");
+    return make_state(dev_ptr, false, n_qubits, dtype, stream, out);
+}
+
+sv_status sv_free(sv_state st)
+{
+    SV_CHECK_STATE(st);
+    unreg(st);
+    (void)hipStreamSynchronize(st->stream);
+    if (st->work) (void)hipFree(st->work);
+    if (st->owned && st->data) (void)hipFree(st->data);
+    delete st;
+    return SV_OK;
+}
+
+sv_status sv_set_stream(sv_state st, void* stream)
+{
+    SV_CHECK_STATE(st);
+    st->stream = (hipStream_t)stream;
+    return SV_OK;
+}
+
+sv_status sv_get_info(sv_state st, int* n_qubits, int* dtype, void** dev_ptr)
+{
+    SV_CHECK_STATE(st);
+    if (n_qubits) *n_qubits = st->n;
+    if (dtype) *dtype = st->dtype;
+    if (dev_ptr) *dev_ptr = st->data;
+    return SV_OK;
+}
+
+sv_status sv_set_basis(sv_state st, uint64_t index)
+{
+    SV_CHECK_STATE(st);
+    const uint64_t na = 1ull << st->n;
+    if (index >= na) return set_error(SV_ERR_ARG, "basis index out of range");
+    const hipError_t e = st->dtype == SV_C128 ? launch_set_basis<double>(st->data, na, index, st->stream)
+                                              : launch_set_basis<float>(st->data, na, index, st->stream);
+    return hip_status(e, "set_basis");
+}
+
+sv_status sv_copy_to_host(sv_state st, void* host, size_t bytes)
+{
+    SV_CHECK_STATE(st);
+    if (!host) return set_error(SV_ERR_ARG, "null host pointer");
+    if (bytes != sv_state_bytes(st->n, (sv_dtype)st->dtype)) return set_error(SV_ERR_ARG, "byte count mismatch");
+    hipError_t e = hipMemcpyAsync(host, st->data, bytes, hipMemcpyDeviceToHost, st->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(st->stream);
+    return hip_status(e, "copy_to_host");
+}
+
+sv_status sv_copy_from_host(sv_state st, const void* host, size_t bytes)
+{
+    SV_CHECK_STATE(st);
+    if (!host) return set_error(SV_ERR_ARG, "null host pointer");
+    if (bytes != sv_state_bytes(st->n, (sv_dtype)st->dtype)) return set_error(SV_ERR_ARG, "byte count mismatch");
+    hipError_t e = hipMemcpyAsync(st->data, host, bytes, hipMemcpyHostToDevice, st->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(st->stream);
+    return hip_status(e, "copy_from_host");
+}
+
+sv_status sv_copy_state(sv_state dst, sv_state src)
+{
+    SV_CHECK_STATE(dst);
+    SV_CHECK_STATE(src);
+    if (dst->n != src->n || dst->dtype != src->dtype) return set_error(SV_ERR_ARG, "state shape mismatch");
+    if (dst == src) return SV_OK;
+    const size_t bytes = sv_state_bytes(src->n, (sv_dtype)src->dtype);
+    return hip_status(hipMemcpyAsync(dst->data, src->data, bytes, hipMemcpyDeviceToDevice, dst->stream),
+                      "copy_state");
+}
+
+sv_status sv_synchronize(sv_state st)
+{
+    SV_CHECK_STATE(st);
+    return hip_status(hipStreamSynchronize(st->stream), "synchronize");
+}
+
+// ---------------------------------------------------------------------------
+// gates
+// ---------------------------------------------------------------------------
+sv_status sv_apply_controlled(sv_state st, sv_gate gate, const int* controls, int nc, const int* targets, int nt,
+                              const double* params, const double* matrix, int adjoint)
+{
+    SV_CHECK_STATE(st);
+    Plan pl;
+    sv_status rc = build_plan(st->n, gate, controls, nc, targets, nt, params, matrix, adjoint, &pl);
+    if (rc) return rc;
+    return run_plan(pl, st, st->data);
+}
+
+sv_status sv_apply_gate(sv_state st, sv_gate gate, const int* targets, int nt, const double* params,
+                        const double* matrix, int adjoint)
+{
+    return sv_apply_controlled(st, gate, nullptr, 0, targets, nt, params, matrix, adjoint);
+}
+
+sv_status sv_apply_general(sv_state st, const int* qubits, int k, const double* matrix)
+{
+    SV_CHECK_STATE(st);
+    if (k < 1 || k > SV_MAX_GENERAL_K) return set_error(SV_ERR_ARG, "general gate needs 1 <= k <= 3");
+    if (!matrix) return set_error(SV_ERR_ARG, "null matrix");
+    sv_status rc = check_qubits(st->n, nullptr, 0, qubits, k);
+    if (rc) return rc;
+    GroupSpec gs = make_groups(st->n, qubits, k, 0);
+    const int M = 1 << k;
+    uint64_t off[8];
+    int low = 64;
+    for (int r = 0; r < M; ++r) {
+        uint64_t o = 0;
+        for (int j = 0; j < k; ++j)
+            if ((r >> (k - 1 - j)) & 1) o |= 1ull << qubits[j];
+        off[r] = o;
+    }
+    for (int j = 0; j < k; ++j) low = std::min(low, qubits[j]);
+    const Launch lc = tune_get(KC_GENERAL, st->dtype, low);
+    hipError_t e;
+    if (st->dtype == SV_C128) {
+        e = launch_general<double>(st->data, gs, k, off, matrix, st->stream, lc);
+    } else {
+        float mf[128];
+        for (int i = 0; i < 2 * M * M; ++i) mf[i] = (float)matrix[i];
+        e = launch_general<float>(st->data, gs, k, off, mf, st->stream, lc);
+    }
+    return hip_status(e, "general launch");
+}
+
+// ---------------------------------------------------------------------------
+// measurement
+// ---------------------------------------------------------------------------
+static sv_status finish_scalar(sv_state st, const double* dres, double* out)
+{
+    hipError_t e = hipMemcpyAsync(out, dres, sizeof(double), hipMemcpyDeviceToHost, st->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(st->stream);
+    return hip_status(e, "result copy");
+}
+
+sv_status sv_norm2(sv_state st, double* out)
+{
+    SV_CHECK_STATE(st);
+    if (!out) return set_error(SV_ERR_ARG, "null output");
+    const uint64_t na = 1ull << st->n;
+    sv_status rw = ensure_work(st, kReduceBlocks);
+    if (rw) return rw;
+    double* partials = st->work + kWorkHead;
+    double* res = st->work;
+    hipError_t e = st->dtype == SV_C128 ? launch_norm_partial<double>(st->data, na, partials, st->stream)
+                                        : launch_norm_partial<float>(st->data, na, partials, st->stream);
+    if (e == hipSuccess) e = launch_sum_partials(partials, reduce_blocks_for(na), res, st->stream);
+    sv_status rc = hip_status(e, "norm");
+    if (rc) return rc;
+    return finish_scalar(st, res, out);
+}
+
+struct ObsPlan {
+    int diag_kind;  // -1 none, 0 generic, 1 sum Z, 2 sum ZZ
+    double diag_coeff;
+    std::vector<double> dc;
+    std::vector<uint64_t> dz;
+    std::vector<double> oc;
+    std::vector<uint64_t> ox, oz;
+    std::vector<int> oy;
+};
+
+static sv_status plan_obs(int n, const sv_obs* obs, ObsPlan* op)
+{
+    if (!obs) return set_error(SV_ERR_ARG, "null observable");
+    if (obs->n_terms < 0) return set_error(SV_ERR_ARG, "negative term count");
+    if (obs->n_terms > 0 && (!obs->coeffs || !obs->xmask || !obs->zmask))
+        return set_error(SV_ERR_ARG, "null observable arrays");
+    const uint64_t all = n >= 64 ? ~0ull : ((1ull << n) - 1ull);
+    op->diag_kind = -1;
+    for (int k = 0; k < obs->n_terms; ++k) {
+        const uint64_t x = obs->xmask[k], z = obs->zmask[k];
+        if ((x | z) & ~all) return set_error(SV_ERR_QUBIT, "observable term acts outside the state");
+        if (x == 0) {
+            op->dc.push_back(obs->coeffs[k]);
+            op->dz.push_back(z);
+        } else {
+            op->oc.push_back(obs->coeffs[k]);
+            op->ox.push_back(x);
+            op->oz.push_back(z);
+            op->oy.push_back(__builtin_popcountll(x & z));
+        }
+    }
+    if (!op->dc.empty()) {
+        op->diag_kind = 0;
+        // closed forms: all unit-free common coefficient, exactly {Z_i} or {Z_i Z_i+1}
+        const double c0 = op->dc[0];
+        bool same = true;
+        for (double c : op->dc) same = same && (c == c0);
+        if (same) {
+            std::vector<uint64_t> zs = op->dz;
+            std::sort(zs.begin(), zs.end());
+            std::vector<uint64_t> sz, szz;
+            for (int i = 0; i < n; ++i) sz.push_back(1ull << i);
+            for (int i = 0; i + 1 < n; ++i) szz.push_back(3ull << i);
+            std::sort(sz.begin(), sz.end());
+            std::sort(szz.begin(), szz.end());
+            if (zs == sz) op->diag_kind = 1;
+            else if (zs == szz && n > 1) op->diag_kind = 2;
+            if (op->diag_kind > 0) op->diag_coeff = c0;
+        }
+    }
+    return SV_OK;
+}
+
+template <typename T>
+static hipError_t obs_passes(sv_state st, const ObsPlan& op, double* partials, int* count)
+{
+    int off = 0;
+    hipError_t e = hipSuccess;
+    const int n = st->n;
+    if (op.diag_kind > 0) {
+        e = launch_diag_obs_partial<T>(st->data, n, op.diag_kind, op.diag_coeff, nullptr, nullptr, 0, partials + off,
+                                       st->stream);
+        off += reduce_blocks_for(1ull << n);
+    } else if (op.diag_kind == 0) {
+        for (size_t k0 = 0; k0 < op.dc.size() && e == hipSuccess; k0 += kDiagTermsPerPass) {
+            const int nt = (int)std::min<size_t>(kDiagTermsPerPass, op.dc.size() - k0);
+            e = launch_diag_obs_partial<T>(st->data, n, 0, 1.0, &op.dc[k0], &op.dz[k0], nt, partials + off,
+                                           st->stream);
+            off += reduce_blocks_for(1ull << n);
+        }
+    }
+    for (size_t k = 0; k < op.oc.size() && e == hipSuccess; ++k) {
+        e = launch_pauli_partial<T>(st->data, n, op.ox[k], op.oz[k], op.oy[k], op.oc[k], partials + off, st->stream);
+        off += reduce_blocks_for(1ull << (n - 1));
+    }
+    *count = off;
+    return e;
+}
+
+static sv_status expval_to_dev(sv_state st, const ObsPlan& op, double* out_dev)
+{
+    // worst case: one segment per pass
+    const size_t passes = (op.dc.size() + kDiagTermsPerPass - 1) / kDiagTermsPerPass + op.oc.size() + 1;
+    sv_status rc = ensure_work(st, passes * kReduceBlocks);
+    if (rc) return rc;
+    int count = 0;
+    double* partials = st->work + kWorkHead;
+    hipError_t e = st->dtype == SV_C128 ? obs_passes<double>(st, op, partials, &count)
+                                        : obs_passes<float>(st, op, partials, &count);
+    // an empty observable sums zero partials: the kernel still writes 0.0
+    if (e == hipSuccess) e = launch_sum_partials(partials, count, out_dev, st->stream);
+    return hip_status(e, "expval");
+}
+
+sv_status sv_expval_obs_dev(sv_state st, const sv_obs* obs, double* out_dev)
+{
+    SV_CHECK_STATE(st);
+    if (!out_dev) return set_error(SV_ERR_ARG, "null output");
+    ObsPlan op;
+    sv_status rc = plan_obs(st->n, obs, &op);
+    if (rc) return rc;
+    return expval_to_dev(st, op, out_dev);
+}
+
+sv_status sv_expval_obs(sv_state st, const sv_obs* obs, double* out)
+{
+    SV_CHECK_STATE(st);
+    if (!out) return set_error(SV_ERR_ARG, "null output");
+    ObsPlan op;
+    sv_status rc = plan_obs(st->n, obs, &op);
+    if (rc) return rc;
+    rc = ensure_work(st, kReduceBlocks);
+    if (rc) return rc;
+    rc = expval_to_dev(st, op, st->work);
+    if (rc) return rc;
+    return finish_scalar(st, st->work, out);
+}
+
+sv_status sv_expval_pauli(sv_state st, const char* paulis, const int* qubits, int n, double* out)
+{
+    SV_CHECK_STATE(st);
+    if (!out || (n > 0 && (!paulis || !qubits)) || n < 0) return set_error(SV_ERR_ARG, "bad arguments");
+    sv_status rc = check_qubits(st->n, nullptr, 0, qubits, n);
+    if (rc) return rc;
+    uint64_t x = 0, z = 0;
+    for (int j = 0; j < n; ++j) {
+        const uint64_t b = 1ull << qubits[j];
+        switch (paulis[j]) {
+        case 'I': break;
+        case 'X': x |= b; break;
+        case 'Y': x |= b; z |= b; break;
+        case 'Z': z |= b; break;
+        default: return set_error(SV_ERR_ARG, "pauli letters must be I, X, Y or Z");
+        }
+    }
+    const double c = 1.0;
+    sv_obs o{1, &c, &x, &z};
+    ObsPlan op;
+    rc = plan_obs(st->n, &o, &op);
+    if (rc) return rc;
+    rc = ensure_work(st, kReduceBlocks);
+    if (rc) return rc;
+    rc = expval_to_dev(st, op, st->work);
+    if (rc) return rc;
+    return finish_scalar(st, st->work, out);
+}
+
+// ---------------------------------------------------------------------------
+// circuits
+// ---------------------------------------------------------------------------
+#define SV_CHECK_CIRC(c)                                                          \
+    do {                                                                          \
+        if (!live(c)) return set_error(SV_ERR_HANDLE, "invalid circuit handle");  \
+    } while (0)
+
+static sv_status op_plan(const sv_circuit_s* c, const OpRec& o, const double* params, int adjoint, Plan* pl)
+{
+    double th = o.value;
+    if (o.pidx >= 0) th = params[o.pidx];
+    return build_plan(c->n, o.gate, o.q, o.nc, o.q + o.nc, o.nt, &th, o.matrix.empty() ? nullptr : o.matrix.data(),
+                      adjoint, pl);
+}
+
+sv_status sv_circuit_create(int n_qubits, const sv_op* ops, int n_ops, int n_params, sv_circuit* out)
+{
+    if (!out) return set_error(SV_ERR_ARG, "null output handle");
+    if (n_qubits < 1 || n_qubits > SV_MAX_QUBITS) return set_error(SV_ERR_ARG, "n_qubits out of range");
+    if (n_ops < 0 || (n_ops > 0 && !ops) || n_params < 0) return set_error(SV_ERR_ARG, "bad op list");
+    auto* c = new sv_circuit_s{};
+    c->n = n_qubits;
+    c->n_params = n_params;
+    int slots = 0;
+    for (int i = 0; i < n_ops; ++i) {
+        const sv_op& s = ops[i];
+        OpRec o;
+        o.gate = s.gate;
+        o.nc = s.n_controls;
+        o.nt = s.n_targets;
+        o.pidx = s.param_index;
+        o.value = s.value;
+        if (o.nc < 0 || o.nt < 0 || o.nc + o.nt > SV_OP_MAX_QUBITS) {
+            delete c;
+            return set_error(SV_ERR_ARG, "op " + std::to_string(i) + ": bad qubit counts");
+        }
+        for (int j = 0; j < o.nc + o.nt; ++j) o.q[j] = s.qubits[j];
+        if (o.pidx >= n_params || o.pidx < -1) {
+            delete c;
+            return set_error(SV_ERR_ARG, "op " + std::to_string(i) + ": parameter index out of range");
+        }
+        if (o.pidx >= 0 && !gate_has_param(o.gate)) {
+            delete c;
+            return set_error(SV_ERR_ARG, "op " + std::to_string(i) + ": gate takes no parameter");
+        }
+        if (s.gate == SV_U2 || s.gate == SV_U4) {
+            const int m = s.gate == SV_U2 ? 8 : 32;
+            if (!s.matrix) {
+                delete c;
+                return set_error(SV_ERR_ARG, "op " + std::to_string(i) + ": missing matrix");
+            }
+            o.matrix.assign(s.matrix, s.matrix + m);
+        }
+        // validate by planning once with a zero angle
+        Plan pl;
+        const double zero = 0.0;
+        sv_status rc = build_plan(n_qubits, o.gate, o.q, o.nc, o.q + o.nc, o.nt, &zero,
+                                  o.matrix.empty() ? nullptr : o.matrix.data(), 0, &pl);
+        if (rc) {
+            delete c;
+            return set_error(rc, "op " + std::to_string(i) + ": " + g_last_error);
+        }
+        if (o.pidx >= 0) ++slots;
+        c->ops.push_back(o);
+    }
+    c->n_slots = slots;
+    c->seg = reduce_blocks_for(1ull << (n_qubits - 1));
+    c->misc_doubles = 8 + (size_t)kReduceBlocks;
+    // device workspace
+    bool ok = hipMalloc((void**)&c->d_partials, sizeof(double) * std::max<size_t>(1, (size_t)slots * c->seg)) ==
+                  hipSuccess &&
+              hipMalloc((void**)&c->d_slot_val, sizeof(double) * std::max(1, slots)) == hipSuccess &&
+              hipMalloc((void**)&c->d_slot_scale, sizeof(double) * std::max(1, slots)) == hipSuccess &&
+              hipMalloc((void**)&c->d_slot_param, sizeof(int) * std::max(1, slots)) == hipSuccess &&
+              hipMalloc((void**)&c->d_grad, sizeof(double) * std::max(1, n_params)) == hipSuccess &&
+              hipMalloc((void**)&c->d_misc, sizeof(double) * c->misc_doubles) == hipSuccess;
+    if (!ok) {
+        (void)hipFree(c->d_partials);
+        (void)hipFree(c->d_slot_val);
+        (void)hipFree(c->d_slot_scale);
+        (void)hipFree(c->d_slot_param);
+        (void)hipFree(c->d_grad);
+        (void)hipFree(c->d_misc);
+        delete c;
+        return set_error(SV_ERR_OOM, "circuit workspace allocation failed");
+    }
+    std::vector<double> scale(std::max(1, slots));
+    std::vector<int> sparam(std::max(1, slots));
+    int s = 0;
+    for (const OpRec& o : c->ops) {
+        if (o.pidx < 0) continue;
+        sparam[s] = o.pidx;
+        scale[s] = o.gate == SV_PHASE ? -2.0 : 1.0;
+        ++s;
+    }
+    (void)hipMemcpy(c->d_slot_scale, scale.data(), sizeof(double) * scale.size(), hipMemcpyHostToDevice);
+    (void)hipMemcpy(c->d_slot_param, sparam.data(), sizeof(int) * sparam.size(), hipMemcpyHostToDevice);
+    reg(c);
+    *out = c;
+    return SV_OK;
+}
+
+sv_status sv_circuit_free(sv_circuit c)
+{
+    SV_CHECK_CIRC(c);
+    unreg(c);
+    (void)hipDeviceSynchronize();
+    (void)hipFree(c->d_partials);
+    (void)hipFree(c->d_slot_val);
+    (void)hipFree(c->d_slot_scale);
+    (void)hipFree(c->d_slot_param);
+    (void)hipFree(c->d_grad);
+    (void)hipFree(c->d_misc);
+    delete c;
+    return SV_OK;
+}
+
+static sv_status circuit_forward(sv_circuit c, sv_state st, const double* params)
+{
+    for (const OpRec& o : c->ops) {
+        Plan pl;
+        sv_status rc = op_plan(c, o, params, 0, &pl);
+        if (rc) return rc;
+        rc = run_plan(pl, st, st->data);
+        if (rc) return rc;
+    }
+    return SV_OK;
+}
+
+sv_status sv_circuit_apply(sv_circuit c, sv_state st, const double* params)
+{
+    SV_CHECK_CIRC(c);
+    SV_CHECK_STATE(st);
+    if (st->n != c->n) return set_error(SV_ERR_ARG, "state size does not match the circuit");
+    if (c->n_params > 0 && !params) return set_error(SV_ERR_ARG, "null params");
+    return circuit_forward(c, st, params);
+}
+
+template <typename T>
+static hipError_t apply_obs_lambda(sv_state psi, sv_state lam, const ObsPlan& op)
+{
+    const int n = psi->n;
+    hipStream_t s = psi->stream;
+    hipError_t e;
+    if (op.diag_kind > 0) {
+        e = launch_obs_diag_apply<T>(psi->data, lam->data, n, op.diag_kind, op.diag_coeff, nullptr, nullptr, 0, 0, s);
+    } else if (op.diag_kind == 0) {
+        e = hipSuccess;
+        for (size_t k0 = 0; k0 < op.dc.size() && e == hipSuccess; k0 += kDiagTermsPerPass) {
+            const int nt = (int)std::min<size_t>(kDiagTermsPerPass, op.dc.size() - k0);
+            e = launch_obs_diag_apply<T>(psi->data, lam->data, n, 0, 1.0, &op.dc[k0], &op.dz[k0], nt, k0 > 0, s);
+        }
+    } else {
+        // lambda = 0 (no diagonal part): o(x) = 0 with an empty term list
+        e = launch_obs_diag_apply<T>(psi->data, lam->data, n, 0, 1.0, nullptr, nullptr, 0, 0, s);
+    }
+    for (size_t k = 0; k < op.oc.size() && e == hipSuccess; ++k)
+        e = launch_obs_pauli_apply<T>(psi->data, lam->data, n, op.ox[k], op.oz[k], op.oy[k], op.oc[k], s);
+    return e;
+}
+
+static int gen_of(int gate)
+{
+    switch (gate) {
+    case SV_RX: return GEN_X;
+    case SV_RY: return GEN_Y;
+    case SV_RZ: return GEN_Z;
+    default: return GEN_P1;
+    }
+}
+
+// U^dagger of a parameterised one-target op as a dense 2x2
+static void rot_dagger(int gate, double th, double* m)
+{
+    const double c = cos(th / 2), s = sin(th / 2);
+    double r[8] = {0};
+    switch (gate) {
+    case SV_RX: { double t[8] = {c, 0, 0, s, 0, s, c, 0}; memcpy(r, t, sizeof t); break; }
+    case SV_RY: { double t[8] = {c, 0, s, 0, -s, 0, c, 0}; memcpy(r, t, sizeof t); break; }
+    case SV_RZ: { double t[8] = {c, s, 0, 0, 0, 0, c, -s}; memcpy(r, t, sizeof t); break; }
+    default: { double t[8] = {1, 0, 0, 0, 0, 0, cos(th), -sin(th)}; memcpy(r, t, sizeof t); break; }
+    }
+    memcpy(m, r, sizeof r);
+}
+
+template <typename T>
+static sv_status adjoint_sweep(sv_circuit c, sv_state psi, sv_state lam, const double* params)
+{
+    hipStream_t s = psi->stream;
+    int slot = c->n_slots - 1;
+    for (int k = (int)c->ops.size() - 1; k >= 0; --k) {
+        const OpRec& o = c->ops[k];
+        if (o.pidx >= 0) {
+            const double th = params[o.pidx];
+            const int t = o.q[o.nc];
+            int ins[kMaxIns];
+            uint64_t cmask = 0;
+            for (int j = 0; j < o.nc; ++j) {
+                ins[j] = o.q[j];
+                cmask |= 1ull << o.q[j];
+            }
+            ins[o.nc] = t;
+            const GroupSpec gs = make_groups(c->n, ins, o.nc + 1, cmask);
+            double md[8];
+            rot_dagger(o.gate, th, md);
+            Coef2<T> u;
+            for (int i = 0; i < 8; ++i) u.m[i] = (T)md[i];
+            hipError_t e = launch_adj_rot<T>(psi->data, lam->data, gs, 1ull << t, gen_of(o.gate), u,
+                                             c->d_partials + (size_t)slot * c->seg, c->seg, s);
+            if (e != hipSuccess) return hip_status(e, "adjoint step");
+            --slot;
+        } else {
+            Plan pl;
+            sv_status rc = op_plan(c, o, params, 1, &pl);
+            if (rc) return rc;
+            rc = run_plan(pl, psi, psi->data);
+            if (rc) return rc;
+            rc = run_plan(pl, psi, lam->data);
+            if (rc) return rc;
+        }
+    }
+    return SV_OK;
+}
+
+sv_status sv_adjoint_grad(sv_circuit c, sv_state psi, sv_state lam, const double* params, const sv_obs* obs,
+                          double* expval_out, double* grad_out)
+{
+    SV_CHECK_CIRC(c);
+    SV_CHECK_STATE(psi);
+    SV_CHECK_STATE(lam);
+    if (psi == lam) return set_error(SV_ERR_ARG, "psi and lam must be different states");
+    if (psi->n != c->n || lam->n != c->n || psi->dtype != lam->dtype)
+        return set_error(SV_ERR_ARG, "state sizes/dtypes do not match the circuit");
+    if (c->n_params > 0 && (!params || !grad_out)) return set_error(SV_ERR_ARG, "null params or grad_out");
+    ObsPlan op;
+    sv_status rc = plan_obs(c->n, obs, &op);
+    if (rc) return rc;
+    if (psi->stream != lam->stream) {
+        // keep all work on psi's stream: lam must be idle first
+        (void)hipStreamSynchronize(lam->stream);
+    }
+    rc = circuit_forward(c, psi, params);
+    if (rc) return rc;
+    const bool d = psi->dtype == SV_C128;
+    hipError_t e = d ? apply_obs_lambda<double>(psi, lam, op) : apply_obs_lambda<float>(psi, lam, op);
+    const uint64_t na = 1ull << c->n;
+    if (e == hipSuccess)
+        e = d ? launch_inner_partial<double>(psi->data, lam->data, na, c->d_misc + 8, psi->stream)
+              : launch_inner_partial<float>(psi->data, lam->data, na, c->d_misc + 8, psi->stream);
+    if (e == hipSuccess) e = launch_sum_partials(c->d_misc + 8, reduce_blocks_for(na), c->d_misc, psi->stream);
+    rc = hip_status(e, "adjoint setup");
+    if (rc) return rc;
+    rc = d ? adjoint_sweep<double>(c, psi, lam, params) : adjoint_sweep<float>(c, psi, lam, params);
+    if (rc) return rc;
+    e = launch_sum_segments(c->d_partials, c->seg, c->n_slots, nullptr, c->d_slot_val, psi->stream);
+    if (e == hipSuccess)
+        e = launch_scatter_grads(c->d_slot_val, c->d_slot_param, c->d_slot_scale, c->n_slots, c->d_grad, c->n_params,
+                                 psi->stream);
+    if (e == hipSuccess && expval_out)
+        e = hipMemcpyAsync(expval_out, c->d_misc, sizeof(double), hipMemcpyDeviceToHost, psi->stream);
+    if (e == hipSuccess && c->n_params > 0)
+        e = hipMemcpyAsync(grad_out, c->d_grad, sizeof(double) * c->n_params, hipMemcpyDeviceToHost, psi->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(psi->stream);
+    return hip_status(e, "adjoint gradient");
+}
+
+// ---------------------------------------------------------------------------
+// tuning + diagnostics
+// ---------------------------------------------------------------------------
+sv_status sv_tune_set(int kernel_class, int dtype, int tier, int block, int unroll)
+{
+    if (!g_tune_init) tune_defaults();
+    if (kernel_class < 0 || kernel_class >= KC_COUNT || (dtype != SV_C64 && dtype != SV_C128) || tier < 0 ||
+        tier >= kTiers)
+        return set_error(SV_ERR_ARG, "bad tuning key");
+    if (block < 64 || block > 1024 || (block & 63)) return set_error(SV_ERR_ARG, "block must be a multiple of 64 in [64, 1024]");
+    if (unroll != 1 && unroll != 2 && unroll != 4 && unroll != 8) return set_error(SV_ERR_ARG, "unroll must be 1, 2, 4 or 8");
+    g_tune[kernel_class][dtype == SV_C128 ? 1 : 0][tier] = Launch{block, unroll};
+    return SV_OK;
+}
+
+sv_status sv_tune_get(int kernel_class, int dtype, int tier, int* block, int* unroll)
+{
+    if (!g_tune_init) tune_defaults();
+    if (kernel_class < 0 || kernel_class >= KC_COUNT || (dtype != SV_C64 && dtype != SV_C128) || tier < 0 ||
+        tier >= kTiers || !block || !unroll)
+        return set_error(SV_ERR_ARG, "bad tuning key");
+    const Launch l = g_tune[kernel_class][dtype == SV_C128 ? 1 : 0][tier];
+    *block = l.block;
+    *unroll = l.unroll;
+    return SV_OK;
+}
+
+const char* sv_last_error(void) { return g_last_error.c_str(); }
+
+const char* sv_status_string(sv_status s)
+{
+    switch (s) {
+    case SV_OK: return "SV_OK";
+    case SV_ERR_ARG: return "SV_ERR_ARG";
+    case SV_ERR_QUBIT: return "SV_ERR_QUBIT";
+    case SV_ERR_OOM: return "SV_ERR_OOM";
+    case SV_ERR_HIP: return "SV_ERR_HIP";
+    case SV_ERR_UNSUPPORTED: return "SV_ERR_UNSUPPORTED";
+    case SV_ERR_HANDLE: return "SV_ERR_HANDLE";
+    }
+    return "unknown";
+}
+
+int sv_version(void) { return 1; }
+

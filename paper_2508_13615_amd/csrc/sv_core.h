@@ -1,0 +1,164 @@
+// sv_core.h -- internal declarations of libsv (kernels <-> host dispatch).
+//
+// Index generation (Sec. 2: a gate acts on the groups of amplitudes that
+// differ only in the gate's qubits; a control selects where it acts): group g
+// in [0, 2^(N - nins)) maps to the base index obtained by inserting a zero bit
+// at each position of `pos` (ascending) and OR-ing `set_mask` (control bits,
+// plus target bits for gates that touch only the |1> subspace).  Members of a
+// group are base + offset[r].
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/sv.h"
+
+namespace svk {
+
+constexpr int kMaxIns = 12;  // controls + targets inserted into a group index
+
+struct GroupSpec {
+    uint64_t n_groups;
+    uint64_t set_mask;
+    int32_t nins;
+    int32_t pos[kMaxIns];
+};
+
+template <typename T> struct Vec2;
+template <> struct Vec2<double> { using type = double2; };
+template <> struct Vec2<float> { using type = float2; };
+
+// Operation kinds of the paired (two-member) kernel.
+enum PairOp : int {
+    PAIR_SWAP = 0,  // permutation: (a, b) -> (b, a)
+    PAIR_Y = 1,     // (a, b) -> (-i b, i a)
+    PAIR_REAL = 2,  // real 2x2 (H, RY)
+    PAIR_RX = 3,    // [[c, -i s], [-i s, c]]
+    PAIR_DENSE = 4  // complex 2x2 (U2 and anything else)
+};
+
+// Operation kinds of the single-member (subset-diagonal) kernel.
+enum OneOp : int {
+    ONE_NEG = 0,   // a -> -a (Z, CZ)
+    ONE_MULI = 1,  // a -> s * i * a with s = +-1 (S, S^dagger)
+    ONE_MUL = 2    // a -> z * a (T, PHASE, controlled phase)
+};
+
+template <typename T>
+struct Coef2 {  // 2x2 complex, row-major interleaved: m00 m01 m10 m11
+    T m[8];
+};
+
+template <typename T>
+struct Coef4 {  // 4x4 complex
+    T m[32];
+};
+
+template <typename T>
+struct DiagSpec {  // element-wise diagonal on up to 3 target bits
+    int32_t k;
+    int32_t tq[3];  // tq[0] is the most significant bit of the entry index
+    T d[16];        // 2^k complex entries
+};
+
+template <typename T, int K>
+struct GeneralSpec {  // dense 2^K x 2^K, all groups, no structure used
+    uint64_t off[1 << K];
+    T m[2 * (1 << K) * (1 << K)];
+};
+
+// Row a2 of the method on the device: group index -> base amplitude index.
+__device__ __forceinline__ uint64_t group_base(uint64_t g, const GroupSpec& gs)
+{
+#pragma unroll
+    for (int i = 0; i < kMaxIns; ++i) {
+        if (i < gs.nins) {
+            const int p = gs.pos[i];
+            const uint64_t lo = g & ((1ull << p) - 1ull);
+            g = ((g >> p) << (p + 1)) | lo;
+        }
+    }
+    return g | gs.set_mask;
+}
+
+struct Launch {
+    int block;   // threads per block
+    int unroll;  // groups per thread
+};
+
+// ---- launchers (k_gates.hip) --------------------------------------------
+template <typename T>
+hipError_t launch_pair(void* psi, const GroupSpec& gs, uint64_t o0, uint64_t o1, int op,
+                       const Coef2<T>& c, hipStream_t s, Launch lc);
+template <typename T>
+hipError_t launch_one(void* psi, const GroupSpec& gs, int op, T zr, T zi, hipStream_t s, Launch lc);
+template <typename T>
+hipError_t launch_diag(void* psi, const GroupSpec& gs, const DiagSpec<T>& d, hipStream_t s, Launch lc);
+template <typename T>
+hipError_t launch_quad(void* psi, const GroupSpec& gs, const uint64_t off[4], const Coef4<T>& c,
+                       hipStream_t s, Launch lc);
+template <typename T>
+hipError_t launch_general(void* psi, const GroupSpec& gs, int k, const uint64_t* off, const T* m,
+                          hipStream_t s, Launch lc);
+template <typename T>
+hipError_t launch_set_basis(void* psi, uint64_t n_amps, uint64_t index, hipStream_t s);
+
+// ---- reductions (k_reduce.hip) -------------------------------------------
+constexpr int kReduceBlocks = 1024;  // fixed stage-1 grid: results are order-stable
+constexpr int kReduceThreads = 256;
+
+template <typename T>
+hipError_t launch_norm_partial(const void* psi, uint64_t n_amps, double* partials, hipStream_t s);
+// One Pauli term: xmask == 0 -> sum |a|^2 (-1)^{pc(x&z)}; else paired form.
+template <typename T>
+hipError_t launch_pauli_partial(const void* psi, int n, uint64_t xmask, uint64_t zmask, int ny,
+                                double coeff, double* partials, hipStream_t s);
+// Diagonal observable sum_k c_k (-1)^{pc(x & z_k)}; kind 1 = sum Z, 2 = sum ZZ
+// (closed forms, scaled by coeff), 0 = generic list of at most
+// kDiagTermsPerPass host terms (passed by value in the kernel arguments).
+constexpr int kDiagTermsPerPass = 32;
+template <typename T>
+hipError_t launch_diag_obs_partial(const void* psi, int n, int kind, double coeff,
+                                   const double* hcoef, const uint64_t* hz, int nterms,
+                                   double* partials, hipStream_t s);
+// Number of stage-1 blocks (= partials written) for n_items work items.
+int reduce_blocks_for(uint64_t n_items);
+hipError_t launch_sum_partials(const double* partials, int count, double* out, hipStream_t s);
+hipError_t launch_sum_segments(const double* partials, int seg_len, int n_seg, const double* scale,
+                               double* out, hipStream_t s);
+
+// ---- circuits / adjoint (k_adjoint.hip) -----------------------------------
+// Generator kinds of parameterised ops: the gradient is
+// scale * Im <lambda| G |phi> over the op's control subspace.
+enum GenKind : int { GEN_X = 0, GEN_Y = 1, GEN_Z = 2, GEN_P1 = 3 };
+
+// Fused reverse step of a parameterised one-target op: per group reads phi and
+// lambda once, adds Im <lambda|G|phi> to a block partial, applies U^dagger to
+// both and writes them back.  Exactly `nblocks` partials are written.
+template <typename T>
+hipError_t launch_adj_rot(void* phi, void* lam, const GroupSpec& gs, uint64_t off, int gen,
+                          const Coef2<T>& udag, double* partials, int nblocks, hipStream_t s);
+// lam = O psi for a diagonal observable (kind as launch_diag_obs_partial).
+template <typename T>
+hipError_t launch_obs_diag_apply(const void* psi, void* lam, int n, int kind, double coeff,
+                                 const double* hcoef, const uint64_t* hz, int nterms, int accumulate,
+                                 hipStream_t s);
+// lam += coeff * P psi for one Pauli term with xmask != 0.
+template <typename T>
+hipError_t launch_obs_pauli_apply(const void* psi, void* lam, int n, uint64_t xmask, uint64_t zmask,
+                                  int ny, double coeff, hipStream_t s);
+// Re <a|b> block partials (fp64).
+template <typename T>
+hipError_t launch_inner_partial(const void* a, const void* b, uint64_t n_amps, double* partials,
+                                hipStream_t s);
+// grad[j] = sum over slots s with slot_param[s] == j of slot_scale[s] * slot_val[s],
+// slots in ascending order (device arrays).
+hipError_t launch_scatter_grads(const double* slot_val, const int* slot_param, const double* slot_scale,
+                                int n_slots, double* grad, int n_params, hipStream_t s);
+
+// ---- helpers ----------------------------------------------------------------
+sv_status set_error(sv_status st, const std::string& msg);
+
+}  // namespace svk

@@ -1,0 +1,160 @@
+"""Host-side tests of the C ABI: the library loads, exports every symbol
+include/sv.h declares, and rejects bad arguments before any device work.
+
+No compute call is made: states are wrapped around a dummy, never
+dereferenced address, and every call below fails validation on the host.
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+sv = pytest.importorskip("paper_2508_13615_amd", reason="libsv.so not built")
+from paper_2508_13615_amd import _lib  # noqa: E402
+
+lib = sv.lib
+OK, ARG, QUBIT, OOM, HIP, UNSUP, HANDLE = range(7)
+FAKE = 0x100000  # 16-byte aligned, never dereferenced by validation paths
+
+
+def header_symbols():
+    txt = open(os.path.join(ROOT, "include", "sv.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(sv_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_every_declared_symbol_is_exported():
+    syms = header_symbols()
+    assert len(syms) >= 25
+    for s in syms:
+        assert hasattr(lib, s), f"libsv.so does not export {s}"
+    assert sorted(_lib.EXPORTS) == syms
+
+
+def test_library_is_the_in_tree_build():
+    assert os.path.dirname(_lib.LIB_PATH) == os.path.join(ROOT, "paper_2508_13615_amd")
+
+
+def test_one_hip_runtime_in_process():
+    maps = open("/proc/self/maps").read()
+    hips = {l.split()[-1] for l in maps.splitlines() if "libamdhip64" in l}
+    assert len(hips) == 1, hips
+
+
+def test_state_bytes_matches_paper_memory_figures():
+    # Sec. 1: a 30-qubit state needs about 16 GB, a 40-qubit one about 16 TB
+    # (complex128, 16 bytes per amplitude).
+    assert lib.sv_state_bytes(30, 2) == 16 * 2 ** 30
+    assert lib.sv_state_bytes(40, 2) == 16 * 2 ** 40
+    assert lib.sv_state_bytes(30, 1) == 8 * 2 ** 30
+    assert lib.sv_state_bytes(0, 2) == 0 and lib.sv_state_bytes(41, 2) == 0 and lib.sv_state_bytes(10, 3) == 0
+
+
+def wrap(n=6, dtype=2):
+    h = ctypes.c_void_p()
+    assert lib.sv_wrap(ctypes.c_void_p(FAKE), n, dtype, None, ctypes.byref(h)) == OK
+    return h
+
+
+def ints(*q):
+    return (ctypes.c_int * max(1, len(q)))(*q)
+
+
+def test_wrap_validation():
+    h = ctypes.c_void_p()
+    assert lib.sv_wrap(ctypes.c_void_p(FAKE), 0, 2, None, ctypes.byref(h)) == ARG
+    assert lib.sv_wrap(ctypes.c_void_p(FAKE), 41, 2, None, ctypes.byref(h)) == ARG
+    assert lib.sv_wrap(ctypes.c_void_p(FAKE), 5, 7, None, ctypes.byref(h)) == ARG
+    assert lib.sv_wrap(ctypes.c_void_p(FAKE + 8), 5, 2, None, ctypes.byref(h)) == ARG
+    assert lib.sv_wrap(None, 5, 2, None, ctypes.byref(h)) == ARG
+    assert lib.sv_wrap(ctypes.c_void_p(FAKE), 5, 2, None, None) == ARG
+    assert lib.sv_alloc(0, 2, None, ctypes.byref(h)) == ARG
+    assert lib.sv_alloc(41, 2, None, ctypes.byref(h)) == ARG
+
+
+def test_gate_validation():
+    h = wrap(6)
+    p = (ctypes.c_double * 1)(0.3)
+    try:
+        assert lib.sv_apply_gate(h, 1, ints(6), 1, None, None, 0) == QUBIT
+        assert lib.sv_apply_gate(h, 1, ints(-1), 1, None, None, 0) == QUBIT
+        assert lib.sv_apply_gate(h, 11, ints(2, 2), 2, None, None, 0) == QUBIT  # repeated
+        assert lib.sv_apply_controlled(h, 1, ints(3), 1, ints(3), 1, None, None, 0) == QUBIT  # control = target
+        assert lib.sv_apply_gate(h, 1, ints(0, 1), 2, None, None, 0) == ARG  # X takes 1 target
+        assert lib.sv_apply_gate(h, 11, ints(0), 1, None, None, 0) == ARG  # SWAP takes 2
+        assert lib.sv_apply_gate(h, 99, ints(0), 1, None, None, 0) == ARG
+        assert lib.sv_apply_gate(h, 8, ints(0), 1, None, None, 0) == ARG  # RY without params
+        assert lib.sv_apply_gate(h, 12, ints(0), 1, p, None, 0) == ARG  # U2 without matrix
+        assert lib.sv_apply_gate(h, 1, None, 1, None, None, 0) == ARG
+        ctl = ints(*range(1, 10))
+        assert lib.sv_apply_controlled(h, 1, ctl, 9, ints(0), 1, None, None, 0) == ARG  # > 8 controls
+        m = (ctypes.c_double * 128)()
+        assert lib.sv_apply_general(h, ints(0, 1, 2, 3), 4, m) == ARG  # k > 3
+        assert lib.sv_apply_general(h, ints(0), 1, None) == ARG
+        assert lib.sv_apply_general(h, ints(0, 0), 2, m) == QUBIT
+        assert lib.sv_set_basis(h, 64) == ARG
+    finally:
+        assert lib.sv_free(h) == OK
+
+
+def test_measurement_validation():
+    h = wrap(4)
+    out = ctypes.c_double()
+    try:
+        assert lib.sv_expval_pauli(h, b"Z", ints(4), 1, ctypes.byref(out)) == QUBIT
+        assert lib.sv_expval_pauli(h, b"Q", ints(0), 1, ctypes.byref(out)) == ARG
+        assert lib.sv_expval_pauli(h, b"ZZ", ints(1, 1), 2, ctypes.byref(out)) == QUBIT
+        assert lib.sv_norm2(h, None) == ARG
+        c = (ctypes.c_double * 1)(1.0)
+        x = (ctypes.c_uint64 * 1)(0)
+        z = (ctypes.c_uint64 * 1)(1 << 4)  # outside a 4-qubit state
+        obs = _lib.SvObs(1, c, x, z)
+        assert lib.sv_expval_obs(h, ctypes.byref(obs), ctypes.byref(out)) == QUBIT
+        assert lib.sv_expval_obs(h, None, ctypes.byref(out)) == ARG
+    finally:
+        lib.sv_free(h)
+
+
+def test_handle_errors():
+    h = wrap(3)
+    assert lib.sv_free(h) == OK
+    assert lib.sv_free(h) == HANDLE
+    assert lib.sv_apply_gate(h, 1, ints(0), 1, None, None, 0) == HANDLE
+    assert lib.sv_set_basis(ctypes.c_void_p(0xdead0), 0) == HANDLE
+    assert lib.sv_circuit_free(ctypes.c_void_p(0)) == HANDLE
+    assert b"invalid" in lib.sv_last_error()
+
+
+def test_circuit_create_validation_is_host_side():
+    ops = (_lib.SvOp * 1)()
+    ops[0].gate = 8
+    ops[0].n_controls = 0
+    ops[0].n_targets = 1
+    ops[0].param_index = 3  # out of range for n_params = 2
+    ops[0].qubits[0] = 0
+    h = ctypes.c_void_p()
+    assert lib.sv_circuit_create(4, ops, 1, 2, ctypes.byref(h)) == ARG
+    ops[0].param_index = 0
+    ops[0].qubits[0] = 9
+    assert lib.sv_circuit_create(4, ops, 1, 2, ctypes.byref(h)) == QUBIT
+    ops[0].gate = 1  # X takes no parameter
+    ops[0].qubits[0] = 0
+    assert lib.sv_circuit_create(4, ops, 1, 2, ctypes.byref(h)) == ARG
+
+
+def test_tuning_table_validation():
+    b, u = ctypes.c_int(), ctypes.c_int()
+    assert lib.sv_tune_get(0, 2, 2, ctypes.byref(b), ctypes.byref(u)) == OK
+    assert b.value % 64 == 0 and u.value in (1, 2, 4, 8)
+    assert lib.sv_tune_set(0, 2, 2, 100, 4) == ARG
+    assert lib.sv_tune_set(0, 2, 2, 256, 3) == ARG
+    assert lib.sv_tune_set(9, 2, 2, 256, 4) == ARG
+    assert lib.sv_tune_set(0, 2, 2, b.value, u.value) == OK
+
+
+def test_status_strings():
+    assert lib.sv_status_string(4) == b"SV_ERR_HIP"
+    assert lib.sv_version() >= 1
