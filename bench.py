@@ -1,0 +1,389 @@
+#!/usr/bin/env python
+"""Benchmark of the state-vector hot path on one MI355X.
+
+One step = one pass of the single-gate sweep on a 30-qubit complex128 state
+(16 GiB, seeded complex Gaussian, normalised): every gate class (H, X, Z, RZ,
+RY, U2, CNOT, SWAP, U4, Toffoli) on every target 0..29, with the second qubit
+or controls drawn from {0, 15, 29}; each case runs through the gate-specific
+kernel and through the general dense kernel (the paper's two approaches,
+Sec. 3.1), and the step ends with one expectation value (sum_i Z_i Z_{i+1}).
+`value` is gates/s of the gate-specific kernels over the timed steps.
+
+Also reported on the same JSON line:
+  roofline      the dominant kernel's algorithmic bytes per launch over its
+                average HIP-event-timed launch duration, against 8 TB/s;
+  copy          a device-to-device copy of the state (the measured ceiling);
+  cpu_baseline  the oracle on the host cores on a bounded sample;
+  adjoint       config "24 qubits, 8 layers RY+RZ + CNOT ladder, 384 params,
+                sum Z_i Z_{i+1}": one adjoint-gradient call vs parameter shift
+                (2 forward+expval runs per parameter) on the same GPU.
+Progress lines go to stderr; stdout carries only the JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "gates/sec & effective HBM GB/s at 30 qubits c128; adjoint grad vs param-shift s"
+PEAK_GBPS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+# kernel instantiation each gate case runs (default launch table: unroll 4 for
+# the paired / subset / diagonal classes, 2 for two-target and general)
+def kernel_of(gate, nc, general_k=0):
+    if general_k:
+        return f"k_general<double, {general_k}, 2>"
+    if gate in ("X", "SWAP"):
+        return "k_pair<double, 0 (move), 4>"
+    if gate in ("H", "RY"):
+        return "k_pair<double, 2 (real), 4>"
+    if gate == "U2":
+        return "k_pair<double, 4 (dense), 4>"
+    if gate == "Z":
+        return "k_one<double, 0 (neg), 4>"
+    if gate == "RZ":
+        return "k_diag<double, 4>"
+    if gate == "U4":
+        return "k_quad<double, 2>"
+    return gate
+
+
+def touched_fraction(gate, nc):
+    """Fraction of amplitudes a gate-specific kernel reads and writes."""
+    if gate in ("X", "H", "RY", "RZ", "U2", "U4"):
+        return 1.0 / (2 ** nc)
+    if gate in ("Z", "SWAP"):
+        return 0.5 / (2 ** nc)
+    return 1.0
+
+
+def sweep_cases(n, rng, W):
+    cases = []
+    for t in range(n):
+        for g in ("H", "X", "Z", "RZ", "RY", "U2"):
+            p = (float(rng.uniform(0, 2 * math.pi)),) if g in ("RZ", "RY") else ()
+            m = W.haar_unitary(1, rng) if g == "U2" else None
+            cases.append((g, (t,), (), p, m))
+        sec = W.second_qubit_choices(t, n)
+        for c in sec:
+            cases.append(("X", (t,), (c,), (), None))            # CNOT c -> t
+            cases.append(("SWAP", (t, c), (), (), None))
+            cases.append(("U4", (t, c), (), (), W.haar_unitary(2, rng)))
+        for i in range(len(sec)):
+            for j in range(i + 1, len(sec)):
+                cases.append(("X", (t,), (sec[i], sec[j]), (), None))  # Toffoli
+    return cases
+
+
+def dense_of(case, oracle_free_matrix):
+    """Dense matrix on (controls..., targets...) for the general kernel; built
+    from the gate definitions in this file's own small table."""
+    import numpy as np
+    g, tg, ct, p, m = case
+    r2 = math.sqrt(0.5)
+    if g == "U2" or g == "U4":
+        u = np.asarray(m, dtype=np.complex128)
+    elif g == "X":
+        u = np.array([[0, 1], [1, 0]], dtype=np.complex128)
+    elif g == "H":
+        u = np.array([[r2, r2], [r2, -r2]], dtype=np.complex128)
+    elif g == "Z":
+        u = np.diag([1, -1]).astype(np.complex128)
+    elif g == "RZ":
+        u = np.diag([np.exp(-0.5j * p[0]), np.exp(0.5j * p[0])])
+    elif g == "RY":
+        c, s = math.cos(p[0] / 2), math.sin(p[0] / 2)
+        u = np.array([[c, -s], [s, c]], dtype=np.complex128)
+    elif g == "SWAP":
+        u = np.eye(4, dtype=np.complex128)[[0, 2, 1, 3]]
+    else:
+        raise ValueError(g)
+    k = len(ct)
+    if k:
+        # controlled-U on (controls..., targets...): identity except the last block
+        d = 2 ** (k + len(tg))
+        full = np.eye(d, dtype=np.complex128)
+        full[d - u.shape[0]:, d - u.shape[0]:] = u
+        u = full
+    return tuple(ct) + tuple(tg), np.ascontiguousarray(u)
+
+
+def run_sweep(sv, torch, state, cases, denses, timed, rec):
+    """One step.  rec[key] accumulates (seconds, bytes, launches) per kernel."""
+    stream = torch.cuda.current_stream()
+    ev = []
+    for i, case in enumerate(cases):
+        g, tg, ct, p, m = case
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        e0.record(stream)
+        state.apply(g, tg, ct, p, m)
+        e1.record(stream)
+        qs, u = denses[i]
+        state.apply_general(qs, u)
+        e2.record(stream)
+        ev.append((case, e0, e1, e2, len(qs)))
+    e3 = torch.cuda.Event(enable_timing=True)
+    e3.record(stream)
+    zz = [(1.0, "ZZ", (q, q + 1)) for q in range(state.n - 1)]
+    state.expval(zz)
+    e4 = torch.cuda.Event(enable_timing=True)
+    e4.record(stream)
+    torch.cuda.synchronize()
+    if not timed:
+        return
+    S = (1 << state.n) * 16
+    for case, e0, e1, e2, k in ev:
+        g, tg, ct, p, m = case
+        ts = e0.elapsed_time(e1) * 1e-3
+        tgen = e1.elapsed_time(e2) * 1e-3
+        b = 2 * S * touched_fraction(g, len(ct))
+        name = g if not ct else ({1: "CNOT", 2: "Toffoli"}[len(ct)] if g == "X" else g)
+        for key, t, byt in ((("specific", name, kernel_of(g, len(ct))), ts, b),
+                            (("general", name, kernel_of(g, len(ct), k)), tgen, 2 * S)):
+            a = rec.setdefault(key, [0.0, 0.0, 0])
+            a[0] += t
+            a[1] += byt
+            a[2] += 1
+    a = rec.setdefault(("expval", "sumZZ", "k_diag_obs_partial<double>"), [0.0, 0.0, 0])
+    a[0] += e3.elapsed_time(e4) * 1e-3
+    a[1] += S
+    a[2] += 1
+
+
+def measure_copy(sv, torch, state):
+    other = sv.State(state.n, state.dtype, basis=None)
+    other.copy_from(state)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(3):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        other.copy_from(state)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1) * 1e-3)
+    del other
+    torch.cuda.empty_cache()
+    t = sorted(ts)[1]
+    return 2 * state.tensor.numel() * state.tensor.element_size() / t / 1e9
+
+
+def cpu_baseline(qubits_cpu, qubits_gpu):
+    import numpy as np
+    import oracle
+    import workloads as W
+    psi = W.gaussian_state(qubits_cpu, 1001)
+    sample = []
+    ts = [0, qubits_cpu // 2, qubits_cpu - 1]
+    for t in ts:
+        c = 0 if t != 0 else qubits_cpu // 2
+        c2 = qubits_cpu - 1 if t != qubits_cpu - 1 else qubits_cpu // 2
+        sample += [("X", (t,), ()), ("H", (t,), ()), ("RZ", (t,), (), (0.7,)), ("X", (t,), (c,)),
+                   ("Z", (t,), (c,)), ("X", (t,), (c, c2))]
+    oracle.apply_gate(psi, "H", (1,))  # warm-up
+    t0 = time.perf_counter()
+    for s in sample:
+        oracle.apply_gate(psi, s[0], s[1], s[2], s[3] if len(s) > 3 else ())
+    dt = time.perf_counter() - t0
+    rate = len(sample) / dt * 2.0 ** (qubits_cpu - qubits_gpu)
+    return {"value": rate, "unit": "gates/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": (f"X, H, RZ, CNOT, CZ, Toffoli at t in {ts} on a {qubits_cpu}-qubit complex128 Gaussian "
+                       f"state ({len(sample)} gates, {dt:.1f} s), rate scaled by 2^{qubits_cpu - qubits_gpu} "
+                       f"to {qubits_gpu} qubits (work is linear in the amplitude count)")}
+
+
+def adjoint_compare(sv, torch, n, layers, ps_params, full_ps):
+    import numpy as np
+    import workloads as W
+    ops = W.hea_ops(n, layers)
+    npar = W.hea_n_params(n, layers)
+    th = W.uniform_angles(npar, 1005)
+    obs = W.sum_zz(n)
+    out = {"qubits": n, "layers": layers, "params": npar, "ops": len(ops), "observable": "sum_i Z_i Z_{i+1}"}
+    circ = sv.Circuit(n, ops, npar)
+    grads = {}
+    for dt in ("c128", "c64"):
+        psi, lam = sv.State(n, dt), sv.State(n, dt)
+        circ.adjoint_grad(psi, lam, th, obs)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        psi.set_basis(0)
+        e, g = circ.adjoint_grad(psi, lam, th, obs)
+        t_adj = time.perf_counter() - t0
+        grads[dt] = (e, g)
+        out[f"adjoint_s_{dt}"] = t_adj
+        del psi, lam
+    # parameter shift on the same GPU, same kernels: 2 forward+expval runs per parameter
+    which = list(range(npar)) if full_ps else list(np.random.default_rng(1007).choice(npar, ps_params, replace=False))
+    res = {}
+    for dt in ("c128", "c64"):
+        s = sv.State(n, dt)
+        sobs = sv.Observable(obs)
+        p = th.copy()
+        s.set_basis(0)
+        circ.apply(s, p)
+        s.expval(sobs)  # warm-up
+        torch.cuda.synchronize()
+        gps = np.zeros(len(which))
+        t0 = time.perf_counter()
+        for i, j in enumerate(which):
+            p[j] = th[j] + math.pi / 2
+            s.set_basis(0)
+            circ.apply(s, p)
+            ep = s.expval(sobs)
+            p[j] = th[j] - math.pi / 2
+            s.set_basis(0)
+            circ.apply(s, p)
+            em = s.expval(sobs)
+            p[j] = th[j]
+            gps[i] = (ep - em) / 2
+        t_ps = time.perf_counter() - t0
+        res[dt] = gps
+        out[f"param_shift_s_{dt}_measured"] = t_ps
+        out[f"param_shift_s_{dt}"] = t_ps * npar / len(which)
+        del s
+    out["param_shift_params_timed"] = len(which)
+    out["param_shift_extrapolated"] = len(which) != npar
+    ref = res["c128"]
+    out["max_abs_err_adjoint_c128_vs_ps_c128"] = float(np.max(np.abs(grads["c128"][1][which] - ref)))
+    out["max_abs_err_adjoint_c64_vs_ps_c128"] = float(np.max(np.abs(grads["c64"][1][which] - ref)))
+    out["max_abs_err_ps_c64_vs_ps_c128"] = float(np.max(np.abs(res["c64"] - ref)))
+    out["expval_c128"] = grads["c128"][0]
+    out["speedup_c128"] = out["param_shift_s_c128"] / out["adjoint_s_c128"]
+    out["speedup_c64"] = out["param_shift_s_c64"] / out["adjoint_s_c64"]
+    torch.cuda.empty_cache()
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--qubits", type=int, default=30)
+    ap.add_argument("--cpu-qubits", type=int, default=26)
+    ap.add_argument("--skip-cpu-baseline", action="store_true")
+    ap.add_argument("--skip-adjoint", action="store_true")
+    ap.add_argument("--adjoint-qubits", type=int, default=24)
+    ap.add_argument("--adjoint-layers", type=int, default=8)
+    ap.add_argument("--ps-params", type=int, default=48, help="parameters timed with parameter shift")
+    ap.add_argument("--full-param-shift", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the state-vector path here is built and measured on a single "
+              "MI355X (the multi-GPU sharding is a design note only); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2508_13615_amd as sv
+    import workloads as W
+
+    torch.cuda.set_device(0)
+    n = args.qubits
+    log(f"[bench] allocating {n}-qubit complex128 state ({(1 << n) * 16 / 2**30:.1f} GiB)")
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(1001)
+    t = torch.randn(1 << n, dtype=torch.complex128, device="cuda", generator=gen)
+    t /= torch.linalg.vector_norm(t)
+    state = sv.State(n, "c128", tensor=t, basis=None)
+    rng = np.random.default_rng(1002)
+    cases = sweep_cases(n, rng, W)
+    denses = [dense_of(c, None) for c in cases]
+    log(f"[bench] {len(cases)} gate cases per step (+ {len(cases)} general-kernel runs + 1 expval)")
+    copy_gbps = measure_copy(sv, torch, state)
+    log(f"[bench] device copy ceiling {copy_gbps:.0f} GB/s")
+
+    rec = {}
+    for w in range(args.warmup):
+        run_sweep(sv, torch, state, cases, denses, False, rec)
+        log(f"[bench] warmup {w + 1}/{args.warmup} done")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        run_sweep(sv, torch, state, cases, denses, True, rec)
+        log(f"[bench] step {k + 1}/{args.steps} done")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    norm = state.norm2()
+
+    spec = {k: v for k, v in rec.items() if k[0] == "specific"}
+    gen_ = {k: v for k, v in rec.items() if k[0] == "general"}
+    t_spec = sum(v[0] for v in spec.values())
+    t_gen = sum(v[0] for v in gen_.values())
+    n_spec = sum(v[2] for v in spec.values())
+    b_spec = sum(v[1] for v in spec.values())
+    per_class = {}
+    for (kind, name, kern), (tt, bb, cnt) in sorted(rec.items()):
+        d = per_class.setdefault(name, {})
+        d[kind] = {"kernel": kern, "launches": cnt, "avg_ms": 1e3 * tt / cnt, "gates_per_s": cnt / tt,
+                   "GBps": bb / tt / 1e9, "frac_of_8TBps": bb / tt / 1e9 / PEAK_GBPS}
+    for name, d in per_class.items():
+        if "specific" in d and "general" in d:
+            d["speedup_specific_vs_general"] = d["general"]["avg_ms"] / d["specific"]["avg_ms"]
+    # dominant kernel: the instantiation with the largest total time
+    by_kernel = {}
+    for (kind, name, kern), (tt, bb, cnt) in rec.items():
+        a = by_kernel.setdefault(kern, [0.0, 0.0, 0])
+        a[0] += tt
+        a[1] += bb
+        a[2] += cnt
+    dom = max(by_kernel.items(), key=lambda kv: kv[1][0])
+    dk, (dt_, db, dc) = dom
+    achieved = db / dt_ / 1e9
+    roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_GBPS, "unit": "GB/s", "frac": achieved / PEAK_GBPS,
+            "traffic": None, "kernel": dk, "launches": dc, "avg_launch_ms": 1e3 * dt_ / dc,
+            "algorithmic_bytes_per_launch": db / dc}
+
+    out = {
+        "metric": METRIC,
+        "value": n_spec / t_spec,
+        "unit": "gates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * wall / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"single-gate sweep, {n} qubits complex128 (seeded Gaussian state), gate-specific "
+                               f"and general kernels", "qubits": n, "state_GiB": (1 << n) * 16 / 2**30,
+                   "gate_classes": ["H", "X", "Z", "RZ", "RY", "U2", "CNOT", "SWAP", "U4", "Toffoli"],
+                   "targets": f"0..{n - 1}", "second_qubits": [0, n // 2, n - 1], "cases_per_step": len(cases)},
+        "effective_GBps": b_spec / t_spec / 1e9,
+        "effective_frac_of_8TBps": b_spec / t_spec / 1e9 / PEAK_GBPS,
+        "general_gates_per_s": sum(v[2] for v in gen_.values()) / t_gen,
+        "copy_GBps": copy_gbps,
+        "per_class": per_class,
+        "roofline": roof,
+        "norm_after": norm,
+    }
+    del state, t
+    torch.cuda.empty_cache()
+    if not args.skip_adjoint:
+        log(f"[bench] adjoint vs parameter shift at {args.adjoint_qubits} qubits")
+        out["adjoint"] = adjoint_compare(sv, torch, args.adjoint_qubits, args.adjoint_layers, args.ps_params,
+                                         args.full_param_shift)
+        log("[bench] adjoint comparison done")
+    if not args.skip_cpu_baseline:
+        log(f"[bench] oracle CPU baseline at {args.cpu_qubits} qubits")
+        out["cpu_baseline"] = cpu_baseline(args.cpu_qubits, n)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

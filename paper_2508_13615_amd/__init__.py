@@ -108,7 +108,7 @@ class State:
 
     def __del__(self):
         h = getattr(self, "handle", None)
-        if h is not None and h.value:
+        if h is not None and h.value and lib is not None:
             lib.sv_free(h)
             self.handle = None
 
@@ -208,7 +208,7 @@ class Circuit:
 
     def __del__(self):
         h = getattr(self, "handle", None)
-        if h is not None and h.value:
+        if h is not None and h.value and lib is not None:
             lib.sv_circuit_free(h)
             self.handle = None
 

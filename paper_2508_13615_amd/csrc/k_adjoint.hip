@@ -122,9 +122,9 @@ k_obs_diag_apply(const typename Vec2<T>::type* __restrict__ psi, typename Vec2<T
     for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n_amps; x += stride) {
         double o;
         if (kind == 1) {
-            o = (double)(nq - 2 * __popcll(x));
+            o = (double)(nq - 2 * (int)__popcll(x));
         } else if (kind == 2) {
-            o = (double)((nq - 1) - 2 * __popcll((x ^ (x >> 1)) & zzmask));
+            o = (double)((nq - 1) - 2 * (int)__popcll((x ^ (x >> 1)) & zzmask));
         } else {
             o = 0.0;
             for (int k = 0; k < terms.nterms; ++k) o += (__popcll(x & terms.z[k]) & 1) ? -terms.c[k] : terms.c[k];

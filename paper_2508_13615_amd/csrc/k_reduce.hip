@@ -152,9 +152,9 @@ k_diag_obs_partial(const typename Vec2<T>::type* __restrict__ psi, uint64_t n_am
             if (x < n_amps) {
                 double o;
                 if (kind == 1) {
-                    o = (double)(nq - 2 * __popcll(x));
+                    o = (double)(nq - 2 * (int)__popcll(x));
                 } else if (kind == 2) {
-                    o = (double)((nq - 1) - 2 * __popcll((x ^ (x >> 1)) & zzmask));
+                    o = (double)((nq - 1) - 2 * (int)__popcll((x ^ (x >> 1)) & zzmask));
                 } else {
                     o = 0.0;
                     for (int k = 0; k < terms.nterms; ++k)

@@ -682,12 +682,17 @@ static hipError_t obs_passes(sv_state st, const ObsPlan& op, double* partials, i
     return e;
 }
 
+// Partials needed by the passes of an observable (worst case: one full
+// stage-1 grid per pass).
+static size_t obs_partials(const ObsPlan& op)
+{
+    return ((op.dc.size() + kDiagTermsPerPass - 1) / kDiagTermsPerPass + op.oc.size() + 1) * kReduceBlocks;
+}
+
+// The caller has reserved obs_partials(op) doubles of workspace; out_dev may
+// point into the workspace head, so nothing here may reallocate it.
 static sv_status expval_to_dev(sv_state st, const ObsPlan& op, double* out_dev)
 {
-    // worst case: one segment per pass
-    const size_t passes = (op.dc.size() + kDiagTermsPerPass - 1) / kDiagTermsPerPass + op.oc.size() + 1;
-    sv_status rc = ensure_work(st, passes * kReduceBlocks);
-    if (rc) return rc;
     int count = 0;
     double* partials = st->work + kWorkHead;
     hipError_t e = st->dtype == SV_C128 ? obs_passes<double>(st, op, partials, &count)
@@ -704,6 +709,8 @@ sv_status sv_expval_obs_dev(sv_state st, const sv_obs* obs, double* out_dev)
     ObsPlan op;
     sv_status rc = plan_obs(st->n, obs, &op);
     if (rc) return rc;
+    rc = ensure_work(st, obs_partials(op));
+    if (rc) return rc;
     return expval_to_dev(st, op, out_dev);
 }
 
@@ -714,7 +721,7 @@ sv_status sv_expval_obs(sv_state st, const sv_obs* obs, double* out)
     ObsPlan op;
     sv_status rc = plan_obs(st->n, obs, &op);
     if (rc) return rc;
-    rc = ensure_work(st, kReduceBlocks);
+    rc = ensure_work(st, obs_partials(op));
     if (rc) return rc;
     rc = expval_to_dev(st, op, st->work);
     if (rc) return rc;
@@ -743,7 +750,7 @@ sv_status sv_expval_pauli(sv_state st, const char* paulis, const int* qubits, in
     ObsPlan op;
     rc = plan_obs(st->n, &o, &op);
     if (rc) return rc;
-    rc = ensure_work(st, kReduceBlocks);
+    rc = ensure_work(st, obs_partials(op));
     if (rc) return rc;
     rc = expval_to_dev(st, op, st->work);
     if (rc) return rc;
