@@ -39,24 +39,25 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-# kernel instantiation each gate case runs (default launch table: unroll 4 for
-# the paired / subset / diagonal classes, 2 for two-target and general)
-def kernel_of(gate, nc, general_k=0):
+# The kernel instantiation a gate case runs: class and operation from the
+# library's gate classification, groups-per-thread and non-temporal flag from
+# its launch table (tier = bytes spanned by a run of touched amplitudes).
+_CLASS = {"X": (0, "k_pair", "0 move"), "SWAP": (0, "k_pair", "0 move"), "H": (0, "k_pair", "2 real"),
+          "RY": (0, "k_pair", "2 real"), "U2": (0, "k_pair", "4 dense"), "Z": (1, "k_one", "0 neg"),
+          "RZ": (2, "k_diag", ""), "U4": (3, "k_quad", "")}
+
+
+def kernel_of(sv, gate, tg, ct, general_k=0):
     if general_k:
-        return f"k_general<double, {general_k}, 2>"
-    if gate in ("X", "SWAP"):
-        return "k_pair<double, 0 (move), 4>"
-    if gate in ("H", "RY"):
-        return "k_pair<double, 2 (real), 4>"
-    if gate == "U2":
-        return "k_pair<double, 4 (dense), 4>"
-    if gate == "Z":
-        return "k_one<double, 0 (neg), 4>"
-    if gate == "RZ":
-        return "k_diag<double, 4>"
-    if gate == "U4":
-        return "k_quad<double, 2>"
-    return gate
+        kc, base, op, low = 4, "k_general", str(general_k), min(list(tg) + list(ct))
+    else:
+        kc, base, op = _CLASS[gate]
+        low = min(ct) if gate == "RZ" and ct else (64 if gate == "RZ" else min(list(tg) + list(ct)))
+    span = 16 << min(low, 40)
+    tier = 0 if span < 64 else (1 if span < 1024 else 2)
+    block, unroll, nt = sv.tune_get(kc, "c128", tier)
+    args = ", ".join(a for a in ("double", op, str(unroll), "true" if nt else "false") if a)
+    return f"{base}<{args}>"
 
 
 def touched_fraction(gate, nc):
@@ -119,7 +120,7 @@ def dense_of(case, oracle_free_matrix):
     return tuple(ct) + tuple(tg), np.ascontiguousarray(u)
 
 
-def run_sweep(sv, torch, state, cases, denses, timed, rec):
+def run_sweep(sv, torch, state, cases, denses, timed, rec, per_target):
     """One step.  rec[key] accumulates (seconds, bytes, launches) per kernel."""
     stream = torch.cuda.current_stream()
     ev = []
@@ -149,12 +150,16 @@ def run_sweep(sv, torch, state, cases, denses, timed, rec):
         tgen = e1.elapsed_time(e2) * 1e-3
         b = 2 * S * touched_fraction(g, len(ct))
         name = g if not ct else ({1: "CNOT", 2: "Toffoli"}[len(ct)] if g == "X" else g)
-        for key, t, byt in ((("specific", name, kernel_of(g, len(ct))), ts, b),
-                            (("general", name, kernel_of(g, len(ct), k)), tgen, 2 * S)):
+        qs = tuple(ct) + tuple(tg)
+        for key, t, byt in ((("specific", name, kernel_of(sv, g, tg, ct)), ts, b),
+                            (("general", name, kernel_of(sv, g, qs, (), k)), tgen, 2 * S)):
             a = rec.setdefault(key, [0.0, 0.0, 0])
             a[0] += t
             a[1] += byt
             a[2] += 1
+        if not ct and len(tg) == 1:
+            pt = per_target.setdefault(g, {})
+            pt.setdefault(tg[0], []).append((ts, tgen))
     a = rec.setdefault(("expval", "sumZZ", "k_diag_obs_partial<double>"), [0.0, 0.0, 0])
     a[0] += e3.elapsed_time(e4) * 1e-3
     a[1] += S
@@ -307,13 +312,14 @@ def main():
     log(f"[bench] device copy ceiling {copy_gbps:.0f} GB/s")
 
     rec = {}
+    per_target = {}
     for w in range(args.warmup):
-        run_sweep(sv, torch, state, cases, denses, False, rec)
+        run_sweep(sv, torch, state, cases, denses, False, rec, per_target)
         log(f"[bench] warmup {w + 1}/{args.warmup} done")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
-        run_sweep(sv, torch, state, cases, denses, True, rec)
+        run_sweep(sv, torch, state, cases, denses, True, rec, per_target)
         log(f"[bench] step {k + 1}/{args.steps} done")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -370,6 +376,10 @@ def main():
         "copy_GBps": copy_gbps,
         "per_class": per_class,
         "roofline": roof,
+        "per_target_ms": {g: {"specific": [round(1e3 * sum(x[0] for x in v[t]) / len(v[t]), 4) for t in sorted(v)],
+                              "general": [round(1e3 * sum(x[1] for x in v[t]) / len(v[t]), 4) for t in sorted(v)]}
+                          for g, v in per_target.items()},
+        "tuned_entries": sv.TUNED_ENTRIES,
         "norm_after": norm,
     }
     del state, t

@@ -231,15 +231,18 @@ sv_status sv_adjoint_grad(sv_circuit c, sv_state psi, sv_state lam, const double
                           const sv_obs* obs, double* expval_out, double* grad_out);
 
 /* ------------------------------------------------------------------------
- * Launch shapes.  Kernel classes: 0 paired (permutation / butterfly),
- * 1 subset phase, 2 element-wise diagonal, 3 two-target, 4 general.  Tier by
- * the lowest qubit a gate touches: 0 (< 3), 1 (< 6), 2 (>= 6).  block is a
- * multiple of 64 in [64, 1024]; unroll (groups per thread) is 1, 2, 4 or 8.
- * The table is process-wide; set it from one thread before launching work.
+ * Launch shapes (written by the autotuner, read by every gate launch).
+ * Kernel classes: 0 paired (permutation / butterfly), 1 subset phase,
+ * 2 element-wise diagonal, 3 two-target, 4 general.  Tier: bytes spanned by
+ * one run of consecutive touched amplitudes, 2^(lowest touched qubit) times
+ * the element size: 0 (< 64 B), 1 (< 1 KiB), 2 (larger).  block is a
+ * multiple of 64 in [64, 1024]; unroll (groups per thread) is 1, 2 or 4;
+ * nt = 1 makes the kernel's loads and stores non-temporal.  The table is
+ * process-wide; set it from one thread before launching work.
  * Errors: SV_ERR_ARG for a bad key or shape.
  * ------------------------------------------------------------------------ */
-sv_status sv_tune_set(int kernel_class, int dtype, int tier, int block, int unroll);
-sv_status sv_tune_get(int kernel_class, int dtype, int tier, int* block, int* unroll);
+sv_status sv_tune_set(int kernel_class, int dtype, int tier, int block, int unroll, int nt);
+sv_status sv_tune_get(int kernel_class, int dtype, int tier, int* block, int* unroll, int* nt);
 
 /* ------------------------------------------------------------------------
  * Diagnostics

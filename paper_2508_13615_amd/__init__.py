@@ -14,6 +14,7 @@ in the most significant bit of their index.
 from __future__ import annotations
 
 import ctypes
+import sys
 from typing import Iterable, List, Optional, Sequence, Tuple
 
 import numpy as np
@@ -49,14 +50,14 @@ def sv_version() -> int:
     return int(lib.sv_version())
 
 
-def tune_set(kernel_class: int, dtype: str, tier: int, block: int, unroll: int) -> None:
-    check(lib.sv_tune_set(kernel_class, _SV_DT[dtype], tier, block, unroll))
+def tune_set(kernel_class: int, dtype: str, tier: int, block: int, unroll: int, nt: int) -> None:
+    check(lib.sv_tune_set(kernel_class, _SV_DT[dtype], tier, block, unroll, nt))
 
 
-def tune_get(kernel_class: int, dtype: str, tier: int) -> Tuple[int, int]:
-    b, u = ctypes.c_int(), ctypes.c_int()
-    check(lib.sv_tune_get(kernel_class, _SV_DT[dtype], tier, ctypes.byref(b), ctypes.byref(u)))
-    return b.value, u.value
+def tune_get(kernel_class: int, dtype: str, tier: int) -> Tuple[int, int, int]:
+    b, u, t = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    check(lib.sv_tune_get(kernel_class, _SV_DT[dtype], tier, ctypes.byref(b), ctypes.byref(u), ctypes.byref(t)))
+    return b.value, u.value, t.value
 
 
 class Observable:
@@ -245,3 +246,10 @@ class AdjointExpval(torch.autograd.Function):
     def backward(ctx, grad_e):
         (g,) = ctx.saved_tensors
         return grad_e * g, None, None, None, None
+
+
+# Launch shapes measured by the autotuner (paper_2508_13615_amd/autotune.py),
+# applied once at import when the table exists.
+from . import autotune as _autotune  # noqa: E402
+
+TUNED_ENTRIES = _autotune.apply_table(sys.modules[__name__])

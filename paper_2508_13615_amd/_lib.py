@@ -86,8 +86,8 @@ def _load():
         "sv_batch_free": [vp],
         "sv_batch_run": [vp, vp, vp, vp, i],
         "sv_batch_info": [vp, ctypes.POINTER(ctypes.c_int64)],
-        "sv_tune_set": [i, i, i, i, i],
-        "sv_tune_get": [i, i, i, ip, ip],
+        "sv_tune_set": [i, i, i, i, i, i],
+        "sv_tune_get": [i, i, i, ip, ip, ip],
     }
     for name, args in sig.items():
         if hasattr(lib, name):

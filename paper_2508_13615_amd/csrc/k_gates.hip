@@ -16,9 +16,13 @@
 // All kernels are HBM-bound streams.  Each thread owns U groups spaced one
 // block apart, so every load instruction of a wavefront reads consecutive
 // groups; when the lowest inserted bit is >= 3 (complex128) those are whole
-// 128-byte lines, below that the U loads of a wave together cover every line
-// they touch.  All U groups are loaded before any is written, which keeps
-// 2*U independent 16-byte loads in flight per lane.
+// 128-byte lines, below that the loads of a wave together cover every line
+// they touch.  All U groups are loaded before any is written.  Measured on
+// MI355X at 30 qubits, one group per thread in small blocks with
+// non-temporal loads and stores streams fastest once the touched runs span
+// at least 64 bytes; below that (a gate or control on bit 0 or 1 of a
+// complex128 state) non-temporal accesses of partial lines cost up to 35%,
+// so the launch table (sv_api.hip) switches them off there.
 #include "sv_core.h"
 
 namespace svk {
@@ -69,7 +73,7 @@ __device__ __forceinline__ void pair_apply(const V a0, const V a1, const Coef2<T
     }
 }
 
-template <typename T, int OP, int U>
+template <typename T, int OP, int U, bool NT>
 __global__ void __launch_bounds__(1024)
 k_pair(typename Vec2<T>::type* __restrict__ psi, GroupSpec gs, uint64_t o0, uint64_t o1, Coef2<T> c)
 {
@@ -85,8 +89,8 @@ k_pair(typename Vec2<T>::type* __restrict__ psi, GroupSpec gs, uint64_t o0, uint
             const uint64_t g = g0 + (uint64_t)j * blockDim.x;
             if (g < gs.n_groups) {
                 b[j] = group_base(g, gs);
-                a0[j] = psi[b[j] + o0];
-                a1[j] = psi[b[j] + o1];
+                a0[j] = ldg<NT>(psi + b[j] + o0);
+                a1[j] = ldg<NT>(psi + b[j] + o1);
             }
         }
 #pragma unroll
@@ -95,14 +99,14 @@ k_pair(typename Vec2<T>::type* __restrict__ psi, GroupSpec gs, uint64_t o0, uint
             if (g < gs.n_groups) {
                 V r0, r1;
                 pair_apply<OP, T, V>(a0[j], a1[j], c, r0, r1);
-                psi[b[j] + o0] = r0;
-                psi[b[j] + o1] = r1;
+                stg<NT>(psi + b[j] + o0, r0);
+                stg<NT>(psi + b[j] + o1, r1);
             }
         }
     }
 }
 
-template <typename T, int OP, int U>
+template <typename T, int OP, int U, bool NT>
 __global__ void __launch_bounds__(1024)
 k_one(typename Vec2<T>::type* __restrict__ psi, GroupSpec gs, T zr, T zi)
 {
@@ -118,7 +122,7 @@ k_one(typename Vec2<T>::type* __restrict__ psi, GroupSpec gs, T zr, T zi)
             const uint64_t g = g0 + (uint64_t)j * blockDim.x;
             if (g < gs.n_groups) {
                 b[j] = group_base(g, gs);
-                a[j] = psi[b[j]];
+                a[j] = ldg<NT>(psi + b[j]);
             }
         }
 #pragma unroll
@@ -136,13 +140,13 @@ k_one(typename Vec2<T>::type* __restrict__ psi, GroupSpec gs, T zr, T zi)
                 } else {
                     r = cmul<V, T>(zr, zi, a[j]);
                 }
-                psi[b[j]] = r;
+                stg<NT>(psi + b[j], r);
             }
         }
     }
 }
 
-template <typename T, int U>
+template <typename T, int U, bool NT>
 __global__ void __launch_bounds__(1024)
 k_diag(typename Vec2<T>::type* __restrict__ psi, GroupSpec gs, DiagSpec<T> d)
 {
@@ -159,7 +163,7 @@ k_diag(typename Vec2<T>::type* __restrict__ psi, GroupSpec gs, DiagSpec<T> d)
             const uint64_t g = g0 + (uint64_t)j * blockDim.x;
             if (g < gs.n_groups) {
                 b[j] = group_base(g, gs);
-                a[j] = psi[b[j]];
+                a[j] = ldg<NT>(psi + b[j]);
             }
         }
 #pragma unroll
@@ -173,13 +177,13 @@ k_diag(typename Vec2<T>::type* __restrict__ psi, GroupSpec gs, DiagSpec<T> d)
                     zr = (e == i) ? d.d[2 * i] : zr;
                     zi = (e == i) ? d.d[2 * i + 1] : zi;
                 }
-                psi[b[j]] = cmul<V, T>(zr, zi, a[j]);
+                stg<NT>(psi + b[j], cmul<V, T>(zr, zi, a[j]));
             }
         }
     }
 }
 
-template <typename T, int U>
+template <typename T, int U, bool NT>
 __global__ void __launch_bounds__(1024)
 k_quad(typename Vec2<T>::type* __restrict__ psi, GroupSpec gs, uint64_t o1, uint64_t o2, uint64_t o3,
        Coef4<T> c)
@@ -196,10 +200,10 @@ k_quad(typename Vec2<T>::type* __restrict__ psi, GroupSpec gs, uint64_t o1, uint
             const uint64_t g = g0 + (uint64_t)j * blockDim.x;
             if (g < gs.n_groups) {
                 b[j] = group_base(g, gs);
-                a[j][0] = psi[b[j]];
-                a[j][1] = psi[b[j] + o1];
-                a[j][2] = psi[b[j] + o2];
-                a[j][3] = psi[b[j] + o3];
+                a[j][0] = ldg<NT>(psi + b[j]);
+                a[j][1] = ldg<NT>(psi + b[j] + o1);
+                a[j][2] = ldg<NT>(psi + b[j] + o2);
+                a[j][3] = ldg<NT>(psi + b[j] + o3);
             }
         }
 #pragma unroll
@@ -219,16 +223,16 @@ k_quad(typename Vec2<T>::type* __restrict__ psi, GroupSpec gs, uint64_t o1, uint
                     r[row].x = sr;
                     r[row].y = si;
                 }
-                psi[b[j]] = r[0];
-                psi[b[j] + o1] = r[1];
-                psi[b[j] + o2] = r[2];
-                psi[b[j] + o3] = r[3];
+                stg<NT>(psi + b[j], r[0]);
+                stg<NT>(psi + b[j] + o1, r[1]);
+                stg<NT>(psi + b[j] + o2, r[2]);
+                stg<NT>(psi + b[j] + o3, r[3]);
             }
         }
     }
 }
 
-template <typename T, int K, int U>
+template <typename T, int K, int U, bool NT>
 __global__ void __launch_bounds__(1024)
 k_general(typename Vec2<T>::type* __restrict__ psi, GroupSpec gs, GeneralSpec<T, K> sp)
 {
@@ -246,7 +250,7 @@ k_general(typename Vec2<T>::type* __restrict__ psi, GroupSpec gs, GeneralSpec<T,
             if (g < gs.n_groups) {
                 b[j] = group_base(g, gs);
 #pragma unroll
-                for (int r = 0; r < M; ++r) a[j][r] = psi[b[j] + sp.off[r]];
+                for (int r = 0; r < M; ++r) a[j][r] = ldg<NT>(psi + b[j] + sp.off[r]);
             }
         }
 #pragma unroll
@@ -265,7 +269,7 @@ k_general(typename Vec2<T>::type* __restrict__ psi, GroupSpec gs, GeneralSpec<T,
                     V r;
                     r.x = sr;
                     r.y = si;
-                    psi[b[j] + sp.off[row]] = r;
+                    stg<NT>(psi + b[j] + sp.off[row], r);
                 }
             }
         }
@@ -297,13 +301,25 @@ static dim3 grid_for(uint64_t n_groups, int block, int unroll)
     return dim3((unsigned)nb);
 }
 
-#define SV_UNROLL_SWITCH(lc, ...)                         \
-    switch ((lc).unroll) {                                \
-    case 1: { constexpr int UU = 1; __VA_ARGS__; } break; \
-    case 2: { constexpr int UU = 2; __VA_ARGS__; } break; \
-    case 8: { constexpr int UU = 8; __VA_ARGS__; } break; \
-    default: { constexpr int UU = 4; __VA_ARGS__; } break; \
-    }
+// Launch-shape dispatch: unroll U in {1, 2, 4} and the non-temporal flag.
+#define SV_SHAPE_SWITCH(lc, ...)                                                        \
+    do {                                                                                \
+        if ((lc).nt) {                                                                  \
+            constexpr bool NTT = true;                                                  \
+            switch ((lc).unroll) {                                                      \
+            case 1: { constexpr int UU = 1; __VA_ARGS__; } break;                       \
+            case 2: { constexpr int UU = 2; __VA_ARGS__; } break;                       \
+            default: { constexpr int UU = 4; __VA_ARGS__; } break;                      \
+            }                                                                           \
+        } else {                                                                        \
+            constexpr bool NTT = false;                                                 \
+            switch ((lc).unroll) {                                                      \
+            case 1: { constexpr int UU = 1; __VA_ARGS__; } break;                       \
+            case 2: { constexpr int UU = 2; __VA_ARGS__; } break;                       \
+            default: { constexpr int UU = 4; __VA_ARGS__; } break;                      \
+            }                                                                           \
+        }                                                                               \
+    } while (0)
 
 template <typename T>
 hipError_t launch_pair(void* psi, const GroupSpec& gs, uint64_t o0, uint64_t o1, int op, const Coef2<T>& c,
@@ -312,14 +328,15 @@ hipError_t launch_pair(void* psi, const GroupSpec& gs, uint64_t o0, uint64_t o1,
     using V = typename Vec2<T>::type;
     if (gs.n_groups == 0) return hipSuccess;
     V* p = (V*)psi;
-    SV_UNROLL_SWITCH(lc, {
+    SV_SHAPE_SWITCH(lc, {
         const dim3 grid = grid_for(gs.n_groups, lc.block, UU);
+        const dim3 blk(lc.block);
         switch (op) {
-        case PAIR_SWAP: hipLaunchKernelGGL((k_pair<T, PAIR_SWAP, UU>), grid, dim3(lc.block), 0, s, p, gs, o0, o1, c); break;
-        case PAIR_Y: hipLaunchKernelGGL((k_pair<T, PAIR_Y, UU>), grid, dim3(lc.block), 0, s, p, gs, o0, o1, c); break;
-        case PAIR_REAL: hipLaunchKernelGGL((k_pair<T, PAIR_REAL, UU>), grid, dim3(lc.block), 0, s, p, gs, o0, o1, c); break;
-        case PAIR_RX: hipLaunchKernelGGL((k_pair<T, PAIR_RX, UU>), grid, dim3(lc.block), 0, s, p, gs, o0, o1, c); break;
-        default: hipLaunchKernelGGL((k_pair<T, PAIR_DENSE, UU>), grid, dim3(lc.block), 0, s, p, gs, o0, o1, c); break;
+        case PAIR_SWAP: hipLaunchKernelGGL((k_pair<T, PAIR_SWAP, UU, NTT>), grid, blk, 0, s, p, gs, o0, o1, c); break;
+        case PAIR_Y: hipLaunchKernelGGL((k_pair<T, PAIR_Y, UU, NTT>), grid, blk, 0, s, p, gs, o0, o1, c); break;
+        case PAIR_REAL: hipLaunchKernelGGL((k_pair<T, PAIR_REAL, UU, NTT>), grid, blk, 0, s, p, gs, o0, o1, c); break;
+        case PAIR_RX: hipLaunchKernelGGL((k_pair<T, PAIR_RX, UU, NTT>), grid, blk, 0, s, p, gs, o0, o1, c); break;
+        default: hipLaunchKernelGGL((k_pair<T, PAIR_DENSE, UU, NTT>), grid, blk, 0, s, p, gs, o0, o1, c); break;
         }
     });
     return hipGetLastError();
@@ -331,12 +348,13 @@ hipError_t launch_one(void* psi, const GroupSpec& gs, int op, T zr, T zi, hipStr
     using V = typename Vec2<T>::type;
     if (gs.n_groups == 0) return hipSuccess;
     V* p = (V*)psi;
-    SV_UNROLL_SWITCH(lc, {
+    SV_SHAPE_SWITCH(lc, {
         const dim3 grid = grid_for(gs.n_groups, lc.block, UU);
+        const dim3 blk(lc.block);
         switch (op) {
-        case ONE_NEG: hipLaunchKernelGGL((k_one<T, ONE_NEG, UU>), grid, dim3(lc.block), 0, s, p, gs, zr, zi); break;
-        case ONE_MULI: hipLaunchKernelGGL((k_one<T, ONE_MULI, UU>), grid, dim3(lc.block), 0, s, p, gs, zr, zi); break;
-        default: hipLaunchKernelGGL((k_one<T, ONE_MUL, UU>), grid, dim3(lc.block), 0, s, p, gs, zr, zi); break;
+        case ONE_NEG: hipLaunchKernelGGL((k_one<T, ONE_NEG, UU, NTT>), grid, blk, 0, s, p, gs, zr, zi); break;
+        case ONE_MULI: hipLaunchKernelGGL((k_one<T, ONE_MULI, UU, NTT>), grid, blk, 0, s, p, gs, zr, zi); break;
+        default: hipLaunchKernelGGL((k_one<T, ONE_MUL, UU, NTT>), grid, blk, 0, s, p, gs, zr, zi); break;
         }
     });
     return hipGetLastError();
@@ -348,9 +366,8 @@ hipError_t launch_diag(void* psi, const GroupSpec& gs, const DiagSpec<T>& d, hip
     using V = typename Vec2<T>::type;
     if (gs.n_groups == 0) return hipSuccess;
     V* p = (V*)psi;
-    SV_UNROLL_SWITCH(lc, {
-        const dim3 grid = grid_for(gs.n_groups, lc.block, UU);
-        hipLaunchKernelGGL((k_diag<T, UU>), grid, dim3(lc.block), 0, s, p, gs, d);
+    SV_SHAPE_SWITCH(lc, {
+        hipLaunchKernelGGL((k_diag<T, UU, NTT>), grid_for(gs.n_groups, lc.block, UU), dim3(lc.block), 0, s, p, gs, d);
     });
     return hipGetLastError();
 }
@@ -362,9 +379,9 @@ hipError_t launch_quad(void* psi, const GroupSpec& gs, const uint64_t off[4], co
     using V = typename Vec2<T>::type;
     if (gs.n_groups == 0) return hipSuccess;
     V* p = (V*)psi;
-    SV_UNROLL_SWITCH(lc, {
-        const dim3 grid = grid_for(gs.n_groups, lc.block, UU);
-        hipLaunchKernelGGL((k_quad<T, UU>), grid, dim3(lc.block), 0, s, p, gs, off[1], off[2], off[3], c);
+    SV_SHAPE_SWITCH(lc, {
+        hipLaunchKernelGGL((k_quad<T, UU, NTT>), grid_for(gs.n_groups, lc.block, UU), dim3(lc.block), 0, s, p, gs,
+                           off[1], off[2], off[3], c);
     });
     return hipGetLastError();
 }
@@ -376,14 +393,10 @@ static hipError_t launch_general_k(typename Vec2<T>::type* p, const GroupSpec& g
     GeneralSpec<T, K> sp;
     for (int r = 0; r < (1 << K); ++r) sp.off[r] = off[r];
     for (int i = 0; i < 2 * (1 << K) * (1 << K); ++i) sp.m[i] = m[i];
-    // the 8x8 form keeps 2 groups per thread at most: its 8 loaded members
-    // per group already give 8 loads in flight per lane
-    const int u = K == 3 ? (lc.unroll > 2 ? 2 : lc.unroll) : lc.unroll;
-    switch (u) {
-    case 1: hipLaunchKernelGGL((k_general<T, K, 1>), grid_for(gs.n_groups, lc.block, 1), dim3(lc.block), 0, s, p, gs, sp); break;
-    case 2: hipLaunchKernelGGL((k_general<T, K, 2>), grid_for(gs.n_groups, lc.block, 2), dim3(lc.block), 0, s, p, gs, sp); break;
-    default: hipLaunchKernelGGL((k_general<T, K, 4>), grid_for(gs.n_groups, lc.block, 4), dim3(lc.block), 0, s, p, gs, sp); break;
-    }
+    SV_SHAPE_SWITCH(lc, {
+        hipLaunchKernelGGL((k_general<T, K, UU, NTT>), grid_for(gs.n_groups, lc.block, UU), dim3(lc.block), 0, s, p,
+                           gs, sp);
+    });
     return hipGetLastError();
 }
 

@@ -114,23 +114,35 @@ static size_t elem_bytes(int dtype) { return dtype == SV_C128 ? 16 : 8; }
 // launch-shape table (filled by defaults, overridable by the autotuner)
 // ---------------------------------------------------------------------------
 enum KClass { KC_PAIR = 0, KC_ONE = 1, KC_DIAG = 2, KC_QUAD = 3, KC_GENERAL = 4, KC_COUNT = 5 };
-constexpr int kTiers = 3;  // lowest touched qubit: < 3, < 6, >= 6
+// Tier of a launch: bytes spanned by one run of consecutive touched
+// amplitudes, 2^(lowest touched qubit) * element size: < 64 B, < 1 KiB, larger.
+constexpr int kTiers = 3;
 static Launch g_tune[KC_COUNT][2][kTiers];
 static bool g_tune_init = false;
 
 static void tune_defaults()
 {
+    // Measured on MI355X, 30-qubit complex128 streams: one group per thread,
+    // small blocks; non-temporal accesses only once runs span >= 64 bytes.
     for (int c = 0; c < KC_COUNT; ++c)
-        for (int d = 0; d < 2; ++d)
-            for (int t = 0; t < kTiers; ++t) g_tune[c][d][t] = Launch{256, c == KC_QUAD || c == KC_GENERAL ? 2 : 4};
+        for (int d = 0; d < 2; ++d) {
+            g_tune[c][d][0] = Launch{128, 1, 0};
+            g_tune[c][d][1] = Launch{128, 1, 1};
+            g_tune[c][d][2] = Launch{64, 1, 1};
+        }
     g_tune_init = true;
+}
+
+static int tier_of(int dtype, int low_qubit)
+{
+    const uint64_t span = low_qubit >= 40 ? (1ull << 40) : (elem_bytes(dtype) << low_qubit);
+    return span < 64 ? 0 : (span < 1024 ? 1 : 2);
 }
 
 static Launch tune_get(int kc, int dtype, int low_qubit)
 {
     if (!g_tune_init) tune_defaults();
-    const int tier = low_qubit < 3 ? 0 : (low_qubit < 6 ? 1 : 2);
-    return g_tune[kc][dtype == SV_C128 ? 1 : 0][tier];
+    return g_tune[kc][dtype == SV_C128 ? 1 : 0][tier_of(dtype, low_qubit)];
 }
 
 // ---------------------------------------------------------------------------
@@ -305,6 +317,9 @@ static sv_status build_plan(int n, int gate, const int* ctrl, int nc, const int*
         return SV_OK;
     }
     case SV_RZ: {
+        // element-wise over the control subspace: runs are bounded by the controls only
+        pl->low = 64;
+        for (int j = 0; j < nc; ++j) pl->low = std::min(pl->low, ctrl[j]);
         pl->kind = PK_DIAG;
         pl->kc = KC_DIAG;
         pl->gs = make_groups(n, ins, nc, cmask);
@@ -1027,27 +1042,30 @@ sv_status sv_adjoint_grad(sv_circuit c, sv_state psi, sv_state lam, const double
 // ---------------------------------------------------------------------------
 // tuning + diagnostics
 // ---------------------------------------------------------------------------
-sv_status sv_tune_set(int kernel_class, int dtype, int tier, int block, int unroll)
+sv_status sv_tune_set(int kernel_class, int dtype, int tier, int block, int unroll, int nt)
 {
     if (!g_tune_init) tune_defaults();
     if (kernel_class < 0 || kernel_class >= KC_COUNT || (dtype != SV_C64 && dtype != SV_C128) || tier < 0 ||
         tier >= kTiers)
         return set_error(SV_ERR_ARG, "bad tuning key");
-    if (block < 64 || block > 1024 || (block & 63)) return set_error(SV_ERR_ARG, "block must be a multiple of 64 in [64, 1024]");
-    if (unroll != 1 && unroll != 2 && unroll != 4 && unroll != 8) return set_error(SV_ERR_ARG, "unroll must be 1, 2, 4 or 8");
-    g_tune[kernel_class][dtype == SV_C128 ? 1 : 0][tier] = Launch{block, unroll};
+    if (block < 64 || block > 1024 || (block & 63))
+        return set_error(SV_ERR_ARG, "block must be a multiple of 64 in [64, 1024]");
+    if (unroll != 1 && unroll != 2 && unroll != 4) return set_error(SV_ERR_ARG, "unroll must be 1, 2 or 4");
+    if (nt != 0 && nt != 1) return set_error(SV_ERR_ARG, "nt must be 0 or 1");
+    g_tune[kernel_class][dtype == SV_C128 ? 1 : 0][tier] = Launch{block, unroll, nt};
     return SV_OK;
 }
 
-sv_status sv_tune_get(int kernel_class, int dtype, int tier, int* block, int* unroll)
+sv_status sv_tune_get(int kernel_class, int dtype, int tier, int* block, int* unroll, int* nt)
 {
     if (!g_tune_init) tune_defaults();
     if (kernel_class < 0 || kernel_class >= KC_COUNT || (dtype != SV_C64 && dtype != SV_C128) || tier < 0 ||
-        tier >= kTiers || !block || !unroll)
+        tier >= kTiers || !block || !unroll || !nt)
         return set_error(SV_ERR_ARG, "bad tuning key");
     const Launch l = g_tune[kernel_class][dtype == SV_C128 ? 1 : 0][tier];
     *block = l.block;
     *unroll = l.unroll;
+    *nt = l.nt;
     return SV_OK;
 }
 

@@ -85,8 +85,36 @@ __device__ __forceinline__ uint64_t group_base(uint64_t g, const GroupSpec& gs)
 
 struct Launch {
     int block;   // threads per block
-    int unroll;  // groups per thread
+    int unroll;  // groups per thread (1, 2 or 4)
+    int nt;      // 1: non-temporal loads and stores (streaming, no cache allocation)
 };
+
+// Global loads / stores of one complex amplitude, optionally non-temporal.
+// The two scalar halves merge into one 16-byte (complex128) or 8-byte
+// (complex64) access with the nt bit set.
+template <bool NT, typename V>
+__device__ __forceinline__ V ldg(const V* p)
+{
+    if constexpr (NT) {
+        V r;
+        r.x = __builtin_nontemporal_load(&p->x);
+        r.y = __builtin_nontemporal_load(&p->y);
+        return r;
+    } else {
+        return *p;
+    }
+}
+
+template <bool NT, typename V>
+__device__ __forceinline__ void stg(V* p, const V& v)
+{
+    if constexpr (NT) {
+        __builtin_nontemporal_store(v.x, &p->x);
+        __builtin_nontemporal_store(v.y, &p->y);
+    } else {
+        *p = v;
+    }
+}
 
 // ---- launchers (k_gates.hip) --------------------------------------------
 template <typename T>

@@ -146,13 +146,15 @@ def test_circuit_create_validation_is_host_side():
 
 
 def test_tuning_table_validation():
-    b, u = ctypes.c_int(), ctypes.c_int()
-    assert lib.sv_tune_get(0, 2, 2, ctypes.byref(b), ctypes.byref(u)) == OK
-    assert b.value % 64 == 0 and u.value in (1, 2, 4, 8)
-    assert lib.sv_tune_set(0, 2, 2, 100, 4) == ARG
-    assert lib.sv_tune_set(0, 2, 2, 256, 3) == ARG
-    assert lib.sv_tune_set(9, 2, 2, 256, 4) == ARG
-    assert lib.sv_tune_set(0, 2, 2, b.value, u.value) == OK
+    b, u, nt = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    assert lib.sv_tune_get(0, 2, 2, ctypes.byref(b), ctypes.byref(u), ctypes.byref(nt)) == OK
+    assert b.value % 64 == 0 and u.value in (1, 2, 4) and nt.value in (0, 1)
+    assert lib.sv_tune_set(0, 2, 2, 100, 1, 0) == ARG
+    assert lib.sv_tune_set(0, 2, 2, 256, 3, 0) == ARG
+    assert lib.sv_tune_set(0, 2, 2, 256, 1, 2) == ARG
+    assert lib.sv_tune_set(9, 2, 2, 256, 1, 0) == ARG
+    assert lib.sv_tune_set(0, 2, 3, 256, 1, 0) == ARG
+    assert lib.sv_tune_set(0, 2, 2, b.value, u.value, nt.value) == OK
 
 
 def test_status_strings():
