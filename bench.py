@@ -39,25 +39,11 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-# The kernel instantiation a gate case runs: class and operation from the
-# library's gate classification, groups-per-thread and non-temporal flag from
-# its launch table (tier = bytes spanned by a run of touched amplitudes).
-_CLASS = {"X": (0, "k_pair", "0 move"), "SWAP": (0, "k_pair", "0 move"), "H": (0, "k_pair", "2 real"),
-          "RY": (0, "k_pair", "2 real"), "U2": (0, "k_pair", "4 dense"), "Z": (1, "k_one", "0 neg"),
-          "RZ": (2, "k_diag", ""), "U4": (3, "k_quad", "")}
-
-
-def kernel_of(sv, gate, tg, ct, general_k=0):
-    if general_k:
-        kc, base, op, low = 4, "k_general", str(general_k), min(list(tg) + list(ct))
-    else:
-        kc, base, op = _CLASS[gate]
-        low = min(ct) if gate == "RZ" and ct else (64 if gate == "RZ" else min(list(tg) + list(ct)))
-    span = 16 << min(low, 40)
-    tier = 0 if span < 64 else (1 if span < 1024 else 2)
-    block, unroll, nt = sv.tune_get(kc, "c128", tier)
-    args = ", ".join(a for a in ("double", op, str(unroll), "true" if nt else "false") if a)
-    return f"{base}<{args}>"
+def kernel_of(sv, gate, tg, ct, general=False):
+    """The kernel instantiation libsv launches for a case (from sv_plan_info)."""
+    if general:
+        return sv.plan_info(30, "c128", "GENERAL", tg)["kernel"]
+    return sv.plan_info(30, "c128", gate, tg, ct)["kernel"]
 
 
 def touched_fraction(gate, nc):
@@ -152,7 +138,7 @@ def run_sweep(sv, torch, state, cases, denses, timed, rec, per_target):
         name = g if not ct else ({1: "CNOT", 2: "Toffoli"}[len(ct)] if g == "X" else g)
         qs = tuple(ct) + tuple(tg)
         for key, t, byt in ((("specific", name, kernel_of(sv, g, tg, ct)), ts, b),
-                            (("general", name, kernel_of(sv, g, qs, (), k)), tgen, 2 * S)):
+                            (("general", name, kernel_of(sv, g, qs, (), True)), tgen, 2 * S)):
             a = rec.setdefault(key, [0.0, 0.0, 0])
             a[0] += t
             a[1] += byt
@@ -332,10 +318,17 @@ def main():
     n_spec = sum(v[2] for v in spec.values())
     b_spec = sum(v[1] for v in spec.values())
     per_class = {}
-    for (kind, name, kern), (tt, bb, cnt) in sorted(rec.items()):
-        d = per_class.setdefault(name, {})
-        d[kind] = {"kernel": kern, "launches": cnt, "avg_ms": 1e3 * tt / cnt, "gates_per_s": cnt / tt,
-                   "GBps": bb / tt / 1e9, "frac_of_8TBps": bb / tt / 1e9 / PEAK_GBPS}
+    agg = {}
+    for (kind, name, kern), (tt, bb, cnt) in rec.items():
+        a = agg.setdefault((name, kind), [0.0, 0.0, 0, set()])
+        a[0] += tt
+        a[1] += bb
+        a[2] += cnt
+        a[3].add(kern)
+    for (name, kind), (tt, bb, cnt, kerns) in sorted(agg.items()):
+        per_class.setdefault(name, {})[kind] = {
+            "kernels": sorted(kerns), "launches": cnt, "avg_ms": 1e3 * tt / cnt, "gates_per_s": cnt / tt,
+            "GBps": bb / tt / 1e9, "frac_of_8TBps": bb / tt / 1e9 / PEAK_GBPS}
     for name, d in per_class.items():
         if "specific" in d and "general" in d:
             d["speedup_specific_vs_general"] = d["general"]["avg_ms"] / d["specific"]["avg_ms"]
@@ -346,6 +339,9 @@ def main():
         a[0] += tt
         a[1] += bb
         a[2] += cnt
+    per_kernel = {k: {"launches": c, "avg_ms": 1e3 * t / c, "GBps": by / t / 1e9, "frac_of_8TBps": by / t / 1e9 / PEAK_GBPS,
+                      "share_of_step_time": t / (t_spec + t_gen)}
+                  for k, (t, by, c) in sorted(by_kernel.items(), key=lambda kv: -kv[1][0])}
     dom = max(by_kernel.items(), key=lambda kv: kv[1][0])
     dk, (dt_, db, dc) = dom
     achieved = db / dt_ / 1e9
@@ -375,6 +371,7 @@ def main():
         "general_gates_per_s": sum(v[2] for v in gen_.values()) / t_gen,
         "copy_GBps": copy_gbps,
         "per_class": per_class,
+        "per_kernel": per_kernel,
         "roofline": roof,
         "per_target_ms": {g: {"specific": [round(1e3 * sum(x[0] for x in v[t]) / len(v[t]), 4) for t in sorted(v)],
                               "general": [round(1e3 * sum(x[1] for x in v[t]) / len(v[t]), 4) for t in sorted(v)]}

@@ -233,7 +233,8 @@ sv_status sv_adjoint_grad(sv_circuit c, sv_state psi, sv_state lam, const double
 /* ------------------------------------------------------------------------
  * Launch shapes (written by the autotuner, read by every gate launch).
  * Kernel classes: 0 paired (permutation / butterfly), 1 subset phase,
- * 2 element-wise diagonal, 3 two-target, 4 general.  Tier: bytes spanned by
+ * 2 element-wise diagonal, 3 two-target, 4 general, 5 paired with the
+ * partner fetched across the lanes of a wavefront (targets 0..5).  Tier: bytes spanned by
  * one run of consecutive touched amplitudes, 2^(lowest touched qubit) times
  * the element size: 0 (< 64 B), 1 (< 1 KiB), 2 (larger).  block is a
  * multiple of 64 in [64, 1024]; unroll (groups per thread) is 1, 2 or 4;
@@ -243,6 +244,14 @@ sv_status sv_adjoint_grad(sv_circuit c, sv_state psi, sv_state lam, const double
  * ------------------------------------------------------------------------ */
 sv_status sv_tune_set(int kernel_class, int dtype, int tier, int block, int unroll, int nt);
 sv_status sv_tune_get(int kernel_class, int dtype, int tier, int* block, int* unroll, int* nt);
+
+/* Host-only report of how a gate would be launched on an n_qubits state of
+ * `dtype`: kernel class, tier, operation code (the pair/subset operation;
+ * for the general kernel, k) and the launch shape.  gate = -1 asks about the
+ * general dense kernel on `targets` (nc must be 0).  No device work.
+ * Errors: as sv_apply_controlled's validation; SV_ERR_ARG for SV_I. */
+sv_status sv_plan_info(int n_qubits, int dtype, int gate, const int* controls, int nc, const int* targets, int nt,
+                       int* kernel_class, int* tier, int* op, int* block, int* unroll, int* nt_flag);
 
 /* ------------------------------------------------------------------------
  * Diagnostics

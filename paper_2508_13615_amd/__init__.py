@@ -23,7 +23,7 @@ import torch
 from ._lib import (GATES, OP_MAX_QUBITS, SV_C64, SV_C128, SvBatchCircuit, SvError, SvObs, SvOp, check, lib)
 
 __all__ = ["State", "Circuit", "Observable", "AdjointExpval", "SvError", "lib", "tune_set", "tune_get",
-           "sv_version"]
+           "plan_info", "sv_version"]
 
 _TORCH_DT = {"c128": torch.complex128, "c64": torch.complex64}
 _SV_DT = {"c128": SV_C128, "c64": SV_C64}
@@ -58,6 +58,25 @@ def tune_get(kernel_class: int, dtype: str, tier: int) -> Tuple[int, int, int]:
     b, u, t = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
     check(lib.sv_tune_get(kernel_class, _SV_DT[dtype], tier, ctypes.byref(b), ctypes.byref(u), ctypes.byref(t)))
     return b.value, u.value, t.value
+
+
+KERNEL_CLASSES = {0: "k_pair", 1: "k_one", 2: "k_diag", 3: "k_quad", 4: "k_general", 5: "k_wpair"}
+
+
+def plan_info(n: int, dtype: str, gate: str, targets: Sequence[int], controls: Sequence[int] = ()) -> dict:
+    """How libsv would launch a gate (host only).  gate = "GENERAL" asks about
+    the dense baseline kernel on `targets`."""
+    out = [ctypes.c_int() for _ in range(6)]
+    g = -1 if gate == "GENERAL" else GATES[gate]
+    check(lib.sv_plan_info(n, _SV_DT[dtype], g, _ints(controls), len(controls), _ints(targets), len(targets),
+                           *[ctypes.byref(o) for o in out]))
+    kc, tier, op, block, unroll, nt = (o.value for o in out)
+    T = "double" if dtype == "c128" else "float"
+    if kc == 2 or kc == 3:
+        name = f"{KERNEL_CLASSES[kc]}<{T}, {unroll}, {'true' if nt else 'false'}>"
+    else:
+        name = f"{KERNEL_CLASSES[kc]}<{T}, {op}, {unroll}, {'true' if nt else 'false'}>"
+    return {"class": kc, "tier": tier, "op": op, "block": block, "unroll": unroll, "nt": nt, "kernel": name}
 
 
 class Observable:

@@ -27,7 +27,7 @@ EXPORTS = [
     "sv_copy_to_host", "sv_copy_from_host", "sv_copy_state", "sv_synchronize", "sv_apply_gate",
     "sv_apply_controlled", "sv_apply_general", "sv_norm2", "sv_expval_pauli", "sv_expval_obs",
     "sv_expval_obs_dev", "sv_circuit_create", "sv_circuit_free", "sv_circuit_apply", "sv_adjoint_grad",
-    "sv_tune_set", "sv_tune_get", "sv_last_error", "sv_status_string", "sv_version",
+    "sv_tune_set", "sv_tune_get", "sv_plan_info", "sv_last_error", "sv_status_string", "sv_version",
 ]
 
 
@@ -88,6 +88,7 @@ def _load():
         "sv_batch_info": [vp, ctypes.POINTER(ctypes.c_int64)],
         "sv_tune_set": [i, i, i, i, i, i],
         "sv_tune_get": [i, i, i, ip, ip, ip],
+        "sv_plan_info": [i, i, i, ip, i, ip, i, ip, ip, ip, ip, ip, ip],
     }
     for name, args in sig.items():
         if hasattr(lib, name):

@@ -19,7 +19,7 @@ import sys
 import time
 
 TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_mi355x.json")
-CLASSES = {0: "paired", 1: "subset", 2: "diagonal", 3: "two-target", 4: "general"}
+CLASSES = {0: "paired", 1: "subset", 2: "diagonal", 3: "two-target", 4: "general", 5: "wave"}
 BLOCKS = (64, 128, 256, 512)
 UNROLLS = (1, 2, 4)
 
@@ -35,38 +35,66 @@ def apply_table(sv, path: str = TABLE) -> int:
     return len(tab["entries"])
 
 
-def _tier_qubit(dtype: str, tier: int) -> list:
-    """Lowest touched qubits that fall in a tier (2^q * elem bytes)."""
-    eb = 16 if dtype == "c128" else 8
-    qs = [q for q in range(0, 30) if {0: eb << q < 64, 1: 64 <= eb << q < 1024, 2: eb << q >= 1024}[tier]]
-    if tier == 2:
-        return [qs[len(qs) // 3], qs[-1]]
-    return [qs[0], qs[-1]]
-
-
-def _cases(kc: int, dtype: str, tier: int, n: int):
-    """(gate, targets, controls) cases whose lowest touched qubit lies in the tier."""
-    import numpy as np
-    out = []
-    rng = np.random.default_rng(11)
-    for low in _tier_qubit(dtype, tier):
-        hi = n - 1 if low != n - 1 else n - 2
+def _candidates(kc: int, n: int, rng, np):
+    """Gate cases of a kernel class with the lowest touched qubit swept from 0."""
+    hi = n - 1
+    for low in range(0, n - 2):
         if kc == 0:
-            out.append(("RY", (low,), (), (0.3,), None))
-            out.append(("X", (hi,), (low,), (), None))
+            yield low, ("SWAP", (low, hi), (), (), None)
         elif kc == 1:
-            out.append(("Z", (low,), (), (), None))
+            yield low, ("Z", (low,), (), (), None)
         elif kc == 2:
-            out.append(("RZ", (hi,), (low,), (0.3,), None))
+            yield low, ("RZ", (hi,), (low,), (0.3,), None)
         elif kc == 3:
             z = rng.standard_normal((4, 4)) + 1j * rng.standard_normal((4, 4))
-            out.append(("U4", (hi, low), (), (), np.linalg.qr(z)[0]))
+            yield low, ("U4", (hi, low), (), (), np.linalg.qr(z)[0])
+        elif kc == 4:
+            yield low, ("GENERAL", (hi, low), (), (), None)
         else:
-            out.append(("GENERAL", (hi, low), (), (), None))
-    return out
+            ctl = (low,) if low >= 6 else ()
+            yield low, ("H", (low % 6,), ctl, (), None)
 
 
-def tune(qubits: int = 30, reps: int = 3, dtypes=("c128", "c64"), log=print) -> dict:
+def _cases(sv, kc: int, dtype: str, tier: int, n: int):
+    """Up to two cases (lowest and highest reachable position) that libsv
+    launches with kernel class `kc` in `tier`; [] if the tier is unreachable."""
+    import numpy as np
+    rng = np.random.default_rng(11)
+    hits = []
+    for low, case in _candidates(kc, n, rng, np):
+        g, tg, ct = case[0], case[1], case[2]
+        info = sv.plan_info(n, dtype, g, tg, ct)
+        if info["class"] == kc and info["tier"] == tier:
+            hits.append(case)
+    if len(hits) > 2:
+        hits = [hits[0], hits[len(hits) // 2]]
+    return hits
+
+
+def _time_shape(sv, torch, st, kc, dtype, tier, shape, cases, u4, reps):
+    import numpy as np
+    sv.tune_set(kc, dtype, tier, *shape)
+    stream = torch.cuda.current_stream()
+    times = []
+    for _ in range(reps + 1):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for g, tg, ct, p, m in cases:
+            if g == "GENERAL":
+                st.apply_general(tg, u4)
+            else:
+                st.apply(g, tg, ct, p, m)
+        e1.record(stream)
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1))
+    return float(np.median(times[1:]))
+
+
+def tune(qubits: int = 30, reps: int = 3, dtypes=("c128", "c64"), log=print, margin: float = 0.02) -> dict:
+    """Two rounds per key: every candidate once (median of `reps`), then the
+    four fastest and the library default again, interleaved, median of
+    2*`reps`.  A candidate replaces the default only if it is `margin` faster."""
     import numpy as np
     import torch
 
@@ -74,43 +102,41 @@ def tune(qubits: int = 30, reps: int = 3, dtypes=("c128", "c64"), log=print) -> 
 
     entries = []
     u4 = np.linalg.qr(np.random.default_rng(5).standard_normal((4, 4)) + 0j)[0]
+    shapes = [(b, u, nt) for b in BLOCKS for u in UNROLLS for nt in (0, 1)]
     for dtype in dtypes:
         st = sv.State(qubits, dtype, basis=0)
-        stream = torch.cuda.current_stream()
         for kc in CLASSES:
             for tier in range(3):
-                cases = _cases(kc, dtype, tier, qubits)
-                best = None
-                for block in BLOCKS:
-                    for unroll in UNROLLS:
-                        for nt in (0, 1):
-                            sv.tune_set(kc, dtype, tier, block, unroll, nt)
-                            times = []
-                            for _ in range(reps + 1):
-                                e0 = torch.cuda.Event(enable_timing=True)
-                                e1 = torch.cuda.Event(enable_timing=True)
-                                e0.record(stream)
-                                for g, tg, ct, p, m in cases:
-                                    if g == "GENERAL":
-                                        st.apply_general(tg, u4)
-                                    else:
-                                        st.apply(g, tg, ct, p, m)
-                                e1.record(stream)
-                                e1.synchronize()
-                                times.append(e0.elapsed_time(e1))
-                            t = float(np.median(times[1:]))
-                            if best is None or t < best[0]:
-                                best = (t, block, unroll, nt)
-                t, block, unroll, nt = best
-                sv.tune_set(kc, dtype, tier, block, unroll, nt)
+                cases = _cases(sv, kc, dtype, tier, qubits)
+                if not cases:
+                    log(f"[autotune] {dtype} {CLASSES[kc]:10s} tier {tier}: not reachable, default kept")
+                    continue
+                default = sv.tune_get(kc, dtype, tier)
+                first = sorted((_time_shape(sv, torch, st, kc, dtype, tier, sh, cases, u4, reps), sh) for sh in shapes)
+                finalists = [sh for _, sh in first[:4]]
+                if default not in finalists:
+                    finalists.append(default)
+                acc = {sh: [] for sh in finalists}
+                for _ in range(2):
+                    for sh in finalists:
+                        acc[sh].append(_time_shape(sv, torch, st, kc, dtype, tier, sh, cases, u4, reps))
+                med = {sh: float(np.median(v)) for sh, v in acc.items()}
+                best = min(med, key=med.get)
+                if med[best] > (1.0 - margin) * med[default]:
+                    best = default
+                sv.tune_set(kc, dtype, tier, *best)
+                block, unroll, nt = best
                 entries.append({"class": kc, "class_name": CLASSES[kc], "dtype": dtype, "tier": tier,
-                                "block": block, "unroll": unroll, "nt": nt, "ms_per_case": t / len(cases),
+                                "block": block, "unroll": unroll, "nt": nt,
+                                "ms_per_case": med[best] / len(cases),
+                                "default": list(default), "default_ms_per_case": med[default] / len(cases),
                                 "cases": [(c[0], list(c[1]), list(c[2])) for c in cases]})
                 log(f"[autotune] {dtype} {CLASSES[kc]:10s} tier {tier}: block {block} unroll {unroll} nt {nt} "
-                    f"({t / len(cases):.3f} ms per gate)")
+                    f"({med[best] / len(cases):.3f} ms per gate; default {default} "
+                    f"{med[default] / len(cases):.3f})")
         del st
         torch.cuda.empty_cache()
-    return {"device": torch.cuda.get_device_name(0), "qubits": qubits, "reps": reps,
+    return {"device": torch.cuda.get_device_name(0), "qubits": qubits, "reps": reps, "margin": margin,
             "created": time.strftime("%Y-%m-%d %H:%M:%S"), "entries": entries}
 
 

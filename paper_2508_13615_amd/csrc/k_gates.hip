@@ -99,8 +99,58 @@ k_pair(typename Vec2<T>::type* __restrict__ psi, GroupSpec gs, uint64_t o0, uint
             if (g < gs.n_groups) {
                 V r0, r1;
                 pair_apply<OP, T, V>(a0[j], a1[j], c, r0, r1);
+                if ((b[j] & gs.pmask) != gs.pmask) {
+                    r0 = a0[j];
+                    r1 = a1[j];
+                }
                 stg<NT>(psi + b[j] + o0, r0);
                 stg<NT>(psi + b[j] + o1, r1);
+            }
+        }
+    }
+}
+
+// Paired update for a target t < 6 with the partner fetched across lanes.
+// The lane's own output is row bit_t(x) of the 2x2 product; groups failing the
+// control predicate keep their amplitude.  Every lane of a wavefront runs the
+// shuffles (the loop bound is uniform per block), so inactive tail lanes only
+// supply values nobody reads: the partner of a valid x is x ^ 2^t < 2^n.
+template <typename T, int OP, int U, bool NT>
+__global__ void __launch_bounds__(1024)
+k_wpair(typename Vec2<T>::type* __restrict__ psi, GroupSpec gs, int t, Coef2<T> c)
+{
+    using V = typename Vec2<T>::type;
+    const uint64_t per_block = (uint64_t)blockDim.x * U;
+    const uint64_t stride = (uint64_t)gridDim.x * per_block;
+    const int lm = 1 << t;
+    for (uint64_t g0 = (uint64_t)blockIdx.x * per_block + threadIdx.x; g0 < gs.n_groups + threadIdx.x;
+         g0 += stride) {
+        uint64_t x[U];
+        V a[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const uint64_t g = g0 + (uint64_t)j * blockDim.x;
+            x[j] = group_base(g < gs.n_groups ? g : 0, gs);
+            if (g < gs.n_groups) {
+                a[j] = ldg<NT>(psi + x[j]);
+            } else {
+                a[j].x = T(0);
+                a[j].y = T(0);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            V p;
+            p.x = __shfl_xor(a[j].x, lm, 64);
+            p.y = __shfl_xor(a[j].y, lm, 64);
+            const uint64_t g = g0 + (uint64_t)j * blockDim.x;
+            if (g < gs.n_groups) {
+                const bool hi = (x[j] >> t) & 1ull;
+                V r0, r1;
+                pair_apply<OP, T, V>(hi ? p : a[j], hi ? a[j] : p, c, r0, r1);
+                V r = hi ? r1 : r0;
+                if ((x[j] & gs.pmask) != gs.pmask) r = a[j];
+                stg<NT>(psi + x[j], r);
             }
         }
     }
@@ -140,6 +190,7 @@ k_one(typename Vec2<T>::type* __restrict__ psi, GroupSpec gs, T zr, T zi)
                 } else {
                     r = cmul<V, T>(zr, zi, a[j]);
                 }
+                if ((b[j] & gs.pmask) != gs.pmask) r = a[j];
                 stg<NT>(psi + b[j], r);
             }
         }
@@ -177,7 +228,8 @@ k_diag(typename Vec2<T>::type* __restrict__ psi, GroupSpec gs, DiagSpec<T> d)
                     zr = (e == i) ? d.d[2 * i] : zr;
                     zi = (e == i) ? d.d[2 * i + 1] : zi;
                 }
-                stg<NT>(psi + b[j], cmul<V, T>(zr, zi, a[j]));
+                const bool act = (b[j] & gs.pmask) == gs.pmask;
+                stg<NT>(psi + b[j], act ? cmul<V, T>(zr, zi, a[j]) : a[j]);
             }
         }
     }
@@ -222,6 +274,10 @@ k_quad(typename Vec2<T>::type* __restrict__ psi, GroupSpec gs, uint64_t o1, uint
                     }
                     r[row].x = sr;
                     r[row].y = si;
+                }
+                if ((b[j] & gs.pmask) != gs.pmask) {
+#pragma unroll
+                    for (int row = 0; row < 4; ++row) r[row] = a[j][row];
                 }
                 stg<NT>(psi + b[j], r[0]);
                 stg<NT>(psi + b[j] + o1, r[1]);
@@ -343,6 +399,28 @@ hipError_t launch_pair(void* psi, const GroupSpec& gs, uint64_t o0, uint64_t o1,
 }
 
 template <typename T>
+hipError_t launch_wpair(void* psi, const GroupSpec& gs, int t, int op, const Coef2<T>& c, hipStream_t s,
+                        Launch lc)
+{
+    using V = typename Vec2<T>::type;
+    if (gs.n_groups == 0) return hipSuccess;
+    if (t < 0 || t > 5 || (lc.block & 63)) return hipErrorInvalidValue;
+    V* p = (V*)psi;
+    SV_SHAPE_SWITCH(lc, {
+        const dim3 grid = grid_for(gs.n_groups, lc.block, UU);
+        const dim3 blk(lc.block);
+        switch (op) {
+        case PAIR_SWAP: hipLaunchKernelGGL((k_wpair<T, PAIR_SWAP, UU, NTT>), grid, blk, 0, s, p, gs, t, c); break;
+        case PAIR_Y: hipLaunchKernelGGL((k_wpair<T, PAIR_Y, UU, NTT>), grid, blk, 0, s, p, gs, t, c); break;
+        case PAIR_REAL: hipLaunchKernelGGL((k_wpair<T, PAIR_REAL, UU, NTT>), grid, blk, 0, s, p, gs, t, c); break;
+        case PAIR_RX: hipLaunchKernelGGL((k_wpair<T, PAIR_RX, UU, NTT>), grid, blk, 0, s, p, gs, t, c); break;
+        default: hipLaunchKernelGGL((k_wpair<T, PAIR_DENSE, UU, NTT>), grid, blk, 0, s, p, gs, t, c); break;
+        }
+    });
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_one(void* psi, const GroupSpec& gs, int op, T zr, T zi, hipStream_t s, Launch lc)
 {
     using V = typename Vec2<T>::type;
@@ -429,6 +507,8 @@ hipError_t launch_set_basis(void* psi, uint64_t n_amps, uint64_t index, hipStrea
     template hipError_t launch_pair<T>(void*, const GroupSpec&, uint64_t, uint64_t, int, const Coef2<T>&,   \
                                        hipStream_t, Launch);                                                \
     template hipError_t launch_one<T>(void*, const GroupSpec&, int, T, T, hipStream_t, Launch);             \
+    template hipError_t launch_wpair<T>(void*, const GroupSpec&, int, int, const Coef2<T>&, hipStream_t,      \
+                                        Launch);                                                            \
     template hipError_t launch_diag<T>(void*, const GroupSpec&, const DiagSpec<T>&, hipStream_t, Launch);   \
     template hipError_t launch_quad<T>(void*, const GroupSpec&, const uint64_t[4], const Coef4<T>&,         \
                                        hipStream_t, Launch);                                                \

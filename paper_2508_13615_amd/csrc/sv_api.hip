@@ -113,7 +113,7 @@ static size_t elem_bytes(int dtype) { return dtype == SV_C128 ? 16 : 8; }
 // ---------------------------------------------------------------------------
 // launch-shape table (filled by defaults, overridable by the autotuner)
 // ---------------------------------------------------------------------------
-enum KClass { KC_PAIR = 0, KC_ONE = 1, KC_DIAG = 2, KC_QUAD = 3, KC_GENERAL = 4, KC_COUNT = 5 };
+enum KClass { KC_PAIR = 0, KC_ONE = 1, KC_DIAG = 2, KC_QUAD = 3, KC_GENERAL = 4, KC_WAVE = 5, KC_COUNT = 6 };
 // Tier of a launch: bytes spanned by one run of consecutive touched
 // amplitudes, 2^(lowest touched qubit) * element size: < 64 B, < 1 KiB, larger.
 constexpr int kTiers = 3;
@@ -122,13 +122,20 @@ static bool g_tune_init = false;
 
 static void tune_defaults()
 {
-    // Measured on MI355X, 30-qubit complex128 streams: one group per thread,
-    // small blocks; non-temporal accesses only once runs span >= 64 bytes.
+    // Measured on MI355X with 30-qubit states: small blocks; enough groups per
+    // thread to keep two or more 16-byte loads in flight per lane (a complex64
+    // amplitude is 8 bytes, so it needs twice the groups); non-temporal
+    // accesses only once runs span >= 64 bytes.  The wavefront form reads
+    // whole runs, so it streams non-temporally in every tier.
     for (int c = 0; c < KC_COUNT; ++c)
         for (int d = 0; d < 2; ++d) {
-            g_tune[c][d][0] = Launch{128, 1, 0};
-            g_tune[c][d][1] = Launch{128, 1, 1};
-            g_tune[c][d][2] = Launch{64, 1, 1};
+            const bool c128 = d == 1;
+            const bool one_amp = c == KC_ONE || c == KC_DIAG || c == KC_WAVE;
+            const int u = one_amp ? (c128 ? 2 : 4) : ((c == KC_PAIR && !c128) ? 2 : 1);
+            const int nt0 = c == KC_WAVE || c == KC_ONE || c == KC_DIAG ? 1 : 0;
+            g_tune[c][d][0] = Launch{128, u, nt0};
+            g_tune[c][d][1] = Launch{128, u, 1};
+            g_tune[c][d][2] = Launch{64, u, 1};
         }
     g_tune_init = true;
 }
@@ -180,21 +187,29 @@ static bool gate_has_param(int gate)
 // ---------------------------------------------------------------------------
 // plans: a gate classified into a kernel class with its index spec
 // ---------------------------------------------------------------------------
-enum PlanKind { PK_NOP = 0, PK_PAIR, PK_ONE, PK_DIAG, PK_QUAD };
+enum PlanKind { PK_NOP = 0, PK_PAIR, PK_ONE, PK_DIAG, PK_QUAD, PK_WPAIR };
 
 struct Plan {
     int kind;
     int kc;
-    int low;  // lowest touched qubit (launch-shape tier)
+    int low;  // lowest inserted qubit (launch-shape tier); 64 = none
     GroupSpec gs;
     uint64_t off[4];
     int op;
+    int wt;  // target of the wavefront form
     double m[32];
     int dk;
     int dtq[3];
 };
 
-static GroupSpec make_groups(int n, const int* ins, int nins, uint64_t set_mask)
+// Bits whose runs of consecutive amplitudes span fewer bytes than this are
+// predicated inside the kernel instead of inserted into the group index, so
+// wavefront accesses stay on whole 128-byte lines.
+constexpr uint64_t kPredBytes = 128;
+
+// Build the group index spec: `ins` are inserted (fixed) bits, `fixed_one`
+// the inserted bits that are 1 in every group, `pmask` the predicated bits.
+static GroupSpec make_groups(int n, const int* ins, int nins, uint64_t set_mask, uint64_t pmask = 0)
 {
     GroupSpec gs{};
     int p[kMaxIns];
@@ -204,7 +219,37 @@ static GroupSpec make_groups(int n, const int* ins, int nins, uint64_t set_mask)
     for (int i = 0; i < nins; ++i) gs.pos[i] = p[i];
     gs.n_groups = 1ull << (n - nins);
     gs.set_mask = set_mask;
+    gs.pmask = pmask;
     return gs;
+}
+
+// Split `bits` (bits that must be 1 for the gate to act) into inserted and
+// predicated ones; a bit is predicated if its run span is under kPredBytes or
+// if it is below `min_insert` (the wavefront form keeps bits 0..5 in-lane).
+struct BitSplit {
+    int ins[kMaxIns];
+    int nins;
+    uint64_t set_mask;
+    uint64_t pmask;
+    int low;
+};
+
+static void split_bits(const int* q, int nq, int dtype, int min_insert, BitSplit* b)
+{
+    b->nins = 0;
+    b->set_mask = 0;
+    b->pmask = 0;
+    b->low = 64;
+    for (int j = 0; j < nq; ++j) {
+        const bool pred = (elem_bytes(dtype) << q[j]) < kPredBytes || q[j] < min_insert;
+        if (pred) {
+            b->pmask |= 1ull << q[j];
+        } else {
+            b->ins[b->nins++] = q[j];
+            b->set_mask |= 1ull << q[j];
+            b->low = std::min(b->low, q[j]);
+        }
+    }
 }
 
 static void conj_transpose2(double* m)
@@ -219,8 +264,10 @@ static void conj_transpose2(double* m)
     memcpy(m, t, sizeof t);
 }
 
-static sv_status build_plan(int n, int gate, const int* ctrl, int nc, const int* tgt, int nt, const double* params,
-                            const double* matrix, int adjoint, Plan* pl)
+// Row a1 of the method: classify a gate into a kernel class with its index
+// spec (group insertion, predicate, member offsets) and coefficients.
+static sv_status build_plan(int n, int dtype, int gate, const int* ctrl, int nc, const int* tgt, int nt,
+                            const double* params, const double* matrix, int adjoint, Plan* pl)
 {
     if (gate < SV_I || gate > SV_U4) return set_error(SV_ERR_ARG, "unknown gate");
     if (nt != gate_targets(gate)) return set_error(SV_ERR_ARG, "wrong number of targets for gate");
@@ -231,18 +278,9 @@ static sv_status build_plan(int n, int gate, const int* ctrl, int nc, const int*
     if (nc + nt > kMaxIns) return set_error(SV_ERR_ARG, "too many qubits");
 
     memset(pl, 0, sizeof *pl);
-    uint64_t cmask = 0;
-    int ins[kMaxIns];
-    int low = 64;
-    for (int j = 0; j < nc; ++j) {
-        cmask |= 1ull << ctrl[j];
-        ins[j] = ctrl[j];
-        low = std::min(low, ctrl[j]);
-    }
-    for (int j = 0; j < nt; ++j) low = std::min(low, tgt[j]);
-    pl->low = low;
     const int t = tgt[0];
     const double sgn = adjoint ? -1.0 : 1.0;
+    BitSplit bs;
 
     switch (gate) {
     case SV_I: pl->kind = PK_NOP; return SV_OK;
@@ -252,12 +290,6 @@ static sv_status build_plan(int n, int gate, const int* ctrl, int nc, const int*
     case SV_RX:
     case SV_RY:
     case SV_U2: {
-        ins[nc] = t;
-        pl->kind = PK_PAIR;
-        pl->kc = KC_PAIR;
-        pl->gs = make_groups(n, ins, nc + 1, cmask);
-        pl->off[0] = 0;
-        pl->off[1] = 1ull << t;
         if (gate == SV_X) {
             pl->op = PAIR_SWAP;
         } else if (gate == SV_Y) {
@@ -282,27 +314,53 @@ static sv_status build_plan(int n, int gate, const int* ctrl, int nc, const int*
             memcpy(pl->m, matrix, 8 * sizeof(double));
             if (adjoint) conj_transpose2(pl->m);
         }
+        if (t < 6) {
+            // wavefront form: lanes own contiguous amplitudes; controls below
+            // bit 6 are predicated, higher ones inserted
+            split_bits(ctrl, nc, dtype, 6, &bs);
+            pl->kind = PK_WPAIR;
+            pl->kc = KC_WAVE;
+            pl->wt = t;
+            pl->gs = make_groups(n, bs.ins, bs.nins, bs.set_mask, bs.pmask);
+            pl->low = bs.low;
+        } else {
+            split_bits(ctrl, nc, dtype, 0, &bs);
+            bs.ins[bs.nins++] = t;
+            pl->kind = PK_PAIR;
+            pl->kc = KC_PAIR;
+            pl->gs = make_groups(n, bs.ins, bs.nins, bs.set_mask, bs.pmask);
+            pl->off[0] = 0;
+            pl->off[1] = 1ull << t;
+            pl->low = std::min(bs.low, t);
+        }
         return SV_OK;
     }
     case SV_SWAP: {
-        ins[nc] = tgt[0];
-        ins[nc + 1] = tgt[1];
+        split_bits(ctrl, nc, dtype, 0, &bs);
+        bs.ins[bs.nins++] = tgt[0];
+        bs.ins[bs.nins++] = tgt[1];
         pl->kind = PK_PAIR;
         pl->kc = KC_PAIR;
         pl->op = PAIR_SWAP;
-        pl->gs = make_groups(n, ins, nc + 2, cmask);
+        pl->gs = make_groups(n, bs.ins, bs.nins, bs.set_mask, bs.pmask);
         pl->off[0] = 1ull << tgt[0];
         pl->off[1] = 1ull << tgt[1];
+        pl->low = std::min(bs.low, std::min(tgt[0], tgt[1]));
         return SV_OK;
     }
     case SV_Z:
     case SV_S:
     case SV_T:
     case SV_PHASE: {
-        ins[nc] = t;
+        // acts on the amplitudes whose control and target bits are all 1
+        int bits[SV_MAX_CONTROLS + 1];
+        for (int j = 0; j < nc; ++j) bits[j] = ctrl[j];
+        bits[nc] = t;
+        split_bits(bits, nc + 1, dtype, 0, &bs);
         pl->kind = PK_ONE;
         pl->kc = KC_ONE;
-        pl->gs = make_groups(n, ins, nc + 1, cmask | (1ull << t));
+        pl->gs = make_groups(n, bs.ins, bs.nins, bs.set_mask, bs.pmask);
+        pl->low = bs.low;
         if (gate == SV_Z) {
             pl->op = ONE_NEG;
         } else if (gate == SV_S) {
@@ -317,12 +375,12 @@ static sv_status build_plan(int n, int gate, const int* ctrl, int nc, const int*
         return SV_OK;
     }
     case SV_RZ: {
-        // element-wise over the control subspace: runs are bounded by the controls only
-        pl->low = 64;
-        for (int j = 0; j < nc; ++j) pl->low = std::min(pl->low, ctrl[j]);
+        // element-wise over the control subspace
+        split_bits(ctrl, nc, dtype, 0, &bs);
         pl->kind = PK_DIAG;
         pl->kc = KC_DIAG;
-        pl->gs = make_groups(n, ins, nc, cmask);
+        pl->gs = make_groups(n, bs.ins, bs.nins, bs.set_mask, bs.pmask);
+        pl->low = bs.low;
         pl->dk = 1;
         pl->dtq[0] = t;
         const double c = cos(params[0] / 2), s = sgn * sin(params[0] / 2);
@@ -334,15 +392,17 @@ static sv_status build_plan(int n, int gate, const int* ctrl, int nc, const int*
     }
     case SV_U4: {
         const int a = tgt[0], b = tgt[1];  // a = most significant matrix bit
-        ins[nc] = a;
-        ins[nc + 1] = b;
+        split_bits(ctrl, nc, dtype, 0, &bs);
+        bs.ins[bs.nins++] = a;
+        bs.ins[bs.nins++] = b;
         pl->kind = PK_QUAD;
         pl->kc = KC_QUAD;
-        pl->gs = make_groups(n, ins, nc + 2, cmask);
+        pl->gs = make_groups(n, bs.ins, bs.nins, bs.set_mask, bs.pmask);
         pl->off[0] = 0;
         pl->off[1] = 1ull << b;
         pl->off[2] = 1ull << a;
         pl->off[3] = (1ull << a) | (1ull << b);
+        pl->low = std::min(bs.low, std::min(a, b));
         for (int r = 0; r < 4; ++r)
             for (int c = 0; c < 4; ++c) {
                 const int src = adjoint ? (4 * c + r) : (4 * r + c);
@@ -365,6 +425,11 @@ static hipError_t run_plan_t(const Plan& pl, void* psi, hipStream_t s, int dtype
         Coef2<T> c;
         for (int i = 0; i < 8; ++i) c.m[i] = (T)pl.m[i];
         return launch_pair<T>(psi, pl.gs, pl.off[0], pl.off[1], pl.op, c, s, lc);
+    }
+    case PK_WPAIR: {
+        Coef2<T> c;
+        for (int i = 0; i < 8; ++i) c.m[i] = (T)pl.m[i];
+        return launch_wpair<T>(psi, pl.gs, pl.wt, pl.op, c, s, lc);
     }
     case PK_ONE: return launch_one<T>(psi, pl.gs, pl.op, (T)pl.m[0], (T)pl.m[1], s, lc);
     case PK_DIAG: {
@@ -550,7 +615,7 @@ sv_status sv_apply_controlled(sv_state st, sv_gate gate, const int* controls, in
 {
     SV_CHECK_STATE(st);
     Plan pl;
-    sv_status rc = build_plan(st->n, gate, controls, nc, targets, nt, params, matrix, adjoint, &pl);
+    sv_status rc = build_plan(st->n, st->dtype, gate, controls, nc, targets, nt, params, matrix, adjoint, &pl);
     if (rc) return rc;
     return run_plan(pl, st, st->data);
 }
@@ -780,11 +845,12 @@ sv_status sv_expval_pauli(sv_state st, const char* paulis, const int* qubits, in
         if (!live(c)) return set_error(SV_ERR_HANDLE, "invalid circuit handle");  \
     } while (0)
 
-static sv_status op_plan(const sv_circuit_s* c, const OpRec& o, const double* params, int adjoint, Plan* pl)
+static sv_status op_plan(const sv_circuit_s* c, int dtype, const OpRec& o, const double* params, int adjoint,
+                         Plan* pl)
 {
     double th = o.value;
     if (o.pidx >= 0) th = params[o.pidx];
-    return build_plan(c->n, o.gate, o.q, o.nc, o.q + o.nc, o.nt, &th, o.matrix.empty() ? nullptr : o.matrix.data(),
+    return build_plan(c->n, dtype, o.gate, o.q, o.nc, o.q + o.nc, o.nt, &th, o.matrix.empty() ? nullptr : o.matrix.data(),
                       adjoint, pl);
 }
 
@@ -829,7 +895,7 @@ sv_status sv_circuit_create(int n_qubits, const sv_op* ops, int n_ops, int n_par
         // validate by planning once with a zero angle
         Plan pl;
         const double zero = 0.0;
-        sv_status rc = build_plan(n_qubits, o.gate, o.q, o.nc, o.q + o.nc, o.nt, &zero,
+        sv_status rc = build_plan(n_qubits, SV_C128, o.gate, o.q, o.nc, o.q + o.nc, o.nt, &zero,
                                   o.matrix.empty() ? nullptr : o.matrix.data(), 0, &pl);
         if (rc) {
             delete c;
@@ -894,7 +960,7 @@ static sv_status circuit_forward(sv_circuit c, sv_state st, const double* params
 {
     for (const OpRec& o : c->ops) {
         Plan pl;
-        sv_status rc = op_plan(c, o, params, 0, &pl);
+        sv_status rc = op_plan(c, st->dtype, o, params, 0, &pl);
         if (rc) return rc;
         rc = run_plan(pl, st, st->data);
         if (rc) return rc;
@@ -986,7 +1052,7 @@ static sv_status adjoint_sweep(sv_circuit c, sv_state psi, sv_state lam, const d
             --slot;
         } else {
             Plan pl;
-            sv_status rc = op_plan(c, o, params, 1, &pl);
+            sv_status rc = op_plan(c, psi->dtype, o, params, 1, &pl);
             if (rc) return rc;
             rc = run_plan(pl, psi, psi->data);
             if (rc) return rc;
@@ -1066,6 +1132,42 @@ sv_status sv_tune_get(int kernel_class, int dtype, int tier, int* block, int* un
     *block = l.block;
     *unroll = l.unroll;
     *nt = l.nt;
+    return SV_OK;
+}
+
+sv_status sv_plan_info(int n_qubits, int dtype, int gate, const int* controls, int nc, const int* targets, int nt,
+                       int* kernel_class, int* tier, int* op, int* block, int* unroll, int* nt_flag)
+{
+    if (n_qubits < 1 || n_qubits > SV_MAX_QUBITS || (dtype != SV_C64 && dtype != SV_C128))
+        return set_error(SV_ERR_ARG, "n_qubits or dtype out of range");
+    if (!kernel_class || !tier || !op || !block || !unroll || !nt_flag) return set_error(SV_ERR_ARG, "null output");
+    int kc, low, opv = 0;
+    if (gate == -1) {  // the general dense kernel on `targets`
+        if (nt < 1 || nt > SV_MAX_GENERAL_K || nc != 0) return set_error(SV_ERR_ARG, "general gate needs 1..3 targets");
+        sv_status rc = check_qubits(n_qubits, nullptr, 0, targets, nt);
+        if (rc) return rc;
+        kc = KC_GENERAL;
+        low = 64;
+        for (int j = 0; j < nt; ++j) low = std::min(low, targets[j]);
+        opv = nt;
+    } else {
+        Plan pl;
+        const double zero = 0.0;
+        double mtx[32] = {0};
+        sv_status rc = build_plan(n_qubits, dtype, gate, controls, nc, targets, nt, &zero, mtx, 0, &pl);
+        if (rc) return rc;
+        if (pl.kind == PK_NOP) return set_error(SV_ERR_ARG, "identity launches nothing");
+        kc = pl.kc;
+        low = pl.low;
+        opv = pl.op;
+    }
+    const Launch l = tune_get(kc, dtype, low);
+    *kernel_class = kc;
+    *tier = tier_of(dtype, low);
+    *op = opv;
+    *block = l.block;
+    *unroll = l.unroll;
+    *nt_flag = l.nt;
     return SV_OK;
 }
 

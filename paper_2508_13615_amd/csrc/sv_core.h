@@ -22,6 +22,11 @@ constexpr int kMaxIns = 12;  // controls + targets inserted into a group index
 struct GroupSpec {
     uint64_t n_groups;
     uint64_t set_mask;
+    // Predicate: the gate acts on a group iff (base & pmask) == pmask.  Control
+    // (or target) bits whose runs would span under 128 bytes are predicated
+    // instead of inserted, so every access stays on whole cache lines; groups
+    // that fail the predicate are written back unchanged.
+    uint64_t pmask;
     int32_t nins;
     int32_t pos[kMaxIns];
 };
@@ -120,6 +125,13 @@ __device__ __forceinline__ void stg(V* p, const V& v)
 template <typename T>
 hipError_t launch_pair(void* psi, const GroupSpec& gs, uint64_t o0, uint64_t o1, int op,
                        const Coef2<T>& c, hipStream_t s, Launch lc);
+// Wavefront form of the paired update for a target t < 6: every lane owns one
+// amplitude of a contiguous run (group_base over inserted bits >= 6 only), the
+// partner amplitude x ^ 2^t sits in lane (lane ^ 2^t) of the same wavefront and
+// is fetched with a cross-lane shuffle.
+template <typename T>
+hipError_t launch_wpair(void* psi, const GroupSpec& gs, int t, int op, const Coef2<T>& c, hipStream_t s,
+                        Launch lc);
 template <typename T>
 hipError_t launch_one(void* psi, const GroupSpec& gs, int op, T zr, T zi, hipStream_t s, Launch lc);
 template <typename T>
