@@ -231,6 +231,65 @@ sv_status sv_adjoint_grad(sv_circuit c, sv_state psi, sv_state lam, const double
                           const sv_obs* obs, double* expval_out, double* grad_out);
 
 /* ------------------------------------------------------------------------
+ * Batched, fused execution (a project addition beyond the paper): many
+ * independent circuits -- or one large one -- run as one hipGraph launch
+ * (captured on first use and replayed): one kernel per stage level, one
+ * workgroup per state tile, every circuit's tiles of a level together.
+ *
+ * Each circuit's ops are grouped into passes whose qubits fit one LDS tile
+ * (2^12 complex128 or 2^13 complex64 amplitudes by default); ops on disjoint
+ * qubits may move ahead of each other to fill a pass.  One pass moves the
+ * state through HBM once, however many gates it holds.  A run executes, per
+ * circuit: the forward passes from |0...0>, the expectation of a diagonal
+ * observable, and (with_grad) the adjoint reverse sweep giving dE/dtheta for
+ * every parameter (Jones & Gacon 2020).  The library owns every circuit's
+ * state (and adjoint work state).
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t n_qubits;
+    int32_t n_ops;
+    const sv_op* ops;    /* host array, read during sv_batch_create */
+    int32_t n_params;    /* parameters of this circuit; ops use indices 0..n_params-1 */
+    int32_t obs_kind;    /* 1 = sum_i Z_i, 2 = sum_i Z_i Z_{i+1} */
+} sv_batch_circuit;
+
+typedef struct {
+    int32_t tile_qubits; /* 0 = default (12 complex128, 13 complex64); 2..13 */
+    int32_t threads;     /* 0 = default (512); multiple of 64 in [64, 1024] */
+    int32_t use_graph;   /* capture the run on first use, replay afterwards */
+    int32_t with_grad;   /* also run the adjoint sweep */
+} sv_batch_opts;
+
+/* Validate, schedule and allocate a batch.  opts may be NULL (defaults,
+ * use_graph = 1, with_grad = 1).  The batch runs on a stream of its own.
+ * Errors: SV_ERR_ARG / SV_ERR_QUBIT (validation, nothing allocated),
+ * SV_ERR_UNSUPPORTED (an op wider than a tile), SV_ERR_OOM. */
+sv_status sv_batch_create(const sv_batch_circuit* circuits, int n_circuits, sv_dtype dtype,
+                          const sv_batch_opts* opts, sv_batch* out);
+
+/* Run the batch.  params: the circuits' parameters concatenated in circuit
+ * order (sum of n_params doubles), in device memory if params_on_device.
+ * expvals: n_circuits doubles; grads: sum of n_params doubles (with_grad
+ * only); both in device memory if outputs_on_device.  Synchronous.
+ * Errors: SV_ERR_ARG, SV_ERR_HIP. */
+sv_status sv_batch_run(sv_batch b, const double* params, int params_on_device, double* expvals, double* grads,
+                       int outputs_on_device);
+
+/* info[0..9]: circuits, work items, passes, max passes per circuit, fused
+ * ops, parameters, state bytes, algorithmic HBM bytes per run, stage levels
+ * (kernel launches per run, besides the small setup and reduction kernels),
+ * LDS bytes per workgroup. */
+sv_status sv_batch_info(sv_batch b, int64_t* info);
+
+/* Device pointer to a circuit's state (after a forward-only run: U|0...0>). */
+sv_status sv_batch_state(sv_batch b, int circuit, void** dev_ptr, int* n_qubits);
+
+/* Copy a circuit's state to host memory of exactly 2^n * element bytes.
+ * Synchronous. */
+sv_status sv_batch_copy_state(sv_batch b, int circuit, void* host, size_t bytes);
+sv_status sv_batch_free(sv_batch b);
+
+/* ------------------------------------------------------------------------
  * Launch shapes (written by the autotuner, read by every gate launch).
  * Kernel classes: 0 paired (permutation / butterfly), 1 subset phase,
  * 2 element-wise diagonal, 3 two-target, 4 general, 5 paired with the

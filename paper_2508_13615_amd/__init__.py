@@ -20,9 +20,10 @@ from typing import Iterable, List, Optional, Sequence, Tuple
 import numpy as np
 import torch
 
-from ._lib import (GATES, OP_MAX_QUBITS, SV_C64, SV_C128, SvBatchCircuit, SvError, SvObs, SvOp, check, lib)
+from ._lib import (GATES, OP_MAX_QUBITS, SV_C64, SV_C128, SvBatchCircuit, SvBatchOpts, SvError, SvObs, SvOp,
+                   check, lib)
 
-__all__ = ["State", "Circuit", "Observable", "AdjointExpval", "SvError", "lib", "tune_set", "tune_get",
+__all__ = ["State", "Circuit", "Batch", "Observable", "AdjointExpval", "SvError", "lib", "tune_set", "tune_get",
            "plan_info", "sv_version"]
 
 _TORCH_DT = {"c128": torch.complex128, "c64": torch.complex64}
@@ -247,6 +248,70 @@ class Circuit:
         check(lib.sv_adjoint_grad(self.handle, psi.handle, lam.handle, pp, ctypes.byref(obs.c), ctypes.byref(e),
                                   g.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
         return e.value, g[: self.n_params]
+
+
+_OBS_KIND = {"sum_z": 1, "sum_zz": 2}
+
+
+class Batch:
+    """Many circuits (or one large one) in one fused graph launch
+    (sv_batch_*).  circuits: sequence of (n_qubits, ops, n_params, observable)
+    with observable "sum_z" or "sum_zz"."""
+
+    def __init__(self, circuits, dtype: str = "c128", tile_qubits: int = 0, threads: int = 0,
+                 use_graph: bool = True, with_grad: bool = True):
+        circuits = list(circuits)
+        self.dtype = dtype
+        self.n_circuits = len(circuits)
+        self.n_qubits = [int(c[0]) for c in circuits]
+        self.n_params = [int(c[2]) for c in circuits]
+        self.with_grad = bool(with_grad)
+        keep = []
+        arr = (SvBatchCircuit * max(1, len(circuits)))()
+        for i, (n, ops, npar, obs) in enumerate(circuits):
+            ops = list(ops)
+            oa = (SvOp * max(1, len(ops)))()
+            for j, op in enumerate(ops):
+                oa[j], k = _sv_op(op)
+                keep.append(k)
+            keep.append(oa)
+            arr[i] = SvBatchCircuit(int(n), len(ops), oa, int(npar), _OBS_KIND[obs])
+        opts = SvBatchOpts(int(tile_qubits), int(threads), int(bool(use_graph)), int(bool(with_grad)))
+        h = ctypes.c_void_p()
+        check(lib.sv_batch_create(arr, len(circuits), _SV_DT[dtype], ctypes.byref(opts), ctypes.byref(h)))
+        self.handle = h
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value and lib is not None:
+            lib.sv_batch_free(h)
+            self.handle = None
+
+    def run(self, params=()):
+        """Returns (expvals[n_circuits], grads[sum n_params] or None)."""
+        p, pp = _dbl(list(params) if len(params) else [0.0])
+        e = np.zeros(self.n_circuits)
+        g = np.zeros(max(1, sum(self.n_params)))
+        check(lib.sv_batch_run(self.handle, ctypes.c_void_p(p.ctypes.data), 0, ctypes.c_void_p(e.ctypes.data),
+                               ctypes.c_void_p(g.ctypes.data), 0))
+        return e, (g[: sum(self.n_params)] if self.with_grad else None)
+
+    def run_device(self, params: torch.Tensor, expvals: torch.Tensor, grads: torch.Tensor) -> None:
+        """Device-resident parameters and outputs (float64 CUDA tensors)."""
+        check(lib.sv_batch_run(self.handle, ctypes.c_void_p(params.data_ptr()), 1,
+                               ctypes.c_void_p(expvals.data_ptr()), ctypes.c_void_p(grads.data_ptr()), 1))
+
+    def info(self) -> dict:
+        a = (ctypes.c_int64 * 10)()
+        check(lib.sv_batch_info(self.handle, a))
+        keys = ["circuits", "items", "passes", "max_passes", "fused_ops", "params", "state_bytes",
+                "pass_bytes", "levels", "lds_bytes"]
+        return dict(zip(keys, list(a)))
+
+    def state(self, i: int) -> np.ndarray:
+        out = np.empty(1 << self.n_qubits[i], dtype=np.complex128 if self.dtype == "c128" else np.complex64)
+        check(lib.sv_batch_copy_state(self.handle, i, ctypes.c_void_p(out.ctypes.data), out.nbytes))
+        return out
 
 
 class AdjointExpval(torch.autograd.Function):

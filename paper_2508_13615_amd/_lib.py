@@ -27,6 +27,8 @@ EXPORTS = [
     "sv_copy_to_host", "sv_copy_from_host", "sv_copy_state", "sv_synchronize", "sv_apply_gate",
     "sv_apply_controlled", "sv_apply_general", "sv_norm2", "sv_expval_pauli", "sv_expval_obs",
     "sv_expval_obs_dev", "sv_circuit_create", "sv_circuit_free", "sv_circuit_apply", "sv_adjoint_grad",
+    "sv_batch_create", "sv_batch_run", "sv_batch_info", "sv_batch_state", "sv_batch_copy_state",
+    "sv_batch_free",
     "sv_tune_set", "sv_tune_get", "sv_plan_info", "sv_last_error", "sv_status_string", "sv_version",
 ]
 
@@ -44,7 +46,12 @@ class SvOp(ctypes.Structure):
 
 class SvBatchCircuit(ctypes.Structure):
     _fields_ = [("n_qubits", ctypes.c_int32), ("n_ops", ctypes.c_int32), ("ops", ctypes.POINTER(SvOp)),
-                ("n_params", ctypes.c_int32), ("param_offset", ctypes.c_int32)]
+                ("n_params", ctypes.c_int32), ("obs_kind", ctypes.c_int32)]
+
+
+class SvBatchOpts(ctypes.Structure):
+    _fields_ = [("tile_qubits", ctypes.c_int32), ("threads", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+                ("with_grad", ctypes.c_int32)]
 
 
 class SvError(RuntimeError):
@@ -82,10 +89,12 @@ def _load():
         "sv_circuit_free": [vp],
         "sv_circuit_apply": [vp, vp, dp],
         "sv_adjoint_grad": [vp, vp, vp, dp, ctypes.POINTER(SvObs), dp, dp],
-        "sv_batch_create": [ctypes.POINTER(SvBatchCircuit), i, i, vp, ctypes.POINTER(vp)],
+        "sv_batch_create": [ctypes.POINTER(SvBatchCircuit), i, i, ctypes.POINTER(SvBatchOpts), ctypes.POINTER(vp)],
         "sv_batch_free": [vp],
-        "sv_batch_run": [vp, vp, vp, vp, i],
+        "sv_batch_run": [vp, vp, i, vp, vp, i],
         "sv_batch_info": [vp, ctypes.POINTER(ctypes.c_int64)],
+        "sv_batch_state": [vp, i, ctypes.POINTER(vp), ip],
+        "sv_batch_copy_state": [vp, i, vp, ctypes.c_size_t],
         "sv_tune_set": [i, i, i, i, i, i],
         "sv_tune_get": [i, i, i, ip, ip, ip],
         "sv_plan_info": [i, i, i, ip, i, ip, i, ip, ip, ip, ip, ip, ip],

@@ -79,21 +79,24 @@ struct sv_circuit_s {
 static std::mutex g_mu;
 static std::unordered_set<const void*> g_live;
 
-static void reg(const void* h)
+void svk::handle_register(const void* h)
 {
     std::lock_guard<std::mutex> lk(g_mu);
     g_live.insert(h);
 }
-static bool live(const void* h)
+bool svk::handle_live(const void* h)
 {
     std::lock_guard<std::mutex> lk(g_mu);
     return h && g_live.count(h);
 }
-static void unreg(const void* h)
+void svk::handle_unregister(const void* h)
 {
     std::lock_guard<std::mutex> lk(g_mu);
     g_live.erase(h);
 }
+static void reg(const void* h) { handle_register(h); }
+static bool live(const void* h) { return handle_live(h); }
+static void unreg(const void* h) { handle_unregister(h); }
 
 #define SV_CHECK_STATE(st)                                                  \
     do {                                                                    \

@@ -1,0 +1,571 @@
+// sv_batch.hip -- host side of the fused pass engine: validation, the pass
+// scheduler (gate fusion), table building, the persistent launch and its
+// hipGraph capture.
+//
+// Pass scheduling.  Each op may move ahead of every earlier op it shares no
+// qubit with (ops on disjoint qubits commute).  An op is ready when it is the
+// next unscheduled op on each of its qubits.  A pass starts from the
+// coalescing bits (the lowest bits, so a tile's loads cover whole 128-byte
+// lines) and greedily takes ready ops in program order while the union of
+// their qubits stays within tq qubits; it is then padded with the lowest
+// unused qubits to exactly tq.  Every op of a pass acts inside one tile, so
+// one HBM round trip of the state serves all of them.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "sv_core.h"
+#include "sv_pass.h"
+
+using namespace svk;
+
+namespace {
+
+struct BOp {
+    int gate;
+    int nc, nt;
+    int q[SV_OP_MAX_QUBITS];
+    int pidx;
+    double value;
+    std::vector<double> mat;
+    uint64_t qmask() const
+    {
+        uint64_t m = 0;
+        for (int j = 0; j < nc + nt; ++j) m |= 1ull << q[j];
+        return m;
+    }
+};
+
+int popc(uint64_t x) { return __builtin_popcountll(x); }
+
+int targets_of(int gate) { return gate == SV_SWAP || gate == SV_U4 ? 2 : 1; }
+
+bool is_rotation(int gate) { return gate == SV_RX || gate == SV_RY || gate == SV_RZ || gate == SV_PHASE; }
+
+sv_status validate(int n, const sv_op& s, int n_params, int index, BOp* out)
+{
+    const std::string at = "op " + std::to_string(index) + ": ";
+    if (s.gate < SV_I || s.gate > SV_U4) return set_error(SV_ERR_ARG, at + "unknown gate");
+    if (s.n_controls < 0 || s.n_controls > SV_MAX_CONTROLS) return set_error(SV_ERR_ARG, at + "bad control count");
+    if (s.n_targets != targets_of(s.gate)) return set_error(SV_ERR_ARG, at + "wrong number of targets");
+    uint64_t seen = 0;
+    for (int j = 0; j < s.n_controls + s.n_targets; ++j) {
+        const int q = s.qubits[j];
+        if (q < 0 || q >= n) return set_error(SV_ERR_QUBIT, at + "qubit out of range");
+        if (seen & (1ull << q)) return set_error(SV_ERR_QUBIT, at + "qubit repeated");
+        seen |= 1ull << q;
+    }
+    if (s.param_index < -1 || s.param_index >= n_params) return set_error(SV_ERR_ARG, at + "parameter index out of range");
+    if (s.param_index >= 0 && !is_rotation(s.gate)) return set_error(SV_ERR_ARG, at + "gate takes no parameter");
+    if ((s.gate == SV_U2 || s.gate == SV_U4) && !s.matrix) return set_error(SV_ERR_ARG, at + "missing matrix");
+    out->gate = s.gate;
+    out->nc = s.n_controls;
+    out->nt = s.n_targets;
+    for (int j = 0; j < s.n_controls + s.n_targets; ++j) out->q[j] = s.qubits[j];
+    out->pidx = s.param_index;
+    out->value = s.value;
+    if (s.gate == SV_U2) out->mat.assign(s.matrix, s.matrix + 8);
+    if (s.gate == SV_U4) out->mat.assign(s.matrix, s.matrix + 32);
+    return SV_OK;
+}
+
+// Greedy commutation-aware grouping of ops into passes of at most tq qubits.
+void schedule(int n, int tq, int cb, const std::vector<BOp>& ops, std::vector<std::vector<int>>& pass_ops,
+              std::vector<uint64_t>& pass_q)
+{
+    const int m = (int)ops.size();
+    std::vector<std::vector<int>> qops(n);
+    for (int i = 0; i < m; ++i)
+        for (int j = 0; j < ops[i].nc + ops[i].nt; ++j) qops[ops[i].q[j]].push_back(i);
+    std::vector<int> front(n, 0);
+    std::vector<char> done(m, 0);
+    int remaining = m, first = 0;
+    const uint64_t cmask = cb > 0 ? ((1ull << cb) - 1ull) : 0ull;
+    while (remaining > 0) {
+        uint64_t P = cmask;
+        int nparam = 0;
+        std::vector<int> po;
+        bool added = true;
+        while (added) {
+            added = false;
+            while (first < m && done[first]) ++first;
+            for (int i = first; i < m; ++i) {
+                if (done[i]) continue;
+                const BOp& o = ops[i];
+                bool ready = true;
+                for (int j = 0; j < o.nc + o.nt && ready; ++j) {
+                    const int q = o.q[j];
+                    ready = qops[q][front[q]] == i;
+                }
+                if (!ready) continue;
+                const uint64_t np = P | o.qmask();
+                if (popc(np) > tq) continue;
+                if (o.pidx >= 0 && nparam >= kMaxPassSlots) continue;
+                done[i] = 1;
+                --remaining;
+                po.push_back(i);
+                P = np;
+                nparam += o.pidx >= 0;
+                for (int j = 0; j < o.nc + o.nt; ++j) ++front[o.q[j]];
+                added = true;
+            }
+        }
+        for (int q = 0; q < n && popc(P) < tq; ++q) P |= 1ull << q;
+        pass_ops.push_back(po);
+        pass_q.push_back(P);
+    }
+}
+
+}  // namespace
+
+struct sv_batch_s {
+    int dtype;
+    hipStream_t stream;
+    int n_circ;
+    int with_grad;
+    int use_graph;
+    int threads;
+    size_t lds;
+    std::vector<int64_t> level_first;  // item range of each stage level
+    int64_t n_items;
+    int n_segs;
+    int n_slots;
+    int n_params;
+    int n_passes;
+    int max_passes;
+    int n_fops;
+    size_t state_bytes;
+    double pass_bytes;  // HBM bytes of all passes of one run (algorithmic)
+    std::vector<size_t> psi_off;
+    std::vector<int> nq;
+    PassTables tb;
+    // device allocations
+    void* d_psi;
+    void* d_lam;
+    FCirc* d_circ;
+    FPass* d_pass;
+    FOp* d_ops;
+    FSeg* d_segs;
+    FCoefSpec* d_cspec;
+    int n_cspec;
+    double* d_coef;
+    double* d_epart;
+    double* d_gpart;
+    int64_t* d_e_off;
+    int* d_e_cnt;
+    int64_t* d_g_off;
+    int* d_g_cnt;
+    double* d_slot_scale;
+    double* d_slot_val;
+    int* d_csr_ptr;
+    int* d_csr_col;
+    double* d_params;
+    double* d_expvals;
+    double* d_grads;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+    bool graph_ready;
+};
+
+namespace {
+
+template <typename X>
+hipError_t dev_upload(X** dst, const std::vector<X>& src)
+{
+    const size_t bytes = std::max<size_t>(1, src.size()) * sizeof(X);
+    hipError_t e = hipMalloc((void**)dst, bytes);
+    if (e != hipSuccess) return e;
+    if (!src.empty()) e = hipMemcpy(*dst, src.data(), src.size() * sizeof(X), hipMemcpyHostToDevice);
+    return e;
+}
+
+void batch_release(sv_batch b)
+{
+    if (!b) return;
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    void* ptrs[] = {b->d_psi, b->d_lam, b->d_circ, b->d_pass, b->d_ops, b->d_segs, b->d_cspec, b->d_coef, b->d_epart, b->d_gpart, b->d_e_off, b->d_e_cnt, b->d_g_off, b->d_g_cnt,
+                    b->d_slot_scale, b->d_slot_val, b->d_csr_ptr, b->d_csr_col, b->d_params, b->d_expvals,
+                    b->d_grads};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+    if (b->stream) (void)hipStreamDestroy(b->stream);
+    delete b;
+}
+
+hipError_t enqueue_run(sv_batch b)
+{
+    hipStream_t s = b->stream;
+    hipError_t e = launch_pass_coef(b->d_cspec, b->n_cspec, b->d_params, b->d_coef, s);
+    for (size_t l = 0; l + 1 < b->level_first.size() && e == hipSuccess; ++l)
+        e = launch_pass_level(b->tb, b->dtype, b->level_first[l], b->level_first[l + 1], b->threads, b->lds, s);
+    if (e == hipSuccess) e = launch_pass_segsum(b->d_epart, b->d_e_off, b->d_e_cnt, nullptr, b->d_expvals, b->n_circ, s);
+    if (e == hipSuccess && b->with_grad) {
+        e = launch_pass_segsum(b->d_gpart, b->d_g_off, b->d_g_cnt, b->d_slot_scale, b->d_slot_val, b->n_slots, s);
+        if (e == hipSuccess) e = launch_pass_grad_csr(b->d_slot_val, b->d_csr_ptr, b->d_csr_col, b->n_params, b->d_grads, s);
+    }
+    return e;
+}
+
+}  // namespace
+
+static sv_status hip_fail(hipError_t e, const char* what)
+{
+    return set_error(SV_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+sv_status sv_batch_create(const sv_batch_circuit* circuits, int n_circuits, sv_dtype dtype, const sv_batch_opts* opts,
+                          sv_batch* out)
+{
+    if (!out || !circuits || n_circuits < 1) return set_error(SV_ERR_ARG, "bad batch arguments");
+    if (dtype != SV_C64 && dtype != SV_C128) return set_error(SV_ERR_ARG, "bad dtype");
+    const int tq_default = dtype == SV_C128 ? 12 : 13;
+    int tq_max = opts && opts->tile_qubits > 0 ? opts->tile_qubits : tq_default;
+    if (tq_max < 2 || tq_max > kMaxTileQubits) return set_error(SV_ERR_ARG, "tile_qubits must be in [2, 13]");
+    const int threads = opts && opts->threads > 0 ? opts->threads : 512;
+    if (threads < 64 || threads > 1024 || (threads & 63)) return set_error(SV_ERR_ARG, "threads must be a multiple of 64 in [64, 1024]");
+    const int with_grad = opts ? (opts->with_grad != 0) : 1;
+    const int cbits_default = dtype == SV_C128 ? 3 : 4;  // 128-byte runs
+
+    // ---- validate and schedule ----------------------------------------------------
+    std::vector<FCirc> circs(n_circuits);
+    std::vector<FPass> passes;
+    std::vector<FOp> fops;
+    std::vector<FCoefSpec> cspec;
+    std::vector<double> slot_scale;
+    std::vector<int> slot_param;  // global parameter of each global slot
+    std::vector<int64_t> g_off;
+    std::vector<int> g_cnt;
+    std::vector<int64_t> e_off;
+    std::vector<int> e_cnt;
+    std::vector<size_t> psi_off(n_circuits);
+    int n_params = 0, coef_total = 0, tq_used = 2, hi_entries = 1;
+    int64_t g_total = 0;
+    int e_total = 0;
+    size_t state_total = 0;
+    double pass_bytes = 0;
+    const size_t eb = dtype == SV_C128 ? 16 : 8;
+    for (int c = 0; c < n_circuits; ++c) {
+        const sv_batch_circuit& bc = circuits[c];
+        if (bc.n_qubits < 1 || bc.n_qubits > SV_MAX_QUBITS || bc.n_ops < 0 || (bc.n_ops > 0 && !bc.ops) ||
+            bc.n_params < 0 || (bc.obs_kind != 1 && bc.obs_kind != 2))
+            return set_error(SV_ERR_ARG, "circuit " + std::to_string(c) + ": bad description");
+        const int n = bc.n_qubits;
+        std::vector<BOp> ops;
+        int max_q = 1;
+        for (int i = 0; i < bc.n_ops; ++i) {
+            BOp o;
+            sv_status rc = validate(n, bc.ops[i], bc.n_params, i, &o);
+            if (rc) return set_error(rc, "circuit " + std::to_string(c) + ": " + sv_last_error());
+            if (o.gate == SV_I) continue;
+            max_q = std::max(max_q, o.nc + o.nt);
+            ops.push_back(o);
+        }
+        const int tq = std::min(n, tq_max);
+        if (max_q > tq) return set_error(SV_ERR_UNSUPPORTED, "circuit " + std::to_string(c) + ": an op has more qubits than a tile");
+        const int cb = std::max(0, std::min(cbits_default, tq - max_q));
+        std::vector<std::vector<int>> pops;
+        std::vector<uint64_t> pq;
+        schedule(n, tq, cb, ops, pops, pq);
+        if (pops.empty()) {  // no ops: one empty pass still builds |0..0>
+            pops.push_back({});
+            uint64_t P = 0;
+            for (int q = 0; q < tq; ++q) P |= 1ull << q;
+            pq.push_back(P);
+        }
+        FCirc& fc = circs[c];
+        memset(&fc, 0, sizeof fc);
+        fc.n = n;
+        fc.tq = tq;
+        fc.cb = cb;
+        hi_entries = std::max(hi_entries, 1 << (tq - cb));
+        fc.n_tiles = 1 << (n - tq);
+        fc.n_pass = (int)pops.size();
+        fc.pass_begin = (int)passes.size();
+        fc.obs_kind = bc.obs_kind;
+        fc.e_part_begin = e_total;
+        fc.g_part_begin = g_total;
+        e_off.push_back(e_total);
+        e_cnt.push_back(fc.n_tiles);
+        e_total += fc.n_tiles;
+        tq_used = std::max(tq_used, tq);
+        int slot = 0;
+        std::vector<int> slot_of(ops.size(), -1);
+        for (size_t i = 0; i < ops.size(); ++i)
+            if (ops[i].pidx >= 0) slot_of[i] = slot++;
+        for (size_t p = 0; p < pops.size(); ++p) {
+            FPass fp;
+            memset(&fp, 0, sizeof fp);
+            int local[64];
+            int k = 0;
+            for (int q = 0; q < n; ++q)
+                if (pq[p] & (1ull << q)) {
+                    local[q] = k;
+                    fp.q[k++] = q;
+                }
+            fp.op_begin = (int)fops.size();
+            for (int i : pops[p]) {
+                const BOp& o = ops[i];
+                FOp f;
+                memset(&f, 0, sizeof f);
+                f.slot = slot_of[i];
+                f.gen = o.gate == SV_RX ? GEN_X : (o.gate == SV_RY ? GEN_Y : (o.gate == SV_RZ ? GEN_Z : GEN_P1));
+                uint32_t cm = 0;
+                for (int j = 0; j < o.nc; ++j) cm |= 1u << local[o.q[j]];
+                f.cm = cm;
+                f.a = local[o.q[o.nc]];
+                f.b = o.nt > 1 ? local[o.q[o.nc + 1]] : 0;
+                FCoefSpec cs;
+                memset(&cs, 0, sizeof cs);
+                cs.gate = o.gate;
+                cs.pidx = o.pidx >= 0 ? n_params + o.pidx : -1;
+                cs.value = o.value;
+                cs.coef = coef_total;
+                f.coef = coef_total;
+                const double r = M_SQRT1_2;
+                switch (o.gate) {
+                case SV_X: { f.kind = FK_PAIR; double m[8] = {0, 0, 1, 0, 1, 0, 0, 0}; memcpy(cs.fixed, m, sizeof m); cs.nfixed = 8; coef_total += 8; break; }
+                case SV_Y: { f.kind = FK_PAIR; double m[8] = {0, 0, 0, -1, 0, 1, 0, 0}; memcpy(cs.fixed, m, sizeof m); cs.nfixed = 8; coef_total += 8; break; }
+                case SV_H: { f.kind = FK_PAIR; double m[8] = {r, 0, r, 0, r, 0, -r, 0}; memcpy(cs.fixed, m, sizeof m); cs.nfixed = 8; coef_total += 8; break; }
+                case SV_U2: { f.kind = FK_PAIR; memcpy(cs.fixed, o.mat.data(), 8 * sizeof(double)); cs.nfixed = 8; coef_total += 8; break; }
+                case SV_RX:
+                case SV_RY: f.kind = FK_PAIR; coef_total += 8; break;
+                case SV_RZ: f.kind = FK_DIAG; coef_total += 4; break;
+                case SV_Z: { f.kind = FK_PHASE; f.cm |= 1u << f.a; cs.fixed[0] = -1; cs.nfixed = 2; coef_total += 2; break; }
+                case SV_S: { f.kind = FK_PHASE; f.cm |= 1u << f.a; cs.fixed[1] = 1; cs.nfixed = 2; coef_total += 2; break; }
+                case SV_T: { f.kind = FK_PHASE; f.cm |= 1u << f.a; cs.fixed[0] = cos(M_PI / 4); cs.fixed[1] = sin(M_PI / 4); cs.nfixed = 2; coef_total += 2; break; }
+                case SV_PHASE: f.kind = FK_PHASE; f.cm |= 1u << f.a; coef_total += 2; break;
+                case SV_SWAP: f.kind = FK_SWAP; break;
+                default: { f.kind = FK_QUAD; memcpy(cs.fixed, o.mat.data(), 32 * sizeof(double)); cs.nfixed = 32; coef_total += 32; break; }
+                }
+                if (o.gate != SV_SWAP) cspec.push_back(cs);
+                fops.push_back(f);
+            }
+            fp.op_end = (int)fops.size();
+            passes.push_back(fp);
+        }
+        for (size_t i = 0; i < ops.size(); ++i)
+            if (ops[i].pidx >= 0) {
+                slot_scale.push_back(ops[i].gate == SV_PHASE ? -2.0 : 1.0);
+                slot_param.push_back(n_params + ops[i].pidx);
+                g_off.push_back(g_total + (int64_t)slot_of[i] * fc.n_tiles);
+                g_cnt.push_back(fc.n_tiles);
+            }
+        g_total += (int64_t)slot * fc.n_tiles;
+        n_params += bc.n_params;
+        psi_off[c] = state_total;
+        const size_t sb = ((size_t)1 << n) * eb;
+        state_total += (sb + 255) & ~(size_t)255;
+        pass_bytes += 2.0 * (double)sb * (with_grad ? 3.0 * fc.n_pass + 1.0 : fc.n_pass + 0.5);
+    }
+
+    // ---- work segments, level-major: stage s of every circuit before stage s+1 ----
+    std::vector<FSeg> segs;
+    int64_t n_items = 0;
+    int max_stages = 0;
+    std::vector<int> stages(n_circuits);
+    for (int c = 0; c < n_circuits; ++c) {
+        stages[c] = with_grad ? 2 * circs[c].n_pass + 1 : circs[c].n_pass + 1;
+        max_stages = std::max(max_stages, stages[c]);
+    }
+    std::vector<int64_t> level_first;
+    for (int s = 0; s < max_stages; ++s) {
+        level_first.push_back(n_items);
+        for (int c = 0; c < n_circuits; ++c) {
+            if (s >= stages[c]) continue;
+            FSeg sg;
+            sg.first = n_items;
+            sg.circ = c;
+            sg.stage = s;
+            sg.n_tiles = circs[c].n_tiles;
+            sg.pad = 0;
+            segs.push_back(sg);
+            n_items += circs[c].n_tiles;
+        }
+    }
+    level_first.push_back(n_items);
+    if (n_items >= (1ll << 31)) return set_error(SV_ERR_UNSUPPORTED, "batch has too many work items");
+
+    // ---- parameter -> slot CSR ----
+    std::vector<int> csr_ptr(n_params + 1, 0), csr_col(slot_param.size());
+    for (int p : slot_param) ++csr_ptr[p + 1];
+    for (int j = 0; j < n_params; ++j) csr_ptr[j + 1] += csr_ptr[j];
+    {
+        std::vector<int> fill(csr_ptr.begin(), csr_ptr.end() - 1);
+        for (size_t s = 0; s < slot_param.size(); ++s) csr_col[fill[slot_param[s]]++] = (int)s;
+    }
+
+    // ---- device side ----
+    sv_batch b = new sv_batch_s();
+    b->dtype = dtype;
+    b->n_circ = n_circuits;
+    b->with_grad = with_grad;
+    b->use_graph = opts ? (opts->use_graph != 0) : 1;
+    b->threads = threads;
+    b->n_items = n_items;
+    b->n_segs = (int)segs.size();
+    b->n_slots = (int)slot_param.size();
+    b->n_params = n_params;
+    b->n_passes = (int)passes.size();
+    b->n_fops = (int)fops.size();
+    b->state_bytes = state_total;
+    b->pass_bytes = pass_bytes;
+    b->psi_off = psi_off;
+    b->n_cspec = (int)cspec.size();
+    b->level_first = level_first;
+    for (int c = 0; c < n_circuits; ++c) {
+        b->nq.push_back(circs[c].n);
+        b->max_passes = std::max(b->max_passes, circs[c].n_pass);
+    }
+    hipError_t e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        delete b;
+        return hip_fail(e, "stream");
+    }
+    if (hipMalloc(&b->d_psi, state_total) != hipSuccess ||
+        (with_grad && hipMalloc(&b->d_lam, state_total) != hipSuccess)) {
+        (void)hipGetLastError();
+        batch_release(b);
+        return set_error(SV_ERR_OOM, "batch state allocation failed");
+    }
+    for (int c = 0; c < n_circuits; ++c) {
+        circs[c].psi = (char*)b->d_psi + psi_off[c];
+        circs[c].lam = with_grad ? (char*)b->d_lam + psi_off[c] : nullptr;
+    }
+    std::vector<double> zeros_e(std::max(1, e_total)), zeros_p(std::max(1, n_params));
+    e = dev_upload(&b->d_circ, circs);
+    if (e == hipSuccess) e = dev_upload(&b->d_pass, passes);
+    if (e == hipSuccess) e = dev_upload(&b->d_ops, fops);
+    if (e == hipSuccess) e = dev_upload(&b->d_segs, segs);
+    if (e == hipSuccess) e = dev_upload(&b->d_cspec, cspec);
+    if (e == hipSuccess) e = dev_upload(&b->d_e_off, e_off);
+    if (e == hipSuccess) e = dev_upload(&b->d_e_cnt, e_cnt);
+    if (e == hipSuccess) e = dev_upload(&b->d_g_off, g_off);
+    if (e == hipSuccess) e = dev_upload(&b->d_g_cnt, g_cnt);
+    if (e == hipSuccess) e = dev_upload(&b->d_slot_scale, slot_scale);
+    if (e == hipSuccess) e = dev_upload(&b->d_csr_ptr, csr_ptr);
+    if (e == hipSuccess) e = dev_upload(&b->d_csr_col, csr_col);
+    if (e == hipSuccess) e = hipMalloc((void**)&b->d_coef, sizeof(double) * std::max(1, coef_total));
+    if (e == hipSuccess) e = hipMalloc((void**)&b->d_epart, sizeof(double) * std::max(1, e_total));
+    if (e == hipSuccess) e = hipMalloc((void**)&b->d_gpart, sizeof(double) * std::max<int64_t>(1, g_total));
+    if (e == hipSuccess) e = hipMalloc((void**)&b->d_slot_val, sizeof(double) * std::max<size_t>(1, slot_param.size()));
+    if (e == hipSuccess) e = hipMalloc((void**)&b->d_params, sizeof(double) * std::max(1, n_params));
+    if (e == hipSuccess) e = hipMalloc((void**)&b->d_expvals, sizeof(double) * n_circuits);
+    if (e == hipSuccess) e = hipMalloc((void**)&b->d_grads, sizeof(double) * std::max(1, n_params));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        batch_release(b);
+        return set_error(SV_ERR_OOM, "batch table allocation failed");
+    }
+    PassTables& tb = b->tb;
+    tb.circs = b->d_circ;
+    tb.passes = b->d_pass;
+    tb.ops = b->d_ops;
+    tb.segs = b->d_segs;
+    tb.coef = b->d_coef;
+    tb.e_part = b->d_epart;
+    tb.g_part = b->d_gpart;
+    tb.n_items = n_items;
+    tb.n_segs = (int)segs.size();
+    tb.tq_max = tq_used;
+    tb.hi_entries = hi_entries;
+    tb.with_grad = with_grad;
+    b->lds = pass_engine_lds_bytes(tq_used, hi_entries, with_grad, dtype);
+    e = pass_engine_prepare(dtype, b->lds);
+    if (e != hipSuccess) {
+        batch_release(b);
+        return hip_fail(e, "pass engine LDS limit");
+    }
+    handle_register(b);
+    *out = b;
+    return SV_OK;
+}
+
+sv_status sv_batch_run(sv_batch b, const double* params, int params_on_device, double* expvals, double* grads,
+                       int outputs_on_device)
+{
+    if (!handle_live(b)) return set_error(SV_ERR_HANDLE, "invalid batch handle");
+    if (b->n_params > 0 && !params) return set_error(SV_ERR_ARG, "null params");
+    if (!expvals) return set_error(SV_ERR_ARG, "null expvals");
+    if (b->with_grad && b->n_params > 0 && !grads) return set_error(SV_ERR_ARG, "null grads");
+    hipStream_t s = b->stream;
+    hipError_t e = hipSuccess;
+    if (b->n_params > 0)
+        e = hipMemcpyAsync(b->d_params, params, sizeof(double) * b->n_params,
+                           params_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "batch params");
+    if (b->use_graph) {
+        if (!b->graph_ready) {
+            e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess) return hip_fail(e, "graph capture");
+            hipError_t e2 = enqueue_run(b);
+            e = hipStreamEndCapture(s, &b->graph);
+            if (e2 != hipSuccess) return hip_fail(e2, "graph capture launch");
+            if (e != hipSuccess) return hip_fail(e, "graph end capture");
+            e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+            if (e != hipSuccess) return hip_fail(e, "graph instantiate");
+            b->graph_ready = true;
+        }
+        e = hipGraphLaunch(b->exec, s);
+    } else {
+        e = enqueue_run(b);
+    }
+    if (e != hipSuccess) return hip_fail(e, "batch launch");
+    const hipMemcpyKind ok = outputs_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    e = hipMemcpyAsync(expvals, b->d_expvals, sizeof(double) * b->n_circ, ok, s);
+    if (e == hipSuccess && b->with_grad && b->n_params > 0)
+        e = hipMemcpyAsync(grads, b->d_grads, sizeof(double) * b->n_params, ok, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "batch run");
+    return SV_OK;
+}
+
+sv_status sv_batch_info(sv_batch b, int64_t* info)
+{
+    if (!handle_live(b)) return set_error(SV_ERR_HANDLE, "invalid batch handle");
+    if (!info) return set_error(SV_ERR_ARG, "null info");
+    info[0] = b->n_circ;
+    info[1] = b->n_items;
+    info[2] = b->n_passes;
+    info[3] = b->max_passes;
+    info[4] = b->n_fops;
+    info[5] = b->n_params;
+    info[6] = (int64_t)b->state_bytes;
+    info[7] = (int64_t)b->pass_bytes;
+    info[8] = (int64_t)b->level_first.size() - 1;
+    info[9] = (int64_t)b->lds;
+    return SV_OK;
+}
+
+sv_status sv_batch_state(sv_batch b, int circuit, void** dev_ptr, int* n_qubits)
+{
+    if (!handle_live(b)) return set_error(SV_ERR_HANDLE, "invalid batch handle");
+    if (circuit < 0 || circuit >= b->n_circ || !dev_ptr) return set_error(SV_ERR_ARG, "bad circuit index");
+    *dev_ptr = (char*)b->d_psi + b->psi_off[circuit];
+    if (n_qubits) *n_qubits = b->nq[circuit];
+    return SV_OK;
+}
+
+sv_status sv_batch_free(sv_batch b)
+{
+    if (!handle_live(b)) return set_error(SV_ERR_HANDLE, "invalid batch handle");
+    handle_unregister(b);
+    batch_release(b);
+    return SV_OK;
+}
+
+sv_status sv_batch_copy_state(sv_batch b, int circuit, void* host, size_t bytes)
+{
+    if (!handle_live(b)) return set_error(SV_ERR_HANDLE, "invalid batch handle");
+    if (circuit < 0 || circuit >= b->n_circ || !host) return set_error(SV_ERR_ARG, "bad circuit index or buffer");
+    const size_t sb = ((size_t)1 << b->nq[circuit]) * (b->dtype == SV_C128 ? 16 : 8);
+    if (bytes != sb) return set_error(SV_ERR_ARG, "byte count mismatch");
+    hipError_t e = hipMemcpyAsync(host, (char*)b->d_psi + b->psi_off[circuit], sb, hipMemcpyDeviceToHost, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return set_error(SV_ERR_HIP, std::string("batch state copy: ") + hipGetErrorString(e));
+    return SV_OK;
+}

@@ -200,5 +200,9 @@ hipError_t launch_scatter_grads(const double* slot_val, const int* slot_param, c
 
 // ---- helpers ----------------------------------------------------------------
 sv_status set_error(sv_status st, const std::string& msg);
+// Registry of live handles (states, circuits, batches).
+void handle_register(const void* h);
+bool handle_live(const void* h);
+void handle_unregister(const void* h);
 
 }  // namespace svk

@@ -160,3 +160,25 @@ def test_tuning_table_validation():
 def test_status_strings():
     assert lib.sv_status_string(4) == b"SV_ERR_HIP"
     assert lib.sv_version() >= 1
+
+
+def test_batch_create_validation_is_host_side():
+    ops = (_lib.SvOp * 1)()
+    ops[0].gate = 8
+    ops[0].n_targets = 1
+    ops[0].param_index = 0
+    ops[0].qubits[0] = 7  # outside a 4-qubit circuit
+    circ = (_lib.SvBatchCircuit * 1)()
+    circ[0] = _lib.SvBatchCircuit(4, 1, ops, 1, 1)
+    h = ctypes.c_void_p()
+    opts = _lib.SvBatchOpts(0, 0, 1, 1)
+    assert lib.sv_batch_create(circ, 1, 2, ctypes.byref(opts), ctypes.byref(h)) == QUBIT
+    ops[0].qubits[0] = 1
+    circ[0] = _lib.SvBatchCircuit(4, 1, ops, 1, 3)  # unknown observable
+    assert lib.sv_batch_create(circ, 1, 2, ctypes.byref(opts), ctypes.byref(h)) == ARG
+    circ[0] = _lib.SvBatchCircuit(4, 1, ops, 1, 1)
+    bad = _lib.SvBatchOpts(14, 0, 1, 1)  # tile too large
+    assert lib.sv_batch_create(circ, 1, 2, ctypes.byref(bad), ctypes.byref(h)) == ARG
+    bad = _lib.SvBatchOpts(0, 100, 1, 1)  # threads not a multiple of 64
+    assert lib.sv_batch_create(circ, 1, 2, ctypes.byref(bad), ctypes.byref(h)) == ARG
+    assert lib.sv_batch_run(ctypes.c_void_p(0x1234), None, 0, None, None, 0) == HANDLE

@@ -1,0 +1,151 @@
+"""The fused pass engine (sv_batch_*) against the oracle and the op-by-op path.
+
+Small tile sizes force many passes and many tiles per pass, so scheduling,
+tile addressing and the cross-workgroup dependencies are exercised on states
+the oracle handles in milliseconds.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+sv = pytest.importorskip("paper_2508_13615_amd")
+
+TOL = {"c128": 1e-12, "c64": 1e-5}
+GATES = ["X", "Y", "Z", "H", "S", "T", "RX", "RY", "RZ", "PHASE", "U2", "U4", "SWAP"]
+
+
+def random_circuit(n, n_ops, rng, max_q, n_params):
+    ops = []
+    for _ in range(n_ops):
+        g = str(rng.choice(GATES))
+        nt = 2 if g in ("U4", "SWAP") else 1
+        if nt > n:
+            continue
+        qs = [int(q) for q in rng.permutation(n)]
+        nc = int(rng.integers(0, max(0, min(2, n - nt, max_q - nt)) + 1))
+        m = W.haar_unitary(nt, rng) if g in ("U2", "U4") else None
+        pidx = int(rng.integers(0, n_params)) if g in ("RX", "RY", "RZ", "PHASE") and n_params else -1
+        val = float(rng.uniform(0, 2 * math.pi))
+        ops.append(W.Op(g, tuple(qs[nt:nt + nc]), tuple(qs[:nt]), pidx, val, m))
+    return ops
+
+
+def obs_terms(kind, n):
+    return W.sum_z(n) if kind == "sum_z" else W.sum_zz(n)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("tile", [4, 5, 0])
+def test_batch_forward_states_and_energies(dtype, tile):
+    rng = np.random.default_rng(5000 + tile)
+    circs, params = [], []
+    for n in (3, 5, 8, 10):
+        npar = 6
+        ops = random_circuit(n, 40, rng, tile if tile else 12, npar)
+        th = rng.uniform(0, 2 * math.pi, size=npar)
+        circs.append((n, ops, npar, "sum_z" if n % 2 else "sum_zz"))
+        params.append(th)
+    b = sv.Batch(circs, dtype, tile_qubits=tile, with_grad=False)
+    e, g = b.run(np.concatenate(params))
+    assert g is None
+    info = b.info()
+    assert info["passes"] >= len(circs)
+    for i, (n, ops, npar, obs) in enumerate(circs):
+        ref = oracle.run_circuit(oracle.zero_state(n), ops, params[i])
+        got = b.state(i).astype(np.complex128)
+        err = float(np.max(np.abs(got - ref)))
+        assert err <= 4 * TOL[dtype], (i, n, err)
+        e_ref = oracle.expval_obs(ref, obs_terms(obs, n))
+        assert abs(e[i] - e_ref) <= 4 * TOL[dtype] * n, (i, e[i], e_ref)
+
+
+@pytest.mark.parametrize("dtype,tol", [("c128", 1e-10), ("c64", 1e-4)])
+def test_batch_gradients_vs_oracle(dtype, tol):
+    rng = np.random.default_rng(5101)
+    circs, params, refs = [], [], []
+    for n, L in ((4, 2), (6, 2), (9, 1)):
+        ops = W.hea_ops(n, L)
+        npar = W.hea_n_params(n, L)
+        th = rng.uniform(0, 2 * math.pi, size=npar)
+        obs = "sum_zz" if n != 4 else "sum_z"
+        circs.append((n, ops, npar, obs))
+        params.append(th)
+        refs.append((oracle.energy(n, ops, th, obs_terms(obs, n)),
+                     oracle.param_shift_grad(n, ops, th, obs_terms(obs, n))))
+    # a circuit with controlled rotations, PHASE and shared parameters: central differences
+    n = 5
+    ops = [W.Op("H", (), (q,)) for q in range(n)]
+    ops += [W.Op("RX", (), (0,), 0), W.Op("PHASE", (), (1,), 1), W.Op("RY", (0,), (2,), 2),
+            W.Op("PHASE", (2,), (3,), 3), W.Op("RZ", (1, 3), (4,), 4), W.Op("X", (4,), (0,)),
+            W.Op("RY", (), (3,), 0), W.Op("SWAP", (), (0, 3)), W.Op("RX", (4,), (1,), 5), W.Op("T", (), (2,))]
+    th = rng.uniform(0, 2 * math.pi, size=6)
+    circs.append((n, ops, 6, "sum_zz"))
+    params.append(th)
+    refs.append((oracle.energy(n, ops, th, W.sum_zz(n)), oracle.fd_grad(n, ops, th, W.sum_zz(n))))
+    for tile in (4, 0):
+        b = sv.Batch(circs, dtype, tile_qubits=tile, with_grad=True)
+        e, g = b.run(np.concatenate(params))
+        off = 0
+        for i, (n, ops, npar, obs) in enumerate(circs):
+            e_ref, g_ref = refs[i]
+            gt = tol if i < 3 else max(tol, 1e-7)
+            assert abs(e[i] - e_ref) <= tol, (tile, i, e[i], e_ref)
+            assert np.max(np.abs(g[off:off + npar] - g_ref)) <= gt, (tile, i, g[off:off + npar], g_ref)
+            off += npar
+
+
+def test_batch_graph_replays_equal_eager():
+    rng = np.random.default_rng(5202)
+    circs = []
+    for n, L in ((6, 3), (8, 2), (11, 2)):
+        circs.append((n, W.hea_ops(n, L), W.hea_n_params(n, L), "sum_z"))
+    total = sum(c[2] for c in circs)
+    bg = sv.Batch(circs, "c128", tile_qubits=5, use_graph=True, with_grad=True)
+    be = sv.Batch(circs, "c128", tile_qubits=5, use_graph=False, with_grad=True)
+    for rep in range(3):
+        th = rng.uniform(0, 2 * math.pi, size=total)
+        eg, gg = bg.run(th)
+        # eager work between replays
+        s = sv.State(7).set_basis(3)
+        s.apply("H", (2,))
+        ee, ge = be.run(th)
+        assert np.array_equal(eg, ee), rep
+        assert np.array_equal(gg, ge), rep
+
+
+@pytest.mark.parametrize("dtype,tol", [("c128", 1e-10), ("c64", 1e-4)])
+def test_batch_matches_op_by_op_adjoint_mixed_sizes(dtype, tol):
+    # config-5 shaped, scaled down: qubit counts and layer counts drawn per circuit
+    spec = W.batch_spec(count=10, seed=5303, qmin=6, qmax=14, lmin=2, lmax=5)
+    circs = [(c.n, W.hea_ops(c.n, c.layers), len(c.params), "sum_z") for c in spec]
+    b = sv.Batch(circs, dtype, with_grad=True)
+    e, g = b.run(np.concatenate([c.params for c in spec]))
+    off = 0
+    for i, c in enumerate(spec):
+        circ = sv.Circuit(c.n, W.hea_ops(c.n, c.layers), len(c.params))
+        e1, g1 = circ.adjoint_grad(sv.State(c.n, "c128"), sv.State(c.n, "c128"), c.params, W.sum_z(c.n))
+        assert abs(e[i] - e1) <= tol, (i, e[i], e1)
+        assert np.max(np.abs(g[off:off + len(c.params)] - g1)) <= tol, i
+        off += len(c.params)
+
+
+def test_batch_large_circuit_multi_tile():
+    # one 20-qubit circuit with the default tile: many tiles and passes
+    n, L = 20, 3
+    ops = W.hea_ops(n, L)
+    th = W.uniform_angles(W.hea_n_params(n, L), 5404)
+    b = sv.Batch([(n, ops, len(th), "sum_zz")], "c128", with_grad=True)
+    e, g = b.run(th)
+    circ = sv.Circuit(n, ops, len(th))
+    e1, g1 = circ.adjoint_grad(sv.State(n), sv.State(n), th, W.sum_zz(n))
+    assert abs(e[0] - e1) <= 1e-11
+    assert np.max(np.abs(g - g1)) <= 1e-10
+    assert abs(e[0] - oracle.energy(n, ops, th, W.sum_zz(n))) <= 1e-11
+    info = b.info()
+    assert info["max_passes"] < len(ops) / 4  # fusion: far fewer passes than gates
