@@ -14,9 +14,15 @@ Also reported on the same JSON line:
                 average HIP-event-timed launch duration, against 8 TB/s;
   copy          a device-to-device copy of the state (the measured ceiling);
   cpu_baseline  the oracle on the host cores on a bounded sample;
-  adjoint       config "24 qubits, 8 layers RY+RZ + CNOT ladder, 384 params,
-                sum Z_i Z_{i+1}": one adjoint-gradient call vs parameter shift
-                (2 forward+expval runs per parameter) on the same GPU.
+  adjoint       24 qubits, 8 layers RY+RZ + CNOT ladder, 384 params,
+                sum Z_i Z_{i+1}: one adjoint-gradient call vs parameter shift
+                (2 forward+expval runs per parameter) on the same GPU, on the
+                op-by-op kernels;
+  adjoint_fused the same on the fused pass engine (parameter shift as
+                batches of 128 shifted circuits per launch);
+  batch         256 circuits of 14..22 qubits, forward + gradient in one
+                graph launch, vs the same circuits one after another;
+  circuits32    32-qubit HEA (10 layers) and QFT on the fused engine.
 Progress lines go to stderr; stdout carries only the JSON line.
 """
 from __future__ import annotations
@@ -257,6 +263,149 @@ def adjoint_compare(sv, torch, n, layers, ps_params, full_ps):
     return out
 
 
+def _timed(torch, fn, reps=3):
+    fn()  # warm-up (graph capture on first run)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        fn()
+        ts.append(time.perf_counter() - t0)
+    return sorted(ts)[len(ts) // 2]
+
+
+def adjoint_fused(sv, torch, n, layers, chunk):
+    """Config 4 on the fused pass engine: one adjoint-gradient run against
+    parameter shift with every shifted parameter set run as a batch of
+    circuits (2 * params circuits, `chunk` per launch)."""
+    import numpy as np
+    import workloads as W
+    ops = W.hea_ops(n, layers)
+    npar = W.hea_n_params(n, layers)
+    th = W.uniform_angles(npar, 1005)
+    out = {"qubits": n, "layers": layers, "params": npar, "engine": "fused passes (sv_batch)"}
+    grads = {}
+    for dt in ("c128", "c64"):
+        b = sv.Batch([(n, ops, npar, "sum_zz")], dt, with_grad=True)
+        res = {}
+
+        def run():
+            res["eg"] = b.run(th)
+
+        out[f"adjoint_s_{dt}"] = _timed(torch, run)
+        grads[dt] = res["eg"]
+        out[f"passes_{dt}"] = b.info()["passes"]
+        del b
+        torch.cuda.empty_cache()
+        shifted = []
+        for j in range(npar):
+            for sgn in (1.0, -1.0):
+                p = th.copy()
+                p[j] += sgn * math.pi / 2
+                shifted.append(p)
+        bf = sv.Batch([(n, ops, npar, "sum_zz")] * chunk, dt, with_grad=False)
+        bf.run(np.concatenate(shifted[:chunk]))  # capture
+        torch.cuda.synchronize()
+        es = []
+        t0 = time.perf_counter()
+        for k in range(0, len(shifted), chunk):
+            part = shifted[k:k + chunk]
+            while len(part) < chunk:
+                part = part + [th]
+            e, _ = bf.run(np.concatenate(part))
+            es.extend(e[:min(chunk, len(shifted) - k)])
+        out[f"param_shift_s_{dt}"] = time.perf_counter() - t0
+        es = np.array(es)
+        gps = (es[0::2] - es[1::2]) / 2.0
+        out[f"max_abs_err_adjoint_vs_ps_{dt}"] = float(np.max(np.abs(grads[dt][1] - gps)))
+        out[f"speedup_{dt}"] = out[f"param_shift_s_{dt}"] / out[f"adjoint_s_{dt}"]
+        if dt == "c128":
+            g_ref = gps
+        del bf
+        torch.cuda.empty_cache()
+    out["param_shift_circuits"] = 2 * npar
+    out["param_shift_circuits_per_launch"] = chunk
+    out["max_abs_err_adjoint_c64_vs_ps_c128"] = float(np.max(np.abs(grads["c64"][1] - g_ref)))
+    out["expval_c128"] = float(grads["c128"][0][0])
+    return out
+
+
+def config5(sv, torch, reps, sequential):
+    """256 circuits, 14..22 qubits, 4..12 HEA layers, sum Z_i, forward +
+    adjoint gradient in one graph launch; against the same circuits run one
+    after another through the op-by-op path."""
+    import numpy as np
+    import workloads as W
+    spec = W.batch_spec(256, 1006, 14, 22, 4, 12)
+    circs = [(c.n, W.hea_ops(c.n, c.layers), len(c.params), "sum_z") for c in spec]
+    params = np.concatenate([c.params for c in spec])
+    out = {"circuits": len(spec), "qubits": "14..22", "layers": "4..12", "observable": "sum_i Z_i",
+           "gates": int(sum(len(c[1]) for c in circs)), "params": int(len(params))}
+    for dt in ("c128", "c64"):
+        b = sv.Batch(circs, dt, with_grad=True)
+        res = {}
+
+        def run():
+            res["eg"] = b.run(params)
+
+        t = _timed(torch, run, reps)
+        info = b.info()
+        out[dt] = {"run_s": t, "circuits_per_s": len(spec) / t, "algorithmic_GBps": info["pass_bytes"] / t / 1e9,
+                   "passes": info["passes"], "levels": info["levels"], "state_GB": info["state_bytes"] / 1e9}
+        e_b, g_b = res["eg"]
+        del b
+        torch.cuda.empty_cache()
+        if sequential:
+            objs = [(sv.Circuit(c.n, W.hea_ops(c.n, c.layers), len(c.params)), sv.State(c.n, dt), sv.State(c.n, dt))
+                    for c in spec]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            es, gs = [], []
+            for (ci, psi, lam), c in zip(objs, spec):
+                psi.set_basis(0)
+                e1, g1 = ci.adjoint_grad(psi, lam, c.params, W.sum_z(c.n))
+                es.append(e1)
+                gs.append(g1)
+            ts = time.perf_counter() - t0
+            out[dt]["sequential_op_by_op_s"] = ts
+            out[dt]["speedup_vs_sequential"] = ts / t
+            out[dt]["max_abs_err_vs_sequential_grad"] = float(np.max(np.abs(g_b - np.concatenate(gs))))
+            out[dt]["max_abs_err_vs_sequential_expval"] = float(np.max(np.abs(e_b - np.array(es))))
+            del objs
+            torch.cuda.empty_cache()
+    return out
+
+
+def config3(sv, torch, n, layers, reps):
+    """32-qubit HEA (10 layers RY+RZ, CNOT ladder, from |0..0>) and QFT of a
+    random basis state, forward + sum Z on the fused engine, both dtypes.
+    The complex64 error is taken against the complex128 GPU result (itself
+    checked against the fp64 oracle at 20 qubits by the GPU tests)."""
+    import numpy as np
+    import workloads as W
+    x = W.random_basis_index(n, 1004)
+    prep = [W.Op("X", (), (q,)) for q in range(n) if (x >> q) & 1]
+    jobs = {"hea": (W.hea_ops(n, layers), W.uniform_angles(W.hea_n_params(n, layers), 1003)),
+            "qft": (prep + W.qft_ops(n), np.zeros(0))}
+    out = {"qubits": n, "hea_layers": layers, "qft_basis_index": x}
+    for name, (ops, th) in jobs.items():
+        for dt in ("c128", "c64"):
+            b = sv.Batch([(n, ops, len(th), "sum_z")], dt, with_grad=False)
+            res = {}
+
+            def run():
+                res["e"] = b.run(th)[0][0]
+
+            t = _timed(torch, run, reps)
+            info = b.info()
+            out[f"{name}_{dt}"] = {"s": t, "gates": len(ops), "passes": info["passes"],
+                                   "algorithmic_GBps": info["pass_bytes"] / t / 1e9, "expval_sum_z": res["e"]}
+            del b
+            torch.cuda.empty_cache()
+        out[f"{name}_abs_err_expval_c64_vs_c128"] = abs(out[f"{name}_c64"]["expval_sum_z"] - out[f"{name}_c128"]["expval_sum_z"])
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -270,6 +419,9 @@ def main():
     ap.add_argument("--adjoint-layers", type=int, default=8)
     ap.add_argument("--ps-params", type=int, default=48, help="parameters timed with parameter shift")
     ap.add_argument("--full-param-shift", action="store_true")
+    ap.add_argument("--skip-fused", action="store_true", help="skip configs 3, 4 (fused) and 5")
+    ap.add_argument("--config3-qubits", type=int, default=32)
+    ap.add_argument("--no-sequential", action="store_true", help="skip the op-by-op baseline of config 5")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the state-vector path here is built and measured on a single "
@@ -386,6 +538,14 @@ def main():
         out["adjoint"] = adjoint_compare(sv, torch, args.adjoint_qubits, args.adjoint_layers, args.ps_params,
                                          args.full_param_shift)
         log("[bench] adjoint comparison done")
+    if not args.skip_fused:
+        log("[bench] config 4 on the fused engine")
+        out["adjoint_fused"] = adjoint_fused(sv, torch, args.adjoint_qubits, args.adjoint_layers, 128)
+        log("[bench] config 5: 256 mixed circuits in one graph launch")
+        out["batch"] = config5(sv, torch, 3, not args.no_sequential)
+        log(f"[bench] config 3: {args.config3_qubits}-qubit HEA and QFT")
+        out["circuits32"] = config3(sv, torch, args.config3_qubits, 10, 3)
+        log("[bench] fused sections done")
     if not args.skip_cpu_baseline:
         log(f"[bench] oracle CPU baseline at {args.cpu_qubits} qubits")
         out["cpu_baseline"] = cpu_baseline(args.cpu_qubits, n)

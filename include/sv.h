@@ -275,6 +275,11 @@ sv_status sv_batch_create(const sv_batch_circuit* circuits, int n_circuits, sv_d
 sv_status sv_batch_run(sv_batch b, const double* params, int params_on_device, double* expvals, double* grads,
                        int outputs_on_device);
 
+/* Host-only: validate and schedule a batch exactly as sv_batch_create would,
+ * without any device work, and report its sv_batch_info figures. */
+sv_status sv_batch_plan(const sv_batch_circuit* circuits, int n_circuits, sv_dtype dtype,
+                        const sv_batch_opts* opts, int64_t* info);
+
 /* info[0..9]: circuits, work items, passes, max passes per circuit, fused
  * ops, parameters, state bytes, algorithmic HBM bytes per run, stage levels
  * (kernel launches per run, besides the small setup and reduction kernels),
@@ -293,7 +298,9 @@ sv_status sv_batch_free(sv_batch b);
  * Launch shapes (written by the autotuner, read by every gate launch).
  * Kernel classes: 0 paired (permutation / butterfly), 1 subset phase,
  * 2 element-wise diagonal, 3 two-target, 4 general, 5 paired with the
- * partner fetched across the lanes of a wavefront (targets 0..5).  Tier: bytes spanned by
+ * partner fetched across the lanes of a wavefront (targets 0..5), 6 staged
+ * through LDS in whole contiguous chunks (general / U4 / SWAP whose lowest
+ * qubit has runs under 1 KiB).  Tier: bytes spanned by
  * one run of consecutive touched amplitudes, 2^(lowest touched qubit) times
  * the element size: 0 (< 64 B), 1 (< 1 KiB), 2 (larger).  block is a
  * multiple of 64 in [64, 1024]; unroll (groups per thread) is 1, 2 or 4;
@@ -306,7 +313,8 @@ sv_status sv_tune_get(int kernel_class, int dtype, int tier, int* block, int* un
 
 /* Host-only report of how a gate would be launched on an n_qubits state of
  * `dtype`: kernel class, tier, operation code (the pair/subset operation;
- * for the general kernel, k) and the launch shape.  gate = -1 asks about the
+ * for the general kernel, k; for class 6, 16 * k + (1 for SWAP, else 0)) and
+ * the launch shape.  gate = -1 asks about the
  * general dense kernel on `targets` (nc must be 0).  No device work.
  * Errors: as sv_apply_controlled's validation; SV_ERR_ARG for SV_I. */
 sv_status sv_plan_info(int n_qubits, int dtype, int gate, const int* controls, int nc, const int* targets, int nt,

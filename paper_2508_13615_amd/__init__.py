@@ -24,7 +24,7 @@ from ._lib import (GATES, OP_MAX_QUBITS, SV_C64, SV_C128, SvBatchCircuit, SvBatc
                    check, lib)
 
 __all__ = ["State", "Circuit", "Batch", "Observable", "AdjointExpval", "SvError", "lib", "tune_set", "tune_get",
-           "plan_info", "sv_version"]
+           "plan_info", "batch_plan", "sv_version"]
 
 _TORCH_DT = {"c128": torch.complex128, "c64": torch.complex64}
 _SV_DT = {"c128": SV_C128, "c64": SV_C64}
@@ -61,7 +61,8 @@ def tune_get(kernel_class: int, dtype: str, tier: int) -> Tuple[int, int, int]:
     return b.value, u.value, t.value
 
 
-KERNEL_CLASSES = {0: "k_pair", 1: "k_one", 2: "k_diag", 3: "k_quad", 4: "k_general", 5: "k_wpair"}
+KERNEL_CLASSES = {0: "k_pair", 1: "k_one", 2: "k_diag", 3: "k_quad", 4: "k_general", 5: "k_wpair",
+                  6: "k_lds_gate"}
 
 
 def plan_info(n: int, dtype: str, gate: str, targets: Sequence[int], controls: Sequence[int] = ()) -> dict:
@@ -75,6 +76,8 @@ def plan_info(n: int, dtype: str, gate: str, targets: Sequence[int], controls: S
     T = "double" if dtype == "c128" else "float"
     if kc == 2 or kc == 3:
         name = f"{KERNEL_CLASSES[kc]}<{T}, {unroll}, {'true' if nt else 'false'}>"
+    elif kc == 6:
+        name = f"k_lds_gate<{T}, {op >> 4}, {op & 15}, {'true' if nt else 'false'}>"
     else:
         name = f"{KERNEL_CLASSES[kc]}<{T}, {op}, {unroll}, {'true' if nt else 'false'}>"
     return {"class": kc, "tier": tier, "op": op, "block": block, "unroll": unroll, "nt": nt, "kernel": name}
@@ -251,6 +254,32 @@ class Circuit:
 
 
 _OBS_KIND = {"sum_z": 1, "sum_zz": 2}
+_INFO_KEYS = ["circuits", "items", "passes", "max_passes", "fused_ops", "params", "state_bytes", "pass_bytes",
+              "levels", "lds_bytes"]
+
+
+def _batch_structs(circuits):
+    keep = []
+    arr = (SvBatchCircuit * max(1, len(circuits)))()
+    for i, (n, ops, npar, obs) in enumerate(circuits):
+        ops = list(ops)
+        oa = (SvOp * max(1, len(ops)))()
+        for j, op in enumerate(ops):
+            oa[j], k = _sv_op(op)
+            keep.append(k)
+        keep.append(oa)
+        arr[i] = SvBatchCircuit(int(n), len(ops), oa, int(npar), _OBS_KIND[obs])
+    return arr, keep
+
+
+def batch_plan(circuits, dtype: str = "c128", tile_qubits: int = 0, threads: int = 0, with_grad: bool = True) -> dict:
+    """Schedule a batch on the host only (no GPU needed) and report its figures."""
+    circuits = list(circuits)
+    arr, keep = _batch_structs(circuits)
+    opts = SvBatchOpts(int(tile_qubits), int(threads), 1, int(bool(with_grad)))
+    a = (ctypes.c_int64 * 10)()
+    check(lib.sv_batch_plan(arr, len(circuits), _SV_DT[dtype], ctypes.byref(opts), a))
+    return dict(zip(_INFO_KEYS, list(a)))
 
 
 class Batch:
@@ -266,16 +295,7 @@ class Batch:
         self.n_qubits = [int(c[0]) for c in circuits]
         self.n_params = [int(c[2]) for c in circuits]
         self.with_grad = bool(with_grad)
-        keep = []
-        arr = (SvBatchCircuit * max(1, len(circuits)))()
-        for i, (n, ops, npar, obs) in enumerate(circuits):
-            ops = list(ops)
-            oa = (SvOp * max(1, len(ops)))()
-            for j, op in enumerate(ops):
-                oa[j], k = _sv_op(op)
-                keep.append(k)
-            keep.append(oa)
-            arr[i] = SvBatchCircuit(int(n), len(ops), oa, int(npar), _OBS_KIND[obs])
+        arr, keep = _batch_structs(circuits)
         opts = SvBatchOpts(int(tile_qubits), int(threads), int(bool(use_graph)), int(bool(with_grad)))
         h = ctypes.c_void_p()
         check(lib.sv_batch_create(arr, len(circuits), _SV_DT[dtype], ctypes.byref(opts), ctypes.byref(h)))
@@ -304,9 +324,7 @@ class Batch:
     def info(self) -> dict:
         a = (ctypes.c_int64 * 10)()
         check(lib.sv_batch_info(self.handle, a))
-        keys = ["circuits", "items", "passes", "max_passes", "fused_ops", "params", "state_bytes",
-                "pass_bytes", "levels", "lds_bytes"]
-        return dict(zip(keys, list(a)))
+        return dict(zip(_INFO_KEYS, list(a)))
 
     def state(self, i: int) -> np.ndarray:
         out = np.empty(1 << self.n_qubits[i], dtype=np.complex128 if self.dtype == "c128" else np.complex64)

@@ -27,7 +27,7 @@ EXPORTS = [
     "sv_copy_to_host", "sv_copy_from_host", "sv_copy_state", "sv_synchronize", "sv_apply_gate",
     "sv_apply_controlled", "sv_apply_general", "sv_norm2", "sv_expval_pauli", "sv_expval_obs",
     "sv_expval_obs_dev", "sv_circuit_create", "sv_circuit_free", "sv_circuit_apply", "sv_adjoint_grad",
-    "sv_batch_create", "sv_batch_run", "sv_batch_info", "sv_batch_state", "sv_batch_copy_state",
+    "sv_batch_create", "sv_batch_plan", "sv_batch_run", "sv_batch_info", "sv_batch_state", "sv_batch_copy_state",
     "sv_batch_free",
     "sv_tune_set", "sv_tune_get", "sv_plan_info", "sv_last_error", "sv_status_string", "sv_version",
 ]
@@ -91,6 +91,8 @@ def _load():
         "sv_adjoint_grad": [vp, vp, vp, dp, ctypes.POINTER(SvObs), dp, dp],
         "sv_batch_create": [ctypes.POINTER(SvBatchCircuit), i, i, ctypes.POINTER(SvBatchOpts), ctypes.POINTER(vp)],
         "sv_batch_free": [vp],
+        "sv_batch_plan": [ctypes.POINTER(SvBatchCircuit), i, i, ctypes.POINTER(SvBatchOpts),
+                          ctypes.POINTER(ctypes.c_int64)],
         "sv_batch_run": [vp, vp, i, vp, vp, i],
         "sv_batch_info": [vp, ctypes.POINTER(ctypes.c_int64)],
         "sv_batch_state": [vp, i, ctypes.POINTER(vp), ip],

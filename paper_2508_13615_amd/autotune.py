@@ -19,7 +19,7 @@ import sys
 import time
 
 TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_mi355x.json")
-CLASSES = {0: "paired", 1: "subset", 2: "diagonal", 3: "two-target", 4: "general", 5: "wave"}
+CLASSES = {0: "paired", 1: "subset", 2: "diagonal", 3: "two-target", 4: "general", 5: "wave", 6: "lds"}
 BLOCKS = (64, 128, 256, 512)
 UNROLLS = (1, 2, 4)
 
@@ -48,7 +48,7 @@ def _candidates(kc: int, n: int, rng, np):
         elif kc == 3:
             z = rng.standard_normal((4, 4)) + 1j * rng.standard_normal((4, 4))
             yield low, ("U4", (hi, low), (), (), np.linalg.qr(z)[0])
-        elif kc == 4:
+        elif kc == 4 or kc == 6:
             yield low, ("GENERAL", (hi, low), (), (), None)
         else:
             ctl = (low,) if low >= 6 else ()

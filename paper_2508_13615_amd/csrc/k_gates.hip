@@ -332,6 +332,84 @@ k_general(typename Vec2<T>::type* __restrict__ psi, GroupSpec gs, GeneralSpec<T,
     }
 }
 
+// LDS-staged gate for gates with a low qubit (runs under 1 KiB): whole
+// contiguous chunks are streamed in and out non-temporally, so every access is
+// a full line however low the gate's qubits sit; the gate itself runs in LDS.
+template <typename T, int K, int OP, bool NT>
+__global__ void __launch_bounds__(1024)
+k_lds_gate(typename Vec2<T>::type* __restrict__ psi, GroupSpec tiles, LdsSpec ls, GeneralSpec<T, K> sp)
+{
+    using V = typename Vec2<T>::type;
+    extern __shared__ double st_raw[];  // 2^(C + h) amplitudes, sized at launch
+    V* const st = (V*)st_raw;
+    constexpr int C = kLdsChunkBits;
+    constexpr int M = 1 << K;
+    const uint32_t nl = 1u << (C + ls.h);
+    const uint32_t cmask_lo = (1u << C) - 1u;
+    for (uint64_t tile = blockIdx.x; tile < tiles.n_groups; tile += gridDim.x) {
+        const uint64_t base = (group_base(tile, tiles) << C) | ls.cmask;
+        for (uint32_t l = threadIdx.x; l < nl; l += blockDim.x) {
+            uint64_t g = base | (l & cmask_lo);
+            const uint32_t hc = l >> C;
+            for (int j = 0; j < ls.h; ++j)
+                if ((hc >> j) & 1u) g |= 1ull << ls.hq[j];
+            st[l] = ldg<NT>(psi + g);
+        }
+        __syncthreads();
+        const uint32_t ng = nl >> K;
+        for (uint32_t p = threadIdx.x; p < ng; p += blockDim.x) {
+            uint32_t lb = p;
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+                const int q = ls.lsort[j];
+                lb = ((lb >> q) << (q + 1)) | (lb & ((1u << q) - 1u));
+            }
+            if ((lb & ls.pmask) != ls.pmask) continue;
+            uint32_t idx[M];
+#pragma unroll
+            for (int r = 0; r < M; ++r) {
+                uint32_t o = lb;
+#pragma unroll
+                for (int j = 0; j < K; ++j)
+                    if ((r >> (K - 1 - j)) & 1) o |= 1u << ls.lpos[j];
+                idx[r] = o;
+            }
+            if constexpr (OP == 1) {
+                const V a = st[idx[1]];
+                st[idx[1]] = st[idx[2]];
+                st[idx[2]] = a;
+            } else {
+                V v[M];
+#pragma unroll
+                for (int r = 0; r < M; ++r) v[r] = st[idx[r]];
+#pragma unroll
+                for (int row = 0; row < M; ++row) {
+                    T sr = T(0), si = T(0);
+#pragma unroll
+                    for (int col = 0; col < M; ++col) {
+                        const T ur = sp.m[2 * (M * row + col)], ui = sp.m[2 * (M * row + col) + 1];
+                        sr += ur * v[col].x - ui * v[col].y;
+                        si += ur * v[col].y + ui * v[col].x;
+                    }
+                    V w;
+                    w.x = sr;
+                    w.y = si;
+                    st[idx[row]] = w;
+                }
+            }
+        }
+        __syncthreads();
+        for (uint32_t l = threadIdx.x; l < nl; l += blockDim.x) {
+            uint64_t g = base | (l & cmask_lo);
+            const uint32_t hc = l >> C;
+            for (int j = 0; j < ls.h; ++j)
+                if ((hc >> j) & 1u) g |= 1ull << ls.hq[j];
+            stg<NT>(psi + g, st[l]);
+        }
+        __syncthreads();
+    }
+}
+
 template <typename T>
 __global__ void k_set_basis(typename Vec2<T>::type* __restrict__ psi, uint64_t n_amps, uint64_t index)
 {
@@ -493,6 +571,47 @@ hipError_t launch_general(void* psi, const GroupSpec& gs, int k, const uint64_t*
     }
 }
 
+template <typename T, int K>
+static hipError_t launch_lds_k(typename Vec2<T>::type* p, const GroupSpec& tiles, const LdsSpec& ls, int op,
+                               const T* m, hipStream_t s, Launch lc)
+{
+    GeneralSpec<T, K> sp{};
+    if (m)
+        for (int i = 0; i < 2 * (1 << K) * (1 << K); ++i) sp.m[i] = m[i];
+    uint64_t nb = tiles.n_groups;
+    if (nb > (1ull << 30)) nb = 1ull << 30;
+    const dim3 grid((unsigned)nb), blk(lc.block);
+    const size_t lds = sizeof(typename Vec2<T>::type) << (kLdsChunkBits + ls.h);
+    if (op == 1) {
+        if constexpr (K == 2) {
+            if (lc.nt) hipLaunchKernelGGL((k_lds_gate<T, 2, 1, true>), grid, blk, lds, s, p, tiles, ls, sp);
+            else hipLaunchKernelGGL((k_lds_gate<T, 2, 1, false>), grid, blk, lds, s, p, tiles, ls, sp);
+        } else {
+            return hipErrorInvalidValue;
+        }
+    } else {
+        if (lc.nt) hipLaunchKernelGGL((k_lds_gate<T, K, 0, true>), grid, blk, lds, s, p, tiles, ls, sp);
+        else hipLaunchKernelGGL((k_lds_gate<T, K, 0, false>), grid, blk, lds, s, p, tiles, ls, sp);
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_lds_gate(void* psi, const GroupSpec& tiles, const LdsSpec& ls, int op, const T* m, hipStream_t s,
+                           Launch lc)
+{
+    using V = typename Vec2<T>::type;
+    if (tiles.n_groups == 0) return hipSuccess;
+    if (ls.h < 0 || ls.h > 3 || (lc.block & 63)) return hipErrorInvalidValue;
+    V* p = (V*)psi;
+    switch (ls.k) {
+    case 1: return launch_lds_k<T, 1>(p, tiles, ls, op, m, s, lc);
+    case 2: return launch_lds_k<T, 2>(p, tiles, ls, op, m, s, lc);
+    case 3: return launch_lds_k<T, 3>(p, tiles, ls, op, m, s, lc);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 template <typename T>
 hipError_t launch_set_basis(void* psi, uint64_t n_amps, uint64_t index, hipStream_t s)
 {
@@ -514,7 +633,9 @@ hipError_t launch_set_basis(void* psi, uint64_t n_amps, uint64_t index, hipStrea
                                        hipStream_t, Launch);                                                \
     template hipError_t launch_general<T>(void*, const GroupSpec&, int, const uint64_t*, const T*,          \
                                           hipStream_t, Launch);                                             \
-    template hipError_t launch_set_basis<T>(void*, uint64_t, uint64_t, hipStream_t);
+    template hipError_t launch_set_basis<T>(void*, uint64_t, uint64_t, hipStream_t);                         \
+    template hipError_t launch_lds_gate<T>(void*, const GroupSpec&, const LdsSpec&, int, const T*, hipStream_t, \
+                                           Launch);
 
 SV_INSTANTIATE(double)
 SV_INSTANTIATE(float)

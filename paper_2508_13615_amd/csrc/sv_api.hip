@@ -116,7 +116,9 @@ static size_t elem_bytes(int dtype) { return dtype == SV_C128 ? 16 : 8; }
 // ---------------------------------------------------------------------------
 // launch-shape table (filled by defaults, overridable by the autotuner)
 // ---------------------------------------------------------------------------
-enum KClass { KC_PAIR = 0, KC_ONE = 1, KC_DIAG = 2, KC_QUAD = 3, KC_GENERAL = 4, KC_WAVE = 5, KC_COUNT = 6 };
+enum KClass {
+    KC_PAIR = 0, KC_ONE = 1, KC_DIAG = 2, KC_QUAD = 3, KC_GENERAL = 4, KC_WAVE = 5, KC_LDS = 6, KC_COUNT = 7
+};
 // Tier of a launch: bytes spanned by one run of consecutive touched
 // amplitudes, 2^(lowest touched qubit) * element size: < 64 B, < 1 KiB, larger.
 constexpr int kTiers = 3;
@@ -139,6 +141,8 @@ static void tune_defaults()
             g_tune[c][d][0] = Launch{128, u, nt0};
             g_tune[c][d][1] = Launch{128, u, 1};
             g_tune[c][d][2] = Launch{64, u, 1};
+            if (c == KC_LDS)  // staged chunks are whole lines in every tier
+                for (int t = 0; t < kTiers; ++t) g_tune[c][d][t] = Launch{128, 1, 1};
         }
     g_tune_init = true;
 }
@@ -190,7 +194,7 @@ static bool gate_has_param(int gate)
 // ---------------------------------------------------------------------------
 // plans: a gate classified into a kernel class with its index spec
 // ---------------------------------------------------------------------------
-enum PlanKind { PK_NOP = 0, PK_PAIR, PK_ONE, PK_DIAG, PK_QUAD, PK_WPAIR };
+enum PlanKind { PK_NOP = 0, PK_PAIR, PK_ONE, PK_DIAG, PK_QUAD, PK_WPAIR, PK_LDS };
 
 struct Plan {
     int kind;
@@ -200,9 +204,11 @@ struct Plan {
     uint64_t off[4];
     int op;
     int wt;  // target of the wavefront form
-    double m[32];
+    double m[128];
     int dk;
     int dtq[3];
+    LdsSpec ls;  // PK_LDS
+    int lk;      // PK_LDS: gate qubits
 };
 
 // Bits whose runs of consecutive amplitudes span fewer bytes than this are
@@ -265,6 +271,57 @@ static void conj_transpose2(double* m)
             t[2 * (2 * r + c) + 1] = -m[2 * (2 * c + r) + 1];
         }
     memcpy(m, t, sizeof t);
+}
+
+// Gates whose lowest qubit has runs under 1 KiB go through the LDS-staged
+// kernel (k_lds_gate) when the state has room for a stage.
+static bool lds_eligible(int n, int dtype, const int* q, int k)
+{
+    int lo = 64, h = 0;
+    for (int j = 0; j < k; ++j) {
+        lo = std::min(lo, q[j]);
+        if (q[j] >= kLdsChunkBits) ++h;
+    }
+    return tier_of(dtype, lo) <= 1 && n >= kLdsChunkBits + h;
+}
+
+static void build_lds(int n, const int* q, int k, const int* ctrl, int nc, Plan* pl)
+{
+    constexpr int C = kLdsChunkBits;
+    LdsSpec& ls = pl->ls;
+    memset(&ls, 0, sizeof ls);
+    ls.k = k;
+    int hq[3], h = 0;
+    for (int j = 0; j < k; ++j)
+        if (q[j] >= C) hq[h++] = q[j];
+    std::sort(hq, hq + h);
+    ls.h = h;
+    for (int j = 0; j < h; ++j) ls.hq[j] = hq[j];
+    for (int j = 0; j < k; ++j) {
+        int lp = q[j];
+        if (q[j] >= C)
+            for (int i = 0; i < h; ++i)
+                if (hq[i] == q[j]) lp = C + i;
+        ls.lpos[j] = lp;
+        ls.lsort[j] = lp;
+    }
+    std::sort(ls.lsort, ls.lsort + k);
+    int ins[kMaxIns], nins = 0;
+    for (int j = 0; j < h; ++j) ins[nins++] = hq[j] - C;
+    for (int j = 0; j < nc; ++j) {
+        if (ctrl[j] < C) {
+            ls.pmask |= 1u << ctrl[j];
+        } else {
+            ls.cmask |= 1ull << ctrl[j];
+            ins[nins++] = ctrl[j] - C;
+        }
+    }
+    pl->gs = make_groups(n - C, ins, nins, 0, 0);
+    pl->kind = PK_LDS;
+    pl->kc = KC_LDS;
+    pl->lk = k;
+    pl->low = 64;
+    for (int j = 0; j < k; ++j) pl->low = std::min(pl->low, q[j]);
 }
 
 // Row a1 of the method: classify a gate into a kernel class with its index
@@ -339,6 +396,11 @@ static sv_status build_plan(int n, int dtype, int gate, const int* ctrl, int nc,
         return SV_OK;
     }
     case SV_SWAP: {
+        if (lds_eligible(n, dtype, tgt, 2)) {
+            build_lds(n, tgt, 2, ctrl, nc, pl);
+            pl->op = 1;
+            return SV_OK;
+        }
         split_bits(ctrl, nc, dtype, 0, &bs);
         bs.ins[bs.nins++] = tgt[0];
         bs.ins[bs.nins++] = tgt[1];
@@ -395,6 +457,17 @@ static sv_status build_plan(int n, int dtype, int gate, const int* ctrl, int nc,
     }
     case SV_U4: {
         const int a = tgt[0], b = tgt[1];  // a = most significant matrix bit
+        if (lds_eligible(n, dtype, tgt, 2)) {
+            build_lds(n, tgt, 2, ctrl, nc, pl);
+            pl->op = 0;
+            for (int r = 0; r < 4; ++r)
+                for (int c = 0; c < 4; ++c) {
+                    const int src = adjoint ? (4 * c + r) : (4 * r + c);
+                    pl->m[2 * (4 * r + c)] = matrix[2 * src];
+                    pl->m[2 * (4 * r + c) + 1] = adjoint ? -matrix[2 * src + 1] : matrix[2 * src + 1];
+                }
+            return SV_OK;
+        }
         split_bits(ctrl, nc, dtype, 0, &bs);
         bs.ins[bs.nins++] = a;
         bs.ins[bs.nins++] = b;
@@ -433,6 +506,12 @@ static hipError_t run_plan_t(const Plan& pl, void* psi, hipStream_t s, int dtype
         Coef2<T> c;
         for (int i = 0; i < 8; ++i) c.m[i] = (T)pl.m[i];
         return launch_wpair<T>(psi, pl.gs, pl.wt, pl.op, c, s, lc);
+    }
+    case PK_LDS: {
+        T m[128];
+        const int mm = 2 * (1 << pl.lk) * (1 << pl.lk);
+        for (int i = 0; i < mm; ++i) m[i] = (T)pl.m[i];
+        return launch_lds_gate<T>(psi, pl.gs, pl.ls, pl.op, m, s, lc);
     }
     case PK_ONE: return launch_one<T>(psi, pl.gs, pl.op, (T)pl.m[0], (T)pl.m[1], s, lc);
     case PK_DIAG: {
@@ -647,6 +726,27 @@ sv_status sv_apply_general(sv_state st, const int* qubits, int k, const double* 
         off[r] = o;
     }
     for (int j = 0; j < k; ++j) low = std::min(low, qubits[j]);
+    if (k == 1 && qubits[0] < 6) {
+        // the same dense 2x2, with the partner amplitude fetched across lanes
+        Plan pl;
+        memset(&pl, 0, sizeof pl);
+        pl.kind = PK_WPAIR;
+        pl.kc = KC_WAVE;
+        pl.wt = qubits[0];
+        pl.op = PAIR_DENSE;
+        pl.low = 64;
+        pl.gs = make_groups(st->n, nullptr, 0, 0, 0);
+        memcpy(pl.m, matrix, 8 * sizeof(double));
+        return run_plan(pl, st, st->data);
+    }
+    if (lds_eligible(st->n, st->dtype, qubits, k)) {
+        Plan pl;
+        memset(&pl, 0, sizeof pl);
+        build_lds(st->n, qubits, k, nullptr, 0, &pl);
+        pl.op = 0;
+        memcpy(pl.m, matrix, sizeof(double) * 2 * M * M);
+        return run_plan(pl, st, st->data);
+    }
     const Launch lc = tune_get(KC_GENERAL, st->dtype, low);
     hipError_t e;
     if (st->dtype == SV_C128) {
@@ -1153,6 +1253,14 @@ sv_status sv_plan_info(int n_qubits, int dtype, int gate, const int* controls, i
         low = 64;
         for (int j = 0; j < nt; ++j) low = std::min(low, targets[j]);
         opv = nt;
+        if (nt == 1 && targets[0] < 6) {
+            kc = KC_WAVE;
+            opv = PAIR_DENSE;
+            low = 64;
+        } else if (lds_eligible(n_qubits, dtype, targets, nt)) {
+            kc = KC_LDS;
+            opv = nt << 4;
+        }
     } else {
         Plan pl;
         const double zero = 0.0;
@@ -1162,7 +1270,7 @@ sv_status sv_plan_info(int n_qubits, int dtype, int gate, const int* controls, i
         if (pl.kind == PK_NOP) return set_error(SV_ERR_ARG, "identity launches nothing");
         kc = pl.kc;
         low = pl.low;
-        opv = pl.op;
+        opv = pl.kind == PK_LDS ? ((pl.lk << 4) | pl.op) : pl.op;
     }
     const Launch l = tune_get(kc, dtype, low);
     *kernel_class = kc;

@@ -218,10 +218,28 @@ static sv_status hip_fail(hipError_t e, const char* what)
     return set_error(SV_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-sv_status sv_batch_create(const sv_batch_circuit* circuits, int n_circuits, sv_dtype dtype, const sv_batch_opts* opts,
-                          sv_batch* out)
+// Everything a batch needs, built on the host (no device work).
+struct HostTables {
+    int tq_max, threads, with_grad, cbits_default, n_params, coef_total, tq_used, hi_entries, e_total;
+    int64_t g_total, n_items;
+    size_t state_total;
+    double pass_bytes;
+    std::vector<FCirc> circs;
+    std::vector<FPass> passes;
+    std::vector<FOp> fops;
+    std::vector<FCoefSpec> cspec;
+    std::vector<double> slot_scale;
+    std::vector<int> slot_param;
+    std::vector<int64_t> g_off, e_off, level_first;
+    std::vector<int> g_cnt, e_cnt, csr_ptr, csr_col;
+    std::vector<FSeg> segs;
+    std::vector<size_t> psi_off;
+};
+
+static sv_status compile_batch(const sv_batch_circuit* circuits, int n_circuits, int dtype, const sv_batch_opts* opts,
+                               HostTables& H)
 {
-    if (!out || !circuits || n_circuits < 1) return set_error(SV_ERR_ARG, "bad batch arguments");
+    if (!circuits || n_circuits < 1) return set_error(SV_ERR_ARG, "bad batch arguments");
     if (dtype != SV_C64 && dtype != SV_C128) return set_error(SV_ERR_ARG, "bad dtype");
     const int tq_default = dtype == SV_C128 ? 12 : 13;
     int tq_max = opts && opts->tile_qubits > 0 ? opts->tile_qubits : tq_default;
@@ -399,6 +417,90 @@ sv_status sv_batch_create(const sv_batch_circuit* circuits, int n_circuits, sv_d
         for (size_t s = 0; s < slot_param.size(); ++s) csr_col[fill[slot_param[s]]++] = (int)s;
     }
 
+    H.tq_max = tq_max;
+    H.threads = threads;
+    H.with_grad = with_grad;
+    H.cbits_default = cbits_default;
+    H.n_params = n_params;
+    H.coef_total = coef_total;
+    H.tq_used = tq_used;
+    H.hi_entries = hi_entries;
+    H.e_total = e_total;
+    H.g_total = g_total;
+    H.n_items = n_items;
+    H.state_total = state_total;
+    H.pass_bytes = pass_bytes;
+    H.circs = std::move(circs);
+    H.passes = std::move(passes);
+    H.fops = std::move(fops);
+    H.cspec = std::move(cspec);
+    H.slot_scale = std::move(slot_scale);
+    H.slot_param = std::move(slot_param);
+    H.g_off = std::move(g_off);
+    H.e_off = std::move(e_off);
+    H.level_first = std::move(level_first);
+    H.g_cnt = std::move(g_cnt);
+    H.e_cnt = std::move(e_cnt);
+    H.csr_ptr = std::move(csr_ptr);
+    H.csr_col = std::move(csr_col);
+    H.segs = std::move(segs);
+    H.psi_off = std::move(psi_off);
+    return SV_OK;
+}
+
+sv_status sv_batch_plan(const sv_batch_circuit* circuits, int n_circuits, sv_dtype dtype, const sv_batch_opts* opts,
+                        int64_t* info)
+{
+    if (!info) return set_error(SV_ERR_ARG, "null info");
+    if (dtype != SV_C64 && dtype != SV_C128) return set_error(SV_ERR_ARG, "bad dtype");
+    HostTables H;
+    sv_status rc = compile_batch(circuits, n_circuits, dtype, opts, H);
+    if (rc) return rc;
+    int maxp = 0;
+    for (const FCirc& c : H.circs) maxp = std::max(maxp, c.n_pass);
+    info[0] = n_circuits;
+    info[1] = H.n_items;
+    info[2] = (int64_t)H.passes.size();
+    info[3] = maxp;
+    info[4] = (int64_t)H.fops.size();
+    info[5] = H.n_params;
+    info[6] = (int64_t)H.state_total;
+    info[7] = (int64_t)H.pass_bytes;
+    info[8] = (int64_t)H.level_first.size() - 1;
+    info[9] = (int64_t)pass_engine_lds_bytes(H.tq_used, H.hi_entries, H.with_grad, dtype);
+    return SV_OK;
+}
+
+sv_status sv_batch_create(const sv_batch_circuit* circuits, int n_circuits, sv_dtype dtype, const sv_batch_opts* opts,
+                          sv_batch* out)
+{
+    if (!out) return set_error(SV_ERR_ARG, "null output handle");
+    if (dtype != SV_C64 && dtype != SV_C128) return set_error(SV_ERR_ARG, "bad dtype");
+    HostTables H;
+    {
+        sv_status rc = compile_batch(circuits, n_circuits, dtype, opts, H);
+        if (rc) return rc;
+    }
+    const int with_grad = H.with_grad, threads = H.threads, n_params = H.n_params, coef_total = H.coef_total;
+    const int tq_used = H.tq_used, hi_entries = H.hi_entries, e_total = H.e_total;
+    const int64_t g_total = H.g_total, n_items = H.n_items;
+    const size_t state_total = H.state_total;
+    const double pass_bytes = H.pass_bytes;
+    std::vector<FCirc>& circs = H.circs;
+    std::vector<FPass>& passes = H.passes;
+    std::vector<FOp>& fops = H.fops;
+    std::vector<FCoefSpec>& cspec = H.cspec;
+    std::vector<double>& slot_scale = H.slot_scale;
+    std::vector<int>& slot_param = H.slot_param;
+    std::vector<int64_t>& g_off = H.g_off;
+    std::vector<int64_t>& e_off = H.e_off;
+    std::vector<int64_t>& level_first = H.level_first;
+    std::vector<int>& g_cnt = H.g_cnt;
+    std::vector<int>& e_cnt = H.e_cnt;
+    std::vector<int>& csr_ptr = H.csr_ptr;
+    std::vector<int>& csr_col = H.csr_col;
+    std::vector<FSeg>& segs = H.segs;
+    std::vector<size_t>& psi_off = H.psi_off;
     // ---- device side ----
     sv_batch b = new sv_batch_s();
     b->dtype = dtype;

@@ -88,6 +88,21 @@ __device__ __forceinline__ uint64_t group_base(uint64_t g, const GroupSpec& gs)
     return g | gs.set_mask;
 }
 
+// LDS-staged single gate: a block stages 2^(kLdsChunkBits + h) amplitudes --
+// 2^h contiguous chunks of 2^kLdsChunkBits, one per combination of the h gate
+// qubits at or above kLdsChunkBits -- applies the gate to every group inside
+// the stage and streams the chunks back.
+constexpr int kLdsChunkBits = 8;
+struct LdsSpec {
+    int32_t k;        // gate qubits (1..3)
+    int32_t h;        // gate qubits >= kLdsChunkBits
+    int32_t hq[3];    // those qubits, ascending (absolute positions)
+    int32_t lpos[3];  // local bit of gate qubit j (j = 0 is the matrix MSB)
+    int32_t lsort[3]; // lpos sorted ascending (group insertion order)
+    uint32_t pmask;   // local bits (controls below kLdsChunkBits) that must be 1
+    uint64_t cmask;   // absolute control bits at or above kLdsChunkBits (inserted, set to 1)
+};
+
 struct Launch {
     int block;   // threads per block
     int unroll;  // groups per thread (1, 2 or 4)
@@ -132,6 +147,12 @@ hipError_t launch_pair(void* psi, const GroupSpec& gs, uint64_t o0, uint64_t o1,
 template <typename T>
 hipError_t launch_wpair(void* psi, const GroupSpec& gs, int t, int op, const Coef2<T>& c, hipStream_t s,
                         Launch lc);
+// op: 0 = dense 2^k x 2^k (m holds 2 * 4^k values), 1 = SWAP of the two
+// gate qubits (k = 2; pure moves).  `tiles` enumerates stages: zero bits
+// inserted at (p - kLdsChunkBits) for every inserted high position p, no set mask.
+template <typename T>
+hipError_t launch_lds_gate(void* psi, const GroupSpec& tiles, const LdsSpec& ls, int op, const T* m, hipStream_t s,
+                           Launch lc);
 template <typename T>
 hipError_t launch_one(void* psi, const GroupSpec& gs, int op, T zr, T zi, hipStream_t s, Launch lc);
 template <typename T>

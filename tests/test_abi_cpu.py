@@ -182,3 +182,24 @@ def test_batch_create_validation_is_host_side():
     bad = _lib.SvBatchOpts(0, 100, 1, 1)  # threads not a multiple of 64
     assert lib.sv_batch_create(circ, 1, 2, ctypes.byref(bad), ctypes.byref(h)) == ARG
     assert lib.sv_batch_run(ctypes.c_void_p(0x1234), None, 0, None, None, 0) == HANDLE
+
+
+def test_batch_plan_fuses_gates_host_only():
+    # The pass scheduler runs on the host: a 32-qubit, 10-layer hardware-efficient
+    # ansatz (950 gates) needs far fewer state passes than gates, every pass
+    # fits a 2^12-amplitude tile, and the adjoint doubles the stage count.
+    import workloads as W
+    ops = W.hea_ops(32, 10)
+    fwd = sv.batch_plan([(32, ops, W.hea_n_params(32, 10), "sum_z")], "c128", with_grad=False)
+    adj = sv.batch_plan([(32, ops, W.hea_n_params(32, 10), "sum_z")], "c128", with_grad=True)
+    assert fwd["fused_ops"] == len(ops)
+    assert fwd["passes"] <= len(ops) // 20
+    assert fwd["items"] == (fwd["passes"] + 1) * 2 ** 20
+    assert adj["levels"] == 2 * adj["passes"] + 1
+    assert fwd["lds_bytes"] <= 160 * 1024 and adj["lds_bytes"] <= 160 * 1024
+    q = sv.batch_plan([(32, W.qft_ops(32), 0, "sum_z")], "c128", with_grad=False)
+    assert q["passes"] < len(W.qft_ops(32)) // 4
+    # tiny tiles: more passes, same gates
+    small = sv.batch_plan([(10, W.hea_ops(10, 3), 60, "sum_z")], "c64", tile_qubits=4, with_grad=False)
+    big = sv.batch_plan([(10, W.hea_ops(10, 3), 60, "sum_z")], "c64", tile_qubits=0, with_grad=False)
+    assert small["passes"] > big["passes"] == 1

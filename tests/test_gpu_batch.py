@@ -149,3 +149,22 @@ def test_batch_large_circuit_multi_tile():
     assert abs(e[0] - oracle.energy(n, ops, th, W.sum_zz(n))) <= 1e-11
     info = b.info()
     assert info["max_passes"] < len(ops) / 4  # fusion: far fewer passes than gates
+
+
+def test_config3_circuits_at_20_qubits_vs_oracle():
+    """HEA (10 layers) and QFT of a random basis state at 20 qubits on the
+    fused engine: complex128 within 1e-12, complex64 within 1e-5 of the fp64
+    oracle per amplitude (the complex64 error is printed)."""
+    n = 20
+    x = W.random_basis_index(n, 1004)
+    prep = [W.Op("X", (), (q,)) for q in range(n) if (x >> q) & 1]
+    th = W.uniform_angles(W.hea_n_params(n, 10), 1003)
+    for name, ops, p in (("hea", W.hea_ops(n, 10), th), ("qft", prep + W.qft_ops(n), np.zeros(0))):
+        ref = oracle.run_circuit(oracle.zero_state(n), ops, p)
+        for dtype, tol in (("c128", 1e-12), ("c64", 1e-5)):
+            b = sv.Batch([(n, ops, len(p), "sum_z")], dtype, with_grad=False)
+            e, _ = b.run(p)
+            err = float(np.max(np.abs(b.state(0).astype(np.complex128) - ref)))
+            print(f"{name} n={n} {dtype}: max |psi - psi_oracle| = {err:.2e}, passes {b.info()['passes']}", flush=True)
+            assert err <= tol, (name, dtype, err)
+            assert abs(e[0] - oracle.expval_obs(ref, W.sum_z(n))) <= tol * n
