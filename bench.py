@@ -12,6 +12,9 @@ Sec. 3.1), and the step ends with one expectation value (sum_i Z_i Z_{i+1}).
 Also reported on the same JSON line:
   roofline      the dominant kernel's algorithmic bytes per launch over its
                 average HIP-event-timed launch duration, against 8 TB/s;
+                `traffic` is its measured HBM bytes per launch, read from the
+                committed PMC summary (null once the kernel sources differ
+                from the ones the counters were taken with);
   copy          a device-to-device copy of the state (the measured ceiling);
   cpu_baseline  the oracle on the host cores on a bounded sample;
   adjoint       24 qubits, 8 layers RY+RZ + CNOT ladder, 384 params,
@@ -39,6 +42,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "gates/sec & effective HBM GB/s at 30 qubits c128; adjoint grad vs param-shift s"
 PEAK_GBPS = 8000.0
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "pmc_sweep30_c128.md")
 
 
 def log(*a):
@@ -176,8 +180,45 @@ def measure_copy(sv, torch, state):
     return 2 * state.tensor.numel() * state.tensor.element_size() / t / 1e9
 
 
-def cpu_baseline(qubits_cpu, qubits_gpu):
-    import numpy as np
+def kernel_sources_sha256():
+    """SHA-256 over the HIP sources and the ABI header (file name + bytes, in
+    name order); the PMC summary records the value it was measured with."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    files = sorted(glob.glob(os.path.join(ROOT, "paper_2508_13615_amd", "csrc", "*")))
+    files.append(os.path.join(ROOT, "include", "sv.h"))
+    for p in files:
+        h.update(os.path.basename(p).encode())
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def pmc_traffic(kernel, summary=PMC_SUMMARY):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 PMC
+    summary (FETCH_SIZE and WRITE_SIZE scaled by a copy of known size), or
+    None when there is no entry or the kernels changed since it was taken."""
+    if not os.path.exists(summary):
+        return None
+    with open(summary) as f:
+        text = f.read()
+    a = text.find("```json")
+    if a < 0:
+        return None
+    b = text.find("```", a + 7)
+    blk = json.loads(text[a + 7:b])
+    if blk.get("source_sha256") != kernel_sources_sha256():
+        return None
+    e = blk["kernels"].get(kernel)
+    return None if e is None else e["traffic_bytes"]
+
+
+def cpu_baseline(qubits_cpu, qubits_gpu, min_seconds=10.0):
+    """The oracle on the host cores: X, H, RZ, CNOT, CZ and Toffoli at three
+    targets on a Gaussian state, the list repeated until at least
+    `min_seconds` of work has run; the rate is scaled to `qubits_gpu`
+    (the oracle's work is linear in the amplitude count)."""
     import oracle
     import workloads as W
     psi = W.gaussian_state(qubits_cpu, 1001)
@@ -189,15 +230,20 @@ def cpu_baseline(qubits_cpu, qubits_gpu):
         sample += [("X", (t,), ()), ("H", (t,), ()), ("RZ", (t,), (), (0.7,)), ("X", (t,), (c,)),
                    ("Z", (t,), (c,)), ("X", (t,), (c, c2))]
     oracle.apply_gate(psi, "H", (1,))  # warm-up
+    gates = 0
     t0 = time.perf_counter()
-    for s in sample:
-        oracle.apply_gate(psi, s[0], s[1], s[2], s[3] if len(s) > 3 else ())
-    dt = time.perf_counter() - t0
-    rate = len(sample) / dt * 2.0 ** (qubits_cpu - qubits_gpu)
+    while True:
+        for s in sample:
+            oracle.apply_gate(psi, s[0], s[1], s[2], s[3] if len(s) > 3 else ())
+        gates += len(sample)
+        dt = time.perf_counter() - t0
+        if dt >= min_seconds:
+            break
+    rate = gates / dt * 2.0 ** (qubits_cpu - qubits_gpu)
     return {"value": rate, "unit": "gates/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": (f"X, H, RZ, CNOT, CZ, Toffoli at t in {ts} on a {qubits_cpu}-qubit complex128 Gaussian "
-                       f"state ({len(sample)} gates, {dt:.1f} s), rate scaled by 2^{qubits_cpu - qubits_gpu} "
-                       f"to {qubits_gpu} qubits (work is linear in the amplitude count)")}
+            "sample": (f"X, H, RZ, CNOT, CZ, Toffoli at t in {ts} on a {qubits_cpu}-qubit complex128 Gaussian state, "
+                       f"{gates} gates in {dt:.1f} s; rate scaled by 2^{qubits_cpu - qubits_gpu} to {qubits_gpu} "
+                       f"qubits (the oracle's work is linear in the amplitude count)")}
 
 
 def adjoint_compare(sv, torch, n, layers, ps_params, full_ps):
@@ -412,7 +458,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--qubits", type=int, default=30)
-    ap.add_argument("--cpu-qubits", type=int, default=26)
+    ap.add_argument("--cpu-qubits", type=int, default=27)
     ap.add_argument("--skip-cpu-baseline", action="store_true")
     ap.add_argument("--skip-adjoint", action="store_true")
     ap.add_argument("--adjoint-qubits", type=int, default=24)
@@ -498,9 +544,11 @@ def main():
     dk, (dt_, db, dc) = dom
     achieved = db / dt_ / 1e9
     roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_GBPS, "unit": "GB/s", "frac": achieved / PEAK_GBPS,
-            "traffic": None, "kernel": dk, "launches": dc, "avg_launch_ms": 1e3 * dt_ / dc,
+            "traffic": pmc_traffic(dk), "kernel": dk, "launches": dc, "avg_launch_ms": 1e3 * dt_ / dc,
             "algorithmic_bytes_per_launch": db / dc}
 
+    if roof["traffic"] is not None:
+        roof["traffic_over_algorithmic"] = roof["traffic"] / roof["algorithmic_bytes_per_launch"]
     out = {
         "metric": METRIC,
         "value": n_spec / t_spec,
