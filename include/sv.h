@@ -255,7 +255,8 @@ typedef struct {
 
 typedef struct {
     int32_t tile_qubits; /* 0 = default (12 complex128, 13 complex64); 2..13 */
-    int32_t threads;     /* 0 = default (512); multiple of 64 in [64, 1024] */
+    int32_t amps_per_thread; /* 0 = default (16); 8 or 16: amplitudes of a tile each thread
+                              * holds in registers (workgroup = 2^tile_qubits / this, >= 64) */
     int32_t use_graph;   /* capture the run on first use, replay afterwards */
     int32_t with_grad;   /* also run the adjoint sweep */
 } sv_batch_opts;
@@ -280,10 +281,12 @@ sv_status sv_batch_run(sv_batch b, const double* params, int params_on_device, d
 sv_status sv_batch_plan(const sv_batch_circuit* circuits, int n_circuits, sv_dtype dtype,
                         const sv_batch_opts* opts, int64_t* info);
 
-/* info[0..9]: circuits, work items, passes, max passes per circuit, fused
- * ops, parameters, state bytes, algorithmic HBM bytes per run, stage levels
- * (kernel launches per run, besides the small setup and reduction kernels),
- * LDS bytes per workgroup. */
+/* info[0..11]: circuits, work items, passes, max passes per circuit, gate
+ * ops scheduled, parameters, state bytes, algorithmic HBM bytes per run,
+ * stage levels (each launches up to three kernels: forward, observable and
+ * reverse items), LDS bytes per workgroup, layout changes in the forward
+ * passes (each an LDS exchange of every tile), workgroup size of forward
+ * passes. */
 sv_status sv_batch_info(sv_batch b, int64_t* info);
 
 /* Device pointer to a circuit's state (after a forward-only run: U|0...0>). */

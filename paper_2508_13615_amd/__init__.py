@@ -255,7 +255,7 @@ class Circuit:
 
 _OBS_KIND = {"sum_z": 1, "sum_zz": 2}
 _INFO_KEYS = ["circuits", "items", "passes", "max_passes", "fused_ops", "params", "state_bytes", "pass_bytes",
-              "levels", "lds_bytes"]
+              "levels", "lds_bytes", "layout_changes", "threads"]
 
 
 def _batch_structs(circuits):
@@ -272,12 +272,13 @@ def _batch_structs(circuits):
     return arr, keep
 
 
-def batch_plan(circuits, dtype: str = "c128", tile_qubits: int = 0, threads: int = 0, with_grad: bool = True) -> dict:
+def batch_plan(circuits, dtype: str = "c128", tile_qubits: int = 0, amps_per_thread: int = 0,
+               with_grad: bool = True) -> dict:
     """Schedule a batch on the host only (no GPU needed) and report its figures."""
     circuits = list(circuits)
     arr, keep = _batch_structs(circuits)
-    opts = SvBatchOpts(int(tile_qubits), int(threads), 1, int(bool(with_grad)))
-    a = (ctypes.c_int64 * 10)()
+    opts = SvBatchOpts(int(tile_qubits), int(amps_per_thread), 1, int(bool(with_grad)))
+    a = (ctypes.c_int64 * 12)()
     check(lib.sv_batch_plan(arr, len(circuits), _SV_DT[dtype], ctypes.byref(opts), a))
     return dict(zip(_INFO_KEYS, list(a)))
 
@@ -287,7 +288,7 @@ class Batch:
     (sv_batch_*).  circuits: sequence of (n_qubits, ops, n_params, observable)
     with observable "sum_z" or "sum_zz"."""
 
-    def __init__(self, circuits, dtype: str = "c128", tile_qubits: int = 0, threads: int = 0,
+    def __init__(self, circuits, dtype: str = "c128", tile_qubits: int = 0, amps_per_thread: int = 0,
                  use_graph: bool = True, with_grad: bool = True):
         circuits = list(circuits)
         self.dtype = dtype
@@ -296,7 +297,7 @@ class Batch:
         self.n_params = [int(c[2]) for c in circuits]
         self.with_grad = bool(with_grad)
         arr, keep = _batch_structs(circuits)
-        opts = SvBatchOpts(int(tile_qubits), int(threads), int(bool(use_graph)), int(bool(with_grad)))
+        opts = SvBatchOpts(int(tile_qubits), int(amps_per_thread), int(bool(use_graph)), int(bool(with_grad)))
         h = ctypes.c_void_p()
         check(lib.sv_batch_create(arr, len(circuits), _SV_DT[dtype], ctypes.byref(opts), ctypes.byref(h)))
         self.handle = h
@@ -322,7 +323,7 @@ class Batch:
                                ctypes.c_void_p(expvals.data_ptr()), ctypes.c_void_p(grads.data_ptr()), 1))
 
     def info(self) -> dict:
-        a = (ctypes.c_int64 * 10)()
+        a = (ctypes.c_int64 * 12)()
         check(lib.sv_batch_info(self.handle, a))
         return dict(zip(_INFO_KEYS, list(a)))
 

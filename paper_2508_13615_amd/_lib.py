@@ -50,7 +50,7 @@ class SvBatchCircuit(ctypes.Structure):
 
 
 class SvBatchOpts(ctypes.Structure):
-    _fields_ = [("tile_qubits", ctypes.c_int32), ("threads", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+    _fields_ = [("tile_qubits", ctypes.c_int32), ("amps_per_thread", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("with_grad", ctypes.c_int32)]
 
 

@@ -20,10 +20,16 @@ CFLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-Wall", "-Wno
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-I", os.path.join(os.path.dirname(HERE), "include")]
 
+# Per-file flags.  The register-tiled pass kernels dispatch on the register
+# bit of a target through a switch whose cases differ only in which array
+# elements they touch; sinking their common code would turn those into
+# dynamically indexed (scratch-resident) arrays.
+FILE_FLAGS = {"k_pass.hip": ["-mllvm", "-simplifycfg-sink-common=false"]}
+
 
 def _compile(src):
     obj = os.path.join(OBJ, os.path.basename(src) + ".o")
-    cmd = ["hipcc", *CFLAGS, "-c", src, "-o", obj]
+    cmd = ["hipcc", *CFLAGS, *FILE_FLAGS.get(os.path.basename(src), []), "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     # hipcc's host pass warns that it does not know the packed-fp32 feature
     err = "\n".join(l for l in r.stderr.splitlines() if "packed-fp32-ops" not in l)

@@ -204,139 +204,646 @@ __device__ double block_sum_fixed(double v, double* red)
     return s;
 }
 
+// ---------------------------------------------------------------------------
+// Register-tiled passes.  The tile's 2^tq amplitudes are spread over
+// 2^(tq - RB) threads, 2^RB per thread (the layout says which tile-local bits
+// are lane bits and which are register bits).  An op whose targets are
+// register bits runs entirely in registers: no LDS traffic and no barrier.
+// Diagonal and subset-phase ops need no particular layout.  Between groups of
+// ops the host inserts a layout change, the only step that goes through LDS
+// (every thread writes its amplitudes, barrier, reads its new ones).
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ uint32_t swz(uint32_t l)
+{
+    // l < 2^16: fold bit groups [4, 8), [8, 12), [12, 16) into [0, 4)
+    return l ^ (((l >> 4) ^ (l >> 8) ^ (l >> 12)) & ((1u << kSwzBits) - 1u));
+}
+
+// Lane bits of the thread and register offsets of a layout.
+template <int RB>
+__device__ __forceinline__ void frame_of(const FLayout* __restrict__ L, int tq, uint32_t tid, uint32_t& tl,
+                                         uint32_t* off)
+{
+    const int nl = tq - RB;
+    uint32_t t = 0;
+    for (int i = 0; i < nl; ++i) t |= ((tid >> i) & 1u) << L->pos[i];
+    tl = t;
+    uint32_t rbit[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) rbit[r] = 1u << L->pos[nl + r];
+    off[0] = 0;
+#pragma unroll
+    for (int j = 1; j < (1 << RB); ++j) off[j] = off[j & (j - 1)] | rbit[__builtin_ctz(j)];
+}
+
+// Global element offsets of this thread's registers in a layout.
+template <int RB>
+__device__ __forceinline__ void global_frame(const FLayout* __restrict__ L, const int32_t* __restrict__ q, int tq,
+                                             uint32_t tid, uint64_t tile_base, uint64_t* g)
+{
+    const int nl = tq - RB;
+    uint64_t t = tile_base;
+    for (int i = 0; i < nl; ++i)
+        if ((tid >> i) & 1u) t |= 1ull << q[L->pos[i]];
+    uint64_t rbit[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) rbit[r] = 1ull << q[L->pos[nl + r]];
+    g[0] = t;
+#pragma unroll
+    for (int j = 1; j < (1 << RB); ++j) g[j] = g[j & (j - 1)] | rbit[__builtin_ctz(j)];
+}
+
+template <typename V, int RB>
+__device__ __forceinline__ void lds_put(V* __restrict__ lds, const V* v, uint32_t tl, const uint32_t* off)
+{
+#pragma unroll
+    for (int j = 0; j < (1 << RB); ++j) lds[swz(tl | off[j])] = v[j];
+}
+
+template <typename V, int RB>
+__device__ __forceinline__ void lds_get(const V* __restrict__ lds, V* v, uint32_t tl, const uint32_t* off)
+{
+#pragma unroll
+    for (int j = 0; j < (1 << RB); ++j) v[j] = lds[swz(tl | off[j])];
+}
+
+template <typename T, int RB, int K>
+__device__ __forceinline__ void rpair_k(typename Vec2<T>::type* v, const T* u, uint32_t tl, const uint32_t* off,
+                                        uint32_t cm)
+{
+#pragma unroll
+    for (int j = 0; j < (1 << RB); ++j) {
+        if (j & (1 << K)) continue;
+        if (((tl | off[j]) & cm) != cm) continue;
+        const int j1 = j | (1 << K);
+        const auto a = v[j], b = v[j1];
+        v[j] = cmul_add2<typename Vec2<T>::type, T>(u[0], u[1], a, u[2], u[3], b);
+        v[j1] = cmul_add2<typename Vec2<T>::type, T>(u[4], u[5], a, u[6], u[7], b);
+    }
+}
+
+template <typename T, int RB, int KA, int KB>
+__device__ __forceinline__ void rswap_k(typename Vec2<T>::type* v, uint32_t tl, const uint32_t* off, uint32_t cm)
+{
+#pragma unroll
+    for (int j = 0; j < (1 << RB); ++j) {
+        if (!(j & (1 << KA)) || (j & (1 << KB))) continue;  // j: bit a = 1, bit b = 0
+        if (((tl | off[j]) & cm) != cm) continue;
+        const int j1 = j ^ (1 << KA) ^ (1 << KB);
+        const auto t = v[j];
+        v[j] = v[j1];
+        v[j1] = t;
+    }
+}
+
+// 4x4 on register bits KA (matrix MSB) and KB; u = 16 complex entries row-major
+template <typename T, int RB, int KA, int KB>
+__device__ __forceinline__ void rquad_k(typename Vec2<T>::type* v, const T* u, uint32_t tl, const uint32_t* off,
+                                        uint32_t cm)
+{
+    using V = typename Vec2<T>::type;
+#pragma unroll
+    for (int j = 0; j < (1 << RB); ++j) {
+        if (j & ((1 << KA) | (1 << KB))) continue;
+        if (((tl | off[j]) & cm) != cm) continue;
+        const int ix[4] = {j, j | (1 << KB), j | (1 << KA), j | (1 << KA) | (1 << KB)};
+        V w[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) w[k] = v[ix[k]];
+#pragma unroll
+        for (int row = 0; row < 4; ++row) {
+            T sr = T(0), si = T(0);
+#pragma unroll
+            for (int col = 0; col < 4; ++col) {
+                const T ur = u[2 * (4 * row + col)], ui = u[2 * (4 * row + col) + 1];
+                sr += ur * w[col].x - ui * w[col].y;
+                si += ur * w[col].y + ui * w[col].x;
+            }
+            v[ix[row]].x = sr;
+            v[ix[row]].y = si;
+        }
+    }
+}
+
+template <typename T, int RB>
+__device__ __forceinline__ void rpair(int k, typename Vec2<T>::type* v, const T* u, uint32_t tl, const uint32_t* off,
+                                      uint32_t cm)
+{
+    switch (k) {
+    case 0: rpair_k<T, RB, 0>(v, u, tl, off, cm); break;
+    case 1: rpair_k<T, RB, 1>(v, u, tl, off, cm); break;
+    case 2: rpair_k<T, RB, 2>(v, u, tl, off, cm); break;
+    default:
+        if constexpr (RB > 3) rpair_k<T, RB, 3>(v, u, tl, off, cm);
+        break;
+    }
+}
+
+#define SV_RB_PAIRS(X)                                                                                             \
+    X(0, 1) X(0, 2) X(1, 0) X(1, 2) X(2, 0) X(2, 1)
+#define SV_RB4_PAIRS(X) X(0, 3) X(1, 3) X(2, 3) X(3, 0) X(3, 1) X(3, 2)
+
+template <typename T, int RB>
+__device__ __forceinline__ void rswap(int ka, int kb, typename Vec2<T>::type* v, uint32_t tl, const uint32_t* off,
+                                      uint32_t cm)
+{
+    switch (ka * 4 + kb) {
+#define SV_CASE(A, B)                                                                                              \
+    case A * 4 + B: rswap_k<T, RB, A, B>(v, tl, off, cm); break;
+        SV_RB_PAIRS(SV_CASE)
+#undef SV_CASE
+    default:
+        if constexpr (RB > 3) {
+            switch (ka * 4 + kb) {
+#define SV_CASE(A, B)                                                                                              \
+    case A * 4 + B: rswap_k<T, RB, (A < 4 ? A : 0), (B < 4 ? B : 0)>(v, tl, off, cm); break;
+                SV_RB4_PAIRS(SV_CASE)
+#undef SV_CASE
+            default: break;
+            }
+        }
+        break;
+    }
+}
+
+template <typename T, int RB>
+__device__ __forceinline__ void rquad(int ka, int kb, typename Vec2<T>::type* v, const T* u, uint32_t tl,
+                                      const uint32_t* off, uint32_t cm)
+{
+    switch (ka * 4 + kb) {
+#define SV_CASE(A, B)                                                                                              \
+    case A * 4 + B: rquad_k<T, RB, A, B>(v, u, tl, off, cm); break;
+        SV_RB_PAIRS(SV_CASE)
+#undef SV_CASE
+    default:
+        if constexpr (RB > 3) {
+            switch (ka * 4 + kb) {
+#define SV_CASE(A, B)                                                                                              \
+    case A * 4 + B: rquad_k<T, RB, (A < 4 ? A : 0), (B < 4 ? B : 0)>(v, u, tl, off, cm); break;
+                SV_RB4_PAIRS(SV_CASE)
+#undef SV_CASE
+            default: break;
+            }
+        }
+        break;
+    }
+}
+
+// Apply one op (or its inverse) to this thread's registers.
+template <typename T, int RB>
+__device__ __forceinline__ void reg_apply(typename Vec2<T>::type* v, const FOp& op, const double* __restrict__ coef,
+                                          bool dagger, uint32_t tl, const uint32_t* off)
+{
+    using V = typename Vec2<T>::type;
+    const double* cf = coef + op.coef;
+    switch (op.kind) {
+    case FK_PAIR: {
+        T u[8];
+        load2x2<T>(cf, dagger, u);
+        rpair<T, RB>(op.ka, v, u, tl, off, op.cm);
+        break;
+    }
+    case FK_DIAG: {
+        const T d0r = (T)cf[0], d0i = (T)(dagger ? -cf[1] : cf[1]);
+        const T d1r = (T)cf[2], d1i = (T)(dagger ? -cf[3] : cf[3]);
+#pragma unroll
+        for (int j = 0; j < (1 << RB); ++j) {
+            const uint32_t l = tl | off[j];
+            if ((l & op.cm) != op.cm) continue;
+            const bool b = (l >> op.a) & 1u;
+            const T zr = b ? d1r : d0r, zi = b ? d1i : d0i;
+            const V x = v[j];
+            v[j].x = zr * x.x - zi * x.y;
+            v[j].y = zr * x.y + zi * x.x;
+        }
+        break;
+    }
+    case FK_PHASE: {
+        const T zr = (T)cf[0], zi = (T)(dagger ? -cf[1] : cf[1]);
+#pragma unroll
+        for (int j = 0; j < (1 << RB); ++j) {
+            if (((tl | off[j]) & op.cm) != op.cm) continue;
+            const V x = v[j];
+            v[j].x = zr * x.x - zi * x.y;
+            v[j].y = zr * x.y + zi * x.x;
+        }
+        break;
+    }
+    case FK_SWAP: rswap<T, RB>(op.ka, op.kb, v, tl, off, op.cm); break;
+    case FK_QUAD: {
+        T u[32];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int e = dagger ? (4 * c + r) : (4 * r + c);
+                u[2 * (4 * r + c)] = (T)cf[2 * e];
+                u[2 * (4 * r + c) + 1] = (T)(dagger ? -cf[2 * e + 1] : cf[2 * e + 1]);
+            }
+        rquad<T, RB>(op.ka, op.kb, v, u, tl, off, op.cm);
+        break;
+    }
+    default: break;
+    }
+}
+
+// Per-thread Im <lambda|G|phi> over this thread's registers (generator of a
+// parameterised one-target op, restricted to its controls).
+template <typename T, int RB, int K>
+__device__ __forceinline__ double rgen_pair_k(const typename Vec2<T>::type* P, const typename Vec2<T>::type* L,
+                                              bool gy, uint32_t tl, const uint32_t* off, uint32_t cm)
+{
+    double acc = 0.0;
+#pragma unroll
+    for (int j = 0; j < (1 << RB); ++j) {
+        if (j & (1 << K)) continue;
+        if (((tl | off[j]) & cm) != cm) continue;
+        const int j1 = j | (1 << K);
+        const double a0r = P[j].x, a0i = P[j].y, a1r = P[j1].x, a1i = P[j1].y;
+        const double l0r = L[j].x, l0i = L[j].y, l1r = L[j1].x, l1i = L[j1].y;
+        if (!gy) acc += (l0r * a1i - l0i * a1r) + (l1r * a0i - l1i * a0r);
+        else acc += (l0r * (-a1r) - l0i * a1i) + (l1r * a0r - l1i * (-a0i));
+    }
+    return acc;
+}
+
+template <typename T, int RB>
+__device__ __forceinline__ double reg_gen_inner(const typename Vec2<T>::type* P, const typename Vec2<T>::type* L,
+                                                const FOp& op, uint32_t tl, const uint32_t* off)
+{
+    const uint32_t cm = op.cm & ~(1u << op.a);  // a subset-phase op lists its target in cm
+    if (op.gen == GEN_X || op.gen == GEN_Y) {
+        const bool gy = op.gen == GEN_Y;
+        switch (op.ka) {
+        case 0: return rgen_pair_k<T, RB, 0>(P, L, gy, tl, off, cm);
+        case 1: return rgen_pair_k<T, RB, 1>(P, L, gy, tl, off, cm);
+        case 2: return rgen_pair_k<T, RB, 2>(P, L, gy, tl, off, cm);
+        default:
+            if constexpr (RB > 3) return rgen_pair_k<T, RB, 3>(P, L, gy, tl, off, cm);
+            return 0.0;
+        }
+    }
+    double acc = 0.0;
+    const bool gz = op.gen == GEN_Z;
+#pragma unroll
+    for (int j = 0; j < (1 << RB); ++j) {
+        const uint32_t l = tl | off[j];
+        if ((l & cm) != cm) continue;
+        const bool b = (l >> op.a) & 1u;
+        const double t = (double)L[j].x * (double)P[j].y - (double)L[j].y * (double)P[j].x;
+        if (gz) acc += b ? -t : t;
+        else if (b) acc += t;
+    }
+    return acc;
+}
+
+// Sum per slot of the wave partials, in fixed wave order, to the per-tile table.
+__device__ __forceinline__ void flush_slots(const PassTables& tb, const FCirc& cc, int op_begin, int op_end,
+                                            int tile, const double* wpart)
+{
+    if (threadIdx.x != 0) return;
+    const int nwaves = (blockDim.x + 63) >> 6;
+    int k = 0;
+    for (int o = op_end - 1; o >= op_begin; --o) {
+        const FOp& op = tb.ops[o];
+        if (op.kind == FK_LAYOUT || op.slot < 0) continue;
+        double s = 0.0;
+        for (int w = 0; w < nwaves; ++w) s += wpart[k * 16 + w];
+        tb.g_part[cc.g_part_begin + (int64_t)op.slot * cc.n_tiles + tile] = s;
+        ++k;
+    }
+}
+
+// Tile base (global index with zeros at the tile's qubits) of tile `tile`.
+__device__ __forceinline__ uint64_t tile_base_of(const FPass& ps, int tq, int tile)
+{
+    uint64_t b = (uint64_t)tile;
+    for (int k = 0; k < tq; ++k) {
+        const int p = ps.q[k];
+        b = ((b >> p) << (p + 1)) | (b & ((1ull << p) - 1ull));
+    }
+    return b;
+}
+
+template <typename T, int RB>
+__device__ __forceinline__ void item_reg_fwd(const PassTables& tb, const FCirc& cc, int pidx, int tile,
+                                             typename Vec2<T>::type* lds)
+{
+    using V = typename Vec2<T>::type;
+    constexpr int R = 1 << RB;
+    const int tq = cc.tq;
+    const FPass& ps = tb.passes[cc.pass_begin + pidx];
+    const bool active = threadIdx.x < (1u << (tq - RB));
+    const uint64_t tile_base = tile_base_of(ps, tq, tile);
+    V* const psi = (V*)cc.psi;
+    uint32_t tl, off[R];
+    V v[R];
+    int cur = ps.lay_begin;
+    frame_of<RB>(tb.lays + cur, tq, threadIdx.x, tl, off);
+    if (active) {
+        uint64_t g[R];
+        global_frame<RB>(tb.lays + cur, ps.q, tq, threadIdx.x, tile_base, g);
+        if (pidx == 0) {
+#pragma unroll
+            for (int j = 0; j < R; ++j) {
+                v[j].x = g[j] == 0 ? T(1) : T(0);
+                v[j].y = T(0);
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < R; ++j) v[j] = ldg<true>(psi + g[j]);
+        }
+    }
+    for (int o = ps.op_begin; o < ps.op_end; ++o) {
+        const FOp op = tb.ops[o];
+        if (op.kind == FK_LAYOUT) {
+            if (op.a == cur) continue;
+            if (active) lds_put<V, RB>(lds, v, tl, off);
+            __syncthreads();
+            cur = op.a;
+            frame_of<RB>(tb.lays + cur, tq, threadIdx.x, tl, off);
+            if (active) lds_get<V, RB>(lds, v, tl, off);
+            __syncthreads();
+            continue;
+        }
+        if (active) reg_apply<T, RB>(v, op, tb.coef, false, tl, off);
+    }
+    if (active) {
+        uint64_t g[R];
+        global_frame<RB>(tb.lays + cur, ps.q, tq, threadIdx.x, tile_base, g);
+#pragma unroll
+        for (int j = 0; j < R; ++j) stg<true>(psi + g[j], v[j]);
+    }
+}
+
+// Reverse pass: phi (= psi) and lambda, the reverse op list walked backwards.
+template <typename T, int RB>
+__device__ __forceinline__ void item_reg_rev(const PassTables& tb, const FCirc& cc, int pidx, int tile,
+                                             typename Vec2<T>::type* lds, double* wpart)
+{
+    using V = typename Vec2<T>::type;
+    constexpr int R = 1 << RB;
+    const int tq = cc.tq;
+    const FPass& ps = tb.passes[cc.pass_begin + pidx];
+    const bool active = threadIdx.x < (1u << (tq - RB));
+    const uint64_t tile_base = tile_base_of(ps, tq, tile);
+    V* const psi = (V*)cc.psi;
+    V* const lam = (V*)cc.lam;
+    uint32_t tl, off[R];
+    V v[R], w[R];
+    int cur = ps.rlay_end;
+    frame_of<RB>(tb.lays + cur, tq, threadIdx.x, tl, off);
+    if (active) {
+        uint64_t g[R];
+        global_frame<RB>(tb.lays + cur, ps.q, tq, threadIdx.x, tile_base, g);
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            v[j] = ldg<true>(psi + g[j]);
+            w[j] = ldg<true>(lam + g[j]);
+        }
+    }
+    int nslot = 0;
+    for (int o = ps.rop_end - 1; o >= ps.rop_begin; --o) {
+        const FOp op = tb.ops[o];
+        if (op.kind == FK_LAYOUT) {
+            if (op.b == cur) continue;
+            uint32_t tl2, off2[R];
+            frame_of<RB>(tb.lays + op.b, tq, threadIdx.x, tl2, off2);
+            if (active) lds_put<V, RB>(lds, v, tl, off);
+            __syncthreads();
+            if (active) lds_get<V, RB>(lds, v, tl2, off2);
+            __syncthreads();
+            if (active) lds_put<V, RB>(lds, w, tl, off);
+            __syncthreads();
+            if (active) lds_get<V, RB>(lds, w, tl2, off2);
+            __syncthreads();
+            cur = op.b;
+            tl = tl2;
+#pragma unroll
+            for (int j = 0; j < R; ++j) off[j] = off2[j];
+            continue;
+        }
+        if (op.slot >= 0) {
+            const double c = wave_sum(active ? reg_gen_inner<T, RB>(v, w, op, tl, off) : 0.0);
+            if ((threadIdx.x & 63) == 0) wpart[nslot * 16 + (threadIdx.x >> 6)] = c;
+            ++nslot;
+        }
+        if (active) {
+            reg_apply<T, RB>(v, op, tb.coef, true, tl, off);
+            reg_apply<T, RB>(w, op, tb.coef, true, tl, off);
+        }
+    }
+    __syncthreads();  // every wave's partials are in LDS
+    flush_slots(tb, cc, ps.rop_begin, ps.rop_end, tile, wpart);
+    if (active) {
+        uint64_t g[R];
+        global_frame<RB>(tb.lays + cur, ps.q, tq, threadIdx.x, tile_base, g);
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            stg<true>(psi + g[j], v[j]);
+            stg<true>(lam + g[j], w[j]);
+        }
+    }
+}
+
+// Observable stage: lambda = O psi on contiguous chunk `tile` and its partial of <psi|O|psi>.
 template <typename T>
-__global__ void __launch_bounds__(1024)
-k_pass_engine(PassTables tb, int64_t item_begin, int64_t item_end)
+__device__ __forceinline__ void item_observable(const PassTables& tb, const FCirc& cc, int tile, double* red)
+{
+    using V = typename Vec2<T>::type;
+    V* const psi = (V*)cc.psi;
+    V* const lam = (V*)cc.lam;
+    const int tq = cc.tq;
+    const uint32_t na = 1u << tq;
+    const uint64_t base = (uint64_t)tile << tq;
+    const uint64_t zzmask = cc.n > 1 ? ((1ull << (cc.n - 1)) - 1ull) : 0ull;
+    double acc = 0.0;
+    for (uint32_t l = threadIdx.x; l < na; l += blockDim.x) {
+        const uint64_t x = base + l;
+        const V a = ldg<true>(psi + x);
+        const double o = cc.obs_kind == 1 ? (double)(cc.n - 2 * (int)__popcll(x))
+                                          : (double)((cc.n - 1) - 2 * (int)__popcll((x ^ (x >> 1)) & zzmask));
+        acc += o * ((double)a.x * (double)a.x + (double)a.y * (double)a.y);
+        if (tb.with_grad) {
+            V r;
+            r.x = (T)(o * (double)a.x);
+            r.y = (T)(o * (double)a.y);
+            stg<true>(lam + x, r);
+        }
+    }
+    const double s = block_sum_fixed(acc, red);
+    if (threadIdx.x == 0) tb.e_part[cc.e_part_begin + tile] = s;
+}
+
+// A pass of a circuit whose tile is smaller than a workgroup's register tile:
+// the tile stays in LDS and every op sweeps it.
+template <typename T>
+__device__ __forceinline__ void item_lds(const PassTables& tb, const FCirc& cc, bool fwd, int pidx, int tile,
+                                         typename Vec2<T>::type* tileA, typename Vec2<T>::type* tileB,
+                                         uint64_t* hi_map, double* wpart)
+{
+    using V = typename Vec2<T>::type;
+    V* const psi = (V*)cc.psi;
+    V* const lam = (V*)cc.lam;
+    const int tq = cc.tq;
+    const uint32_t na = 1u << tq;
+    const FPass& ps = tb.passes[cc.pass_begin + pidx];
+    // tile base: insert zeros at Q into the tile index; hi_map deposits local bits >= cb
+    uint64_t base = (uint64_t)tile;
+    for (int k = 0; k < tq; ++k) {
+        const int p = ps.q[k];
+        const uint64_t lo = base & ((1ull << p) - 1ull);
+        base = ((base >> p) << (p + 1)) | lo;
+    }
+    const int cb = cc.cb;  // <= tq; 2^(tq - cb) <= hi_entries
+    for (uint32_t h = threadIdx.x; h < (na >> cb); h += blockDim.x) {
+        uint64_t g = 0;
+        for (int k = cb; k < tq; ++k)
+            if ((h >> (k - cb)) & 1u) g |= 1ull << ps.q[k];
+        hi_map[h] = g | base;
+    }
+    __syncthreads();
+    const uint32_t lomask = (1u << cb) - 1u;
+    if (fwd) {
+        if (pidx == 0) {
+            for (uint32_t l = threadIdx.x; l < na; l += blockDim.x) {
+                const uint64_t g = hi_map[l >> cb] | (l & lomask);
+                V v;
+                v.x = g == 0 ? T(1) : T(0);
+                v.y = T(0);
+                tileA[l] = v;
+            }
+        } else {
+            for (uint32_t l = threadIdx.x; l < na; l += blockDim.x)
+                tileA[l] = ldg<true>(psi + (hi_map[l >> cb] | (l & lomask)));
+        }
+        __syncthreads();
+        for (int o = ps.op_begin; o < ps.op_end; ++o) {
+            lds_apply<T>(tileA, tb.ops[o], tb.coef, false, tq);
+            __syncthreads();
+        }
+        for (uint32_t l = threadIdx.x; l < na; l += blockDim.x)
+            stg<true>(psi + (hi_map[l >> cb] | (l & lomask)), tileA[l]);
+        return;
+    }
+    for (uint32_t l = threadIdx.x; l < na; l += blockDim.x) {
+        const uint64_t g = hi_map[l >> cb] | (l & lomask);
+        tileA[l] = ldg<true>(psi + g);
+        tileB[l] = ldg<true>(lam + g);
+    }
+    __syncthreads();
+    int nslot = 0;
+    for (int o = ps.rop_end - 1; o >= ps.rop_begin; --o) {
+        const FOp op = tb.ops[o];
+        if (op.slot >= 0) {
+            const double c = wave_sum(lds_gen_inner<T>(tileA, tileB, op, tq));
+            if ((threadIdx.x & 63) == 0) wpart[nslot * 16 + (threadIdx.x >> 6)] = c;
+            ++nslot;
+            __syncthreads();  // every read of the tiles precedes the un-apply below
+        }
+        lds_apply<T>(tileA, op, tb.coef, true, tq);
+        lds_apply<T>(tileB, op, tb.coef, true, tq);
+        __syncthreads();
+    }
+    flush_slots(tb, cc, ps.rop_begin, ps.rop_end, tile, wpart);
+    for (uint32_t l = threadIdx.x; l < na; l += blockDim.x) {
+        const uint64_t g = hi_map[l >> cb] | (l & lomask);
+        stg<true>(psi + g, tileA[l]);
+        stg<true>(lam + g, tileB[l]);
+    }
+}
+
+// LDS of a run: [tiles][address map][per-slot wave partials][block sum scratch]
+struct EngineLds {
+    void* tileA;
+    void* tileB;
+    uint64_t* hi_map;
+    double* wpart;  // [kMaxPassSlots][16 waves]
+    double* red;
+};
+
+template <typename T>
+__device__ __forceinline__ EngineLds engine_lds(const PassTables& tb, double* smem)
+{
+    using V = typename Vec2<T>::type;
+    EngineLds e;
+    const size_t tile_elems = (size_t)1 << tb.tq_max;
+    V* const a = (V*)smem;
+    e.tileA = a;
+    e.tileB = a + tile_elems;
+    e.hi_map = (uint64_t*)(a + (tb.lds_small && tb.with_grad ? 2 * tile_elems : tile_elems));
+    e.wpart = (double*)(e.hi_map + (tb.lds_small ? tb.hi_entries : 0));
+    e.red = e.wpart + kMaxPassSlots * 16;
+    return e;
+}
+
+// Segment of a work item: the last segment whose first item is <= item.
+__device__ __forceinline__ const FSeg& seg_of(const PassTables& tb, int64_t item)
+{
+    int lo = 0, hi = tb.n_segs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tb.segs[mid].first <= item) lo = mid;
+        else hi = mid - 1;
+    }
+    return tb.segs[lo];
+}
+
+// Target waves per SIMD (which sets the VGPR budget: 512 / waves).  Forward
+// complex64 passes fit 128 VGPRs, so two 512-thread workgroups share a CU;
+// the others need more registers than that without spilling.
+template <typename T, bool REV>
+constexpr int pass_waves_per_eu()
+{
+    return (!REV && sizeof(T) == 4) ? 4 : 2;
+}
+
+template <typename T, int RB>
+__global__ void __launch_bounds__(kMaxPassThreads, (pass_waves_per_eu<T, false>()))
+k_pass_fwd(PassTables tb, int64_t item_begin, int64_t item_end)
 {
     using V = typename Vec2<T>::type;
     extern __shared__ double smem_d[];
-    V* const tileA = (V*)smem_d;
-    V* const tileB = tileA + (1 << tb.tq_max);
-    uint64_t* const hi_map = (uint64_t*)(tileB + (tb.with_grad ? (1 << tb.tq_max) : 0));
-    double* const wpart = (double*)(hi_map + tb.hi_entries);  // [kMaxPassSlots][16 waves]
-    double* const red = wpart + kMaxPassSlots * 16;
-    const int nwaves = blockDim.x >> 6;
-
+    const EngineLds L = engine_lds<T>(tb, smem_d);
     for (int64_t item = item_begin + blockIdx.x; item < item_end; item += gridDim.x) {
-        // decode: last segment whose first item is <= item
-        int lo = 0, hi = tb.n_segs - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (tb.segs[mid].first <= item) lo = mid;
-            else hi = mid - 1;
-        }
-        const FSeg sg = tb.segs[lo];
-        struct {
-            int circ, stage, tile;
-        } it = {sg.circ, sg.stage, (int)(item - sg.first)};
-        const FCirc cc = tb.circs[it.circ];
-        V* const psi = (V*)cc.psi;
-        V* const lam = (V*)cc.lam;
-        const int tq = cc.tq;
-        const uint32_t na = 1u << tq;
-        const int nfwd = cc.n_pass;
-        if (it.stage == nfwd) {
-            // observable stage: contiguous chunk it.tile
-            const uint64_t base = (uint64_t)it.tile << tq;
-            const uint64_t zzmask = cc.n > 1 ? ((1ull << (cc.n - 1)) - 1ull) : 0ull;
-            double acc = 0.0;
-            for (uint32_t l = threadIdx.x; l < na; l += blockDim.x) {
-                const uint64_t x = base + l;
-                const V a = ldg<true>(psi + x);
-                const double o = cc.obs_kind == 1 ? (double)(cc.n - 2 * (int)__popcll(x))
-                                                  : (double)((cc.n - 1) - 2 * (int)__popcll((x ^ (x >> 1)) & zzmask));
-                acc += o * ((double)a.x * (double)a.x + (double)a.y * (double)a.y);
-                if (tb.with_grad) {
-                    V r;
-                    r.x = (T)(o * (double)a.x);
-                    r.y = (T)(o * (double)a.y);
-                    stg<true>(lam + x, r);
-                }
-            }
-            const double s = block_sum_fixed(acc, red);
-            if (threadIdx.x == 0) tb.e_part[cc.e_part_begin + it.tile] = s;
-        } else {
-            const bool fwd = it.stage < nfwd;
-            const int pidx = fwd ? it.stage : (2 * nfwd - it.stage);  // reverse stage nfwd+1+r -> pass nfwd-1-r
-            const FPass ps = tb.passes[cc.pass_begin + pidx];
-            // tile base: insert zeros at Q into the tile index; hi_map deposits local bits >= c_bits
-            uint64_t base = (uint64_t)it.tile;
-            for (int k = 0; k < tq; ++k) {
-                const int p = ps.q[k];
-                const uint64_t lo = base & ((1ull << p) - 1ull);
-                base = ((base >> p) << (p + 1)) | lo;
-            }
-            const int cb = cc.cb;  // <= tq; 2^(tq - cb) <= hi_entries
-            for (uint32_t h = threadIdx.x; h < (na >> cb); h += blockDim.x) {
-                uint64_t g = 0;
-                for (int k = cb; k < tq; ++k)
-                    if ((h >> (k - cb)) & 1u) g |= 1ull << ps.q[k];
-                hi_map[h] = g | base;
-            }
-            __syncthreads();
-            const uint32_t lomask = (1u << cb) - 1u;
-            if (fwd) {
-                if (pidx == 0) {
-                    for (uint32_t l = threadIdx.x; l < na; l += blockDim.x) {
-                        const uint64_t g = hi_map[l >> cb] | (l & lomask);
-                        V v;
-                        v.x = g == 0 ? T(1) : T(0);
-                        v.y = T(0);
-                        tileA[l] = v;
-                    }
-                } else {
-                    for (uint32_t l = threadIdx.x; l < na; l += blockDim.x)
-                        tileA[l] = ldg<true>(psi + (hi_map[l >> cb] | (l & lomask)));
-                }
-                __syncthreads();
-                for (int o = ps.op_begin; o < ps.op_end; ++o) {
-                    lds_apply<T>(tileA, tb.ops[o], tb.coef, false, tq);
-                    __syncthreads();
-                }
-                for (uint32_t l = threadIdx.x; l < na; l += blockDim.x)
-                    stg<true>(psi + (hi_map[l >> cb] | (l & lomask)), tileA[l]);
-            } else {
-                for (uint32_t l = threadIdx.x; l < na; l += blockDim.x) {
-                    const uint64_t g = hi_map[l >> cb] | (l & lomask);
-                    tileA[l] = ldg<true>(psi + g);
-                    tileB[l] = ldg<true>(lam + g);
-                }
-                __syncthreads();
-                int nslot = 0;
-                for (int o = ps.op_end - 1; o >= ps.op_begin; --o) {
-                    const FOp op = tb.ops[o];
-                    if (op.slot >= 0) {
-                        const double c = wave_sum(lds_gen_inner<T>(tileA, tileB, op, tq));
-                        if ((threadIdx.x & 63) == 0) wpart[nslot * 16 + (threadIdx.x >> 6)] = c;
-                        ++nslot;
-                        __syncthreads();  // every read of the tiles precedes the un-apply below
-                    }
-                    lds_apply<T>(tileA, op, tb.coef, true, tq);
-                    lds_apply<T>(tileB, op, tb.coef, true, tq);
-                    __syncthreads();
-                }
-                // per-op partials of this tile, in fixed wave order
-                {
-                    int k = 0;
-                    for (int o = ps.op_end - 1; o >= ps.op_begin; --o) {
-                        const FOp& op = tb.ops[o];
-                        if (op.slot < 0) continue;
-                        if (threadIdx.x == 0) {
-                            double s = 0.0;
-                            for (int w = 0; w < nwaves; ++w) s += wpart[k * 16 + w];
-                            tb.g_part[cc.g_part_begin + (int64_t)op.slot * cc.n_tiles + it.tile] = s;
-                        }
-                        ++k;
-                    }
-                }
-                for (uint32_t l = threadIdx.x; l < na; l += blockDim.x) {
-                    const uint64_t g = hi_map[l >> cb] | (l & lomask);
-                    stg<true>(psi + g, tileA[l]);
-                    stg<true>(lam + g, tileB[l]);
-                }
-            }
-        }
-        __syncthreads();  // the LDS tiles are reused by the next item of this workgroup
+        const FSeg& sg = seg_of(tb, item);
+        const int tile = (int)(item - sg.first);
+        const FCirc& cc = tb.circs[sg.circ];
+        if (cc.reg) item_reg_fwd<T, RB>(tb, cc, sg.stage, tile, (V*)L.tileA);
+        else item_lds<T>(tb, cc, true, sg.stage, tile, (V*)L.tileA, (V*)L.tileB, L.hi_map, L.wpart);
+        __syncthreads();  // LDS is reused by the next item of this workgroup
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kMaxPassThreads)
+k_pass_obs(PassTables tb, int64_t item_begin, int64_t item_end)
+{
+    extern __shared__ double smem_d[];
+    const EngineLds L = engine_lds<T>(tb, smem_d);
+    for (int64_t item = item_begin + blockIdx.x; item < item_end; item += gridDim.x) {
+        const FSeg& sg = seg_of(tb, item);
+        item_observable<T>(tb, tb.circs[sg.circ], (int)(item - sg.first), L.red);
+        __syncthreads();
+    }
+}
+
+template <typename T, int RB>
+__global__ void __launch_bounds__(kMaxPassThreads, (pass_waves_per_eu<T, true>()))
+k_pass_rev(PassTables tb, int64_t item_begin, int64_t item_end)
+{
+    using V = typename Vec2<T>::type;
+    extern __shared__ double smem_d[];
+    const EngineLds L = engine_lds<T>(tb, smem_d);
+    for (int64_t item = item_begin + blockIdx.x; item < item_end; item += gridDim.x) {
+        const FSeg& sg = seg_of(tb, item);
+        const int tile = (int)(item - sg.first);
+        const FCirc& cc = tb.circs[sg.circ];
+        const int pidx = 2 * cc.n_pass - sg.stage;  // reverse stage n_pass+1+r -> pass n_pass-1-r
+        if (cc.rreg) item_reg_rev<T, RB>(tb, cc, pidx, tile, (V*)L.tileA, L.wpart);
+        else item_lds<T>(tb, cc, false, pidx, tile, (V*)L.tileA, (V*)L.tileB, L.hi_map, L.wpart);
+        __syncthreads();
     }
 }
 
@@ -392,32 +899,79 @@ __global__ void k_pass_grad_csr(const double* __restrict__ slot_val, const int* 
     grad[j] = g;
 }
 
-size_t pass_engine_lds_bytes(int tq_max, int hi_entries, int with_grad, int dtype)
+int pass_engine_threads(int tq_max, int reg_bits)
+{
+    const int t = tq_max > reg_bits ? 1 << (tq_max - reg_bits) : 1;
+    return t < 64 ? 64 : t;
+}
+
+size_t pass_engine_lds_bytes(int tq_max, int hi_entries, int with_grad, int dtype, int lds_small)
 {
     const size_t eb = dtype == SV_C128 ? 16 : 8;
-    return eb * ((size_t)1 << tq_max) * (with_grad ? 2 : 1) + 8 * (size_t)hi_entries +
+    const size_t tiles = (size_t)1 << tq_max;
+    return eb * tiles * (lds_small && with_grad ? 2 : 1) + (lds_small ? 8 * (size_t)hi_entries : 0) +
            8 * (size_t)kMaxPassSlots * 16 + 8 * 16;
 }
 
-hipError_t pass_engine_prepare(int dtype, size_t lds_bytes)
+template <typename T>
+static const void* fwd_fn(int rb)
 {
-    if (dtype == SV_C128)
-        return hipFuncSetAttribute((const void*)k_pass_engine<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   (int)lds_bytes);
-    return hipFuncSetAttribute((const void*)k_pass_engine<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)lds_bytes);
+    return rb == 3 ? (const void*)k_pass_fwd<T, 3> : (const void*)k_pass_fwd<T, 4>;
 }
 
-hipError_t launch_pass_level(const PassTables& tb, int dtype, int64_t item_begin, int64_t item_end, int threads,
-                             size_t lds_bytes, hipStream_t s)
+// complex128 reverse passes always hold 8 amplitudes of phi and of lambda per thread
+template <typename T>
+static const void* rev_fn(int rb)
+{
+    if constexpr (sizeof(T) == 8) return (void)rb, (const void*)k_pass_rev<T, 3>;
+    else return rb == 3 ? (const void*)k_pass_rev<T, 3> : (const void*)k_pass_rev<T, 4>;
+}
+
+hipError_t pass_engine_prepare(int dtype, int reg_bits, int rreg_bits, size_t lds_bytes)
+{
+    const void* f[3];
+    if (dtype == SV_C128) {
+        f[0] = fwd_fn<double>(reg_bits);
+        f[1] = (const void*)k_pass_obs<double>;
+        f[2] = rev_fn<double>(rreg_bits);
+    } else {
+        f[0] = fwd_fn<float>(reg_bits);
+        f[1] = (const void*)k_pass_obs<float>;
+        f[2] = rev_fn<float>(rreg_bits);
+    }
+    for (const void* k : f) {
+        const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+template <typename T>
+static void launch_items_t(const PassTables& tb, int mode, unsigned grid, int threads, size_t lds, hipStream_t s,
+                           int64_t b, int64_t e)
+{
+    if (mode == PM_OBS) {
+        hipLaunchKernelGGL((k_pass_obs<T>), dim3(grid), dim3(threads), lds, s, tb, b, e);
+    } else if (mode == PM_FWD) {
+        if (tb.reg_bits == 3) hipLaunchKernelGGL((k_pass_fwd<T, 3>), dim3(grid), dim3(threads), lds, s, tb, b, e);
+        else hipLaunchKernelGGL((k_pass_fwd<T, 4>), dim3(grid), dim3(threads), lds, s, tb, b, e);
+    } else if constexpr (sizeof(T) == 8) {
+        hipLaunchKernelGGL((k_pass_rev<T, 3>), dim3(grid), dim3(threads), lds, s, tb, b, e);
+    } else {
+        if (tb.rreg_bits == 3) hipLaunchKernelGGL((k_pass_rev<T, 3>), dim3(grid), dim3(threads), lds, s, tb, b, e);
+        else hipLaunchKernelGGL((k_pass_rev<T, 4>), dim3(grid), dim3(threads), lds, s, tb, b, e);
+    }
+}
+
+hipError_t launch_pass_items(const PassTables& tb, int dtype, int mode, int64_t item_begin, int64_t item_end,
+                             int threads, size_t lds_bytes, hipStream_t s)
 {
     const int64_t n = item_end - item_begin;
     if (n <= 0) return hipSuccess;
+    if (threads < 64 || threads > kMaxPassThreads) return hipErrorInvalidValue;
     const unsigned grid = (unsigned)(n < (1 << 30) ? n : (1 << 30));
-    if (dtype == SV_C128)
-        hipLaunchKernelGGL(k_pass_engine<double>, dim3(grid), dim3(threads), lds_bytes, s, tb, item_begin, item_end);
-    else
-        hipLaunchKernelGGL(k_pass_engine<float>, dim3(grid), dim3(threads), lds_bytes, s, tb, item_begin, item_end);
+    if (dtype == SV_C128) launch_items_t<double>(tb, mode, grid, threads, lds_bytes, s, item_begin, item_end);
+    else launch_items_t<float>(tb, mode, grid, threads, lds_bytes, s, item_begin, item_end);
     return hipGetLastError();
 }
 

@@ -10,6 +10,13 @@
 // their qubits stays within tq qubits; it is then padded with the lowest
 // unused qubits to exactly tq.  Every op of a pass acts inside one tile, so
 // one HBM round trip of the state serves all of them.
+//
+// Register tiling.  Inside a pass each thread holds 2^rb amplitudes of the
+// tile.  The ops of the pass are grouped again (same commutation rule) into
+// runs whose targets fit in rb register bits; each run gets a layout (which
+// tile bits are register bits, and an order of the lane bits chosen for
+// coalesced loads and conflict-free LDS exchange), and a layout change
+// between runs is the only LDS step.
 #include <math.h>
 #include <string.h>
 
@@ -119,6 +126,140 @@ void schedule(int n, int tq, int cb, const std::vector<BOp>& ops, std::vector<st
     }
 }
 
+// Tile bits an op needs in registers (its targets, except for diagonal and
+// subset-phase ops, which act element-wise in any layout).
+uint32_t op_need(const FOp& f)
+{
+    switch (f.kind) {
+    case FK_PAIR: return 1u << f.a;
+    case FK_SWAP:
+    case FK_QUAD: return (1u << f.a) | (1u << f.b);
+    default: return 0u;
+    }
+}
+
+uint32_t op_touch(const FOp& f)
+{
+    uint32_t m = f.cm | (1u << f.a);
+    if (f.kind == FK_SWAP || f.kind == FK_QUAD) m |= 1u << f.b;
+    return m;
+}
+
+// Fill a register set up to rb bits, highest free bits first, keeping the
+// lowest `keep` bits (the coalescing run) as lane bits where possible.
+uint32_t pad_regs(uint32_t S, int tq, int rb, int keep)
+{
+    for (int p = tq - 1; p >= keep && popc(S) < rb; --p) S |= 1u << p;
+    for (int p = tq - 1; p >= 0 && popc(S) < rb; --p) S |= 1u << p;
+    return S;
+}
+
+// Lane order: first up to kSwzBits lane bits with distinct residues mod
+// kSwzBits, scanning upwards (so a coalescing run 0..cb-1 of lane bits comes
+// first, in order), then the other lane bits ascending; register bits ascending.
+FLayout make_layout(uint32_t S, int tq, int rb)
+{
+    FLayout L;
+    memset(&L, 0, sizeof L);
+    int lanes[16], nl = 0;
+    bool used[16] = {}, res[kSwzBits] = {};
+    for (int p = 0; p < tq && nl < kSwzBits; ++p) {
+        if ((S >> p) & 1u) continue;
+        if (res[p % kSwzBits]) continue;
+        res[p % kSwzBits] = true;
+        used[p] = true;
+        lanes[nl++] = p;
+    }
+    for (int p = 0; p < tq; ++p)
+        if (!((S >> p) & 1u) && !used[p]) lanes[nl++] = p;
+    for (int i = 0; i < nl; ++i) L.pos[i] = (uint8_t)lanes[i];
+    int r = 0;
+    for (int p = 0; p < tq; ++p)
+        if ((S >> p) & 1u) L.pos[(tq - rb) + r++] = (uint8_t)p;
+    return L;
+}
+
+int reg_index(uint32_t S, int p) { return popc(S & ((1u << p) - 1u)); }
+
+// Reorder one pass's ops into register runs and insert the layout changes.
+void plan_layouts(std::vector<FOp>& pass_ops, int tq, int rb, int cb, std::vector<FLayout>& lays, int& lay_begin,
+                  int& lay_end)
+{
+    const int keep = std::max(0, std::min(cb, tq - rb));
+    const uint32_t lowmask = (1u << keep) - 1u;
+    std::vector<std::pair<uint32_t, std::vector<int>>> runs;
+    std::vector<int> remaining(pass_ops.size());
+    for (size_t i = 0; i < pass_ops.size(); ++i) remaining[i] = (int)i;
+    while (!remaining.empty()) {
+        uint32_t S = 0, blocked = 0;
+        std::vector<int> taken, rest;
+        for (int i : remaining) {
+            const FOp& f = pass_ops[i];
+            const uint32_t m = op_touch(f);
+            if (m & blocked) {
+                blocked |= m;
+                rest.push_back(i);
+                continue;
+            }
+            const uint32_t nd = op_need(f);
+            if (popc(S | nd) <= rb) {
+                S |= nd;
+                taken.push_back(i);
+            } else {
+                blocked |= m;
+                rest.push_back(i);
+            }
+        }
+        runs.push_back({pad_regs(S, tq, rb, keep), taken});
+        remaining.swap(rest);
+    }
+    const uint32_t C = pad_regs(0, tq, rb, keep);
+    std::vector<std::pair<uint32_t, int>> seen;  // register set -> layout index (this pass)
+    auto layout_of = [&](uint32_t S) {
+        for (auto& e : seen)
+            if (e.first == S) return e.second;
+        lays.push_back(make_layout(S, tq, rb));
+        seen.push_back({S, (int)lays.size() - 1});
+        return (int)lays.size() - 1;
+    };
+    std::vector<FOp> out;
+    auto marker = [&](int to, int from) {
+        FOp m;
+        memset(&m, 0, sizeof m);
+        m.kind = FK_LAYOUT;
+        m.a = to;
+        m.b = from;
+        m.slot = -1;
+        out.push_back(m);
+    };
+    int cur;
+    if (runs.empty() || (runs[0].first & lowmask)) cur = layout_of(C);
+    else cur = layout_of(runs[0].first);
+    lay_begin = cur;
+    for (auto& r : runs) {
+        const int li = layout_of(r.first);
+        if (li != cur) {
+            marker(li, cur);
+            cur = li;
+        }
+        for (int i : r.second) {
+            FOp f = pass_ops[i];
+            f.ka = (int16_t)((op_need(f) & (1u << f.a)) ? reg_index(r.first, f.a) : 0);
+            f.kb = (int16_t)((f.kind == FK_SWAP || f.kind == FK_QUAD) ? reg_index(r.first, f.b) : 0);
+            out.push_back(f);
+        }
+    }
+    if (!runs.empty() && (runs.back().first & lowmask)) {
+        const int li = layout_of(C);
+        if (li != cur) {
+            marker(li, cur);
+            cur = li;
+        }
+    }
+    lay_end = cur;
+    pass_ops.swap(out);
+}
+
 }  // namespace
 
 struct sv_batch_s {
@@ -127,16 +268,19 @@ struct sv_batch_s {
     int n_circ;
     int with_grad;
     int use_graph;
-    int threads;
+    int threads, rthreads;
+    int reg_bits, rreg_bits;
     size_t lds;
-    std::vector<int64_t> level_first;  // item range of each stage level
+    std::vector<int64_t> level_first;  // per level: forward, observable, reverse item ranges (4 bounds)
     int64_t n_items;
     int n_segs;
     int n_slots;
     int n_params;
     int n_passes;
     int max_passes;
-    int n_fops;
+    int n_fops;  // gate ops scheduled
+    int n_layout_changes;
+    int n_levels;
     size_t state_bytes;
     double pass_bytes;  // HBM bytes of all passes of one run (algorithmic)
     std::vector<size_t> psi_off;
@@ -148,6 +292,7 @@ struct sv_batch_s {
     FCirc* d_circ;
     FPass* d_pass;
     FOp* d_ops;
+    FLayout* d_lays;
     FSeg* d_segs;
     FCoefSpec* d_cspec;
     int n_cspec;
@@ -188,7 +333,7 @@ void batch_release(sv_batch b)
     if (b->stream) (void)hipStreamSynchronize(b->stream);
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
-    void* ptrs[] = {b->d_psi, b->d_lam, b->d_circ, b->d_pass, b->d_ops, b->d_segs, b->d_cspec, b->d_coef, b->d_epart, b->d_gpart, b->d_e_off, b->d_e_cnt, b->d_g_off, b->d_g_cnt,
+    void* ptrs[] = {b->d_psi, b->d_lam, b->d_circ, b->d_pass, b->d_ops, b->d_lays, b->d_segs, b->d_cspec, b->d_coef, b->d_epart, b->d_gpart, b->d_e_off, b->d_e_cnt, b->d_g_off, b->d_g_cnt,
                     b->d_slot_scale, b->d_slot_val, b->d_csr_ptr, b->d_csr_col, b->d_params, b->d_expvals,
                     b->d_grads};
     for (void* p : ptrs)
@@ -201,8 +346,12 @@ hipError_t enqueue_run(sv_batch b)
 {
     hipStream_t s = b->stream;
     hipError_t e = launch_pass_coef(b->d_cspec, b->n_cspec, b->d_params, b->d_coef, s);
-    for (size_t l = 0; l + 1 < b->level_first.size() && e == hipSuccess; ++l)
-        e = launch_pass_level(b->tb, b->dtype, b->level_first[l], b->level_first[l + 1], b->threads, b->lds, s);
+    const std::vector<int64_t>& lf = b->level_first;
+    for (size_t l = 0; l + 3 < lf.size() && e == hipSuccess; l += 3) {
+        e = launch_pass_items(b->tb, b->dtype, PM_FWD, lf[l], lf[l + 1], b->threads, b->lds, s);
+        if (e == hipSuccess) e = launch_pass_items(b->tb, b->dtype, PM_OBS, lf[l + 1], lf[l + 2], b->threads, b->lds, s);
+        if (e == hipSuccess) e = launch_pass_items(b->tb, b->dtype, PM_REV, lf[l + 2], lf[l + 3], b->rthreads, b->lds, s);
+    }
     if (e == hipSuccess) e = launch_pass_segsum(b->d_epart, b->d_e_off, b->d_e_cnt, nullptr, b->d_expvals, b->n_circ, s);
     if (e == hipSuccess && b->with_grad) {
         e = launch_pass_segsum(b->d_gpart, b->d_g_off, b->d_g_cnt, b->d_slot_scale, b->d_slot_val, b->n_slots, s);
@@ -220,13 +369,15 @@ static sv_status hip_fail(hipError_t e, const char* what)
 
 // Everything a batch needs, built on the host (no device work).
 struct HostTables {
-    int tq_max, threads, with_grad, cbits_default, n_params, coef_total, tq_used, hi_entries, e_total;
+    int tq_max, threads, rthreads, reg_bits, rreg_bits, lds_small, with_grad, cbits_default, n_params, coef_total,
+        tq_used, hi_entries, e_total, n_levels, n_gate_ops, n_layout_changes;
     int64_t g_total, n_items;
     size_t state_total;
     double pass_bytes;
     std::vector<FCirc> circs;
     std::vector<FPass> passes;
     std::vector<FOp> fops;
+    std::vector<FLayout> lays;
     std::vector<FCoefSpec> cspec;
     std::vector<double> slot_scale;
     std::vector<int> slot_param;
@@ -241,11 +392,20 @@ static sv_status compile_batch(const sv_batch_circuit* circuits, int n_circuits,
 {
     if (!circuits || n_circuits < 1) return set_error(SV_ERR_ARG, "bad batch arguments");
     if (dtype != SV_C64 && dtype != SV_C128) return set_error(SV_ERR_ARG, "bad dtype");
-    const int tq_default = dtype == SV_C128 ? 12 : 13;
+    const int apt = opts && opts->amps_per_thread > 0 ? opts->amps_per_thread : (1 << kMaxRegBits);
+    int reg_bits = 0;
+    for (int r = kMinRegBits; r <= kMaxRegBits; ++r)
+        if (apt == (1 << r)) reg_bits = r;
+    if (!reg_bits) return set_error(SV_ERR_ARG, "amps_per_thread must be 8 or 16");
+    // reverse passes hold phi and lambda: complex128 keeps 8 amplitudes of each per thread
+    const int rreg_bits = dtype == SV_C128 ? std::min(reg_bits, 3) : reg_bits;
+    // default tile: 64 KiB (2^12 complex128 / 2^13 complex64 amplitudes), within
+    // kMaxPassThreads threads of the narrower register width
+    int lg_threads = 0;
+    while ((2 << lg_threads) <= kMaxPassThreads) ++lg_threads;
+    const int tq_default = std::min(dtype == SV_C128 ? 12 : 13, std::min(reg_bits, rreg_bits) + lg_threads);
     int tq_max = opts && opts->tile_qubits > 0 ? opts->tile_qubits : tq_default;
     if (tq_max < 2 || tq_max > kMaxTileQubits) return set_error(SV_ERR_ARG, "tile_qubits must be in [2, 13]");
-    const int threads = opts && opts->threads > 0 ? opts->threads : 512;
-    if (threads < 64 || threads > 1024 || (threads & 63)) return set_error(SV_ERR_ARG, "threads must be a multiple of 64 in [64, 1024]");
     const int with_grad = opts ? (opts->with_grad != 0) : 1;
     const int cbits_default = dtype == SV_C128 ? 3 : 4;  // 128-byte runs
 
@@ -253,6 +413,7 @@ static sv_status compile_batch(const sv_batch_circuit* circuits, int n_circuits,
     std::vector<FCirc> circs(n_circuits);
     std::vector<FPass> passes;
     std::vector<FOp> fops;
+    std::vector<FLayout> lays;
     std::vector<FCoefSpec> cspec;
     std::vector<double> slot_scale;
     std::vector<int> slot_param;  // global parameter of each global slot
@@ -261,7 +422,7 @@ static sv_status compile_batch(const sv_batch_circuit* circuits, int n_circuits,
     std::vector<int64_t> e_off;
     std::vector<int> e_cnt;
     std::vector<size_t> psi_off(n_circuits);
-    int n_params = 0, coef_total = 0, tq_used = 2, hi_entries = 1;
+    int n_params = 0, coef_total = 0, tq_used = 2, hi_entries = 1, lds_small = 0;
     int64_t g_total = 0;
     int e_total = 0;
     size_t state_total = 0;
@@ -300,7 +461,12 @@ static sv_status compile_batch(const sv_batch_circuit* circuits, int n_circuits,
         fc.n = n;
         fc.tq = tq;
         fc.cb = cb;
-        hi_entries = std::max(hi_entries, 1 << (tq - cb));
+        fc.reg = tq >= reg_bits ? 1 : 0;
+        fc.rreg = tq >= rreg_bits ? 1 : 0;
+        if (!fc.reg || (with_grad && !fc.rreg)) {
+            lds_small = 1;
+            hi_entries = std::max(hi_entries, 1 << (tq - cb));
+        }
         fc.n_tiles = 1 << (n - tq);
         fc.n_pass = (int)pops.size();
         fc.pass_begin = (int)passes.size();
@@ -325,7 +491,7 @@ static sv_status compile_batch(const sv_batch_circuit* circuits, int n_circuits,
                     local[q] = k;
                     fp.q[k++] = q;
                 }
-            fp.op_begin = (int)fops.size();
+            std::vector<FOp> pass_ops;
             for (int i : pops[p]) {
                 const BOp& o = ops[i];
                 FOp f;
@@ -361,9 +527,24 @@ static sv_status compile_batch(const sv_batch_circuit* circuits, int n_circuits,
                 default: { f.kind = FK_QUAD; memcpy(cs.fixed, o.mat.data(), 32 * sizeof(double)); cs.nfixed = 32; coef_total += 32; break; }
                 }
                 if (o.gate != SV_SWAP) cspec.push_back(cs);
-                fops.push_back(f);
+                pass_ops.push_back(f);
             }
+            std::vector<FOp> fwd_ops = pass_ops;
+            if (fc.reg) plan_layouts(fwd_ops, tq, reg_bits, cb, lays, fp.lay_begin, fp.lay_end);
+            fp.op_begin = (int)fops.size();
+            fops.insert(fops.end(), fwd_ops.begin(), fwd_ops.end());
             fp.op_end = (int)fops.size();
+            fp.rop_begin = fp.op_begin;
+            fp.rop_end = fp.op_end;
+            fp.rlay_begin = fp.lay_begin;
+            fp.rlay_end = fp.lay_end;
+            if (with_grad && (fc.reg != fc.rreg || (fc.rreg && rreg_bits != reg_bits))) {
+                std::vector<FOp> rev_ops = pass_ops;
+                if (fc.rreg) plan_layouts(rev_ops, tq, rreg_bits, cb, lays, fp.rlay_begin, fp.rlay_end);
+                fp.rop_begin = (int)fops.size();
+                fops.insert(fops.end(), rev_ops.begin(), rev_ops.end());
+                fp.rop_end = (int)fops.size();
+            }
             passes.push_back(fp);
         }
         for (size_t i = 0; i < ops.size(); ++i)
@@ -381,7 +562,8 @@ static sv_status compile_batch(const sv_batch_circuit* circuits, int n_circuits,
         pass_bytes += 2.0 * (double)sb * (with_grad ? 3.0 * fc.n_pass + 1.0 : fc.n_pass + 0.5);
     }
 
-    // ---- work segments, level-major: stage s of every circuit before stage s+1 ----
+    // ---- work segments, level-major: stage s of every circuit before stage s+1;
+    //      inside a level forward stages, then observable stages, then reverse ----
     std::vector<FSeg> segs;
     int64_t n_items = 0;
     int max_stages = 0;
@@ -392,17 +574,22 @@ static sv_status compile_batch(const sv_batch_circuit* circuits, int n_circuits,
     }
     std::vector<int64_t> level_first;
     for (int s = 0; s < max_stages; ++s) {
-        level_first.push_back(n_items);
-        for (int c = 0; c < n_circuits; ++c) {
-            if (s >= stages[c]) continue;
-            FSeg sg;
-            sg.first = n_items;
-            sg.circ = c;
-            sg.stage = s;
-            sg.n_tiles = circs[c].n_tiles;
-            sg.pad = 0;
-            segs.push_back(sg);
-            n_items += circs[c].n_tiles;
+        for (int kind = PM_FWD; kind <= PM_REV; ++kind) {
+            level_first.push_back(n_items);
+            for (int c = 0; c < n_circuits; ++c) {
+                if (s >= stages[c]) continue;
+                const int np = circs[c].n_pass;
+                const int k = s < np ? PM_FWD : (s == np ? PM_OBS : PM_REV);
+                if (k != kind) continue;
+                FSeg sg;
+                sg.first = n_items;
+                sg.circ = c;
+                sg.stage = s;
+                sg.n_tiles = circs[c].n_tiles;
+                sg.pad = 0;
+                segs.push_back(sg);
+                n_items += circs[c].n_tiles;
+            }
         }
     }
     level_first.push_back(n_items);
@@ -418,7 +605,14 @@ static sv_status compile_batch(const sv_batch_circuit* circuits, int n_circuits,
     }
 
     H.tq_max = tq_max;
-    H.threads = threads;
+    H.threads = pass_engine_threads(tq_used, reg_bits);
+    H.rthreads = pass_engine_threads(tq_used, rreg_bits);
+    if (H.threads > kMaxPassThreads || (with_grad && H.rthreads > kMaxPassThreads))
+        return set_error(SV_ERR_ARG, "tile_qubits too large for amps_per_thread (at most 512 threads per tile)");
+    H.reg_bits = reg_bits;
+    H.rreg_bits = rreg_bits;
+    H.n_levels = max_stages;
+    H.lds_small = lds_small;
     H.with_grad = with_grad;
     H.cbits_default = cbits_default;
     H.n_params = n_params;
@@ -433,6 +627,7 @@ static sv_status compile_batch(const sv_batch_circuit* circuits, int n_circuits,
     H.circs = std::move(circs);
     H.passes = std::move(passes);
     H.fops = std::move(fops);
+    H.lays = std::move(lays);
     H.cspec = std::move(cspec);
     H.slot_scale = std::move(slot_scale);
     H.slot_param = std::move(slot_param);
@@ -445,6 +640,13 @@ static sv_status compile_batch(const sv_batch_circuit* circuits, int n_circuits,
     H.csr_col = std::move(csr_col);
     H.segs = std::move(segs);
     H.psi_off = std::move(psi_off);
+    H.n_gate_ops = 0;
+    H.n_layout_changes = 0;
+    for (const FPass& fp : H.passes)
+        for (int o = fp.op_begin; o < fp.op_end; ++o) {
+            if (H.fops[o].kind == FK_LAYOUT) ++H.n_layout_changes;
+            else ++H.n_gate_ops;
+        }
     return SV_OK;
 }
 
@@ -462,12 +664,14 @@ sv_status sv_batch_plan(const sv_batch_circuit* circuits, int n_circuits, sv_dty
     info[1] = H.n_items;
     info[2] = (int64_t)H.passes.size();
     info[3] = maxp;
-    info[4] = (int64_t)H.fops.size();
+    info[4] = H.n_gate_ops;
     info[5] = H.n_params;
     info[6] = (int64_t)H.state_total;
     info[7] = (int64_t)H.pass_bytes;
-    info[8] = (int64_t)H.level_first.size() - 1;
-    info[9] = (int64_t)pass_engine_lds_bytes(H.tq_used, H.hi_entries, H.with_grad, dtype);
+    info[8] = H.n_levels;
+    info[9] = (int64_t)pass_engine_lds_bytes(H.tq_used, H.hi_entries, H.with_grad, dtype, H.lds_small);
+    info[10] = H.n_layout_changes;
+    info[11] = H.threads;
     return SV_OK;
 }
 
@@ -508,12 +712,17 @@ sv_status sv_batch_create(const sv_batch_circuit* circuits, int n_circuits, sv_d
     b->with_grad = with_grad;
     b->use_graph = opts ? (opts->use_graph != 0) : 1;
     b->threads = threads;
+    b->rthreads = H.rthreads;
+    b->reg_bits = H.reg_bits;
+    b->rreg_bits = H.rreg_bits;
+    b->n_levels = H.n_levels;
     b->n_items = n_items;
     b->n_segs = (int)segs.size();
     b->n_slots = (int)slot_param.size();
     b->n_params = n_params;
     b->n_passes = (int)passes.size();
-    b->n_fops = (int)fops.size();
+    b->n_fops = H.n_gate_ops;
+    b->n_layout_changes = H.n_layout_changes;
     b->state_bytes = state_total;
     b->pass_bytes = pass_bytes;
     b->psi_off = psi_off;
@@ -542,6 +751,7 @@ sv_status sv_batch_create(const sv_batch_circuit* circuits, int n_circuits, sv_d
     e = dev_upload(&b->d_circ, circs);
     if (e == hipSuccess) e = dev_upload(&b->d_pass, passes);
     if (e == hipSuccess) e = dev_upload(&b->d_ops, fops);
+    if (e == hipSuccess) e = dev_upload(&b->d_lays, H.lays);
     if (e == hipSuccess) e = dev_upload(&b->d_segs, segs);
     if (e == hipSuccess) e = dev_upload(&b->d_cspec, cspec);
     if (e == hipSuccess) e = dev_upload(&b->d_e_off, e_off);
@@ -567,6 +777,7 @@ sv_status sv_batch_create(const sv_batch_circuit* circuits, int n_circuits, sv_d
     tb.circs = b->d_circ;
     tb.passes = b->d_pass;
     tb.ops = b->d_ops;
+    tb.lays = b->d_lays;
     tb.segs = b->d_segs;
     tb.coef = b->d_coef;
     tb.e_part = b->d_epart;
@@ -576,8 +787,11 @@ sv_status sv_batch_create(const sv_batch_circuit* circuits, int n_circuits, sv_d
     tb.tq_max = tq_used;
     tb.hi_entries = hi_entries;
     tb.with_grad = with_grad;
-    b->lds = pass_engine_lds_bytes(tq_used, hi_entries, with_grad, dtype);
-    e = pass_engine_prepare(dtype, b->lds);
+    tb.reg_bits = H.reg_bits;
+    tb.rreg_bits = H.rreg_bits;
+    tb.lds_small = H.lds_small;
+    b->lds = pass_engine_lds_bytes(tq_used, hi_entries, with_grad, dtype, H.lds_small);
+    e = pass_engine_prepare(dtype, H.reg_bits, H.rreg_bits, b->lds);
     if (e != hipSuccess) {
         batch_release(b);
         return hip_fail(e, "pass engine LDS limit");
@@ -638,8 +852,10 @@ sv_status sv_batch_info(sv_batch b, int64_t* info)
     info[5] = b->n_params;
     info[6] = (int64_t)b->state_bytes;
     info[7] = (int64_t)b->pass_bytes;
-    info[8] = (int64_t)b->level_first.size() - 1;
+    info[8] = b->n_levels;
     info[9] = (int64_t)b->lds;
+    info[10] = b->n_layout_changes;
+    info[11] = b->threads;
     return SV_OK;
 }
 

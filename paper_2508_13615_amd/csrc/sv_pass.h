@@ -8,10 +8,21 @@ namespace svk {
 
 constexpr int kMaxPassSlots = 64;  // parameterised ops per pass (LDS partial slots)
 constexpr int kMaxTileQubits = 13;
+// Register-tiled passes: each thread holds 2^rb amplitudes of the tile;
+// a workgroup has at most kMaxPassThreads threads (2^(tq - rb)).
+constexpr int kMinRegBits = 3, kMaxRegBits = 4;
+constexpr int kMaxPassThreads = 512;
+// LDS swizzle group: a tile-local index l is stored at l ^ fold(l), where
+// fold XORs every higher group of kSwzBits bits into the lowest group, so
+// lanes whose lowest kSwzBits lane bits sit at positions of distinct
+// residues mod kSwzBits hit distinct banks.
+constexpr int kSwzBits = 4;
 
-enum FusedKind : int32_t { FK_PAIR = 0, FK_DIAG = 1, FK_PHASE = 2, FK_SWAP = 3, FK_QUAD = 4 };
+enum FusedKind : int32_t { FK_PAIR = 0, FK_DIAG = 1, FK_PHASE = 2, FK_SWAP = 3, FK_QUAD = 4, FK_LAYOUT = 5 };
 
-// One op of a pass, in tile-local bit positions.
+// One op of a pass, in tile-local bit positions.  FK_LAYOUT (register-tiled
+// passes only) re-distributes the tile: a = index of the layout that holds
+// from here on, b = the layout that held before.
 struct FOp {
     int32_t kind;
     int32_t a, b;   // local target bits (b: second target of SWAP / QUAD)
@@ -19,12 +30,25 @@ struct FOp {
     int32_t coef;   // offset of the op's coefficients in the coefficient table (doubles)
     int32_t slot;   // gradient slot within the circuit, -1 if not parameterised
     int32_t gen;    // generator (GenKind) of a parameterised op
-    int32_t pad;
+    int16_t ka, kb; // register bits holding a and b in the current layout (register-tiled passes)
 };
 
+// A distribution of a tile over the threads of a workgroup: lane bit i of
+// the thread index is tile-local bit pos[i] (i < tq - rb), register bit r is
+// tile-local bit pos[tq - rb + r].
+struct FLayout {
+    uint8_t pos[16];
+};
+
+// A pass has two op lists over the same ops: the forward list (planned for
+// the forward register width) and the list the reverse sweep walks backwards
+// (planned for the reverse width; the same range when the widths agree).
 struct FPass {
     int32_t q[16];  // tile qubits, ascending; local bit k <-> global qubit q[k]
     int32_t op_begin, op_end;
+    int32_t lay_begin, lay_end;  // layouts a register-tiled forward pass loads in and ends in
+    int32_t rop_begin, rop_end;
+    int32_t rlay_begin, rlay_end;
 };
 
 struct FCirc {
@@ -38,6 +62,9 @@ struct FCirc {
     int32_t obs_kind;      // 1 = sum_i Z_i, 2 = sum_i Z_i Z_{i+1}
     int32_t e_part_begin;
     int32_t cb;            // coalescing bits: every pass's tile holds global bits 0..cb-1 as local bits 0..cb-1
+    int32_t reg;           // 1: forward passes are register-tiled (tq >= rb); 0: every op sweeps an LDS tile
+    int32_t rreg;          // the same for reverse passes (tq >= reverse rb)
+    int32_t pad_;
 };
 
 // Items [first, first + n_tiles) are the tiles of stage `stage` of `circ`;
@@ -64,6 +91,7 @@ struct PassTables {
     const FCirc* circs;
     const FPass* passes;
     const FOp* ops;
+    const FLayout* lays;
     const FSeg* segs;
     const double* coef;
     double* e_part;
@@ -73,18 +101,24 @@ struct PassTables {
     int32_t tq_max;
     int32_t with_grad;
     int32_t hi_entries;  // LDS address-map entries: max over circuits of 2^(tq - cb)
+    int32_t reg_bits;    // rb of register-tiled forward passes
+    int32_t rreg_bits;   // rb of register-tiled reverse passes
+    int32_t lds_small;   // 1 if some circuit takes the LDS-sweep form (tq < rb)
 };
 
-// Set the engine's dynamic LDS limit (once, outside any graph capture).
-hipError_t pass_engine_prepare(int dtype, size_t lds_bytes);
-// Items [item_begin, item_end) of one stage level, one workgroup per tile.
-hipError_t launch_pass_level(const PassTables& tb, int dtype, int64_t item_begin, int64_t item_end, int threads,
-                             size_t lds_bytes, hipStream_t s);
+enum PassMode : int { PM_FWD = 0, PM_OBS = 1, PM_REV = 2 };
+// Set the engine kernels' dynamic LDS limit (once, outside any graph capture).
+hipError_t pass_engine_prepare(int dtype, int reg_bits, int rreg_bits, size_t lds_bytes);
+// Items [item_begin, item_end), all of stage kind `mode`, one workgroup per tile.
+hipError_t launch_pass_items(const PassTables& tb, int dtype, int mode, int64_t item_begin, int64_t item_end,
+                             int threads, size_t lds_bytes, hipStream_t s);
 hipError_t launch_pass_coef(const FCoefSpec* spec, int n, const double* params, double* coef, hipStream_t s);
 hipError_t launch_pass_segsum(const double* part, const int64_t* off, const int* cnt, const double* scale, double* out,
                               int n_seg, hipStream_t s);
 hipError_t launch_pass_grad_csr(const double* slot_val, const int* rowptr, const int* cols, int n_params, double* grad,
                                 hipStream_t s);
-size_t pass_engine_lds_bytes(int tq_max, int hi_entries, int with_grad, int dtype);
+size_t pass_engine_lds_bytes(int tq_max, int hi_entries, int with_grad, int dtype, int lds_small);
+// Workgroup size for register width rb: 2^(tq_max - rb), at least one wavefront.
+int pass_engine_threads(int tq_max, int reg_bits);
 
 }  // namespace svk

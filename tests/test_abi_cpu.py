@@ -179,7 +179,7 @@ def test_batch_create_validation_is_host_side():
     circ[0] = _lib.SvBatchCircuit(4, 1, ops, 1, 1)
     bad = _lib.SvBatchOpts(14, 0, 1, 1)  # tile too large
     assert lib.sv_batch_create(circ, 1, 2, ctypes.byref(bad), ctypes.byref(h)) == ARG
-    bad = _lib.SvBatchOpts(0, 100, 1, 1)  # threads not a multiple of 64
+    bad = _lib.SvBatchOpts(0, 100, 1, 1)  # amplitudes per thread neither 8 nor 16
     assert lib.sv_batch_create(circ, 1, 2, ctypes.byref(bad), ctypes.byref(h)) == ARG
     assert lib.sv_batch_run(ctypes.c_void_p(0x1234), None, 0, None, None, 0) == HANDLE
 
@@ -194,6 +194,9 @@ def test_batch_plan_fuses_gates_host_only():
     adj = sv.batch_plan([(32, ops, W.hea_n_params(32, 10), "sum_z")], "c128", with_grad=True)
     assert fwd["fused_ops"] == len(ops)
     assert fwd["passes"] <= len(ops) // 20
+    # register tiling: LDS exchanges of the tile are rare next to gates
+    assert fwd["layout_changes"] <= len(ops) // 5
+    assert fwd["threads"] == 2 ** 12 // 16
     assert fwd["items"] == (fwd["passes"] + 1) * 2 ** 20
     assert adj["levels"] == 2 * adj["passes"] + 1
     assert fwd["lds_bytes"] <= 160 * 1024 and adj["lds_bytes"] <= 160 * 1024

@@ -40,9 +40,11 @@ def obs_terms(kind, n):
     return W.sum_z(n) if kind == "sum_z" else W.sum_zz(n)
 
 
+@pytest.mark.parametrize("apt", [16, 8])
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 @pytest.mark.parametrize("tile", [4, 5, 0])
-def test_batch_forward_states_and_energies(dtype, tile):
+def test_batch_forward_states_and_energies(dtype, tile, apt):
+    # 3 qubits is below a register tile (LDS-sweep form); the others are register-tiled
     rng = np.random.default_rng(5000 + tile)
     circs, params = [], []
     for n in (3, 5, 8, 10):
@@ -51,7 +53,7 @@ def test_batch_forward_states_and_energies(dtype, tile):
         th = rng.uniform(0, 2 * math.pi, size=npar)
         circs.append((n, ops, npar, "sum_z" if n % 2 else "sum_zz"))
         params.append(th)
-    b = sv.Batch(circs, dtype, tile_qubits=tile, with_grad=False)
+    b = sv.Batch(circs, dtype, tile_qubits=tile, amps_per_thread=apt, with_grad=False)
     e, g = b.run(np.concatenate(params))
     assert g is None
     info = b.info()
@@ -65,8 +67,9 @@ def test_batch_forward_states_and_energies(dtype, tile):
         assert abs(e[i] - e_ref) <= 4 * TOL[dtype] * n, (i, e[i], e_ref)
 
 
+@pytest.mark.parametrize("apt", [16, 8])
 @pytest.mark.parametrize("dtype,tol", [("c128", 1e-10), ("c64", 1e-4)])
-def test_batch_gradients_vs_oracle(dtype, tol):
+def test_batch_gradients_vs_oracle(dtype, tol, apt):
     rng = np.random.default_rng(5101)
     circs, params, refs = [], [], []
     for n, L in ((4, 2), (6, 2), (9, 1)):
@@ -89,7 +92,7 @@ def test_batch_gradients_vs_oracle(dtype, tol):
     params.append(th)
     refs.append((oracle.energy(n, ops, th, W.sum_zz(n)), oracle.fd_grad(n, ops, th, W.sum_zz(n))))
     for tile in (4, 0):
-        b = sv.Batch(circs, dtype, tile_qubits=tile, with_grad=True)
+        b = sv.Batch(circs, dtype, tile_qubits=tile, amps_per_thread=apt, with_grad=True)
         e, g = b.run(np.concatenate(params))
         off = 0
         for i, (n, ops, npar, obs) in enumerate(circs):
