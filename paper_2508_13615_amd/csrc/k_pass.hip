@@ -29,6 +29,35 @@
 
 namespace svk {
 
+// The run's tables (segments, circuits, passes, layouts, ops, coefficients)
+// are not written while a pass launch runs.  Reading them through the
+// constant address space lets the compiler use scalar loads; through a
+// generic pointer it must assume the state stores may alias them and
+// fetch every uniform value with per-lane vector loads.
+template <typename X>
+using cptr = const __attribute__((address_space(4))) X*;
+
+template <typename X>
+__device__ __forceinline__ cptr<X> as_const(const X* p)
+{
+    return (cptr<X>)p;
+}
+
+// Copy of a table entry read through the constant address space.
+template <typename X>
+__device__ __forceinline__ X ld_const(cptr<X> p)
+{
+    static_assert(sizeof(X) % 4 == 0, "table entries are whole words");
+    union {
+        X x;
+        uint32_t w[sizeof(X) / 4];
+    } u;
+    const cptr<uint32_t> q = (cptr<uint32_t>)p;
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(X) / 4); ++i) u.w[i] = q[i];
+    return u.x;
+}
+
 template <typename V, typename T>
 __device__ __forceinline__ V cmul_add2(T ar_, T ai_, V a, T br_, T bi_, V b)
 {
@@ -45,8 +74,8 @@ __device__ __forceinline__ uint32_t ins0(uint32_t x, int p)
 }
 
 // Coefficients of a 2x2 (row-major, interleaved) or its conjugate transpose.
-template <typename T>
-__device__ __forceinline__ void load2x2(const double* cf, bool dagger, T* u)
+template <typename T, typename P>
+__device__ __forceinline__ void load2x2(P cf, bool dagger, T* u)
 {
     if (!dagger) {
 #pragma unroll
@@ -60,16 +89,29 @@ __device__ __forceinline__ void load2x2(const double* cf, bool dagger, T* u)
     }
 }
 
-// Apply one op (or its inverse) to an LDS tile of 2^tq amplitudes.
-template <typename T>
-__device__ void lds_apply(typename Vec2<T>::type* A, const FOp& op, const double* __restrict__ coef, bool dagger,
-                          int tq)
+// LDS address of tile-local index l in the register engine's exchange buffer.
+__device__ __forceinline__ uint32_t swz(uint32_t l)
+{
+    // l < 2^16: fold bit groups [4, 8), [8, 12), [12, 16) into [0, 4)
+    return l ^ (((l >> 4) ^ (l >> 8) ^ (l >> 12)) & ((1u << kSwzBits) - 1u));
+}
+
+// Apply one op (or its inverse) to an LDS tile of 2^tq amplitudes; with SWZ
+// the tile is stored at swz(l) (the register engine's exchange layout).
+template <typename T, bool SWZ = false, typename P = const double*>
+__device__ void lds_apply(typename Vec2<T>::type* A0, const FOp op, P coef, bool dagger, int tq)
 {
     using V = typename Vec2<T>::type;
+    struct Tile {
+        V* a;
+        __device__ V& operator[](uint32_t i) const { return a[SWZ ? swz(i) : i]; }
+    } A{A0};
     const int nthr = blockDim.x;
     const uint32_t cm = op.cm;
-    const double* cf = coef + op.coef;
+    const P cf = coef + op.coef;
     switch (op.kind) {
+    case FK_PAIRX:
+    case FK_PAIRR:
     case FK_PAIR: {
         T u[8];
         load2x2<T>(cf, dagger, u);
@@ -214,44 +256,33 @@ __device__ double block_sum_fixed(double v, double* red)
 // (every thread writes its amplitudes, barrier, reads its new ones).
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ uint32_t swz(uint32_t l)
-{
-    // l < 2^16: fold bit groups [4, 8), [8, 12), [12, 16) into [0, 4)
-    return l ^ (((l >> 4) ^ (l >> 8) ^ (l >> 12)) & ((1u << kSwzBits) - 1u));
-}
 
-// Lane bits of the thread and register offsets of a layout.
+// Lane bits of the thread and register offsets of a layout.  The layout
+// table holds the bit values, so nothing here waits on a dependent load.
 template <int RB>
-__device__ __forceinline__ void frame_of(const FLayout* __restrict__ L, int tq, uint32_t tid, uint32_t& tl,
-                                         uint32_t* off)
+__device__ __forceinline__ void frame_of(cptr<FLayout> L, uint32_t tid, uint32_t& tl, uint32_t* off)
 {
-    const int nl = tq - RB;
     uint32_t t = 0;
-    for (int i = 0; i < nl; ++i) t |= ((tid >> i) & 1u) << L->pos[i];
-    tl = t;
-    uint32_t rbit[RB];
 #pragma unroll
-    for (int r = 0; r < RB; ++r) rbit[r] = 1u << L->pos[nl + r];
+    for (int i = 0; i < 16; ++i)
+        if ((tid >> i) & 1u) t |= L->lane_l[i];
+    tl = t;
     off[0] = 0;
 #pragma unroll
-    for (int j = 1; j < (1 << RB); ++j) off[j] = off[j & (j - 1)] | rbit[__builtin_ctz(j)];
+    for (int j = 1; j < (1 << RB); ++j) off[j] = off[j & (j - 1)] | L->reg_l[__builtin_ctz(j)];
 }
 
 // Global element offsets of this thread's registers in a layout.
 template <int RB>
-__device__ __forceinline__ void global_frame(const FLayout* __restrict__ L, const int32_t* __restrict__ q, int tq,
-                                             uint32_t tid, uint64_t tile_base, uint64_t* g)
+__device__ __forceinline__ void global_frame(cptr<FLayout> L, uint32_t tid, uint64_t tile_base, uint64_t* g)
 {
-    const int nl = tq - RB;
     uint64_t t = tile_base;
-    for (int i = 0; i < nl; ++i)
-        if ((tid >> i) & 1u) t |= 1ull << q[L->pos[i]];
-    uint64_t rbit[RB];
 #pragma unroll
-    for (int r = 0; r < RB; ++r) rbit[r] = 1ull << q[L->pos[nl + r]];
+    for (int i = 0; i < 16; ++i)
+        if ((tid >> i) & 1u) t |= L->lane_g[i];
     g[0] = t;
 #pragma unroll
-    for (int j = 1; j < (1 << RB); ++j) g[j] = g[j & (j - 1)] | rbit[__builtin_ctz(j)];
+    for (int j = 1; j < (1 << RB); ++j) g[j] = g[j & (j - 1)] | L->reg_g[__builtin_ctz(j)];
 }
 
 template <typename V, int RB>
@@ -268,14 +299,37 @@ __device__ __forceinline__ void lds_get(const V* __restrict__ lds, V* v, uint32_
     for (int j = 0; j < (1 << RB); ++j) v[j] = lds[swz(tl | off[j])];
 }
 
-template <typename T, int RB, int K>
-__device__ __forceinline__ void rpair_k(typename Vec2<T>::type* v, const T* u, uint32_t tl, const uint32_t* off,
-                                        uint32_t cm)
+// In the register routines below, a control mask is split in two: the lane
+// part has been checked once per op for the thread (the routine only runs
+// when it holds); `cmr`, the register part, is the same for every thread,
+// and off[j] is too, so each register's test is a uniform branch.
+
+#define SV_K_SWITCH(k, CALL)                                                                                       \
+    switch (k) {                                                                                                   \
+    case 0: CALL(0); break;                                                                                        \
+    case 1: CALL(1); break;                                                                                        \
+    case 2: CALL(2); break;                                                                                        \
+    default:                                                                                                       \
+        if constexpr (RB > 3) { CALL(3); }                                                                         \
+        break;                                                                                                     \
+    }
+
+
+// Apply one op (or its inverse) to this thread's registers.  cf: the op's
+// coefficients; coef: the table (for 4x4 matrices).
+// In the register routines below, a control mask is split in two.  The lane
+// part selects, per thread, between the op's coefficients and the identity
+// (SEL).  The register part `cmr` is the same for every thread, and off[j]
+// is too, so each register's test (CHK) is a uniform branch.
+
+// Complex 2x2 on register bit K.
+template <typename T, int RB, int K, bool CHK>
+__device__ __forceinline__ void rpair_k(typename Vec2<T>::type* v, const T* u, const uint32_t* off, uint32_t cmr)
 {
 #pragma unroll
     for (int j = 0; j < (1 << RB); ++j) {
         if (j & (1 << K)) continue;
-        if (((tl | off[j]) & cm) != cm) continue;
+        if (CHK && (off[j] & cmr) != cmr) continue;
         const int j1 = j | (1 << K);
         const auto a = v[j], b = v[j1];
         v[j] = cmul_add2<typename Vec2<T>::type, T>(u[0], u[1], a, u[2], u[3], b);
@@ -283,39 +337,112 @@ __device__ __forceinline__ void rpair_k(typename Vec2<T>::type* v, const T* u, u
     }
 }
 
-template <typename T, int RB, int KA, int KB>
-__device__ __forceinline__ void rswap_k(typename Vec2<T>::type* v, uint32_t tl, const uint32_t* off, uint32_t cm)
+// Real 2x2 [[r0, r1], [r2, r3]] on register bit K.
+template <typename T, int RB, int K, bool CHK>
+__device__ __forceinline__ void rpairr_k(typename Vec2<T>::type* v, const T* r, const uint32_t* off, uint32_t cmr)
+{
+#pragma unroll
+    for (int j = 0; j < (1 << RB); ++j) {
+        if (j & (1 << K)) continue;
+        if (CHK && (off[j] & cmr) != cmr) continue;
+        const int j1 = j | (1 << K);
+        const auto a = v[j], b = v[j1];
+        v[j].x = r[0] * a.x + r[1] * b.x;
+        v[j].y = r[0] * a.y + r[1] * b.y;
+        v[j1].x = r[2] * a.x + r[3] * b.x;
+        v[j1].y = r[2] * a.y + r[3] * b.y;
+    }
+}
+
+// Exchange of the pair on register bit K (X); with SEL only where `ok` holds.
+template <typename T, int RB, int K, bool CHK, bool SEL>
+__device__ __forceinline__ void rpairx_k(typename Vec2<T>::type* v, bool ok, const uint32_t* off, uint32_t cmr)
+{
+#pragma unroll
+    for (int j = 0; j < (1 << RB); ++j) {
+        if (j & (1 << K)) continue;
+        if (CHK && (off[j] & cmr) != cmr) continue;
+        const int j1 = j | (1 << K);
+        const auto a = v[j], b = v[j1];
+        if constexpr (SEL) {
+            v[j].x = ok ? b.x : a.x;
+            v[j].y = ok ? b.y : a.y;
+            v[j1].x = ok ? a.x : b.x;
+            v[j1].y = ok ? a.y : b.y;
+        } else {
+            v[j] = b;
+            v[j1] = a;
+        }
+    }
+}
+
+// Element-wise diagonal d[bit of register K].
+template <typename T, int RB, int K, bool CHK>
+__device__ __forceinline__ void rdiag_k(typename Vec2<T>::type* v, const T* d, const uint32_t* off, uint32_t cmr)
+{
+#pragma unroll
+    for (int j = 0; j < (1 << RB); ++j) {
+        if (CHK && (off[j] & cmr) != cmr) continue;
+        const T zr = (j >> K) & 1 ? d[2] : d[0], zi = (j >> K) & 1 ? d[3] : d[1];
+        const auto x = v[j];
+        v[j].x = zr * x.x - zi * x.y;
+        v[j].y = zr * x.y + zi * x.x;
+    }
+}
+
+// One phase z on every register (passing the register-bit controls).
+template <typename T, int RB, bool CHK>
+__device__ __forceinline__ void rphase(typename Vec2<T>::type* v, T zr, T zi, const uint32_t* off, uint32_t cmr)
+{
+#pragma unroll
+    for (int j = 0; j < (1 << RB); ++j) {
+        if (CHK && (off[j] & cmr) != cmr) continue;
+        const auto x = v[j];
+        v[j].x = zr * x.x - zi * x.y;
+        v[j].y = zr * x.y + zi * x.x;
+    }
+}
+
+template <typename T, int RB, int KA, int KB, bool CHK, bool SEL>
+__device__ __forceinline__ void rswap_k(typename Vec2<T>::type* v, bool ok, const uint32_t* off, uint32_t cmr)
 {
 #pragma unroll
     for (int j = 0; j < (1 << RB); ++j) {
         if (!(j & (1 << KA)) || (j & (1 << KB))) continue;  // j: bit a = 1, bit b = 0
-        if (((tl | off[j]) & cm) != cm) continue;
+        if (CHK && (off[j] & cmr) != cmr) continue;
         const int j1 = j ^ (1 << KA) ^ (1 << KB);
-        const auto t = v[j];
-        v[j] = v[j1];
-        v[j1] = t;
+        const auto a = v[j], b = v[j1];
+        if constexpr (SEL) {
+            v[j].x = ok ? b.x : a.x;
+            v[j].y = ok ? b.y : a.y;
+            v[j1].x = ok ? a.x : b.x;
+            v[j1].y = ok ? a.y : b.y;
+        } else {
+            v[j] = b;
+            v[j1] = a;
+        }
     }
 }
 
 // 4x4 on register bits KA (matrix MSB) and KB; u = 16 complex entries row-major
-template <typename T, int RB, int KA, int KB>
-__device__ __forceinline__ void rquad_k(typename Vec2<T>::type* v, const T* u, uint32_t tl, const uint32_t* off,
-                                        uint32_t cm)
+template <typename T, int RB, int KA, int KB, bool CHK>
+__device__ __forceinline__ void rquad_k(typename Vec2<T>::type* v, const T* u, const uint32_t* off, uint32_t cmr)
 {
     using V = typename Vec2<T>::type;
 #pragma unroll
     for (int j = 0; j < (1 << RB); ++j) {
         if (j & ((1 << KA) | (1 << KB))) continue;
-        if (((tl | off[j]) & cm) != cm) continue;
+        if (CHK && (off[j] & cmr) != cmr) continue;
         const int ix[4] = {j, j | (1 << KB), j | (1 << KA), j | (1 << KA) | (1 << KB)};
         V w[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) w[k] = v[ix[k]];
 #pragma unroll
         for (int row = 0; row < 4; ++row) {
-            T sr = T(0), si = T(0);
+            T sr = u[8 * row] * w[0].x - u[8 * row + 1] * w[0].y;
+            T si = u[8 * row] * w[0].y + u[8 * row + 1] * w[0].x;
 #pragma unroll
-            for (int col = 0; col < 4; ++col) {
+            for (int col = 1; col < 4; ++col) {
                 const T ur = u[2 * (4 * row + col)], ui = u[2 * (4 * row + col) + 1];
                 sr += ur * w[col].x - ui * w[col].y;
                 si += ur * w[col].y + ui * w[col].x;
@@ -326,38 +453,23 @@ __device__ __forceinline__ void rquad_k(typename Vec2<T>::type* v, const T* u, u
     }
 }
 
-template <typename T, int RB>
-__device__ __forceinline__ void rpair(int k, typename Vec2<T>::type* v, const T* u, uint32_t tl, const uint32_t* off,
-                                      uint32_t cm)
-{
-    switch (k) {
-    case 0: rpair_k<T, RB, 0>(v, u, tl, off, cm); break;
-    case 1: rpair_k<T, RB, 1>(v, u, tl, off, cm); break;
-    case 2: rpair_k<T, RB, 2>(v, u, tl, off, cm); break;
-    default:
-        if constexpr (RB > 3) rpair_k<T, RB, 3>(v, u, tl, off, cm);
-        break;
-    }
-}
-
-#define SV_RB_PAIRS(X)                                                                                             \
-    X(0, 1) X(0, 2) X(1, 0) X(1, 2) X(2, 0) X(2, 1)
+#define SV_RB_PAIRS(X) X(0, 1) X(0, 2) X(1, 0) X(1, 2) X(2, 0) X(2, 1)
 #define SV_RB4_PAIRS(X) X(0, 3) X(1, 3) X(2, 3) X(3, 0) X(3, 1) X(3, 2)
 
-template <typename T, int RB>
-__device__ __forceinline__ void rswap(int ka, int kb, typename Vec2<T>::type* v, uint32_t tl, const uint32_t* off,
-                                      uint32_t cm)
+template <typename T, int RB, bool CHK, bool SEL>
+__device__ __forceinline__ void rswap(int ka, int kb, typename Vec2<T>::type* v, bool ok, const uint32_t* off,
+                                      uint32_t cmr)
 {
     switch (ka * 4 + kb) {
 #define SV_CASE(A, B)                                                                                              \
-    case A * 4 + B: rswap_k<T, RB, A, B>(v, tl, off, cm); break;
+    case A * 4 + B: rswap_k<T, RB, A, B, CHK, SEL>(v, ok, off, cmr); break;
         SV_RB_PAIRS(SV_CASE)
 #undef SV_CASE
     default:
         if constexpr (RB > 3) {
             switch (ka * 4 + kb) {
 #define SV_CASE(A, B)                                                                                              \
-    case A * 4 + B: rswap_k<T, RB, (A < 4 ? A : 0), (B < 4 ? B : 0)>(v, tl, off, cm); break;
+    case A * 4 + B: rswap_k<T, RB, A, B, CHK, SEL>(v, ok, off, cmr); break;
                 SV_RB4_PAIRS(SV_CASE)
 #undef SV_CASE
             default: break;
@@ -367,20 +479,20 @@ __device__ __forceinline__ void rswap(int ka, int kb, typename Vec2<T>::type* v,
     }
 }
 
-template <typename T, int RB>
-__device__ __forceinline__ void rquad(int ka, int kb, typename Vec2<T>::type* v, const T* u, uint32_t tl,
-                                      const uint32_t* off, uint32_t cm)
+template <typename T, int RB, bool CHK>
+__device__ __forceinline__ void rquad(int ka, int kb, typename Vec2<T>::type* v, const T* u, const uint32_t* off,
+                                      uint32_t cmr)
 {
     switch (ka * 4 + kb) {
 #define SV_CASE(A, B)                                                                                              \
-    case A * 4 + B: rquad_k<T, RB, A, B>(v, u, tl, off, cm); break;
+    case A * 4 + B: rquad_k<T, RB, A, B, CHK>(v, u, off, cmr); break;
         SV_RB_PAIRS(SV_CASE)
 #undef SV_CASE
     default:
         if constexpr (RB > 3) {
             switch (ka * 4 + kb) {
 #define SV_CASE(A, B)                                                                                              \
-    case A * 4 + B: rquad_k<T, RB, (A < 4 ? A : 0), (B < 4 ? B : 0)>(v, u, tl, off, cm); break;
+    case A * 4 + B: rquad_k<T, RB, A, B, CHK>(v, u, off, cmr); break;
                 SV_RB4_PAIRS(SV_CASE)
 #undef SV_CASE
             default: break;
@@ -390,48 +502,81 @@ __device__ __forceinline__ void rquad(int ka, int kb, typename Vec2<T>::type* v,
     }
 }
 
-// Apply one op (or its inverse) to this thread's registers.
-template <typename T, int RB>
-__device__ __forceinline__ void reg_apply(typename Vec2<T>::type* v, const FOp& op, const double* __restrict__ coef,
-                                          bool dagger, uint32_t tl, const uint32_t* off)
+// TWO: two-target ops (SWAP, 4x4) run in registers; reverse passes leave them
+// to an LDS sweep instead (lds_op), which keeps their register code smaller.
+template <typename T, int RB, bool CHK, bool SEL, bool TWO>
+__device__ __forceinline__ void reg_apply_c(typename Vec2<T>::type* v, const FOp& op, cptr<T> cf, bool dagger,
+                                            uint32_t tl, const uint32_t* off, uint32_t cmr, bool ok)
 {
-    using V = typename Vec2<T>::type;
-    const double* cf = coef + op.coef;
     switch (op.kind) {
+    case FK_PAIRX: {
+#define SV_CALL(K) rpairx_k<T, RB, K, CHK, SEL>(v, ok, off, cmr)
+        SV_K_SWITCH(op.ka, SV_CALL)
+#undef SV_CALL
+        break;
+    }
+    case FK_PAIRR: {  // real: the transpose is the inverse's matrix
+        T r[4] = {(T)cf[0], (T)cf[2], (T)cf[4], (T)cf[6]};
+        if (dagger) {
+            const T t = r[1];
+            r[1] = r[2];
+            r[2] = t;
+        }
+        if constexpr (SEL) {
+            r[0] = ok ? r[0] : T(1);
+            r[1] = ok ? r[1] : T(0);
+            r[2] = ok ? r[2] : T(0);
+            r[3] = ok ? r[3] : T(1);
+        }
+#define SV_CALL(K) rpairr_k<T, RB, K, CHK>(v, r, off, cmr)
+        SV_K_SWITCH(op.ka, SV_CALL)
+#undef SV_CALL
+        break;
+    }
     case FK_PAIR: {
         T u[8];
         load2x2<T>(cf, dagger, u);
-        rpair<T, RB>(op.ka, v, u, tl, off, op.cm);
+        if constexpr (SEL) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) u[k] = ok ? u[k] : ((k == 0 || k == 6) ? T(1) : T(0));
+        }
+#define SV_CALL(K) rpair_k<T, RB, K, CHK>(v, u, off, cmr)
+        SV_K_SWITCH(op.ka, SV_CALL)
+#undef SV_CALL
         break;
     }
     case FK_DIAG: {
-        const T d0r = (T)cf[0], d0i = (T)(dagger ? -cf[1] : cf[1]);
-        const T d1r = (T)cf[2], d1i = (T)(dagger ? -cf[3] : cf[3]);
-#pragma unroll
-        for (int j = 0; j < (1 << RB); ++j) {
-            const uint32_t l = tl | off[j];
-            if ((l & op.cm) != op.cm) continue;
-            const bool b = (l >> op.a) & 1u;
-            const T zr = b ? d1r : d0r, zi = b ? d1i : d0i;
-            const V x = v[j];
-            v[j].x = zr * x.x - zi * x.y;
-            v[j].y = zr * x.y + zi * x.x;
+        T d[4] = {(T)cf[0], (T)(dagger ? -cf[1] : cf[1]), (T)cf[2], (T)(dagger ? -cf[3] : cf[3])};
+        if constexpr (SEL) {
+            d[0] = ok ? d[0] : T(1);
+            d[1] = ok ? d[1] : T(0);
+            d[2] = ok ? d[2] : T(1);
+            d[3] = ok ? d[3] : T(0);
+        }
+        if (op.ka >= 0) {
+#define SV_CALL(K) rdiag_k<T, RB, K, CHK>(v, d, off, cmr)
+            SV_K_SWITCH(op.ka, SV_CALL)
+#undef SV_CALL
+        } else {  // target on a lane bit: one phase for all of this thread's registers
+            const bool b = (tl >> op.a) & 1u;
+            rphase<T, RB, CHK>(v, b ? d[2] : d[0], b ? d[3] : d[1], off, cmr);
         }
         break;
     }
     case FK_PHASE: {
-        const T zr = (T)cf[0], zi = (T)(dagger ? -cf[1] : cf[1]);
-#pragma unroll
-        for (int j = 0; j < (1 << RB); ++j) {
-            if (((tl | off[j]) & op.cm) != op.cm) continue;
-            const V x = v[j];
-            v[j].x = zr * x.x - zi * x.y;
-            v[j].y = zr * x.y + zi * x.x;
+        T zr = (T)cf[0], zi = (T)(dagger ? -cf[1] : cf[1]);
+        if constexpr (SEL) {
+            zr = ok ? zr : T(1);
+            zi = ok ? zi : T(0);
         }
+        rphase<T, RB, CHK>(v, zr, zi, off, cmr);
         break;
     }
-    case FK_SWAP: rswap<T, RB>(op.ka, op.kb, v, tl, off, op.cm); break;
+    case FK_SWAP:
+        if constexpr (TWO) rswap<T, RB, CHK, SEL>(op.ka, op.kb, v, ok, off, cmr);
+        break;
     case FK_QUAD: {
+        if constexpr (!TWO) break;
         T u[32];
 #pragma unroll
         for (int r = 0; r < 4; ++r)
@@ -441,24 +586,46 @@ __device__ __forceinline__ void reg_apply(typename Vec2<T>::type* v, const FOp& 
                 u[2 * (4 * r + c)] = (T)cf[2 * e];
                 u[2 * (4 * r + c) + 1] = (T)(dagger ? -cf[2 * e + 1] : cf[2 * e + 1]);
             }
-        rquad<T, RB>(op.ka, op.kb, v, u, tl, off, op.cm);
+        // lane-controlled 4x4 ops are rare: a plain branch
+        if (!SEL || ok) rquad<T, RB, CHK>(op.ka, op.kb, v, u, off, cmr);
         break;
     }
     default: break;
     }
 }
 
+// Every thread runs every op (no divergent branch around the registers, which
+// would make the compiler copy all of them at each join): a lane-bit control
+// turns the op into the identity for threads where it is 0.
+template <typename T, int RB, bool TWO = true>
+__device__ __forceinline__ void reg_apply(typename Vec2<T>::type* v, const FOp& op, cptr<T> cf, bool dagger,
+                                          uint32_t tl, const uint32_t* off)
+{
+    const uint32_t regmask = off[(1 << RB) - 1];
+    const uint32_t cmr = op.cm & regmask;
+    const uint32_t cml = op.cm & ~regmask;
+    const bool ok = (tl & cml) == cml;
+    if (cml) {
+        if (cmr) reg_apply_c<T, RB, true, true, TWO>(v, op, cf, dagger, tl, off, cmr, ok);
+        else reg_apply_c<T, RB, false, true, TWO>(v, op, cf, dagger, tl, off, 0u, ok);
+    } else {
+        if (cmr) reg_apply_c<T, RB, true, false, TWO>(v, op, cf, dagger, tl, off, cmr, true);
+        else reg_apply_c<T, RB, false, false, TWO>(v, op, cf, dagger, tl, off, 0u, true);
+    }
+}
+
 // Per-thread Im <lambda|G|phi> over this thread's registers (generator of a
-// parameterised one-target op, restricted to its controls).
-template <typename T, int RB, int K>
+// parameterised one-target op, restricted to its controls; the target's own
+// bit is excluded from the mask).
+template <typename T, int RB, int K, bool CHK>
 __device__ __forceinline__ double rgen_pair_k(const typename Vec2<T>::type* P, const typename Vec2<T>::type* L,
-                                              bool gy, uint32_t tl, const uint32_t* off, uint32_t cm)
+                                              bool gy, const uint32_t* off, uint32_t cmr)
 {
     double acc = 0.0;
 #pragma unroll
     for (int j = 0; j < (1 << RB); ++j) {
         if (j & (1 << K)) continue;
-        if (((tl | off[j]) & cm) != cm) continue;
+        if (CHK && (off[j] & cmr) != cmr) continue;
         const int j1 = j | (1 << K);
         const double a0r = P[j].x, a0i = P[j].y, a1r = P[j1].x, a1i = P[j1].y;
         const double l0r = L[j].x, l0i = L[j].y, l1r = L[j1].x, l1i = L[j1].y;
@@ -468,34 +635,52 @@ __device__ __forceinline__ double rgen_pair_k(const typename Vec2<T>::type* P, c
     return acc;
 }
 
-template <typename T, int RB>
-__device__ __forceinline__ double reg_gen_inner(const typename Vec2<T>::type* P, const typename Vec2<T>::type* L,
-                                                const FOp& op, uint32_t tl, const uint32_t* off)
+// Z-type generators: sign (GEN_Z) or indicator (GEN_P1) of the target bit;
+// sel(j) gives that bit for register j.
+template <typename T, int RB, bool CHK, typename Sel>
+__device__ __forceinline__ double rgen_elem(const typename Vec2<T>::type* P, const typename Vec2<T>::type* L, bool gz,
+                                            const uint32_t* off, uint32_t cmr, Sel sel)
 {
-    const uint32_t cm = op.cm & ~(1u << op.a);  // a subset-phase op lists its target in cm
-    if (op.gen == GEN_X || op.gen == GEN_Y) {
-        const bool gy = op.gen == GEN_Y;
-        switch (op.ka) {
-        case 0: return rgen_pair_k<T, RB, 0>(P, L, gy, tl, off, cm);
-        case 1: return rgen_pair_k<T, RB, 1>(P, L, gy, tl, off, cm);
-        case 2: return rgen_pair_k<T, RB, 2>(P, L, gy, tl, off, cm);
-        default:
-            if constexpr (RB > 3) return rgen_pair_k<T, RB, 3>(P, L, gy, tl, off, cm);
-            return 0.0;
-        }
-    }
     double acc = 0.0;
-    const bool gz = op.gen == GEN_Z;
 #pragma unroll
     for (int j = 0; j < (1 << RB); ++j) {
-        const uint32_t l = tl | off[j];
-        if ((l & cm) != cm) continue;
-        const bool b = (l >> op.a) & 1u;
+        if (CHK && (off[j] & cmr) != cmr) continue;
+        const bool b = sel(j);
         const double t = (double)L[j].x * (double)P[j].y - (double)L[j].y * (double)P[j].x;
         if (gz) acc += b ? -t : t;
         else if (b) acc += t;
     }
     return acc;
+}
+
+template <typename T, int RB>
+__device__ __forceinline__ double reg_gen_inner(const typename Vec2<T>::type* P, const typename Vec2<T>::type* L,
+                                                const FOp& op, uint32_t tl, const uint32_t* off)
+{
+    const uint32_t regmask = off[(1 << RB) - 1];
+    const uint32_t cm = op.cm & ~(1u << op.a);  // a subset-phase op lists its target in cm
+    const uint32_t cmr = cm & regmask;
+    if ((tl & cm) != (cm & ~regmask)) return 0.0;
+    if (op.gen == GEN_X || op.gen == GEN_Y) {
+        const bool gy = op.gen == GEN_Y;
+        double r = 0.0;
+        if (cmr) {
+#define SV_CALL(K) r = rgen_pair_k<T, RB, K, true>(P, L, gy, off, cmr)
+            SV_K_SWITCH(op.ka, SV_CALL)
+#undef SV_CALL
+        } else {
+#define SV_CALL(K) r = rgen_pair_k<T, RB, K, false>(P, L, gy, off, 0u)
+            SV_K_SWITCH(op.ka, SV_CALL)
+#undef SV_CALL
+        }
+        return r;
+    }
+    const bool gz = op.gen == GEN_Z;
+    const uint32_t abit = 1u << op.a;
+    if (abit & regmask)
+        return rgen_elem<T, RB, true>(P, L, gz, off, cmr, [&](int j) { return (off[j] & abit) != 0; });
+    const bool b = (tl & abit) != 0;
+    return rgen_elem<T, RB, true>(P, L, gz, off, cmr, [&](int) { return b; });
 }
 
 // Sum per slot of the wave partials, in fixed wave order, to the per-tile table.
@@ -506,7 +691,7 @@ __device__ __forceinline__ void flush_slots(const PassTables& tb, const FCirc& c
     const int nwaves = (blockDim.x + 63) >> 6;
     int k = 0;
     for (int o = op_end - 1; o >= op_begin; --o) {
-        const FOp& op = tb.ops[o];
+        const FOp op = ld_const(as_const(tb.ops) + o);
         if (op.kind == FK_LAYOUT || op.slot < 0) continue;
         double s = 0.0;
         for (int w = 0; w < nwaves; ++w) s += wpart[k * 16 + w];
@@ -515,15 +700,47 @@ __device__ __forceinline__ void flush_slots(const PassTables& tb, const FCirc& c
     }
 }
 
-// Tile base (global index with zeros at the tile's qubits) of tile `tile`.
-__device__ __forceinline__ uint64_t tile_base_of(const FPass& ps, int tq, int tile)
+// The coefficient table in the run's precision (complex64 runs read the
+// float copy, so no per-use conversion lands in vector registers).
+template <typename T>
+__device__ __forceinline__ cptr<T> coef_table(const PassTables& tb)
 {
-    uint64_t b = (uint64_t)tile;
-    for (int k = 0; k < tq; ++k) {
-        const int p = ps.q[k];
-        b = ((b >> p) << (p + 1)) | (b & ((1ull << p) - 1ull));
-    }
+    if constexpr (sizeof(T) == 8) return (cptr<T>)as_const(tb.coef);
+    else return (cptr<T>)as_const(tb.coef_f);
+}
+
+// Tile base: the tile index deposited into the global bits outside the tile.
+__device__ __forceinline__ uint64_t tile_base_of(uint64_t free_mask, uint64_t tile)
+{
+    uint64_t b = 0;
+    for (uint64_t m = free_mask; m && tile; m &= m - 1, tile >>= 1)
+        if (tile & 1) b |= m & (~m + 1);
     return b;
+}
+
+// The next op's descriptor is fetched one op ahead, so its load overlaps the
+// current op's arithmetic.
+struct OpPre {
+    FOp op;
+};
+
+__device__ __forceinline__ void op_fetch(const PassTables& tb, int o, OpPre& p) { p.op = ld_const(as_const(tb.ops) + o); }
+
+// A two-target op (SWAP, 4x4) in a reverse pass: the tile goes to LDS, every
+// thread sweeps the op over it, and the registers are read back.  These ops
+// are rare in the workloads, and keeping them out of the reverse kernel's
+// register switch makes its code smaller and faster.
+template <typename T, int RB, typename P>
+__device__ __forceinline__ void lds_op(typename Vec2<T>::type* v, typename Vec2<T>::type* lds, const FOp& op, P coef,
+                                       bool dagger, int tq, bool active, uint32_t tl, const uint32_t* off)
+{
+    using V = typename Vec2<T>::type;
+    if (active) lds_put<V, RB>(lds, v, tl, off);
+    __syncthreads();
+    lds_apply<T, true, P>(lds, op, coef, dagger, tq);
+    __syncthreads();
+    if (active) lds_get<V, RB>(lds, v, tl, off);
+    __syncthreads();
 }
 
 template <typename T, int RB>
@@ -533,17 +750,21 @@ __device__ __forceinline__ void item_reg_fwd(const PassTables& tb, const FCirc& 
     using V = typename Vec2<T>::type;
     constexpr int R = 1 << RB;
     const int tq = cc.tq;
-    const FPass& ps = tb.passes[cc.pass_begin + pidx];
+    const cptr<FPass> pp = as_const(tb.passes) + cc.pass_begin + pidx;
+    const cptr<FLayout> lays = as_const(tb.lays);
+    const int op_begin = pp->op_begin, op_end = pp->op_end;
     const bool active = threadIdx.x < (1u << (tq - RB));
-    const uint64_t tile_base = tile_base_of(ps, tq, tile);
+    const uint64_t tile_base = tile_base_of(pp->free_mask, (uint64_t)tile);
     V* const psi = (V*)cc.psi;
     uint32_t tl, off[R];
     V v[R];
-    int cur = ps.lay_begin;
-    frame_of<RB>(tb.lays + cur, tq, threadIdx.x, tl, off);
+    int cur = pp->lay_begin;
+    frame_of<RB>(lays + cur, threadIdx.x, tl, off);
+#pragma unroll
+    for (int j = 0; j < R; ++j) v[j].x = v[j].y = T(0);  // threads past the tile keep zeros
     if (active) {
         uint64_t g[R];
-        global_frame<RB>(tb.lays + cur, ps.q, tq, threadIdx.x, tile_base, g);
+        global_frame<RB>(lays + cur, threadIdx.x, tile_base, g);
         if (pidx == 0) {
 #pragma unroll
             for (int j = 0; j < R; ++j) {
@@ -555,23 +776,28 @@ __device__ __forceinline__ void item_reg_fwd(const PassTables& tb, const FCirc& 
             for (int j = 0; j < R; ++j) v[j] = ldg<true>(psi + g[j]);
         }
     }
-    for (int o = ps.op_begin; o < ps.op_end; ++o) {
-        const FOp op = tb.ops[o];
+    const cptr<T> coef = coef_table<T>(tb);
+    OpPre nx;
+    if (op_begin < op_end) op_fetch(tb, op_begin, nx);
+    for (int o = op_begin; o < op_end; ++o) {
+        const OpPre p = nx;
+        if (o + 1 < op_end) op_fetch(tb, o + 1, nx);
+        const FOp& op = p.op;
         if (op.kind == FK_LAYOUT) {
             if (op.a == cur) continue;
             if (active) lds_put<V, RB>(lds, v, tl, off);
             __syncthreads();
             cur = op.a;
-            frame_of<RB>(tb.lays + cur, tq, threadIdx.x, tl, off);
+            frame_of<RB>(lays + cur, threadIdx.x, tl, off);
             if (active) lds_get<V, RB>(lds, v, tl, off);
             __syncthreads();
             continue;
         }
-        if (active) reg_apply<T, RB>(v, op, tb.coef, false, tl, off);
+        reg_apply<T, RB>(v, op, coef + op.coef, false, tl, off);
     }
     if (active) {
         uint64_t g[R];
-        global_frame<RB>(tb.lays + cur, ps.q, tq, threadIdx.x, tile_base, g);
+        global_frame<RB>(lays + cur, threadIdx.x, tile_base, g);
 #pragma unroll
         for (int j = 0; j < R; ++j) stg<true>(psi + g[j], v[j]);
     }
@@ -585,18 +811,23 @@ __device__ __forceinline__ void item_reg_rev(const PassTables& tb, const FCirc& 
     using V = typename Vec2<T>::type;
     constexpr int R = 1 << RB;
     const int tq = cc.tq;
-    const FPass& ps = tb.passes[cc.pass_begin + pidx];
+    const cptr<FPass> pp = as_const(tb.passes) + cc.pass_begin + pidx;
+    const cptr<FLayout> lays = as_const(tb.lays);
+    const cptr<T> coef = coef_table<T>(tb);
+    const int rop_begin = pp->rop_begin, rop_end = pp->rop_end;
     const bool active = threadIdx.x < (1u << (tq - RB));
-    const uint64_t tile_base = tile_base_of(ps, tq, tile);
+    const uint64_t tile_base = tile_base_of(pp->free_mask, (uint64_t)tile);
     V* const psi = (V*)cc.psi;
     V* const lam = (V*)cc.lam;
     uint32_t tl, off[R];
     V v[R], w[R];
-    int cur = ps.rlay_end;
-    frame_of<RB>(tb.lays + cur, tq, threadIdx.x, tl, off);
+    int cur = pp->rlay_end;
+    frame_of<RB>(lays + cur, threadIdx.x, tl, off);
+#pragma unroll
+    for (int j = 0; j < R; ++j) v[j].x = v[j].y = w[j].x = w[j].y = T(0);  // threads past the tile keep zeros
     if (active) {
         uint64_t g[R];
-        global_frame<RB>(tb.lays + cur, ps.q, tq, threadIdx.x, tile_base, g);
+        global_frame<RB>(lays + cur, threadIdx.x, tile_base, g);
 #pragma unroll
         for (int j = 0; j < R; ++j) {
             v[j] = ldg<true>(psi + g[j]);
@@ -604,12 +835,16 @@ __device__ __forceinline__ void item_reg_rev(const PassTables& tb, const FCirc& 
         }
     }
     int nslot = 0;
-    for (int o = ps.rop_end - 1; o >= ps.rop_begin; --o) {
-        const FOp op = tb.ops[o];
+    OpPre nx;
+    if (rop_begin < rop_end) op_fetch(tb, rop_end - 1, nx);
+    for (int o = rop_end - 1; o >= rop_begin; --o) {
+        const OpPre p = nx;
+        if (o - 1 >= rop_begin) op_fetch(tb, o - 1, nx);
+        const FOp& op = p.op;
         if (op.kind == FK_LAYOUT) {
             if (op.b == cur) continue;
             uint32_t tl2, off2[R];
-            frame_of<RB>(tb.lays + op.b, tq, threadIdx.x, tl2, off2);
+            frame_of<RB>(lays + op.b, threadIdx.x, tl2, off2);
             if (active) lds_put<V, RB>(lds, v, tl, off);
             __syncthreads();
             if (active) lds_get<V, RB>(lds, v, tl2, off2);
@@ -629,16 +864,19 @@ __device__ __forceinline__ void item_reg_rev(const PassTables& tb, const FCirc& 
             if ((threadIdx.x & 63) == 0) wpart[nslot * 16 + (threadIdx.x >> 6)] = c;
             ++nslot;
         }
-        if (active) {
-            reg_apply<T, RB>(v, op, tb.coef, true, tl, off);
-            reg_apply<T, RB>(w, op, tb.coef, true, tl, off);
+        if (op.kind == FK_SWAP || op.kind == FK_QUAD) {
+            lds_op<T, RB>(v, lds, op, coef, true, tq, active, tl, off);
+            lds_op<T, RB>(w, lds, op, coef, true, tq, active, tl, off);
+        } else {
+            reg_apply<T, RB, false>(v, op, coef + op.coef, true, tl, off);
+            reg_apply<T, RB, false>(w, op, coef + op.coef, true, tl, off);
         }
     }
     __syncthreads();  // every wave's partials are in LDS
-    flush_slots(tb, cc, ps.rop_begin, ps.rop_end, tile, wpart);
+    flush_slots(tb, cc, rop_begin, rop_end, tile, wpart);
     if (active) {
         uint64_t g[R];
-        global_frame<RB>(tb.lays + cur, ps.q, tq, threadIdx.x, tile_base, g);
+        global_frame<RB>(lays + cur, threadIdx.x, tile_base, g);
 #pragma unroll
         for (int j = 0; j < R; ++j) {
             stg<true>(psi + g[j], v[j]);
@@ -779,15 +1017,16 @@ __device__ __forceinline__ EngineLds engine_lds(const PassTables& tb, double* sm
 }
 
 // Segment of a work item: the last segment whose first item is <= item.
-__device__ __forceinline__ const FSeg& seg_of(const PassTables& tb, int64_t item)
+__device__ __forceinline__ FSeg seg_of(const PassTables& tb, int64_t item)
 {
+    const cptr<FSeg> segs = as_const(tb.segs);
     int lo = 0, hi = tb.n_segs - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (tb.segs[mid].first <= item) lo = mid;
+        if (segs[mid].first <= item) lo = mid;
         else hi = mid - 1;
     }
-    return tb.segs[lo];
+    return ld_const(segs + lo);
 }
 
 // Target waves per SIMD (which sets the VGPR budget: 512 / waves).  Forward
@@ -807,9 +1046,9 @@ k_pass_fwd(PassTables tb, int64_t item_begin, int64_t item_end)
     extern __shared__ double smem_d[];
     const EngineLds L = engine_lds<T>(tb, smem_d);
     for (int64_t item = item_begin + blockIdx.x; item < item_end; item += gridDim.x) {
-        const FSeg& sg = seg_of(tb, item);
+        const FSeg sg = seg_of(tb, item);
         const int tile = (int)(item - sg.first);
-        const FCirc& cc = tb.circs[sg.circ];
+        const FCirc cc = ld_const(as_const(tb.circs) + sg.circ);
         if (cc.reg) item_reg_fwd<T, RB>(tb, cc, sg.stage, tile, (V*)L.tileA);
         else item_lds<T>(tb, cc, true, sg.stage, tile, (V*)L.tileA, (V*)L.tileB, L.hi_map, L.wpart);
         __syncthreads();  // LDS is reused by the next item of this workgroup
@@ -820,11 +1059,10 @@ template <typename T>
 __global__ void __launch_bounds__(kMaxPassThreads)
 k_pass_obs(PassTables tb, int64_t item_begin, int64_t item_end)
 {
-    extern __shared__ double smem_d[];
-    const EngineLds L = engine_lds<T>(tb, smem_d);
+    __shared__ double red[16];
     for (int64_t item = item_begin + blockIdx.x; item < item_end; item += gridDim.x) {
-        const FSeg& sg = seg_of(tb, item);
-        item_observable<T>(tb, tb.circs[sg.circ], (int)(item - sg.first), L.red);
+        const FSeg sg = seg_of(tb, item);
+        item_observable<T>(tb, ld_const(as_const(tb.circs) + sg.circ), (int)(item - sg.first), red);
         __syncthreads();
     }
 }
@@ -837,9 +1075,9 @@ k_pass_rev(PassTables tb, int64_t item_begin, int64_t item_end)
     extern __shared__ double smem_d[];
     const EngineLds L = engine_lds<T>(tb, smem_d);
     for (int64_t item = item_begin + blockIdx.x; item < item_end; item += gridDim.x) {
-        const FSeg& sg = seg_of(tb, item);
+        const FSeg sg = seg_of(tb, item);
         const int tile = (int)(item - sg.first);
-        const FCirc& cc = tb.circs[sg.circ];
+        const FCirc cc = ld_const(as_const(tb.circs) + sg.circ);
         const int pidx = 2 * cc.n_pass - sg.stage;  // reverse stage n_pass+1+r -> pass n_pass-1-r
         if (cc.rreg) item_reg_rev<T, RB>(tb, cc, pidx, tile, (V*)L.tileA, L.wpart);
         else item_lds<T>(tb, cc, false, pidx, tile, (V*)L.tileA, (V*)L.tileB, L.hi_map, L.wpart);
@@ -847,9 +1085,10 @@ k_pass_rev(PassTables tb, int64_t item_begin, int64_t item_end)
     }
 }
 
-// One thread per op: gate coefficients from the parameters.
+// One thread per op: gate coefficients from the parameters, in double and
+// (if coef_f is set) rounded once to float for complex64 runs.
 __global__ void k_pass_coef(const FCoefSpec* __restrict__ spec, int n, const double* __restrict__ params,
-                            double* __restrict__ coef)
+                            double* __restrict__ coef, float* __restrict__ coef_f)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -857,15 +1096,19 @@ __global__ void k_pass_coef(const FCoefSpec* __restrict__ spec, int n, const dou
     double* c = coef + s.coef;
     const double th = s.pidx >= 0 ? params[s.pidx] : s.value;
     const double ch = cos(th / 2), sh = sin(th / 2);
+    int cnt;
     switch (s.gate) {
-    case SV_RX: c[0] = ch; c[1] = 0; c[2] = 0; c[3] = -sh; c[4] = 0; c[5] = -sh; c[6] = ch; c[7] = 0; break;
-    case SV_RY: c[0] = ch; c[1] = 0; c[2] = -sh; c[3] = 0; c[4] = sh; c[5] = 0; c[6] = ch; c[7] = 0; break;
-    case SV_RZ: c[0] = ch; c[1] = -sh; c[2] = ch; c[3] = sh; break;
-    case SV_PHASE: c[0] = cos(th); c[1] = sin(th); break;
+    case SV_RX: c[0] = ch; c[1] = 0; c[2] = 0; c[3] = -sh; c[4] = 0; c[5] = -sh; c[6] = ch; c[7] = 0; cnt = 8; break;
+    case SV_RY: c[0] = ch; c[1] = 0; c[2] = -sh; c[3] = 0; c[4] = sh; c[5] = 0; c[6] = ch; c[7] = 0; cnt = 8; break;
+    case SV_RZ: c[0] = ch; c[1] = -sh; c[2] = ch; c[3] = sh; cnt = 4; break;
+    case SV_PHASE: c[0] = cos(th); c[1] = sin(th); cnt = 2; break;
     default:
         for (int k = 0; k < s.nfixed; ++k) c[k] = s.fixed[k];
+        cnt = s.nfixed;
         break;
     }
+    if (coef_f)
+        for (int k = 0; k < cnt; ++k) coef_f[s.coef + k] = (float)c[k];
 }
 
 // out[k] = scale[k] * sum_{i < cnt[k]} part[off[k] + i], fixed order.
@@ -951,7 +1194,7 @@ static void launch_items_t(const PassTables& tb, int mode, unsigned grid, int th
                            int64_t b, int64_t e)
 {
     if (mode == PM_OBS) {
-        hipLaunchKernelGGL((k_pass_obs<T>), dim3(grid), dim3(threads), lds, s, tb, b, e);
+        hipLaunchKernelGGL((k_pass_obs<T>), dim3(grid), dim3(threads), 0, s, tb, b, e);
     } else if (mode == PM_FWD) {
         if (tb.reg_bits == 3) hipLaunchKernelGGL((k_pass_fwd<T, 3>), dim3(grid), dim3(threads), lds, s, tb, b, e);
         else hipLaunchKernelGGL((k_pass_fwd<T, 4>), dim3(grid), dim3(threads), lds, s, tb, b, e);
@@ -975,10 +1218,11 @@ hipError_t launch_pass_items(const PassTables& tb, int dtype, int mode, int64_t 
     return hipGetLastError();
 }
 
-hipError_t launch_pass_coef(const FCoefSpec* spec, int n, const double* params, double* coef, hipStream_t s)
+hipError_t launch_pass_coef(const FCoefSpec* spec, int n, const double* params, double* coef, float* coef_f,
+                            hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_pass_coef, dim3((n + 127) / 128), dim3(128), 0, s, spec, n, params, coef);
+    hipLaunchKernelGGL(k_pass_coef, dim3((n + 127) / 128), dim3(128), 0, s, spec, n, params, coef, coef_f);
     return hipGetLastError();
 }
 

@@ -126,12 +126,15 @@ void schedule(int n, int tq, int cb, const std::vector<BOp>& ops, std::vector<st
     }
 }
 
-// Tile bits an op needs in registers (its targets, except for diagonal and
-// subset-phase ops, which act element-wise in any layout).
+// Tile bits an op needs in registers: the target of a one-target pair op.
+// Diagonal and subset-phase ops act element-wise in any layout; two-target
+// ops (SWAP, 4x4) are applied by a sweep over the LDS tile.
 uint32_t op_need(const FOp& f)
 {
     switch (f.kind) {
-    case FK_PAIR: return 1u << f.a;
+    case FK_PAIR:
+    case FK_PAIRR:
+    case FK_PAIRX: return 1u << f.a;
     case FK_SWAP:
     case FK_QUAD: return (1u << f.a) | (1u << f.b);
     default: return 0u;
@@ -157,7 +160,7 @@ uint32_t pad_regs(uint32_t S, int tq, int rb, int keep)
 // Lane order: first up to kSwzBits lane bits with distinct residues mod
 // kSwzBits, scanning upwards (so a coalescing run 0..cb-1 of lane bits comes
 // first, in order), then the other lane bits ascending; register bits ascending.
-FLayout make_layout(uint32_t S, int tq, int rb)
+FLayout make_layout(uint32_t S, int tq, int rb, const int32_t* q)
 {
     FLayout L;
     memset(&L, 0, sizeof L);
@@ -176,14 +179,22 @@ FLayout make_layout(uint32_t S, int tq, int rb)
     int r = 0;
     for (int p = 0; p < tq; ++p)
         if ((S >> p) & 1u) L.pos[(tq - rb) + r++] = (uint8_t)p;
+    for (int i = 0; i < nl; ++i) {
+        L.lane_l[i] = (uint16_t)(1u << L.pos[i]);
+        L.lane_g[i] = 1ull << q[L.pos[i]];
+    }
+    for (int k = 0; k < rb; ++k) {
+        L.reg_l[k] = (uint16_t)(1u << L.pos[nl + k]);
+        L.reg_g[k] = 1ull << q[L.pos[nl + k]];
+    }
     return L;
 }
 
 int reg_index(uint32_t S, int p) { return popc(S & ((1u << p) - 1u)); }
 
 // Reorder one pass's ops into register runs and insert the layout changes.
-void plan_layouts(std::vector<FOp>& pass_ops, int tq, int rb, int cb, std::vector<FLayout>& lays, int& lay_begin,
-                  int& lay_end)
+void plan_layouts(std::vector<FOp>& pass_ops, int tq, int rb, int cb, const int32_t* q, std::vector<FLayout>& lays,
+                  int& lay_begin, int& lay_end)
 {
     const int keep = std::max(0, std::min(cb, tq - rb));
     const uint32_t lowmask = (1u << keep) - 1u;
@@ -218,7 +229,7 @@ void plan_layouts(std::vector<FOp>& pass_ops, int tq, int rb, int cb, std::vecto
     auto layout_of = [&](uint32_t S) {
         for (auto& e : seen)
             if (e.first == S) return e.second;
-        lays.push_back(make_layout(S, tq, rb));
+        lays.push_back(make_layout(S, tq, rb, q));
         seen.push_back({S, (int)lays.size() - 1});
         return (int)lays.size() - 1;
     };
@@ -244,7 +255,8 @@ void plan_layouts(std::vector<FOp>& pass_ops, int tq, int rb, int cb, std::vecto
         }
         for (int i : r.second) {
             FOp f = pass_ops[i];
-            f.ka = (int16_t)((op_need(f) & (1u << f.a)) ? reg_index(r.first, f.a) : 0);
+            if (f.kind == FK_DIAG) f.ka = (int16_t)(((r.first >> f.a) & 1u) ? reg_index(r.first, f.a) : -1);
+            else f.ka = (int16_t)((op_need(f) & (1u << f.a)) ? reg_index(r.first, f.a) : 0);
             f.kb = (int16_t)((f.kind == FK_SWAP || f.kind == FK_QUAD) ? reg_index(r.first, f.b) : 0);
             out.push_back(f);
         }
@@ -297,6 +309,7 @@ struct sv_batch_s {
     FCoefSpec* d_cspec;
     int n_cspec;
     double* d_coef;
+    float* d_coef_f;
     double* d_epart;
     double* d_gpart;
     int64_t* d_e_off;
@@ -333,7 +346,7 @@ void batch_release(sv_batch b)
     if (b->stream) (void)hipStreamSynchronize(b->stream);
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
-    void* ptrs[] = {b->d_psi, b->d_lam, b->d_circ, b->d_pass, b->d_ops, b->d_lays, b->d_segs, b->d_cspec, b->d_coef, b->d_epart, b->d_gpart, b->d_e_off, b->d_e_cnt, b->d_g_off, b->d_g_cnt,
+    void* ptrs[] = {b->d_psi, b->d_lam, b->d_circ, b->d_pass, b->d_ops, b->d_lays, b->d_segs, b->d_cspec, b->d_coef, b->d_coef_f, b->d_epart, b->d_gpart, b->d_e_off, b->d_e_cnt, b->d_g_off, b->d_g_cnt,
                     b->d_slot_scale, b->d_slot_val, b->d_csr_ptr, b->d_csr_col, b->d_params, b->d_expvals,
                     b->d_grads};
     for (void* p : ptrs)
@@ -345,7 +358,8 @@ void batch_release(sv_batch b)
 hipError_t enqueue_run(sv_batch b)
 {
     hipStream_t s = b->stream;
-    hipError_t e = launch_pass_coef(b->d_cspec, b->n_cspec, b->d_params, b->d_coef, s);
+    hipError_t e = launch_pass_coef(b->d_cspec, b->n_cspec, b->d_params, b->d_coef,
+                                    b->dtype == SV_C64 ? b->d_coef_f : nullptr, s);
     const std::vector<int64_t>& lf = b->level_first;
     for (size_t l = 0; l + 3 < lf.size() && e == hipSuccess; l += 3) {
         e = launch_pass_items(b->tb, b->dtype, PM_FWD, lf[l], lf[l + 1], b->threads, b->lds, s);
@@ -491,6 +505,7 @@ static sv_status compile_batch(const sv_batch_circuit* circuits, int n_circuits,
                     local[q] = k;
                     fp.q[k++] = q;
                 }
+            fp.free_mask = (n >= 64 ? ~0ull : ((1ull << n) - 1ull)) & ~pq[p];
             std::vector<FOp> pass_ops;
             for (int i : pops[p]) {
                 const BOp& o = ops[i];
@@ -512,12 +527,12 @@ static sv_status compile_batch(const sv_batch_circuit* circuits, int n_circuits,
                 f.coef = coef_total;
                 const double r = M_SQRT1_2;
                 switch (o.gate) {
-                case SV_X: { f.kind = FK_PAIR; double m[8] = {0, 0, 1, 0, 1, 0, 0, 0}; memcpy(cs.fixed, m, sizeof m); cs.nfixed = 8; coef_total += 8; break; }
+                case SV_X: { f.kind = FK_PAIRX; double m[8] = {0, 0, 1, 0, 1, 0, 0, 0}; memcpy(cs.fixed, m, sizeof m); cs.nfixed = 8; coef_total += 8; break; }
                 case SV_Y: { f.kind = FK_PAIR; double m[8] = {0, 0, 0, -1, 0, 1, 0, 0}; memcpy(cs.fixed, m, sizeof m); cs.nfixed = 8; coef_total += 8; break; }
-                case SV_H: { f.kind = FK_PAIR; double m[8] = {r, 0, r, 0, r, 0, -r, 0}; memcpy(cs.fixed, m, sizeof m); cs.nfixed = 8; coef_total += 8; break; }
+                case SV_H: { f.kind = FK_PAIRR; double m[8] = {r, 0, r, 0, r, 0, -r, 0}; memcpy(cs.fixed, m, sizeof m); cs.nfixed = 8; coef_total += 8; break; }
                 case SV_U2: { f.kind = FK_PAIR; memcpy(cs.fixed, o.mat.data(), 8 * sizeof(double)); cs.nfixed = 8; coef_total += 8; break; }
-                case SV_RX:
-                case SV_RY: f.kind = FK_PAIR; coef_total += 8; break;
+                case SV_RX: f.kind = FK_PAIR; coef_total += 8; break;
+                case SV_RY: f.kind = FK_PAIRR; coef_total += 8; break;
                 case SV_RZ: f.kind = FK_DIAG; coef_total += 4; break;
                 case SV_Z: { f.kind = FK_PHASE; f.cm |= 1u << f.a; cs.fixed[0] = -1; cs.nfixed = 2; coef_total += 2; break; }
                 case SV_S: { f.kind = FK_PHASE; f.cm |= 1u << f.a; cs.fixed[1] = 1; cs.nfixed = 2; coef_total += 2; break; }
@@ -530,7 +545,7 @@ static sv_status compile_batch(const sv_batch_circuit* circuits, int n_circuits,
                 pass_ops.push_back(f);
             }
             std::vector<FOp> fwd_ops = pass_ops;
-            if (fc.reg) plan_layouts(fwd_ops, tq, reg_bits, cb, lays, fp.lay_begin, fp.lay_end);
+            if (fc.reg) plan_layouts(fwd_ops, tq, reg_bits, cb, fp.q, lays, fp.lay_begin, fp.lay_end);
             fp.op_begin = (int)fops.size();
             fops.insert(fops.end(), fwd_ops.begin(), fwd_ops.end());
             fp.op_end = (int)fops.size();
@@ -540,7 +555,7 @@ static sv_status compile_batch(const sv_batch_circuit* circuits, int n_circuits,
             fp.rlay_end = fp.lay_end;
             if (with_grad && (fc.reg != fc.rreg || (fc.rreg && rreg_bits != reg_bits))) {
                 std::vector<FOp> rev_ops = pass_ops;
-                if (fc.rreg) plan_layouts(rev_ops, tq, rreg_bits, cb, lays, fp.rlay_begin, fp.rlay_end);
+                if (fc.rreg) plan_layouts(rev_ops, tq, rreg_bits, cb, fp.q, lays, fp.rlay_begin, fp.rlay_end);
                 fp.rop_begin = (int)fops.size();
                 fops.insert(fops.end(), rev_ops.begin(), rev_ops.end());
                 fp.rop_end = (int)fops.size();
@@ -762,6 +777,7 @@ sv_status sv_batch_create(const sv_batch_circuit* circuits, int n_circuits, sv_d
     if (e == hipSuccess) e = dev_upload(&b->d_csr_ptr, csr_ptr);
     if (e == hipSuccess) e = dev_upload(&b->d_csr_col, csr_col);
     if (e == hipSuccess) e = hipMalloc((void**)&b->d_coef, sizeof(double) * std::max(1, coef_total));
+    if (e == hipSuccess && dtype == SV_C64) e = hipMalloc((void**)&b->d_coef_f, sizeof(float) * std::max(1, coef_total));
     if (e == hipSuccess) e = hipMalloc((void**)&b->d_epart, sizeof(double) * std::max(1, e_total));
     if (e == hipSuccess) e = hipMalloc((void**)&b->d_gpart, sizeof(double) * std::max<int64_t>(1, g_total));
     if (e == hipSuccess) e = hipMalloc((void**)&b->d_slot_val, sizeof(double) * std::max<size_t>(1, slot_param.size()));
@@ -780,6 +796,7 @@ sv_status sv_batch_create(const sv_batch_circuit* circuits, int n_circuits, sv_d
     tb.lays = b->d_lays;
     tb.segs = b->d_segs;
     tb.coef = b->d_coef;
+    tb.coef_f = b->d_coef_f;
     tb.e_part = b->d_epart;
     tb.g_part = b->d_gpart;
     tb.n_items = n_items;

@@ -18,7 +18,12 @@ constexpr int kMaxPassThreads = 512;
 // residues mod kSwzBits hit distinct banks.
 constexpr int kSwzBits = 4;
 
-enum FusedKind : int32_t { FK_PAIR = 0, FK_DIAG = 1, FK_PHASE = 2, FK_SWAP = 3, FK_QUAD = 4, FK_LAYOUT = 5 };
+// FK_PAIR: complex 2x2 on a target; FK_PAIRR: real 2x2 (H, RY); FK_PAIRX: the
+// exchange of the pair (X).  All three keep the complex 2x2 in the coefficient
+// table, so the LDS-sweep form treats them alike.
+enum FusedKind : int32_t {
+    FK_PAIR = 0, FK_DIAG = 1, FK_PHASE = 2, FK_SWAP = 3, FK_QUAD = 4, FK_LAYOUT = 5, FK_PAIRR = 6, FK_PAIRX = 7
+};
 
 // One op of a pass, in tile-local bit positions.  FK_LAYOUT (register-tiled
 // passes only) re-distributes the tile: a = index of the layout that holds
@@ -30,14 +35,22 @@ struct FOp {
     int32_t coef;   // offset of the op's coefficients in the coefficient table (doubles)
     int32_t slot;   // gradient slot within the circuit, -1 if not parameterised
     int32_t gen;    // generator (GenKind) of a parameterised op
-    int16_t ka, kb; // register bits holding a and b in the current layout (register-tiled passes)
+    int16_t ka, kb; // register-tiled passes: register bit holding a for one-target pair ops;
+                    // for FK_DIAG the register bit of a, or -1 when a is a lane bit; kb unused
 };
 
 // A distribution of a tile over the threads of a workgroup: lane bit i of
 // the thread index is tile-local bit pos[i] (i < tq - rb), register bit r is
-// tile-local bit pos[tq - rb + r].
+// tile-local bit pos[tq - rb + r].  A layout belongs to one pass, so the
+// tile-local and global bit values are stored ready for use (zero past the
+// lane bits).
 struct FLayout {
     uint8_t pos[16];
+    uint16_t lane_l[16];  // 1 << pos[i] for lane bit i
+    uint16_t reg_l[4];    // 1 << pos[tq - rb + r]
+    uint32_t pad_;
+    uint64_t lane_g[16];  // global bit of lane bit i: 1 << q[pos[i]]
+    uint64_t reg_g[4];    // global bit of register bit r
 };
 
 // A pass has two op lists over the same ops: the forward list (planned for
@@ -49,6 +62,7 @@ struct FPass {
     int32_t lay_begin, lay_end;  // layouts a register-tiled forward pass loads in and ends in
     int32_t rop_begin, rop_end;
     int32_t rlay_begin, rlay_end;
+    uint64_t free_mask;  // global bits outside the tile (the tile index is deposited into them)
 };
 
 struct FCirc {
@@ -94,6 +108,7 @@ struct PassTables {
     const FLayout* lays;
     const FSeg* segs;
     const double* coef;
+    const float* coef_f;  // the same coefficients rounded to float (complex64 runs)
     double* e_part;
     double* g_part;
     int64_t n_items;
@@ -112,7 +127,8 @@ hipError_t pass_engine_prepare(int dtype, int reg_bits, int rreg_bits, size_t ld
 // Items [item_begin, item_end), all of stage kind `mode`, one workgroup per tile.
 hipError_t launch_pass_items(const PassTables& tb, int dtype, int mode, int64_t item_begin, int64_t item_end,
                              int threads, size_t lds_bytes, hipStream_t s);
-hipError_t launch_pass_coef(const FCoefSpec* spec, int n, const double* params, double* coef, hipStream_t s);
+hipError_t launch_pass_coef(const FCoefSpec* spec, int n, const double* params, double* coef, float* coef_f,
+                            hipStream_t s);
 hipError_t launch_pass_segsum(const double* part, const int64_t* off, const int* cnt, const double* scale, double* out,
                               int n_seg, hipStream_t s);
 hipError_t launch_pass_grad_csr(const double* slot_val, const int* rowptr, const int* cols, int n_params, double* grad,
