@@ -13,8 +13,8 @@ Also reported on the same JSON line:
   roofline      the dominant kernel's algorithmic bytes per launch over its
                 average HIP-event-timed launch duration, against 8 TB/s;
                 `traffic` is its measured HBM bytes per launch, read from the
-                committed PMC summary (null once the kernel sources differ
-                from the ones the counters were taken with);
+                committed PMC summary (null once the sweep kernels' sources
+                differ from the ones the counters were taken with);
   copy          a device-to-device copy of the state (the measured ceiling);
   cpu_baseline  the oracle on the host cores on a bounded sample;
   adjoint       24 qubits, 8 layers RY+RZ + CNOT ladder, 384 params,
@@ -180,17 +180,19 @@ def measure_copy(sv, torch, state):
     return 2 * state.tensor.numel() * state.tensor.element_size() / t / 1e9
 
 
+# The files the single-gate and reduction kernels are compiled from; the PMC
+# summary records their hash, so a change to any of them voids its traffic.
+SWEEP_KERNEL_SOURCES = ("k_gates.hip", "k_reduce.hip", "sv_core.h")
+
+
 def kernel_sources_sha256():
-    """SHA-256 over the HIP sources and the ABI header (file name + bytes, in
-    name order); the PMC summary records the value it was measured with."""
-    import glob
+    """SHA-256 over the sweep kernels' source files (file name + bytes, in
+    the order above); the PMC summary records the value it was measured with."""
     import hashlib
     h = hashlib.sha256()
-    files = sorted(glob.glob(os.path.join(ROOT, "paper_2508_13615_amd", "csrc", "*")))
-    files.append(os.path.join(ROOT, "include", "sv.h"))
-    for p in files:
-        h.update(os.path.basename(p).encode())
-        with open(p, "rb") as f:
+    for name in SWEEP_KERNEL_SOURCES:
+        h.update(name.encode())
+        with open(os.path.join(ROOT, "paper_2508_13615_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
 
