@@ -16,7 +16,11 @@ Also reported on the same JSON line:
                 committed PMC summary (null once the sweep kernels' sources
                 differ from the ones the counters were taken with);
   copy          a device-to-device copy of the state (the measured ceiling);
-  cpu_baseline  the oracle on the host cores on a bounded sample;
+  line_GBps     the same sweep in line-granular bytes (every 128-byte line
+                holding a touched amplitude is read and written whole);
+  sweep_c64     the same sweep on a complex64 state (secondary, one step);
+  cpu_baseline  the oracle on the host cores on a bounded sample (and on one
+                thread, in `single_thread`);
   adjoint       24 qubits, 8 layers RY+RZ + CNOT ladder, 384 params,
                 sum Z_i Z_{i+1}: one adjoint-gradient call vs parameter shift
                 (2 forward+expval runs per parameter) on the same GPU, on the
@@ -49,11 +53,11 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_of(sv, gate, tg, ct, general=False):
+def kernel_of(sv, gate, tg, ct, general=False, n=30, dtype="c128"):
     """The kernel instantiation libsv launches for a case (from sv_plan_info)."""
     if general:
-        return sv.plan_info(30, "c128", "GENERAL", tg)["kernel"]
-    return sv.plan_info(30, "c128", gate, tg, ct)["kernel"]
+        return sv.plan_info(n, dtype, "GENERAL", tg)["kernel"]
+    return sv.plan_info(n, dtype, gate, tg, ct)["kernel"]
 
 
 def touched_fraction(gate, nc):
@@ -63,6 +67,19 @@ def touched_fraction(gate, nc):
     if gate in ("Z", "SWAP"):
         return 0.5 / (2 ** nc)
     return 1.0
+
+
+def line_fraction(gate, tg, ct, line_bits):
+    """Fraction of the state's 128-byte lines holding an amplitude the gate
+    touches (a line spans the lowest `line_bits` qubits): a constrained bit
+    below the line size does not spare any line."""
+    hi = [q for q in ct if q >= line_bits]
+    f = 0.5 ** len(hi)
+    if gate == "Z":
+        f *= 0.5 if tg[0] >= line_bits else 1.0
+    elif gate == "SWAP":
+        f *= 0.5 if min(tg) >= line_bits else 1.0
+    return f
 
 
 def sweep_cases(n, rng, W):
@@ -117,7 +134,8 @@ def dense_of(case, oracle_free_matrix):
 
 
 def run_sweep(sv, torch, state, cases, denses, timed, rec, per_target):
-    """One step.  rec[key] accumulates (seconds, bytes, launches) per kernel."""
+    """One step.  rec[key] accumulates (seconds, algorithmic bytes, launches,
+    line-granular bytes) per kernel."""
     stream = torch.cuda.current_stream()
     ev = []
     for i, case in enumerate(cases):
@@ -139,27 +157,76 @@ def run_sweep(sv, torch, state, cases, denses, timed, rec, per_target):
     torch.cuda.synchronize()
     if not timed:
         return
-    S = (1 << state.n) * 16
+    eb = 16 if state.dtype == "c128" else 8
+    S = (1 << state.n) * eb
+    lb = 3 if eb == 16 else 4  # qubits spanned by a 128-byte line
     for case, e0, e1, e2, k in ev:
         g, tg, ct, p, m = case
         ts = e0.elapsed_time(e1) * 1e-3
         tgen = e1.elapsed_time(e2) * 1e-3
         b = 2 * S * touched_fraction(g, len(ct))
+        bl = 2 * S * line_fraction(g, tg, ct, lb)
         name = g if not ct else ({1: "CNOT", 2: "Toffoli"}[len(ct)] if g == "X" else g)
         qs = tuple(ct) + tuple(tg)
-        for key, t, byt in ((("specific", name, kernel_of(sv, g, tg, ct)), ts, b),
-                            (("general", name, kernel_of(sv, g, qs, (), True)), tgen, 2 * S)):
-            a = rec.setdefault(key, [0.0, 0.0, 0])
+        for key, t, byt, lbyt in ((("specific", name, kernel_of(sv, g, tg, ct, n=state.n, dtype=state.dtype)), ts, b, bl),
+                                  (("general", name, kernel_of(sv, g, qs, (), True, state.n, state.dtype)), tgen,
+                                   2 * S, 2 * S)):
+            a = rec.setdefault(key, [0.0, 0.0, 0, 0.0])
             a[0] += t
             a[1] += byt
             a[2] += 1
+            a[3] += lbyt
         if not ct and len(tg) == 1:
             pt = per_target.setdefault(g, {})
             pt.setdefault(tg[0], []).append((ts, tgen))
-    a = rec.setdefault(("expval", "sumZZ", "k_diag_obs_partial<double>"), [0.0, 0.0, 0])
+    a = rec.setdefault(("expval", "sumZZ", "k_diag_obs_partial<double>"), [0.0, 0.0, 0, 0.0])
     a[0] += e3.elapsed_time(e4) * 1e-3
     a[1] += S
     a[2] += 1
+    a[3] += S
+
+
+def summarize_sweep(rec, copy_gbps):
+    """Per class (specific / general), per kernel and whole-sweep figures from
+    run_sweep's records; GB/s are algorithmic, line_GBps line-granular."""
+    spec = {k: v for k, v in rec.items() if k[0] == "specific"}
+    gen_ = {k: v for k, v in rec.items() if k[0] == "general"}
+    t_spec = sum(v[0] for v in spec.values())
+    t_gen = sum(v[0] for v in gen_.values())
+    tot = {"gates_per_s": sum(v[2] for v in spec.values()) / t_spec,
+           "effective_GBps": sum(v[1] for v in spec.values()) / t_spec / 1e9,
+           "line_GBps": sum(v[3] for v in spec.values()) / t_spec / 1e9,
+           "general_gates_per_s": sum(v[2] for v in gen_.values()) / t_gen}
+    tot["effective_frac_of_8TBps"] = tot["effective_GBps"] / PEAK_GBPS
+    tot["line_frac_of_8TBps"] = tot["line_GBps"] / PEAK_GBPS
+    tot["effective_frac_of_copy"] = tot["effective_GBps"] / copy_gbps
+    per_class = {}
+    agg = {}
+    for (kind, name, kern), (tt, bb, cnt, lb) in rec.items():
+        a = agg.setdefault((name, kind), [0.0, 0.0, 0, set(), 0.0])
+        a[0] += tt
+        a[1] += bb
+        a[2] += cnt
+        a[3].add(kern)
+        a[4] += lb
+    for (name, kind), (tt, bb, cnt, kerns, lb) in sorted(agg.items()):
+        per_class.setdefault(name, {})[kind] = {
+            "kernels": sorted(kerns), "launches": cnt, "avg_ms": 1e3 * tt / cnt, "gates_per_s": cnt / tt,
+            "GBps": bb / tt / 1e9, "frac_of_8TBps": bb / tt / 1e9 / PEAK_GBPS, "frac_of_copy": bb / tt / 1e9 / copy_gbps,
+            "line_GBps": lb / tt / 1e9}
+    for name, d in per_class.items():
+        if "specific" in d and "general" in d:
+            d["speedup_specific_vs_general"] = d["general"]["avg_ms"] / d["specific"]["avg_ms"]
+    by_kernel = {}
+    for (kind, name, kern), (tt, bb, cnt, lb) in rec.items():
+        a = by_kernel.setdefault(kern, [0.0, 0.0, 0])
+        a[0] += tt
+        a[1] += bb
+        a[2] += cnt
+    per_kernel = {k: {"launches": c, "avg_ms": 1e3 * t / c, "GBps": by / t / 1e9, "frac_of_8TBps": by / t / 1e9 / PEAK_GBPS,
+                      "share_of_step_time": t / (t_spec + t_gen)}
+                  for k, (t, by, c) in sorted(by_kernel.items(), key=lambda kv: -kv[1][0])}
+    return tot, per_class, per_kernel, by_kernel
 
 
 def measure_copy(sv, torch, state):
@@ -462,6 +529,7 @@ def main():
     ap.add_argument("--qubits", type=int, default=30)
     ap.add_argument("--cpu-qubits", type=int, default=27)
     ap.add_argument("--skip-cpu-baseline", action="store_true")
+    ap.add_argument("--skip-c64-sweep", action="store_true", help="skip the secondary complex64 sweep (one step)")
     ap.add_argument("--skip-adjoint", action="store_true")
     ap.add_argument("--adjoint-qubits", type=int, default=24)
     ap.add_argument("--adjoint-layers", type=int, default=8)
@@ -511,37 +579,8 @@ def main():
     wall = time.perf_counter() - t0
     norm = state.norm2()
 
-    spec = {k: v for k, v in rec.items() if k[0] == "specific"}
-    gen_ = {k: v for k, v in rec.items() if k[0] == "general"}
-    t_spec = sum(v[0] for v in spec.values())
-    t_gen = sum(v[0] for v in gen_.values())
-    n_spec = sum(v[2] for v in spec.values())
-    b_spec = sum(v[1] for v in spec.values())
-    per_class = {}
-    agg = {}
-    for (kind, name, kern), (tt, bb, cnt) in rec.items():
-        a = agg.setdefault((name, kind), [0.0, 0.0, 0, set()])
-        a[0] += tt
-        a[1] += bb
-        a[2] += cnt
-        a[3].add(kern)
-    for (name, kind), (tt, bb, cnt, kerns) in sorted(agg.items()):
-        per_class.setdefault(name, {})[kind] = {
-            "kernels": sorted(kerns), "launches": cnt, "avg_ms": 1e3 * tt / cnt, "gates_per_s": cnt / tt,
-            "GBps": bb / tt / 1e9, "frac_of_8TBps": bb / tt / 1e9 / PEAK_GBPS}
-    for name, d in per_class.items():
-        if "specific" in d and "general" in d:
-            d["speedup_specific_vs_general"] = d["general"]["avg_ms"] / d["specific"]["avg_ms"]
+    tot, per_class, per_kernel, by_kernel = summarize_sweep(rec, copy_gbps)
     # dominant kernel: the instantiation with the largest total time
-    by_kernel = {}
-    for (kind, name, kern), (tt, bb, cnt) in rec.items():
-        a = by_kernel.setdefault(kern, [0.0, 0.0, 0])
-        a[0] += tt
-        a[1] += bb
-        a[2] += cnt
-    per_kernel = {k: {"launches": c, "avg_ms": 1e3 * t / c, "GBps": by / t / 1e9, "frac_of_8TBps": by / t / 1e9 / PEAK_GBPS,
-                      "share_of_step_time": t / (t_spec + t_gen)}
-                  for k, (t, by, c) in sorted(by_kernel.items(), key=lambda kv: -kv[1][0])}
     dom = max(by_kernel.items(), key=lambda kv: kv[1][0])
     dk, (dt_, db, dc) = dom
     achieved = db / dt_ / 1e9
@@ -553,7 +592,7 @@ def main():
         roof["traffic_over_algorithmic"] = roof["traffic"] / roof["algorithmic_bytes_per_launch"]
     out = {
         "metric": METRIC,
-        "value": n_spec / t_spec,
+        "value": tot["gates_per_s"],
         "unit": "gates/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -568,9 +607,12 @@ def main():
                                f"and general kernels", "qubits": n, "state_GiB": (1 << n) * 16 / 2**30,
                    "gate_classes": ["H", "X", "Z", "RZ", "RY", "U2", "CNOT", "SWAP", "U4", "Toffoli"],
                    "targets": f"0..{n - 1}", "second_qubits": [0, n // 2, n - 1], "cases_per_step": len(cases)},
-        "effective_GBps": b_spec / t_spec / 1e9,
-        "effective_frac_of_8TBps": b_spec / t_spec / 1e9 / PEAK_GBPS,
-        "general_gates_per_s": sum(v[2] for v in gen_.values()) / t_gen,
+        "effective_GBps": tot["effective_GBps"],
+        "effective_frac_of_8TBps": tot["effective_frac_of_8TBps"],
+        "effective_frac_of_copy": tot["effective_frac_of_copy"],
+        "line_GBps": tot["line_GBps"],
+        "line_frac_of_8TBps": tot["line_frac_of_8TBps"],
+        "general_gates_per_s": tot["general_gates_per_s"],
         "copy_GBps": copy_gbps,
         "per_class": per_class,
         "per_kernel": per_kernel,
@@ -583,6 +625,22 @@ def main():
     }
     del state, t
     torch.cuda.empty_cache()
+    if not args.skip_c64_sweep:
+        log(f"[bench] secondary: the same sweep on a {n}-qubit complex64 state, one step after one warm-up")
+        t = torch.randn(1 << n, dtype=torch.complex64, device="cuda", generator=gen)
+        t /= torch.linalg.vector_norm(t)
+        st64 = sv.State(n, "c64", tensor=t, basis=None)
+        rec64, pt64 = {}, {}
+        run_sweep(sv, torch, st64, cases, denses, False, rec64, pt64)
+        run_sweep(sv, torch, st64, cases, denses, True, rec64, pt64)
+        tot64, pc64, _, _ = summarize_sweep(rec64, copy_gbps)
+        out["sweep_c64"] = dict(tot64, state_GiB=(1 << n) * 8 / 2**30,
+                                per_class={k: {kind: {x: v[kind][x] for x in ("avg_ms", "GBps", "frac_of_8TBps", "line_GBps")}
+                                               for kind in v if kind in ("specific", "general")}
+                                           for k, v in pc64.items()})
+        del st64, t
+        torch.cuda.empty_cache()
+        log("[bench] complex64 sweep done")
     if not args.skip_adjoint:
         log(f"[bench] adjoint vs parameter shift at {args.adjoint_qubits} qubits")
         out["adjoint"] = adjoint_compare(sv, torch, args.adjoint_qubits, args.adjoint_layers, args.ps_params,
@@ -599,6 +657,14 @@ def main():
     if not args.skip_cpu_baseline:
         log(f"[bench] oracle CPU baseline at {args.cpu_qubits} qubits")
         out["cpu_baseline"] = cpu_baseline(args.cpu_qubits, n)
+        # the same oracle on one host thread (separate process: OpenMP's thread
+        # count is fixed when the oracle library loads), on a 24-qubit sample
+        import subprocess
+        r = subprocess.run([sys.executable, "-c", "import json, bench; print(json.dumps(bench.cpu_baseline(24, %d, 5.0)))" % n],
+                           cwd=ROOT, env=dict(os.environ, OMP_NUM_THREADS="1"), capture_output=True, text=True)
+        if r.returncode == 0:
+            one = json.loads(r.stdout.strip().splitlines()[-1])
+            out["cpu_baseline"]["single_thread"] = {"value": one["value"], "cores": one["cores"], "sample": one["sample"]}
     print(json.dumps(out), flush=True)
 
 
