@@ -29,7 +29,8 @@ Also reported on the same JSON line:
                 batches of 128 shifted circuits per launch);
   batch         256 circuits of 14..22 qubits, forward + gradient in one
                 graph launch, vs the same circuits one after another;
-  circuits32    32-qubit HEA (10 layers) and QFT on the fused engine.
+  circuits32    32-qubit HEA (10 layers), QFT and universal circuit on the
+                fused engine.
 Progress lines go to stderr; stdout carries only the JSON line.
 """
 from __future__ import annotations
@@ -492,16 +493,18 @@ def config5(sv, torch, reps, sequential):
 
 
 def config3(sv, torch, n, layers, reps):
-    """32-qubit HEA (10 layers RY+RZ, CNOT ladder, from |0..0>) and QFT of a
-    random basis state, forward + sum Z on the fused engine, both dtypes.
-    The complex64 error is taken against the complex128 GPU result (itself
+    """32-qubit HEA (10 layers RY+RZ, CNOT ladder, from |0..0>), QFT of a
+    random basis state and the universal circuit (2 n^2 gates after an H on
+    every qubit), forward + sum Z on the fused engine, both dtypes.  The
+    complex64 error is taken against the complex128 GPU result (itself
     checked against the fp64 oracle at 20 qubits by the GPU tests)."""
     import numpy as np
     import workloads as W
     x = W.random_basis_index(n, 1004)
     prep = [W.Op("X", (), (q,)) for q in range(n) if (x >> q) & 1]
     jobs = {"hea": (W.hea_ops(n, layers), W.uniform_angles(W.hea_n_params(n, layers), 1003)),
-            "qft": (prep + W.qft_ops(n), np.zeros(0))}
+            "qft": (prep + W.qft_ops(n), np.zeros(0)),
+            "universal": ([W.Op("H", (), (q,)) for q in range(n)] + W.universal_ops(n), np.zeros(0))}
     out = {"qubits": n, "hea_layers": layers, "qft_basis_index": x}
     for name, (ops, th) in jobs.items():
         for dt in ("c128", "c64"):
@@ -513,7 +516,7 @@ def config3(sv, torch, n, layers, reps):
 
             t = _timed(torch, run, reps)
             info = b.info()
-            out[f"{name}_{dt}"] = {"s": t, "gates": len(ops), "passes": info["passes"],
+            out[f"{name}_{dt}"] = {"s": t, "gates": len(ops), "gates_per_s": len(ops) / t, "passes": info["passes"],
                                    "algorithmic_GBps": info["pass_bytes"] / t / 1e9, "expval_sum_z": res["e"]}
             del b
             torch.cuda.empty_cache()

@@ -1085,27 +1085,78 @@ k_pass_rev(PassTables tb, int64_t item_begin, int64_t item_end)
     }
 }
 
+// The 2x2 (row-major, interleaved) of a one-target gate: rotations from the
+// parameter, fixed gates from fixed[0..7].
+__device__ void gate2x2(const FCoefSpec& f, const double* __restrict__ params, double* u)
+{
+    const double th = f.pidx >= 0 ? params[f.pidx] : f.value;
+    const double ch = cos(th / 2), sh = sin(th / 2);
+    switch (f.gate) {
+    case SV_RX: u[0] = ch; u[1] = 0; u[2] = 0; u[3] = -sh; u[4] = 0; u[5] = -sh; u[6] = ch; u[7] = 0; break;
+    case SV_RY: u[0] = ch; u[1] = 0; u[2] = -sh; u[3] = 0; u[4] = sh; u[5] = 0; u[6] = ch; u[7] = 0; break;
+    case SV_RZ: u[0] = ch; u[1] = -sh; u[2] = 0; u[3] = 0; u[4] = 0; u[5] = 0; u[6] = ch; u[7] = sh; break;
+    case SV_PHASE: u[0] = 1; u[1] = 0; u[2] = 0; u[3] = 0; u[4] = 0; u[5] = 0; u[6] = cos(th); u[7] = sin(th); break;
+    default:
+        for (int k = 0; k < 8; ++k) u[k] = f.fixed[k];
+        break;
+    }
+}
+
 // One thread per op: gate coefficients from the parameters, in double and
 // (if coef_f is set) rounded once to float for complex64 runs.
-__global__ void k_pass_coef(const FCoefSpec* __restrict__ spec, int n, const double* __restrict__ params,
-                            double* __restrict__ coef, float* __restrict__ coef_f)
+__global__ void k_pass_coef(const FCoefSpec* __restrict__ spec, int n, const FCoefSpec* __restrict__ factors,
+                            const double* __restrict__ params, double* __restrict__ coef, float* __restrict__ coef_f)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const FCoefSpec s = spec[i];
     double* c = coef + s.coef;
-    const double th = s.pidx >= 0 ? params[s.pidx] : s.value;
-    const double ch = cos(th / 2), sh = sin(th / 2);
     int cnt;
-    switch (s.gate) {
-    case SV_RX: c[0] = ch; c[1] = 0; c[2] = 0; c[3] = -sh; c[4] = 0; c[5] = -sh; c[6] = ch; c[7] = 0; cnt = 8; break;
-    case SV_RY: c[0] = ch; c[1] = 0; c[2] = -sh; c[3] = 0; c[4] = sh; c[5] = 0; c[6] = ch; c[7] = 0; cnt = 8; break;
-    case SV_RZ: c[0] = ch; c[1] = -sh; c[2] = ch; c[3] = sh; cnt = 4; break;
-    case SV_PHASE: c[0] = cos(th); c[1] = sin(th); cnt = 2; break;
-    default:
-        for (int k = 0; k < s.nfixed; ++k) c[k] = s.fixed[k];
-        cnt = s.nfixed;
-        break;
+    if (s.nfactor > 0) {
+        // M = G_last ... G_first
+        double m[8] = {1, 0, 0, 0, 0, 0, 1, 0};
+        for (int k = 0; k < s.nfactor; ++k) {
+            double g[8], r[8];
+            gate2x2(factors[s.factor_begin + k], params, g);
+#pragma unroll
+            for (int row = 0; row < 2; ++row)
+#pragma unroll
+                for (int col = 0; col < 2; ++col) {
+                    // r[row][col] = sum_t g[row][t] * m[t][col]
+                    double re = 0, im = 0;
+#pragma unroll
+                    for (int t = 0; t < 2; ++t) {
+                        const double gr = g[2 * (2 * row + t)], gi = g[2 * (2 * row + t) + 1];
+                        const double mr = m[2 * (2 * t + col)], mi = m[2 * (2 * t + col) + 1];
+                        re += gr * mr - gi * mi;
+                        im += gr * mi + gi * mr;
+                    }
+                    r[2 * (2 * row + col)] = re;
+                    r[2 * (2 * row + col) + 1] = im;
+                }
+#pragma unroll
+            for (int k2 = 0; k2 < 8; ++k2) m[k2] = r[k2];
+        }
+        if (s.out_diag) {
+            c[0] = m[0]; c[1] = m[1]; c[2] = m[6]; c[3] = m[7];
+            cnt = 4;
+        } else {
+            for (int k = 0; k < 8; ++k) c[k] = m[k];
+            cnt = 8;
+        }
+    } else {
+        const double th = s.pidx >= 0 ? params[s.pidx] : s.value;
+        const double ch = cos(th / 2), sh = sin(th / 2);
+        switch (s.gate) {
+        case SV_RX: c[0] = ch; c[1] = 0; c[2] = 0; c[3] = -sh; c[4] = 0; c[5] = -sh; c[6] = ch; c[7] = 0; cnt = 8; break;
+        case SV_RY: c[0] = ch; c[1] = 0; c[2] = -sh; c[3] = 0; c[4] = sh; c[5] = 0; c[6] = ch; c[7] = 0; cnt = 8; break;
+        case SV_RZ: c[0] = ch; c[1] = -sh; c[2] = ch; c[3] = sh; cnt = 4; break;
+        case SV_PHASE: c[0] = cos(th); c[1] = sin(th); cnt = 2; break;
+        default:
+            for (int k = 0; k < s.nfixed; ++k) c[k] = s.fixed[k];
+            cnt = s.nfixed;
+            break;
+        }
     }
     if (coef_f)
         for (int k = 0; k < cnt; ++k) coef_f[s.coef + k] = (float)c[k];
@@ -1218,11 +1269,11 @@ hipError_t launch_pass_items(const PassTables& tb, int dtype, int mode, int64_t 
     return hipGetLastError();
 }
 
-hipError_t launch_pass_coef(const FCoefSpec* spec, int n, const double* params, double* coef, float* coef_f,
-                            hipStream_t s)
+hipError_t launch_pass_coef(const FCoefSpec* spec, int n, const FCoefSpec* factors, const double* params,
+                            double* coef, float* coef_f, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_pass_coef, dim3((n + 127) / 128), dim3(128), 0, s, spec, n, params, coef, coef_f);
+    hipLaunchKernelGGL(k_pass_coef, dim3((n + 127) / 128), dim3(128), 0, s, spec, n, factors, params, coef, coef_f);
     return hipGetLastError();
 }
 

@@ -272,6 +272,106 @@ void plan_layouts(std::vector<FOp>& pass_ops, int tq, int rb, int cb, const int3
     pass_ops.swap(out);
 }
 
+bool diag_gate(int g) { return g == SV_RZ || g == SV_PHASE || g == SV_Z || g == SV_S || g == SV_T; }
+bool real_gate(int g) { return g == SV_RY || g == SV_H || g == SV_X || g == SV_Z; }
+bool one_target_kind(int k) { return k == FK_PAIR || k == FK_PAIRR || k == FK_PAIRX || k == FK_DIAG || k == FK_PHASE; }
+
+// Factor entry of a one-target gate: rotations are evaluated from their
+// parameter on the device, fixed gates carry their full 2x2.
+FCoefSpec factor_of(const BOp& o, int param_base)
+{
+    FCoefSpec f;
+    memset(&f, 0, sizeof f);
+    f.gate = o.gate;
+    f.pidx = o.pidx >= 0 ? param_base + o.pidx : -1;
+    f.value = o.value;
+    const double r = M_SQRT1_2;
+    double m[8] = {1, 0, 0, 0, 0, 0, 1, 0};
+    switch (o.gate) {
+    case SV_X: { const double x[8] = {0, 0, 1, 0, 1, 0, 0, 0}; memcpy(m, x, sizeof m); break; }
+    case SV_Y: { const double x[8] = {0, 0, 0, -1, 0, 1, 0, 0}; memcpy(m, x, sizeof m); break; }
+    case SV_H: { const double x[8] = {r, 0, r, 0, r, 0, -r, 0}; memcpy(m, x, sizeof m); break; }
+    case SV_U2: memcpy(m, o.mat.data(), sizeof m); break;
+    case SV_Z: m[6] = -1; break;
+    case SV_S: m[6] = 0; m[7] = 1; break;
+    case SV_T: m[6] = cos(M_PI / 4); m[7] = sin(M_PI / 4); break;
+    default: break;  // rotations: evaluated on the device
+    }
+    memcpy(f.fixed, m, sizeof m);
+    return f;
+}
+
+// Forward-list gate fusion: a one-target op joins the previous op on the same
+// target with the same controls when no op in between touches any of their
+// qubits (ops on disjoint qubits commute).  A group of more than one op
+// becomes one op whose coefficients are the product of its gates (evaluated
+// on the device from the parameters).  Reverse passes keep the ops unfused:
+// each parameterised op needs its own gradient partial.
+std::vector<FOp> fuse_forward(const std::vector<FOp>& ops, const std::vector<int>& src, const std::vector<BOp>& bops,
+                              int param_base, std::vector<FCoefSpec>& cspec, std::vector<FCoefSpec>& cfac,
+                              int& coef_total)
+{
+    struct Grp {
+        FOp op;
+        uint32_t ctrl;
+        bool fusable;
+        std::vector<int> members;  // indices into bops
+    };
+    std::vector<Grp> g;
+    int last[32];
+    for (int& x : last) x = -1;
+    for (size_t i = 0; i < ops.size(); ++i) {
+        const FOp& f = ops[i];
+        const bool fus = one_target_kind(f.kind);
+        const uint32_t ctrl = f.kind == FK_PHASE ? (f.cm & ~(1u << f.a)) : f.cm;
+        uint32_t touch = f.cm | (1u << f.a);
+        if (f.kind == FK_SWAP || f.kind == FK_QUAD) touch |= 1u << f.b;
+        if (fus) {
+            const int c = last[f.a];
+            bool ok = c >= 0 && g[c].fusable && g[c].op.a == f.a && g[c].ctrl == ctrl;
+            for (int q = 0; ok && q < 32; ++q)
+                if ((touch >> q) & 1u) ok = last[q] == c;
+            if (ok) {
+                g[c].members.push_back(src[i]);
+                continue;
+            }
+        }
+        g.push_back({f, ctrl, fus, {src[i]}});
+        for (int q = 0; q < 32; ++q)
+            if ((touch >> q) & 1u) last[q] = (int)g.size() - 1;
+    }
+    std::vector<FOp> out;
+    for (Grp& gr : g) {
+        if (gr.members.size() == 1) {
+            out.push_back(gr.op);
+            continue;
+        }
+        bool all_diag = true, all_real = true;
+        for (int m : gr.members) {
+            all_diag = all_diag && diag_gate(bops[m].gate);
+            all_real = all_real && real_gate(bops[m].gate);
+        }
+        FOp f = gr.op;
+        f.kind = all_diag ? FK_DIAG : (all_real ? FK_PAIRR : FK_PAIR);
+        f.cm = gr.ctrl;
+        f.slot = -1;
+        f.coef = coef_total;
+        FCoefSpec cs;
+        memset(&cs, 0, sizeof cs);
+        cs.gate = SV_I;
+        cs.pidx = -1;
+        cs.coef = coef_total;
+        cs.nfactor = (int)gr.members.size();
+        cs.factor_begin = (int)cfac.size();
+        cs.out_diag = all_diag ? 1 : 0;
+        for (int m : gr.members) cfac.push_back(factor_of(bops[m], param_base));
+        cspec.push_back(cs);
+        coef_total += all_diag ? 4 : 8;
+        out.push_back(f);
+    }
+    return out;
+}
+
 }  // namespace
 
 struct sv_batch_s {
@@ -307,6 +407,7 @@ struct sv_batch_s {
     FLayout* d_lays;
     FSeg* d_segs;
     FCoefSpec* d_cspec;
+    FCoefSpec* d_cfac;
     int n_cspec;
     double* d_coef;
     float* d_coef_f;
@@ -346,7 +447,7 @@ void batch_release(sv_batch b)
     if (b->stream) (void)hipStreamSynchronize(b->stream);
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
-    void* ptrs[] = {b->d_psi, b->d_lam, b->d_circ, b->d_pass, b->d_ops, b->d_lays, b->d_segs, b->d_cspec, b->d_coef, b->d_coef_f, b->d_epart, b->d_gpart, b->d_e_off, b->d_e_cnt, b->d_g_off, b->d_g_cnt,
+    void* ptrs[] = {b->d_psi, b->d_lam, b->d_circ, b->d_pass, b->d_ops, b->d_lays, b->d_segs, b->d_cspec, b->d_cfac, b->d_coef, b->d_coef_f, b->d_epart, b->d_gpart, b->d_e_off, b->d_e_cnt, b->d_g_off, b->d_g_cnt,
                     b->d_slot_scale, b->d_slot_val, b->d_csr_ptr, b->d_csr_col, b->d_params, b->d_expvals,
                     b->d_grads};
     for (void* p : ptrs)
@@ -358,7 +459,7 @@ void batch_release(sv_batch b)
 hipError_t enqueue_run(sv_batch b)
 {
     hipStream_t s = b->stream;
-    hipError_t e = launch_pass_coef(b->d_cspec, b->n_cspec, b->d_params, b->d_coef,
+    hipError_t e = launch_pass_coef(b->d_cspec, b->n_cspec, b->d_cfac, b->d_params, b->d_coef,
                                     b->dtype == SV_C64 ? b->d_coef_f : nullptr, s);
     const std::vector<int64_t>& lf = b->level_first;
     for (size_t l = 0; l + 3 < lf.size() && e == hipSuccess; l += 3) {
@@ -392,7 +493,7 @@ struct HostTables {
     std::vector<FPass> passes;
     std::vector<FOp> fops;
     std::vector<FLayout> lays;
-    std::vector<FCoefSpec> cspec;
+    std::vector<FCoefSpec> cspec, cfac;
     std::vector<double> slot_scale;
     std::vector<int> slot_param;
     std::vector<int64_t> g_off, e_off, level_first;
@@ -428,7 +529,7 @@ static sv_status compile_batch(const sv_batch_circuit* circuits, int n_circuits,
     std::vector<FPass> passes;
     std::vector<FOp> fops;
     std::vector<FLayout> lays;
-    std::vector<FCoefSpec> cspec;
+    std::vector<FCoefSpec> cspec, cfac;
     std::vector<double> slot_scale;
     std::vector<int> slot_param;  // global parameter of each global slot
     std::vector<int64_t> g_off;
@@ -507,6 +608,7 @@ static sv_status compile_batch(const sv_batch_circuit* circuits, int n_circuits,
                 }
             fp.free_mask = (n >= 64 ? ~0ull : ((1ull << n) - 1ull)) & ~pq[p];
             std::vector<FOp> pass_ops;
+            std::vector<int> pass_src;
             for (int i : pops[p]) {
                 const BOp& o = ops[i];
                 FOp f;
@@ -543,8 +645,10 @@ static sv_status compile_batch(const sv_batch_circuit* circuits, int n_circuits,
                 }
                 if (o.gate != SV_SWAP) cspec.push_back(cs);
                 pass_ops.push_back(f);
+                pass_src.push_back(i);
             }
-            std::vector<FOp> fwd_ops = pass_ops;
+            std::vector<FOp> fwd_ops = fuse_forward(pass_ops, pass_src, ops, n_params, cspec, cfac, coef_total);
+            const bool fused = fwd_ops.size() != pass_ops.size();
             if (fc.reg) plan_layouts(fwd_ops, tq, reg_bits, cb, fp.q, lays, fp.lay_begin, fp.lay_end);
             fp.op_begin = (int)fops.size();
             fops.insert(fops.end(), fwd_ops.begin(), fwd_ops.end());
@@ -553,7 +657,7 @@ static sv_status compile_batch(const sv_batch_circuit* circuits, int n_circuits,
             fp.rop_end = fp.op_end;
             fp.rlay_begin = fp.lay_begin;
             fp.rlay_end = fp.lay_end;
-            if (with_grad && (fc.reg != fc.rreg || (fc.rreg && rreg_bits != reg_bits))) {
+            if (with_grad && (fused || fc.reg != fc.rreg || (fc.rreg && rreg_bits != reg_bits))) {
                 std::vector<FOp> rev_ops = pass_ops;
                 if (fc.rreg) plan_layouts(rev_ops, tq, rreg_bits, cb, fp.q, lays, fp.rlay_begin, fp.rlay_end);
                 fp.rop_begin = (int)fops.size();
@@ -644,6 +748,7 @@ static sv_status compile_batch(const sv_batch_circuit* circuits, int n_circuits,
     H.fops = std::move(fops);
     H.lays = std::move(lays);
     H.cspec = std::move(cspec);
+    H.cfac = std::move(cfac);
     H.slot_scale = std::move(slot_scale);
     H.slot_param = std::move(slot_param);
     H.g_off = std::move(g_off);
@@ -769,6 +874,7 @@ sv_status sv_batch_create(const sv_batch_circuit* circuits, int n_circuits, sv_d
     if (e == hipSuccess) e = dev_upload(&b->d_lays, H.lays);
     if (e == hipSuccess) e = dev_upload(&b->d_segs, segs);
     if (e == hipSuccess) e = dev_upload(&b->d_cspec, cspec);
+    if (e == hipSuccess) e = dev_upload(&b->d_cfac, H.cfac);
     if (e == hipSuccess) e = dev_upload(&b->d_e_off, e_off);
     if (e == hipSuccess) e = dev_upload(&b->d_e_cnt, e_cnt);
     if (e == hipSuccess) e = dev_upload(&b->d_g_off, g_off);

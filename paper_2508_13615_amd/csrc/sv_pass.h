@@ -92,6 +92,12 @@ struct FSeg {
 };
 
 // Per-op coefficient recipe (evaluated on the device from the parameters).
+// A fused op (several one-target gates on the same target and controls in a
+// row, forward passes only) has nfactor > 0: its coefficients are the
+// product of the factor gates' 2x2 matrices, factors [factor_begin,
+// factor_begin + nfactor) of the factor table in the order applied; each
+// factor is an FCoefSpec whose fixed[0..7] holds the full 2x2 of a fixed gate.
+// out_diag = 1 writes the product's diagonal only (d0, d1), else all 8 values.
 struct FCoefSpec {
     int32_t gate;
     int32_t pidx;    // global parameter index, -1 = fixed angle `value`
@@ -99,6 +105,8 @@ struct FCoefSpec {
     int32_t nfixed;  // fixed coefficient count (non-rotation gates)
     double value;
     double fixed[32];
+    int32_t nfactor, factor_begin;
+    int32_t out_diag, pad_;
 };
 
 struct PassTables {
@@ -127,8 +135,8 @@ hipError_t pass_engine_prepare(int dtype, int reg_bits, int rreg_bits, size_t ld
 // Items [item_begin, item_end), all of stage kind `mode`, one workgroup per tile.
 hipError_t launch_pass_items(const PassTables& tb, int dtype, int mode, int64_t item_begin, int64_t item_end,
                              int threads, size_t lds_bytes, hipStream_t s);
-hipError_t launch_pass_coef(const FCoefSpec* spec, int n, const double* params, double* coef, float* coef_f,
-                            hipStream_t s);
+hipError_t launch_pass_coef(const FCoefSpec* spec, int n, const FCoefSpec* factors, const double* params,
+                            double* coef, float* coef_f, hipStream_t s);
 hipError_t launch_pass_segsum(const double* part, const int64_t* off, const int* cnt, const double* scale, double* out,
                               int n_seg, hipStream_t s);
 hipError_t launch_pass_grad_csr(const double* slot_val, const int* rowptr, const int* cols, int n_params, double* grad,

@@ -102,8 +102,43 @@ static double ref_energy(int n, const std::vector<sv_op>& ops, const std::vector
 }
 
 // ---------------- emulation of the kernels -------------------------------
-static void coef_eval(const FCoefSpec& s, const double* params, double* c)
+static int errors = 0;
+#define CHECK(c, ...) do { if (!(c)) { ++errors; if (errors < 20) { printf("FAIL %s:%d ", __FILE__, __LINE__); printf(__VA_ARGS__); printf("\n"); } } } while (0)
+
+static void gate2x2_h(const FCoefSpec& f, const double* params, cd u[4])
 {
+    const double th = f.pidx >= 0 ? params[f.pidx] : f.value;
+    const double ch = cos(th / 2), sh = sin(th / 2);
+    switch (f.gate) {
+    case SV_RX: u[0] = ch; u[1] = cd(0, -sh); u[2] = cd(0, -sh); u[3] = ch; break;
+    case SV_RY: u[0] = ch; u[1] = -sh; u[2] = sh; u[3] = ch; break;
+    case SV_RZ: u[0] = cd(ch, -sh); u[1] = 0; u[2] = 0; u[3] = cd(ch, sh); break;
+    case SV_PHASE: u[0] = 1; u[1] = 0; u[2] = 0; u[3] = std::polar(1.0, th); break;
+    default: for (int k = 0; k < 4; ++k) u[k] = cd(f.fixed[2 * k], f.fixed[2 * k + 1]); break;
+    }
+}
+
+static void coef_eval(const FCoefSpec& s, const std::vector<FCoefSpec>& fac, const double* params, double* c)
+{
+    if (s.nfactor > 0) {
+        cd m[4] = {1, 0, 0, 1};
+        for (int k = 0; k < s.nfactor; ++k) {
+            cd g[4], r[4];
+            gate2x2_h(fac[s.factor_begin + k], params, g);
+            r[0] = g[0] * m[0] + g[1] * m[2];
+            r[1] = g[0] * m[1] + g[1] * m[3];
+            r[2] = g[2] * m[0] + g[3] * m[2];
+            r[3] = g[2] * m[1] + g[3] * m[3];
+            for (int q = 0; q < 4; ++q) m[q] = r[q];
+        }
+        if (s.out_diag) {
+            CHECK(std::abs(m[1]) == 0 && std::abs(m[2]) == 0, "diagonal fusion has off-diagonal terms");
+            c[0] = m[0].real(); c[1] = m[0].imag(); c[2] = m[3].real(); c[3] = m[3].imag();
+        } else {
+            for (int q = 0; q < 4; ++q) { c[2 * q] = m[q].real(); c[2 * q + 1] = m[q].imag(); }
+        }
+        return;
+    }
     const double th = s.pidx >= 0 ? params[s.pidx] : s.value;
     const double ch = cos(th / 2), sh = sin(th / 2);
     switch (s.gate) {
@@ -157,8 +192,6 @@ static bool check_layout(const FLayout& L, int tq, int rb = -1, const int32_t* q
     return true;
 }
 
-static int errors = 0;
-#define CHECK(c, ...) do { if (!(c)) { ++errors; if (errors < 20) { printf("FAIL %s:%d ", __FILE__, __LINE__); printf(__VA_ARGS__); printf("\n"); } } } while (0)
 
 static void reg_apply_h(cd* v, int rb, const FOp& op, const double* cf, bool dagger, uint32_t tl, const uint32_t* off,
                         const FLayout& L, int tq)
@@ -286,7 +319,7 @@ static void run_emu(Emu& E, const std::vector<double>& params)
 {
     HostTables& H = E.H;
     E.coef.assign(std::max(1, H.coef_total), 0.0);
-    for (auto& s : H.cspec) coef_eval(s, params.data(), E.coef.data() + s.coef);
+    for (auto& s : H.cspec) coef_eval(s, H.cfac, params.data(), E.coef.data() + s.coef);
     const int nc = (int)H.circs.size();
     E.psi.assign(nc, {});
     E.lam.assign(nc, {});

@@ -171,3 +171,23 @@ def test_config3_circuits_at_20_qubits_vs_oracle():
             print(f"{name} n={n} {dtype}: max |psi - psi_oracle| = {err:.2e}, passes {b.info()['passes']}", flush=True)
             assert err <= tol, (name, dtype, err)
             assert abs(e[0] - oracle.expval_obs(ref, W.sum_z(n))) <= tol * n
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_universal_circuit_fused_and_op_by_op_vs_oracle(dtype):
+    """The universal circuit (2 n^2 gates: CNOTs and Z rotations) after an H on
+    every qubit, at 10 qubits: fused engine and op-by-op kernels against the
+    oracle on the same op list (its gate order is one reading of the paper;
+    the comparison pins the kernels, not that reading)."""
+    n = 10
+    ops = [W.Op("H", (), (q,)) for q in range(n)] + W.universal_ops(n)
+    ref = oracle.run_circuit(oracle.zero_state(n), ops, np.zeros(0))
+    b = sv.Batch([(n, ops, 0, "sum_zz")], dtype, with_grad=False)
+    e, _ = b.run([])
+    err = float(np.max(np.abs(b.state(0).astype(np.complex128) - ref)))
+    assert err <= 4 * TOL[dtype], err
+    assert abs(e[0] - oracle.expval_obs(ref, W.sum_zz(n))) <= 4 * TOL[dtype] * n
+    st = sv.State(n, dtype)
+    sv.Circuit(n, ops, 0).apply(st)
+    err2 = float(np.max(np.abs(st.numpy().astype(np.complex128) - ref)))
+    assert err2 <= 4 * TOL[dtype], err2
