@@ -332,6 +332,18 @@ class Batch:
         check(lib.sv_batch_copy_state(self.handle, i, ctypes.c_void_p(out.ctypes.data), out.nbytes))
         return out
 
+    def state_tensor(self, i: int) -> torch.Tensor:
+        """Zero-copy torch view of circuit i's device state (valid while the
+        batch lives; the next run overwrites it)."""
+        ptr, nq = ctypes.c_void_p(), ctypes.c_int()
+        check(lib.sv_batch_state(self.handle, i, ctypes.byref(ptr), ctypes.byref(nq)))
+
+        class _View:
+            __cuda_array_interface__ = {"shape": (1 << nq.value,), "typestr": "<c16" if self.dtype == "c128" else "<c8",
+                                        "data": (ptr.value, False), "version": 3}
+
+        return torch.as_tensor(_View(), device="cuda")
+
 
 class AdjointExpval(torch.autograd.Function):
     """E(params) = <psi|O|psi> with psi = U(params)|0...0>, differentiated by the

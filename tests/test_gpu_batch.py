@@ -191,3 +191,33 @@ def test_universal_circuit_fused_and_op_by_op_vs_oracle(dtype):
     sv.Circuit(n, ops, 0).apply(st)
     err2 = float(np.max(np.abs(st.numpy().astype(np.complex128) - ref)))
     assert err2 <= 4 * TOL[dtype], err2
+
+
+@pytest.mark.parametrize("dtype,tol", [("c128", 1e-10), ("c64", 1e-4)])
+def test_batch_tiny_and_empty_circuits_with_gradients_device_io(dtype, tol):
+    """1- and 2-qubit circuits (tiles below a register tile: the LDS-sweep
+    form), a circuit with no ops, and a larger one in the same batch; inputs
+    and outputs in device memory (run_device)."""
+    import torch
+    rng = np.random.default_rng(5505)
+    circs = [(1, [W.Op("RY", (), (0,), 0), W.Op("RZ", (), (0,), 1)], 2, "sum_z"),
+             (2, [W.Op("RX", (), (1,), 0), W.Op("X", (1,), (0,)), W.Op("PHASE", (0,), (1,), 1)], 2, "sum_zz"),
+             (3, [], 0, "sum_z"),
+             (8, W.hea_ops(8, 2), W.hea_n_params(8, 2), "sum_zz")]
+    params = [rng.uniform(0, 2 * math.pi, size=c[2]) for c in circs]
+    b = sv.Batch(circs, dtype, with_grad=True)
+    p = torch.as_tensor(np.concatenate(params), device="cuda", dtype=torch.float64)
+    e = torch.zeros(len(circs), device="cuda", dtype=torch.float64)
+    g = torch.zeros(max(1, sum(c[2] for c in circs)), device="cuda", dtype=torch.float64)
+    b.run_device(p, e, g)
+    e, g = e.cpu().numpy(), g.cpu().numpy()
+    off = 0
+    for i, (n, ops, npar, obs) in enumerate(circs):
+        terms = obs_terms(obs, n)
+        e_ref = oracle.energy(n, ops, params[i], terms)
+        assert abs(e[i] - e_ref) <= tol, (i, e[i], e_ref)
+        if npar:
+            g_ref = oracle.fd_grad(n, ops, params[i], terms)
+            assert np.max(np.abs(g[off:off + npar] - g_ref)) <= max(tol, 1e-7), (i, g[off:off + npar], g_ref)
+        off += npar
+    assert e[2] == 3.0  # |000>: sum Z = 3 exactly
