@@ -299,11 +299,6 @@ __device__ __forceinline__ void lds_get(const V* __restrict__ lds, V* v, uint32_
     for (int j = 0; j < (1 << RB); ++j) v[j] = lds[swz(tl | off[j])];
 }
 
-// In the register routines below, a control mask is split in two: the lane
-// part has been checked once per op for the thread (the routine only runs
-// when it holds); `cmr`, the register part, is the same for every thread,
-// and off[j] is too, so each register's test is a uniform branch.
-
 #define SV_K_SWITCH(k, CALL)                                                                                       \
     switch (k) {                                                                                                   \
     case 0: CALL(0); break;                                                                                        \
@@ -315,21 +310,22 @@ __device__ __forceinline__ void lds_get(const V* __restrict__ lds, V* v, uint32_
     }
 
 
-// Apply one op (or its inverse) to this thread's registers.  cf: the op's
-// coefficients; coef: the table (for 4x4 matrices).
-// In the register routines below, a control mask is split in two.  The lane
-// part selects, per thread, between the op's coefficients and the identity
-// (SEL).  The register part `cmr` is the same for every thread, and off[j]
-// is too, so each register's test (CHK) is a uniform branch.
+// In the register routines below, an op's control mask comes in two parts
+// prepared by the host for the op's layout: `cml`, the controls on lane bits
+// (tile-local bits), selects per thread between the op's coefficients and the
+// identity (SEL); `cmk`, the controls on register bits as register indices,
+// gives each register j a test (j & cmk) == cmk that is the same for every
+// thread (CHK).  Neither needs the layout's register offsets, which keeps the
+// scalar registers free across the op loop.
 
 // Complex 2x2 on register bit K.
 template <typename T, int RB, int K, bool CHK>
-__device__ __forceinline__ void rpair_k(typename Vec2<T>::type* v, const T* u, const uint32_t* off, uint32_t cmr)
+__device__ __forceinline__ void rpair_k(typename Vec2<T>::type* v, const T* u, uint32_t cmk)
 {
 #pragma unroll
     for (int j = 0; j < (1 << RB); ++j) {
         if (j & (1 << K)) continue;
-        if (CHK && (off[j] & cmr) != cmr) continue;
+        if (CHK && (j & cmk) != cmk) continue;
         const int j1 = j | (1 << K);
         const auto a = v[j], b = v[j1];
         v[j] = cmul_add2<typename Vec2<T>::type, T>(u[0], u[1], a, u[2], u[3], b);
@@ -339,12 +335,12 @@ __device__ __forceinline__ void rpair_k(typename Vec2<T>::type* v, const T* u, c
 
 // Real 2x2 [[r0, r1], [r2, r3]] on register bit K.
 template <typename T, int RB, int K, bool CHK>
-__device__ __forceinline__ void rpairr_k(typename Vec2<T>::type* v, const T* r, const uint32_t* off, uint32_t cmr)
+__device__ __forceinline__ void rpairr_k(typename Vec2<T>::type* v, const T* r, uint32_t cmk)
 {
 #pragma unroll
     for (int j = 0; j < (1 << RB); ++j) {
         if (j & (1 << K)) continue;
-        if (CHK && (off[j] & cmr) != cmr) continue;
+        if (CHK && (j & cmk) != cmk) continue;
         const int j1 = j | (1 << K);
         const auto a = v[j], b = v[j1];
         v[j].x = r[0] * a.x + r[1] * b.x;
@@ -356,12 +352,12 @@ __device__ __forceinline__ void rpairr_k(typename Vec2<T>::type* v, const T* r, 
 
 // Exchange of the pair on register bit K (X); with SEL only where `ok` holds.
 template <typename T, int RB, int K, bool CHK, bool SEL>
-__device__ __forceinline__ void rpairx_k(typename Vec2<T>::type* v, bool ok, const uint32_t* off, uint32_t cmr)
+__device__ __forceinline__ void rpairx_k(typename Vec2<T>::type* v, bool ok, uint32_t cmk)
 {
 #pragma unroll
     for (int j = 0; j < (1 << RB); ++j) {
         if (j & (1 << K)) continue;
-        if (CHK && (off[j] & cmr) != cmr) continue;
+        if (CHK && (j & cmk) != cmk) continue;
         const int j1 = j | (1 << K);
         const auto a = v[j], b = v[j1];
         if constexpr (SEL) {
@@ -378,11 +374,11 @@ __device__ __forceinline__ void rpairx_k(typename Vec2<T>::type* v, bool ok, con
 
 // Element-wise diagonal d[bit of register K].
 template <typename T, int RB, int K, bool CHK>
-__device__ __forceinline__ void rdiag_k(typename Vec2<T>::type* v, const T* d, const uint32_t* off, uint32_t cmr)
+__device__ __forceinline__ void rdiag_k(typename Vec2<T>::type* v, const T* d, uint32_t cmk)
 {
 #pragma unroll
     for (int j = 0; j < (1 << RB); ++j) {
-        if (CHK && (off[j] & cmr) != cmr) continue;
+        if (CHK && (j & cmk) != cmk) continue;
         const T zr = (j >> K) & 1 ? d[2] : d[0], zi = (j >> K) & 1 ? d[3] : d[1];
         const auto x = v[j];
         v[j].x = zr * x.x - zi * x.y;
@@ -392,11 +388,11 @@ __device__ __forceinline__ void rdiag_k(typename Vec2<T>::type* v, const T* d, c
 
 // One phase z on every register (passing the register-bit controls).
 template <typename T, int RB, bool CHK>
-__device__ __forceinline__ void rphase(typename Vec2<T>::type* v, T zr, T zi, const uint32_t* off, uint32_t cmr)
+__device__ __forceinline__ void rphase(typename Vec2<T>::type* v, T zr, T zi, uint32_t cmk)
 {
 #pragma unroll
     for (int j = 0; j < (1 << RB); ++j) {
-        if (CHK && (off[j] & cmr) != cmr) continue;
+        if (CHK && (j & cmk) != cmk) continue;
         const auto x = v[j];
         v[j].x = zr * x.x - zi * x.y;
         v[j].y = zr * x.y + zi * x.x;
@@ -404,12 +400,12 @@ __device__ __forceinline__ void rphase(typename Vec2<T>::type* v, T zr, T zi, co
 }
 
 template <typename T, int RB, int KA, int KB, bool CHK, bool SEL>
-__device__ __forceinline__ void rswap_k(typename Vec2<T>::type* v, bool ok, const uint32_t* off, uint32_t cmr)
+__device__ __forceinline__ void rswap_k(typename Vec2<T>::type* v, bool ok, uint32_t cmk)
 {
 #pragma unroll
     for (int j = 0; j < (1 << RB); ++j) {
         if (!(j & (1 << KA)) || (j & (1 << KB))) continue;  // j: bit a = 1, bit b = 0
-        if (CHK && (off[j] & cmr) != cmr) continue;
+        if (CHK && (j & cmk) != cmk) continue;
         const int j1 = j ^ (1 << KA) ^ (1 << KB);
         const auto a = v[j], b = v[j1];
         if constexpr (SEL) {
@@ -424,52 +420,22 @@ __device__ __forceinline__ void rswap_k(typename Vec2<T>::type* v, bool ok, cons
     }
 }
 
-// 4x4 on register bits KA (matrix MSB) and KB; u = 16 complex entries row-major
-template <typename T, int RB, int KA, int KB, bool CHK>
-__device__ __forceinline__ void rquad_k(typename Vec2<T>::type* v, const T* u, const uint32_t* off, uint32_t cmr)
-{
-    using V = typename Vec2<T>::type;
-#pragma unroll
-    for (int j = 0; j < (1 << RB); ++j) {
-        if (j & ((1 << KA) | (1 << KB))) continue;
-        if (CHK && (off[j] & cmr) != cmr) continue;
-        const int ix[4] = {j, j | (1 << KB), j | (1 << KA), j | (1 << KA) | (1 << KB)};
-        V w[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) w[k] = v[ix[k]];
-#pragma unroll
-        for (int row = 0; row < 4; ++row) {
-            T sr = u[8 * row] * w[0].x - u[8 * row + 1] * w[0].y;
-            T si = u[8 * row] * w[0].y + u[8 * row + 1] * w[0].x;
-#pragma unroll
-            for (int col = 1; col < 4; ++col) {
-                const T ur = u[2 * (4 * row + col)], ui = u[2 * (4 * row + col) + 1];
-                sr += ur * w[col].x - ui * w[col].y;
-                si += ur * w[col].y + ui * w[col].x;
-            }
-            v[ix[row]].x = sr;
-            v[ix[row]].y = si;
-        }
-    }
-}
-
 #define SV_RB_PAIRS(X) X(0, 1) X(0, 2) X(1, 0) X(1, 2) X(2, 0) X(2, 1)
 #define SV_RB4_PAIRS(X) X(0, 3) X(1, 3) X(2, 3) X(3, 0) X(3, 1) X(3, 2)
 
 template <typename T, int RB, bool CHK, bool SEL>
-__device__ __forceinline__ void rswap(int ka, int kb, typename Vec2<T>::type* v, bool ok, const uint32_t* off,
-                                      uint32_t cmr)
+__device__ __forceinline__ void rswap(int ka, int kb, typename Vec2<T>::type* v, bool ok, uint32_t cmk)
 {
     switch (ka * 4 + kb) {
 #define SV_CASE(A, B)                                                                                              \
-    case A * 4 + B: rswap_k<T, RB, A, B, CHK, SEL>(v, ok, off, cmr); break;
+    case A * 4 + B: rswap_k<T, RB, A, B, CHK, SEL>(v, ok, cmk); break;
         SV_RB_PAIRS(SV_CASE)
 #undef SV_CASE
     default:
         if constexpr (RB > 3) {
             switch (ka * 4 + kb) {
 #define SV_CASE(A, B)                                                                                              \
-    case A * 4 + B: rswap_k<T, RB, A, B, CHK, SEL>(v, ok, off, cmr); break;
+    case A * 4 + B: rswap_k<T, RB, A, B, CHK, SEL>(v, ok, cmk); break;
                 SV_RB4_PAIRS(SV_CASE)
 #undef SV_CASE
             default: break;
@@ -479,38 +445,17 @@ __device__ __forceinline__ void rswap(int ka, int kb, typename Vec2<T>::type* v,
     }
 }
 
-template <typename T, int RB, bool CHK>
-__device__ __forceinline__ void rquad(int ka, int kb, typename Vec2<T>::type* v, const T* u, const uint32_t* off,
-                                      uint32_t cmr)
-{
-    switch (ka * 4 + kb) {
-#define SV_CASE(A, B)                                                                                              \
-    case A * 4 + B: rquad_k<T, RB, A, B, CHK>(v, u, off, cmr); break;
-        SV_RB_PAIRS(SV_CASE)
-#undef SV_CASE
-    default:
-        if constexpr (RB > 3) {
-            switch (ka * 4 + kb) {
-#define SV_CASE(A, B)                                                                                              \
-    case A * 4 + B: rquad_k<T, RB, A, B, CHK>(v, u, off, cmr); break;
-                SV_RB4_PAIRS(SV_CASE)
-#undef SV_CASE
-            default: break;
-            }
-        }
-        break;
-    }
-}
-
-// TWO: two-target ops (SWAP, 4x4) run in registers; reverse passes leave them
-// to an LDS sweep instead (lds_op), which keeps their register code smaller.
+// TWO: SWAP runs in registers (forward passes); reverse passes leave it to an
+// LDS sweep (lds_op).  4x4 ops always take the LDS sweep: their 32 complex
+// coefficients would claim 64 scalar registers in this switch and make the
+// compiler spill scalar registers across the whole op loop.
 template <typename T, int RB, bool CHK, bool SEL, bool TWO>
 __device__ __forceinline__ void reg_apply_c(typename Vec2<T>::type* v, const FOp& op, cptr<T> cf, bool dagger,
-                                            uint32_t tl, const uint32_t* off, uint32_t cmr, bool ok)
+                                            uint32_t tl, uint32_t cmk, bool ok)
 {
     switch (op.kind) {
     case FK_PAIRX: {
-#define SV_CALL(K) rpairx_k<T, RB, K, CHK, SEL>(v, ok, off, cmr)
+#define SV_CALL(K) rpairx_k<T, RB, K, CHK, SEL>(v, ok, cmk)
         SV_K_SWITCH(op.ka, SV_CALL)
 #undef SV_CALL
         break;
@@ -528,7 +473,7 @@ __device__ __forceinline__ void reg_apply_c(typename Vec2<T>::type* v, const FOp
             r[2] = ok ? r[2] : T(0);
             r[3] = ok ? r[3] : T(1);
         }
-#define SV_CALL(K) rpairr_k<T, RB, K, CHK>(v, r, off, cmr)
+#define SV_CALL(K) rpairr_k<T, RB, K, CHK>(v, r, cmk)
         SV_K_SWITCH(op.ka, SV_CALL)
 #undef SV_CALL
         break;
@@ -540,7 +485,7 @@ __device__ __forceinline__ void reg_apply_c(typename Vec2<T>::type* v, const FOp
 #pragma unroll
             for (int k = 0; k < 8; ++k) u[k] = ok ? u[k] : ((k == 0 || k == 6) ? T(1) : T(0));
         }
-#define SV_CALL(K) rpair_k<T, RB, K, CHK>(v, u, off, cmr)
+#define SV_CALL(K) rpair_k<T, RB, K, CHK>(v, u, cmk)
         SV_K_SWITCH(op.ka, SV_CALL)
 #undef SV_CALL
         break;
@@ -554,12 +499,12 @@ __device__ __forceinline__ void reg_apply_c(typename Vec2<T>::type* v, const FOp
             d[3] = ok ? d[3] : T(0);
         }
         if (op.ka >= 0) {
-#define SV_CALL(K) rdiag_k<T, RB, K, CHK>(v, d, off, cmr)
+#define SV_CALL(K) rdiag_k<T, RB, K, CHK>(v, d, cmk)
             SV_K_SWITCH(op.ka, SV_CALL)
 #undef SV_CALL
         } else {  // target on a lane bit: one phase for all of this thread's registers
             const bool b = (tl >> op.a) & 1u;
-            rphase<T, RB, CHK>(v, b ? d[2] : d[0], b ? d[3] : d[1], off, cmr);
+            rphase<T, RB, CHK>(v, b ? d[2] : d[0], b ? d[3] : d[1], cmk);
         }
         break;
     }
@@ -569,27 +514,12 @@ __device__ __forceinline__ void reg_apply_c(typename Vec2<T>::type* v, const FOp
             zr = ok ? zr : T(1);
             zi = ok ? zi : T(0);
         }
-        rphase<T, RB, CHK>(v, zr, zi, off, cmr);
+        rphase<T, RB, CHK>(v, zr, zi, cmk);
         break;
     }
     case FK_SWAP:
-        if constexpr (TWO) rswap<T, RB, CHK, SEL>(op.ka, op.kb, v, ok, off, cmr);
+        if constexpr (TWO) rswap<T, RB, CHK, SEL>(op.ka, op.kb, v, ok, cmk);
         break;
-    case FK_QUAD: {
-        if constexpr (!TWO) break;
-        T u[32];
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                const int e = dagger ? (4 * c + r) : (4 * r + c);
-                u[2 * (4 * r + c)] = (T)cf[2 * e];
-                u[2 * (4 * r + c) + 1] = (T)(dagger ? -cf[2 * e + 1] : cf[2 * e + 1]);
-            }
-        // lane-controlled 4x4 ops are rare: a plain branch
-        if (!SEL || ok) rquad<T, RB, CHK>(op.ka, op.kb, v, u, off, cmr);
-        break;
-    }
     default: break;
     }
 }
@@ -599,18 +529,16 @@ __device__ __forceinline__ void reg_apply_c(typename Vec2<T>::type* v, const FOp
 // turns the op into the identity for threads where it is 0.
 template <typename T, int RB, bool TWO = true>
 __device__ __forceinline__ void reg_apply(typename Vec2<T>::type* v, const FOp& op, cptr<T> cf, bool dagger,
-                                          uint32_t tl, const uint32_t* off)
+                                          uint32_t tl)
 {
-    const uint32_t regmask = off[(1 << RB) - 1];
-    const uint32_t cmr = op.cm & regmask;
-    const uint32_t cml = op.cm & ~regmask;
+    const uint32_t cmk = op.cmk, cml = op.cml;
     const bool ok = (tl & cml) == cml;
     if (cml) {
-        if (cmr) reg_apply_c<T, RB, true, true, TWO>(v, op, cf, dagger, tl, off, cmr, ok);
-        else reg_apply_c<T, RB, false, true, TWO>(v, op, cf, dagger, tl, off, 0u, ok);
+        if (cmk) reg_apply_c<T, RB, true, true, TWO>(v, op, cf, dagger, tl, cmk, ok);
+        else reg_apply_c<T, RB, false, true, TWO>(v, op, cf, dagger, tl, 0u, ok);
     } else {
-        if (cmr) reg_apply_c<T, RB, true, false, TWO>(v, op, cf, dagger, tl, off, cmr, true);
-        else reg_apply_c<T, RB, false, false, TWO>(v, op, cf, dagger, tl, off, 0u, true);
+        if (cmk) reg_apply_c<T, RB, true, false, TWO>(v, op, cf, dagger, tl, cmk, true);
+        else reg_apply_c<T, RB, false, false, TWO>(v, op, cf, dagger, tl, 0u, true);
     }
 }
 
@@ -619,13 +547,13 @@ __device__ __forceinline__ void reg_apply(typename Vec2<T>::type* v, const FOp& 
 // bit is excluded from the mask).
 template <typename T, int RB, int K, bool CHK>
 __device__ __forceinline__ double rgen_pair_k(const typename Vec2<T>::type* P, const typename Vec2<T>::type* L,
-                                              bool gy, const uint32_t* off, uint32_t cmr)
+                                              bool gy, uint32_t cmk)
 {
     double acc = 0.0;
 #pragma unroll
     for (int j = 0; j < (1 << RB); ++j) {
         if (j & (1 << K)) continue;
-        if (CHK && (off[j] & cmr) != cmr) continue;
+        if (CHK && (j & cmk) != cmk) continue;
         const int j1 = j | (1 << K);
         const double a0r = P[j].x, a0i = P[j].y, a1r = P[j1].x, a1i = P[j1].y;
         const double l0r = L[j].x, l0i = L[j].y, l1r = L[j1].x, l1i = L[j1].y;
@@ -639,12 +567,12 @@ __device__ __forceinline__ double rgen_pair_k(const typename Vec2<T>::type* P, c
 // sel(j) gives that bit for register j.
 template <typename T, int RB, bool CHK, typename Sel>
 __device__ __forceinline__ double rgen_elem(const typename Vec2<T>::type* P, const typename Vec2<T>::type* L, bool gz,
-                                            const uint32_t* off, uint32_t cmr, Sel sel)
+                                            uint32_t cmk, Sel sel)
 {
     double acc = 0.0;
 #pragma unroll
     for (int j = 0; j < (1 << RB); ++j) {
-        if (CHK && (off[j] & cmr) != cmr) continue;
+        if (CHK && (j & cmk) != cmk) continue;
         const bool b = sel(j);
         const double t = (double)L[j].x * (double)P[j].y - (double)L[j].y * (double)P[j].x;
         if (gz) acc += b ? -t : t;
@@ -655,32 +583,33 @@ __device__ __forceinline__ double rgen_elem(const typename Vec2<T>::type* P, con
 
 template <typename T, int RB>
 __device__ __forceinline__ double reg_gen_inner(const typename Vec2<T>::type* P, const typename Vec2<T>::type* L,
-                                                const FOp& op, uint32_t tl, const uint32_t* off)
+                                                const FOp& op, uint32_t tl)
 {
-    const uint32_t regmask = off[(1 << RB) - 1];
-    const uint32_t cm = op.cm & ~(1u << op.a);  // a subset-phase op lists its target in cm
-    const uint32_t cmr = cm & regmask;
-    if ((tl & cm) != (cm & ~regmask)) return 0.0;
+    // the generator's controls exclude the target (a subset-phase op lists it)
+    const uint32_t tk = op.ka >= 0 ? 1u << op.ka : 0u, tlb = op.ka >= 0 ? 0u : 1u << op.a;
+    const uint32_t cmk = op.cmk & ~tk, cml = op.cml & ~tlb;
+    if ((tl & cml) != cml) return 0.0;
     if (op.gen == GEN_X || op.gen == GEN_Y) {
         const bool gy = op.gen == GEN_Y;
         double r = 0.0;
-        if (cmr) {
-#define SV_CALL(K) r = rgen_pair_k<T, RB, K, true>(P, L, gy, off, cmr)
+        if (cmk) {
+#define SV_CALL(K) r = rgen_pair_k<T, RB, K, true>(P, L, gy, cmk)
             SV_K_SWITCH(op.ka, SV_CALL)
 #undef SV_CALL
         } else {
-#define SV_CALL(K) r = rgen_pair_k<T, RB, K, false>(P, L, gy, off, 0u)
+#define SV_CALL(K) r = rgen_pair_k<T, RB, K, false>(P, L, gy, 0u)
             SV_K_SWITCH(op.ka, SV_CALL)
 #undef SV_CALL
         }
         return r;
     }
     const bool gz = op.gen == GEN_Z;
-    const uint32_t abit = 1u << op.a;
-    if (abit & regmask)
-        return rgen_elem<T, RB, true>(P, L, gz, off, cmr, [&](int j) { return (off[j] & abit) != 0; });
-    const bool b = (tl & abit) != 0;
-    return rgen_elem<T, RB, true>(P, L, gz, off, cmr, [&](int) { return b; });
+    if (op.ka >= 0) {
+        const int ka = op.ka;
+        return rgen_elem<T, RB, true>(P, L, gz, cmk, [&](int j) { return ((j >> ka) & 1) != 0; });
+    }
+    const bool b = (tl >> op.a) & 1u;
+    return rgen_elem<T, RB, true>(P, L, gz, cmk, [&](int) { return b; });
 }
 
 // Sum per slot of the wave partials, in fixed wave order, to the per-tile table.
@@ -726,15 +655,17 @@ struct OpPre {
 
 __device__ __forceinline__ void op_fetch(const PassTables& tb, int o, OpPre& p) { p.op = ld_const(as_const(tb.ops) + o); }
 
-// A two-target op (SWAP, 4x4) in a reverse pass: the tile goes to LDS, every
-// thread sweeps the op over it, and the registers are read back.  These ops
-// are rare in the workloads, and keeping them out of the reverse kernel's
-// register switch makes its code smaller and faster.
+// A two-target op by a sweep over the LDS tile (4x4 ops in both directions,
+// SWAP in reverse passes): the tile goes to LDS, every thread sweeps the op
+// over it, and the registers are read back.  These ops are rare in the
+// workloads; keeping them out of the register switch keeps its code small.
 template <typename T, int RB, typename P>
 __device__ __forceinline__ void lds_op(typename Vec2<T>::type* v, typename Vec2<T>::type* lds, const FOp& op, P coef,
-                                       bool dagger, int tq, bool active, uint32_t tl, const uint32_t* off)
+                                       bool dagger, int tq, bool active, cptr<FLayout> L)
 {
     using V = typename Vec2<T>::type;
+    uint32_t tl, off[1 << RB];
+    frame_of<RB>(L, threadIdx.x, tl, off);
     if (active) lds_put<V, RB>(lds, v, tl, off);
     __syncthreads();
     lds_apply<T, true, P>(lds, op, coef, dagger, tq);
@@ -756,10 +687,13 @@ __device__ __forceinline__ void item_reg_fwd(const PassTables& tb, const FCirc& 
     const bool active = threadIdx.x < (1u << (tq - RB));
     const uint64_t tile_base = tile_base_of(pp->free_mask, (uint64_t)tile);
     V* const psi = (V*)cc.psi;
-    uint32_t tl, off[R];
+    uint32_t tl;
     V v[R];
     int cur = pp->lay_begin;
-    frame_of<RB>(lays + cur, threadIdx.x, tl, off);
+    {
+        uint32_t off[R];
+        frame_of<RB>(lays + cur, threadIdx.x, tl, off);
+    }
 #pragma unroll
     for (int j = 0; j < R; ++j) v[j].x = v[j].y = T(0);  // threads past the tile keep zeros
     if (active) {
@@ -785,6 +719,8 @@ __device__ __forceinline__ void item_reg_fwd(const PassTables& tb, const FCirc& 
         const FOp& op = p.op;
         if (op.kind == FK_LAYOUT) {
             if (op.a == cur) continue;
+            uint32_t off[R];
+            frame_of<RB>(lays + cur, threadIdx.x, tl, off);
             if (active) lds_put<V, RB>(lds, v, tl, off);
             __syncthreads();
             cur = op.a;
@@ -793,7 +729,8 @@ __device__ __forceinline__ void item_reg_fwd(const PassTables& tb, const FCirc& 
             __syncthreads();
             continue;
         }
-        reg_apply<T, RB>(v, op, coef + op.coef, false, tl, off);
+        if (op.kind == FK_QUAD) lds_op<T, RB>(v, lds, op, coef, false, tq, active, lays + cur);
+        else reg_apply<T, RB>(v, op, coef + op.coef, false, tl);
     }
     if (active) {
         uint64_t g[R];
@@ -819,10 +756,13 @@ __device__ __forceinline__ void item_reg_rev(const PassTables& tb, const FCirc& 
     const uint64_t tile_base = tile_base_of(pp->free_mask, (uint64_t)tile);
     V* const psi = (V*)cc.psi;
     V* const lam = (V*)cc.lam;
-    uint32_t tl, off[R];
+    uint32_t tl;
     V v[R], w[R];
     int cur = pp->rlay_end;
-    frame_of<RB>(lays + cur, threadIdx.x, tl, off);
+    {
+        uint32_t off[R];
+        frame_of<RB>(lays + cur, threadIdx.x, tl, off);
+    }
 #pragma unroll
     for (int j = 0; j < R; ++j) v[j].x = v[j].y = w[j].x = w[j].y = T(0);  // threads past the tile keep zeros
     if (active) {
@@ -843,7 +783,8 @@ __device__ __forceinline__ void item_reg_rev(const PassTables& tb, const FCirc& 
         const FOp& op = p.op;
         if (op.kind == FK_LAYOUT) {
             if (op.b == cur) continue;
-            uint32_t tl2, off2[R];
+            uint32_t tl2, off2[R], off[R];
+            frame_of<RB>(lays + cur, threadIdx.x, tl, off);
             frame_of<RB>(lays + op.b, threadIdx.x, tl2, off2);
             if (active) lds_put<V, RB>(lds, v, tl, off);
             __syncthreads();
@@ -855,21 +796,19 @@ __device__ __forceinline__ void item_reg_rev(const PassTables& tb, const FCirc& 
             __syncthreads();
             cur = op.b;
             tl = tl2;
-#pragma unroll
-            for (int j = 0; j < R; ++j) off[j] = off2[j];
             continue;
         }
         if (op.slot >= 0) {
-            const double c = wave_sum(active ? reg_gen_inner<T, RB>(v, w, op, tl, off) : 0.0);
+            const double c = wave_sum(active ? reg_gen_inner<T, RB>(v, w, op, tl) : 0.0);
             if ((threadIdx.x & 63) == 0) wpart[nslot * 16 + (threadIdx.x >> 6)] = c;
             ++nslot;
         }
         if (op.kind == FK_SWAP || op.kind == FK_QUAD) {
-            lds_op<T, RB>(v, lds, op, coef, true, tq, active, tl, off);
-            lds_op<T, RB>(w, lds, op, coef, true, tq, active, tl, off);
+            lds_op<T, RB>(v, lds, op, coef, true, tq, active, lays + cur);
+            lds_op<T, RB>(w, lds, op, coef, true, tq, active, lays + cur);
         } else {
-            reg_apply<T, RB, false>(v, op, coef + op.coef, true, tl, off);
-            reg_apply<T, RB, false>(w, op, coef + op.coef, true, tl, off);
+            reg_apply<T, RB, false>(v, op, coef + op.coef, true, tl);
+            reg_apply<T, RB, false>(w, op, coef + op.coef, true, tl);
         }
     }
     __syncthreads();  // every wave's partials are in LDS

@@ -126,17 +126,16 @@ void schedule(int n, int tq, int cb, const std::vector<BOp>& ops, std::vector<st
     }
 }
 
-// Tile bits an op needs in registers: the target of a one-target pair op.
-// Diagonal and subset-phase ops act element-wise in any layout; two-target
-// ops (SWAP, 4x4) are applied by a sweep over the LDS tile.
+// Tile bits an op needs in registers: the targets of pair ops and SWAP.
+// Diagonal and subset-phase ops act element-wise in any layout; 4x4 ops are
+// applied by a sweep over the LDS tile.
 uint32_t op_need(const FOp& f)
 {
     switch (f.kind) {
     case FK_PAIR:
     case FK_PAIRR:
     case FK_PAIRX: return 1u << f.a;
-    case FK_SWAP:
-    case FK_QUAD: return (1u << f.a) | (1u << f.b);
+    case FK_SWAP: return (1u << f.a) | (1u << f.b);
     default: return 0u;
     }
 }
@@ -255,9 +254,14 @@ void plan_layouts(std::vector<FOp>& pass_ops, int tq, int rb, int cb, const int3
         }
         for (int i : r.second) {
             FOp f = pass_ops[i];
-            if (f.kind == FK_DIAG) f.ka = (int16_t)(((r.first >> f.a) & 1u) ? reg_index(r.first, f.a) : -1);
-            else f.ka = (int16_t)((op_need(f) & (1u << f.a)) ? reg_index(r.first, f.a) : 0);
-            f.kb = (int16_t)((f.kind == FK_SWAP || f.kind == FK_QUAD) ? reg_index(r.first, f.b) : 0);
+            const uint32_t S = r.first;
+            f.ka = (int8_t)(((S >> f.a) & 1u) ? reg_index(S, f.a) : -1);
+            f.kb = (int8_t)(((S >> f.b) & 1u) && (f.kind == FK_SWAP || f.kind == FK_QUAD) ? reg_index(S, f.b) : -1);
+            uint32_t cmk = 0;
+            for (int q = 0; q < 32; ++q)
+                if (((f.cm & S) >> q) & 1u) cmk |= 1u << reg_index(S, q);
+            f.cmk = (uint8_t)cmk;
+            f.cml = f.cm & ~S;
             out.push_back(f);
         }
     }
@@ -614,7 +618,7 @@ static sv_status compile_batch(const sv_batch_circuit* circuits, int n_circuits,
                 FOp f;
                 memset(&f, 0, sizeof f);
                 f.slot = slot_of[i];
-                f.gen = o.gate == SV_RX ? GEN_X : (o.gate == SV_RY ? GEN_Y : (o.gate == SV_RZ ? GEN_Z : GEN_P1));
+                f.gen = (int8_t)(o.gate == SV_RX ? GEN_X : (o.gate == SV_RY ? GEN_Y : (o.gate == SV_RZ ? GEN_Z : GEN_P1)));
                 uint32_t cm = 0;
                 for (int j = 0; j < o.nc; ++j) cm |= 1u << local[o.q[j]];
                 f.cm = cm;

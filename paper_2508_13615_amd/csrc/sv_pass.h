@@ -34,9 +34,13 @@ struct FOp {
     uint32_t cm;    // local bits that must all be 1 (controls; for FK_PHASE also the target)
     int32_t coef;   // offset of the op's coefficients in the coefficient table (doubles)
     int32_t slot;   // gradient slot within the circuit, -1 if not parameterised
-    int32_t gen;    // generator (GenKind) of a parameterised op
-    int16_t ka, kb; // register-tiled passes: register bit holding a for one-target pair ops;
-                    // for FK_DIAG the register bit of a, or -1 when a is a lane bit; kb unused
+    int8_t gen;     // generator (GenKind) of a parameterised op
+    // Register-tiled passes, for the layout the op runs in: the register bits
+    // holding a and b (-1 where the bit is a lane bit), and cm split into its
+    // register bits (as register indices, cmk) and its lane bits (cml).
+    int8_t ka, kb;
+    uint8_t cmk;
+    uint32_t cml;
 };
 
 // A distribution of a tile over the threads of a workgroup: lane bit i of

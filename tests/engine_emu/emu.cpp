@@ -197,6 +197,15 @@ static void reg_apply_h(cd* v, int rb, const FOp& op, const double* cf, bool dag
                         const FLayout& L, int tq)
 {
     const int R = 1 << rb, nl = tq - rb;
+    {
+        uint32_t Sm = 0, cmk = 0;
+        for (int r = 0; r < rb; ++r) Sm |= 1u << L.pos[nl + r];
+        for (int r = 0; r < rb; ++r)
+            if ((op.cm >> L.pos[nl + r]) & 1u) cmk |= 1u << r;
+        CHECK(op.cml == (op.cm & ~Sm), "cml %x != lane part of cm %x", op.cml, op.cm & ~Sm);
+        CHECK(op.cmk == cmk, "cmk %x != %x", op.cmk, cmk);
+        CHECK(op.ka == -1 || L.pos[nl + op.ka] == op.a, "ka does not hold a");
+    }
     switch (op.kind) {
     case FK_PAIRX:
     case FK_PAIRR:
@@ -235,7 +244,8 @@ static void reg_apply_h(cd* v, int rb, const FOp& op, const double* cf, bool dag
         break;
     }
     case FK_SWAP: {
-        CHECK(L.pos[nl + op.ka] == op.a && L.pos[nl + op.kb] == op.b, "swap targets not in registers");
+        CHECK(op.ka >= 0 && op.kb >= 0 && L.pos[nl + op.ka] == op.a && L.pos[nl + op.kb] == op.b,
+              "swap targets not in registers");
         for (int j = 0; j < R; ++j) {
             if (!(j & (1 << op.ka)) || (j & (1 << op.kb))) continue;
             if (((tl | off[j]) & op.cm) != op.cm) continue;
@@ -243,30 +253,44 @@ static void reg_apply_h(cd* v, int rb, const FOp& op, const double* cf, bool dag
         }
         break;
     }
-    case FK_QUAD: {
-        CHECK(L.pos[nl + op.ka] == op.a && L.pos[nl + op.kb] == op.b, "quad targets not in registers");
-        cd U[16];
-        for (int r = 0; r < 4; ++r)
-            for (int c = 0; c < 4; ++c) {
-                const int e = dagger ? (4 * c + r) : (4 * r + c);
-                U[4 * r + c] = cd(cf[2 * e], dagger ? -cf[2 * e + 1] : cf[2 * e + 1]);
-            }
-        for (int j = 0; j < R; ++j) {
-            if (j & ((1 << op.ka) | (1 << op.kb))) continue;
-            if (((tl | off[j]) & op.cm) != op.cm) continue;
-            const int ix[4] = {j, j | (1 << op.kb), j | (1 << op.ka), j | (1 << op.ka) | (1 << op.kb)};
-            cd w[4], r4[4];
-            for (int k = 0; k < 4; ++k) w[k] = v[ix[k]];
-            for (int r = 0; r < 4; ++r) {
-                r4[r] = 0;
-                for (int c = 0; c < 4; ++c) r4[r] += U[4 * r + c] * w[c];
-            }
-            for (int k = 0; k < 4; ++k) v[ix[k]] = r4[k];
-        }
-        break;
-    }
     default: CHECK(0, "bad kind %d", op.kind);
     }
+}
+
+// A 4x4 op or a SWAP by a sweep over the whole tile, as the kernels do through LDS:
+// registers -> swizzled LDS (poisoned with NaN first) -> tile in local order
+// -> op -> LDS -> registers.
+static void quad_sweep_h(std::vector<cd>& v, int nthr, int R, const Frame& f, int tq, const FOp& op, const double* cf,
+                         bool dagger)
+{
+    std::vector<cd> lds(1u << 13, cd(NAN, NAN)), A(1u << tq);
+    for (int t = 0; t < nthr; ++t)
+        for (int j = 0; j < R; ++j) lds[swz_h(f.tl[t] | f.off[j])] = v[t * R + j];
+    for (uint32_t l = 0; l < (1u << tq); ++l) A[l] = lds[swz_h(l)];
+    cd U[16];
+    if (op.kind == FK_SWAP) {
+        for (int e = 0; e < 16; ++e) U[e] = 0;
+        U[0] = U[6] = U[9] = U[15] = 1;
+    } else
+    for (int r = 0; r < 4; ++r)
+        for (int c = 0; c < 4; ++c) {
+            const int e = dagger ? (4 * c + r) : (4 * r + c);
+            U[4 * r + c] = cd(cf[2 * e], dagger ? -cf[2 * e + 1] : cf[2 * e + 1]);
+        }
+    for (uint32_t i = 0; i < (1u << tq); ++i) {
+        if (((i >> op.a) & 1) || ((i >> op.b) & 1) || (i & op.cm) != op.cm) continue;
+        const uint32_t ix[4] = {i, i | (1u << op.b), i | (1u << op.a), i | (1u << op.a) | (1u << op.b)};
+        cd w[4], r4[4];
+        for (int k = 0; k < 4; ++k) w[k] = A[ix[k]];
+        for (int r = 0; r < 4; ++r) {
+            r4[r] = 0;
+            for (int c = 0; c < 4; ++c) r4[r] += U[4 * r + c] * w[c];
+        }
+        for (int k = 0; k < 4; ++k) A[ix[k]] = r4[k];
+    }
+    for (uint32_t l = 0; l < (1u << tq); ++l) lds[swz_h(l)] = A[l];
+    for (int t = 0; t < nthr; ++t)
+        for (int j = 0; j < R; ++j) v[t * R + j] = lds[swz_h(f.tl[t] | f.off[j])];
 }
 
 static double gen_inner_h(const cd* P, const cd* Lm, int rb, const FOp& op, uint32_t tl, const uint32_t* off,
@@ -392,6 +416,10 @@ static void run_emu(Emu& E, const std::vector<double>& params)
                                 for (int j = 0; j < R; ++j) v[t * R + j] = lds[swz_h(f.tl[t] | f.off[j])];
                             continue;
                         }
+                        if (op.kind == FK_QUAD) {
+                            quad_sweep_h(v, nthr, R, f, tq, op, E.coef.data() + op.coef, false);
+                            continue;
+                        }
                         for (int t = 0; t < nthr; ++t)
                             reg_apply_h(&v[t * R], rb, op, E.coef.data() + op.coef, false, f.tl[t], f.off, H.lays[cur], tq);
                     }
@@ -462,6 +490,11 @@ static void run_emu(Emu& E, const std::vector<double>& params)
                         for (int t = 0; t < nthr; ++t)
                             acc += gen_inner_h(&v[t * R], &w[t * R], rb, op, f.tl[t], f.off, H.lays[cur], tq);
                         E.gpart[cc.g_part_begin + (int64_t)op.slot * cc.n_tiles + tile] = acc;
+                    }
+                    if (op.kind == FK_QUAD || op.kind == FK_SWAP) {
+                        quad_sweep_h(v, nthr, R, f, tq, op, E.coef.data() + op.coef, true);
+                        quad_sweep_h(w, nthr, R, f, tq, op, E.coef.data() + op.coef, true);
+                        continue;
                     }
                     for (int t = 0; t < nthr; ++t) {
                         reg_apply_h(&v[t * R], rb, op, E.coef.data() + op.coef, true, f.tl[t], f.off, H.lays[cur], tq);
