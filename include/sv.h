@@ -254,8 +254,8 @@ typedef struct {
 } sv_batch_circuit;
 
 typedef struct {
-    int32_t tile_qubits; /* 0 = default (12 complex128, 13 complex64); 2..13 */
-    int32_t amps_per_thread; /* 0 = default (16); 8 or 16: amplitudes of a tile each thread
+    int32_t tile_qubits; /* 0 = the engine shape (sv_tune_engine_set), else 2..13 */
+    int32_t amps_per_thread; /* 0 = the engine shape; 8 or 16: amplitudes of a tile each thread
                               * holds in registers (workgroup = 2^tile_qubits / this, >= 64) */
     int32_t use_graph;   /* capture the run on first use, replay afterwards */
     int32_t with_grad;   /* also run the adjoint sweep */
@@ -313,6 +313,19 @@ sv_status sv_batch_free(sv_batch b);
  * ------------------------------------------------------------------------ */
 sv_status sv_tune_set(int kernel_class, int dtype, int tier, int block, int unroll, int nt);
 sv_status sv_tune_get(int kernel_class, int dtype, int tier, int* block, int* unroll, int* nt);
+
+/* Engine tile shape (written by the autotuner, read by sv_batch_create and
+ * sv_batch_plan where sv_batch_opts leaves tile_qubits or amps_per_thread at
+ * 0).  tile_qubits 0 = the built-in default, 12 for complex128 and 13 for
+ * complex64 (64 KiB tiles), capped so that a workgroup holding one tile has
+ * at most 512 threads (complex128 reverse passes keep 8 amplitudes of each
+ * state per thread); amps_per_thread 0 = 16.  Process-wide; set it from one
+ * thread before creating batches; existing batches keep their shape.
+ * sv_tune_engine_get reports the shape a batch with zeroed options gets.
+ * Errors: SV_ERR_ARG for a bad dtype, amps_per_thread not 0/8/16,
+ * tile_qubits outside {0} U [2, 13] or too large for the thread limit. */
+sv_status sv_tune_engine_set(int dtype, int tile_qubits, int amps_per_thread);
+sv_status sv_tune_engine_get(int dtype, int* tile_qubits, int* amps_per_thread);
 
 /* Host-only report of how a gate would be launched on an n_qubits state of
  * `dtype`: kernel class, tier, operation code (the pair/subset operation;

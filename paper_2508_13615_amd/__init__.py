@@ -61,6 +61,19 @@ def tune_get(kernel_class: int, dtype: str, tier: int) -> Tuple[int, int, int]:
     return b.value, u.value, t.value
 
 
+def tune_engine_set(dtype: str, tile_qubits: int, amps_per_thread: int) -> None:
+    """Fused-engine tile shape for batches created with the options at 0
+    (0 = built-in default)."""
+    check(lib.sv_tune_engine_set(_SV_DT[dtype], int(tile_qubits), int(amps_per_thread)))
+
+
+def tune_engine_get(dtype: str) -> Tuple[int, int]:
+    """(tile_qubits, amps_per_thread) a batch with default options gets."""
+    t, a = ctypes.c_int(), ctypes.c_int()
+    check(lib.sv_tune_engine_get(_SV_DT[dtype], ctypes.byref(t), ctypes.byref(a)))
+    return t.value, a.value
+
+
 KERNEL_CLASSES = {0: "k_pair", 1: "k_one", 2: "k_diag", 3: "k_quad", 4: "k_general", 5: "k_wpair",
                   6: "k_lds_gate"}
 

@@ -5,10 +5,16 @@ two-target, general), both dtypes and the three run-length tiers (bytes
 spanned by a run of consecutive touched amplitudes: < 64 B, < 1 KiB, larger),
 it times representative gates under each candidate shape
 (block x groups-per-thread x non-temporal flag) with HIP events and keeps the
-fastest.  The result is written as JSON next to the library and loaded by
+fastest.  For the fused pass engine it times, per dtype, every tile shape
+(tile qubits x amplitudes per thread) on three workloads: the adjoint
+gradient of a 24-qubit, 8-layer hardware-efficient ansatz, a batch of 256
+such circuits of 14-22 qubits with forward, observable and adjoint stages,
+and the adjoint gradient of a 28-qubit, 4-layer one (a state far larger
+than the caches).  The
+result is written as JSON next to the library and loaded by
 ``paper_2508_13615_amd`` at import (``apply_table``).
 
-Run on the GPU:  python -m paper_2508_13615_amd.autotune [--qubits 30]
+Run on the GPU:  python -m paper_2508_13615_amd.autotune [--qubits 30] [--engine-only]
 """
 from __future__ import annotations
 
@@ -32,7 +38,9 @@ def apply_table(sv, path: str = TABLE) -> int:
         tab = json.load(f)
     for e in tab["entries"]:
         sv.tune_set(e["class"], e["dtype"], e["tier"], e["block"], e["unroll"], e["nt"])
-    return len(tab["entries"])
+    for e in tab.get("engine", []):
+        sv.tune_engine_set(e["dtype"], e["tile_qubits"], e["amps_per_thread"])
+    return len(tab["entries"]) + len(tab.get("engine", []))
 
 
 def _candidates(kc: int, n: int, rng, np):
@@ -140,19 +148,105 @@ def tune(qubits: int = 30, reps: int = 3, dtypes=("c128", "c64"), log=print, mar
             "created": time.strftime("%Y-%m-%d %H:%M:%S"), "entries": entries}
 
 
+# Engine tile shapes tried per dtype: (tile_qubits, amps_per_thread).  Every
+# one keeps forward and reverse workgroups within 64..512 threads.
+def _engine_shape_ok(dtype, tq, apt):
+    rb = apt.bit_length() - 1
+    rrb = min(rb, 3) if dtype == "c128" else rb
+    return 6 <= tq - rb and tq - min(rb, rrb) <= 9
+
+
+ENGINE_SHAPES = {dt: [(t, a) for a in (8, 16) for t in range(9, 14) if _engine_shape_ok(dt, t, a)]
+                 for dt in ("c128", "c64")}
+
+
+def _engine_workloads():
+    """(name, circuits) pairs: circuits as sv.Batch takes them."""
+    import workloads as W
+    hea = [(24, W.hea_ops(24, 8), W.hea_n_params(24, 8), "sum_zz")]
+    spec = W.batch_spec(256, 1006, 14, 22, 4, 12)
+    batch = [(c.n, W.hea_ops(c.n, c.layers), len(c.params), "sum_z") for c in spec]
+    big = [(28, W.hea_ops(28, 4), W.hea_n_params(28, 4), "sum_zz")]
+    return [("adjoint_hea24", hea), ("batch256", batch), ("adjoint_hea28", big)]
+
+
+def _time_engine(sv, circuits, dtype, shape, reps):
+    import numpy as np
+    b = sv.Batch(circuits, dtype, tile_qubits=shape[0], amps_per_thread=shape[1], with_grad=True)
+    params = np.random.default_rng(7).uniform(0, 2 * np.pi, sum(c[2] for c in circuits))
+    b.run(params)  # capture + first replay
+    times = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        b.run(params)
+        times.append(time.perf_counter() - t0)
+    del b
+    return float(np.median(times))
+
+
+def tune_engine(reps: int = 5, dtypes=("c128", "c64"), log=print, margin: float = 0.02) -> list:
+    """Per dtype: each shape's time on each workload, relative to the built-in
+    default shape, averaged over the workloads; the best replaces the default
+    only if it is `margin` faster.  Wall time of synchronous runs (parameters
+    uploaded, expectation values and gradients read back) is what a caller sees."""
+    import numpy as np
+    import torch
+
+    import paper_2508_13615_amd as sv
+
+    out = []
+    work = _engine_workloads()
+    for dtype in dtypes:
+        sv.tune_engine_set(dtype, 0, 0)
+        default = sv.tune_engine_get(dtype)
+        shapes = ENGINE_SHAPES[dtype]
+        if default not in shapes:
+            shapes = shapes + [default]
+        t = {sh: {} for sh in shapes}
+        for name, circs in work:
+            for _ in range(2):  # two interleaved rounds, the faster kept
+                for sh in shapes:
+                    v = _time_engine(sv, circs, dtype, sh, reps)
+                    t[sh][name] = min(v, t[sh].get(name, float("inf")))
+            torch.cuda.empty_cache()
+            log(f"[autotune] engine {dtype} {name}: {len(shapes)} shapes timed")
+        score = {sh: float(np.mean([t[sh][n] / t[default][n] for n, _ in work])) for sh in shapes}
+        for sh in shapes:
+            log(f"[autotune] engine {dtype} tile_qubits {sh[0]:2d} amps_per_thread {sh[1]:2d}: "
+                + ", ".join(f"{n} {t[sh][n] * 1e3:.2f} ms" for n, _ in work) + f" (relative {score[sh]:.3f})")
+        best = min(score, key=score.get)
+        if score[best] > 1.0 - margin:
+            best = default
+        sv.tune_engine_set(dtype, *best)
+        out.append({"dtype": dtype, "tile_qubits": best[0], "amps_per_thread": best[1],
+                    "relative_to_default": score[best], "default": list(default),
+                    "ms": {f"{sh[0]}x{sh[1]}": {n: t[sh][n] * 1e3 for n, _ in work} for sh in shapes}})
+        log(f"[autotune] engine {dtype}: tile_qubits {best[0]} amps_per_thread {best[1]}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--qubits", type=int, default=30)
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--out", default=TABLE)
+    ap.add_argument("--engine-only", action="store_true",
+                    help="tune only the fused engine's tile shape and keep the table's gate entries")
     args = ap.parse_args()
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     if root not in sys.path:
         sys.path.insert(0, root)
-    tab = tune(args.qubits, args.reps, log=lambda *a: print(*a, file=sys.stderr, flush=True))
+    log = lambda *a: print(*a, file=sys.stderr, flush=True)  # noqa: E731
+    if args.engine_only:
+        with open(args.out) as f:
+            tab = json.load(f)
+    else:
+        tab = tune(args.qubits, args.reps, log=log)
+    tab["engine"] = tune_engine(log=log)
     with open(args.out, "w") as f:
         json.dump(tab, f, indent=1)
-    print(f"wrote {args.out} ({len(tab['entries'])} entries)", file=sys.stderr)
+    print(f"wrote {args.out} ({len(tab['entries'])} gate entries, {len(tab['engine'])} engine entries)",
+          file=sys.stderr)
 
 
 if __name__ == "__main__":

@@ -506,23 +506,38 @@ struct HostTables {
     std::vector<size_t> psi_off;
 };
 
+// Engine tile shape per dtype (index 0 complex64, 1 complex128) used where
+// sv_batch_opts leaves a field 0; 0 here means the built-in default.
+static int g_engine_tq[2] = {0, 0};
+static int g_engine_apt[2] = {0, 0};
+
+// Largest tile whose forward and reverse workgroups stay within kMaxPassThreads.
+static int engine_tq_fit(int reg_bits, int rreg_bits)
+{
+    int lg_threads = 0;
+    while ((2 << lg_threads) <= kMaxPassThreads) ++lg_threads;
+    return std::min(reg_bits, rreg_bits) + lg_threads;
+}
+
 static sv_status compile_batch(const sv_batch_circuit* circuits, int n_circuits, int dtype, const sv_batch_opts* opts,
                                HostTables& H)
 {
     if (!circuits || n_circuits < 1) return set_error(SV_ERR_ARG, "bad batch arguments");
     if (dtype != SV_C64 && dtype != SV_C128) return set_error(SV_ERR_ARG, "bad dtype");
-    const int apt = opts && opts->amps_per_thread > 0 ? opts->amps_per_thread : (1 << kMaxRegBits);
+    const int d = dtype == SV_C128 ? 1 : 0;
+    const int apt = opts && opts->amps_per_thread > 0 ? opts->amps_per_thread
+                    : g_engine_apt[d] > 0              ? g_engine_apt[d]
+                                                       : (1 << kMaxRegBits);
     int reg_bits = 0;
     for (int r = kMinRegBits; r <= kMaxRegBits; ++r)
         if (apt == (1 << r)) reg_bits = r;
     if (!reg_bits) return set_error(SV_ERR_ARG, "amps_per_thread must be 8 or 16");
     // reverse passes hold phi and lambda: complex128 keeps 8 amplitudes of each per thread
     const int rreg_bits = dtype == SV_C128 ? std::min(reg_bits, 3) : reg_bits;
-    // default tile: 64 KiB (2^12 complex128 / 2^13 complex64 amplitudes), within
-    // kMaxPassThreads threads of the narrower register width
-    int lg_threads = 0;
-    while ((2 << lg_threads) <= kMaxPassThreads) ++lg_threads;
-    const int tq_default = std::min(dtype == SV_C128 ? 12 : 13, std::min(reg_bits, rreg_bits) + lg_threads);
+    // default tile: the tuned one, else 64 KiB (2^12 complex128 / 2^13 complex64
+    // amplitudes); either within kMaxPassThreads threads of the narrower register width
+    const int tq_base = g_engine_tq[d] > 0 ? g_engine_tq[d] : (dtype == SV_C128 ? 12 : 13);
+    const int tq_default = std::min(tq_base, engine_tq_fit(reg_bits, rreg_bits));
     int tq_max = opts && opts->tile_qubits > 0 ? opts->tile_qubits : tq_default;
     if (tq_max < 2 || tq_max > kMaxTileQubits) return set_error(SV_ERR_ARG, "tile_qubits must be in [2, 13]");
     const int with_grad = opts ? (opts->with_grad != 0) : 1;
@@ -771,6 +786,38 @@ static sv_status compile_batch(const sv_batch_circuit* circuits, int n_circuits,
             if (H.fops[o].kind == FK_LAYOUT) ++H.n_layout_changes;
             else ++H.n_gate_ops;
         }
+    return SV_OK;
+}
+
+sv_status sv_tune_engine_set(int dtype, int tile_qubits, int amps_per_thread)
+{
+    if (dtype != SV_C64 && dtype != SV_C128) return set_error(SV_ERR_ARG, "bad dtype");
+    if (amps_per_thread != 0 && amps_per_thread != 8 && amps_per_thread != 16)
+        return set_error(SV_ERR_ARG, "amps_per_thread must be 0, 8 or 16");
+    if (tile_qubits != 0 && (tile_qubits < 2 || tile_qubits > kMaxTileQubits))
+        return set_error(SV_ERR_ARG, "tile_qubits must be 0 or in [2, 13]");
+    if (tile_qubits) {
+        const int rb = amps_per_thread == 8 ? 3 : 4;
+        const int rrb = dtype == SV_C128 ? std::min(rb, 3) : rb;
+        if (tile_qubits > engine_tq_fit(rb, rrb))
+            return set_error(SV_ERR_ARG, "tile_qubits too large for amps_per_thread (at most 512 threads per tile)");
+    }
+    const int d = dtype == SV_C128 ? 1 : 0;
+    g_engine_tq[d] = tile_qubits;
+    g_engine_apt[d] = amps_per_thread;
+    return SV_OK;
+}
+
+sv_status sv_tune_engine_get(int dtype, int* tile_qubits, int* amps_per_thread)
+{
+    if ((dtype != SV_C64 && dtype != SV_C128) || !tile_qubits || !amps_per_thread)
+        return set_error(SV_ERR_ARG, "bad dtype or null output");
+    const int d = dtype == SV_C128 ? 1 : 0;
+    const int rb = g_engine_apt[d] == 8 ? 3 : 4;
+    const int rrb = dtype == SV_C128 ? std::min(rb, 3) : rb;
+    const int tq_base = g_engine_tq[d] > 0 ? g_engine_tq[d] : (dtype == SV_C128 ? 12 : 13);
+    *tile_qubits = std::min(tq_base, engine_tq_fit(rb, rrb));
+    *amps_per_thread = 1 << rb;
     return SV_OK;
 }
 

@@ -190,8 +190,9 @@ def test_batch_plan_fuses_gates_host_only():
     # fits a 2^12-amplitude tile, and the adjoint doubles the stage count.
     import workloads as W
     ops = W.hea_ops(32, 10)
-    fwd = sv.batch_plan([(32, ops, W.hea_n_params(32, 10), "sum_z")], "c128", with_grad=False)
-    adj = sv.batch_plan([(32, ops, W.hea_n_params(32, 10), "sum_z")], "c128", with_grad=True)
+    shape = dict(tile_qubits=12, amps_per_thread=16)
+    fwd = sv.batch_plan([(32, ops, W.hea_n_params(32, 10), "sum_z")], "c128", with_grad=False, **shape)
+    adj = sv.batch_plan([(32, ops, W.hea_n_params(32, 10), "sum_z")], "c128", with_grad=True, **shape)
     # forward passes fuse each RY with the RZ after it on the same qubit
     assert fwd["fused_ops"] == len(ops) - 32 * 10
     assert adj["fused_ops"] == fwd["fused_ops"]
@@ -202,9 +203,39 @@ def test_batch_plan_fuses_gates_host_only():
     assert fwd["items"] == (fwd["passes"] + 1) * 2 ** 20
     assert adj["levels"] == 2 * adj["passes"] + 1
     assert fwd["lds_bytes"] <= 160 * 1024 and adj["lds_bytes"] <= 160 * 1024
-    q = sv.batch_plan([(32, W.qft_ops(32), 0, "sum_z")], "c128", with_grad=False)
+    q = sv.batch_plan([(32, W.qft_ops(32), 0, "sum_z")], "c128", with_grad=False, **shape)
     assert q["passes"] < len(W.qft_ops(32)) // 4
     # tiny tiles: more passes, same gates
     small = sv.batch_plan([(10, W.hea_ops(10, 3), 60, "sum_z")], "c64", tile_qubits=4, with_grad=False)
     big = sv.batch_plan([(10, W.hea_ops(10, 3), 60, "sum_z")], "c64", tile_qubits=0, with_grad=False)
     assert small["passes"] > big["passes"] == 1
+
+
+def test_engine_tile_shape_tuning_host_only():
+    # Zeroed batch options take the engine shape of sv_tune_engine_set; shapes
+    # that break the 512-thread limit or the allowed values are refused and
+    # leave the setting unchanged.
+    import workloads as W
+    circ = [(16, W.hea_ops(16, 2), W.hea_n_params(16, 2), "sum_z")]
+    saved = {dt: sv.tune_engine_get(dt) for dt in ("c128", "c64")}
+    try:
+        sv.tune_engine_set("c128", 0, 0)
+        assert sv.tune_engine_get("c128") == (12, 16)
+        sv.tune_engine_set("c64", 0, 0)
+        assert sv.tune_engine_get("c64") == (13, 16)
+        sv.tune_engine_set("c64", 0, 8)  # 13 would need 1024 threads of 8 amplitudes
+        assert sv.tune_engine_get("c64") == (12, 8)
+        sv.tune_engine_set("c128", 10, 8)
+        p = sv.batch_plan(circ, "c128")
+        assert p["threads"] == 2 ** 10 // 8 and p["items"] % 2 ** 6 == 0
+        explicit = sv.batch_plan(circ, "c128", tile_qubits=12, amps_per_thread=16)
+        assert explicit["threads"] == 2 ** 12 // 16
+        for dt, tq, apt in (("c128", 13, 16), ("c128", 13, 8), ("c64", 13, 8), ("c128", 1, 16), ("c128", 14, 0),
+                            ("c128", 12, 4), ("c64", 0, 32)):
+            with pytest.raises(sv.SvError):
+                sv.tune_engine_set(dt, tq, apt)
+        assert sv.tune_engine_get("c128") == (10, 8)
+        assert sv.lib.sv_tune_engine_set(7, 0, 0) == ARG  # bad dtype
+    finally:
+        for dt, (tq, apt) in saved.items():
+            sv.tune_engine_set(dt, tq, apt)
