@@ -316,16 +316,20 @@ sv_status sv_tune_get(int kernel_class, int dtype, int tier, int* block, int* un
 
 /* Engine tile shape (written by the autotuner, read by sv_batch_create and
  * sv_batch_plan where sv_batch_opts leaves tile_qubits or amps_per_thread at
- * 0).  tile_qubits 0 = the built-in default, 12 for complex128 and 13 for
- * complex64 (64 KiB tiles), capped so that a workgroup holding one tile has
- * at most 512 threads (complex128 reverse passes keep 8 amplitudes of each
- * state per thread); amps_per_thread 0 = 16.  Process-wide; set it from one
- * thread before creating batches; existing batches keep their shape.
+ * 0), one per dtype and per stage mix: with_grad = 0 for forward-only
+ * batches, 1 for batches that also run the adjoint sweep (its reverse
+ * workgroups hold two states, so they favour other tiles).  tile_qubits 0 =
+ * the built-in default, 12 for complex128 and 13 for complex64 (64 KiB
+ * tiles), capped so that a workgroup holding one tile has at most 512
+ * threads (complex128 reverse passes keep 8 amplitudes of each state per
+ * thread); amps_per_thread 0 = 16.  Process-wide; set it from one thread
+ * before creating batches; existing batches keep their shape.
  * sv_tune_engine_get reports the shape a batch with zeroed options gets.
- * Errors: SV_ERR_ARG for a bad dtype, amps_per_thread not 0/8/16,
- * tile_qubits outside {0} U [2, 13] or too large for the thread limit. */
-sv_status sv_tune_engine_set(int dtype, int tile_qubits, int amps_per_thread);
-sv_status sv_tune_engine_get(int dtype, int* tile_qubits, int* amps_per_thread);
+ * Errors: SV_ERR_ARG for a bad dtype or with_grad, amps_per_thread not
+ * 0/8/16, tile_qubits outside {0} U [2, 13] or too large for the thread
+ * limit. */
+sv_status sv_tune_engine_set(int dtype, int with_grad, int tile_qubits, int amps_per_thread);
+sv_status sv_tune_engine_get(int dtype, int with_grad, int* tile_qubits, int* amps_per_thread);
 
 /* Host-only report of how a gate would be launched on an n_qubits state of
  * `dtype`: kernel class, tier, operation code (the pair/subset operation;

@@ -61,16 +61,16 @@ def tune_get(kernel_class: int, dtype: str, tier: int) -> Tuple[int, int, int]:
     return b.value, u.value, t.value
 
 
-def tune_engine_set(dtype: str, tile_qubits: int, amps_per_thread: int) -> None:
-    """Fused-engine tile shape for batches created with the options at 0
-    (0 = built-in default)."""
-    check(lib.sv_tune_engine_set(_SV_DT[dtype], int(tile_qubits), int(amps_per_thread)))
+def tune_engine_set(dtype: str, with_grad: bool, tile_qubits: int, amps_per_thread: int) -> None:
+    """Fused-engine tile shape for batches of this dtype and stage mix created
+    with the shape options at 0 (0 = built-in default)."""
+    check(lib.sv_tune_engine_set(_SV_DT[dtype], int(bool(with_grad)), int(tile_qubits), int(amps_per_thread)))
 
 
-def tune_engine_get(dtype: str) -> Tuple[int, int]:
-    """(tile_qubits, amps_per_thread) a batch with default options gets."""
+def tune_engine_get(dtype: str, with_grad: bool) -> Tuple[int, int]:
+    """(tile_qubits, amps_per_thread) a batch with default shape options gets."""
     t, a = ctypes.c_int(), ctypes.c_int()
-    check(lib.sv_tune_engine_get(_SV_DT[dtype], ctypes.byref(t), ctypes.byref(a)))
+    check(lib.sv_tune_engine_get(_SV_DT[dtype], int(bool(with_grad)), ctypes.byref(t), ctypes.byref(a)))
     return t.value, a.value
 
 

@@ -100,8 +100,8 @@ def _load():
         "sv_batch_copy_state": [vp, i, vp, ctypes.c_size_t],
         "sv_tune_set": [i, i, i, i, i, i],
         "sv_tune_get": [i, i, i, ip, ip, ip],
-        "sv_tune_engine_set": [i, i, i],
-        "sv_tune_engine_get": [i, ip, ip],
+        "sv_tune_engine_set": [i, i, i, i],
+        "sv_tune_engine_get": [i, i, ip, ip],
         "sv_plan_info": [i, i, i, ip, i, ip, i, ip, ip, ip, ip, ip, ip],
     }
     for name, args in sig.items():

@@ -5,12 +5,13 @@ two-target, general), both dtypes and the three run-length tiers (bytes
 spanned by a run of consecutive touched amplitudes: < 64 B, < 1 KiB, larger),
 it times representative gates under each candidate shape
 (block x groups-per-thread x non-temporal flag) with HIP events and keeps the
-fastest.  For the fused pass engine it times, per dtype, every tile shape
-(tile qubits x amplitudes per thread) on three workloads: the adjoint
-gradient of a 24-qubit, 8-layer hardware-efficient ansatz, a batch of 256
-such circuits of 14-22 qubits with forward, observable and adjoint stages,
-and the adjoint gradient of a 28-qubit, 4-layer one (a state far larger
-than the caches).  The
+fastest.  For the fused pass engine it times every tile shape (tile qubits x
+amplitudes per thread), per dtype and per stage mix.  Batches with the
+adjoint sweep are timed on the adjoint gradient of a 24-qubit, 8-layer
+hardware-efficient ansatz, on a batch of 256 such circuits of 14-22 qubits
+and on the adjoint gradient of a 28-qubit, 4-layer one (a state far larger
+than the caches).  Forward-only batches are timed on a 30-qubit, 10-layer
+ansatz, a 30-qubit QFT and the same batch of 256 without the adjoint.  The
 result is written as JSON next to the library and loaded by
 ``paper_2508_13615_amd`` at import (``apply_table``).
 
@@ -39,7 +40,7 @@ def apply_table(sv, path: str = TABLE) -> int:
     for e in tab["entries"]:
         sv.tune_set(e["class"], e["dtype"], e["tier"], e["block"], e["unroll"], e["nt"])
     for e in tab.get("engine", []):
-        sv.tune_engine_set(e["dtype"], e["tile_qubits"], e["amps_per_thread"])
+        sv.tune_engine_set(e["dtype"], e["with_grad"], e["tile_qubits"], e["amps_per_thread"])
     return len(tab["entries"]) + len(tab.get("engine", []))
 
 
@@ -160,19 +161,23 @@ ENGINE_SHAPES = {dt: [(t, a) for a in (8, 16) for t in range(9, 14) if _engine_s
                  for dt in ("c128", "c64")}
 
 
-def _engine_workloads():
-    """(name, circuits) pairs: circuits as sv.Batch takes them."""
+def _engine_workloads(with_grad: bool):
+    """(name, circuits) pairs for one stage mix: circuits as sv.Batch takes them."""
     import workloads as W
-    hea = [(24, W.hea_ops(24, 8), W.hea_n_params(24, 8), "sum_zz")]
     spec = W.batch_spec(256, 1006, 14, 22, 4, 12)
     batch = [(c.n, W.hea_ops(c.n, c.layers), len(c.params), "sum_z") for c in spec]
-    big = [(28, W.hea_ops(28, 4), W.hea_n_params(28, 4), "sum_zz")]
-    return [("adjoint_hea24", hea), ("batch256", batch), ("adjoint_hea28", big)]
+    if with_grad:
+        return [("adjoint_hea24", [(24, W.hea_ops(24, 8), W.hea_n_params(24, 8), "sum_zz")]),
+                ("batch256", batch),
+                ("adjoint_hea28", [(28, W.hea_ops(28, 4), W.hea_n_params(28, 4), "sum_zz")])]
+    return [("hea30", [(30, W.hea_ops(30, 10), W.hea_n_params(30, 10), "sum_z")]),
+            ("qft30", [(30, [W.Op("H", (), (q,)) for q in range(30)] + W.qft_ops(30), 0, "sum_z")]),
+            ("batch256_forward", batch)]
 
 
-def _time_engine(sv, circuits, dtype, shape, reps):
+def _time_engine(sv, circuits, dtype, shape, reps, with_grad=True):
     import numpy as np
-    b = sv.Batch(circuits, dtype, tile_qubits=shape[0], amps_per_thread=shape[1], with_grad=True)
+    b = sv.Batch(circuits, dtype, tile_qubits=shape[0], amps_per_thread=shape[1], with_grad=with_grad)
     params = np.random.default_rng(7).uniform(0, 2 * np.pi, sum(c[2] for c in circuits))
     b.run(params)  # capture + first replay
     times = []
@@ -185,43 +190,46 @@ def _time_engine(sv, circuits, dtype, shape, reps):
 
 
 def tune_engine(reps: int = 5, dtypes=("c128", "c64"), log=print, margin: float = 0.02) -> list:
-    """Per dtype: each shape's time on each workload, relative to the built-in
-    default shape, averaged over the workloads; the best replaces the default
-    only if it is `margin` faster.  Wall time of synchronous runs (parameters
-    uploaded, expectation values and gradients read back) is what a caller sees."""
+    """Per dtype and stage mix: each shape's time on each workload of that mix,
+    relative to the built-in default shape, averaged over the workloads; the
+    best replaces the default only if it is `margin` faster.  Wall time of
+    synchronous runs (parameters uploaded, expectation values and gradients
+    read back) is what a caller sees."""
     import numpy as np
     import torch
 
     import paper_2508_13615_amd as sv
 
     out = []
-    work = _engine_workloads()
     for dtype in dtypes:
-        sv.tune_engine_set(dtype, 0, 0)
-        default = sv.tune_engine_get(dtype)
-        shapes = ENGINE_SHAPES[dtype]
-        if default not in shapes:
-            shapes = shapes + [default]
-        t = {sh: {} for sh in shapes}
-        for name, circs in work:
-            for _ in range(2):  # two interleaved rounds, the faster kept
-                for sh in shapes:
-                    v = _time_engine(sv, circs, dtype, sh, reps)
-                    t[sh][name] = min(v, t[sh].get(name, float("inf")))
-            torch.cuda.empty_cache()
-            log(f"[autotune] engine {dtype} {name}: {len(shapes)} shapes timed")
-        score = {sh: float(np.mean([t[sh][n] / t[default][n] for n, _ in work])) for sh in shapes}
-        for sh in shapes:
-            log(f"[autotune] engine {dtype} tile_qubits {sh[0]:2d} amps_per_thread {sh[1]:2d}: "
-                + ", ".join(f"{n} {t[sh][n] * 1e3:.2f} ms" for n, _ in work) + f" (relative {score[sh]:.3f})")
-        best = min(score, key=score.get)
-        if score[best] > 1.0 - margin:
-            best = default
-        sv.tune_engine_set(dtype, *best)
-        out.append({"dtype": dtype, "tile_qubits": best[0], "amps_per_thread": best[1],
-                    "relative_to_default": score[best], "default": list(default),
-                    "ms": {f"{sh[0]}x{sh[1]}": {n: t[sh][n] * 1e3 for n, _ in work} for sh in shapes}})
-        log(f"[autotune] engine {dtype}: tile_qubits {best[0]} amps_per_thread {best[1]}")
+        for grad in (True, False):
+            mix = "adjoint" if grad else "forward"
+            work = _engine_workloads(grad)
+            sv.tune_engine_set(dtype, grad, 0, 0)
+            default = sv.tune_engine_get(dtype, grad)
+            shapes = ENGINE_SHAPES[dtype]
+            if default not in shapes:
+                shapes = shapes + [default]
+            t = {sh: {} for sh in shapes}
+            for name, circs in work:
+                for _ in range(2):  # two interleaved rounds, the faster kept
+                    for sh in shapes:
+                        v = _time_engine(sv, circs, dtype, sh, reps, grad)
+                        t[sh][name] = min(v, t[sh].get(name, float("inf")))
+                torch.cuda.empty_cache()
+                log(f"[autotune] engine {dtype} {mix} {name}: {len(shapes)} shapes timed")
+            score = {sh: float(np.mean([t[sh][n] / t[default][n] for n, _ in work])) for sh in shapes}
+            for sh in shapes:
+                log(f"[autotune] engine {dtype} {mix} tile_qubits {sh[0]:2d} amps_per_thread {sh[1]:2d}: "
+                    + ", ".join(f"{n} {t[sh][n] * 1e3:.2f} ms" for n, _ in work) + f" (relative {score[sh]:.3f})")
+            best = min(score, key=score.get)
+            if score[best] > 1.0 - margin:
+                best = default
+            sv.tune_engine_set(dtype, grad, *best)
+            out.append({"dtype": dtype, "with_grad": int(grad), "tile_qubits": best[0], "amps_per_thread": best[1],
+                        "relative_to_default": score[best], "default": list(default),
+                        "ms": {f"{sh[0]}x{sh[1]}": {n: t[sh][n] * 1e3 for n, _ in work} for sh in shapes}})
+            log(f"[autotune] engine {dtype} {mix}: tile_qubits {best[0]} amps_per_thread {best[1]}")
     return out
 
 

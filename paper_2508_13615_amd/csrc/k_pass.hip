@@ -617,13 +617,13 @@ __device__ __forceinline__ void flush_slots(const PassTables& tb, const FCirc& c
                                             int tile, const double* wpart)
 {
     if (threadIdx.x != 0) return;
-    const int nwaves = (blockDim.x + 63) >> 6;
+    const int nwaves = blockDim.x >> 6;
     int k = 0;
     for (int o = op_end - 1; o >= op_begin; --o) {
         const FOp op = ld_const(as_const(tb.ops) + o);
         if (op.kind == FK_LAYOUT || op.slot < 0) continue;
         double s = 0.0;
-        for (int w = 0; w < nwaves; ++w) s += wpart[k * 16 + w];
+        for (int w = 0; w < nwaves; ++w) s += wpart[k * nwaves + w];
         tb.g_part[cc.g_part_begin + (int64_t)op.slot * cc.n_tiles + tile] = s;
         ++k;
     }
@@ -800,7 +800,7 @@ __device__ __forceinline__ void item_reg_rev(const PassTables& tb, const FCirc& 
         }
         if (op.slot >= 0) {
             const double c = wave_sum(active ? reg_gen_inner<T, RB>(v, w, op, tl) : 0.0);
-            if ((threadIdx.x & 63) == 0) wpart[nslot * 16 + (threadIdx.x >> 6)] = c;
+            if ((threadIdx.x & 63) == 0) wpart[nslot * (blockDim.x >> 6) + (threadIdx.x >> 6)] = c;
             ++nslot;
         }
         if (op.kind == FK_SWAP || op.kind == FK_QUAD) {
@@ -915,7 +915,7 @@ __device__ __forceinline__ void item_lds(const PassTables& tb, const FCirc& cc, 
         const FOp op = tb.ops[o];
         if (op.slot >= 0) {
             const double c = wave_sum(lds_gen_inner<T>(tileA, tileB, op, tq));
-            if ((threadIdx.x & 63) == 0) wpart[nslot * 16 + (threadIdx.x >> 6)] = c;
+            if ((threadIdx.x & 63) == 0) wpart[nslot * (blockDim.x >> 6) + (threadIdx.x >> 6)] = c;
             ++nslot;
             __syncthreads();  // every read of the tiles precedes the un-apply below
         }
@@ -931,13 +931,12 @@ __device__ __forceinline__ void item_lds(const PassTables& tb, const FCirc& cc, 
     }
 }
 
-// LDS of a run: [tiles][address map][per-slot wave partials][block sum scratch]
+// LDS of a run: [tiles][address map][per-slot wave partials (reverse only)]
 struct EngineLds {
     void* tileA;
     void* tileB;
     uint64_t* hi_map;
-    double* wpart;  // [kMaxPassSlots][16 waves]
-    double* red;
+    double* wpart;  // [kMaxPassSlots][waves of the workgroup]
 };
 
 template <typename T>
@@ -951,7 +950,6 @@ __device__ __forceinline__ EngineLds engine_lds(const PassTables& tb, double* sm
     e.tileB = a + tile_elems;
     e.hi_map = (uint64_t*)(a + (tb.lds_small && tb.with_grad ? 2 * tile_elems : tile_elems));
     e.wpart = (double*)(e.hi_map + (tb.lds_small ? tb.hi_entries : 0));
-    e.red = e.wpart + kMaxPassSlots * 16;
     return e;
 }
 
@@ -968,17 +966,20 @@ __device__ __forceinline__ FSeg seg_of(const PassTables& tb, int64_t item)
     return ld_const(segs + lo);
 }
 
-// Target waves per SIMD (which sets the VGPR budget: 512 / waves).  Forward
-// complex64 passes fit 128 VGPRs, so two 512-thread workgroups share a CU;
-// the others need more registers than that without spilling.
-template <typename T, bool REV>
+// Target waves per SIMD, which sets the VGPR budget (512 / waves).  Forward
+// complex64 passes and 8-amplitude complex128 forward passes fit 128 VGPRs;
+// the complex128 kernels with 16 amplitudes (forward) or 2 x 8 (reverse)
+// fit 168 with a few spilled registers; complex64 reverse passes with 2 x 16
+// amplitudes need the 256 of two waves.
+template <typename T, int RB, bool REV>
 constexpr int pass_waves_per_eu()
 {
-    return (!REV && sizeof(T) == 4) ? 4 : 2;
+    if constexpr (sizeof(T) == 4) return REV && RB == 4 ? 2 : 4;
+    else return !REV && RB == 3 ? 4 : 3;
 }
 
 template <typename T, int RB>
-__global__ void __launch_bounds__(kMaxPassThreads, (pass_waves_per_eu<T, false>()))
+__global__ void __launch_bounds__(kMaxPassThreads, (pass_waves_per_eu<T, RB, false>()))
 k_pass_fwd(PassTables tb, int64_t item_begin, int64_t item_end)
 {
     using V = typename Vec2<T>::type;
@@ -1007,7 +1008,7 @@ k_pass_obs(PassTables tb, int64_t item_begin, int64_t item_end)
 }
 
 template <typename T, int RB>
-__global__ void __launch_bounds__(kMaxPassThreads, (pass_waves_per_eu<T, true>()))
+__global__ void __launch_bounds__(kMaxPassThreads, (pass_waves_per_eu<T, RB, true>()))
 k_pass_rev(PassTables tb, int64_t item_begin, int64_t item_end)
 {
     using V = typename Vec2<T>::type;
@@ -1138,44 +1139,29 @@ int pass_engine_threads(int tq_max, int reg_bits)
     return t < 64 ? 64 : t;
 }
 
-size_t pass_engine_lds_bytes(int tq_max, int hi_entries, int with_grad, int dtype, int lds_small)
+size_t pass_engine_lds_bytes(int tq_max, int hi_entries, int with_grad, int dtype, int lds_small, int slot_waves)
 {
     const size_t eb = dtype == SV_C128 ? 16 : 8;
     const size_t tiles = (size_t)1 << tq_max;
     return eb * tiles * (lds_small && with_grad ? 2 : 1) + (lds_small ? 8 * (size_t)hi_entries : 0) +
-           8 * (size_t)kMaxPassSlots * 16 + 8 * 16;
+           8 * (size_t)kMaxPassSlots * slot_waves;
 }
 
-template <typename T>
-static const void* fwd_fn(int rb)
+// The dynamic-LDS limit only grows: batches that are alive at the same time
+// launch the same kernels with different LDS sizes.
+hipError_t pass_engine_prepare(size_t lds_bytes)
 {
-    return rb == 3 ? (const void*)k_pass_fwd<T, 3> : (const void*)k_pass_fwd<T, 4>;
-}
-
-// complex128 reverse passes always hold 8 amplitudes of phi and of lambda per thread
-template <typename T>
-static const void* rev_fn(int rb)
-{
-    if constexpr (sizeof(T) == 8) return (void)rb, (const void*)k_pass_rev<T, 3>;
-    else return rb == 3 ? (const void*)k_pass_rev<T, 3> : (const void*)k_pass_rev<T, 4>;
-}
-
-hipError_t pass_engine_prepare(int dtype, int reg_bits, int rreg_bits, size_t lds_bytes)
-{
-    const void* f[3];
-    if (dtype == SV_C128) {
-        f[0] = fwd_fn<double>(reg_bits);
-        f[1] = (const void*)k_pass_obs<double>;
-        f[2] = rev_fn<double>(rreg_bits);
-    } else {
-        f[0] = fwd_fn<float>(reg_bits);
-        f[1] = (const void*)k_pass_obs<float>;
-        f[2] = rev_fn<float>(rreg_bits);
-    }
+    static size_t limit = 0;
+    if (lds_bytes <= limit) return hipSuccess;
+    const void* f[] = {(const void*)k_pass_fwd<double, 3>, (const void*)k_pass_fwd<double, 4>,
+                       (const void*)k_pass_rev<double, 3>, (const void*)k_pass_fwd<float, 3>,
+                       (const void*)k_pass_fwd<float, 4>,  (const void*)k_pass_rev<float, 3>,
+                       (const void*)k_pass_rev<float, 4>};
     for (const void* k : f) {
         const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
         if (e != hipSuccess) return e;
     }
+    limit = lds_bytes;
     return hipSuccess;
 }
 

@@ -386,7 +386,7 @@ struct sv_batch_s {
     int use_graph;
     int threads, rthreads;
     int reg_bits, rreg_bits;
-    size_t lds;
+    size_t lds_fwd, lds_rev;  // dynamic LDS of forward and reverse workgroups
     std::vector<int64_t> level_first;  // per level: forward, observable, reverse item ranges (4 bounds)
     int64_t n_items;
     int n_segs;
@@ -467,9 +467,10 @@ hipError_t enqueue_run(sv_batch b)
                                     b->dtype == SV_C64 ? b->d_coef_f : nullptr, s);
     const std::vector<int64_t>& lf = b->level_first;
     for (size_t l = 0; l + 3 < lf.size() && e == hipSuccess; l += 3) {
-        e = launch_pass_items(b->tb, b->dtype, PM_FWD, lf[l], lf[l + 1], b->threads, b->lds, s);
-        if (e == hipSuccess) e = launch_pass_items(b->tb, b->dtype, PM_OBS, lf[l + 1], lf[l + 2], b->threads, b->lds, s);
-        if (e == hipSuccess) e = launch_pass_items(b->tb, b->dtype, PM_REV, lf[l + 2], lf[l + 3], b->rthreads, b->lds, s);
+        e = launch_pass_items(b->tb, b->dtype, PM_FWD, lf[l], lf[l + 1], b->threads, b->lds_fwd, s);
+        if (e == hipSuccess) e = launch_pass_items(b->tb, b->dtype, PM_OBS, lf[l + 1], lf[l + 2], b->threads, 0, s);
+        if (e == hipSuccess)
+            e = launch_pass_items(b->tb, b->dtype, PM_REV, lf[l + 2], lf[l + 3], b->rthreads, b->lds_rev, s);
     }
     if (e == hipSuccess) e = launch_pass_segsum(b->d_epart, b->d_e_off, b->d_e_cnt, nullptr, b->d_expvals, b->n_circ, s);
     if (e == hipSuccess && b->with_grad) {
@@ -506,10 +507,11 @@ struct HostTables {
     std::vector<size_t> psi_off;
 };
 
-// Engine tile shape per dtype (index 0 complex64, 1 complex128) used where
-// sv_batch_opts leaves a field 0; 0 here means the built-in default.
-static int g_engine_tq[2] = {0, 0};
-static int g_engine_apt[2] = {0, 0};
+// Engine tile shape per dtype (index 0 complex64, 1 complex128) and stage mix
+// (index 0 forward only, 1 with the adjoint sweep) used where sv_batch_opts
+// leaves a field 0; 0 here means the built-in default.
+static int g_engine_tq[2][2] = {{0, 0}, {0, 0}};
+static int g_engine_apt[2][2] = {{0, 0}, {0, 0}};
 
 // Largest tile whose forward and reverse workgroups stay within kMaxPassThreads.
 static int engine_tq_fit(int reg_bits, int rreg_bits)
@@ -525,8 +527,9 @@ static sv_status compile_batch(const sv_batch_circuit* circuits, int n_circuits,
     if (!circuits || n_circuits < 1) return set_error(SV_ERR_ARG, "bad batch arguments");
     if (dtype != SV_C64 && dtype != SV_C128) return set_error(SV_ERR_ARG, "bad dtype");
     const int d = dtype == SV_C128 ? 1 : 0;
+    const int with_grad = opts ? (opts->with_grad != 0) : 1;
     const int apt = opts && opts->amps_per_thread > 0 ? opts->amps_per_thread
-                    : g_engine_apt[d] > 0              ? g_engine_apt[d]
+                    : g_engine_apt[d][with_grad] > 0   ? g_engine_apt[d][with_grad]
                                                        : (1 << kMaxRegBits);
     int reg_bits = 0;
     for (int r = kMinRegBits; r <= kMaxRegBits; ++r)
@@ -536,11 +539,10 @@ static sv_status compile_batch(const sv_batch_circuit* circuits, int n_circuits,
     const int rreg_bits = dtype == SV_C128 ? std::min(reg_bits, 3) : reg_bits;
     // default tile: the tuned one, else 64 KiB (2^12 complex128 / 2^13 complex64
     // amplitudes); either within kMaxPassThreads threads of the narrower register width
-    const int tq_base = g_engine_tq[d] > 0 ? g_engine_tq[d] : (dtype == SV_C128 ? 12 : 13);
+    const int tq_base = g_engine_tq[d][with_grad] > 0 ? g_engine_tq[d][with_grad] : (dtype == SV_C128 ? 12 : 13);
     const int tq_default = std::min(tq_base, engine_tq_fit(reg_bits, rreg_bits));
     int tq_max = opts && opts->tile_qubits > 0 ? opts->tile_qubits : tq_default;
     if (tq_max < 2 || tq_max > kMaxTileQubits) return set_error(SV_ERR_ARG, "tile_qubits must be in [2, 13]");
-    const int with_grad = opts ? (opts->with_grad != 0) : 1;
     const int cbits_default = dtype == SV_C128 ? 3 : 4;  // 128-byte runs
 
     // ---- validate and schedule ----------------------------------------------------
@@ -789,9 +791,18 @@ static sv_status compile_batch(const sv_batch_circuit* circuits, int n_circuits,
     return SV_OK;
 }
 
-sv_status sv_tune_engine_set(int dtype, int tile_qubits, int amps_per_thread)
+// Largest dynamic LDS a workgroup of the batch uses (reverse passes hold the
+// per-slot wave partials on top of the forward layout).
+static size_t engine_lds_max(const HostTables& H, int dtype)
+{
+    return pass_engine_lds_bytes(H.tq_used, H.hi_entries, H.with_grad, dtype, H.lds_small,
+                                 H.with_grad ? H.rthreads / 64 : 0);
+}
+
+sv_status sv_tune_engine_set(int dtype, int with_grad, int tile_qubits, int amps_per_thread)
 {
     if (dtype != SV_C64 && dtype != SV_C128) return set_error(SV_ERR_ARG, "bad dtype");
+    if (with_grad != 0 && with_grad != 1) return set_error(SV_ERR_ARG, "with_grad must be 0 or 1");
     if (amps_per_thread != 0 && amps_per_thread != 8 && amps_per_thread != 16)
         return set_error(SV_ERR_ARG, "amps_per_thread must be 0, 8 or 16");
     if (tile_qubits != 0 && (tile_qubits < 2 || tile_qubits > kMaxTileQubits))
@@ -803,19 +814,20 @@ sv_status sv_tune_engine_set(int dtype, int tile_qubits, int amps_per_thread)
             return set_error(SV_ERR_ARG, "tile_qubits too large for amps_per_thread (at most 512 threads per tile)");
     }
     const int d = dtype == SV_C128 ? 1 : 0;
-    g_engine_tq[d] = tile_qubits;
-    g_engine_apt[d] = amps_per_thread;
+    g_engine_tq[d][with_grad] = tile_qubits;
+    g_engine_apt[d][with_grad] = amps_per_thread;
     return SV_OK;
 }
 
-sv_status sv_tune_engine_get(int dtype, int* tile_qubits, int* amps_per_thread)
+sv_status sv_tune_engine_get(int dtype, int with_grad, int* tile_qubits, int* amps_per_thread)
 {
-    if ((dtype != SV_C64 && dtype != SV_C128) || !tile_qubits || !amps_per_thread)
-        return set_error(SV_ERR_ARG, "bad dtype or null output");
+    if ((dtype != SV_C64 && dtype != SV_C128) || (with_grad != 0 && with_grad != 1) || !tile_qubits ||
+        !amps_per_thread)
+        return set_error(SV_ERR_ARG, "bad dtype, with_grad or null output");
     const int d = dtype == SV_C128 ? 1 : 0;
-    const int rb = g_engine_apt[d] == 8 ? 3 : 4;
+    const int rb = g_engine_apt[d][with_grad] == 8 ? 3 : 4;
     const int rrb = dtype == SV_C128 ? std::min(rb, 3) : rb;
-    const int tq_base = g_engine_tq[d] > 0 ? g_engine_tq[d] : (dtype == SV_C128 ? 12 : 13);
+    const int tq_base = g_engine_tq[d][with_grad] > 0 ? g_engine_tq[d][with_grad] : (dtype == SV_C128 ? 12 : 13);
     *tile_qubits = std::min(tq_base, engine_tq_fit(rb, rrb));
     *amps_per_thread = 1 << rb;
     return SV_OK;
@@ -840,7 +852,7 @@ sv_status sv_batch_plan(const sv_batch_circuit* circuits, int n_circuits, sv_dty
     info[6] = (int64_t)H.state_total;
     info[7] = (int64_t)H.pass_bytes;
     info[8] = H.n_levels;
-    info[9] = (int64_t)pass_engine_lds_bytes(H.tq_used, H.hi_entries, H.with_grad, dtype, H.lds_small);
+    info[9] = (int64_t)engine_lds_max(H, dtype);
     info[10] = H.n_layout_changes;
     info[11] = H.threads;
     return SV_OK;
@@ -964,8 +976,9 @@ sv_status sv_batch_create(const sv_batch_circuit* circuits, int n_circuits, sv_d
     tb.reg_bits = H.reg_bits;
     tb.rreg_bits = H.rreg_bits;
     tb.lds_small = H.lds_small;
-    b->lds = pass_engine_lds_bytes(tq_used, hi_entries, with_grad, dtype, H.lds_small);
-    e = pass_engine_prepare(dtype, H.reg_bits, H.rreg_bits, b->lds);
+    b->lds_fwd = pass_engine_lds_bytes(tq_used, hi_entries, with_grad, dtype, H.lds_small, 0);
+    b->lds_rev = pass_engine_lds_bytes(tq_used, hi_entries, with_grad, dtype, H.lds_small, H.rthreads / 64);
+    e = pass_engine_prepare(engine_lds_max(H, dtype));
     if (e != hipSuccess) {
         batch_release(b);
         return hip_fail(e, "pass engine LDS limit");
@@ -1027,7 +1040,7 @@ sv_status sv_batch_info(sv_batch b, int64_t* info)
     info[6] = (int64_t)b->state_bytes;
     info[7] = (int64_t)b->pass_bytes;
     info[8] = b->n_levels;
-    info[9] = (int64_t)b->lds;
+    info[9] = (int64_t)std::max(b->lds_fwd, b->with_grad ? b->lds_rev : 0);
     info[10] = b->n_layout_changes;
     info[11] = b->threads;
     return SV_OK;

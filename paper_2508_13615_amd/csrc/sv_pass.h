@@ -134,8 +134,9 @@ struct PassTables {
 };
 
 enum PassMode : int { PM_FWD = 0, PM_OBS = 1, PM_REV = 2 };
-// Set the engine kernels' dynamic LDS limit (once, outside any graph capture).
-hipError_t pass_engine_prepare(int dtype, int reg_bits, int rreg_bits, size_t lds_bytes);
+// Raise the engine kernels' dynamic LDS limit to at least lds_bytes (outside
+// any graph capture).
+hipError_t pass_engine_prepare(size_t lds_bytes);
 // Items [item_begin, item_end), all of stage kind `mode`, one workgroup per tile.
 hipError_t launch_pass_items(const PassTables& tb, int dtype, int mode, int64_t item_begin, int64_t item_end,
                              int threads, size_t lds_bytes, hipStream_t s);
@@ -145,7 +146,9 @@ hipError_t launch_pass_segsum(const double* part, const int64_t* off, const int*
                               int n_seg, hipStream_t s);
 hipError_t launch_pass_grad_csr(const double* slot_val, const int* rowptr, const int* cols, int n_params, double* grad,
                                 hipStream_t s);
-size_t pass_engine_lds_bytes(int tq_max, int hi_entries, int with_grad, int dtype, int lds_small);
+// Dynamic LDS of a pass workgroup: tiles and address map, plus per-slot wave
+// partials for slot_waves waves (reverse passes; 0 for forward ones).
+size_t pass_engine_lds_bytes(int tq_max, int hi_entries, int with_grad, int dtype, int lds_small, int slot_waves);
 // Workgroup size for register width rb: 2^(tq_max - rb), at least one wavefront.
 int pass_engine_threads(int tq_max, int reg_bits);
 

@@ -212,30 +212,35 @@ def test_batch_plan_fuses_gates_host_only():
 
 
 def test_engine_tile_shape_tuning_host_only():
-    # Zeroed batch options take the engine shape of sv_tune_engine_set; shapes
-    # that break the 512-thread limit or the allowed values are refused and
-    # leave the setting unchanged.
+    # Zeroed batch shape options take the engine shape of sv_tune_engine_set
+    # for the batch's dtype and stage mix; shapes that break the 512-thread
+    # limit or the allowed values are refused and leave the setting unchanged.
     import workloads as W
     circ = [(16, W.hea_ops(16, 2), W.hea_n_params(16, 2), "sum_z")]
-    saved = {dt: sv.tune_engine_get(dt) for dt in ("c128", "c64")}
+    keys = [(dt, g) for dt in ("c128", "c64") for g in (False, True)]
+    saved = {k: sv.tune_engine_get(*k) for k in keys}
     try:
-        sv.tune_engine_set("c128", 0, 0)
-        assert sv.tune_engine_get("c128") == (12, 16)
-        sv.tune_engine_set("c64", 0, 0)
-        assert sv.tune_engine_get("c64") == (13, 16)
-        sv.tune_engine_set("c64", 0, 8)  # 13 would need 1024 threads of 8 amplitudes
-        assert sv.tune_engine_get("c64") == (12, 8)
-        sv.tune_engine_set("c128", 10, 8)
-        p = sv.batch_plan(circ, "c128")
+        for k in keys:
+            sv.tune_engine_set(*k, 0, 0)
+        assert sv.tune_engine_get("c128", True) == (12, 16)
+        assert sv.tune_engine_get("c64", False) == (13, 16)
+        sv.tune_engine_set("c64", False, 0, 8)  # 13 would need 1024 threads of 8 amplitudes
+        assert sv.tune_engine_get("c64", False) == (12, 8)
+        sv.tune_engine_set("c128", True, 10, 8)
+        sv.tune_engine_set("c128", False, 11, 16)
+        p = sv.batch_plan(circ, "c128", with_grad=True)
         assert p["threads"] == 2 ** 10 // 8 and p["items"] % 2 ** 6 == 0
+        p = sv.batch_plan(circ, "c128", with_grad=False)
+        assert p["threads"] == 2 ** 11 // 16 and p["items"] % 2 ** 5 == 0
         explicit = sv.batch_plan(circ, "c128", tile_qubits=12, amps_per_thread=16)
         assert explicit["threads"] == 2 ** 12 // 16
         for dt, tq, apt in (("c128", 13, 16), ("c128", 13, 8), ("c64", 13, 8), ("c128", 1, 16), ("c128", 14, 0),
                             ("c128", 12, 4), ("c64", 0, 32)):
             with pytest.raises(sv.SvError):
-                sv.tune_engine_set(dt, tq, apt)
-        assert sv.tune_engine_get("c128") == (10, 8)
-        assert sv.lib.sv_tune_engine_set(7, 0, 0) == ARG  # bad dtype
+                sv.tune_engine_set(dt, True, tq, apt)
+        assert sv.tune_engine_get("c128", True) == (10, 8)
+        assert sv.lib.sv_tune_engine_set(7, 1, 0, 0) == ARG  # bad dtype
+        assert sv.lib.sv_tune_engine_set(2, 2, 0, 0) == ARG  # with_grad not 0/1
     finally:
-        for dt, (tq, apt) in saved.items():
-            sv.tune_engine_set(dt, tq, apt)
+        for k, (tq, apt) in saved.items():
+            sv.tune_engine_set(*k, tq, apt)
