@@ -58,12 +58,23 @@ __device__ __forceinline__ X ld_const(cptr<X> p)
     return u.x;
 }
 
+__device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// (ar + i ai) a + (br + i bi) b.  In double precision as one multiply and
+// three fused multiply-adds per component: those kernels are bound by vector
+// instruction issue.  The float kernels are bound by dependency latency, and
+// the shorter chains of two products summed suit them better.
 template <typename V, typename T>
 __device__ __forceinline__ V cmul_add2(T ar_, T ai_, V a, T br_, T bi_, V b)
 {
     V r;
-    r.x = (ar_ * a.x - ai_ * a.y) + (br_ * b.x - bi_ * b.y);
-    r.y = (ar_ * a.y + ai_ * a.x) + (br_ * b.y + bi_ * b.x);
+    if constexpr (sizeof(T) == 8) {
+        r.x = fmadd(ar_, a.x, fmadd(-ai_, a.y, fmadd(br_, b.x, -bi_ * b.y)));
+        r.y = fmadd(ar_, a.y, fmadd(ai_, a.x, fmadd(br_, b.y, bi_ * b.x)));
+    } else {
+        r.x = (ar_ * a.x - ai_ * a.y) + (br_ * b.x - bi_ * b.y);
+        r.y = (ar_ * a.y + ai_ * a.x) + (br_ * b.y + bi_ * b.x);
+    }
     return r;
 }
 
@@ -319,13 +330,24 @@ __device__ __forceinline__ void lds_get(const V* __restrict__ lds, V* v, uint32_
 // scalar registers free across the op loop.
 
 // Complex 2x2 on register bit K.
+// Register-bit control test of register j (a uniform value).  The empty
+// volatile asm on the passing side keeps it a scalar branch: without it the
+// compiler evaluates the gate for every register and selects per lane, which
+// costs more vector instructions than the gate on the passing registers.
+__device__ __forceinline__ bool skip_reg(int j, uint32_t cmk)
+{
+    if (((uint32_t)j & cmk) != cmk) return true;
+    asm volatile("");
+    return false;
+}
+
 template <typename T, int RB, int K, bool CHK>
 __device__ __forceinline__ void rpair_k(typename Vec2<T>::type* v, const T* u, uint32_t cmk)
 {
 #pragma unroll
     for (int j = 0; j < (1 << RB); ++j) {
         if (j & (1 << K)) continue;
-        if (CHK && (j & cmk) != cmk) continue;
+        if (CHK && skip_reg(j, cmk)) continue;
         const int j1 = j | (1 << K);
         const auto a = v[j], b = v[j1];
         v[j] = cmul_add2<typename Vec2<T>::type, T>(u[0], u[1], a, u[2], u[3], b);
@@ -340,7 +362,7 @@ __device__ __forceinline__ void rpairr_k(typename Vec2<T>::type* v, const T* r, 
 #pragma unroll
     for (int j = 0; j < (1 << RB); ++j) {
         if (j & (1 << K)) continue;
-        if (CHK && (j & cmk) != cmk) continue;
+        if (CHK && skip_reg(j, cmk)) continue;
         const int j1 = j | (1 << K);
         const auto a = v[j], b = v[j1];
         v[j].x = r[0] * a.x + r[1] * b.x;
@@ -357,7 +379,7 @@ __device__ __forceinline__ void rpairx_k(typename Vec2<T>::type* v, bool ok, uin
 #pragma unroll
     for (int j = 0; j < (1 << RB); ++j) {
         if (j & (1 << K)) continue;
-        if (CHK && (j & cmk) != cmk) continue;
+        if (CHK && skip_reg(j, cmk)) continue;
         const int j1 = j | (1 << K);
         const auto a = v[j], b = v[j1];
         if constexpr (SEL) {
@@ -378,7 +400,7 @@ __device__ __forceinline__ void rdiag_k(typename Vec2<T>::type* v, const T* d, u
 {
 #pragma unroll
     for (int j = 0; j < (1 << RB); ++j) {
-        if (CHK && (j & cmk) != cmk) continue;
+        if (CHK && skip_reg(j, cmk)) continue;
         const T zr = (j >> K) & 1 ? d[2] : d[0], zi = (j >> K) & 1 ? d[3] : d[1];
         const auto x = v[j];
         v[j].x = zr * x.x - zi * x.y;
@@ -392,7 +414,7 @@ __device__ __forceinline__ void rphase(typename Vec2<T>::type* v, T zr, T zi, ui
 {
 #pragma unroll
     for (int j = 0; j < (1 << RB); ++j) {
-        if (CHK && (j & cmk) != cmk) continue;
+        if (CHK && skip_reg(j, cmk)) continue;
         const auto x = v[j];
         v[j].x = zr * x.x - zi * x.y;
         v[j].y = zr * x.y + zi * x.x;
@@ -405,7 +427,7 @@ __device__ __forceinline__ void rswap_k(typename Vec2<T>::type* v, bool ok, uint
 #pragma unroll
     for (int j = 0; j < (1 << RB); ++j) {
         if (!(j & (1 << KA)) || (j & (1 << KB))) continue;  // j: bit a = 1, bit b = 0
-        if (CHK && (j & cmk) != cmk) continue;
+        if (CHK && skip_reg(j, cmk)) continue;
         const int j1 = j ^ (1 << KA) ^ (1 << KB);
         const auto a = v[j], b = v[j1];
         if constexpr (SEL) {
@@ -553,7 +575,7 @@ __device__ __forceinline__ double rgen_pair_k(const typename Vec2<T>::type* P, c
 #pragma unroll
     for (int j = 0; j < (1 << RB); ++j) {
         if (j & (1 << K)) continue;
-        if (CHK && (j & cmk) != cmk) continue;
+        if (CHK && skip_reg(j, cmk)) continue;
         const int j1 = j | (1 << K);
         const double a0r = P[j].x, a0i = P[j].y, a1r = P[j1].x, a1i = P[j1].y;
         const double l0r = L[j].x, l0i = L[j].y, l1r = L[j1].x, l1i = L[j1].y;
@@ -572,7 +594,7 @@ __device__ __forceinline__ double rgen_elem(const typename Vec2<T>::type* P, con
     double acc = 0.0;
 #pragma unroll
     for (int j = 0; j < (1 << RB); ++j) {
-        if (CHK && (j & cmk) != cmk) continue;
+        if (CHK && skip_reg(j, cmk)) continue;
         const bool b = sel(j);
         const double t = (double)L[j].x * (double)P[j].y - (double)L[j].y * (double)P[j].x;
         if (gz) acc += b ? -t : t;
