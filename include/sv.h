@@ -322,7 +322,8 @@ sv_status sv_tune_get(int kernel_class, int dtype, int tier, int* block, int* un
  * the built-in default, 12 for complex128 and 13 for complex64 (64 KiB
  * tiles), capped so that a workgroup holding one tile has at most 512
  * threads (complex128 reverse passes keep 8 amplitudes of each state per
- * thread); amps_per_thread 0 = 16.  Process-wide; set it from one thread
+ * thread; forward-only batches have no reverse workgroups, so complex128
+ * tiles of 2^13 fit there); amps_per_thread 0 = 16.  Process-wide; set it from one thread
  * before creating batches; existing batches keep their shape.
  * sv_tune_engine_get reports the shape a batch with zeroed options gets.
  * Errors: SV_ERR_ARG for a bad dtype or with_grad, amps_per_thread not

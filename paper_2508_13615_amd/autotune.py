@@ -149,16 +149,17 @@ def tune(qubits: int = 30, reps: int = 3, dtypes=("c128", "c64"), log=print, mar
             "created": time.strftime("%Y-%m-%d %H:%M:%S"), "entries": entries}
 
 
-# Engine tile shapes tried per dtype: (tile_qubits, amps_per_thread).  Every
-# one keeps forward and reverse workgroups within 64..512 threads.
-def _engine_shape_ok(dtype, tq, apt):
+# Engine tile shapes tried per dtype and stage mix: (tile_qubits,
+# amps_per_thread).  Every one keeps forward workgroups, and with the adjoint
+# reverse ones, within 64..512 threads.
+def _engine_shape_ok(dtype, tq, apt, with_grad):
     rb = apt.bit_length() - 1
     rrb = min(rb, 3) if dtype == "c128" else rb
-    return 6 <= tq - rb and tq - min(rb, rrb) <= 9
+    return 6 <= tq - rb and tq - (min(rb, rrb) if with_grad else rb) <= 9
 
 
-ENGINE_SHAPES = {dt: [(t, a) for a in (8, 16) for t in range(9, 14) if _engine_shape_ok(dt, t, a)]
-                 for dt in ("c128", "c64")}
+ENGINE_SHAPES = {(dt, g): [(t, a) for a in (8, 16) for t in range(9, 14) if _engine_shape_ok(dt, t, a, g)]
+                 for dt in ("c128", "c64") for g in (True, False)}
 
 
 def _engine_workloads(with_grad: bool):
@@ -207,7 +208,7 @@ def tune_engine(reps: int = 5, dtypes=("c128", "c64"), log=print, margin: float 
             work = _engine_workloads(grad)
             sv.tune_engine_set(dtype, grad, 0, 0)
             default = sv.tune_engine_get(dtype, grad)
-            shapes = ENGINE_SHAPES[dtype]
+            shapes = ENGINE_SHAPES[(dtype, grad)]
             if default not in shapes:
                 shapes = shapes + [default]
             t = {sh: {} for sh in shapes}

@@ -513,12 +513,13 @@ struct HostTables {
 static int g_engine_tq[2][2] = {{0, 0}, {0, 0}};
 static int g_engine_apt[2][2] = {{0, 0}, {0, 0}};
 
-// Largest tile whose forward and reverse workgroups stay within kMaxPassThreads.
-static int engine_tq_fit(int reg_bits, int rreg_bits)
+// Largest tile whose forward workgroups (and reverse ones, with the adjoint)
+// stay within kMaxPassThreads.
+static int engine_tq_fit(int reg_bits, int rreg_bits, int with_grad)
 {
     int lg_threads = 0;
     while ((2 << lg_threads) <= kMaxPassThreads) ++lg_threads;
-    return std::min(reg_bits, rreg_bits) + lg_threads;
+    return (with_grad ? std::min(reg_bits, rreg_bits) : reg_bits) + lg_threads;
 }
 
 static sv_status compile_batch(const sv_batch_circuit* circuits, int n_circuits, int dtype, const sv_batch_opts* opts,
@@ -540,7 +541,7 @@ static sv_status compile_batch(const sv_batch_circuit* circuits, int n_circuits,
     // default tile: the tuned one, else 64 KiB (2^12 complex128 / 2^13 complex64
     // amplitudes); either within kMaxPassThreads threads of the narrower register width
     const int tq_base = g_engine_tq[d][with_grad] > 0 ? g_engine_tq[d][with_grad] : (dtype == SV_C128 ? 12 : 13);
-    const int tq_default = std::min(tq_base, engine_tq_fit(reg_bits, rreg_bits));
+    const int tq_default = std::min(tq_base, engine_tq_fit(reg_bits, rreg_bits, with_grad));
     int tq_max = opts && opts->tile_qubits > 0 ? opts->tile_qubits : tq_default;
     if (tq_max < 2 || tq_max > kMaxTileQubits) return set_error(SV_ERR_ARG, "tile_qubits must be in [2, 13]");
     const int cbits_default = dtype == SV_C128 ? 3 : 4;  // 128-byte runs
@@ -810,7 +811,7 @@ sv_status sv_tune_engine_set(int dtype, int with_grad, int tile_qubits, int amps
     if (tile_qubits) {
         const int rb = amps_per_thread == 8 ? 3 : 4;
         const int rrb = dtype == SV_C128 ? std::min(rb, 3) : rb;
-        if (tile_qubits > engine_tq_fit(rb, rrb))
+        if (tile_qubits > engine_tq_fit(rb, rrb, with_grad))
             return set_error(SV_ERR_ARG, "tile_qubits too large for amps_per_thread (at most 512 threads per tile)");
     }
     const int d = dtype == SV_C128 ? 1 : 0;
@@ -828,7 +829,7 @@ sv_status sv_tune_engine_get(int dtype, int with_grad, int* tile_qubits, int* am
     const int rb = g_engine_apt[d][with_grad] == 8 ? 3 : 4;
     const int rrb = dtype == SV_C128 ? std::min(rb, 3) : rb;
     const int tq_base = g_engine_tq[d][with_grad] > 0 ? g_engine_tq[d][with_grad] : (dtype == SV_C128 ? 12 : 13);
-    *tile_qubits = std::min(tq_base, engine_tq_fit(rb, rrb));
+    *tile_qubits = std::min(tq_base, engine_tq_fit(rb, rrb, with_grad));
     *amps_per_thread = 1 << rb;
     return SV_OK;
 }

@@ -238,6 +238,12 @@ def test_engine_tile_shape_tuning_host_only():
                             ("c128", 12, 4), ("c64", 0, 32)):
             with pytest.raises(sv.SvError):
                 sv.tune_engine_set(dt, True, tq, apt)
+        # forward-only: no reverse workgroups, so a complex128 2^13 tile of 16 per thread fits
+        sv.tune_engine_set("c128", False, 13, 16)
+        assert sv.tune_engine_get("c128", False) == (13, 16)
+        assert sv.batch_plan(circ, "c128", with_grad=False)["threads"] == 512
+        with pytest.raises(sv.SvError):
+            sv.tune_engine_set("c128", False, 13, 8)
         assert sv.tune_engine_get("c128", True) == (10, 8)
         assert sv.lib.sv_tune_engine_set(7, 1, 0, 0) == ARG  # bad dtype
         assert sv.lib.sv_tune_engine_set(2, 2, 0, 0) == ARG  # with_grad not 0/1

@@ -154,6 +154,30 @@ def test_batch_large_circuit_multi_tile():
     assert info["max_passes"] < len(ops) / 4  # fusion: far fewer passes than gates
 
 
+@pytest.mark.parametrize("dtype,tol", [("c128", 1e-10), ("c64", 1e-4)])
+def test_every_tunable_engine_shape_vs_oracle(dtype, tol):
+    """Every tile shape the autotuner may pick, for each stage mix: the
+    forward state against the fp64 oracle, and with the adjoint, energy and
+    gradient against the op-by-op adjoint kernels."""
+    from paper_2508_13615_amd.autotune import ENGINE_SHAPES
+    n, L = 16, 3
+    ops = W.hea_ops(n, L)
+    th = W.uniform_angles(W.hea_n_params(n, L), 5405)
+    ref = oracle.run_circuit(oracle.zero_state(n), ops, th)
+    e1, g1 = sv.Circuit(n, ops, len(th)).adjoint_grad(sv.State(n), sv.State(n), th, W.sum_zz(n))
+    for grad in (False, True):
+        for tq, apt in ENGINE_SHAPES[(dtype, grad)]:
+            print(f"shape {dtype} grad={grad} tile {tq} x {apt}", flush=True)
+            b = sv.Batch([(n, ops, len(th), "sum_zz")], dtype, tile_qubits=tq, amps_per_thread=apt, with_grad=grad)
+            e, g = b.run(th)
+            assert b.info()["threads"] == max(64, 2 ** tq // apt)
+            if grad:
+                assert abs(e[0] - e1) <= tol * n and np.max(np.abs(g - g1)) <= tol, (tq, apt)
+            else:
+                err = float(np.max(np.abs(b.state(0).astype(np.complex128) - ref)))
+                assert err <= (1e-12 if dtype == "c128" else 1e-5), (tq, apt, err)
+
+
 def test_config3_circuits_at_20_qubits_vs_oracle():
     """HEA (10 layers) and QFT of a random basis state at 20 qubits on the
     fused engine: complex128 within 1e-12, complex64 within 1e-5 of the fp64
