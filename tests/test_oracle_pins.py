@@ -481,3 +481,45 @@ def test_golden_oracle_regression_hea6():
     ref = np.array([rows[x] for x in range(1 << n)])
     assert np.max(np.abs(psi - ref)) < 1e-15
     assert abs(oracle.expval_obs(psi, W.sum_zz(n)) - e_ref) < 1e-15
+
+
+def test_dense_four_to_six_qubit_blocks_vs_tensordot():
+    # the oracle's dense path at the block sizes of the matrix-core kernel
+    # (k = 4..6): against numpy's tensor contraction, for target orders that
+    # are ascending, descending and scattered
+    n = 8
+    rng = np.random.default_rng(140)
+    psi = rand_state(n, 141)
+    for tg in [(0, 1, 2, 3), (7, 5, 3, 1), (6, 0, 4, 2, 7), (3, 4, 5, 6, 7), (5, 1, 7, 0, 3, 6), (0, 1, 2, 3, 4, 5)]:
+        u = W.haar_unitary(len(tg), rng)
+        got = oracle.apply_matrix(psi.copy(), tg, u)
+        assert np.max(np.abs(got - tensordot_apply(psi, tg, u))) < TOL, tg
+
+
+def test_dense_block_of_kron_product_equals_one_qubit_gates():
+    # a 4-qubit Kronecker product u0 (x) u1 (x) u2 (x) u3 on targets (a, b, c, d)
+    # (first factor on the first-listed target, the matrix MSB) equals the
+    # four one-qubit gates applied one by one
+    n = 7
+    rng = np.random.default_rng(150)
+    psi = rand_state(n, 151)
+    tg = (5, 0, 3, 6)
+    us = [W.haar_unitary(1, rng) for _ in tg]
+    big = np.kron(np.kron(np.kron(us[0], us[1]), us[2]), us[3])
+    got = oracle.apply_matrix(psi.copy(), tg, big)
+    ref = psi.copy()
+    for t, u in zip(tg, us):
+        ref = oracle.apply_matrix(ref, (t,), u)
+    assert np.max(np.abs(got - ref)) < TOL
+
+
+def test_dense_six_qubit_adjoint_roundtrip():
+    n = 9
+    rng = np.random.default_rng(160)
+    psi = rand_state(n, 161)
+    tg = (8, 2, 5, 0, 7, 3)
+    u = W.haar_unitary(6, rng)
+    a = oracle.apply_matrix(psi.copy(), tg, u)
+    b = oracle.apply_matrix(a, tg, np.ascontiguousarray(u.conj().T))
+    assert abs(oracle.norm2(a) - 1.0) < 1e-13
+    assert np.max(np.abs(b - psi)) < TOL
