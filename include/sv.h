@@ -157,6 +157,22 @@ sv_status sv_apply_controlled(sv_state st, sv_gate gate, const int* controls, in
  * baseline the gate-specific routines are measured against. */
 sv_status sv_apply_general(sv_state st, const int* qubits, int k, const double* matrix);
 
+/* A dense 2^k x 2^k unitary on k in [4, 6] qubits, on the matrix cores: the
+ * fused dense block that stands for a run of gates on k qubits (Sec. 2's
+ * logic-matrix application, one group of 2^k amplitudes per matrix-vector
+ * product).  The complex product runs as a real one (FP64 MFMA for
+ * complex128, FP32 MFMA for complex64), 8 * 2^k flops per amplitude.
+ * qubits: k distinct indices < n, the first the most significant bit of the
+ * matrix index (as in sv_apply_general).  matrix: host, row-major,
+ * interleaved (re, im), 2 * 4^k doubles, read during the call (it is staged
+ * in pinned memory and uploaded on the state's stream).  The state keeps a
+ * 128 KiB device buffer and a 128 KiB pinned buffer from the first call
+ * until sv_free.  Asynchronous on the state's stream, except that a call
+ * waits for the previous call's upload to finish.
+ * Errors: SV_ERR_ARG (k outside [4, 6], null matrix), SV_ERR_QUBIT (bad or
+ * repeated qubits), SV_ERR_OOM (buffers), SV_ERR_HIP. */
+sv_status sv_apply_dense(sv_state st, const int* qubits, int k, const double* matrix);
+
 /* ------------------------------------------------------------------------
  * Measurement (Sec. 2: routines for "measurement processes"; Listing 1 takes
  * the expectation of a Hamiltonian).  All sums use fp64 with a fixed

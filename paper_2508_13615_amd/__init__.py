@@ -185,6 +185,12 @@ class State:
         check(lib.sv_apply_general(self.handle, _ints(qubits), len(qubits), mp))
         return self
 
+    def apply_dense(self, qubits: Sequence[int], matrix) -> "State":
+        """Dense 2^k x 2^k unitary, 4 <= k <= 6, on the matrix cores (sv_apply_dense)."""
+        m, mp = _matrix(matrix)
+        check(lib.sv_apply_dense(self.handle, _ints(qubits), len(qubits), mp))
+        return self
+
     # ---- measurement -------------------------------------------------------
     def norm2(self) -> float:
         out = ctypes.c_double()

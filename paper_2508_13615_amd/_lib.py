@@ -25,7 +25,7 @@ OP_MAX_QUBITS = 10
 EXPORTS = [
     "sv_alloc", "sv_wrap", "sv_free", "sv_set_stream", "sv_get_info", "sv_state_bytes", "sv_set_basis",
     "sv_copy_to_host", "sv_copy_from_host", "sv_copy_state", "sv_synchronize", "sv_apply_gate",
-    "sv_apply_controlled", "sv_apply_general", "sv_norm2", "sv_expval_pauli", "sv_expval_obs",
+    "sv_apply_controlled", "sv_apply_general", "sv_apply_dense", "sv_norm2", "sv_expval_pauli", "sv_expval_obs",
     "sv_expval_obs_dev", "sv_circuit_create", "sv_circuit_free", "sv_circuit_apply", "sv_adjoint_grad",
     "sv_batch_create", "sv_batch_plan", "sv_batch_run", "sv_batch_info", "sv_batch_state", "sv_batch_copy_state",
     "sv_batch_free",
@@ -82,6 +82,7 @@ def _load():
         "sv_apply_gate": [vp, i, ip, i, dp, dp, i],
         "sv_apply_controlled": [vp, i, ip, i, ip, i, dp, dp, i],
         "sv_apply_general": [vp, ip, i, dp],
+        "sv_apply_dense": [vp, ip, i, dp],
         "sv_norm2": [vp, dp],
         "sv_expval_pauli": [vp, ctypes.c_char_p, ip, i, dp],
         "sv_expval_obs": [vp, ctypes.POINTER(SvObs), dp],

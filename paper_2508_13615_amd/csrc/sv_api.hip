@@ -23,6 +23,7 @@
 #include <vector>
 
 #include "sv_core.h"
+#include "sv_dense.h"
 
 namespace svk {
 
@@ -49,6 +50,9 @@ struct sv_state_s {
     hipStream_t stream;
     double* work;        // stage-1 partials + results
     size_t work_doubles;
+    void* dense_dev;     // real form of the last dense block (device), allocated on first use
+    void* dense_host;    // pinned staging of that real form
+    hipEvent_t dense_ev; // the staging copy has been read once this completes
 };
 
 struct OpRec {
@@ -583,6 +587,9 @@ static sv_status make_state(void* ptr, bool owned, int n, sv_dtype dtype, void* 
     st->stream = (hipStream_t)stream;
     st->work = nullptr;  // reduction workspace is allocated on first use
     st->work_doubles = 0;
+    st->dense_dev = nullptr;
+    st->dense_host = nullptr;
+    st->dense_ev = nullptr;
     reg(st);
     *out = st;
     return SV_OK;
@@ -621,6 +628,9 @@ sv_status sv_free(sv_state st)
     unreg(st);
     (void)hipStreamSynchronize(st->stream);
     if (st->work) (void)hipFree(st->work);
+    if (st->dense_dev) (void)hipFree(st->dense_dev);
+    if (st->dense_host) (void)hipHostFree(st->dense_host);
+    if (st->dense_ev) (void)hipEventDestroy(st->dense_ev);
     if (st->owned && st->data) (void)hipFree(st->data);
     delete st;
     return SV_OK;
@@ -757,6 +767,52 @@ sv_status sv_apply_general(sv_state st, const int* qubits, int k, const double* 
         e = launch_general<float>(st->data, gs, k, off, mf, st->stream, lc);
     }
     return hip_status(e, "general launch");
+}
+
+sv_status sv_apply_dense(sv_state st, const int* qubits, int k, const double* matrix)
+{
+    SV_CHECK_STATE(st);
+    if (k < kDenseMinK || k > kDenseMaxK) return set_error(SV_ERR_ARG, "dense block needs 4 <= k <= 6");
+    if (!matrix) return set_error(SV_ERR_ARG, "null matrix");
+    sv_status rc = check_qubits(st->n, nullptr, 0, qubits, k);
+    if (rc) return rc;
+    DenseSpec sp;
+    memset(&sp, 0, sizeof sp);
+    sp.k = k;
+    for (int j = 0; j < k; ++j) sp.qs_sorted[j] = qubits[j];
+    std::sort(sp.qs_sorted, sp.qs_sorted + k);
+    for (int c = 0; c < (1 << k); ++c)
+        for (int j = 0; j < k; ++j)
+            if ((c >> (k - 1 - j)) & 1) sp.dep[c] |= 1ull << qubits[j];
+    sp.groups = (int64_t)1 << (st->n - k);
+    // one buffer of the largest real form (k = kDenseMaxK) serves every call
+    const size_t cap = dense_lds_bytes(kDenseMaxK, SV_C128);
+    if (!st->dense_dev) {
+        if (hipMalloc(&st->dense_dev, cap) != hipSuccess || hipHostMalloc(&st->dense_host, cap) != hipSuccess ||
+            hipEventCreateWithFlags(&st->dense_ev, hipEventDisableTiming) != hipSuccess) {
+            (void)hipGetLastError();
+            if (st->dense_dev) (void)hipFree(st->dense_dev);
+            if (st->dense_host) (void)hipHostFree(st->dense_host);
+            st->dense_dev = st->dense_host = nullptr;
+            st->dense_ev = nullptr;
+            return set_error(SV_ERR_OOM, "dense block buffers");
+        }
+    } else {
+        // the previous call's upload must have read the staging buffer
+        const hipError_t e = hipEventSynchronize(st->dense_ev);
+        if (e != hipSuccess) return hip_status(e, "dense staging");
+    }
+    const int n2 = 2 << k;
+    std::vector<double> B((size_t)n2 * n2);
+    dense_real_form(matrix, k, B.data());
+    const size_t bytes = dense_lds_bytes(k, st->dtype);
+    if (st->dtype == SV_C128) memcpy(st->dense_host, B.data(), bytes);
+    else
+        for (size_t i = 0; i < B.size(); ++i) ((float*)st->dense_host)[i] = (float)B[i];
+    hipError_t e = hipMemcpyAsync(st->dense_dev, st->dense_host, bytes, hipMemcpyHostToDevice, st->stream);
+    if (e == hipSuccess) e = hipEventRecord(st->dense_ev, st->stream);
+    if (e == hipSuccess) e = launch_dense(st->data, st->dtype, st->dense_dev, sp, st->stream);
+    return hip_status(e, "dense block launch");
 }
 
 // ---------------------------------------------------------------------------

@@ -95,6 +95,13 @@ def test_gate_validation():
         assert lib.sv_apply_general(h, ints(0, 1, 2, 3), 4, m) == ARG  # k > 3
         assert lib.sv_apply_general(h, ints(0), 1, None) == ARG
         assert lib.sv_apply_general(h, ints(0, 0), 2, m) == QUBIT
+        md = (ctypes.c_double * (2 * 4 ** 6))()
+        assert lib.sv_apply_dense(h, ints(0, 1, 2), 3, md) == ARG  # k < 4: the vector kernels
+        assert lib.sv_apply_dense(h, ints(0, 1, 2, 3, 4, 5, 6), 7, md) == ARG  # k > 6
+        assert lib.sv_apply_dense(h, ints(0, 1, 2, 3), 4, None) == ARG
+        assert lib.sv_apply_dense(h, ints(0, 1, 2, 2), 4, md) == QUBIT  # repeated
+        assert lib.sv_apply_dense(h, ints(0, 1, 2, 6), 4, md) == QUBIT  # out of range
+        assert lib.sv_apply_dense(h, None, 4, md) == ARG
         assert lib.sv_set_basis(h, 64) == ARG
     finally:
         assert lib.sv_free(h) == OK
