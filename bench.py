@@ -524,6 +524,62 @@ def config3(sv, torch, n, layers, reps):
     return out
 
 
+def dense_block(sv, torch, W, n, gen, reps=5):
+    """Dense k-qubit blocks (k = 4..6) on the matrix cores at n qubits, both
+    dtypes: ms per block, HBM GB/s (2S moved) and achieved TFLOP/s (8 * 2^k
+    flops per amplitude) against the dense matrix-core peak of the dtype, for
+    targets at the bottom, the top and scattered over the index; beside it,
+    the same Kronecker-product block as k one-qubit kernel launches."""
+    import numpy as np
+    peak = {"c128": 78.6, "c64": 157.3}  # TFLOP/s, dense FP64 / FP32 MFMA
+    tdt = {"c128": torch.complex128, "c64": torch.complex64}
+    rng = np.random.default_rng(1010)
+    out = {}
+    for dt in ("c128", "c64"):
+        t = torch.randn(1 << n, dtype=tdt[dt], device="cuda", generator=gen)
+        t /= torch.linalg.vector_norm(t)
+        st = sv.State(n, dt, tensor=t, basis=None)
+        S = (1 << n) * (16 if dt == "c128" else 8)
+        res = {}
+        for k in (4, 5, 6):
+            us = [W.haar_unitary(1, rng) for _ in range(k)]
+            big = us[0]
+            for u in us[1:]:
+                big = np.kron(big, u)
+            placements = {"low": tuple(range(k - 1, -1, -1)), "high": tuple(range(n - 1, n - 1 - k, -1)),
+                          "scattered": tuple(int(q) for q in rng.permutation(n)[:k])}
+            rk = {}
+            for name, tg in placements.items():
+                def run_block():
+                    st.apply_dense(tg, big)
+
+                def run_gates():
+                    for q, u in zip(tg, us):
+                        st.apply("U2", (q,), matrix=u)
+                ms = {}
+                for label, fn in (("block", run_block), ("one_qubit_gates", run_gates)):
+                    fn()
+                    torch.cuda.synchronize()
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record()
+                    for _ in range(reps):
+                        fn()
+                    e1.record()
+                    e1.synchronize()
+                    ms[label] = e0.elapsed_time(e1) / reps
+                tflops = 8 * (1 << k) * (1 << n) / (ms["block"] * 1e-3) / 1e12
+                rk[name] = {"targets": list(tg), "ms": ms["block"], "GBps": 2 * S / (ms["block"] * 1e-3) / 1e9,
+                            "frac_of_8TBps": 2 * S / (ms["block"] * 1e-3) / 8e12, "TFLOPs": tflops,
+                            "frac_of_mfma_peak": tflops / peak[dt], "one_qubit_gates_ms": ms["one_qubit_gates"]}
+            res[f"k{k}"] = rk
+            log(f"[bench] dense {dt} k={k}: " + ", ".join(f"{nm} {v['ms']:.2f} ms ({v['TFLOPs']:.1f} TF/s, "
+                                                            f"{v['GBps']:.0f} GB/s)" for nm, v in rk.items()))
+        out[dt] = res
+        del st, t
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -541,6 +597,7 @@ def main():
     ap.add_argument("--skip-fused", action="store_true", help="skip configs 3, 4 (fused) and 5")
     ap.add_argument("--config3-qubits", type=int, default=32)
     ap.add_argument("--no-sequential", action="store_true", help="skip the op-by-op baseline of config 5")
+    ap.add_argument("--skip-dense", action="store_true", help="skip the matrix-core dense-block section")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the state-vector path here is built and measured on a single "
@@ -657,6 +714,9 @@ def main():
         log(f"[bench] config 3: {args.config3_qubits}-qubit HEA and QFT")
         out["circuits32"] = config3(sv, torch, args.config3_qubits, 10, 3)
         log("[bench] fused sections done")
+    if not args.skip_dense:
+        log(f"[bench] dense 4- to 6-qubit blocks on the matrix cores at {n} qubits")
+        out["dense_block"] = dense_block(sv, torch, W, n, gen)
     if not args.skip_cpu_baseline:
         log(f"[bench] oracle CPU baseline at {args.cpu_qubits} qubits")
         out["cpu_baseline"] = cpu_baseline(args.cpu_qubits, n)
