@@ -3,17 +3,24 @@
 // small logic matrix to the amplitude groups its qubits select; here one
 // 2^k x 2^k matrix stands for a run of gates on k qubits).
 //
-// The amplitudes of group g form a row of 2^(k+1) reals (re, im interleaved
-// in matrix-index order).  The output row is that row times the real form of
-// U (dense_real_form), so a block of 16 groups is a 16 x 2^(k+1) by
-// 2^(k+1) x 2^(k+1) real product: 16x16x4 MFMA steps, FP64 for complex128
-// and FP32 for complex64.  Per amplitude that is 8 * 2^k flops for 32 (or
-// 16) bytes moved: HBM-bound up to k = 5, matrix-core-bound at k = 6
-// (complex128).
+// The amplitudes of group g form a row of 2^(k+1) reals.  The output row is
+// that row times a real form of U (dense_real_form), so a block of 16 groups
+// is a 16 x 2^(k+1) by 2^(k+1) x 2^(k+1) real product: 16x16x4 MFMA steps,
+// FP64 for complex128 and FP32 for complex64.  Per amplitude that is
+// 8 * 2^k flops for 32 (or 16) bytes moved: HBM-bound up to k = 5,
+// matrix-core-bound at k = 6 (complex128).
 //
 // Operand layouts (16x16x4, one wavefront): lane l supplies A[l % 16][l / 16]
 // and B[l / 16][l % 16]; accumulator value r of lane l is D[l / 16 + 4 r][l % 16]
-// in FP64 and D[4 (l / 16) + r][l % 16] in FP32.
+// in FP64 and D[4 (l / 16) + r][l % 16] in FP32.  The order of the reals is
+// free (it is the real form's row and column order), and is chosen so that
+// every access is a whole amplitude: at steps 2j and 2j + 1 the lanes with
+// l / 16 = kk take the real and the imaginary part of amplitude 4 j + kk
+// (one 16- or 8-byte load for two steps), and output tiles 2t and 2t + 1 hold
+// the real and the imaginary parts of amplitudes 16 t .. 16 t + 15 (one store
+// per amplitude).  A load instruction takes 4 consecutive amplitudes of each
+// of 16 groups, so a line is often completed by the next instruction: plain
+// (cached) accesses, which measured faster here than non-temporal ones.
 #include <algorithm>
 
 #include "sv.h"
@@ -23,6 +30,17 @@ namespace svk {
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 typedef float flt4 __attribute__((ext_vector_type(4)));
+
+template <typename T>
+struct Cplx;
+template <>
+struct Cplx<double> {
+    using type = double2;
+};
+template <>
+struct Cplx<float> {
+    using type = float2;
+};
 
 template <typename T>
 struct DenseAcc;
@@ -73,6 +91,7 @@ __global__ void __launch_bounds__(512) k_dense(T* __restrict__ psi, const T* __r
     constexpr int NT = N2 / 16;  // 16-column output tiles
     constexpr int CH = KS < 8 ? KS : 8;  // MFMA steps per chunk of input loads
     using Acc = typename DenseAcc<T>::type;
+    using V = typename Cplx<T>::type;
     extern __shared__ double dense_smem[];
     T* const Bl = (T*)dense_smem;
     __shared__ uint64_t dep[1 << K];
@@ -83,32 +102,52 @@ __global__ void __launch_bounds__(512) k_dense(T* __restrict__ psi, const T* __r
     const int l = threadIdx.x & 63;
     const int wpg = blockDim.x >> 6;
     const int64_t nblk = (sp.groups + 15) >> 4;
-    for (int64_t blk = (int64_t)blockIdx.x * wpg + (threadIdx.x >> 6); blk < nblk; blk += (int64_t)gridDim.x * wpg) {
-        const int64_t g = blk * 16 + (l & 15);
-        const bool valid = g < sp.groups;  // the last block of a small state is partial
-        const uint64_t base = group_base<K>(valid ? (uint64_t)g : 0ull, sp);
-        const T* const row = psi + 2 * base + ((l >> 4) & 1);  // this lane's component
-        // lane l reads input real m = 4 ks + l / 16: amplitude 2 ks + l / 32
-        auto load_chunk = [&](int kc, T* a) {
+    const int64_t stride = (int64_t)gridDim.x * wpg;
+    // this lane's group row of block b (the last block of a small state is
+    // partial: rows past the groups read zeros and are not stored)
+    auto row_of = [&](int64_t b, bool& valid) {
+        const int64_t g = b * 16 + (l & 15);
+        valid = g < sp.groups;
+        return (const V*)psi + group_base<K>(valid ? (uint64_t)g : 0ull, sp);
+    };
+    // chunk of CH steps = CH / 2 amplitudes per lane: 4 j + l / 16 for step pair j
+    auto load_chunk = [&](const V* row, bool valid, int kc, V* a) {
 #pragma unroll
-            for (int i = 0; i < CH; ++i) a[i] = valid ? row[2 * dep[2 * (kc + i) + (l >> 5)]] : T(0);
-        };
+        for (int i = 0; i < CH / 2; ++i) {
+            const int j = kc / 2 + i;
+            a[i] = valid ? row[dep[4 * j + (l >> 4)]] : V{T(0), T(0)};
+        }
+    };
+    int64_t blk = (int64_t)blockIdx.x * wpg + (threadIdx.x >> 6);
+    V a_cur[CH / 2], a_nxt[CH / 2];
+    bool valid = false;
+    const V* row = nullptr;
+    if (blk < nblk) {
+        row = row_of(blk, valid);
+        load_chunk(row, valid, 0, a_cur);
+    }
+    for (; blk < nblk; blk += stride) {
+        const int64_t nb = blk + stride;
+        bool nvalid = false;
+        const V* const nrow = nb < nblk ? row_of(nb, nvalid) : nullptr;
         Acc acc[NT];
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) acc[nt] = Acc{0, 0, 0, 0};
-        T a_cur[CH], a_nxt[CH];
-        load_chunk(0, a_cur);
 #pragma unroll 1
         for (int kc = 0; kc < KS; kc += CH) {
-            if (kc + CH < KS) load_chunk(kc + CH, a_nxt);  // in flight during this chunk's products
+            // in flight during this chunk's products: the next chunk, or the
+            // first chunk of this wavefront's next block (other groups)
+            if (kc + CH < KS) load_chunk(row, valid, kc + CH, a_nxt);
+            else if (nb < nblk) load_chunk(nrow, nvalid, 0, a_nxt);
 #pragma unroll
             for (int i = 0; i < CH; ++i) {
                 const T* const brow = Bl + (4 * (kc + i) + (l >> 4)) * N2 + (l & 15);
+                const T av = (i & 1) ? a_cur[i >> 1].y : a_cur[i >> 1].x;
 #pragma unroll
-                for (int nt = 0; nt < NT; ++nt) acc[nt] = mfma16x16x4(a_cur[i], brow[16 * nt], acc[nt]);
+                for (int nt = 0; nt < NT; ++nt) acc[nt] = mfma16x16x4(av, brow[16 * nt], acc[nt]);
             }
 #pragma unroll
-            for (int i = 0; i < CH; ++i) a_cur[i] = a_nxt[i];
+            for (int i = 0; i < CH / 2; ++i) a_cur[i] = a_nxt[i];
         }
         // every amplitude of this block was read above (the products depend
         // on all of them), and no other wavefront touches these groups
@@ -116,15 +155,19 @@ __global__ void __launch_bounds__(512) k_dense(T* __restrict__ psi, const T* __r
         for (int r = 0; r < 4; ++r) {
             const int64_t gi = blk * 16 + acc_row<T>(l, r);
             if (gi >= sp.groups) continue;
-            const uint64_t bi = group_base<K>((uint64_t)gi, sp);
+            V* const orow = (V*)psi + group_base<K>((uint64_t)gi, sp);
 #pragma unroll
-            for (int nt = 0; nt < NT; ++nt) {
-                const int m = 16 * nt + (l & 15);
-                psi[2 * (bi | dep[m >> 1]) + (m & 1)] = acc[nt][r];
-            }
+            for (int t = 0; t < NT / 2; ++t) orow[dep[16 * t + (l & 15)]] = V{acc[2 * t][r], acc[2 * t + 1][r]};
         }
+        row = nrow;
+        valid = nvalid;
     }
 }
+
+// Row of the real form that holds component p of input amplitude c, and
+// column that holds component q of output amplitude r (the kernel's order).
+static int in_pos(int c, int p) { return 4 * (2 * (c >> 2) + p) + (c & 3); }
+static int out_pos(int r, int q) { return 16 * (2 * (r >> 4) + q) + (r & 15); }
 
 void dense_real_form(const double* U, int k, double* B)
 {
@@ -132,10 +175,10 @@ void dense_real_form(const double* U, int k, double* B)
     for (int r = 0; r < M; ++r)
         for (int c = 0; c < M; ++c) {
             const double ur = U[2 * (r * M + c)], ui = U[2 * (r * M + c) + 1];
-            B[(2 * c) * N2 + 2 * r] = ur;
-            B[(2 * c + 1) * N2 + 2 * r] = -ui;
-            B[(2 * c) * N2 + 2 * r + 1] = ui;
-            B[(2 * c + 1) * N2 + 2 * r + 1] = ur;
+            B[in_pos(c, 0) * N2 + out_pos(r, 0)] = ur;   // re(out) += ur re(in)
+            B[in_pos(c, 1) * N2 + out_pos(r, 0)] = -ui;  // re(out) -= ui im(in)
+            B[in_pos(c, 0) * N2 + out_pos(r, 1)] = ui;   // im(out) += ui re(in)
+            B[in_pos(c, 1) * N2 + out_pos(r, 1)] = ur;   // im(out) += ur im(in)
         }
 }
 

@@ -20,9 +20,10 @@ struct DenseSpec {
     int64_t groups;  // 2^(n-k)
 };
 
-// Real form of the 2^k x 2^k complex matrix U acting on interleaved (re, im)
-// amplitudes: 2^(k+1) x 2^(k+1), row-major, entry [2c + p][2r + q] the weight
-// of input component p of amplitude c in output component q of amplitude r.
+// Real form of the 2^k x 2^k complex matrix U: 2^(k+1) x 2^(k+1), row-major,
+// entry [row of (c, p)][column of (r, q)] the weight of component p (0 re,
+// 1 im) of input amplitude c in component q of output amplitude r, rows and
+// columns in the kernels' order (k_dense.hip).
 void dense_real_form(const double* U, int k, double* B);
 
 // psi (interleaved complex128 or complex64, per `dtype`) <- U on the spec's
