@@ -23,6 +23,8 @@
 // at least 64 bytes; below that (a gate or control on bit 0 or 1 of a
 // complex128 state) non-temporal accesses of partial lines cost up to 35%,
 // so the launch table (sv_api.hip) switches them off there.
+#include <algorithm>
+
 #include "sv_core.h"
 
 namespace svk {
@@ -426,13 +428,19 @@ __global__ void k_set_basis(typename Vec2<T>::type* __restrict__ psi, uint64_t n
 // --------------------------------------------------------------------------
 // launchers
 // --------------------------------------------------------------------------
+// Workgroups for a grid-stride loop over n work units of `per` each: at most
+// 2^30 of them, and blocks x threads below 2^32 (the launch limit of one grid
+// dimension; 32-qubit states reach it).
+static uint64_t grid_cap(uint64_t nb, int block)
+{
+    const uint64_t lim = std::min<uint64_t>(1ull << 30, 0xffffffffull / (uint64_t)block);
+    return nb < 1 ? 1 : (nb > lim ? lim : nb);
+}
+
 static dim3 grid_for(uint64_t n_groups, int block, int unroll)
 {
     const uint64_t per = (uint64_t)block * (uint64_t)unroll;
-    uint64_t nb = (n_groups + per - 1) / per;
-    if (nb < 1) nb = 1;
-    if (nb > (1ull << 30)) nb = 1ull << 30;  // grid-stride loop covers the rest
-    return dim3((unsigned)nb);
+    return dim3((unsigned)grid_cap((n_groups + per - 1) / per, block));  // the stride loop covers the rest
 }
 
 // Launch-shape dispatch: unroll U in {1, 2, 4} and the non-temporal flag.
@@ -578,9 +586,7 @@ static hipError_t launch_lds_k(typename Vec2<T>::type* p, const GroupSpec& tiles
     GeneralSpec<T, K> sp{};
     if (m)
         for (int i = 0; i < 2 * (1 << K) * (1 << K); ++i) sp.m[i] = m[i];
-    uint64_t nb = tiles.n_groups;
-    if (nb > (1ull << 30)) nb = 1ull << 30;
-    const dim3 grid((unsigned)nb), blk(lc.block);
+    const dim3 grid((unsigned)grid_cap(tiles.n_groups, lc.block)), blk(lc.block);
     const size_t lds = sizeof(typename Vec2<T>::type) << (kLdsChunkBits + ls.h);
     if (op == 1) {
         if constexpr (K == 2) {

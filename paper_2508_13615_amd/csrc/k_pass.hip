@@ -1210,7 +1210,10 @@ hipError_t launch_pass_items(const PassTables& tb, int dtype, int mode, int64_t 
     const int64_t n = item_end - item_begin;
     if (n <= 0) return hipSuccess;
     if (threads < 64 || threads > kMaxPassThreads) return hipErrorInvalidValue;
-    const unsigned grid = (unsigned)(n < (1 << 30) ? n : (1 << 30));
+    // one workgroup per item, within the launch limits (blocks below 2^30 and
+    // blocks x threads below 2^32); the kernels' item loops cover the rest
+    const int64_t cap = std::min<int64_t>(1 << 30, 0xffffffffll / threads);
+    const unsigned grid = (unsigned)(n < cap ? n : cap);
     if (dtype == SV_C128) launch_items_t<double>(tb, mode, grid, threads, lds_bytes, s, item_begin, item_end);
     else launch_items_t<float>(tb, mode, grid, threads, lds_bytes, s, item_begin, item_end);
     return hipGetLastError();

@@ -290,3 +290,52 @@ def test_full_size_sampled_parity_30q():
                 assert np.max(np.abs(after[row] - ref)) <= 1e-12, (gate, tg, ct, row)
     del s, t
     torch.cuda.empty_cache()
+
+
+def test_single_gates_on_32_qubits_sampled():
+    """32-qubit complex64 state (32 GiB): launches whose work-item count
+    exceeds 2^32 for a naive grid (pairs, element-wise, LDS-staged and
+    general kernels) run, checked on 256 sampled groups per gate."""
+    import torch
+    n = 32
+    log("32-qubit single gates: allocating complex64 state")
+    g = torch.Generator(device="cuda")
+    g.manual_seed(1032)
+    t = torch.randn(1 << n, dtype=torch.complex64, device="cuda", generator=g)
+    t /= torch.linalg.vector_norm(t)
+    s = sv.State(n, "c64", tensor=t, basis=None)
+    rng = np.random.default_rng(3032)
+    cases = [("H", (0,), ()), ("H", (31,), ()), ("RZ", (12,), ()), ("U4", (31, 1), ()), ("SWAP", (2, 30), ()),
+             ("X", (5,), (0,)), ("GENERAL", (2, 1, 0), ())]
+    for gate, tg, ct in cases:
+        log("  case", gate, tg, ct)
+        p = (float(rng.uniform(0, 2 * math.pi)),)
+        k = len(tg)
+        m = W.haar_unitary(k, rng) if gate in ("U4", "GENERAL") else None
+        free = rng.integers(0, 1 << n, size=256, dtype=np.int64)
+        for q in list(ct) + list(tg):
+            free &= ~(1 << q)
+        for q in ct:
+            free |= 1 << q
+        members = []
+        for r in range(1 << k):
+            off = 0
+            for j, q in enumerate(tg):
+                if (r >> (k - 1 - j)) & 1:
+                    off |= 1 << q
+            members.append(free | off)
+        idx = torch.from_numpy(np.stack(members, axis=1).reshape(-1)).cuda()
+        before = t[idx].cpu().numpy().astype(np.complex128).reshape(256, -1)
+        if gate == "GENERAL":
+            s.apply_general(tg, m)
+            u = m
+        else:
+            s.apply(gate, tg, ct, p, m)
+            u = oracle.gate_matrix(gate, p, m)
+        s.synchronize()
+        after = t[idx].cpu().numpy().astype(np.complex128).reshape(256, -1)
+        for row in range(256):
+            ref = oracle.apply_matrix(before[row].copy(), tuple(range(k - 1, -1, -1)), u)
+            assert np.max(np.abs(after[row] - ref)) <= 1e-5, (gate, tg, ct, row)
+    del s, t
+    torch.cuda.empty_cache()
