@@ -234,6 +234,24 @@ sv_status sv_circuit_free(sv_circuit c);
 /* Apply the circuit to st (in place) with host parameters params[n_params]. */
 sv_status sv_circuit_apply(sv_circuit c, sv_state st, const double* params);
 
+/* As sv_circuit_apply, with every run of two or more consecutive diagonal
+ * ops (Z, S, T, PHASE, RZ, any controls; identity) applied as one pass of
+ * sv_apply_phases: one read and write of the touched amplitudes per run
+ * instead of per gate (diagonal gates commute; Sec. 2's Z-type gates only
+ * rescale amplitudes).  The result equals sv_circuit_apply's within
+ * rounding (phases are summed as angles). */
+sv_status sv_circuit_apply_fused(sv_circuit c, sv_state st, const double* params);
+
+/* One pass of diagonal phases: psi[x] *= exp(i sum_t angles[t]) over the
+ * terms t whose mask bits are all set in x (mask 0: every amplitude).  A
+ * controlled phase on qubits S is the term (bits of S, phi).  Amplitudes
+ * lacking a bit common to every mask are not touched.  n_terms in [1, 64];
+ * masks and angles (radians) are host arrays read during the call; angles
+ * at multiples of pi/2 give exact phases.  Asynchronous on the state's
+ * stream.  Errors: SV_ERR_ARG (term count, null arrays), SV_ERR_QUBIT (a mask
+ * bit at or above n). */
+sv_status sv_apply_phases(sv_state st, int n_terms, const uint64_t* masks, const double* angles);
+
 /* Adjoint gradient of E(th) = <psi(th)|O|psi(th)>, psi(th) = U(th)|psi_in>.
  * On entry psi holds |psi_in> (not modified in the end beyond rounding: the
  * reverse sweep un-applies every gate).  lam is a work state of the same size

@@ -185,6 +185,16 @@ class State:
         check(lib.sv_apply_general(self.handle, _ints(qubits), len(qubits), mp))
         return self
 
+    def apply_phases(self, masks: Sequence[int], angles: Sequence[float]) -> "State":
+        """psi[x] *= exp(i sum of angles[t] over the terms whose mask bits x contains) (sv_apply_phases)."""
+        m = np.ascontiguousarray(np.asarray(masks, dtype=np.uint64))
+        a = np.ascontiguousarray(np.asarray(angles, dtype=np.float64))
+        if m.shape != a.shape:
+            raise ValueError("one angle per mask")
+        check(lib.sv_apply_phases(self.handle, len(m), m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                  a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return self
+
     def apply_dense(self, qubits: Sequence[int], matrix) -> "State":
         """Dense 2^k x 2^k unitary, 4 <= k <= 6, on the matrix cores (sv_apply_dense)."""
         m, mp = _matrix(matrix)
@@ -255,9 +265,12 @@ class Circuit:
             lib.sv_circuit_free(h)
             self.handle = None
 
-    def apply(self, state: State, params=()) -> State:
+    def apply(self, state: State, params=(), fuse_diagonal: bool = False) -> State:
+        """Apply op by op; with fuse_diagonal, each run of consecutive diagonal
+        ops is one phase pass (sv_circuit_apply_fused)."""
         p, pp = _dbl(list(params) if len(params) else [0.0])
-        check(lib.sv_circuit_apply(self.handle, state.handle, pp))
+        fn = lib.sv_circuit_apply_fused if fuse_diagonal else lib.sv_circuit_apply
+        check(fn(self.handle, state.handle, pp))
         return state
 
     def adjoint_grad(self, psi: State, lam: State, params, obs) -> Tuple[float, np.ndarray]:

@@ -24,6 +24,7 @@
 
 #include "sv_core.h"
 #include "sv_dense.h"
+#include "sv_phase.h"
 
 namespace svk {
 
@@ -1125,6 +1126,120 @@ static sv_status circuit_forward(sv_circuit c, sv_state st, const double* params
         if (rc) return rc;
     }
     return SV_OK;
+}
+
+// ---- runs of diagonal gates -------------------------------------------------
+
+// Phase terms (mask, angle in half-turns) of a diagonal op: exp(i pi turns)
+// on every amplitude whose index contains mask.  Returns false for other ops.
+static bool diag_terms(const OpRec& o, const double* params, std::vector<uint64_t>& masks,
+                       std::vector<double>& turns)
+{
+    if (o.nt != 1) return false;
+    uint64_t cm = 0;
+    for (int j = 0; j < o.nc; ++j) cm |= 1ull << o.q[j];
+    const uint64_t tm = cm | (1ull << o.q[o.nc]);
+    const double th = o.pidx >= 0 ? params[o.pidx] : o.value;
+    switch (o.gate) {
+    case SV_I: return true;
+    case SV_Z: masks.push_back(tm); turns.push_back(1.0); return true;
+    case SV_S: masks.push_back(tm); turns.push_back(0.5); return true;
+    case SV_T: masks.push_back(tm); turns.push_back(0.25); return true;
+    case SV_PHASE: masks.push_back(tm); turns.push_back(th / M_PI); return true;
+    case SV_RZ:  // exp(-i th/2) on the control subspace, exp(i th) more where the target is 1
+        masks.push_back(cm);
+        turns.push_back(-0.5 * th / M_PI);
+        masks.push_back(tm);
+        turns.push_back(th / M_PI);
+        return true;
+    default: return false;
+    }
+}
+
+static sv_status run_phase_terms(sv_state st, const uint64_t* masks, const double* turns, int nt)
+{
+    PhaseRun pr;
+    memset(&pr, 0, sizeof pr);
+    uint64_t common = ~0ull;
+    for (int t = 0; t < nt; ++t) {
+        pr.mask[t] = masks[t];
+        pr.turns[t] = turns[t];
+        common &= masks[t];
+    }
+    pr.n_terms = nt;
+    for (int q = 0; q < st->n; ++q)
+        if ((common >> q) & 1) pr.common_pos[pr.n_common++] = q;
+    pr.groups = (int64_t)1 << (st->n - pr.n_common);
+    return hip_status(launch_phase_run(st->data, st->dtype, pr, st->stream), "phase run launch");
+}
+
+sv_status sv_apply_phases(sv_state st, int n_terms, const uint64_t* masks, const double* angles)
+{
+    SV_CHECK_STATE(st);
+    if (n_terms < 1 || n_terms > kMaxPhaseTerms || !masks || !angles)
+        return set_error(SV_ERR_ARG, "phase run needs 1..64 terms and non-null arrays");
+    std::vector<double> turns(n_terms);
+    for (int t = 0; t < n_terms; ++t) {
+        if (st->n < 64 && (masks[t] >> st->n)) return set_error(SV_ERR_QUBIT, "phase term mask beyond the state");
+        turns[t] = angles[t] / M_PI;
+    }
+    return run_phase_terms(st, masks, turns.data(), n_terms);
+}
+
+// The circuit with every run of two or more consecutive diagonal ops applied
+// as one phase pass (a run longer than kMaxPhaseTerms terms takes several).
+static sv_status circuit_forward_fused(sv_circuit c, sv_state st, const double* params)
+{
+    std::vector<uint64_t> masks;
+    std::vector<double> turns;
+    size_t run_begin = 0, run_len = 0;
+    auto flush = [&]() -> sv_status {
+        sv_status rc = SV_OK;
+        if (run_len == 1) {  // a lone diagonal op keeps its own kernel
+            Plan pl;
+            rc = op_plan(c, st->dtype, c->ops[run_begin], params, 0, &pl);
+            if (!rc) rc = run_plan(pl, st, st->data);
+        } else if (!masks.empty()) {
+            rc = run_phase_terms(st, masks.data(), turns.data(), (int)masks.size());
+        }
+        masks.clear();
+        turns.clear();
+        run_len = 0;
+        return rc;
+    };
+    for (size_t i = 0; i < c->ops.size(); ++i) {
+        const OpRec& o = c->ops[i];
+        std::vector<uint64_t> m;
+        std::vector<double> tt;
+        if (diag_terms(o, params, m, tt)) {
+            if (masks.size() + m.size() > (size_t)kMaxPhaseTerms) {
+                sv_status rc = flush();
+                if (rc) return rc;
+            }
+            if (run_len == 0) run_begin = i;
+            ++run_len;
+            masks.insert(masks.end(), m.begin(), m.end());
+            turns.insert(turns.end(), tt.begin(), tt.end());
+            continue;
+        }
+        sv_status rc = flush();
+        if (rc) return rc;
+        Plan pl;
+        rc = op_plan(c, st->dtype, o, params, 0, &pl);
+        if (rc) return rc;
+        rc = run_plan(pl, st, st->data);
+        if (rc) return rc;
+    }
+    return flush();
+}
+
+sv_status sv_circuit_apply_fused(sv_circuit c, sv_state st, const double* params)
+{
+    SV_CHECK_CIRC(c);
+    SV_CHECK_STATE(st);
+    if (st->n != c->n) return set_error(SV_ERR_ARG, "state size does not match the circuit");
+    if (c->n_params > 0 && !params) return set_error(SV_ERR_ARG, "null params");
+    return circuit_forward_fused(c, st, params);
 }
 
 sv_status sv_circuit_apply(sv_circuit c, sv_state st, const double* params)

@@ -1,0 +1,26 @@
+// Runs of diagonal gates as one pass: declarations shared by the entry points
+// (sv_api.hip) and the kernel (k_phase.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace svk {
+
+constexpr int kMaxPhaseTerms = 64;
+constexpr int kMaxPhaseCommon = 40;
+
+// psi[x] *= exp(i pi sum_t turns[t] [x contains mask[t]]).  Amplitudes without
+// every bit of `common` (the bits all masks share) are not touched: the pass
+// enumerates the others, inserting `common`'s bits (ascending positions) as 1.
+struct PhaseRun {
+    int n_terms;
+    int n_common;
+    int common_pos[kMaxPhaseCommon];
+    int64_t groups;  // 2^(n - n_common)
+    uint64_t mask[kMaxPhaseTerms];
+    double turns[kMaxPhaseTerms];  // angle / pi
+};
+
+hipError_t launch_phase_run(void* psi, int dtype, const PhaseRun& pr, hipStream_t s);
+
+}  // namespace svk

@@ -102,6 +102,13 @@ def test_gate_validation():
         assert lib.sv_apply_dense(h, ints(0, 1, 2, 2), 4, md) == QUBIT  # repeated
         assert lib.sv_apply_dense(h, ints(0, 1, 2, 6), 4, md) == QUBIT  # out of range
         assert lib.sv_apply_dense(h, None, 4, md) == ARG
+        u64 = lambda *v: (ctypes.c_uint64 * max(1, len(v)))(*v)  # noqa: E731
+        ang = (ctypes.c_double * 65)()
+        assert lib.sv_apply_phases(h, 0, u64(1), ang) == ARG
+        assert lib.sv_apply_phases(h, 65, u64(*([1] * 65)), ang) == ARG  # more than 64 terms
+        assert lib.sv_apply_phases(h, 1, None, ang) == ARG
+        assert lib.sv_apply_phases(h, 1, u64(1), None) == ARG
+        assert lib.sv_apply_phases(h, 2, u64(1, 1 << 6), ang) == QUBIT  # bit 6 of a 6-qubit state
         assert lib.sv_set_basis(h, 64) == ARG
     finally:
         assert lib.sv_free(h) == OK
