@@ -521,6 +521,26 @@ def config3(sv, torch, n, layers, reps):
             del b
             torch.cuda.empty_cache()
         out[f"{name}_abs_err_expval_c64_vs_c128"] = abs(out[f"{name}_c64"]["expval_sum_z"] - out[f"{name}_c128"]["expval_sum_z"])
+    # the same QFT op by op on the single-gate kernels, with and without its
+    # controlled-phase runs fused into one phase pass per target
+    qft = sv.Circuit(n, W.qft_ops(n), 0)
+    for dt in ("c128", "c64"):
+        st = sv.State(n, dt, basis=x)
+        r = {}
+        for label, fuse in (("op_by_op_s", False), ("fused_diagonal_s", True)):
+            def run():
+                st.set_basis(x)
+                qft.apply(st, [], fuse_diagonal=fuse)
+                st.synchronize()
+            r[label] = _timed(torch, run, 1)
+        r["launches_op_by_op"] = len(W.qft_ops(n))
+        r["launches_fused"] = 2 * n - 1
+        r["speedup"] = r["op_by_op_s"] / r["fused_diagonal_s"]
+        out[f"qft_single_gate_kernels_{dt}"] = r
+        log(f"[bench] {n}-qubit QFT op by op {dt}: {r['op_by_op_s']:.3f} s, diagonal runs fused "
+            f"{r['fused_diagonal_s']:.3f} s")
+        del st
+        torch.cuda.empty_cache()
     return out
 
 
