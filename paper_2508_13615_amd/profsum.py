@@ -3,6 +3,7 @@
     python -m paper_2508_13615_amd.profsum stats  <prefix_kernel_stats.csv> [--top N]
     python -m paper_2508_13615_amd.profsum pmc    <prefix_counter_collection.csv> <out.json>
     python -m paper_2508_13615_amd.profsum traffic <fetch.json> <write.json> <stats.csv>
+    python -m paper_2508_13615_amd.profsum sweep-pmc <fetch.json> <write.json> <source_sha256>
 
 ``stats`` tabulates the kernel statistics that ``rocprofv3 --stats`` writes.
 ``pmc`` folds a per-dispatch counter CSV (one counter per run) into
@@ -10,7 +11,10 @@ per-kernel aggregates, small enough to keep.  ``traffic`` combines a
 FETCH_SIZE and a WRITE_SIZE aggregate with the kernel times: both counters are
 scaled by what they read for the runtime's copy kernel in the same run, which
 copies one whole state (as many bytes read as written), so that the scaled
-write of the copy equals its scaled read.
+write of the copy equals its scaled read.  ``sweep-pmc`` gives the same
+per launch for every kernel, with a machine-readable block (bytes per
+launch, scale factors, and the hash of the kernel sources the counters were
+taken with) that ``bench.py`` reads for ``roofline.traffic``.
 """
 from __future__ import annotations
 
@@ -81,6 +85,31 @@ def traffic_table(fetch_json: str, write_json: str, stats_csv: str, min_ms: floa
     return head + "\n".join(rows)
 
 
+def sweep_pmc(fetch_json: str, write_json: str, sha: str) -> str:
+    f = json.load(open(fetch_json))
+    w = json.load(open(write_json))
+    copy_f, copy_w = f[COPY_KERNEL]["max"], w[COPY_KERNEL]["max"]
+    ff = copy_w / copy_f
+    rows = ["| kernel | dispatches | FETCH KiB (raw) | WRITE KiB (raw) | read GiB (scaled) | written GiB (scaled) | "
+            "traffic GB |", "|---|---|---|---|---|---|---|"]
+    blk = {"fetch_factor": ff, "write_factor": 1.0, "source_sha256": sha, "kernels": {}}
+    for k in sorted(f, key=lambda k: -f[k]["dispatches"]):
+        if k == COPY_KERNEL or k not in w or not k.startswith("k_"):
+            continue
+        rd = f[k]["mean"] * ff * 1024
+        wr = w[k]["mean"] * 1024
+        rows.append(f"| `{k}` | {f[k]['dispatches']} | {f[k]['mean']:.0f} | {w[k]['mean']:.0f} | {rd / 2**30:.3f} | "
+                    f"{wr / 2**30:.3f} | {(rd + wr) / 1e9:.2f} |")
+        blk["kernels"][k] = {"dispatches": f[k]["dispatches"], "fetch_kib_raw": f[k]["mean"],
+                             "write_kib_raw": w[k]["mean"], "read_bytes": rd, "write_bytes": wr,
+                             "traffic_bytes": rd + wr}
+    head = (f"The scale factors come from the runtime's copy kernel (`{COPY_KERNEL}`) in the same runs, which "
+            f"copies one whole state: FETCH_SIZE reads {copy_f:.0f} KiB for it (fetch factor {ff:.4f}), "
+            f"WRITE_SIZE {copy_w:.0f} KiB (factor 1.0000).  Means per dispatch over the run.\n\n")
+    return head + "\n".join(rows) + "\n\nMachine-readable (bytes per dispatch after scaling):\n\n```json\n" + \
+        json.dumps(blk, indent=1) + "\n```\n"
+
+
 def main(argv):
     if len(argv) >= 2 and argv[0] == "stats":
         top = int(argv[argv.index("--top") + 1]) if "--top" in argv else 40
@@ -89,6 +118,8 @@ def main(argv):
         json.dump(pmc_aggregate(argv[1]), open(argv[2], "w"), indent=1)
     elif len(argv) == 4 and argv[0] == "traffic":
         print(traffic_table(argv[1], argv[2], argv[3]))
+    elif len(argv) == 4 and argv[0] == "sweep-pmc":
+        print(sweep_pmc(argv[1], argv[2], argv[3]))
     else:
         sys.exit(__doc__)
 
