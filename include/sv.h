@@ -242,6 +242,27 @@ sv_status sv_circuit_apply(sv_circuit c, sv_state st, const double* params);
  * rounding (phases are summed as angles). */
 sv_status sv_circuit_apply_fused(sv_circuit c, sv_state st, const double* params);
 
+/* As sv_circuit_apply, with the circuit packed into dense blocks of at most
+ * k qubits (k in [4, 6]) applied on the matrix cores (sv_apply_dense): a
+ * block starts from the earliest unapplied op and absorbs ready ops (every
+ * earlier op on their qubits already in a block; ops on disjoint qubits
+ * commute) that grow its qubit set least, while it spans at most k qubits.
+ * Each block's 2^k x 2^k matrix is formed on the host in double precision
+ * from the parameters; a block of a single op runs that op's own kernel, and
+ * blocks under 4 qubits are padded with further qubits.  The result equals
+ * sv_circuit_apply's within rounding.  *n_dense_blocks (may be NULL)
+ * receives the number of matrix-core blocks launched.
+ * Errors: as sv_circuit_apply; SV_ERR_ARG for k outside [4, 6] or a state
+ * of fewer than 4 qubits. */
+sv_status sv_circuit_apply_blocks(sv_circuit c, sv_state st, const double* params, int k, int* n_dense_blocks);
+
+/* Host-only: how sv_circuit_apply_blocks packs an op list (as given to
+ * sv_circuit_create) for block size k.  info[0] dense blocks, info[1] ops
+ * run alone, info[2] ops inside dense blocks (info[1] + info[2] = n_ops),
+ * info[3] the widest block in qubits (before padding).  Errors: SV_ERR_ARG,
+ * SV_ERR_QUBIT (bad or repeated qubits). */
+sv_status sv_block_plan(int n_qubits, const sv_op* ops, int n_ops, int k, int64_t* info);
+
 /* One pass of diagonal phases: psi[x] *= exp(i sum_t angles[t]) over the
  * terms t whose mask bits are all set in x (mask 0: every amplitude).  A
  * controlled phase on qubits S is the term (bits of S, phi).  Amplitudes

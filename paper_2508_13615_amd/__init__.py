@@ -243,6 +243,19 @@ def _sv_op(op) -> Tuple[SvOp, Optional[np.ndarray]]:
     return s, keep
 
 
+def block_plan(n: int, ops, k: int) -> dict:
+    """How Circuit.apply(dense_block=k) packs an op list (host only, sv_block_plan)."""
+    ops = list(ops)
+    arr = (SvOp * max(1, len(ops)))()
+    keep = []
+    for i, op in enumerate(ops):
+        arr[i], kp = _sv_op(op)
+        keep.append(kp)
+    a = (ctypes.c_int64 * 4)()
+    check(lib.sv_block_plan(int(n), arr, len(ops), int(k), a))
+    return dict(zip(["dense_blocks", "single_ops", "ops_in_dense", "widest"], list(a)))
+
+
 class Circuit:
     """An op list bound into libsv (sv_circuit_create)."""
 
@@ -265,13 +278,21 @@ class Circuit:
             lib.sv_circuit_free(h)
             self.handle = None
 
-    def apply(self, state: State, params=(), fuse_diagonal: bool = False) -> State:
+    def apply(self, state: State, params=(), fuse_diagonal: bool = False, dense_block: int = 0) -> State:
         """Apply op by op; with fuse_diagonal, each run of consecutive diagonal
-        ops is one phase pass (sv_circuit_apply_fused)."""
+        ops is one phase pass (sv_circuit_apply_fused); with dense_block = k
+        (4..6), the circuit runs as dense k-qubit blocks on the matrix cores
+        (sv_circuit_apply_blocks)."""
         p, pp = _dbl(list(params) if len(params) else [0.0])
+        if dense_block:
+            nb = ctypes.c_int()
+            check(lib.sv_circuit_apply_blocks(self.handle, state.handle, pp, int(dense_block), ctypes.byref(nb)))
+            self.last_dense_blocks = nb.value
+            return state
         fn = lib.sv_circuit_apply_fused if fuse_diagonal else lib.sv_circuit_apply
         check(fn(self.handle, state.handle, pp))
         return state
+
 
     def adjoint_grad(self, psi: State, lam: State, params, obs) -> Tuple[float, np.ndarray]:
         """Returns (E, dE/dparams); psi holds the input state on entry and again

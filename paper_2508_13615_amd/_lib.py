@@ -27,7 +27,7 @@ EXPORTS = [
     "sv_copy_to_host", "sv_copy_from_host", "sv_copy_state", "sv_synchronize", "sv_apply_gate",
     "sv_apply_controlled", "sv_apply_general", "sv_apply_dense", "sv_apply_phases", "sv_norm2", "sv_expval_pauli",
     "sv_expval_obs", "sv_expval_obs_dev", "sv_circuit_create", "sv_circuit_free", "sv_circuit_apply",
-    "sv_circuit_apply_fused", "sv_adjoint_grad",
+    "sv_circuit_apply_fused", "sv_circuit_apply_blocks", "sv_block_plan", "sv_adjoint_grad",
     "sv_batch_create", "sv_batch_plan", "sv_batch_run", "sv_batch_info", "sv_batch_state", "sv_batch_copy_state",
     "sv_batch_free",
     "sv_tune_set", "sv_tune_get", "sv_tune_engine_set", "sv_tune_engine_get", "sv_plan_info", "sv_last_error",
@@ -93,6 +93,8 @@ def _load():
         "sv_circuit_free": [vp],
         "sv_circuit_apply": [vp, vp, dp],
         "sv_circuit_apply_fused": [vp, vp, dp],
+        "sv_circuit_apply_blocks": [vp, vp, dp, i, ip],
+        "sv_block_plan": [i, ctypes.POINTER(SvOp), i, i, ctypes.POINTER(ctypes.c_int64)],
         "sv_adjoint_grad": [vp, vp, vp, dp, ctypes.POINTER(SvObs), dp, dp],
         "sv_batch_create": [ctypes.POINTER(SvBatchCircuit), i, i, ctypes.POINTER(SvBatchOpts), ctypes.POINTER(vp)],
         "sv_batch_free": [vp],

@@ -16,6 +16,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <complex>
 #include <cstdio>
 #include <mutex>
 #include <string>
@@ -1240,6 +1241,233 @@ sv_status sv_circuit_apply_fused(sv_circuit c, sv_state st, const double* params
     if (st->n != c->n) return set_error(SV_ERR_ARG, "state size does not match the circuit");
     if (c->n_params > 0 && !params) return set_error(SV_ERR_ARG, "null params");
     return circuit_forward_fused(c, st, params);
+}
+
+// ---- circuits as dense blocks on the matrix cores ---------------------------
+
+using cplx = std::complex<double>;
+
+static uint64_t op_qubit_mask(const OpRec& o)
+{
+    uint64_t m = 0;
+    for (int j = 0; j < o.nc + o.nt; ++j) m |= 1ull << o.q[j];
+    return m;
+}
+
+// The op's matrix on its targets (2^nt square, row-major, first target the
+// most significant bit), as the gate kernels apply it.
+static void op_target_matrix(const OpRec& o, const double* params, std::vector<cplx>& m)
+{
+    const double th = o.pidx >= 0 ? params[o.pidx] : o.value;
+    const double c = cos(th / 2), s = sin(th / 2), r = M_SQRT1_2;
+    const cplx i1(0, 1);
+    switch (o.gate) {
+    case SV_X: m = {0, 1, 1, 0}; break;
+    case SV_Y: m = {0, -i1, i1, 0}; break;
+    case SV_Z: m = {1, 0, 0, -1}; break;
+    case SV_H: m = {r, r, r, -r}; break;
+    case SV_S: m = {1, 0, 0, i1}; break;
+    case SV_T: m = {1, 0, 0, std::polar(1.0, M_PI / 4)}; break;
+    case SV_RX: m = {c, -i1 * s, -i1 * s, c}; break;
+    case SV_RY: m = {c, -s, s, c}; break;
+    case SV_RZ: m = {std::polar(1.0, -th / 2), 0, 0, std::polar(1.0, th / 2)}; break;
+    case SV_PHASE: m = {1, 0, 0, std::polar(1.0, th)}; break;
+    case SV_SWAP: m = {1, 0, 0, 0, 0, 0, 1, 0, 0, 1, 0, 0, 0, 0, 0, 1}; break;
+    case SV_U2:
+    case SV_U4: {
+        const size_t d = (size_t)1 << o.nt;
+        m.resize(d * d);
+        for (size_t i = 0; i < d * d; ++i) m[i] = cplx(o.matrix[2 * i], o.matrix[2 * i + 1]);
+        break;
+    }
+    default: m = {1, 0, 0, 1}; break;  // identity
+    }
+}
+
+// v (2^k amplitudes, local bit p of the index = block qubit of position p)
+// <- the op on local target bits lt (lt[0] the matrix MSB), local controls lc.
+static void apply_local(cplx* v, int k, const std::vector<cplx>& g, const int* lt, int nt, const int* lc, int nc)
+{
+    uint64_t tmask = 0, cmask = 0;
+    for (int j = 0; j < nt; ++j) tmask |= 1ull << lt[j];
+    for (int j = 0; j < nc; ++j) cmask |= 1ull << lc[j];
+    const int d = 1 << nt;
+    uint64_t idx[4];
+    cplx w[4];
+    for (uint64_t i = 0; i < (1ull << k); ++i) {
+        if ((i & tmask) || (i & cmask) != cmask) continue;
+        for (int r = 0; r < d; ++r) {
+            uint64_t o = i;
+            for (int j = 0; j < nt; ++j)
+                if ((r >> (nt - 1 - j)) & 1) o |= 1ull << lt[j];
+            idx[r] = o;
+        }
+        for (int r = 0; r < d; ++r) {
+            cplx acc = 0;
+            for (int c2 = 0; c2 < d; ++c2) acc += g[r * d + c2] * v[idx[c2]];
+            w[r] = acc;
+        }
+        for (int r = 0; r < d; ++r) v[idx[r]] = w[r];
+    }
+}
+
+struct BlockPlan {
+    std::vector<std::vector<int>> blocks;  // op indices in application order
+    std::vector<uint64_t> qubits;          // qubit mask of each block
+};
+
+// Greedy, commutation-aware packing: a block starts from the earliest
+// unscheduled op and keeps absorbing a ready op (every earlier op sharing a
+// qubit with it already placed) that grows its qubit set least, while the
+// set stays within k qubits.  Ops on more than k qubits form blocks alone.
+static void plan_blocks(int n, const std::vector<OpRec>& ops, int k, BlockPlan& bp)
+{
+    const int nops = (int)ops.size();
+    std::vector<std::vector<int>> qops(n);
+    std::vector<uint64_t> mask(nops);
+    for (int i = 0; i < nops; ++i) {
+        mask[i] = op_qubit_mask(ops[i]);
+        for (int q = 0; q < n; ++q)
+            if ((mask[i] >> q) & 1) qops[q].push_back(i);
+    }
+    std::vector<size_t> head(n, 0);
+    std::vector<char> done(nops, 0);
+    auto ready = [&](int i) {
+        for (int q = 0; q < n; ++q)
+            if (((mask[i] >> q) & 1) && qops[q][head[q]] != i) return false;
+        return true;
+    };
+    auto place = [&](int i) {
+        for (int q = 0; q < n; ++q)
+            if ((mask[i] >> q) & 1) ++head[q];
+        done[i] = 1;
+    };
+    int next = 0;
+    while (true) {
+        while (next < nops && done[next]) ++next;
+        if (next == nops) break;
+        std::vector<int> blk{next};
+        uint64_t S = mask[next];
+        place(next);
+        if (__builtin_popcountll(S) <= k) {
+            while (true) {
+                int best = -1, best_growth = 64;
+                for (int q = 0; q < n; ++q) {
+                    if (head[q] >= qops[q].size()) continue;
+                    const int i = qops[q][head[q]];
+                    if (done[i] || !ready(i) || __builtin_popcountll(S | mask[i]) > k) continue;
+                    const int growth = __builtin_popcountll(mask[i] & ~S);
+                    if (growth < best_growth || (growth == best_growth && i < best)) {
+                        best = i;
+                        best_growth = growth;
+                    }
+                }
+                if (best < 0) break;
+                blk.push_back(best);
+                S |= mask[best];
+                place(best);
+            }
+        }
+        bp.blocks.push_back(blk);
+        bp.qubits.push_back(S);
+    }
+}
+
+static sv_status circuit_forward_blocks(sv_circuit c, sv_state st, const double* params, int k, int* n_dense)
+{
+    BlockPlan bp;
+    plan_blocks(c->n, c->ops, k, bp);
+    int dense = 0;
+    std::vector<cplx> g, M, col;
+    for (size_t b = 0; b < bp.blocks.size(); ++b) {
+        const std::vector<int>& blk = bp.blocks[b];
+        uint64_t S = bp.qubits[b];
+        if (blk.size() == 1) {  // a lone op keeps its own kernel
+            Plan pl;
+            sv_status rc = op_plan(c, st->dtype, c->ops[blk[0]], params, 0, &pl);
+            if (!rc) rc = run_plan(pl, st, st->data);
+            if (rc) return rc;
+            continue;
+        }
+        // the matrix cores take 4..6 qubits: pad with the lowest qubits outside the block
+        for (int q = 0; q < st->n && __builtin_popcountll(S) < kDenseMinK; ++q) S |= 1ull << q;
+        std::vector<int> Q;  // block qubits, first = matrix MSB (descending)
+        for (int q = st->n - 1; q >= 0; --q)
+            if ((S >> q) & 1) Q.push_back(q);
+        const int kb = (int)Q.size();
+        int pos[64];  // qubit -> local bit of the matrix index
+        for (int j = 0; j < kb; ++j) pos[Q[j]] = kb - 1 - j;
+        const size_t d = (size_t)1 << kb;
+        M.assign(d * d, 0);
+        col.assign(d, 0);
+        std::vector<std::vector<cplx>> mats(blk.size());
+        for (size_t t = 0; t < blk.size(); ++t) op_target_matrix(c->ops[blk[t]], params, mats[t]);
+        for (size_t cc = 0; cc < d; ++cc) {
+            std::fill(col.begin(), col.end(), cplx(0));
+            col[cc] = 1;
+            for (size_t t = 0; t < blk.size(); ++t) {
+                const OpRec& o = c->ops[blk[t]];
+                int lt[2], lc[SV_OP_MAX_QUBITS];
+                for (int j = 0; j < o.nc; ++j) lc[j] = pos[o.q[j]];
+                for (int j = 0; j < o.nt; ++j) lt[j] = pos[o.q[o.nc + j]];
+                apply_local(col.data(), kb, mats[t], lt, o.nt, lc, o.nc);
+            }
+            for (size_t r = 0; r < d; ++r) M[r * d + cc] = col[r];
+        }
+        sv_status rc = sv_apply_dense(st, Q.data(), kb, (const double*)M.data());
+        if (rc) return rc;
+        ++dense;
+    }
+    if (n_dense) *n_dense = dense;
+    return SV_OK;
+}
+
+sv_status sv_circuit_apply_blocks(sv_circuit c, sv_state st, const double* params, int k, int* n_dense_blocks)
+{
+    SV_CHECK_CIRC(c);
+    SV_CHECK_STATE(st);
+    if (st->n != c->n) return set_error(SV_ERR_ARG, "state size does not match the circuit");
+    if (c->n_params > 0 && !params) return set_error(SV_ERR_ARG, "null params");
+    if (k < kDenseMinK || k > kDenseMaxK) return set_error(SV_ERR_ARG, "block size must be 4..6 qubits");
+    if (st->n < kDenseMinK) return set_error(SV_ERR_ARG, "dense blocks need a state of at least 4 qubits");
+    return circuit_forward_blocks(c, st, params, k, n_dense_blocks);
+}
+
+sv_status sv_block_plan(int n_qubits, const sv_op* ops, int n_ops, int k, int64_t* info)
+{
+    if (!info) return set_error(SV_ERR_ARG, "null info");
+    if (k < kDenseMinK || k > kDenseMaxK) return set_error(SV_ERR_ARG, "block size must be 4..6 qubits");
+    if (n_qubits < 1 || n_qubits > SV_MAX_QUBITS) return set_error(SV_ERR_ARG, "n_qubits out of range");
+    if (n_ops < 0 || (n_ops > 0 && !ops)) return set_error(SV_ERR_ARG, "bad op list");
+    std::vector<OpRec> recs(n_ops);
+    for (int i = 0; i < n_ops; ++i) {
+        const sv_op& so = ops[i];
+        OpRec& o = recs[i];
+        o.gate = so.gate;
+        o.nc = so.n_controls;
+        o.nt = so.n_targets;
+        if (o.nc < 0 || o.nt < 1 || o.nc + o.nt > SV_OP_MAX_QUBITS)
+            return set_error(SV_ERR_ARG, "op " + std::to_string(i) + ": bad qubit counts");
+        for (int j = 0; j < o.nc + o.nt; ++j) o.q[j] = so.qubits[j];
+        sv_status rc = check_qubits(n_qubits, o.q, o.nc, o.q + o.nc, o.nt);
+        if (rc) return rc;
+    }
+    BlockPlan bp;
+    plan_blocks(n_qubits, recs, k, bp);
+    int64_t dense = 0, single = 0, in_dense = 0, widest = 0;
+    for (size_t b = 0; b < bp.blocks.size(); ++b) {
+        if (bp.blocks[b].size() == 1) ++single;
+        else {
+            ++dense;
+            in_dense += (int64_t)bp.blocks[b].size();
+        }
+        widest = std::max<int64_t>(widest, __builtin_popcountll(bp.qubits[b]));
+    }
+    info[0] = dense;
+    info[1] = single;
+    info[2] = in_dense;
+    info[3] = widest;
+    return SV_OK;
 }
 
 sv_status sv_circuit_apply(sv_circuit c, sv_state st, const double* params)

@@ -264,3 +264,23 @@ def test_engine_tile_shape_tuning_host_only():
     finally:
         for k, (tq, apt) in saved.items():
             sv.tune_engine_set(*k, tq, apt)
+
+
+def test_block_plan_host_only():
+    # every op lands in exactly one block; blocks span at most k qubits; the
+    # 10-layer 32-qubit HEA packs into about 8 five-qubit blocks per layer
+    import workloads as W
+    for n, ops in ((32, W.hea_ops(32, 10)), (32, W.qft_ops(32)), (32, W.universal_ops(32)), (9, W.ghz_ops(9))):
+        for k in (4, 5, 6):
+            p = sv.block_plan(n, ops, k)
+            assert p["single_ops"] + p["ops_in_dense"] == len(ops)
+            assert p["widest"] <= k
+    assert sv.block_plan(32, W.hea_ops(32, 10), 5)["dense_blocks"] <= 9 * 10
+    # a Toffoli with two more controls (5 qubits) cannot join a 4-qubit block
+    big = [W.Op("X", (0, 1, 2, 3), (4,)), W.Op("H", (), (0,))]
+    p = sv.block_plan(6, big, 4)
+    assert p["single_ops"] == 2 and p["dense_blocks"] == 0 and p["widest"] == 5
+    with pytest.raises(sv.SvError):
+        sv.block_plan(6, big, 3)
+    with pytest.raises(sv.SvError):
+        sv.block_plan(6, [W.Op("H", (), (6,))], 4)

@@ -2,7 +2,10 @@
 the fp64 oracle: every block size in both dtypes, target orders ascending,
 descending, scattered and at the top of the index; states smaller than one
 16-group block; repeated calls that reuse the staging buffers; a 30-qubit
-complex128 state checked on sampled groups."""
+complex128 state checked on sampled groups.  Circuits packed into dense
+blocks (sv_circuit_apply_blocks): random circuits of every gate kind against
+the oracle, the QFT against its closed form, and the 32-qubit HEA against the
+fused pass engine on sampled amplitudes."""
 import sys
 
 import numpy as np
@@ -144,4 +147,100 @@ def test_dense_full_size_sampled_30q():
             ref = oracle.apply_matrix(before[row].copy(), tuple(range(k - 1, -1, -1)), u)
             assert np.max(np.abs(after[row] - ref)) <= 1e-12, (tg, row)
     del s, t
+    torch.cuda.empty_cache()
+
+
+def _mixed_circuit(n, rng, count):
+    ops, npar = [], 0
+    for _ in range(count):
+        q = [int(v) for v in rng.permutation(n)[:4]]
+        r = rng.random()
+        if r < 0.12:
+            ops.append(W.Op("H", (), (q[0],)))
+        elif r < 0.24:
+            ops.append(W.Op("X", (q[1],), (q[0],)))
+        elif r < 0.30:
+            ops.append(W.Op("X", (q[1], q[2]), (q[0],)))  # Toffoli
+        elif r < 0.40:
+            ops.append(W.Op("RY", (), (q[0],), npar, 0.0))
+            npar += 1
+        elif r < 0.50:
+            ops.append(W.Op("RZ", (q[1],), (q[0],), npar, 0.0))
+            npar += 1
+        elif r < 0.58:
+            ops.append(W.Op("RX", (), (q[0],), npar, 0.0))
+            npar += 1
+        elif r < 0.66:
+            ops.append(W.Op("PHASE", (q[1],), (q[0],), -1, float(rng.uniform(-3, 3))))
+        elif r < 0.72:
+            ops.append(W.Op("SWAP", (), (q[0], q[1])))
+        elif r < 0.80:
+            ops.append(W.Op("U4", (), (q[0], q[1]), -1, 0.0, W.haar_unitary(2, rng)))
+        elif r < 0.88:
+            ops.append(W.Op("U2", (q[2],), (q[0],), -1, 0.0, W.haar_unitary(1, rng)))
+        else:
+            ops.append(W.Op(["Y", "Z", "S", "T"][int(rng.integers(0, 4))], (), (q[0],)))
+    return ops, npar
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_circuit_dense_blocks_vs_oracle(dtype):
+    # random circuits of every gate kind, packed into 4-, 5- and 6-qubit
+    # blocks, against the oracle; the block count is the host plan's
+    n = 12
+    rng = np.random.default_rng(7700)
+    for trial, k in enumerate((4, 5, 6, 5)):
+        ops, npar = _mixed_circuit(n, rng, 150)
+        th = rng.uniform(0, 2 * np.pi, size=npar)
+        psi0 = _input(n, dtype, 7710 + trial)
+        circ = sv.Circuit(n, ops, npar)
+        a = circ.apply(sv.State(n, dtype, basis=None).load(psi0), th, dense_block=k).numpy().astype(np.complex128)
+        nb = circ.last_dense_blocks
+        ref = oracle.run_circuit(psi0.copy(), ops, th)
+        err = float(np.max(np.abs(a - ref)))
+        log(f"blocks {dtype} k={k}: {nb} dense blocks for {len(ops)} ops, error {err:.2e}")
+        assert nb == sv.block_plan(n, ops, k)["dense_blocks"]
+        assert err <= 10 * TOL[dtype], (k, err)
+
+
+@pytest.mark.parametrize("dtype,tol", [("c128", 1e-13), ("c64", 2e-7)])
+def test_qft_dense_blocks_closed_form(dtype, tol):
+    import math
+    n = 14
+    x = W.random_basis_index(n, 7800)
+    st = sv.State(n, dtype, basis=x)
+    sv.Circuit(n, W.qft_ops(n), 0).apply(st, [], dense_block=5)
+    got = st.numpy().astype(np.complex128)
+
+    def rev(y):
+        return int(format(y, f"0{n}b")[::-1], 2)
+    want = np.array([math.pow(2.0, -n / 2) * np.exp(2j * math.pi * ((x * rev(v)) % (1 << n)) / (1 << n))
+                     for v in range(1 << n)])
+    assert float(np.max(np.abs(got - want))) <= tol
+
+
+def test_hea32_dense_blocks_vs_engine_sampled():
+    """The 32-qubit, 10-layer HEA (complex128, 64 GiB) as 5-qubit blocks on
+    the matrix cores against the fused pass engine (an independent path, each
+    pinned to the oracle at small sizes) on 4096 sampled amplitudes."""
+    import torch
+    n, L = 32, 10
+    ops = W.hea_ops(n, L)
+    th = W.uniform_angles(W.hea_n_params(n, L), 1003)
+    idx = torch.as_tensor(np.unique(np.random.default_rng(7900).integers(0, 1 << n, size=4096, dtype=np.int64)),
+                          device="cuda")
+    log("hea32: fused engine")
+    b = sv.Batch([(n, ops, len(th), "sum_z")], "c128", with_grad=False)
+    b.run(th)
+    ref = b.state_tensor(0)[idx].cpu().numpy()
+    del b
+    torch.cuda.empty_cache()
+    log("hea32: dense blocks")
+    st = sv.State(n, "c128", basis=0)
+    sv.Circuit(n, ops, len(th)).apply(st, th, dense_block=5)
+    got = st.tensor[idx].cpu().numpy()
+    err = float(np.max(np.abs(got - ref)))
+    log(f"hea32 blocks vs engine: max sampled difference {err:.2e}")
+    assert err <= 1e-12, err
+    del st
     torch.cuda.empty_cache()
