@@ -495,7 +495,9 @@ def config5(sv, torch, reps, sequential):
 def config3(sv, torch, n, layers, reps):
     """32-qubit HEA (10 layers RY+RZ, CNOT ladder, from |0..0>), QFT of a
     random basis state and the universal circuit (2 n^2 gates after an H on
-    every qubit), forward + sum Z on the fused engine, both dtypes.  The
+    every qubit), forward + sum Z on the fused engine, both dtypes; the same
+    circuits as dense 5-qubit blocks on the matrix cores, and the QFT on the
+    single-gate kernels with and without fused diagonal runs.  The
     complex64 error is taken against the complex128 GPU result (itself
     checked against the fp64 oracle at 20 qubits by the GPU tests)."""
     import numpy as np
@@ -521,6 +523,24 @@ def config3(sv, torch, n, layers, reps):
             del b
             torch.cuda.empty_cache()
         out[f"{name}_abs_err_expval_c64_vs_c128"] = abs(out[f"{name}_c64"]["expval_sum_z"] - out[f"{name}_c128"]["expval_sum_z"])
+    # the same circuits packed into 5-qubit dense blocks on the matrix cores
+    for name, (ops, th) in jobs.items():
+        circ = sv.Circuit(n, ops, len(th))
+        plan = sv.block_plan(n, ops, 5)
+        for dt in ("c128", "c64"):
+            st = sv.State(n, dt, basis=0)
+
+            def run():
+                st.set_basis(0)
+                circ.apply(st, th, dense_block=5)
+                st.synchronize()
+            t = _timed(torch, run, 1)
+            out[f"{name}_{dt}"]["dense_blocks_k5_s"] = t
+            out[f"{name}_{dt}"]["dense_blocks_k5"] = plan["dense_blocks"]
+            log(f"[bench] {n}-qubit {name} {dt} as {plan['dense_blocks']} dense 5-qubit blocks: {t:.3f} s "
+                f"(pass engine {out[f'{name}_{dt}']['s']:.3f} s)")
+            del st
+            torch.cuda.empty_cache()
     # the same QFT op by op on the single-gate kernels, with and without its
     # controlled-phase runs fused into one phase pass per target
     qft = sv.Circuit(n, W.qft_ops(n), 0)
