@@ -238,7 +238,9 @@ sv_status sv_circuit_apply(sv_circuit c, sv_state st, const double* params);
  * ops (Z, S, T, PHASE, RZ, any controls; identity) applied as one pass of
  * sv_apply_phases: one read and write of the touched amplitudes per run
  * instead of per gate (diagonal gates commute; Sec. 2's Z-type gates only
- * rescale amplitudes).  The result equals sv_circuit_apply's within
+ * rescale amplitudes).  An uncontrolled one-target gate (X, Y, H, RX, RY,
+ * U2) directly followed by a diagonal run shares that run's pass: the QFT
+ * becomes one pass per target.  The result equals sv_circuit_apply's within
  * rounding (phases are summed as angles). */
 sv_status sv_circuit_apply_fused(sv_circuit c, sv_state st, const double* params);
 

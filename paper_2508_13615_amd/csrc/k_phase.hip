@@ -25,10 +25,42 @@ struct PhaseCplx<float> {
     using type = float2;
 };
 
+// The run's terms, staged in LDS once per workgroup: the per-amplitude loop
+// then reads them without a dependent scalar load per term.
+struct PhaseLds {
+    uint64_t mask[kMaxPhaseTerms];
+    double turns[kMaxPhaseTerms];
+};
+
+__device__ __forceinline__ void stage_terms(const PhaseRun& pr, PhaseLds& sm)
+{
+    for (int t = threadIdx.x; t < pr.n_terms; t += blockDim.x) {
+        sm.mask[t] = pr.mask[t];
+        sm.turns[t] = pr.turns[t];
+    }
+    __syncthreads();
+}
+
+// Sum of the angles (half-turns) of terms [begin, end) whose bits x holds.
+template <typename T>
+__device__ __forceinline__ T run_turns(uint64_t x, const PhaseLds& sm, int begin, int end)
+{
+    T th = T(0);
+#pragma unroll 4
+    for (int t = begin; t < end; ++t) {
+        const uint64_t m = sm.mask[t];
+        const T a = (T)sm.turns[t];
+        th += (x & m) == m ? a : T(0);
+    }
+    return th;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_phase_run(typename PhaseCplx<T>::type* __restrict__ psi, PhaseRun pr)
 {
     using V = typename PhaseCplx<T>::type;
+    __shared__ PhaseLds sm;
+    stage_terms(pr, sm);
     const int64_t step = (int64_t)gridDim.x * blockDim.x;
     for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < pr.groups; g += step) {
         uint64_t x = (uint64_t)g;
@@ -37,15 +69,69 @@ __global__ void __launch_bounds__(256) k_phase_run(typename PhaseCplx<T>::type* 
             const uint64_t lo = x & ((1ull << q) - 1ull);
             x = ((x >> q) << (q + 1)) | (1ull << q) | lo;
         }
-        T th = T(0);
-        for (int t = 0; t < pr.n_terms; ++t)
-            if ((x & pr.mask[t]) == pr.mask[t]) th += (T)pr.turns[t];
+        const T th = run_turns<T>(x, sm, 0, pr.n_terms);
         T sn, cs;
         if constexpr (sizeof(T) == 8) sincospi(th, &sn, &cs);
         else sincospif(th, &sn, &cs);
         const V a = psi[x];
         psi[x] = V{cs * a.x - sn * a.y, cs * a.y + sn * a.x};
     }
+}
+
+// A one-target gate u (row-major 2x2, interleaved) on qubit t followed by a
+// phase run, in one pass over the pairs of amplitudes that differ in bit t.
+// The first n_with terms hold bit t: only the partner with bit t set can
+// contain them.  The others hold neither or both partners alike, so each
+// term is tested once; with none of them the bit-0 partner keeps its phase.
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_pair_phase_run(typename PhaseCplx<T>::type* __restrict__ psi, int tq,
+                                                        PairCoef u, PhaseRun pr, int n_with)
+{
+    using V = typename PhaseCplx<T>::type;
+    const T u0r = (T)u.m[0], u0i = (T)u.m[1], u1r = (T)u.m[2], u1i = (T)u.m[3];
+    const T u2r = (T)u.m[4], u2i = (T)u.m[5], u3r = (T)u.m[6], u3i = (T)u.m[7];
+    __shared__ PhaseLds sm;
+    stage_terms(pr, sm);
+    const int64_t step = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < pr.groups; g += step) {
+        const uint64_t lo = (uint64_t)g & ((1ull << tq) - 1ull);
+        const uint64_t x0 = (((uint64_t)g >> tq) << (tq + 1)) | lo, x1 = x0 | (1ull << tq);
+        const V a = psi[x0], b = psi[x1];
+        const V p{u0r * a.x - u0i * a.y + u1r * b.x - u1i * b.y, u0r * a.y + u0i * a.x + u1r * b.y + u1i * b.x};
+        const V q{u2r * a.x - u2i * a.y + u3r * b.x - u3i * b.y, u2r * a.y + u2i * a.x + u3r * b.y + u3i * b.x};
+        const T th_both = run_turns<T>(x0, sm, n_with, pr.n_terms);
+        const T th1 = th_both + run_turns<T>(x1, sm, 0, n_with);
+        T s1, c1;
+        if constexpr (sizeof(T) == 8) sincospi(th1, &s1, &c1);
+        else sincospif(th1, &s1, &c1);
+        psi[x1] = V{c1 * q.x - s1 * q.y, c1 * q.y + s1 * q.x};
+        if (n_with == pr.n_terms) {  // uniform: no term can hold the bit-0 partner
+            psi[x0] = p;
+        } else {
+            T s0, c0;
+            if constexpr (sizeof(T) == 8) sincospi(th_both, &s0, &c0);
+            else sincospif(th_both, &s0, &c0);
+            psi[x0] = V{c0 * p.x - s0 * p.y, c0 * p.y + s0 * p.x};
+        }
+    }
+}
+
+hipError_t launch_pair_phase_run(void* psi, int dtype, int t, const PairCoef& u, const PhaseRun& pr, int n_with,
+                                 hipStream_t s)
+{
+    if (pr.groups <= 0 || pr.n_terms < 1 || pr.n_terms > kMaxPhaseTerms || pr.n_common != 0 || n_with < 0 ||
+        n_with > pr.n_terms)
+        return hipErrorInvalidValue;
+    const int threads = 256;
+    const int64_t blocks = std::min<int64_t>((pr.groups + threads - 1) / threads, 256 * 64);
+    if (dtype == SV_C128)
+        hipLaunchKernelGGL(k_pair_phase_run<double>, dim3((unsigned)blocks), dim3(threads), 0, s, (double2*)psi, t, u,
+                           pr, n_with);
+    else
+        hipLaunchKernelGGL(k_pair_phase_run<float>, dim3((unsigned)blocks), dim3(threads), 0, s, (float2*)psi, t, u, pr,
+                           n_with);
+    return hipGetLastError();
 }
 
 hipError_t launch_phase_run(void* psi, int dtype, const PhaseRun& pr, hipStream_t s)

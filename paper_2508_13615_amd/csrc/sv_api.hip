@@ -1187,25 +1187,80 @@ sv_status sv_apply_phases(sv_state st, int n_terms, const uint64_t* masks, const
     return run_phase_terms(st, masks, turns.data(), n_terms);
 }
 
+static void op_target_matrix(const OpRec& o, const double* params, std::vector<std::complex<double>>& m);
+
+// An uncontrolled one-target gate that is not diagonal: it can share a pass
+// with the diagonal run that follows it.
+static bool pair_fusable(const OpRec& o)
+{
+    if (o.nc != 0 || o.nt != 1) return false;
+    switch (o.gate) {
+    case SV_X:
+    case SV_Y:
+    case SV_H:
+    case SV_RX:
+    case SV_RY:
+    case SV_U2: return true;
+    default: return false;
+    }
+}
+
 // The circuit with every run of two or more consecutive diagonal ops applied
-// as one phase pass (a run longer than kMaxPhaseTerms terms takes several).
+// as one phase pass (a run longer than kMaxPhaseTerms terms takes several),
+// and an uncontrolled one-target gate followed by a diagonal run applied
+// together with it in one pass.
 static sv_status circuit_forward_fused(sv_circuit c, sv_state st, const double* params)
 {
     std::vector<uint64_t> masks;
     std::vector<double> turns;
     size_t run_begin = 0, run_len = 0;
+    int pending = -1;  // a pair gate waiting for the run after it
+    auto run_op = [&](const OpRec& o) -> sv_status {
+        Plan pl;
+        sv_status rc = op_plan(c, st->dtype, o, params, 0, &pl);
+        if (!rc) rc = run_plan(pl, st, st->data);
+        return rc;
+    };
     auto flush = [&]() -> sv_status {
         sv_status rc = SV_OK;
-        if (run_len == 1) {  // a lone diagonal op keeps its own kernel
-            Plan pl;
-            rc = op_plan(c, st->dtype, c->ops[run_begin], params, 0, &pl);
-            if (!rc) rc = run_plan(pl, st, st->data);
+        if (pending >= 0) {
+            if (masks.empty()) {
+                rc = run_op(c->ops[pending]);
+            } else {
+                std::vector<std::complex<double>> m;
+                op_target_matrix(c->ops[pending], params, m);
+                PairCoef u;
+                for (int e = 0; e < 4; ++e) {
+                    u.m[2 * e] = m[e].real();
+                    u.m[2 * e + 1] = m[e].imag();
+                }
+                // terms holding the gate's qubit first (they reach only its 1 side)
+                const uint64_t tb = 1ull << c->ops[pending].q[0];
+                PhaseRun pr;
+                memset(&pr, 0, sizeof pr);
+                int n_with = 0;
+                for (int pass = 0; pass < 2; ++pass)
+                    for (size_t t = 0; t < masks.size(); ++t)
+                        if (((masks[t] & tb) != 0) == (pass == 0)) {
+                            pr.mask[pr.n_terms] = masks[t];
+                            pr.turns[pr.n_terms] = turns[t];
+                            ++pr.n_terms;
+                            n_with += pass == 0;
+                        }
+                pr.groups = (int64_t)1 << (st->n - 1);
+                rc = hip_status(
+                    launch_pair_phase_run(st->data, st->dtype, c->ops[pending].q[0], u, pr, n_with, st->stream),
+                    "pair and phase run launch");
+            }
+        } else if (run_len == 1) {  // a lone diagonal op keeps its own kernel
+            rc = run_op(c->ops[run_begin]);
         } else if (!masks.empty()) {
             rc = run_phase_terms(st, masks.data(), turns.data(), (int)masks.size());
         }
         masks.clear();
         turns.clear();
         run_len = 0;
+        pending = -1;
         return rc;
     };
     for (size_t i = 0; i < c->ops.size(); ++i) {
@@ -1225,10 +1280,11 @@ static sv_status circuit_forward_fused(sv_circuit c, sv_state st, const double* 
         }
         sv_status rc = flush();
         if (rc) return rc;
-        Plan pl;
-        rc = op_plan(c, st->dtype, o, params, 0, &pl);
-        if (rc) return rc;
-        rc = run_plan(pl, st, st->data);
+        if (pair_fusable(o)) {
+            pending = (int)i;
+            continue;
+        }
+        rc = run_op(o);
         if (rc) return rc;
     }
     return flush();

@@ -23,4 +23,15 @@ struct PhaseRun {
 
 hipError_t launch_phase_run(void* psi, int dtype, const PhaseRun& pr, hipStream_t s);
 
+// Row-major 2x2 of a one-target gate, interleaved (re, im).
+struct PairCoef {
+    double m[8];
+};
+
+// The one-target gate u on qubit t, then the phase run, in one pass over the
+// amplitude pairs of bit t (pr.groups = 2^(n-1), pr.n_common = 0); the
+// run's first n_with terms hold bit t, the others do not.
+hipError_t launch_pair_phase_run(void* psi, int dtype, int t, const PairCoef& u, const PhaseRun& pr, int n_with,
+                                 hipStream_t s);
+
 }  // namespace svk
