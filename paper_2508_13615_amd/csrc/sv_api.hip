@@ -1234,8 +1234,40 @@ static sv_status circuit_forward_fused(sv_circuit c, sv_state st, const double* 
                     u.m[2 * e] = m[e].real();
                     u.m[2 * e + 1] = m[e].imag();
                 }
-                // terms holding the gate's qubit first (they reach only its 1 side)
                 const uint64_t tb = 1ull << c->ops[pending].q[0];
+                // every term holds the gate's qubit and at most one more bit: a
+                // phase linear in the bits, tabulated per byte by the kernel
+                bool linear = true;
+                for (uint64_t m2 : masks) linear &= (m2 & tb) && __builtin_popcountll(m2 & ~tb) <= 1;
+                if (linear) {
+                    LinearPhase lp;
+                    memset(&lp, 0, sizeof lp);
+                    int top = 0;
+                    for (size_t t = 0; t < masks.size(); ++t) {
+                        const uint64_t other = masks[t] & ~tb;
+                        if (!other) {
+                            lp.turns_const += turns[t];
+                            continue;
+                        }
+                        const int b = __builtin_ctzll(other);
+                        lp.turns_of_bit[b] += turns[t];
+                        top = std::max(top, b);
+                    }
+                    lp.n_bytes = top / 8 + 1;
+                    // the per-byte phase tables live in the state's workspace
+                    rc = ensure_work(st, kLinearPhaseTableBytes / sizeof(double));
+                    if (!rc)
+                        rc = hip_status(launch_pair_linear_phase(st->data, st->dtype, c->ops[pending].q[0], u, lp,
+                                                                 (int64_t)1 << (st->n - 1), st->work + kWorkHead,
+                                                                 st->stream),
+                                        "pair and linear phase launch");
+                    masks.clear();
+                    turns.clear();
+                    run_len = 0;
+                    pending = -1;
+                    return rc;
+                }
+                // terms holding the gate's qubit first (they reach only its 1 side)
                 PhaseRun pr;
                 memset(&pr, 0, sizeof pr);
                 int n_with = 0;

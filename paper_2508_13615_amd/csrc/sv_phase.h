@@ -34,4 +34,18 @@ struct PairCoef {
 hipError_t launch_pair_phase_run(void* psi, int dtype, int t, const PairCoef& u, const PhaseRun& pr, int n_with,
                                  hipStream_t s);
 
+// A phase run linear in the index's bits on the 1 side of a pair gate:
+// exp(i pi (turns_const + sum_b turns_of_bit[b] x_b)), bits 0 .. 8 n_bytes - 1.
+constexpr int kLinearPhaseBytes = 5;
+struct LinearPhase {
+    int n_bytes;
+    double turns_const;
+    double turns_of_bit[8 * kLinearPhaseBytes];
+};
+
+// table: device scratch of at least kLinearPhaseTableBytes (stream-ordered use).
+constexpr size_t kLinearPhaseTableBytes = (size_t)kLinearPhaseBytes * 256 * 16;
+hipError_t launch_pair_linear_phase(void* psi, int dtype, int t, const PairCoef& u, const LinearPhase& lp,
+                                    int64_t groups, void* table, hipStream_t s);
+
 }  // namespace svk
