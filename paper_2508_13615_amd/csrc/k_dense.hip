@@ -204,7 +204,11 @@ static hipError_t launch_k(T* psi, const T* B, const DenseSpec& sp, hipStream_t 
     }
     const int64_t nblk = (sp.groups + 15) / 16;
     const int64_t wpg = threads / 64;
-    const int64_t grid = std::min<int64_t>((nblk + wpg - 1) / wpg, 256 * 16);
+    // every workgroup loads the real form into LDS first: k = 6 (128 KiB,
+    // complex128) amortises it over many blocks per workgroup; smaller forms
+    // take a larger grid, whose concurrent workgroups stream closer together
+    const int64_t cap = K == 6 ? 256 * 16 : 256 * 256;
+    const int64_t grid = std::min<int64_t>((nblk + wpg - 1) / wpg, cap);
     hipLaunchKernelGGL((k_dense<T, K>), dim3((unsigned)grid), dim3(threads), lds, s, psi, B, sp);
     return hipGetLastError();
 }
