@@ -90,7 +90,7 @@ def plan_info(n: int, dtype: str, gate: str, targets: Sequence[int], controls: S
     if kc == 2 or kc == 3:
         name = f"{KERNEL_CLASSES[kc]}<{T}, {unroll}, {'true' if nt else 'false'}>"
     elif kc == 6:
-        name = f"k_lds_gate<{T}, {op >> 4}, {op & 15}, {'true' if nt else 'false'}>"
+        name = f"k_lds_gate<{T}, {op >> 4}, {op & 15}, {'true' if nt else 'false'}, {unroll}>"
     else:
         name = f"{KERNEL_CLASSES[kc]}<{T}, {op}, {unroll}, {'true' if nt else 'false'}>"
     return {"class": kc, "tier": tier, "op": op, "block": block, "unroll": unroll, "nt": nt, "kernel": name}

@@ -15,7 +15,7 @@ ansatz, a 30-qubit QFT and the same batch of 256 without the adjoint.  The
 result is written as JSON next to the library and loaded by
 ``paper_2508_13615_amd`` at import (``apply_table``).
 
-Run on the GPU:  python -m paper_2508_13615_amd.autotune [--qubits 30] [--engine-only]
+Run on the GPU:  python -m paper_2508_13615_amd.autotune [--qubits 30] [--engine-only | --classes K ...]
 """
 from __future__ import annotations
 
@@ -64,10 +64,34 @@ def _candidates(kc: int, n: int, rng, np):
             yield low, ("H", (low % 6,), ctl, (), None)
 
 
+def _lds_cases(sv, dtype: str, tier: int, n: int):
+    """The LDS-staged kernel at the lowest qubit of `tier`, in each of its
+    forms: 2-qubit matrices with none or one of the qubits above the staged
+    chunk, 3-qubit matrices with one or two above it, and the SWAP move.  Its
+    best block and staging depth differ between these forms, so the tier's
+    shape is chosen on all of them together."""
+    lows = [lo for lo in range(0, 6) if sv.plan_info(n, dtype, "GENERAL", (n - 1, lo))["class"] == 6
+            and sv.plan_info(n, dtype, "GENERAL", (n - 1, lo))["tier"] == tier]
+    if not lows:
+        return []
+    lo = lows[0]  # at most 5; qubits lo + 1 .. 7 sit inside the chunk
+    forms = [("GENERAL", (n - 1, lo)), ("GENERAL", (lo, 7)), ("GENERAL", (n - 1, n // 2, lo)),
+             ("GENERAL", (lo, lo + 1, n - 1)), ("SWAP", (n - 1, lo))]
+    out = []
+    for g, tg in forms:
+        info = sv.plan_info(n, dtype, g, tg)
+        if info["class"] == 6 and info["tier"] == tier:
+            out.append((g, tg, (), (), None))
+    return out
+
+
 def _cases(sv, kc: int, dtype: str, tier: int, n: int):
     """Up to two cases (lowest and highest reachable position) that libsv
-    launches with kernel class `kc` in `tier`; [] if the tier is unreachable."""
+    launches with kernel class `kc` in `tier`; [] if the tier is unreachable.
+    The LDS-staged class takes one case per form of the kernel instead."""
     import numpy as np
+    if kc == 6:
+        return _lds_cases(sv, dtype, tier, n)
     rng = np.random.default_rng(11)
     hits = []
     for low, case in _candidates(kc, n, rng, np):
@@ -80,7 +104,7 @@ def _cases(sv, kc: int, dtype: str, tier: int, n: int):
     return hits
 
 
-def _time_shape(sv, torch, st, kc, dtype, tier, shape, cases, u4, reps):
+def _time_shape(sv, torch, st, kc, dtype, tier, shape, cases, dense, reps):
     import numpy as np
     sv.tune_set(kc, dtype, tier, *shape)
     stream = torch.cuda.current_stream()
@@ -91,7 +115,7 @@ def _time_shape(sv, torch, st, kc, dtype, tier, shape, cases, u4, reps):
         e0.record(stream)
         for g, tg, ct, p, m in cases:
             if g == "GENERAL":
-                st.apply_general(tg, u4)
+                st.apply_general(tg, dense[len(tg)])
             else:
                 st.apply(g, tg, ct, p, m)
         e1.record(stream)
@@ -100,7 +124,8 @@ def _time_shape(sv, torch, st, kc, dtype, tier, shape, cases, u4, reps):
     return float(np.median(times[1:]))
 
 
-def tune(qubits: int = 30, reps: int = 3, dtypes=("c128", "c64"), log=print, margin: float = 0.02) -> dict:
+def tune(qubits: int = 30, reps: int = 3, dtypes=("c128", "c64"), log=print, margin: float = 0.02,
+         classes=tuple(CLASSES)) -> dict:
     """Two rounds per key: every candidate once (median of `reps`), then the
     four fastest and the library default again, interleaved, median of
     2*`reps`.  A candidate replaces the default only if it is `margin` faster."""
@@ -110,25 +135,26 @@ def tune(qubits: int = 30, reps: int = 3, dtypes=("c128", "c64"), log=print, mar
     import paper_2508_13615_amd as sv
 
     entries = []
-    u4 = np.linalg.qr(np.random.default_rng(5).standard_normal((4, 4)) + 0j)[0]
+    # dense unitaries for the GENERAL cases, by qubit count
+    dense = {k: np.linalg.qr(np.random.default_rng(3 + k).standard_normal((2 ** k, 2 ** k)) + 0j)[0] for k in (2, 3)}
     shapes = [(b, u, nt) for b in BLOCKS for u in UNROLLS for nt in (0, 1)]
     for dtype in dtypes:
         st = sv.State(qubits, dtype, basis=0)
-        for kc in CLASSES:
+        for kc in classes:
             for tier in range(3):
                 cases = _cases(sv, kc, dtype, tier, qubits)
                 if not cases:
                     log(f"[autotune] {dtype} {CLASSES[kc]:10s} tier {tier}: not reachable, default kept")
                     continue
                 default = sv.tune_get(kc, dtype, tier)
-                first = sorted((_time_shape(sv, torch, st, kc, dtype, tier, sh, cases, u4, reps), sh) for sh in shapes)
+                first = sorted((_time_shape(sv, torch, st, kc, dtype, tier, sh, cases, dense, reps), sh) for sh in shapes)
                 finalists = [sh for _, sh in first[:4]]
                 if default not in finalists:
                     finalists.append(default)
                 acc = {sh: [] for sh in finalists}
                 for _ in range(2):
                     for sh in finalists:
-                        acc[sh].append(_time_shape(sv, torch, st, kc, dtype, tier, sh, cases, u4, reps))
+                        acc[sh].append(_time_shape(sv, torch, st, kc, dtype, tier, sh, cases, dense, reps))
                 med = {sh: float(np.median(v)) for sh, v in acc.items()}
                 best = min(med, key=med.get)
                 if med[best] > (1.0 - margin) * med[default]:
@@ -241,17 +267,27 @@ def main():
     ap.add_argument("--out", default=TABLE)
     ap.add_argument("--engine-only", action="store_true",
                     help="tune only the fused engine's tile shape and keep the table's gate entries")
+    ap.add_argument("--classes", type=int, nargs="+", choices=sorted(CLASSES),
+                    help="tune only these gate kernel classes; the table's other entries, engine included, are kept")
     args = ap.parse_args()
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     if root not in sys.path:
         sys.path.insert(0, root)
     log = lambda *a: print(*a, file=sys.stderr, flush=True)  # noqa: E731
-    if args.engine_only:
+    if args.classes:
+        with open(TABLE) as f:
+            tab = json.load(f)
+        new = tune(args.qubits, args.reps, log=log, classes=tuple(args.classes))
+        keep = [e for e in tab["entries"] if e["class"] not in args.classes]
+        tab["entries"] = sorted(keep + new["entries"], key=lambda e: (e["dtype"] != "c128", e["class"], e["tier"]))
+        tab["created"] = new["created"]
+    elif args.engine_only:
         with open(args.out) as f:
             tab = json.load(f)
+        tab["engine"] = tune_engine(log=log)
     else:
         tab = tune(args.qubits, args.reps, log=log)
-    tab["engine"] = tune_engine(log=log)
+        tab["engine"] = tune_engine(log=log)
     with open(args.out, "w") as f:
         json.dump(tab, f, indent=1)
     print(f"wrote {args.out} ({len(tab['entries'])} gate entries, {len(tab['engine'])} engine entries)",

@@ -24,6 +24,7 @@
 // complex128 state) non-temporal accesses of partial lines cost up to 35%,
 // so the launch table (sv_api.hip) switches them off there.
 #include <algorithm>
+#include <type_traits>
 
 #include "sv_core.h"
 
@@ -337,7 +338,7 @@ k_general(typename Vec2<T>::type* __restrict__ psi, GroupSpec gs, GeneralSpec<T,
 // LDS-staged gate for gates with a low qubit (runs under 1 KiB): whole
 // contiguous chunks are streamed in and out non-temporally, so every access is
 // a full line however low the gate's qubits sit; the gate itself runs in LDS.
-template <typename T, int K, int OP, bool NT>
+template <typename T, int K, int OP, bool NT, int B>
 __global__ void __launch_bounds__(1024)
 k_lds_gate(typename Vec2<T>::type* __restrict__ psi, GroupSpec tiles, LdsSpec ls, GeneralSpec<T, K> sp)
 {
@@ -348,14 +349,35 @@ k_lds_gate(typename Vec2<T>::type* __restrict__ psi, GroupSpec tiles, LdsSpec ls
     constexpr int M = 1 << K;
     const uint32_t nl = 1u << (C + ls.h);
     const uint32_t cmask_lo = (1u << C) - 1u;
+    // stage element l (0 .. nl - 1) <-> state index: its low C bits stay in
+    // place, bit j of l >> C goes to gate qubit hq[j]
+    auto index_of = [&](uint64_t base, uint32_t l) {
+        uint64_t g = base | (l & cmask_lo);
+        const uint32_t hc = l >> C;
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            if (j < ls.h && ((hc >> j) & 1u)) g |= 1ull << ls.hq[j];
+        return g;
+    };
+    // a thread moves up to B elements per round trip: all its loads are
+    // issued before the first LDS write (and all LDS reads before the first
+    // store), so B lines per thread are in flight at once; B = 1 keeps the
+    // registers, and with them the occupancy, at their lowest
+    const uint32_t step = blockDim.x * B;
     for (uint64_t tile = blockIdx.x; tile < tiles.n_groups; tile += gridDim.x) {
         const uint64_t base = (group_base(tile, tiles) << C) | ls.cmask;
-        for (uint32_t l = threadIdx.x; l < nl; l += blockDim.x) {
-            uint64_t g = base | (l & cmask_lo);
-            const uint32_t hc = l >> C;
-            for (int j = 0; j < ls.h; ++j)
-                if ((hc >> j) & 1u) g |= 1ull << ls.hq[j];
-            st[l] = ldg<NT>(psi + g);
+        for (uint32_t l0 = threadIdx.x; l0 < nl; l0 += step) {
+            V buf[B];
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                const uint32_t l = l0 + u * blockDim.x;
+                if (l < nl) buf[u] = ldg<NT>(psi + index_of(base, l));
+            }
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                const uint32_t l = l0 + u * blockDim.x;
+                if (l < nl) st[l] = buf[u];
+            }
         }
         __syncthreads();
         const uint32_t ng = nl >> K;
@@ -401,12 +423,18 @@ k_lds_gate(typename Vec2<T>::type* __restrict__ psi, GroupSpec tiles, LdsSpec ls
             }
         }
         __syncthreads();
-        for (uint32_t l = threadIdx.x; l < nl; l += blockDim.x) {
-            uint64_t g = base | (l & cmask_lo);
-            const uint32_t hc = l >> C;
-            for (int j = 0; j < ls.h; ++j)
-                if ((hc >> j) & 1u) g |= 1ull << ls.hq[j];
-            stg<NT>(psi + g, st[l]);
+        for (uint32_t l0 = threadIdx.x; l0 < nl; l0 += step) {
+            V buf[B];
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                const uint32_t l = l0 + u * blockDim.x;
+                if (l < nl) buf[u] = st[l];
+            }
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                const uint32_t l = l0 + u * blockDim.x;
+                if (l < nl) stg<NT>(psi + index_of(base, l), buf[u]);
+            }
         }
         __syncthreads();
     }
@@ -588,16 +616,29 @@ static hipError_t launch_lds_k(typename Vec2<T>::type* p, const GroupSpec& tiles
         for (int i = 0; i < 2 * (1 << K) * (1 << K); ++i) sp.m[i] = m[i];
     const dim3 grid((unsigned)grid_cap(tiles.n_groups, lc.block)), blk(lc.block);
     const size_t lds = sizeof(typename Vec2<T>::type) << (kLdsChunkBits + ls.h);
-    if (op == 1) {
-        if constexpr (K == 2) {
-            if (lc.nt) hipLaunchKernelGGL((k_lds_gate<T, 2, 1, true>), grid, blk, lds, s, p, tiles, ls, sp);
-            else hipLaunchKernelGGL((k_lds_gate<T, 2, 1, false>), grid, blk, lds, s, p, tiles, ls, sp);
+    if (op == 1 && K != 2) return hipErrorInvalidValue;
+    // the launch shape's unroll is the number of lines a thread stages per
+    // round trip
+    auto go = [&](auto nt_tag, auto b_tag) {
+        constexpr bool NTv = decltype(nt_tag)::value;
+        constexpr int Bv = decltype(b_tag)::value;
+        if (op == 1) {
+            if constexpr (K == 2) hipLaunchKernelGGL((k_lds_gate<T, 2, 1, NTv, Bv>), grid, blk, lds, s, p, tiles, ls, sp);
         } else {
-            return hipErrorInvalidValue;
+            hipLaunchKernelGGL((k_lds_gate<T, K, 0, NTv, Bv>), grid, blk, lds, s, p, tiles, ls, sp);
         }
+    };
+    using I1 = std::integral_constant<int, 1>;
+    using I2 = std::integral_constant<int, 2>;
+    using I4 = std::integral_constant<int, 4>;
+    if (lc.nt) {
+        if (lc.unroll == 4) go(std::true_type{}, I4{});
+        else if (lc.unroll == 2) go(std::true_type{}, I2{});
+        else go(std::true_type{}, I1{});
     } else {
-        if (lc.nt) hipLaunchKernelGGL((k_lds_gate<T, K, 0, true>), grid, blk, lds, s, p, tiles, ls, sp);
-        else hipLaunchKernelGGL((k_lds_gate<T, K, 0, false>), grid, blk, lds, s, p, tiles, ls, sp);
+        if (lc.unroll == 4) go(std::false_type{}, I4{});
+        else if (lc.unroll == 2) go(std::false_type{}, I2{});
+        else go(std::false_type{}, I1{});
     }
     return hipGetLastError();
 }

@@ -83,6 +83,62 @@ def test_general_kernel_vs_oracle(dtype):
             assert err <= TOL[dtype], (k, qs, err)
 
 
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_lds_staged_gate_every_launch_shape(dtype):
+    """Every launch shape the tuner may pick for the LDS-staged kernel (block,
+    lines staged per thread, non-temporal or not) on gates with a qubit
+    below the 1 KiB run: dense 2- and 3-qubit matrices, U4 with and without
+    controls below and above the 256-amplitude chunk, and the SWAP move, with
+    0 to 2 gate qubits above the chunk, against the oracle (SWAP
+    bit-exact).  The launch table is restored after."""
+    n = 13
+    rng = np.random.default_rng(2010)
+    psi0 = W.gaussian_state(n, 2011).astype(NP_DT[dtype])
+    base = sv.State(n, dtype).load(psi0)
+    work = sv.State(n, dtype)
+    ref_in = psi0.astype(np.complex128)
+    cases = []
+    for qs in [(0, 3), (12, 0), (2, 9), (1, 2, 5), (0, 12, 8), (11, 4, 10)]:
+        cases.append(("GENERAL", qs, (), W.haar_unitary(len(qs), rng)))
+    cases += [("U4", (12, 1), (), W.haar_unitary(2, rng)), ("U4", (1, 12), (5,), W.haar_unitary(2, rng)),
+              ("U4", (0, 4), (9, 11), W.haar_unitary(2, rng)), ("SWAP", (0, 11), (), None),
+              ("SWAP", (4, 2), (), None), ("SWAP", (1, 3), (12,), None)]
+    hit = set()
+    for g, qs, ct, m in cases:
+        info = sv.plan_info(n, dtype, g, qs, ct)
+        if info["class"] == 6:
+            hit.add((len(qs), info["op"] & 15))
+    assert {(2, 0), (3, 0), (2, 1)} <= hit, hit
+    saved = {t: sv.tune_get(6, dtype, t) for t in range(3)}
+    try:
+        for block in (64, 128, 256, 512):
+            for unroll in (1, 2, 4):
+                for nt in (0, 1):
+                    for t in range(3):
+                        sv.tune_set(6, dtype, t, block, unroll, nt)
+                    for g, qs, ct, m in cases:
+                        work.copy_from(base)
+                        if g == "GENERAL":
+                            work.apply_general(qs, m)
+                            ref = oracle.apply_matrix(ref_in.copy(), qs, m)
+                        elif g == "SWAP":
+                            work.apply("SWAP", qs, ct)
+                            ref = oracle.apply_gate(psi0.copy(), "SWAP", qs, ct)
+                        else:
+                            work.apply(g, qs, ct, matrix=m)
+                            ref = oracle.apply_gate(ref_in.copy(), g, qs, ct, (), m)
+                        got = work.numpy()
+                        if g == "SWAP":
+                            assert np.array_equal(got.view(np.uint8), ref.view(np.uint8)), (block, unroll, nt, qs)
+                        else:
+                            err = float(np.max(np.abs(got.astype(np.complex128) - ref)))
+                            assert err <= TOL[dtype], (block, unroll, nt, g, qs, err)
+                log(f"lds {dtype}: block {block} shapes ok")
+    finally:
+        for t, shp in saved.items():
+            sv.tune_set(6, dtype, t, *shp)
+
+
 def test_general_kernel_equals_specific_for_permutations():
     # Sec. 3.1 "general approach": CNOT as a 4x4 and Toffoli as an 8x8 dense
     # matrix give the same state as the dedicated move kernels (products with
