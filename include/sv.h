@@ -363,8 +363,10 @@ sv_status sv_batch_free(sv_batch b);
  * qubit has runs under 1 KiB).  Tier: bytes spanned by
  * one run of consecutive touched amplitudes, 2^(lowest touched qubit) times
  * the element size: 0 (< 64 B), 1 (< 1 KiB), 2 (larger).  block is a
- * multiple of 64 in [64, 1024]; unroll (groups per thread) is 1, 2 or 4;
- * nt = 1 makes the kernel's loads and stores non-temporal.  The table is
+ * multiple of 64 in [64, 1024]; unroll is 1, 2 or 4: groups per thread,
+ * and for class 6 the contiguous chunk elements a thread loads (and stores)
+ * per round trip between HBM and LDS; nt = 1 makes the kernel's loads and
+ * stores non-temporal.  The table is
  * process-wide; set it from one thread before launching work.
  * Errors: SV_ERR_ARG for a bad key or shape.
  * ------------------------------------------------------------------------ */
