@@ -364,9 +364,9 @@ sv_status sv_batch_free(sv_batch b);
  * one run of consecutive touched amplitudes, 2^(lowest touched qubit) times
  * the element size: 0 (< 64 B), 1 (< 1 KiB), 2 (larger).  block is a
  * multiple of 64 in [64, 1024]; unroll is 1, 2 or 4: groups per thread,
- * and for class 6 the contiguous chunk elements a thread loads (and stores)
- * per round trip between HBM and LDS; nt = 1 makes the kernel's loads and
- * stores non-temporal.  The table is
+ * and for class 6 the chunk elements a thread of a 3-qubit gate loads (and
+ * stores) per round trip between HBM and LDS (1- and 2-qubit gates move
+ * one); nt = 1 makes the kernel's loads and stores non-temporal.  The table is
  * process-wide; set it from one thread before launching work.
  * Errors: SV_ERR_ARG for a bad key or shape.
  * ------------------------------------------------------------------------ */

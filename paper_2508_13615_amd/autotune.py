@@ -68,8 +68,9 @@ def _lds_cases(sv, dtype: str, tier: int, n: int):
     """The LDS-staged kernel at the lowest qubit of `tier`, in each of its
     forms: 2-qubit matrices with none or one of the qubits above the staged
     chunk, 3-qubit matrices with one or two above it, and the SWAP move.  Its
-    best block and staging depth differ between these forms, so the tier's
-    shape is chosen on all of them together."""
+    best block differs between these forms, so the tier's shape is chosen on
+    all of them together; the unroll (lines staged per thread per round
+    trip) acts on the 3-qubit form only."""
     lows = [lo for lo in range(0, 6) if sv.plan_info(n, dtype, "GENERAL", (n - 1, lo))["class"] == 6
             and sv.plan_info(n, dtype, "GENERAL", (n - 1, lo))["tier"] == tier]
     if not lows:

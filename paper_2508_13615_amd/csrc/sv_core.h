@@ -93,6 +93,9 @@ __device__ __forceinline__ uint64_t group_base(uint64_t g, const GroupSpec& gs)
 // qubits at or above kLdsChunkBits -- applies the gate to every group inside
 // the stage and streams the chunks back.
 constexpr int kLdsChunkBits = 8;
+// Lines a thread of the LDS-staged kernel moves per round trip between HBM
+// and LDS for a k-qubit gate under a launch shape's unroll.
+inline int lds_stage_depth(int k, int unroll) { return k == 3 ? unroll : 1; }
 struct LdsSpec {
     int32_t k;        // gate qubits (1..3)
     int32_t h;        // gate qubits >= kLdsChunkBits
