@@ -238,10 +238,12 @@ sv_status sv_circuit_apply(sv_circuit c, sv_state st, const double* params);
  * ops (Z, S, T, PHASE, RZ, any controls; identity) applied as one pass of
  * sv_apply_phases: one read and write of the touched amplitudes per run
  * instead of per gate (diagonal gates commute; Sec. 2's Z-type gates only
- * rescale amplitudes).  An uncontrolled one-target gate (X, Y, H, RX, RY,
- * U2) directly followed by a diagonal run shares that run's pass: the QFT
- * becomes one pass per target.  The result equals sv_circuit_apply's within
- * rounding (phases are summed as angles). */
+ * rescale amplitudes).  Consecutive uncontrolled one-target gates (X, Y, H,
+ * RX, RY, U2) on one qubit are multiplied into one 2x2 on the host and
+ * applied once; such a gate (or product) directly followed by a diagonal
+ * run shares that run's pass: the QFT becomes one pass per target.  The
+ * result equals sv_circuit_apply's within rounding (phases are summed as
+ * angles, 2x2 products formed in double precision). */
 sv_status sv_circuit_apply_fused(sv_circuit c, sv_state st, const double* params);
 
 /* As sv_circuit_apply, with the circuit packed into dense blocks of at most

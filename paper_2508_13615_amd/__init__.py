@@ -280,7 +280,8 @@ class Circuit:
 
     def apply(self, state: State, params=(), fuse_diagonal: bool = False, dense_block: int = 0) -> State:
         """Apply op by op; with fuse_diagonal, each run of consecutive diagonal
-        ops is one phase pass (sv_circuit_apply_fused); with dense_block = k
+        ops is one phase pass and consecutive one-target gates on one qubit
+        one 2x2 (sv_circuit_apply_fused); with dense_block = k
         (4..6), the circuit runs as dense k-qubit blocks on the matrix cores
         (sv_circuit_apply_blocks)."""
         p, pp = _dbl(list(params) if len(params) else [0.0])

@@ -1207,14 +1207,17 @@ static bool pair_fusable(const OpRec& o)
 
 // The circuit with every run of two or more consecutive diagonal ops applied
 // as one phase pass (a run longer than kMaxPhaseTerms terms takes several),
-// and an uncontrolled one-target gate followed by a diagonal run applied
-// together with it in one pass.
+// consecutive uncontrolled one-target gates on one qubit composed into one
+// 2x2, and such a gate followed by a diagonal run applied together with it
+// in one pass.
 static sv_status circuit_forward_fused(sv_circuit c, sv_state st, const double* params)
 {
     std::vector<uint64_t> masks;
     std::vector<double> turns;
     size_t run_begin = 0, run_len = 0;
     int pending = -1;  // a pair gate waiting for the run after it
+    std::vector<std::complex<double>> pend;  // its matrix, later same-qubit gates composed on
+    int pend_ops = 0;                        // ops composed into pend
     auto run_op = [&](const OpRec& o) -> sv_status {
         Plan pl;
         sv_status rc = op_plan(c, st->dtype, o, params, 0, &pl);
@@ -1225,14 +1228,24 @@ static sv_status circuit_forward_fused(sv_circuit c, sv_state st, const double* 
         sv_status rc = SV_OK;
         if (pending >= 0) {
             if (masks.empty()) {
-                rc = run_op(c->ops[pending]);
+                if (pend_ops == 1) {
+                    rc = run_op(c->ops[pending]);
+                } else {  // the composed 2x2 as a U2 on the same qubit
+                    OpRec u2 = c->ops[pending];
+                    u2.gate = SV_U2;
+                    u2.pidx = -1;
+                    u2.matrix.resize(8);
+                    for (int e = 0; e < 4; ++e) {
+                        u2.matrix[2 * e] = pend[e].real();
+                        u2.matrix[2 * e + 1] = pend[e].imag();
+                    }
+                    rc = run_op(u2);
+                }
             } else {
-                std::vector<std::complex<double>> m;
-                op_target_matrix(c->ops[pending], params, m);
                 PairCoef u;
                 for (int e = 0; e < 4; ++e) {
-                    u.m[2 * e] = m[e].real();
-                    u.m[2 * e + 1] = m[e].imag();
+                    u.m[2 * e] = pend[e].real();
+                    u.m[2 * e + 1] = pend[e].imag();
                 }
                 const uint64_t tb = 1ull << c->ops[pending].q[0];
                 // every term holds the gate's qubit and at most one more bit: a
@@ -1310,10 +1323,22 @@ static sv_status circuit_forward_fused(sv_circuit c, sv_state st, const double* 
             turns.insert(turns.end(), tt.begin(), tt.end());
             continue;
         }
+        if (pair_fusable(o) && pending >= 0 && run_len == 0 && c->ops[pending].q[0] == o.q[0]) {
+            // o after the pending gate on the same qubit: pend <- M(o) pend
+            std::vector<std::complex<double>> m;
+            op_target_matrix(o, params, m);
+            const std::vector<std::complex<double>> a = pend;
+            for (int r = 0; r < 2; ++r)
+                for (int k = 0; k < 2; ++k) pend[2 * r + k] = m[2 * r] * a[k] + m[2 * r + 1] * a[2 + k];
+            ++pend_ops;
+            continue;
+        }
         sv_status rc = flush();
         if (rc) return rc;
         if (pair_fusable(o)) {
             pending = (int)i;
+            op_target_matrix(o, params, pend);
+            pend_ops = 1;
             continue;
         }
         rc = run_op(o);

@@ -119,6 +119,48 @@ def test_fused_circuit_vs_oracle_and_op_by_op(dtype):
         assert float(np.max(np.abs(a.astype(np.complex128) - b.astype(np.complex128)))) <= 10 * TOL[dtype]
 
 
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_fused_same_qubit_products_vs_oracle(dtype):
+    """Runs of 1 to 4 uncontrolled one-target gates (X, Y, H, RX, RY, U2) on
+    one qubit, composed into one 2x2 by the fused path, alone, followed by a
+    diagonal run (the product shares its pass) and between controlled gates,
+    against the oracle and the op-by-op path."""
+    n = 11
+    rng = np.random.default_rng(8250)
+    kinds = ["X", "Y", "H", "RX", "RY", "U2"]
+    for trial in range(4):
+        ops, npar = [], 0
+        for _ in range(40):
+            q = int(rng.integers(0, n))
+            for _ in range(int(rng.integers(1, 5))):
+                g = kinds[int(rng.integers(0, len(kinds)))]
+                if g in ("RX", "RY"):
+                    ops.append(W.Op(g, (), (q,), npar, 0.0))
+                    npar += 1
+                elif g == "U2":
+                    ops.append(W.Op("U2", (), (q,), -1, 0.0, W.haar_unitary(1, rng)))
+                else:
+                    ops.append(W.Op(g, (), (q,)))
+            r = rng.random()
+            other = int((q + 1 + rng.integers(0, n - 1)) % n)
+            if r < 0.4:
+                for _ in range(int(rng.integers(1, 4))):
+                    c = int(rng.integers(0, n))
+                    ops.append(W.Op("PHASE", (c,) if c != q else (), (q,), -1, float(rng.uniform(-3, 3))))
+            elif r < 0.7:
+                ops.append(W.Op("X", (q,), (other,)))
+        th = rng.uniform(0, 2 * math.pi, size=npar)
+        psi0 = _input(n, dtype, 8260 + trial)
+        circ = sv.Circuit(n, ops, npar)
+        a = circ.apply(sv.State(n, dtype, basis=None).load(psi0), th, fuse_diagonal=True).numpy()
+        b = circ.apply(sv.State(n, dtype, basis=None).load(psi0), th).numpy()
+        ref = oracle.run_circuit(psi0.copy(), ops, th)
+        err = float(np.max(np.abs(a.astype(np.complex128) - ref)))
+        print(f"same-qubit products {dtype} trial {trial}: {len(ops)} ops, {err:.2e}", flush=True)
+        assert err <= 10 * TOL[dtype], (trial, err)
+        assert float(np.max(np.abs(a.astype(np.complex128) - b.astype(np.complex128)))) <= 10 * TOL[dtype]
+
+
 @pytest.mark.parametrize("dtype,tol", [("c128", 1e-13), ("c64", 2e-7)])
 def test_fused_qft_closed_form(dtype, tol):
     n = 14
