@@ -171,6 +171,28 @@ def test_tuning_table_validation():
     assert lib.sv_tune_set(0, 2, 2, b.value, u.value, nt.value) == OK
 
 
+def test_lds_staging_depth_reported_per_form():
+    """The LDS-staged class's unroll sets the staging depth of 3-qubit gates
+    only; sv_plan_info reports the depth each launch uses, which names the
+    kernel instantiation the bench attributes time to (host only)."""
+    saved = {t: sv.tune_get(6, "c128", t) for t in range(3)}
+    try:
+        for u in (1, 2, 4):
+            for t in range(3):
+                sv.tune_set(6, "c128", t, 128, u, 1)
+            two = sv.plan_info(30, "c128", "GENERAL", (29, 0))
+            three = sv.plan_info(30, "c128", "GENERAL", (29, 15, 0))
+            swap = sv.plan_info(30, "c128", "SWAP", (29, 0))
+            assert (two["class"], three["class"], swap["class"]) == (6, 6, 6)
+            assert two["unroll"] == 1 and swap["unroll"] == 1 and three["unroll"] == u
+            assert two["kernel"] == "k_lds_gate<double, 2, 0, true, 1>"
+            assert three["kernel"] == f"k_lds_gate<double, 3, 0, true, {u}>"
+            assert swap["kernel"] == "k_lds_gate<double, 2, 1, true, 1>"
+    finally:
+        for t, shp in saved.items():
+            sv.tune_set(6, "c128", t, *shp)
+
+
 def test_status_strings():
     assert lib.sv_status_string(4) == b"SV_ERR_HIP"
     assert lib.sv_version() >= 1
