@@ -1,9 +1,11 @@
 """Pins of the oracle against facts that do not come from the oracle itself.
 
 Each test below would fail on a plausible slip in the oracle: a transposed
-matrix index, a dropped or mis-signed term, a control read as a 0-control, a
-wrong rotation sign or half-angle, a Y with the wrong sign, an expectation
-that forgets the conjugate.  Routes used: Kronecker-product and
+matrix index, a dropped or mis-signed term, a control read as a 0-control or
+ignored, a wrong rotation sign or half-angle, a Y gate or a Pauli Y inside an
+expectation with the wrong sign, an expectation that forgets the conjugate.
+Nothing here takes its reference from the oracle's own gate table: the
+brute-force routes use the Pauli matrices written out in tests/bruteforce.py.  Routes used: Kronecker-product and
 tensor-contraction embeddings (tests/bruteforce.py), closed forms (GHZ, QFT of
 a basis state and of an arbitrary state via numpy.fft), gate identities,
 analytic expectation values and derivatives, and hand-derived fixtures
@@ -18,7 +20,7 @@ import pytest
 
 import oracle
 import workloads as W
-from bruteforce import (PAULI, full_operator_tensordot, kron_controlled_single, kron_factors,
+from bruteforce import (P1, PAULI, full_operator_tensordot, kron_controlled_single, kron_factors,
                         kron_pauli, kron_single, tensordot_apply)
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -77,6 +79,103 @@ def test_toffoli_every_triple_vs_kron():
         ref = kron_controlled_single(n, (a, b), t, X) @ psi
         got = oracle.apply_gate(psi.copy(), "X", (t,), (a, b))
         assert np.array_equal(got, ref), (a, b, t)
+
+
+def test_y_gate_vs_independent_pauli_matrix():
+    # The Y gate against the Pauli Y written out in tests/bruteforce.py (not
+    # the oracle's gate table), uncontrolled and with one or two controls.
+    n = 4
+    psi = rand_state(n, 52)
+    Y = PAULI["Y"]
+    for t in range(n):
+        got = oracle.apply_gate(psi.copy(), "Y", (t,))
+        assert np.max(np.abs(got - kron_single(n, t, Y) @ psi)) < TOL, t
+    for c, t in itertools.permutations(range(n), 2):
+        got = oracle.apply_gate(psi.copy(), "Y", (t,), (c,))
+        assert np.max(np.abs(got - kron_controlled_single(n, (c,), t, Y) @ psi)) < TOL, (c, t)
+    for a, b, t in itertools.permutations(range(n), 3):
+        got = oracle.apply_gate(psi.copy(), "Y", (t,), (a, b))
+        assert np.max(np.abs(got - kron_controlled_single(n, (a, b), t, Y) @ psi)) < TOL, (a, b, t)
+
+
+def test_y_gate_identities_and_basis_action():
+    # Y = i X Z through the oracle's X move and Z; Y^2 = I; RY(pi) = -i Y and
+    # RX(pi) = -i X; Y|0> = i|1>, Y|1> = -i|0> exactly.
+    n = 3
+    psi = rand_state(n, 53)
+    for t in range(n):
+        y = oracle.apply_gate(psi.copy(), "Y", (t,))
+        ixz = 1j * oracle.apply_gate(oracle.apply_gate(psi.copy(), "Z", (t,)), "X", (t,))
+        assert np.max(np.abs(y - ixz)) < TOL
+        yy = oracle.apply_gate(y.copy(), "Y", (t,))
+        assert np.max(np.abs(yy - psi)) < TOL
+        ry = oracle.apply_gate(psi.copy(), "RY", (t,), (), (math.pi,))
+        assert np.max(np.abs(ry - (-1j) * y)) < TOL
+        rx = oracle.apply_gate(psi.copy(), "RX", (t,), (), (math.pi,))
+        assert np.max(np.abs(rx - (-1j) * oracle.apply_gate(psi.copy(), "X", (t,)))) < TOL
+    e0 = oracle.apply_gate(oracle.basis_state(1, 0), "Y", (0,))
+    assert np.array_equal(e0, np.array([0, 1j]))
+    e1 = oracle.apply_gate(oracle.basis_state(1, 1), "Y", (0,))
+    assert np.array_equal(e1, np.array([-1j, 0]))
+
+
+def _swap_operator(n, a, b):
+    """SWAP of qubits a and b as (I + XX + YY + ZZ) / 2, from Kronecker
+    factors of the written-out Pauli matrices (entries are exact 0 and 1)."""
+    terms = [kron_factors(n, {})] + [kron_factors(n, {a: PAULI[p], b: PAULI[p]}) for p in "XYZ"]
+    return sum(terms) / 2
+
+
+def test_swap_operator_route_is_a_permutation():
+    # the route itself: a 0/1 permutation matrix that exchanges the two bits
+    n = 3
+    for a, b in itertools.permutations(range(n), 2):
+        op = _swap_operator(n, a, b)
+        for x in range(1 << n):
+            ba, bb = (x >> a) & 1, (x >> b) & 1
+            y = x & ~((1 << a) | (1 << b)) | (bb << a) | (ba << b)
+            col = np.zeros(1 << n)
+            col[y] = 1
+            assert np.array_equal(op[:, x], col)
+
+
+@pytest.mark.parametrize("dtype", [np.complex128, np.complex64])
+def test_controlled_swap_every_triple_vs_kron(dtype):
+    # Fredkin on every ordered (control, a, b) at n = 4, and with two controls
+    # on every ordered 4-tuple: I - Pi + Pi SWAP_ab, Pi the projector onto
+    # all controls in |1>; bit-exact (the operator has 0/1 entries).
+    n = 4
+    psi = rand_state(n, 54)
+    for c, a, b in itertools.permutations(range(n), 3):
+        pi = kron_factors(n, {c: P1})
+        op = np.eye(1 << n) - pi + pi @ _swap_operator(n, a, b)
+        ref = (op @ psi).astype(dtype)
+        got = oracle.move_swap(psi.astype(dtype), a, b, (c,))
+        assert np.array_equal(got.view(np.uint8), ref.view(np.uint8)), (c, a, b)
+    for c1, c2, a, b in itertools.permutations(range(n), 4):
+        pi = kron_factors(n, {c1: P1, c2: P1})
+        op = np.eye(1 << n) - pi + pi @ _swap_operator(n, a, b)
+        got = oracle.move_swap(psi.copy(), a, b, (c1, c2))
+        assert np.array_equal(got, op @ psi), (c1, c2, a, b)
+
+
+def test_controlled_swap_hand_fixture():
+    # 3 qubits, control 2, swap (1, 0): only |101> <-> |110> trade places
+    # (indices 5 and 6); every other amplitude stays.  With the control at 0
+    # everywhere the move is the identity.
+    psi = np.arange(1, 9, dtype=np.float64) + 1j * np.arange(11, 19, dtype=np.float64)
+    got = oracle.move_swap(psi.copy(), 1, 0, (2,))
+    ref = psi.copy()
+    ref[5], ref[6] = psi[6], psi[5]
+    assert np.array_equal(got, ref)
+    off = psi.copy()
+    off[4:] = 0
+    assert np.array_equal(oracle.move_swap(off.copy(), 1, 0, (2,)), off)
+    # uncontrolled: |01x> <-> |10x> style exchange of bits 1 and 0 everywhere
+    got = oracle.move_swap(psi.copy(), 1, 0)
+    ref = psi.copy()
+    ref[1], ref[2], ref[5], ref[6] = psi[2], psi[1], psi[6], psi[5]
+    assert np.array_equal(got, ref)
 
 
 def test_cnot_textbook_matrix():
@@ -459,6 +558,19 @@ def test_planted_sign_is_caught():
     wrong_rz = oracle.apply_matrix(W.gaussian_state(2, 3), (1,), oracle.gate_matrix("RZ", (-0.8,)))
     good_rz = kron_single(2, 1, np.diag([np.exp(-0.4j), np.exp(0.4j)])) @ W.gaussian_state(2, 3)
     assert np.max(np.abs(wrong_rz - good_rz)) > 1e-2
+
+
+def test_planted_y_sign_and_ignored_control_are_caught():
+    # a Y gate of the wrong sign, and a controlled SWAP that ignores its
+    # control, both differ from the independent routes used by the pins
+    n = 3
+    psi = rand_state(n, 182)
+    wrong_y = oracle.apply_matrix(psi.copy(), (1,), np.ascontiguousarray(-PAULI["Y"]))
+    assert np.max(np.abs(wrong_y - kron_single(n, 1, PAULI["Y"]) @ psi)) > 1e-2
+    ignored = oracle.move_swap(psi.copy(), 1, 0)
+    pi = kron_factors(n, {2: P1})
+    op = np.eye(1 << n) - pi + pi @ _swap_operator(n, 1, 0)
+    assert not np.array_equal(ignored, op @ psi)
 
 
 def test_golden_oracle_regression_hea6():
