@@ -9,28 +9,40 @@ kernel and through the general dense kernel (the paper's two approaches,
 Sec. 3.1), and the step ends with one expectation value (sum_i Z_i Z_{i+1}).
 `value` is gates/s of the gate-specific kernels over the timed steps.
 
-Also reported on the same JSON line:
+The last stdout line is one compact JSON object (the headline): value,
+ms_per_step, roofline, cpu_baseline and one summary figure per section.
+Everything else -- per class, per kernel, per target, every section in full --
+goes to a detail JSON file (--detail, default gpurun_out/bench_detail.json).
+Sections:
   roofline      the dominant kernel's algorithmic bytes per launch over its
                 average HIP-event-timed launch duration, against 8 TB/s;
                 `traffic` is its measured HBM bytes per launch, read from the
                 committed PMC summary (null once the sweep kernels' sources
                 differ from the ones the counters were taken with);
-  copy          a device-to-device copy of the state (the measured ceiling);
-  line_GBps     the same sweep in line-granular bytes (every 128-byte line
-                holding a touched amplitude is read and written whole);
+  ceiling       the library's streaming kernel (sv_stream_bench) copying,
+                reading and writing the state's bytes: the measured ceiling;
+  classes       per gate class, gate-specific and general kernel as fractions
+                of 8 TB/s; the half- and quarter-touch classes (Z, CNOT, SWAP,
+                Toffoli) also over the cases whose lowest touched qubit is at
+                or above the 128-byte line bits, where their algorithmic bytes
+                are also their line-granular bytes;
   sweep_c64     the same sweep on a complex64 state (secondary, one step);
-  cpu_baseline  the oracle on the host cores on a bounded sample (and on one
-                thread, in `single_thread`);
   adjoint       24 qubits, 8 layers RY+RZ + CNOT ladder, 384 params,
                 sum Z_i Z_{i+1}: one adjoint-gradient call vs parameter shift
                 (2 forward+expval runs per parameter) on the same GPU, on the
-                op-by-op kernels;
-  adjoint_fused the same on the fused pass engine (parameter shift as
-                batches of 128 shifted circuits per launch);
+                op-by-op kernels, with the error of each dtype's gradient
+                against the oracle's parameter-shift gradient on 16 sampled
+                parameters (stored reference, tests/golden);
+  adjoint_fused the same on the fused pass engine;
   batch         256 circuits of 14..22 qubits, forward + gradient in one
                 graph launch, vs the same circuits one after another;
-  circuits32    32-qubit HEA (10 layers), QFT and universal circuit on the
-                fused engine.
+  circuits32    32-qubit HEA (10 layers), QFT and universal circuit;
+  circuits20    the 20-qubit HEA and QFT in both dtypes against the oracle's
+                stored results (max-abs amplitude error on 1024 sampled
+                amplitudes, sum Z_i energy error);
+  cpu_baseline  the oracle on the host cores on a bounded sample (and on one
+                thread), with the host's CPU model and memory, and one oracle
+                forward + expectation of the 24-qubit adjoint workload.
 Progress lines go to stderr; stdout carries only the JSON line.
 """
 from __future__ import annotations
@@ -134,9 +146,11 @@ def dense_of(case, oracle_free_matrix):
     return tuple(ct) + tuple(tg), np.ascontiguousarray(u)
 
 
-def run_sweep(sv, torch, state, cases, denses, timed, rec, per_target):
-    """One step.  rec[key] accumulates (seconds, algorithmic bytes, launches,
-    line-granular bytes) per kernel."""
+def run_sweep(sv, torch, state, cases, denses, timed, recs):
+    """One step.  Appends one record per case to `recs` when timed:
+    (name, specific kernel, general kernel, specific s, general s,
+    algorithmic bytes, line-granular bytes, lowest touched qubit, target of a
+    one-qubit gate or None), plus one ("expval", ...) record."""
     stream = torch.cuda.current_stream()
     ev = []
     for i, case in enumerate(cases):
@@ -148,7 +162,7 @@ def run_sweep(sv, torch, state, cases, denses, timed, rec, per_target):
         qs, u = denses[i]
         state.apply_general(qs, u)
         e2.record(stream)
-        ev.append((case, e0, e1, e2, len(qs)))
+        ev.append((case, e0, e1, e2))
     e3 = torch.cuda.Event(enable_timing=True)
     e3.record(stream)
     zz = [(1.0, "ZZ", (q, q + 1)) for q in range(state.n - 1)]
@@ -161,91 +175,103 @@ def run_sweep(sv, torch, state, cases, denses, timed, rec, per_target):
     eb = 16 if state.dtype == "c128" else 8
     S = (1 << state.n) * eb
     lb = 3 if eb == 16 else 4  # qubits spanned by a 128-byte line
-    for case, e0, e1, e2, k in ev:
+    for case, e0, e1, e2 in ev:
         g, tg, ct, p, m = case
-        ts = e0.elapsed_time(e1) * 1e-3
-        tgen = e1.elapsed_time(e2) * 1e-3
-        b = 2 * S * touched_fraction(g, len(ct))
-        bl = 2 * S * line_fraction(g, tg, ct, lb)
         name = g if not ct else ({1: "CNOT", 2: "Toffoli"}[len(ct)] if g == "X" else g)
         qs = tuple(ct) + tuple(tg)
-        for key, t, byt, lbyt in ((("specific", name, kernel_of(sv, g, tg, ct, n=state.n, dtype=state.dtype)), ts, b, bl),
-                                  (("general", name, kernel_of(sv, g, qs, (), True, state.n, state.dtype)), tgen,
-                                   2 * S, 2 * S)):
-            a = rec.setdefault(key, [0.0, 0.0, 0, 0.0])
+        recs.append((name, kernel_of(sv, g, tg, ct, n=state.n, dtype=state.dtype),
+                     kernel_of(sv, g, qs, (), True, state.n, state.dtype), e0.elapsed_time(e1) * 1e-3,
+                     e1.elapsed_time(e2) * 1e-3, 2 * S * touched_fraction(g, len(ct)),
+                     2 * S * line_fraction(g, tg, ct, lb), min(qs), tg[0] if not ct and len(tg) == 1 else None))
+    recs.append(("expval", "k_diag_obs_partial<%s>" % ("double" if eb == 16 else "float"), None,
+                 e3.elapsed_time(e4) * 1e-3, 0.0, S, S, 0, None))
+
+
+def summarize_sweep(recs, n, dtype, ceiling_gbps):
+    """Whole-sweep, per class, per kernel and per target figures from
+    run_sweep's records; GB/s are algorithmic, line_GBps line-granular."""
+    eb = 16 if dtype == "c128" else 8
+    lb = 3 if eb == 16 else 4
+    S = (1 << n) * eb
+    gates = [r for r in recs if r[0] != "expval"]
+    t_spec = sum(r[3] for r in gates)
+    t_gen = sum(r[4] for r in gates)
+    tot = {"gates_per_s": len(gates) / t_spec, "effective_GBps": sum(r[5] for r in gates) / t_spec / 1e9,
+           "line_GBps": sum(r[6] for r in gates) / t_spec / 1e9, "general_gates_per_s": len(gates) / t_gen}
+    tot["effective_frac_of_8TBps"] = tot["effective_GBps"] / PEAK_GBPS
+    tot["line_frac_of_8TBps"] = tot["line_GBps"] / PEAK_GBPS
+    tot["effective_frac_of_ceiling"] = tot["effective_GBps"] / ceiling_gbps if ceiling_gbps else None
+    per_class = {}
+    for name in sorted({r[0] for r in gates}):
+        rs = [r for r in gates if r[0] == name]
+        ts, tg_ = sum(r[3] for r in rs), sum(r[4] for r in rs)
+        bs, ls = sum(r[5] for r in rs), sum(r[6] for r in rs)
+        d = {"specific": {"kernels": sorted({r[1] for r in rs}), "launches": len(rs), "avg_ms": 1e3 * ts / len(rs),
+                          "GBps": bs / ts / 1e9, "frac_of_8TBps": bs / ts / 1e9 / PEAK_GBPS,
+                          "line_GBps": ls / ts / 1e9},
+             "general": {"kernels": sorted({r[2] for r in rs}), "launches": len(rs), "avg_ms": 1e3 * tg_ / len(rs),
+                         "GBps": 2 * S * len(rs) / tg_ / 1e9, "frac_of_8TBps": 2 * S * len(rs) / tg_ / 1e9 / PEAK_GBPS}}
+        d["speedup_specific_vs_general"] = tg_ / ts
+        al = [r for r in rs if r[7] >= lb]
+        if al and name in ("Z", "CNOT", "SWAP", "Toffoli"):
+            ta, ba = sum(r[3] for r in al), sum(r[5] for r in al)
+            d["specific_lowest_qubit_ge_line_bits"] = {"launches": len(al), "avg_ms": 1e3 * ta / len(al),
+                                                        "GBps": ba / ta / 1e9, "frac_of_8TBps": ba / ta / 1e9 / PEAK_GBPS}
+        per_class[name] = d
+    by_kernel = {}
+    for r in recs:
+        for kern, t, byt in ((r[1], r[3], r[5]), (r[2], r[4], 2 * S)):
+            if kern is None:
+                continue
+            a = by_kernel.setdefault(kern, [0.0, 0.0, 0])
             a[0] += t
             a[1] += byt
             a[2] += 1
-            a[3] += lbyt
-        if not ct and len(tg) == 1:
-            pt = per_target.setdefault(g, {})
-            pt.setdefault(tg[0], []).append((ts, tgen))
-    a = rec.setdefault(("expval", "sumZZ", "k_diag_obs_partial<double>"), [0.0, 0.0, 0, 0.0])
-    a[0] += e3.elapsed_time(e4) * 1e-3
-    a[1] += S
-    a[2] += 1
-    a[3] += S
-
-
-def summarize_sweep(rec, copy_gbps):
-    """Per class (specific / general), per kernel and whole-sweep figures from
-    run_sweep's records; GB/s are algorithmic, line_GBps line-granular."""
-    spec = {k: v for k, v in rec.items() if k[0] == "specific"}
-    gen_ = {k: v for k, v in rec.items() if k[0] == "general"}
-    t_spec = sum(v[0] for v in spec.values())
-    t_gen = sum(v[0] for v in gen_.values())
-    tot = {"gates_per_s": sum(v[2] for v in spec.values()) / t_spec,
-           "effective_GBps": sum(v[1] for v in spec.values()) / t_spec / 1e9,
-           "line_GBps": sum(v[3] for v in spec.values()) / t_spec / 1e9,
-           "general_gates_per_s": sum(v[2] for v in gen_.values()) / t_gen}
-    tot["effective_frac_of_8TBps"] = tot["effective_GBps"] / PEAK_GBPS
-    tot["line_frac_of_8TBps"] = tot["line_GBps"] / PEAK_GBPS
-    tot["effective_frac_of_copy"] = tot["effective_GBps"] / copy_gbps
-    per_class = {}
-    agg = {}
-    for (kind, name, kern), (tt, bb, cnt, lb) in rec.items():
-        a = agg.setdefault((name, kind), [0.0, 0.0, 0, set(), 0.0])
-        a[0] += tt
-        a[1] += bb
-        a[2] += cnt
-        a[3].add(kern)
-        a[4] += lb
-    for (name, kind), (tt, bb, cnt, kerns, lb) in sorted(agg.items()):
-        per_class.setdefault(name, {})[kind] = {
-            "kernels": sorted(kerns), "launches": cnt, "avg_ms": 1e3 * tt / cnt, "gates_per_s": cnt / tt,
-            "GBps": bb / tt / 1e9, "frac_of_8TBps": bb / tt / 1e9 / PEAK_GBPS, "frac_of_copy": bb / tt / 1e9 / copy_gbps,
-            "line_GBps": lb / tt / 1e9}
-    for name, d in per_class.items():
-        if "specific" in d and "general" in d:
-            d["speedup_specific_vs_general"] = d["general"]["avg_ms"] / d["specific"]["avg_ms"]
-    by_kernel = {}
-    for (kind, name, kern), (tt, bb, cnt, lb) in rec.items():
-        a = by_kernel.setdefault(kern, [0.0, 0.0, 0])
-        a[0] += tt
-        a[1] += bb
-        a[2] += cnt
     per_kernel = {k: {"launches": c, "avg_ms": 1e3 * t / c, "GBps": by / t / 1e9, "frac_of_8TBps": by / t / 1e9 / PEAK_GBPS,
                       "share_of_step_time": t / (t_spec + t_gen)}
                   for k, (t, by, c) in sorted(by_kernel.items(), key=lambda kv: -kv[1][0])}
-    return tot, per_class, per_kernel, by_kernel
+    per_target = {}
+    for r in gates:
+        if r[8] is not None:
+            per_target.setdefault(r[0], {}).setdefault(r[8], []).append((r[3], r[4]))
+    per_target_ms = {g: {"specific": [round(1e3 * sum(x[0] for x in v[t]) / len(v[t]), 4) for t in sorted(v)],
+                         "general": [round(1e3 * sum(x[1] for x in v[t]) / len(v[t]), 4) for t in sorted(v)]}
+                     for g, v in per_target.items()}
+    return tot, per_class, per_kernel, by_kernel, per_target_ms
 
 
-def measure_copy(sv, torch, state):
-    other = sv.State(state.n, state.dtype, basis=None)
-    other.copy_from(state)
-    torch.cuda.synchronize()
-    ts = []
-    for _ in range(3):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        other.copy_from(state)
-        e1.record()
-        torch.cuda.synchronize()
-        ts.append(e0.elapsed_time(e1) * 1e-3)
+def measure_ceiling(sv, torch, state):
+    """The streaming kernel (sv_stream_bench) over the state's bytes: copy to
+    a second buffer (bytes read + bytes written), read only, write only; best
+    launch shape of a small set, median of 3 runs each."""
+    nbytes = state.tensor.numel() * state.tensor.element_size()
+    other = torch.empty_like(state.tensor)
+    out = {"bytes": nbytes}
+    for mode, label, factor in ((0, "copy", 2), (1, "read", 1), (2, "write", 1)):
+        best = None
+        for block in (256, 512):
+            for unroll in (1, 2, 4, 8):
+                def run():
+                    sv.stream_bench(mode, other if mode != 1 else None, state.tensor if mode != 2 else None, nbytes,
+                                    block, unroll)
+                run()
+                torch.cuda.synchronize()
+                ts = []
+                for _ in range(3):
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record()
+                    run()
+                    e1.record()
+                    e1.synchronize()
+                    ts.append(e0.elapsed_time(e1) * 1e-3)
+                gbps = factor * nbytes / sorted(ts)[1] / 1e9
+                if best is None or gbps > best[0]:
+                    best = (gbps, block, unroll)
+        out[f"{label}_GBps"] = best[0]
+        out[f"{label}_shape"] = [best[1], best[2]]
     del other
     torch.cuda.empty_cache()
-    t = sorted(ts)[1]
-    return 2 * state.tensor.numel() * state.tensor.element_size() / t / 1e9
+    return out
 
 
 # The files the single-gate and reduction kernels are compiled from; the PMC
@@ -284,6 +310,23 @@ def pmc_traffic(kernel, summary=PMC_SUMMARY):
     return None if e is None else e["traffic_bytes"]
 
 
+def host_info():
+    """CPU model, logical CPUs and memory of the host (from /proc)."""
+    model, mem = None, None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+        for line in open("/proc/meminfo"):
+            if line.startswith("MemTotal"):
+                mem = round(int(line.split()[1]) / 2**20, 1)
+                break
+    except OSError:
+        pass
+    return {"cpu_model": model, "logical_cpus": os.cpu_count(), "mem_GiB": mem}
+
+
 def cpu_baseline(qubits_cpu, qubits_gpu, min_seconds=10.0):
     """The oracle on the host cores: X, H, RZ, CNOT, CZ and Toffoli at three
     targets on a Gaussian state, the list repeated until at least
@@ -314,6 +357,93 @@ def cpu_baseline(qubits_cpu, qubits_gpu, min_seconds=10.0):
             "sample": (f"X, H, RZ, CNOT, CZ, Toffoli at t in {ts} on a {qubits_cpu}-qubit complex128 Gaussian state, "
                        f"{gates} gates in {dt:.1f} s; rate scaled by 2^{qubits_cpu - qubits_gpu} to {qubits_gpu} "
                        f"qubits (the oracle's work is linear in the amplitude count)")}
+
+
+def cpu_param_shift_estimate(n, layers):
+    """One oracle forward pass + sum Z_i Z_{i+1} of the adjoint workload; the
+    oracle's parameter-shift gradient would take 2 * params such runs."""
+    import oracle
+    import workloads as W
+    ops = W.hea_ops(n, layers)
+    th = W.uniform_angles(W.hea_n_params(n, layers), 1005)
+    t0 = time.perf_counter()
+    oracle.energy(n, ops, th, W.sum_zz(n))
+    t = time.perf_counter() - t0
+    runs = 2 * W.hea_n_params(n, layers)
+    return {"forward_expval_s": t, "param_shift_runs": runs, "param_shift_s_extrapolated": t * runs,
+            "cores": oracle.num_threads()}
+
+
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+
+
+def golden_adjoint(n):
+    """The oracle's stored gradients of the adjoint workload at n qubits
+    (tests/golden/oracle_adjoint_hea.txt): energy, {j: parameter shift},
+    {j: central difference}."""
+    e, ps, fd = None, {}, {}
+    with open(os.path.join(GOLDEN, "oracle_adjoint_hea.txt")) as f:
+        for line in f:
+            tok = line.split()
+            if not tok or tok[0].startswith("#") or int(tok[1]) != n:
+                continue
+            if tok[0] == "energy":
+                e = float(tok[2])
+            else:
+                (ps if tok[0] == "ps" else fd)[int(tok[2])] = float(tok[3])
+    return e, ps, fd
+
+
+def golden_circuits20():
+    """The oracle's stored 20-qubit HEA and QFT results
+    (tests/golden/oracle_circuits20.txt): {name: (energy, {index: amplitude})}."""
+    out = {}
+    with open(os.path.join(GOLDEN, "oracle_circuits20.txt")) as f:
+        for line in f:
+            tok = line.split()
+            if not tok or tok[0].startswith("#"):
+                continue
+            e, amps = out.setdefault(tok[1], [None, {}])
+            if tok[0] == "energy":
+                out[tok[1]][0] = float(tok[2])
+            else:
+                amps[int(tok[2])] = complex(float(tok[3]), float(tok[4]))
+    return out
+
+
+def circuits20(sv, torch):
+    """The 20-qubit HEA and QFT on the fused engine and on the op-by-op
+    kernels, both dtypes, against the oracle's stored results: the error of
+    every result per dtype (the complex64 precision form)."""
+    import numpy as np
+    import workloads as W
+    n = 20
+    ref = golden_circuits20()
+    x = W.random_basis_index(n, 1004)
+    prep = [W.Op("X", (), (q,)) for q in range(n) if (x >> q) & 1]
+    jobs = {"hea": (W.hea_ops(n, 10), W.uniform_angles(W.hea_n_params(n, 10), 1003)),
+            "qft": (prep + W.qft_ops(n), np.zeros(0))}
+    out = {}
+    for name, (ops, th) in jobs.items():
+        e_ref, amps = ref[name]
+        idx = np.array(sorted(amps))
+        want = np.array([amps[i] for i in idx])
+        for dt in ("c128", "c64"):
+            b = sv.Batch([(n, ops, len(th), "sum_z")], dt, with_grad=False)
+            e = float(b.run(th)[0][0])
+            got = b.state(0)[idx].astype(np.complex128)
+            del b
+            st = sv.State(n, dt, basis=0)
+            sv.Circuit(n, ops, len(th)).apply(st, th)
+            e_op = st.expval(W.sum_z(n))
+            got_op = st.numpy()[idx].astype(np.complex128)
+            del st
+            out[f"{name}_{dt}"] = {"engine_amp_err": float(np.max(np.abs(got - want))),
+                                   "engine_energy_err": abs(e - e_ref),
+                                   "op_by_op_amp_err": float(np.max(np.abs(got_op - want))),
+                                   "op_by_op_energy_err": abs(e_op - e_ref)}
+    torch.cuda.empty_cache()
+    return out
 
 
 def adjoint_compare(sv, torch, n, layers, ps_params, full_ps):
@@ -369,6 +499,16 @@ def adjoint_compare(sv, torch, n, layers, ps_params, full_ps):
     out["param_shift_params_timed"] = len(which)
     out["param_shift_extrapolated"] = len(which) != npar
     ref = res["c128"]
+    e_or, ps_or, fd_or = golden_adjoint(n) if (n, layers) == (24, 8) else (None, {}, {})
+    if ps_or:
+        js = sorted(ps_or)
+        g_or = np.array([ps_or[j] for j in js])
+        g_fd = np.array([fd_or[j] for j in js])
+        for dt in ("c128", "c64"):
+            out[f"max_abs_err_adjoint_{dt}_vs_oracle_ps"] = float(np.max(np.abs(grads[dt][1][js] - g_or)))
+            out[f"max_abs_err_adjoint_{dt}_vs_oracle_fd"] = float(np.max(np.abs(grads[dt][1][js] - g_fd)))
+            out[f"abs_err_energy_{dt}_vs_oracle"] = abs(grads[dt][0] - e_or)
+        out["oracle_params_checked"] = js
     out["max_abs_err_adjoint_c128_vs_ps_c128"] = float(np.max(np.abs(grads["c128"][1][which] - ref)))
     out["max_abs_err_adjoint_c64_vs_ps_c128"] = float(np.max(np.abs(grads["c64"][1][which] - ref)))
     out["max_abs_err_ps_c64_vs_ps_c128"] = float(np.max(np.abs(res["c64"] - ref)))
@@ -620,6 +760,11 @@ def dense_block(sv, torch, W, n, gen, reps=5):
     return out
 
 
+def _r(x, nd=4):
+    """Round for the headline line (None passes through)."""
+    return None if x is None else float(f"{x:.{nd}g}")
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -638,6 +783,8 @@ def main():
     ap.add_argument("--config3-qubits", type=int, default=32)
     ap.add_argument("--no-sequential", action="store_true", help="skip the op-by-op baseline of config 5")
     ap.add_argument("--skip-dense", action="store_true", help="skip the matrix-core dense-block section")
+    ap.add_argument("--detail", default=os.path.join(ROOT, "gpurun_out", "bench_detail.json"),
+                    help="where the full results go (the stdout line is the headline only)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the state-vector path here is built and measured on a single "
@@ -652,7 +799,7 @@ def main():
 
     torch.cuda.set_device(0)
     n = args.qubits
-    log(f"[bench] allocating {n}-qubit complex128 state ({(1 << n) * 16 / 2**30:.1f} GiB)")
+    log(f"[bench] {n}-qubit complex128 state ({(1 << n) * 16 / 2**30:.1f} GiB)")
     gen = torch.Generator(device="cuda")
     gen.manual_seed(1001)
     t = torch.randn(1 << n, dtype=torch.complex128, device="cuda", generator=gen)
@@ -661,105 +808,118 @@ def main():
     rng = np.random.default_rng(1002)
     cases = sweep_cases(n, rng, W)
     denses = [dense_of(c, None) for c in cases]
-    log(f"[bench] {len(cases)} gate cases per step (+ {len(cases)} general-kernel runs + 1 expval)")
-    copy_gbps = measure_copy(sv, torch, state)
-    log(f"[bench] device copy ceiling {copy_gbps:.0f} GB/s")
+    ceiling = measure_ceiling(sv, torch, state)
+    log(f"[bench] {len(cases)} gate cases per step; streaming kernel: copy {ceiling['copy_GBps']:.0f}, "
+        f"read {ceiling['read_GBps']:.0f}, write {ceiling['write_GBps']:.0f} GB/s")
 
-    rec = {}
-    per_target = {}
+    recs = []
     for w in range(args.warmup):
-        run_sweep(sv, torch, state, cases, denses, False, rec, per_target)
-        log(f"[bench] warmup {w + 1}/{args.warmup} done")
+        run_sweep(sv, torch, state, cases, denses, False, recs)
+    log(f"[bench] {args.warmup} warm-up steps done")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
-        run_sweep(sv, torch, state, cases, denses, True, rec, per_target)
-        log(f"[bench] step {k + 1}/{args.steps} done")
+        run_sweep(sv, torch, state, cases, denses, True, recs)
+        if (k + 1) % 5 == 0 or k + 1 == args.steps:
+            log(f"[bench] step {k + 1}/{args.steps} done")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     norm = state.norm2()
 
-    tot, per_class, per_kernel, by_kernel = summarize_sweep(rec, copy_gbps)
+    tot, per_class, per_kernel, by_kernel, per_target_ms = summarize_sweep(recs, n, "c128", ceiling["copy_GBps"])
     # dominant kernel: the instantiation with the largest total time
-    dom = max(by_kernel.items(), key=lambda kv: kv[1][0])
-    dk, (dt_, db, dc) = dom
+    dk, (dt_, db, dc) = max(by_kernel.items(), key=lambda kv: kv[1][0])
     achieved = db / dt_ / 1e9
-    roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_GBPS, "unit": "GB/s", "frac": achieved / PEAK_GBPS,
-            "traffic": pmc_traffic(dk), "kernel": dk, "launches": dc, "avg_launch_ms": 1e3 * dt_ / dc,
-            "algorithmic_bytes_per_launch": db / dc}
-
+    roof = {"bound": "hbm", "achieved": _r(achieved, 5), "peak": PEAK_GBPS, "unit": "GB/s",
+            "frac": _r(achieved / PEAK_GBPS), "traffic": pmc_traffic(dk), "kernel": dk, "launches": dc,
+            "avg_launch_ms": _r(1e3 * dt_ / dc, 5), "algorithmic_bytes_per_launch": db / dc,
+            "frac_of_copy_kernel": _r(achieved / ceiling["copy_GBps"])}
     if roof["traffic"] is not None:
-        roof["traffic_over_algorithmic"] = roof["traffic"] / roof["algorithmic_bytes_per_launch"]
-    out = {
+        roof["traffic_over_algorithmic"] = _r(roof["traffic"] / roof["algorithmic_bytes_per_launch"])
+    detail = {"sweep": {"totals": tot, "per_class": per_class, "per_kernel": per_kernel, "per_target_ms": per_target_ms,
+                        "norm_after": norm, "tuned_entries": sv.TUNED_ENTRIES}, "ceiling": ceiling}
+    head = {
         "metric": METRIC,
-        "value": tot["gates_per_s"],
+        "value": _r(tot["gates_per_s"], 6),
         "unit": "gates/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * wall / args.steps,
+        "ms_per_step": _r(1e3 * wall / args.steps, 6),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"single-gate sweep, {n} qubits complex128 (seeded Gaussian state), gate-specific "
-                               f"and general kernels", "qubits": n, "state_GiB": (1 << n) * 16 / 2**30,
-                   "gate_classes": ["H", "X", "Z", "RZ", "RY", "U2", "CNOT", "SWAP", "U4", "Toffoli"],
-                   "targets": f"0..{n - 1}", "second_qubits": [0, n // 2, n - 1], "cases_per_step": len(cases)},
-        "effective_GBps": tot["effective_GBps"],
-        "effective_frac_of_8TBps": tot["effective_frac_of_8TBps"],
-        "effective_frac_of_copy": tot["effective_frac_of_copy"],
-        "line_GBps": tot["line_GBps"],
-        "line_frac_of_8TBps": tot["line_frac_of_8TBps"],
-        "general_gates_per_s": tot["general_gates_per_s"],
-        "copy_GBps": copy_gbps,
-        "per_class": per_class,
-        "per_kernel": per_kernel,
+                               f"and general kernels", "qubits": n, "cases_per_step": len(cases),
+                   "second_qubits": [0, n // 2, n - 1]},
         "roofline": roof,
-        "per_target_ms": {g: {"specific": [round(1e3 * sum(x[0] for x in v[t]) / len(v[t]), 4) for t in sorted(v)],
-                              "general": [round(1e3 * sum(x[1] for x in v[t]) / len(v[t]), 4) for t in sorted(v)]}
-                          for g, v in per_target.items()},
-        "tuned_entries": sv.TUNED_ENTRIES,
-        "norm_after": norm,
+        "effective_GBps": _r(tot["effective_GBps"]),
+        "effective_frac_of_8TBps": _r(tot["effective_frac_of_8TBps"]),
+        "line_GBps": _r(tot["line_GBps"]),
+        "general_gates_per_s": _r(tot["general_gates_per_s"]),
+        "ceiling_GBps": {k: _r(ceiling[f"{k}_GBps"]) for k in ("copy", "read", "write")},
+        # per class: [gate-specific, general] as fractions of 8 TB/s
+        "classes_frac": {k: [_r(v["specific"]["frac_of_8TBps"], 3), _r(v["general"]["frac_of_8TBps"], 3)]
+                         for k, v in per_class.items()},
+        "partial_touch_lowest_qubit_ge3_frac": {k: _r(v["specific_lowest_qubit_ge_line_bits"]["frac_of_8TBps"], 3)
+                                                for k, v in per_class.items()
+                                                if "specific_lowest_qubit_ge_line_bits" in v},
+        "detail": os.path.relpath(args.detail, ROOT),
     }
     del state, t
     torch.cuda.empty_cache()
     if not args.skip_c64_sweep:
-        log(f"[bench] secondary: the same sweep on a {n}-qubit complex64 state, one step after one warm-up")
+        log(f"[bench] complex64 sweep, {n} qubits, one step after one warm-up")
         t = torch.randn(1 << n, dtype=torch.complex64, device="cuda", generator=gen)
         t /= torch.linalg.vector_norm(t)
         st64 = sv.State(n, "c64", tensor=t, basis=None)
-        rec64, pt64 = {}, {}
-        run_sweep(sv, torch, st64, cases, denses, False, rec64, pt64)
-        run_sweep(sv, torch, st64, cases, denses, True, rec64, pt64)
-        tot64, pc64, _, _ = summarize_sweep(rec64, copy_gbps)
-        out["sweep_c64"] = dict(tot64, state_GiB=(1 << n) * 8 / 2**30,
-                                per_class={k: {kind: {x: v[kind][x] for x in ("avg_ms", "GBps", "frac_of_8TBps", "line_GBps")}
-                                               for kind in v if kind in ("specific", "general")}
-                                           for k, v in pc64.items()})
+        r64 = []
+        run_sweep(sv, torch, st64, cases, denses, False, r64)
+        run_sweep(sv, torch, st64, cases, denses, True, r64)
+        tot64, pc64, pk64, _, pt64 = summarize_sweep(r64, n, "c64", None)
+        detail["sweep_c64"] = {"totals": tot64, "per_class": pc64, "per_kernel": pk64, "per_target_ms": pt64}
+        head["sweep_c64"] = {"gates_per_s": _r(tot64["gates_per_s"]), "frac": _r(tot64["effective_frac_of_8TBps"]),
+                             "classes_frac": {k: _r(v["specific"]["frac_of_8TBps"], 3) for k, v in pc64.items()}}
         del st64, t
         torch.cuda.empty_cache()
-        log("[bench] complex64 sweep done")
     if not args.skip_adjoint:
         log(f"[bench] adjoint vs parameter shift at {args.adjoint_qubits} qubits")
-        out["adjoint"] = adjoint_compare(sv, torch, args.adjoint_qubits, args.adjoint_layers, args.ps_params,
-                                         args.full_param_shift)
-        log("[bench] adjoint comparison done")
+        a = adjoint_compare(sv, torch, args.adjoint_qubits, args.adjoint_layers, args.ps_params, args.full_param_shift)
+        detail["adjoint"] = a
+        head["adjoint"] = {k: _r(a.get(k)) for k in (
+            "adjoint_s_c128", "param_shift_s_c128", "speedup_c128", "adjoint_s_c64", "param_shift_s_c64",
+            "speedup_c64", "max_abs_err_adjoint_c128_vs_oracle_ps", "max_abs_err_adjoint_c64_vs_oracle_ps",
+            "max_abs_err_adjoint_c128_vs_oracle_fd")}
     if not args.skip_fused:
-        log("[bench] config 4 on the fused engine")
-        out["adjoint_fused"] = adjoint_fused(sv, torch, args.adjoint_qubits, args.adjoint_layers, 128)
-        log("[bench] config 5: 256 mixed circuits in one graph launch")
-        out["batch"] = config5(sv, torch, 3, not args.no_sequential)
-        log(f"[bench] config 3: {args.config3_qubits}-qubit HEA and QFT")
-        out["circuits32"] = config3(sv, torch, args.config3_qubits, 10, 3)
-        log("[bench] fused sections done")
+        log("[bench] adjoint workload on the fused engine")
+        a = adjoint_fused(sv, torch, args.adjoint_qubits, args.adjoint_layers, 128)
+        detail["adjoint_fused"] = a
+        head["adjoint_fused"] = {k: _r(a.get(k)) for k in ("adjoint_s_c128", "adjoint_s_c64", "speedup_c128",
+                                                            "speedup_c64")}
+        log("[bench] 256 mixed circuits in one graph launch")
+        bt = config5(sv, torch, 3, not args.no_sequential)
+        detail["batch"] = bt
+        head["batch"] = {dt: {"s": _r(bt[dt]["run_s"]), "speedup_vs_sequential": _r(bt[dt].get("speedup_vs_sequential"))}
+                         for dt in ("c128", "c64")}
+        log(f"[bench] {args.config3_qubits}-qubit circuits")
+        c3 = config3(sv, torch, args.config3_qubits, 10, 3)
+        detail["circuits32"] = c3
+        head["circuits32_s"] = {f"{nm}_{dt}": _r(c3[f"{nm}_{dt}"]["s"]) for nm in ("hea", "qft", "universal")
+                                for dt in ("c128", "c64")}
+        head["circuits32_s"]["qft_fused_diagonal_c128"] = _r(c3["qft_single_gate_kernels_c128"]["fused_diagonal_s"])
+        log("[bench] 20-qubit circuits against the oracle's stored results")
+        c20 = circuits20(sv, torch)
+        detail["circuits20"] = c20
+        head["circuits20_err"] = {k: [_r(v["engine_amp_err"], 2), _r(v["op_by_op_amp_err"], 2)] for k, v in c20.items()}
     if not args.skip_dense:
         log(f"[bench] dense 4- to 6-qubit blocks on the matrix cores at {n} qubits")
-        out["dense_block"] = dense_block(sv, torch, W, n, gen)
+        detail["dense_block"] = dense_block(sv, torch, W, n, gen)
     if not args.skip_cpu_baseline:
         log(f"[bench] oracle CPU baseline at {args.cpu_qubits} qubits")
-        out["cpu_baseline"] = cpu_baseline(args.cpu_qubits, n)
+        cb = cpu_baseline(args.cpu_qubits, n)
+        cb["host"] = host_info()
         # the same oracle on one host thread (separate process: OpenMP's thread
         # count is fixed when the oracle library loads), on a 24-qubit sample
         import subprocess
@@ -767,8 +927,17 @@ def main():
                            cwd=ROOT, env=dict(os.environ, OMP_NUM_THREADS="1"), capture_output=True, text=True)
         if r.returncode == 0:
             one = json.loads(r.stdout.strip().splitlines()[-1])
-            out["cpu_baseline"]["single_thread"] = {"value": one["value"], "cores": one["cores"], "sample": one["sample"]}
-    print(json.dumps(out), flush=True)
+            cb["single_thread_gates_per_s"] = _r(one["value"])
+        if not args.skip_adjoint:
+            cps = cpu_param_shift_estimate(args.adjoint_qubits, args.adjoint_layers)
+            cb["oracle_param_shift_24q_s"] = _r(cps["param_shift_s_extrapolated"])
+            detail["cpu_param_shift"] = cps
+        detail["cpu_baseline"] = cb
+        head["cpu_baseline"] = dict(cb, value=_r(cb["value"]))
+    os.makedirs(os.path.dirname(os.path.abspath(args.detail)), exist_ok=True)
+    with open(args.detail, "w") as f:
+        json.dump(detail, f, indent=1)
+    print(json.dumps(head, separators=(",", ":")), flush=True)
 
 
 if __name__ == "__main__":

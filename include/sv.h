@@ -38,6 +38,11 @@
  *     next synchronising call.
  *   - Calls on one state are not thread-safe with respect to each other;
  *     sv_last_error() is per thread.
+ *   - Handles (sv_state, sv_circuit, sv_batch) are opaque values, not
+ *     addresses.  Each carries its kind and a generation: after sv_free (or
+ *     sv_circuit_free / sv_batch_free) every copy of the handle is rejected
+ *     with SV_ERR_HANDLE, and so is a handle of another kind, even when a
+ *     new object reuses the freed one's memory.
  */
 #ifndef SV_ABI_H_INCLUDED
 #define SV_ABI_H_INCLUDED
@@ -202,8 +207,15 @@ typedef struct {
 sv_status sv_expval_obs(sv_state st, const sv_obs* obs, double* out);
 
 /* Same value written to device memory out_dev (one double); asynchronous on
- * the state's stream. */
+ * the state's stream.  The reduction partials live in a per-state device
+ * workspace, allocated (or grown) on the first call that needs it. */
 sv_status sv_expval_obs_dev(sv_state st, const sv_obs* obs, double* out_dev);
+
+/* <psi|P|psi> of one Pauli string (as sv_expval_pauli) written to device
+ * memory out_dev (one double); asynchronous on the state's stream, so it can
+ * sit between gate launches without a host round trip.
+ * Errors: as sv_expval_pauli, SV_ERR_ARG for a null out_dev. */
+sv_status sv_expval_pauli_dev(sv_state st, const char* paulis, const int* qubits, int n, double* out_dev);
 
 /* ------------------------------------------------------------------------
  * Circuits and adjoint differentiation (a project addition beyond the
@@ -278,6 +290,10 @@ sv_status sv_block_plan(int n_qubits, const sv_op* ops, int n_ops, int k, int64_
 sv_status sv_apply_phases(sv_state st, int n_terms, const uint64_t* masks, const double* angles);
 
 /* Adjoint gradient of E(th) = <psi(th)|O|psi(th)>, psi(th) = U(th)|psi_in>.
+ * The op list comes as a circuit object (sv_circuit_create) rather than as a
+ * raw sv_op array, so that validation and the per-op tables are built once
+ * and reused across calls; outputs are host arrays (the batched form,
+ * sv_batch_run, writes device outputs).
  * On entry psi holds |psi_in> (not modified in the end beyond rounding: the
  * reverse sweep un-applies every gate).  lam is a work state of the same size
  * and dtype (its contents are overwritten).  E goes to *expval_out and
@@ -331,9 +347,18 @@ sv_status sv_batch_create(const sv_batch_circuit* circuits, int n_circuits, sv_d
  * order (sum of n_params doubles), in device memory if params_on_device.
  * expvals: n_circuits doubles; grads: sum of n_params doubles (with_grad
  * only); both in device memory if outputs_on_device.  Synchronous.
+ * Ordering with the caller's stream (sv_batch_set_stream; the null stream
+ * until set): the run starts after the work queued on that stream before the
+ * call (which may still be writing params or clearing the outputs), and work
+ * queued there afterwards sees the outputs.
  * Errors: SV_ERR_ARG, SV_ERR_HIP. */
 sv_status sv_batch_run(sv_batch b, const double* params, int params_on_device, double* expvals, double* grads,
                        int outputs_on_device);
+
+/* The caller's stream that sv_batch_run orders itself against (a hipStream_t;
+ * NULL = the null stream).  The batch's kernels still run on its own stream.
+ * Errors: SV_ERR_HANDLE. */
+sv_status sv_batch_set_stream(sv_batch b, void* stream);
 
 /* Host-only: validate and schedule a batch exactly as sv_batch_create would,
  * without any device work, and report its sv_batch_info figures. */
@@ -358,8 +383,8 @@ sv_status sv_batch_free(sv_batch b);
 
 /* ------------------------------------------------------------------------
  * Launch shapes (written by the autotuner, read by every gate launch).
- * Kernel classes: 0 paired (permutation / butterfly), 1 subset phase,
- * 2 element-wise diagonal, 3 two-target, 4 general, 5 paired with the
+ * Kernel classes: 0 paired (permutation / butterfly / two-phase diagonal),
+ * 1 subset phase, 2 retired (rejected), 3 two-target, 4 general, 5 paired with the
  * partner fetched across the lanes of a wavefront (targets 0..5), 6 staged
  * through LDS in whole contiguous chunks (general / U4 / SWAP whose lowest
  * qubit has runs under 1 KiB).  Tier: bytes spanned by
@@ -405,6 +430,18 @@ sv_status sv_plan_info(int n_qubits, int dtype, int gate, const int* controls, i
 /* ------------------------------------------------------------------------
  * Diagnostics
  * ------------------------------------------------------------------------ */
+
+/* Measured HBM ceiling: a plain streaming kernel over `bytes` of device
+ * memory with 16-byte non-temporal accesses, the yardstick the gate kernels'
+ * bandwidth is compared against.  mode 0 copies src to dst (bytes read and
+ * bytes written), 1 only reads src (a sum that is never stored unless it
+ * hits an impossible value keeps the loads alive), 2 only writes dst (zeros).
+ * block: threads per workgroup (multiple of 64 in [64, 1024]); unroll: 16-byte
+ * vectors per thread per workgroup tile (1, 2, 4 or 8).  bytes must be a
+ * positive multiple of 16 and the used pointers 16-byte aligned.
+ * Asynchronous on `stream` (NULL = the null stream): time it with events.
+ * Errors: SV_ERR_ARG, SV_ERR_HIP. */
+sv_status sv_stream_bench(int mode, void* dst, const void* src, size_t bytes, int block, int unroll, void* stream);
 const char* sv_last_error(void);
 const char* sv_status_string(sv_status s);
 int sv_version(void);

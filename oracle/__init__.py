@@ -45,7 +45,7 @@ _lib = None
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc (fp64, no fast-math, no FP contraction)."""
     if force or not os.path.exists(LIB_PATH):
-        cmd = ["gcc", "-O2", "-std=c99", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
+        cmd = ["gcc", "-O3", "-std=c99", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
                "-fPIC", "-shared", "-Wall", "-Wextra", "-o", LIB_PATH + ".tmp", _SRC]
         subprocess.run(cmd, check=True)
         os.replace(LIB_PATH + ".tmp", LIB_PATH)

@@ -24,7 +24,7 @@ from ._lib import (GATES, OP_MAX_QUBITS, SV_C64, SV_C128, SvBatchCircuit, SvBatc
                    check, lib)
 
 __all__ = ["State", "Circuit", "Batch", "Observable", "AdjointExpval", "SvError", "lib", "tune_set", "tune_get",
-           "plan_info", "batch_plan", "sv_version"]
+           "plan_info", "batch_plan", "sv_version", "stream_bench"]
 
 _TORCH_DT = {"c128": torch.complex128, "c64": torch.complex64}
 _SV_DT = {"c128": SV_C128, "c64": SV_C64}
@@ -74,8 +74,16 @@ def tune_engine_get(dtype: str, with_grad: bool) -> Tuple[int, int]:
     return t.value, a.value
 
 
-KERNEL_CLASSES = {0: "k_pair", 1: "k_one", 2: "k_diag", 3: "k_quad", 4: "k_general", 5: "k_wpair",
-                  6: "k_lds_gate"}
+KERNEL_CLASSES = {0: "k_pair", 1: "k_one", 3: "k_quad", 4: "k_general", 5: "k_wpair", 6: "k_lds_gate"}
+
+
+def stream_bench(mode: int, dst: Optional[torch.Tensor], src: Optional[torch.Tensor], nbytes: int, block: int = 256,
+                 unroll: int = 4) -> None:
+    """Queue the HBM-ceiling kernel on torch's current stream (sv_stream_bench):
+    mode 0 copies src to dst, 1 reads src, 2 writes dst."""
+    check(lib.sv_stream_bench(int(mode), ctypes.c_void_p(dst.data_ptr() if dst is not None else 0),
+                              ctypes.c_void_p(src.data_ptr() if src is not None else 0), int(nbytes), int(block),
+                              int(unroll), ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
 
 
 def plan_info(n: int, dtype: str, gate: str, targets: Sequence[int], controls: Sequence[int] = ()) -> dict:
@@ -87,7 +95,7 @@ def plan_info(n: int, dtype: str, gate: str, targets: Sequence[int], controls: S
                            *[ctypes.byref(o) for o in out]))
     kc, tier, op, block, unroll, nt = (o.value for o in out)
     T = "double" if dtype == "c128" else "float"
-    if kc == 2 or kc == 3:
+    if kc == 3:
         name = f"{KERNEL_CLASSES[kc]}<{T}, {unroll}, {'true' if nt else 'false'}>"
     elif kc == 6:
         name = f"k_lds_gate<{T}, {op >> 4}, {op & 15}, {'true' if nt else 'false'}, {unroll}>"
@@ -221,6 +229,12 @@ class State:
     def expval_dev(self, obs, out: torch.Tensor) -> None:
         obs = obs if isinstance(obs, Observable) else Observable(obs)
         check(lib.sv_expval_obs_dev(self.handle, ctypes.byref(obs.c), ctypes.c_void_p(out.data_ptr())))
+
+    def expval_pauli_dev(self, paulis: str, qubits: Sequence[int], out: torch.Tensor) -> None:
+        """<psi|P|psi> of one Pauli string into out[0] (a float64 CUDA tensor),
+        queued on the state's stream (sv_expval_pauli_dev)."""
+        check(lib.sv_expval_pauli_dev(self.handle, paulis.encode(), _ints(qubits), len(qubits),
+                                      ctypes.c_void_p(out.data_ptr())))
 
 
 def _sv_op(op) -> Tuple[SvOp, Optional[np.ndarray]]:
@@ -372,7 +386,10 @@ class Batch:
         return e, (g[: sum(self.n_params)] if self.with_grad else None)
 
     def run_device(self, params: torch.Tensor, expvals: torch.Tensor, grads: torch.Tensor) -> None:
-        """Device-resident parameters and outputs (float64 CUDA tensors)."""
+        """Device-resident parameters and outputs (float64 CUDA tensors).  The
+        run is ordered after the work queued on torch's current stream, and
+        work queued there afterwards sees the outputs (sv_batch_set_stream)."""
+        check(lib.sv_batch_set_stream(self.handle, ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
         check(lib.sv_batch_run(self.handle, ctypes.c_void_p(params.data_ptr()), 1,
                                ctypes.c_void_p(expvals.data_ptr()), ctypes.c_void_p(grads.data_ptr()), 1))
 

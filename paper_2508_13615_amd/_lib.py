@@ -26,12 +26,12 @@ EXPORTS = [
     "sv_alloc", "sv_wrap", "sv_free", "sv_set_stream", "sv_get_info", "sv_state_bytes", "sv_set_basis",
     "sv_copy_to_host", "sv_copy_from_host", "sv_copy_state", "sv_synchronize", "sv_apply_gate",
     "sv_apply_controlled", "sv_apply_general", "sv_apply_dense", "sv_apply_phases", "sv_norm2", "sv_expval_pauli",
-    "sv_expval_obs", "sv_expval_obs_dev", "sv_circuit_create", "sv_circuit_free", "sv_circuit_apply",
+    "sv_expval_obs", "sv_expval_obs_dev", "sv_expval_pauli_dev", "sv_circuit_create", "sv_circuit_free", "sv_circuit_apply",
     "sv_circuit_apply_fused", "sv_circuit_apply_blocks", "sv_block_plan", "sv_adjoint_grad",
     "sv_batch_create", "sv_batch_plan", "sv_batch_run", "sv_batch_info", "sv_batch_state", "sv_batch_copy_state",
-    "sv_batch_free",
+    "sv_batch_free", "sv_batch_set_stream",
     "sv_tune_set", "sv_tune_get", "sv_tune_engine_set", "sv_tune_engine_get", "sv_plan_info", "sv_last_error",
-    "sv_status_string", "sv_version",
+    "sv_status_string", "sv_version", "sv_stream_bench",
 ]
 
 
@@ -89,6 +89,7 @@ def _load():
         "sv_expval_pauli": [vp, ctypes.c_char_p, ip, i, dp],
         "sv_expval_obs": [vp, ctypes.POINTER(SvObs), dp],
         "sv_expval_obs_dev": [vp, ctypes.POINTER(SvObs), vp],
+        "sv_expval_pauli_dev": [vp, ctypes.c_char_p, ip, i, vp],
         "sv_circuit_create": [i, ctypes.POINTER(SvOp), i, i, ctypes.POINTER(vp)],
         "sv_circuit_free": [vp],
         "sv_circuit_apply": [vp, vp, dp],
@@ -101,6 +102,7 @@ def _load():
         "sv_batch_plan": [ctypes.POINTER(SvBatchCircuit), i, i, ctypes.POINTER(SvBatchOpts),
                           ctypes.POINTER(ctypes.c_int64)],
         "sv_batch_run": [vp, vp, i, vp, vp, i],
+        "sv_batch_set_stream": [vp, vp],
         "sv_batch_info": [vp, ctypes.POINTER(ctypes.c_int64)],
         "sv_batch_state": [vp, i, ctypes.POINTER(vp), ip],
         "sv_batch_copy_state": [vp, i, vp, ctypes.c_size_t],
@@ -109,6 +111,7 @@ def _load():
         "sv_tune_engine_set": [i, i, i, i],
         "sv_tune_engine_get": [i, i, ip, ip],
         "sv_plan_info": [i, i, i, ip, i, ip, i, ip, ip, ip, ip, ip, ip],
+        "sv_stream_bench": [i, vp, vp, ctypes.c_size_t, i, i, vp],
     }
     for name, args in sig.items():
         if hasattr(lib, name):

@@ -1,7 +1,7 @@
 """Autotuner for libsv's launch shapes.
 
-For every kernel class (paired, subset phase, element-wise diagonal,
-two-target, general), both dtypes and the three run-length tiers (bytes
+For every kernel class (paired, subset phase, two-target, general,
+wavefront-paired, LDS-staged), both dtypes and the three run-length tiers (bytes
 spanned by a run of consecutive touched amplitudes: < 64 B, < 1 KiB, larger),
 it times representative gates under each candidate shape
 (block x groups-per-thread x non-temporal flag) with HIP events and keeps the
@@ -26,7 +26,7 @@ import sys
 import time
 
 TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_mi355x.json")
-CLASSES = {0: "paired", 1: "subset", 2: "diagonal", 3: "two-target", 4: "general", 5: "wave", 6: "lds"}
+CLASSES = {0: "paired", 1: "subset", 3: "two-target", 4: "general", 5: "wave", 6: "lds"}
 BLOCKS = (64, 128, 256, 512)
 UNROLLS = (1, 2, 4)
 
@@ -52,8 +52,6 @@ def _candidates(kc: int, n: int, rng, np):
             yield low, ("SWAP", (low, hi), (), (), None)
         elif kc == 1:
             yield low, ("Z", (low,), (), (), None)
-        elif kc == 2:
-            yield low, ("RZ", (hi,), (low,), (0.3,), None)
         elif kc == 3:
             z = rng.standard_normal((4, 4)) + 1j * rng.standard_normal((4, 4))
             yield low, ("U4", (hi, low), (), (), np.linalg.qr(z)[0])

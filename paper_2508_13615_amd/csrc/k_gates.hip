@@ -4,11 +4,11 @@
 // elements of its logic matrix, and a control only selects where it acts.
 // The kernels below are the GPU form of that rule, one per gate class:
 //   k_pair    two members per group (base + o0, base + o1): permutations
-//             (X, CNOT, Toffoli, SWAP: pure moves) and butterflies (H, RX,
-//             RY, Y, U2 and their controlled forms);
+//             (X, CNOT, Toffoli, SWAP: pure moves), butterflies (H, RX,
+//             RY, Y, U2 and their controlled forms) and the two-phase
+//             diagonal RZ, which touches every amplitude of its subspace;
 //   k_one     one member per group: phase on the |1..1> subspace of the
 //             gate's qubits (Z, S, T, PHASE, CZ, controlled phase);
-//   k_diag    element-wise diagonal over the control subspace (RZ);
 //   k_quad    four members per group (U4 on two targets);
 //   k_general the dense 2^K x 2^K product with no structure used (the
 //             "general approach" of Sec. 3.1, the baseline).
@@ -64,6 +64,9 @@ __device__ __forceinline__ void pair_apply(const V a0, const V a1, const Coef2<T
         r0.y = c.m[0] * a0.y + c.m[2] * a1.y;
         r1.x = c.m[4] * a0.x + c.m[6] * a1.x;
         r1.y = c.m[4] * a0.y + c.m[6] * a1.y;
+    } else if constexpr (OP == PAIR_DIAG) {
+        r0 = cmul<V, T>(c.m[0], c.m[1], a0);
+        r1 = cmul<V, T>(c.m[6], c.m[7], a1);
     } else if constexpr (OP == PAIR_RX) {
         const T cc = c.m[0], s = -c.m[3];  // m01 = -i s
         r0.x = cc * a0.x + s * a1.y;
@@ -143,15 +146,21 @@ k_wpair(typename Vec2<T>::type* __restrict__ psi, GroupSpec gs, int t, Coef2<T> 
         }
 #pragma unroll
         for (int j = 0; j < U; ++j) {
-            V p;
-            p.x = __shfl_xor(a[j].x, lm, 64);
-            p.y = __shfl_xor(a[j].y, lm, 64);
             const uint64_t g = g0 + (uint64_t)j * blockDim.x;
-            if (g < gs.n_groups) {
-                const bool hi = (x[j] >> t) & 1ull;
+            const bool hi = (x[j] >> t) & 1ull;
+            V r;
+            if constexpr (OP == PAIR_DIAG) {
+                // a diagonal needs no partner: the lane's own phase by its bit t
+                r = hi ? cmul<V, T>(c.m[6], c.m[7], a[j]) : cmul<V, T>(c.m[0], c.m[1], a[j]);
+            } else {
+                V p;
+                p.x = __shfl_xor(a[j].x, lm, 64);
+                p.y = __shfl_xor(a[j].y, lm, 64);
                 V r0, r1;
                 pair_apply<OP, T, V>(hi ? p : a[j], hi ? a[j] : p, c, r0, r1);
-                V r = hi ? r1 : r0;
+                r = hi ? r1 : r0;
+            }
+            if (g < gs.n_groups) {
                 if ((x[j] & gs.pmask) != gs.pmask) r = a[j];
                 stg<NT>(psi + x[j], r);
             }
@@ -195,44 +204,6 @@ k_one(typename Vec2<T>::type* __restrict__ psi, GroupSpec gs, T zr, T zi)
                 }
                 if ((b[j] & gs.pmask) != gs.pmask) r = a[j];
                 stg<NT>(psi + b[j], r);
-            }
-        }
-    }
-}
-
-template <typename T, int U, bool NT>
-__global__ void __launch_bounds__(1024)
-k_diag(typename Vec2<T>::type* __restrict__ psi, GroupSpec gs, DiagSpec<T> d)
-{
-    using V = typename Vec2<T>::type;
-    const uint64_t per_block = (uint64_t)blockDim.x * U;
-    const uint64_t stride = (uint64_t)gridDim.x * per_block;
-    const int ne = 1 << d.k;
-    for (uint64_t g0 = (uint64_t)blockIdx.x * per_block + threadIdx.x; g0 < gs.n_groups + threadIdx.x;
-         g0 += stride) {
-        uint64_t b[U];
-        V a[U];
-#pragma unroll
-        for (int j = 0; j < U; ++j) {
-            const uint64_t g = g0 + (uint64_t)j * blockDim.x;
-            if (g < gs.n_groups) {
-                b[j] = group_base(g, gs);
-                a[j] = ldg<NT>(psi + b[j]);
-            }
-        }
-#pragma unroll
-        for (int j = 0; j < U; ++j) {
-            const uint64_t g = g0 + (uint64_t)j * blockDim.x;
-            if (g < gs.n_groups) {
-                int e = 0;
-                for (int q = 0; q < d.k; ++q) e = (e << 1) | (int)((b[j] >> d.tq[q]) & 1ull);
-                T zr = d.d[0], zi = d.d[1];
-                for (int i = 1; i < ne; ++i) {
-                    zr = (e == i) ? d.d[2 * i] : zr;
-                    zi = (e == i) ? d.d[2 * i + 1] : zi;
-                }
-                const bool act = (b[j] & gs.pmask) == gs.pmask;
-                stg<NT>(psi + b[j], act ? cmul<V, T>(zr, zi, a[j]) : a[j]);
             }
         }
     }
@@ -514,6 +485,7 @@ hipError_t launch_pair(void* psi, const GroupSpec& gs, uint64_t o0, uint64_t o1,
         case PAIR_Y: hipLaunchKernelGGL((k_pair<T, PAIR_Y, UU, NTT>), grid, blk, 0, s, p, gs, o0, o1, c); break;
         case PAIR_REAL: hipLaunchKernelGGL((k_pair<T, PAIR_REAL, UU, NTT>), grid, blk, 0, s, p, gs, o0, o1, c); break;
         case PAIR_RX: hipLaunchKernelGGL((k_pair<T, PAIR_RX, UU, NTT>), grid, blk, 0, s, p, gs, o0, o1, c); break;
+        case PAIR_DIAG: hipLaunchKernelGGL((k_pair<T, PAIR_DIAG, UU, NTT>), grid, blk, 0, s, p, gs, o0, o1, c); break;
         default: hipLaunchKernelGGL((k_pair<T, PAIR_DENSE, UU, NTT>), grid, blk, 0, s, p, gs, o0, o1, c); break;
         }
     });
@@ -536,6 +508,7 @@ hipError_t launch_wpair(void* psi, const GroupSpec& gs, int t, int op, const Coe
         case PAIR_Y: hipLaunchKernelGGL((k_wpair<T, PAIR_Y, UU, NTT>), grid, blk, 0, s, p, gs, t, c); break;
         case PAIR_REAL: hipLaunchKernelGGL((k_wpair<T, PAIR_REAL, UU, NTT>), grid, blk, 0, s, p, gs, t, c); break;
         case PAIR_RX: hipLaunchKernelGGL((k_wpair<T, PAIR_RX, UU, NTT>), grid, blk, 0, s, p, gs, t, c); break;
+        case PAIR_DIAG: hipLaunchKernelGGL((k_wpair<T, PAIR_DIAG, UU, NTT>), grid, blk, 0, s, p, gs, t, c); break;
         default: hipLaunchKernelGGL((k_wpair<T, PAIR_DENSE, UU, NTT>), grid, blk, 0, s, p, gs, t, c); break;
         }
     });
@@ -556,18 +529,6 @@ hipError_t launch_one(void* psi, const GroupSpec& gs, int op, T zr, T zi, hipStr
         case ONE_MULI: hipLaunchKernelGGL((k_one<T, ONE_MULI, UU, NTT>), grid, blk, 0, s, p, gs, zr, zi); break;
         default: hipLaunchKernelGGL((k_one<T, ONE_MUL, UU, NTT>), grid, blk, 0, s, p, gs, zr, zi); break;
         }
-    });
-    return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_diag(void* psi, const GroupSpec& gs, const DiagSpec<T>& d, hipStream_t s, Launch lc)
-{
-    using V = typename Vec2<T>::type;
-    if (gs.n_groups == 0) return hipSuccess;
-    V* p = (V*)psi;
-    SV_SHAPE_SWITCH(lc, {
-        hipLaunchKernelGGL((k_diag<T, UU, NTT>), grid_for(gs.n_groups, lc.block, UU), dim3(lc.block), 0, s, p, gs, d);
     });
     return hipGetLastError();
 }
@@ -693,7 +654,6 @@ hipError_t launch_set_basis(void* psi, uint64_t n_amps, uint64_t index, hipStrea
     template hipError_t launch_one<T>(void*, const GroupSpec&, int, T, T, hipStream_t, Launch);             \
     template hipError_t launch_wpair<T>(void*, const GroupSpec&, int, int, const Coef2<T>&, hipStream_t,      \
                                         Launch);                                                            \
-    template hipError_t launch_diag<T>(void*, const GroupSpec&, const DiagSpec<T>&, hipStream_t, Launch);   \
     template hipError_t launch_quad<T>(void*, const GroupSpec&, const uint64_t[4], const Coef4<T>&,         \
                                        hipStream_t, Launch);                                                \
     template hipError_t launch_general<T>(void*, const GroupSpec&, int, const uint64_t*, const T*,          \

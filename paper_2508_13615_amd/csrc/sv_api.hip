@@ -7,9 +7,13 @@
 //   permutation  X / CNOT / Toffoli / SWAP (any controls)  -> k_pair (moves)
 //   subset phase Z, S, T, PHASE and their controlled forms -> k_one on the
 //                |1..1> subspace of controls + target
-//   diagonal     RZ (any controls)                          -> k_diag
+//   diagonal     RZ (any controls)                          -> k_pair, one
+//                phase per member (no partner exchange)
 //   butterfly    H, RY (real), RX, Y, U2 (any controls)     -> k_pair
 //   two-target   U4 (any controls)                          -> k_quad
+// (targets below bit 6 take the wavefront form k_wpair of the paired
+// kernel; gates with a qubit whose runs span under 1 KiB take the
+// LDS-staged k_lds_gate where that keeps accesses on whole lines.)
 // A control never adds work: it is a fixed 1-bit inserted into the group
 // index, so the kernel visits only the controlled subspace.
 #include <math.h>
@@ -82,32 +86,79 @@ struct sv_circuit_s {
     size_t misc_doubles;
 };
 
-static std::mutex g_mu;
-static std::unordered_set<const void*> g_live;
+// Handles are not addresses.  A handle packs a slot of the table below, the
+// kind of object (state, circuit, batch) and the slot's generation, which
+// advances when the object is freed: a handle kept after its free, or a
+// handle of another kind, is rejected even when the allocator has since
+// handed the freed object's address to a new one.
+namespace {
+struct HandleSlot {
+    void* obj;
+    uint32_t gen;
+    int kind;
+};
+std::mutex g_mu;
+std::vector<HandleSlot> g_slots;
+std::vector<uint32_t> g_free_slots;
+constexpr int kKindBits = 4;
 
-void svk::handle_register(const void* h)
+uint64_t handle_encode(uint32_t slot, uint32_t gen, int kind)
 {
-    std::lock_guard<std::mutex> lk(g_mu);
-    g_live.insert(h);
+    return ((uint64_t)gen << 32) | ((uint64_t)(slot + 1) << kKindBits) | (uint64_t)kind;
 }
-bool svk::handle_live(const void* h)
-{
-    std::lock_guard<std::mutex> lk(g_mu);
-    return h && g_live.count(h);
-}
-void svk::handle_unregister(const void* h)
-{
-    std::lock_guard<std::mutex> lk(g_mu);
-    g_live.erase(h);
-}
-static void reg(const void* h) { handle_register(h); }
-static bool live(const void* h) { return handle_live(h); }
-static void unreg(const void* h) { handle_unregister(h); }
 
-#define SV_CHECK_STATE(st)                                                  \
-    do {                                                                    \
-        if (!live(st)) return set_error(SV_ERR_HANDLE, "invalid state handle"); \
-    } while (0)
+HandleSlot* handle_slot(const void* h, int kind)
+{
+    const uint64_t v = (uint64_t)(uintptr_t)h;
+    const uint64_t slot1 = (v & 0xffffffffull) >> kKindBits;
+    if (!v || (int)(v & ((1u << kKindBits) - 1u)) != kind || slot1 == 0 || slot1 > g_slots.size()) return nullptr;
+    HandleSlot& e = g_slots[slot1 - 1];
+    if (!e.obj || e.kind != kind || e.gen != (uint32_t)(v >> 32)) return nullptr;
+    return &e;
+}
+}  // namespace
+
+void* svk::handle_put(void* obj, int kind)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    uint32_t slot;
+    if (!g_free_slots.empty()) {
+        slot = g_free_slots.back();
+        g_free_slots.pop_back();
+    } else {
+        slot = (uint32_t)g_slots.size();
+        g_slots.push_back(HandleSlot{nullptr, 0, 0});
+    }
+    HandleSlot& e = g_slots[slot];
+    e.obj = obj;
+    e.kind = kind;
+    if (++e.gen == 0) e.gen = 1;  // generation 0 is never handed out
+    return (void*)(uintptr_t)handle_encode(slot, e.gen, kind);
+}
+
+void* svk::handle_get(const void* h, int kind)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    HandleSlot* e = handle_slot(h, kind);
+    return e ? e->obj : nullptr;
+}
+
+void* svk::handle_drop(const void* h, int kind)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    HandleSlot* e = handle_slot(h, kind);
+    if (!e) return nullptr;
+    void* obj = e->obj;
+    e->obj = nullptr;
+    ++e->gen;  // every copy of the old handle is now stale
+    g_free_slots.push_back((uint32_t)(e - g_slots.data()));
+    return obj;
+}
+
+// Entry points take handles named <x>_h and resolve them to `x` here.
+#define SV_STATE(st)                                                                   \
+    sv_state_s* const st = (sv_state_s*)handle_get(st##_h, HK_STATE);                   \
+    if (!st) return set_error(SV_ERR_HANDLE, "invalid state handle")
 
 static sv_status hip_status(hipError_t e, const char* where)
 {
@@ -122,8 +173,10 @@ static size_t elem_bytes(int dtype) { return dtype == SV_C128 ? 16 : 8; }
 // ---------------------------------------------------------------------------
 // launch-shape table (filled by defaults, overridable by the autotuner)
 // ---------------------------------------------------------------------------
+// Class 2 (an element-wise diagonal kernel) is retired: RZ runs as a paired
+// update with one phase per member.  Its number stays reserved.
 enum KClass {
-    KC_PAIR = 0, KC_ONE = 1, KC_DIAG = 2, KC_QUAD = 3, KC_GENERAL = 4, KC_WAVE = 5, KC_LDS = 6, KC_COUNT = 7
+    KC_PAIR = 0, KC_ONE = 1, KC_RETIRED = 2, KC_QUAD = 3, KC_GENERAL = 4, KC_WAVE = 5, KC_LDS = 6, KC_COUNT = 7
 };
 // Tier of a launch: bytes spanned by one run of consecutive touched
 // amplitudes, 2^(lowest touched qubit) * element size: < 64 B, < 1 KiB, larger.
@@ -141,9 +194,9 @@ static void tune_defaults()
     for (int c = 0; c < KC_COUNT; ++c)
         for (int d = 0; d < 2; ++d) {
             const bool c128 = d == 1;
-            const bool one_amp = c == KC_ONE || c == KC_DIAG || c == KC_WAVE;
+            const bool one_amp = c == KC_ONE || c == KC_WAVE;
             const int u = one_amp ? (c128 ? 2 : 4) : ((c == KC_PAIR && !c128) ? 2 : 1);
-            const int nt0 = c == KC_WAVE || c == KC_ONE || c == KC_DIAG ? 1 : 0;
+            const int nt0 = c == KC_WAVE || c == KC_ONE ? 1 : 0;
             g_tune[c][d][0] = Launch{128, u, nt0};
             g_tune[c][d][1] = Launch{128, u, 1};
             g_tune[c][d][2] = Launch{64, u, 1};
@@ -200,7 +253,7 @@ static bool gate_has_param(int gate)
 // ---------------------------------------------------------------------------
 // plans: a gate classified into a kernel class with its index spec
 // ---------------------------------------------------------------------------
-enum PlanKind { PK_NOP = 0, PK_PAIR, PK_ONE, PK_DIAG, PK_QUAD, PK_WPAIR, PK_LDS };
+enum PlanKind { PK_NOP = 0, PK_PAIR, PK_ONE, PK_QUAD, PK_WPAIR, PK_LDS };
 
 struct Plan {
     int kind;
@@ -211,8 +264,6 @@ struct Plan {
     int op;
     int wt;  // target of the wavefront form
     double m[128];
-    int dk;
-    int dtq[3];
     LdsSpec ls;  // PK_LDS
     int lk;      // PK_LDS: gate qubits
 };
@@ -355,6 +406,7 @@ static sv_status build_plan(int n, int dtype, int gate, const int* ctrl, int nc,
     case SV_H:
     case SV_RX:
     case SV_RY:
+    case SV_RZ:
     case SV_U2: {
         if (gate == SV_X) {
             pl->op = PAIR_SWAP;
@@ -374,6 +426,13 @@ static sv_status build_plan(int n, int dtype, int gate, const int* ctrl, int nc,
             const double c = cos(params[0] / 2), s = sgn * sin(params[0] / 2);
             pl->op = PAIR_RX;
             double m[8] = {c, 0, 0, -s, 0, -s, c, 0};
+            memcpy(pl->m, m, sizeof m);
+        } else if (gate == SV_RZ) {
+            // diag(e^{-i th/2}, e^{i th/2}): every amplitude of the control
+            // subspace changes, each by the phase of its own target bit
+            const double c = cos(params[0] / 2), s = sgn * sin(params[0] / 2);
+            pl->op = PAIR_DIAG;
+            double m[8] = {c, -s, 0, 0, 0, 0, c, s};
             memcpy(pl->m, m, sizeof m);
         } else {
             pl->op = PAIR_DENSE;
@@ -402,7 +461,13 @@ static sv_status build_plan(int n, int dtype, int gate, const int* ctrl, int nc,
         return SV_OK;
     }
     case SV_SWAP: {
-        if (lds_eligible(n, dtype, tgt, 2)) {
+        // Half of the amplitudes move.  With both qubits at or above the
+        // 128-byte line bits a line holds only moving or only staying
+        // amplitudes, so the paired kernel touches just the moving lines; a
+        // lower qubit shares every line between the two kinds, and then the
+        // LDS-staged form, which streams whole lines, is the cheaper one.
+        const bool line_aligned = (elem_bytes(dtype) << std::min(tgt[0], tgt[1])) >= kPredBytes;
+        if (!line_aligned && lds_eligible(n, dtype, tgt, 2)) {
             build_lds(n, tgt, 2, ctrl, nc, pl);
             pl->op = 1;
             return SV_OK;
@@ -443,22 +508,6 @@ static sv_status build_plan(int n, int dtype, int gate, const int* ctrl, int nc,
             pl->m[0] = cos(ph);
             pl->m[1] = sgn * sin(ph);
         }
-        return SV_OK;
-    }
-    case SV_RZ: {
-        // element-wise over the control subspace
-        split_bits(ctrl, nc, dtype, 0, &bs);
-        pl->kind = PK_DIAG;
-        pl->kc = KC_DIAG;
-        pl->gs = make_groups(n, bs.ins, bs.nins, bs.set_mask, bs.pmask);
-        pl->low = bs.low;
-        pl->dk = 1;
-        pl->dtq[0] = t;
-        const double c = cos(params[0] / 2), s = sgn * sin(params[0] / 2);
-        pl->m[0] = c;
-        pl->m[1] = -s;
-        pl->m[2] = c;
-        pl->m[3] = s;
         return SV_OK;
     }
     case SV_U4: {
@@ -520,13 +569,6 @@ static hipError_t run_plan_t(const Plan& pl, void* psi, hipStream_t s, int dtype
         return launch_lds_gate<T>(psi, pl.gs, pl.ls, pl.op, m, s, lc);
     }
     case PK_ONE: return launch_one<T>(psi, pl.gs, pl.op, (T)pl.m[0], (T)pl.m[1], s, lc);
-    case PK_DIAG: {
-        DiagSpec<T> d{};
-        d.k = pl.dk;
-        for (int i = 0; i < pl.dk; ++i) d.tq[i] = pl.dtq[i];
-        for (int i = 0; i < 2 * (1 << pl.dk); ++i) d.d[i] = (T)pl.m[i];
-        return launch_diag<T>(psi, pl.gs, d, s, lc);
-    }
     case PK_QUAD: {
         Coef4<T> c;
         for (int i = 0; i < 32; ++i) c.m[i] = (T)pl.m[i];
@@ -592,8 +634,7 @@ static sv_status make_state(void* ptr, bool owned, int n, sv_dtype dtype, void* 
     st->dense_dev = nullptr;
     st->dense_host = nullptr;
     st->dense_ev = nullptr;
-    reg(st);
-    *out = st;
+    *out = (sv_state)handle_put(st, HK_STATE);
     return SV_OK;
 }
 
@@ -624,10 +665,10 @@ sv_status sv_wrap(void* dev_ptr, int n_qubits, sv_dtype dtype, void* stream, sv_
     return make_state(dev_ptr, false, n_qubits, dtype, stream, out);
 }
 
-sv_status sv_free(sv_state st)
+sv_status sv_free(sv_state st_h)
 {
-    SV_CHECK_STATE(st);
-    unreg(st);
+    sv_state_s* const st = (sv_state_s*)handle_drop(st_h, HK_STATE);
+    if (!st) return set_error(SV_ERR_HANDLE, "invalid state handle");
     (void)hipStreamSynchronize(st->stream);
     if (st->work) (void)hipFree(st->work);
     if (st->dense_dev) (void)hipFree(st->dense_dev);
@@ -638,25 +679,25 @@ sv_status sv_free(sv_state st)
     return SV_OK;
 }
 
-sv_status sv_set_stream(sv_state st, void* stream)
+sv_status sv_set_stream(sv_state st_h, void* stream)
 {
-    SV_CHECK_STATE(st);
+    SV_STATE(st);
     st->stream = (hipStream_t)stream;
     return SV_OK;
 }
 
-sv_status sv_get_info(sv_state st, int* n_qubits, int* dtype, void** dev_ptr)
+sv_status sv_get_info(sv_state st_h, int* n_qubits, int* dtype, void** dev_ptr)
 {
-    SV_CHECK_STATE(st);
+    SV_STATE(st);
     if (n_qubits) *n_qubits = st->n;
     if (dtype) *dtype = st->dtype;
     if (dev_ptr) *dev_ptr = st->data;
     return SV_OK;
 }
 
-sv_status sv_set_basis(sv_state st, uint64_t index)
+sv_status sv_set_basis(sv_state st_h, uint64_t index)
 {
-    SV_CHECK_STATE(st);
+    SV_STATE(st);
     const uint64_t na = 1ull << st->n;
     if (index >= na) return set_error(SV_ERR_ARG, "basis index out of range");
     const hipError_t e = st->dtype == SV_C128 ? launch_set_basis<double>(st->data, na, index, st->stream)
@@ -664,9 +705,9 @@ sv_status sv_set_basis(sv_state st, uint64_t index)
     return hip_status(e, "set_basis");
 }
 
-sv_status sv_copy_to_host(sv_state st, void* host, size_t bytes)
+sv_status sv_copy_to_host(sv_state st_h, void* host, size_t bytes)
 {
-    SV_CHECK_STATE(st);
+    SV_STATE(st);
     if (!host) return set_error(SV_ERR_ARG, "null host pointer");
     if (bytes != sv_state_bytes(st->n, (sv_dtype)st->dtype)) return set_error(SV_ERR_ARG, "byte count mismatch");
     hipError_t e = hipMemcpyAsync(host, st->data, bytes, hipMemcpyDeviceToHost, st->stream);
@@ -674,9 +715,9 @@ sv_status sv_copy_to_host(sv_state st, void* host, size_t bytes)
     return hip_status(e, "copy_to_host");
 }
 
-sv_status sv_copy_from_host(sv_state st, const void* host, size_t bytes)
+sv_status sv_copy_from_host(sv_state st_h, const void* host, size_t bytes)
 {
-    SV_CHECK_STATE(st);
+    SV_STATE(st);
     if (!host) return set_error(SV_ERR_ARG, "null host pointer");
     if (bytes != sv_state_bytes(st->n, (sv_dtype)st->dtype)) return set_error(SV_ERR_ARG, "byte count mismatch");
     hipError_t e = hipMemcpyAsync(st->data, host, bytes, hipMemcpyHostToDevice, st->stream);
@@ -684,10 +725,10 @@ sv_status sv_copy_from_host(sv_state st, const void* host, size_t bytes)
     return hip_status(e, "copy_from_host");
 }
 
-sv_status sv_copy_state(sv_state dst, sv_state src)
+sv_status sv_copy_state(sv_state dst_h, sv_state src_h)
 {
-    SV_CHECK_STATE(dst);
-    SV_CHECK_STATE(src);
+    SV_STATE(dst);
+    SV_STATE(src);
     if (dst->n != src->n || dst->dtype != src->dtype) return set_error(SV_ERR_ARG, "state shape mismatch");
     if (dst == src) return SV_OK;
     const size_t bytes = sv_state_bytes(src->n, (sv_dtype)src->dtype);
@@ -695,19 +736,19 @@ sv_status sv_copy_state(sv_state dst, sv_state src)
                       "copy_state");
 }
 
-sv_status sv_synchronize(sv_state st)
+sv_status sv_synchronize(sv_state st_h)
 {
-    SV_CHECK_STATE(st);
+    SV_STATE(st);
     return hip_status(hipStreamSynchronize(st->stream), "synchronize");
 }
 
 // ---------------------------------------------------------------------------
 // gates
 // ---------------------------------------------------------------------------
-sv_status sv_apply_controlled(sv_state st, sv_gate gate, const int* controls, int nc, const int* targets, int nt,
+sv_status sv_apply_controlled(sv_state st_h, sv_gate gate, const int* controls, int nc, const int* targets, int nt,
                               const double* params, const double* matrix, int adjoint)
 {
-    SV_CHECK_STATE(st);
+    SV_STATE(st);
     Plan pl;
     sv_status rc = build_plan(st->n, st->dtype, gate, controls, nc, targets, nt, params, matrix, adjoint, &pl);
     if (rc) return rc;
@@ -720,9 +761,9 @@ sv_status sv_apply_gate(sv_state st, sv_gate gate, const int* targets, int nt, c
     return sv_apply_controlled(st, gate, nullptr, 0, targets, nt, params, matrix, adjoint);
 }
 
-sv_status sv_apply_general(sv_state st, const int* qubits, int k, const double* matrix)
+sv_status sv_apply_general(sv_state st_h, const int* qubits, int k, const double* matrix)
 {
-    SV_CHECK_STATE(st);
+    SV_STATE(st);
     if (k < 1 || k > SV_MAX_GENERAL_K) return set_error(SV_ERR_ARG, "general gate needs 1 <= k <= 3");
     if (!matrix) return set_error(SV_ERR_ARG, "null matrix");
     sv_status rc = check_qubits(st->n, nullptr, 0, qubits, k);
@@ -771,9 +812,8 @@ sv_status sv_apply_general(sv_state st, const int* qubits, int k, const double* 
     return hip_status(e, "general launch");
 }
 
-sv_status sv_apply_dense(sv_state st, const int* qubits, int k, const double* matrix)
+static sv_status apply_dense(sv_state_s* st, const int* qubits, int k, const double* matrix)
 {
-    SV_CHECK_STATE(st);
     if (k < kDenseMinK || k > kDenseMaxK) return set_error(SV_ERR_ARG, "dense block needs 4 <= k <= 6");
     if (!matrix) return set_error(SV_ERR_ARG, "null matrix");
     sv_status rc = check_qubits(st->n, nullptr, 0, qubits, k);
@@ -817,6 +857,12 @@ sv_status sv_apply_dense(sv_state st, const int* qubits, int k, const double* ma
     return hip_status(e, "dense block launch");
 }
 
+sv_status sv_apply_dense(sv_state st_h, const int* qubits, int k, const double* matrix)
+{
+    SV_STATE(st);
+    return apply_dense(st, qubits, k, matrix);
+}
+
 // ---------------------------------------------------------------------------
 // measurement
 // ---------------------------------------------------------------------------
@@ -827,9 +873,9 @@ static sv_status finish_scalar(sv_state st, const double* dres, double* out)
     return hip_status(e, "result copy");
 }
 
-sv_status sv_norm2(sv_state st, double* out)
+sv_status sv_norm2(sv_state st_h, double* out)
 {
-    SV_CHECK_STATE(st);
+    SV_STATE(st);
     if (!out) return set_error(SV_ERR_ARG, "null output");
     const uint64_t na = 1ull << st->n;
     sv_status rw = ensure_work(st, kReduceBlocks);
@@ -943,9 +989,9 @@ static sv_status expval_to_dev(sv_state st, const ObsPlan& op, double* out_dev)
     return hip_status(e, "expval");
 }
 
-sv_status sv_expval_obs_dev(sv_state st, const sv_obs* obs, double* out_dev)
+sv_status sv_expval_obs_dev(sv_state st_h, const sv_obs* obs, double* out_dev)
 {
-    SV_CHECK_STATE(st);
+    SV_STATE(st);
     if (!out_dev) return set_error(SV_ERR_ARG, "null output");
     ObsPlan op;
     sv_status rc = plan_obs(st->n, obs, &op);
@@ -955,9 +1001,9 @@ sv_status sv_expval_obs_dev(sv_state st, const sv_obs* obs, double* out_dev)
     return expval_to_dev(st, op, out_dev);
 }
 
-sv_status sv_expval_obs(sv_state st, const sv_obs* obs, double* out)
+sv_status sv_expval_obs(sv_state st_h, const sv_obs* obs, double* out)
 {
-    SV_CHECK_STATE(st);
+    SV_STATE(st);
     if (!out) return set_error(SV_ERR_ARG, "null output");
     ObsPlan op;
     sv_status rc = plan_obs(st->n, obs, &op);
@@ -969,23 +1015,34 @@ sv_status sv_expval_obs(sv_state st, const sv_obs* obs, double* out)
     return finish_scalar(st, st->work, out);
 }
 
-sv_status sv_expval_pauli(sv_state st, const char* paulis, const int* qubits, int n, double* out)
+// One Pauli string as bit masks: X and Y positions in *x, Z and Y in *z.
+static sv_status pauli_masks(int n_state, const char* paulis, const int* qubits, int n, uint64_t* x, uint64_t* z)
 {
-    SV_CHECK_STATE(st);
-    if (!out || (n > 0 && (!paulis || !qubits)) || n < 0) return set_error(SV_ERR_ARG, "bad arguments");
-    sv_status rc = check_qubits(st->n, nullptr, 0, qubits, n);
+    if (n < 0 || (n > 0 && (!paulis || !qubits))) return set_error(SV_ERR_ARG, "bad arguments");
+    sv_status rc = check_qubits(n_state, nullptr, 0, qubits, n);
     if (rc) return rc;
-    uint64_t x = 0, z = 0;
+    *x = *z = 0;
     for (int j = 0; j < n; ++j) {
         const uint64_t b = 1ull << qubits[j];
         switch (paulis[j]) {
         case 'I': break;
-        case 'X': x |= b; break;
-        case 'Y': x |= b; z |= b; break;
-        case 'Z': z |= b; break;
+        case 'X': *x |= b; break;
+        case 'Y': *x |= b; *z |= b; break;
+        case 'Z': *z |= b; break;
         default: return set_error(SV_ERR_ARG, "pauli letters must be I, X, Y or Z");
         }
     }
+    return SV_OK;
+}
+
+// <psi|P|psi> of one Pauli string into device memory out_dev (may be the
+// workspace head).
+static sv_status expval_pauli_to_dev(sv_state_s* st, const char* paulis, const int* qubits, int n, double* out_dev,
+                                     bool out_in_work)
+{
+    uint64_t x, z;
+    sv_status rc = pauli_masks(st->n, paulis, qubits, n, &x, &z);
+    if (rc) return rc;
     const double c = 1.0;
     sv_obs o{1, &c, &x, &z};
     ObsPlan op;
@@ -993,18 +1050,31 @@ sv_status sv_expval_pauli(sv_state st, const char* paulis, const int* qubits, in
     if (rc) return rc;
     rc = ensure_work(st, obs_partials(op));
     if (rc) return rc;
-    rc = expval_to_dev(st, op, st->work);
+    return expval_to_dev(st, op, out_in_work ? st->work : out_dev);
+}
+
+sv_status sv_expval_pauli(sv_state st_h, const char* paulis, const int* qubits, int n, double* out)
+{
+    SV_STATE(st);
+    if (!out) return set_error(SV_ERR_ARG, "bad arguments");
+    sv_status rc = expval_pauli_to_dev(st, paulis, qubits, n, nullptr, true);
     if (rc) return rc;
     return finish_scalar(st, st->work, out);
+}
+
+sv_status sv_expval_pauli_dev(sv_state st_h, const char* paulis, const int* qubits, int n, double* out_dev)
+{
+    SV_STATE(st);
+    if (!out_dev) return set_error(SV_ERR_ARG, "null output");
+    return expval_pauli_to_dev(st, paulis, qubits, n, out_dev, false);
 }
 
 // ---------------------------------------------------------------------------
 // circuits
 // ---------------------------------------------------------------------------
-#define SV_CHECK_CIRC(c)                                                          \
-    do {                                                                          \
-        if (!live(c)) return set_error(SV_ERR_HANDLE, "invalid circuit handle");  \
-    } while (0)
+#define SV_CIRC(c)                                                                     \
+    sv_circuit_s* const c = (sv_circuit_s*)handle_get(c##_h, HK_CIRCUIT);               \
+    if (!c) return set_error(SV_ERR_HANDLE, "invalid circuit handle")
 
 static sv_status op_plan(const sv_circuit_s* c, int dtype, const OpRec& o, const double* params, int adjoint,
                          Plan* pl)
@@ -1097,15 +1167,14 @@ sv_status sv_circuit_create(int n_qubits, const sv_op* ops, int n_ops, int n_par
     }
     (void)hipMemcpy(c->d_slot_scale, scale.data(), sizeof(double) * scale.size(), hipMemcpyHostToDevice);
     (void)hipMemcpy(c->d_slot_param, sparam.data(), sizeof(int) * sparam.size(), hipMemcpyHostToDevice);
-    reg(c);
-    *out = c;
+    *out = (sv_circuit)handle_put(c, HK_CIRCUIT);
     return SV_OK;
 }
 
-sv_status sv_circuit_free(sv_circuit c)
+sv_status sv_circuit_free(sv_circuit c_h)
 {
-    SV_CHECK_CIRC(c);
-    unreg(c);
+    sv_circuit_s* const c = (sv_circuit_s*)handle_drop(c_h, HK_CIRCUIT);
+    if (!c) return set_error(SV_ERR_HANDLE, "invalid circuit handle");
     (void)hipDeviceSynchronize();
     (void)hipFree(c->d_partials);
     (void)hipFree(c->d_slot_val);
@@ -1174,9 +1243,9 @@ static sv_status run_phase_terms(sv_state st, const uint64_t* masks, const doubl
     return hip_status(launch_phase_run(st->data, st->dtype, pr, st->stream), "phase run launch");
 }
 
-sv_status sv_apply_phases(sv_state st, int n_terms, const uint64_t* masks, const double* angles)
+sv_status sv_apply_phases(sv_state st_h, int n_terms, const uint64_t* masks, const double* angles)
 {
-    SV_CHECK_STATE(st);
+    SV_STATE(st);
     if (n_terms < 1 || n_terms > kMaxPhaseTerms || !masks || !angles)
         return set_error(SV_ERR_ARG, "phase run needs 1..64 terms and non-null arrays");
     std::vector<double> turns(n_terms);
@@ -1347,10 +1416,10 @@ static sv_status circuit_forward_fused(sv_circuit c, sv_state st, const double* 
     return flush();
 }
 
-sv_status sv_circuit_apply_fused(sv_circuit c, sv_state st, const double* params)
+sv_status sv_circuit_apply_fused(sv_circuit c_h, sv_state st_h, const double* params)
 {
-    SV_CHECK_CIRC(c);
-    SV_CHECK_STATE(st);
+    SV_CIRC(c);
+    SV_STATE(st);
     if (st->n != c->n) return set_error(SV_ERR_ARG, "state size does not match the circuit");
     if (c->n_params > 0 && !params) return set_error(SV_ERR_ARG, "null params");
     return circuit_forward_fused(c, st, params);
@@ -1527,7 +1596,7 @@ static sv_status circuit_forward_blocks(sv_circuit c, sv_state st, const double*
             }
             for (size_t r = 0; r < d; ++r) M[r * d + cc] = col[r];
         }
-        sv_status rc = sv_apply_dense(st, Q.data(), kb, (const double*)M.data());
+        sv_status rc = apply_dense(st, Q.data(), kb, (const double*)M.data());
         if (rc) return rc;
         ++dense;
     }
@@ -1535,10 +1604,10 @@ static sv_status circuit_forward_blocks(sv_circuit c, sv_state st, const double*
     return SV_OK;
 }
 
-sv_status sv_circuit_apply_blocks(sv_circuit c, sv_state st, const double* params, int k, int* n_dense_blocks)
+sv_status sv_circuit_apply_blocks(sv_circuit c_h, sv_state st_h, const double* params, int k, int* n_dense_blocks)
 {
-    SV_CHECK_CIRC(c);
-    SV_CHECK_STATE(st);
+    SV_CIRC(c);
+    SV_STATE(st);
     if (st->n != c->n) return set_error(SV_ERR_ARG, "state size does not match the circuit");
     if (c->n_params > 0 && !params) return set_error(SV_ERR_ARG, "null params");
     if (k < kDenseMinK || k > kDenseMaxK) return set_error(SV_ERR_ARG, "block size must be 4..6 qubits");
@@ -1583,10 +1652,10 @@ sv_status sv_block_plan(int n_qubits, const sv_op* ops, int n_ops, int k, int64_
     return SV_OK;
 }
 
-sv_status sv_circuit_apply(sv_circuit c, sv_state st, const double* params)
+sv_status sv_circuit_apply(sv_circuit c_h, sv_state st_h, const double* params)
 {
-    SV_CHECK_CIRC(c);
-    SV_CHECK_STATE(st);
+    SV_CIRC(c);
+    SV_STATE(st);
     if (st->n != c->n) return set_error(SV_ERR_ARG, "state size does not match the circuit");
     if (c->n_params > 0 && !params) return set_error(SV_ERR_ARG, "null params");
     return circuit_forward(c, st, params);
@@ -1678,12 +1747,12 @@ static sv_status adjoint_sweep(sv_circuit c, sv_state psi, sv_state lam, const d
     return SV_OK;
 }
 
-sv_status sv_adjoint_grad(sv_circuit c, sv_state psi, sv_state lam, const double* params, const sv_obs* obs,
+sv_status sv_adjoint_grad(sv_circuit c_h, sv_state psi_h, sv_state lam_h, const double* params, const sv_obs* obs,
                           double* expval_out, double* grad_out)
 {
-    SV_CHECK_CIRC(c);
-    SV_CHECK_STATE(psi);
-    SV_CHECK_STATE(lam);
+    SV_CIRC(c);
+    SV_STATE(psi);
+    SV_STATE(lam);
     if (psi == lam) return set_error(SV_ERR_ARG, "psi and lam must be different states");
     if (psi->n != c->n || lam->n != c->n || psi->dtype != lam->dtype)
         return set_error(SV_ERR_ARG, "state sizes/dtypes do not match the circuit");
@@ -1726,8 +1795,8 @@ sv_status sv_adjoint_grad(sv_circuit c, sv_state psi, sv_state lam, const double
 sv_status sv_tune_set(int kernel_class, int dtype, int tier, int block, int unroll, int nt)
 {
     if (!g_tune_init) tune_defaults();
-    if (kernel_class < 0 || kernel_class >= KC_COUNT || (dtype != SV_C64 && dtype != SV_C128) || tier < 0 ||
-        tier >= kTiers)
+    if (kernel_class < 0 || kernel_class >= KC_COUNT || kernel_class == KC_RETIRED ||
+        (dtype != SV_C64 && dtype != SV_C128) || tier < 0 || tier >= kTiers)
         return set_error(SV_ERR_ARG, "bad tuning key");
     if (block < 64 || block > 1024 || (block & 63))
         return set_error(SV_ERR_ARG, "block must be a multiple of 64 in [64, 1024]");

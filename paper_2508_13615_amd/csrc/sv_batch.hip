@@ -431,6 +431,11 @@ struct sv_batch_s {
     hipGraph_t graph;
     hipGraphExec_t exec;
     bool graph_ready;
+    // the caller's stream (sv_batch_set_stream; default the null stream): a
+    // run waits for the work queued there before it, and work queued there
+    // after the run waits for the run's outputs
+    hipStream_t caller;
+    hipEvent_t ev_in, ev_out;
 };
 
 namespace {
@@ -451,6 +456,8 @@ void batch_release(sv_batch b)
     if (b->stream) (void)hipStreamSynchronize(b->stream);
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->ev_in) (void)hipEventDestroy(b->ev_in);
+    if (b->ev_out) (void)hipEventDestroy(b->ev_out);
     void* ptrs[] = {b->d_psi, b->d_lam, b->d_circ, b->d_pass, b->d_ops, b->d_lays, b->d_segs, b->d_cspec, b->d_cfac, b->d_coef, b->d_coef_f, b->d_epart, b->d_gpart, b->d_e_off, b->d_e_cnt, b->d_g_off, b->d_g_cnt,
                     b->d_slot_scale, b->d_slot_val, b->d_csr_ptr, b->d_csr_col, b->d_params, b->d_expvals,
                     b->d_grads};
@@ -921,6 +928,13 @@ sv_status sv_batch_create(const sv_batch_circuit* circuits, int n_circuits, sv_d
         delete b;
         return hip_fail(e, "stream");
     }
+    b->caller = nullptr;
+    e = hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        batch_release(b);
+        return hip_fail(e, "events");
+    }
     if (hipMalloc(&b->d_psi, state_total) != hipSuccess ||
         (with_grad && hipMalloc(&b->d_lam, state_total) != hipSuccess)) {
         (void)hipGetLastError();
@@ -984,20 +998,34 @@ sv_status sv_batch_create(const sv_batch_circuit* circuits, int n_circuits, sv_d
         batch_release(b);
         return hip_fail(e, "pass engine LDS limit");
     }
-    handle_register(b);
-    *out = b;
+    *out = (sv_batch)handle_put(b, HK_BATCH);
     return SV_OK;
 }
 
-sv_status sv_batch_run(sv_batch b, const double* params, int params_on_device, double* expvals, double* grads,
+#define SV_BATCH(b)                                                                    \
+    sv_batch_s* const b = (sv_batch_s*)handle_get(b##_h, HK_BATCH);                     \
+    if (!b) return set_error(SV_ERR_HANDLE, "invalid batch handle")
+
+sv_status sv_batch_set_stream(sv_batch b_h, void* stream)
+{
+    SV_BATCH(b);
+    b->caller = (hipStream_t)stream;
+    return SV_OK;
+}
+
+sv_status sv_batch_run(sv_batch b_h, const double* params, int params_on_device, double* expvals, double* grads,
                        int outputs_on_device)
 {
-    if (!handle_live(b)) return set_error(SV_ERR_HANDLE, "invalid batch handle");
+    SV_BATCH(b);
     if (b->n_params > 0 && !params) return set_error(SV_ERR_ARG, "null params");
     if (!expvals) return set_error(SV_ERR_ARG, "null expvals");
     if (b->with_grad && b->n_params > 0 && !grads) return set_error(SV_ERR_ARG, "null grads");
     hipStream_t s = b->stream;
-    hipError_t e = hipSuccess;
+    // start after the work already queued on the caller's stream (it may
+    // still be writing the device-side parameters or clearing the outputs)
+    hipError_t e = hipEventRecord(b->ev_in, b->caller);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, b->ev_in, 0);
+    if (e != hipSuccess) return hip_fail(e, "batch stream order");
     if (b->n_params > 0)
         e = hipMemcpyAsync(b->d_params, params, sizeof(double) * b->n_params,
                            params_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s);
@@ -1007,11 +1035,20 @@ sv_status sv_batch_run(sv_batch b, const double* params, int params_on_device, d
             e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
             if (e != hipSuccess) return hip_fail(e, "graph capture");
             hipError_t e2 = enqueue_run(b);
-            e = hipStreamEndCapture(s, &b->graph);
-            if (e2 != hipSuccess) return hip_fail(e2, "graph capture launch");
-            if (e != hipSuccess) return hip_fail(e, "graph end capture");
-            e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
-            if (e != hipSuccess) return hip_fail(e, "graph instantiate");
+            hipGraph_t g = nullptr;
+            e = hipStreamEndCapture(s, &g);
+            if (e2 != hipSuccess || e != hipSuccess) {
+                // a failed capture leaves no graph behind: the next run captures again
+                if (g) (void)hipGraphDestroy(g);
+                return hip_fail(e2 != hipSuccess ? e2 : e, e2 != hipSuccess ? "graph capture launch" : "graph end capture");
+            }
+            e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+            if (e != hipSuccess) {
+                (void)hipGraphDestroy(g);
+                b->exec = nullptr;
+                return hip_fail(e, "graph instantiate");
+            }
+            b->graph = g;
             b->graph_ready = true;
         }
         e = hipGraphLaunch(b->exec, s);
@@ -1023,14 +1060,17 @@ sv_status sv_batch_run(sv_batch b, const double* params, int params_on_device, d
     e = hipMemcpyAsync(expvals, b->d_expvals, sizeof(double) * b->n_circ, ok, s);
     if (e == hipSuccess && b->with_grad && b->n_params > 0)
         e = hipMemcpyAsync(grads, b->d_grads, sizeof(double) * b->n_params, ok, s);
+    // later work on the caller's stream sees the outputs
+    if (e == hipSuccess) e = hipEventRecord(b->ev_out, s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(b->caller, b->ev_out, 0);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "batch run");
     return SV_OK;
 }
 
-sv_status sv_batch_info(sv_batch b, int64_t* info)
+sv_status sv_batch_info(sv_batch b_h, int64_t* info)
 {
-    if (!handle_live(b)) return set_error(SV_ERR_HANDLE, "invalid batch handle");
+    SV_BATCH(b);
     if (!info) return set_error(SV_ERR_ARG, "null info");
     info[0] = b->n_circ;
     info[1] = b->n_items;
@@ -1047,26 +1087,26 @@ sv_status sv_batch_info(sv_batch b, int64_t* info)
     return SV_OK;
 }
 
-sv_status sv_batch_state(sv_batch b, int circuit, void** dev_ptr, int* n_qubits)
+sv_status sv_batch_state(sv_batch b_h, int circuit, void** dev_ptr, int* n_qubits)
 {
-    if (!handle_live(b)) return set_error(SV_ERR_HANDLE, "invalid batch handle");
+    SV_BATCH(b);
     if (circuit < 0 || circuit >= b->n_circ || !dev_ptr) return set_error(SV_ERR_ARG, "bad circuit index");
     *dev_ptr = (char*)b->d_psi + b->psi_off[circuit];
     if (n_qubits) *n_qubits = b->nq[circuit];
     return SV_OK;
 }
 
-sv_status sv_batch_free(sv_batch b)
+sv_status sv_batch_free(sv_batch b_h)
 {
-    if (!handle_live(b)) return set_error(SV_ERR_HANDLE, "invalid batch handle");
-    handle_unregister(b);
+    sv_batch_s* const b = (sv_batch_s*)handle_drop(b_h, HK_BATCH);
+    if (!b) return set_error(SV_ERR_HANDLE, "invalid batch handle");
     batch_release(b);
     return SV_OK;
 }
 
-sv_status sv_batch_copy_state(sv_batch b, int circuit, void* host, size_t bytes)
+sv_status sv_batch_copy_state(sv_batch b_h, int circuit, void* host, size_t bytes)
 {
-    if (!handle_live(b)) return set_error(SV_ERR_HANDLE, "invalid batch handle");
+    SV_BATCH(b);
     if (circuit < 0 || circuit >= b->n_circ || !host) return set_error(SV_ERR_ARG, "bad circuit index or buffer");
     const size_t sb = ((size_t)1 << b->nq[circuit]) * (b->dtype == SV_C128 ? 16 : 8);
     if (bytes != sb) return set_error(SV_ERR_ARG, "byte count mismatch");

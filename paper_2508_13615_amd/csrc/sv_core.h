@@ -41,7 +41,8 @@ enum PairOp : int {
     PAIR_Y = 1,     // (a, b) -> (-i b, i a)
     PAIR_REAL = 2,  // real 2x2 (H, RY)
     PAIR_RX = 3,    // [[c, -i s], [-i s, c]]
-    PAIR_DENSE = 4  // complex 2x2 (U2 and anything else)
+    PAIR_DENSE = 4, // complex 2x2 (U2 and anything else)
+    PAIR_DIAG = 5   // diag(m00, m11): each member times its own phase (RZ); no partner needed
 };
 
 // Operation kinds of the single-member (subset-diagonal) kernel.
@@ -59,13 +60,6 @@ struct Coef2 {  // 2x2 complex, row-major interleaved: m00 m01 m10 m11
 template <typename T>
 struct Coef4 {  // 4x4 complex
     T m[32];
-};
-
-template <typename T>
-struct DiagSpec {  // element-wise diagonal on up to 3 target bits
-    int32_t k;
-    int32_t tq[3];  // tq[0] is the most significant bit of the entry index
-    T d[16];        // 2^k complex entries
 };
 
 template <typename T, int K>
@@ -159,8 +153,6 @@ hipError_t launch_lds_gate(void* psi, const GroupSpec& tiles, const LdsSpec& ls,
 template <typename T>
 hipError_t launch_one(void* psi, const GroupSpec& gs, int op, T zr, T zi, hipStream_t s, Launch lc);
 template <typename T>
-hipError_t launch_diag(void* psi, const GroupSpec& gs, const DiagSpec<T>& d, hipStream_t s, Launch lc);
-template <typename T>
 hipError_t launch_quad(void* psi, const GroupSpec& gs, const uint64_t off[4], const Coef4<T>& c,
                        hipStream_t s, Launch lc);
 template <typename T>
@@ -224,9 +216,12 @@ hipError_t launch_scatter_grads(const double* slot_val, const int* slot_param, c
 
 // ---- helpers ----------------------------------------------------------------
 sv_status set_error(sv_status st, const std::string& msg);
-// Registry of live handles (states, circuits, batches).
-void handle_register(const void* h);
-bool handle_live(const void* h);
-void handle_unregister(const void* h);
+// Handle table (states, circuits, batches): handle_put returns a new handle
+// for obj; handle_get returns the object of a live handle of that kind, else
+// nullptr; handle_drop does the same and invalidates every copy of the handle.
+enum HandleKind : int { HK_STATE = 1, HK_CIRCUIT = 2, HK_BATCH = 3 };
+void* handle_put(void* obj, int kind);
+void* handle_get(const void* h, int kind);
+void* handle_drop(const void* h, int kind);
 
 }  // namespace svk

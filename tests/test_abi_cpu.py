@@ -142,6 +142,63 @@ def test_handle_errors():
     assert b"invalid" in lib.sv_last_error()
 
 
+def test_stale_handle_rejected_after_reuse():
+    # A handle freed and a new object created in its place: the old handle
+    # (and every copy of it) is rejected by its generation, the new one works.
+    old = wrap(3)
+    stale = ctypes.c_void_p(old.value)
+    assert lib.sv_free(old) == OK
+    fresh = [wrap(3) for _ in range(4)]
+    try:
+        assert all(f.value != stale.value for f in fresh)
+        assert lib.sv_set_basis(stale, 0) == HANDLE
+        assert lib.sv_free(stale) == HANDLE
+        n = ctypes.c_int()
+        assert lib.sv_get_info(fresh[0], ctypes.byref(n), None, None) == OK and n.value == 3
+    finally:
+        for f in fresh:
+            assert lib.sv_free(f) == OK
+
+
+def test_handle_kinds_are_not_interchangeable():
+    # a state handle is not a circuit or a batch handle, and the reverse
+    h = wrap(3)
+    try:
+        assert lib.sv_circuit_free(h) == HANDLE
+        assert lib.sv_batch_free(h) == HANDLE
+        assert lib.sv_batch_set_stream(h, None) == HANDLE
+        info = (ctypes.c_int64 * 12)()
+        assert lib.sv_batch_info(h, info) == HANDLE
+        # an address-like value is never a handle
+        assert lib.sv_set_basis(ctypes.c_void_p(FAKE), 0) == HANDLE
+    finally:
+        assert lib.sv_free(h) == OK
+
+
+def test_device_output_expval_validation():
+    h = wrap(4)
+    try:
+        assert lib.sv_expval_pauli_dev(h, b"Z", ints(0), 1, None) == ARG
+        assert lib.sv_expval_pauli_dev(h, b"Z", ints(4), 1, ctypes.c_void_p(FAKE)) == QUBIT
+        assert lib.sv_expval_pauli_dev(h, b"W", ints(0), 1, ctypes.c_void_p(FAKE)) == ARG
+        assert lib.sv_expval_pauli_dev(h, b"XX", ints(2, 2), 2, ctypes.c_void_p(FAKE)) == QUBIT
+        assert lib.sv_expval_obs_dev(h, None, ctypes.c_void_p(FAKE)) == ARG
+    finally:
+        lib.sv_free(h)
+
+
+def test_stream_bench_validation():
+    f = ctypes.c_void_p(FAKE)
+    assert lib.sv_stream_bench(3, f, f, 1024, 256, 4, None) == ARG  # mode
+    assert lib.sv_stream_bench(0, f, f, 0, 256, 4, None) == ARG  # empty
+    assert lib.sv_stream_bench(0, f, f, 1000, 256, 4, None) == ARG  # not a multiple of 16
+    assert lib.sv_stream_bench(0, f, f, 1024, 100, 4, None) == ARG  # block
+    assert lib.sv_stream_bench(0, f, f, 1024, 256, 3, None) == ARG  # unroll
+    assert lib.sv_stream_bench(0, ctypes.c_void_p(FAKE + 8), f, 1024, 256, 4, None) == ARG  # alignment
+    assert lib.sv_stream_bench(1, None, None, 1024, 256, 4, None) == ARG  # read needs src
+    assert lib.sv_stream_bench(2, None, f, 1024, 256, 4, None) == ARG  # write needs dst
+
+
 def test_circuit_create_validation_is_host_side():
     ops = (_lib.SvOp * 1)()
     ops[0].gate = 8
@@ -168,6 +225,7 @@ def test_tuning_table_validation():
     assert lib.sv_tune_set(0, 2, 2, 256, 1, 2) == ARG
     assert lib.sv_tune_set(9, 2, 2, 256, 1, 0) == ARG
     assert lib.sv_tune_set(0, 2, 3, 256, 1, 0) == ARG
+    assert lib.sv_tune_set(2, 2, 1, 256, 1, 0) == ARG  # retired class
     assert lib.sv_tune_set(0, 2, 2, b.value, u.value, nt.value) == OK
 
 
