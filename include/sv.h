@@ -211,6 +211,24 @@ sv_status sv_expval_obs(sv_state st, const sv_obs* obs, double* out);
  * workspace, allocated (or grown) on the first call that needs it. */
 sv_status sv_expval_obs_dev(sv_state st, const sv_obs* obs, double* out_dev);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the value
+ * of sv_expval_obs_dev, computed by the same kernels in the same order
+ * (bit-identical), with every intermediate in a static device array that
+ * each GPU holds from the library's first use until the process ends
+ * (512 KiB).  No hipMalloc, hipFree or other allocating device call is
+ * made, and on success the host side allocates nothing either (only an
+ * error's message does).
+ * Limit: the observable may need at most 64 reduction passes (one per off-
+ * diagonal term, one per 32 diagonal terms, one for sum Z_i or
+ * sum Z_i Z_i+1); larger ones are rejected with SV_ERR_ARG before any device
+ * work.  The state must live on the current device.  Every call on a GPU
+ * shares that GPU's array: calls that overlap on one GPU (different streams
+ * or threads without ordering between them) race and give wrong values.
+ * Asynchronous on the state's stream.
+ * Errors: as sv_expval_obs_dev, SV_ERR_ARG for too many passes. */
+sv_status sv_expval_obs_dev_noalloc(sv_state st, const sv_obs* obs, double* out_dev);
+
 /* <psi|P|psi> of one Pauli string (as sv_expval_pauli) written to device
  * memory out_dev (one double); asynchronous on the state's stream, so it can
  * sit between gate launches without a host round trip.

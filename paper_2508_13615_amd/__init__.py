@@ -230,6 +230,13 @@ class State:
         obs = obs if isinstance(obs, Observable) else Observable(obs)
         check(lib.sv_expval_obs_dev(self.handle, ctypes.byref(obs.c), ctypes.c_void_p(out.data_ptr())))
 
+    def expval_dev_noalloc(self, obs, out: torch.Tensor) -> None:
+        """As expval_dev with no device allocation: the partials live in the
+        library's static per-GPU array (sv_expval_obs_dev_noalloc; at most 64
+        reduction passes; overlapping calls on one GPU race)."""
+        obs = obs if isinstance(obs, Observable) else Observable(obs)
+        check(lib.sv_expval_obs_dev_noalloc(self.handle, ctypes.byref(obs.c), ctypes.c_void_p(out.data_ptr())))
+
     def expval_pauli_dev(self, paulis: str, qubits: Sequence[int], out: torch.Tensor) -> None:
         """<psi|P|psi> of one Pauli string into out[0] (a float64 CUDA tensor),
         queued on the state's stream (sv_expval_pauli_dev)."""

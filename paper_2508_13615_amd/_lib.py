@@ -26,7 +26,7 @@ EXPORTS = [
     "sv_alloc", "sv_wrap", "sv_free", "sv_set_stream", "sv_get_info", "sv_state_bytes", "sv_set_basis",
     "sv_copy_to_host", "sv_copy_from_host", "sv_copy_state", "sv_synchronize", "sv_apply_gate",
     "sv_apply_controlled", "sv_apply_general", "sv_apply_dense", "sv_apply_phases", "sv_norm2", "sv_expval_pauli",
-    "sv_expval_obs", "sv_expval_obs_dev", "sv_expval_pauli_dev", "sv_circuit_create", "sv_circuit_free", "sv_circuit_apply",
+    "sv_expval_obs", "sv_expval_obs_dev", "sv_expval_obs_dev_noalloc", "sv_expval_pauli_dev", "sv_circuit_create", "sv_circuit_free", "sv_circuit_apply",
     "sv_circuit_apply_fused", "sv_circuit_apply_blocks", "sv_block_plan", "sv_adjoint_grad",
     "sv_batch_create", "sv_batch_plan", "sv_batch_run", "sv_batch_info", "sv_batch_state", "sv_batch_copy_state",
     "sv_batch_free", "sv_batch_set_stream",
@@ -90,6 +90,7 @@ def _load():
         "sv_expval_obs": [vp, ctypes.POINTER(SvObs), dp],
         "sv_expval_obs_dev": [vp, ctypes.POINTER(SvObs), vp],
         "sv_expval_pauli_dev": [vp, ctypes.c_char_p, ip, i, vp],
+        "sv_expval_obs_dev_noalloc": [vp, ctypes.POINTER(SvObs), vp],
         "sv_circuit_create": [i, ctypes.POINTER(SvOp), i, i, ctypes.POINTER(vp)],
         "sv_circuit_free": [vp],
         "sv_circuit_apply": [vp, vp, dp],

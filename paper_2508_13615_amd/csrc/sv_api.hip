@@ -890,6 +890,33 @@ sv_status sv_norm2(sv_state st_h, double* out)
     return finish_scalar(st, res, out);
 }
 
+// An observable split into diagonal terms (xmask = 0: one pass evaluates up
+// to kDiagTermsPerPass of them, or the closed forms sum Z_i / sum Z_i Z_i+1
+// in one) and off-diagonal terms (one pass each).  The term lists are
+// std::vector here and fixed-capacity arrays in the allocation-free plan.
+template <typename T, int N>
+struct FixedVec {
+    T v[N];
+    int n = 0;
+    size_t size() const { return (size_t)n; }
+    bool empty() const { return n == 0; }
+    T& operator[](size_t i) { return v[i]; }
+    const T& operator[](size_t i) const { return v[i]; }
+};
+template <typename T>
+static bool add_term(std::vector<T>& v, const T& x)
+{
+    v.push_back(x);
+    return true;
+}
+template <typename T, int N>
+static bool add_term(FixedVec<T, N>& v, const T& x)
+{
+    if (v.n >= N) return false;
+    v.v[v.n++] = x;
+    return true;
+}
+
 struct ObsPlan {
     int diag_kind;  // -1 none, 0 generic, 1 sum Z, 2 sum ZZ
     double diag_coeff;
@@ -900,7 +927,44 @@ struct ObsPlan {
     std::vector<int> oy;
 };
 
-static sv_status plan_obs(int n, const sv_obs* obs, ObsPlan* op)
+// Term capacity of the allocation-free plan: at most kNoAllocPasses
+// reduction passes, each a pass of up to kDiagTermsPerPass diagonal terms or
+// one off-diagonal term.
+constexpr int kNoAllocPasses = 64;
+struct ObsPlanFixed {
+    int diag_kind;
+    double diag_coeff;
+    FixedVec<double, kNoAllocPasses * kDiagTermsPerPass> dc;
+    FixedVec<uint64_t, kNoAllocPasses * kDiagTermsPerPass> dz;
+    FixedVec<double, kNoAllocPasses> oc;
+    FixedVec<uint64_t, kNoAllocPasses> ox, oz;
+    FixedVec<int, kNoAllocPasses> oy;
+};
+
+// Closed forms among the diagonal terms: one common coefficient and the z
+// masks exactly {2^i : i < n} (sum Z_i, kind 1) or {3 * 2^i : i < n - 1}
+// (sum Z_i Z_i+1, kind 2), in any order; else 0 (generic list).
+template <typename V, typename W>
+static int closed_form(int n, const V& dc, const W& dz)
+{
+    for (size_t k = 1; k < dc.size(); ++k)
+        if (dc[k] != dc[0]) return 0;
+    const size_t m = dz.size();
+    uint64_t seen = 0;
+    bool single = m == (size_t)n, pairs = n > 1 && m == (size_t)(n - 1);
+    for (size_t k = 0; k < m && (single || pairs); ++k) {
+        const uint64_t z = dz[k];
+        const int i = z ? __builtin_ctzll(z) : 64;
+        if (i >= 64 || (seen >> i) & 1ull) return 0;
+        seen |= 1ull << i;
+        if (z != (1ull << i) || i >= n) single = false;
+        if (z != (3ull << i) || i + 1 >= n) pairs = false;
+    }
+    return single ? 1 : (pairs ? 2 : 0);
+}
+
+template <typename P>
+static sv_status plan_obs(int n, const sv_obs* obs, P* op)
 {
     if (!obs) return set_error(SV_ERR_ARG, "null observable");
     if (obs->n_terms < 0) return set_error(SV_ERR_ARG, "negative term count");
@@ -911,40 +975,34 @@ static sv_status plan_obs(int n, const sv_obs* obs, ObsPlan* op)
     for (int k = 0; k < obs->n_terms; ++k) {
         const uint64_t x = obs->xmask[k], z = obs->zmask[k];
         if ((x | z) & ~all) return set_error(SV_ERR_QUBIT, "observable term acts outside the state");
+        bool ok;
         if (x == 0) {
-            op->dc.push_back(obs->coeffs[k]);
-            op->dz.push_back(z);
+            ok = add_term(op->dc, obs->coeffs[k]) && add_term(op->dz, z);
         } else {
-            op->oc.push_back(obs->coeffs[k]);
-            op->ox.push_back(x);
-            op->oz.push_back(z);
-            op->oy.push_back(__builtin_popcountll(x & z));
+            ok = add_term(op->oc, obs->coeffs[k]) && add_term(op->ox, x) && add_term(op->oz, z) &&
+                 add_term(op->oy, (int)__builtin_popcountll(x & z));
         }
+        if (!ok)  // only the fixed-capacity plan can run out of room
+            return set_error(SV_ERR_ARG, "observable needs more reduction passes than this entry point holds (" +
+                                             std::to_string(kNoAllocPasses) + ")");
     }
     if (!op->dc.empty()) {
-        op->diag_kind = 0;
-        // closed forms: all unit-free common coefficient, exactly {Z_i} or {Z_i Z_i+1}
-        const double c0 = op->dc[0];
-        bool same = true;
-        for (double c : op->dc) same = same && (c == c0);
-        if (same) {
-            std::vector<uint64_t> zs = op->dz;
-            std::sort(zs.begin(), zs.end());
-            std::vector<uint64_t> sz, szz;
-            for (int i = 0; i < n; ++i) sz.push_back(1ull << i);
-            for (int i = 0; i + 1 < n; ++i) szz.push_back(3ull << i);
-            std::sort(sz.begin(), sz.end());
-            std::sort(szz.begin(), szz.end());
-            if (zs == sz) op->diag_kind = 1;
-            else if (zs == szz && n > 1) op->diag_kind = 2;
-            if (op->diag_kind > 0) op->diag_coeff = c0;
-        }
+        op->diag_kind = closed_form(n, op->dc, op->dz);
+        if (op->diag_kind > 0) op->diag_coeff = op->dc[0];
     }
     return SV_OK;
 }
 
-template <typename T>
-static hipError_t obs_passes(sv_state st, const ObsPlan& op, double* partials, int* count)
+// Reduction passes of a plan (each writes one stage-1 grid of partials).
+template <typename P>
+static int obs_pass_count(const P& op)
+{
+    const int diag = op.diag_kind > 0 ? 1 : (int)((op.dc.size() + kDiagTermsPerPass - 1) / kDiagTermsPerPass);
+    return diag + (int)op.oc.size();
+}
+
+template <typename T, typename P>
+static hipError_t obs_passes(sv_state st, const P& op, double* partials, int* count)
 {
     int off = 0;
     hipError_t e = hipSuccess;
@@ -999,6 +1057,61 @@ sv_status sv_expval_obs_dev(sv_state st_h, const sv_obs* obs, double* out_dev)
     rc = ensure_work(st, obs_partials(op));
     if (rc) return rc;
     return expval_to_dev(st, op, out_dev);
+}
+
+// ---------------------------------------------------------------------------
+// expectation value into device memory without any allocation
+// ---------------------------------------------------------------------------
+// The reduction partials of sv_expval_obs_dev_noalloc live in this file-scope
+// device array, one copy per GPU, held until the process ends (512 KiB).
+// Host code never passes its name to a kernel: the name is a host-side
+// stand-in, so each device's address is looked up once, with that device
+// current, and kept in scratch_dev.
+static __device__ __align__(256) double scratch[kNoAllocPasses * kReduceBlocks];
+
+constexpr int kScratchDevices = 64;
+static std::mutex g_scratch_mu;
+static double* g_scratch_dev[kScratchDevices];
+
+// The current device's address of `scratch`.
+static sv_status scratch_dev(double** out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_status(e, "current device");
+    if (dev < 0 || dev >= kScratchDevices) return set_error(SV_ERR_UNSUPPORTED, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return hip_status(e != hipSuccess ? e : hipErrorInvalidSymbol, "scratch address");
+        g_scratch_dev[dev] = (double*)p;
+    }
+    *out = g_scratch_dev[dev];
+    return SV_OK;
+}
+
+sv_status sv_expval_obs_dev_noalloc(sv_state st_h, const sv_obs* obs, double* out_dev)
+{
+    SV_STATE(st);
+    if (!out_dev) return set_error(SV_ERR_ARG, "null output");
+    ObsPlanFixed op;  // fixed-capacity term lists: no heap
+    sv_status rc = plan_obs(st->n, obs, &op);
+    if (rc) return rc;
+    if (obs_pass_count(op) > kNoAllocPasses)
+        return set_error(SV_ERR_ARG, "observable needs " + std::to_string(obs_pass_count(op)) +
+                                         " reduction passes; this entry point holds at most " +
+                                         std::to_string(kNoAllocPasses));
+    double* partials = nullptr;
+    rc = scratch_dev(&partials);
+    if (rc) return rc;
+    // every partial the final sum reads is written first by this call's own
+    // stage-1 kernels on the same stream, so nothing needs clearing
+    int count = 0;
+    hipError_t e = st->dtype == SV_C128 ? obs_passes<double>(st, op, partials, &count)
+                                        : obs_passes<float>(st, op, partials, &count);
+    if (e == hipSuccess) e = launch_sum_partials(partials, count, out_dev, st->stream);
+    return hip_status(e, "expval");
 }
 
 sv_status sv_expval_obs(sv_state st_h, const sv_obs* obs, double* out)
