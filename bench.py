@@ -382,7 +382,10 @@ def golden_adjoint(n):
     (tests/golden/oracle_adjoint_hea.txt): energy, {j: parameter shift},
     {j: central difference}."""
     e, ps, fd = None, {}, {}
-    with open(os.path.join(GOLDEN, "oracle_adjoint_hea.txt")) as f:
+    path = os.path.join(GOLDEN, "oracle_adjoint_hea.txt")
+    if not os.path.exists(path):
+        return e, ps, fd
+    with open(path) as f:
         for line in f:
             tok = line.split()
             if not tok or tok[0].startswith("#") or int(tok[1]) != n:
