@@ -242,18 +242,20 @@ def summarize_sweep(recs, n, dtype, ceiling_gbps):
 
 def measure_ceiling(sv, torch, state):
     """The streaming kernel (sv_stream_bench) over the state's bytes: copy to
-    a second buffer (bytes read + bytes written), read only, write only; best
-    launch shape of a small set, median of 3 runs each."""
+    a second buffer (bytes read + bytes written), read only, write only, and
+    in place (read and write back, a full-touch gate's access pattern; run on
+    the second buffer); best launch shape of a small set, median of 3 runs
+    each.  `ceiling_GBps` is the in-place figure: the bound for a gate."""
     nbytes = state.tensor.numel() * state.tensor.element_size()
-    other = torch.empty_like(state.tensor)
+    other = torch.zeros_like(state.tensor)
     out = {"bytes": nbytes}
-    for mode, label, factor in ((0, "copy", 2), (1, "read", 1), (2, "write", 1)):
+    for mode, label, factor in ((0, "copy", 2), (1, "read", 1), (2, "write", 1), (3, "inplace", 2)):
         best = None
-        for block in (256, 512):
+        for block in (64, 128, 256, 512):
             for unroll in (1, 2, 4, 8):
                 def run():
-                    sv.stream_bench(mode, other if mode != 1 else None, state.tensor if mode != 2 else None, nbytes,
-                                    block, unroll)
+                    sv.stream_bench(mode, other if mode != 1 else None, state.tensor if mode in (0, 1) else None,
+                                    nbytes, block, unroll)
                 run()
                 torch.cuda.synchronize()
                 ts = []
@@ -269,6 +271,7 @@ def measure_ceiling(sv, torch, state):
                     best = (gbps, block, unroll)
         out[f"{label}_GBps"] = best[0]
         out[f"{label}_shape"] = [best[1], best[2]]
+    out["ceiling_GBps"] = out["inplace_GBps"]
     del other
     torch.cuda.empty_cache()
     return out
@@ -635,7 +638,7 @@ def config5(sv, torch, reps, sequential):
     return out
 
 
-def config3(sv, torch, n, layers, reps):
+def config3(sv, torch, n, layers, reps, names=("hea", "qft", "universal"), engine_only=False):
     """32-qubit HEA (10 layers RY+RZ, CNOT ladder, from |0..0>), QFT of a
     random basis state and the universal circuit (2 n^2 gates after an H on
     every qubit), forward + sum Z on the fused engine, both dtypes; the same
@@ -650,6 +653,7 @@ def config3(sv, torch, n, layers, reps):
     jobs = {"hea": (W.hea_ops(n, layers), W.uniform_angles(W.hea_n_params(n, layers), 1003)),
             "qft": (prep + W.qft_ops(n), np.zeros(0)),
             "universal": ([W.Op("H", (), (q,)) for q in range(n)] + W.universal_ops(n), np.zeros(0))}
+    jobs = {k: v for k, v in jobs.items() if k in names}
     out = {"qubits": n, "hea_layers": layers, "qft_basis_index": x}
     for name, (ops, th) in jobs.items():
         for dt in ("c128", "c64"):
@@ -666,6 +670,8 @@ def config3(sv, torch, n, layers, reps):
             del b
             torch.cuda.empty_cache()
         out[f"{name}_abs_err_expval_c64_vs_c128"] = abs(out[f"{name}_c64"]["expval_sum_z"] - out[f"{name}_c128"]["expval_sum_z"])
+    if engine_only:
+        return out
     # the same circuits packed into 5-qubit dense blocks on the matrix cores
     for name, (ops, th) in jobs.items():
         circ = sv.Circuit(n, ops, len(th))
@@ -684,6 +690,8 @@ def config3(sv, torch, n, layers, reps):
                 f"(pass engine {out[f'{name}_{dt}']['s']:.3f} s)")
             del st
             torch.cuda.empty_cache()
+    if "qft" not in jobs:
+        return out
     # the same QFT on the single-gate kernels, op by op, and with each target's
     # H and controlled-phase run fused into one pass
     qft = sv.Circuit(n, W.qft_ops(n), 0)
@@ -788,7 +796,20 @@ def main():
     ap.add_argument("--skip-dense", action="store_true", help="skip the matrix-core dense-block section")
     ap.add_argument("--detail", default=os.path.join(ROOT, "gpurun_out", "bench_detail.json"),
                     help="where the full results go (the stdout line is the headline only)")
+    ap.add_argument("--only", default="",
+                    help="comma list of sections to run alone (profiling runs): sweep, c64, adjoint, adjoint_fused, "
+                         "batch, circuits32, circuits20, dense, cpu")
+    ap.add_argument("--circuits", default="hea,qft,universal", help="circuits of the circuits32 section")
+    ap.add_argument("--engine-only", action="store_true",
+                    help="circuits32: the pass engine only (no dense blocks, no single-gate QFT)")
     args = ap.parse_args()
+    only = {x for x in args.only.split(",") if x}
+    known = {"sweep", "c64", "adjoint", "adjoint_fused", "batch", "circuits32", "circuits20", "dense", "cpu"}
+    if only - known:
+        ap.error(f"unknown sections {sorted(only - known)}")
+
+    def want(section, skipped=False):
+        return section in only if only else not skipped
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the state-vector path here is built and measured on a single "
               "MI355X (the multi-GPU sharding is a design note only); run with --gpus 1", file=sys.stderr)
@@ -802,78 +823,84 @@ def main():
 
     torch.cuda.set_device(0)
     n = args.qubits
-    log(f"[bench] {n}-qubit complex128 state ({(1 << n) * 16 / 2**30:.1f} GiB)")
     gen = torch.Generator(device="cuda")
     gen.manual_seed(1001)
-    t = torch.randn(1 << n, dtype=torch.complex128, device="cuda", generator=gen)
-    t /= torch.linalg.vector_norm(t)
-    state = sv.State(n, "c128", tensor=t, basis=None)
     rng = np.random.default_rng(1002)
     cases = sweep_cases(n, rng, W)
     denses = [dense_of(c, None) for c in cases]
-    ceiling = measure_ceiling(sv, torch, state)
-    log(f"[bench] {len(cases)} gate cases per step; streaming kernel: copy {ceiling['copy_GBps']:.0f}, "
-        f"read {ceiling['read_GBps']:.0f}, write {ceiling['write_GBps']:.0f} GB/s")
+    head = {"metric": METRIC, "value": None, "unit": "gates/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f64", "data": "synthetic"}
+    detail = {}
+    if want("sweep"):
+        log(f"[bench] {n}-qubit complex128 state ({(1 << n) * 16 / 2**30:.1f} GiB)")
+        t = torch.randn(1 << n, dtype=torch.complex128, device="cuda", generator=gen)
+        t /= torch.linalg.vector_norm(t)
+        state = sv.State(n, "c128", tensor=t, basis=None)
+        ceiling = measure_ceiling(sv, torch, state)
+        log(f"[bench] {len(cases)} gate cases per step; streaming kernel: in place {ceiling['inplace_GBps']:.0f}, copy "
+            f"{ceiling['copy_GBps']:.0f}, read {ceiling['read_GBps']:.0f}, write {ceiling['write_GBps']:.0f} GB/s")
 
-    recs = []
-    for w in range(args.warmup):
-        run_sweep(sv, torch, state, cases, denses, False, recs)
-    log(f"[bench] {args.warmup} warm-up steps done")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        run_sweep(sv, torch, state, cases, denses, True, recs)
-        if (k + 1) % 5 == 0 or k + 1 == args.steps:
-            log(f"[bench] step {k + 1}/{args.steps} done")
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    norm = state.norm2()
+        recs = []
+        for w in range(args.warmup):
+            run_sweep(sv, torch, state, cases, denses, False, recs)
+        log(f"[bench] {args.warmup} warm-up steps done")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            run_sweep(sv, torch, state, cases, denses, True, recs)
+            if (k + 1) % 5 == 0 or k + 1 == args.steps:
+                log(f"[bench] step {k + 1}/{args.steps} done")
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        norm = state.norm2()
 
-    tot, per_class, per_kernel, by_kernel, per_target_ms = summarize_sweep(recs, n, "c128", ceiling["copy_GBps"])
-    # dominant kernel: the instantiation with the largest total time
-    dk, (dt_, db, dc) = max(by_kernel.items(), key=lambda kv: kv[1][0])
-    achieved = db / dt_ / 1e9
-    roof = {"bound": "hbm", "achieved": _r(achieved, 5), "peak": PEAK_GBPS, "unit": "GB/s",
-            "frac": _r(achieved / PEAK_GBPS), "traffic": pmc_traffic(dk), "kernel": dk, "launches": dc,
-            "avg_launch_ms": _r(1e3 * dt_ / dc, 5), "algorithmic_bytes_per_launch": db / dc,
-            "frac_of_copy_kernel": _r(achieved / ceiling["copy_GBps"])}
-    if roof["traffic"] is not None:
-        roof["traffic_over_algorithmic"] = _r(roof["traffic"] / roof["algorithmic_bytes_per_launch"])
-    detail = {"sweep": {"totals": tot, "per_class": per_class, "per_kernel": per_kernel, "per_target_ms": per_target_ms,
-                        "norm_after": norm, "tuned_entries": sv.TUNED_ENTRIES}, "ceiling": ceiling}
-    head = {
-        "metric": METRIC,
-        "value": _r(tot["gates_per_s"], 6),
-        "unit": "gates/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": _r(1e3 * wall / args.steps, 6),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": f"single-gate sweep, {n} qubits complex128 (seeded Gaussian state), gate-specific "
-                               f"and general kernels", "qubits": n, "cases_per_step": len(cases),
-                   "second_qubits": [0, n // 2, n - 1]},
-        "roofline": roof,
-        "effective_GBps": _r(tot["effective_GBps"]),
-        "effective_frac_of_8TBps": _r(tot["effective_frac_of_8TBps"]),
-        "line_GBps": _r(tot["line_GBps"]),
-        "general_gates_per_s": _r(tot["general_gates_per_s"]),
-        "ceiling_GBps": {k: _r(ceiling[f"{k}_GBps"]) for k in ("copy", "read", "write")},
-        # per class: [gate-specific, general] as fractions of 8 TB/s
-        "classes_frac": {k: [_r(v["specific"]["frac_of_8TBps"], 3), _r(v["general"]["frac_of_8TBps"], 3)]
-                         for k, v in per_class.items()},
-        "partial_touch_lowest_qubit_ge3_frac": {k: _r(v["specific_lowest_qubit_ge_line_bits"]["frac_of_8TBps"], 3)
-                                                for k, v in per_class.items()
-                                                if "specific_lowest_qubit_ge_line_bits" in v},
-        "detail": os.path.relpath(args.detail, ROOT),
-    }
-    del state, t
-    torch.cuda.empty_cache()
-    if not args.skip_c64_sweep:
+        tot, per_class, per_kernel, by_kernel, per_target_ms = summarize_sweep(recs, n, "c128", ceiling["ceiling_GBps"])
+        # dominant kernel: the instantiation with the largest total time
+        dk, (dt_, db, dc) = max(by_kernel.items(), key=lambda kv: kv[1][0])
+        achieved = db / dt_ / 1e9
+        roof = {"bound": "hbm", "achieved": _r(achieved, 5), "peak": PEAK_GBPS, "unit": "GB/s",
+                "frac": _r(achieved / PEAK_GBPS), "traffic": pmc_traffic(dk), "kernel": dk, "launches": dc,
+                "avg_launch_ms": _r(1e3 * dt_ / dc, 5), "algorithmic_bytes_per_launch": db / dc,
+                "frac_of_streaming_ceiling": _r(achieved / ceiling["ceiling_GBps"])}
+        if roof["traffic"] is not None:
+            roof["traffic_over_algorithmic"] = _r(roof["traffic"] / roof["algorithmic_bytes_per_launch"])
+        detail.update({"sweep": {"totals": tot, "per_class": per_class, "per_kernel": per_kernel,
+                                 "per_target_ms": per_target_ms, "norm_after": norm, "tuned_entries": sv.TUNED_ENTRIES},
+                       "ceiling": ceiling})
+        head = {
+            "metric": METRIC,
+            "value": _r(tot["gates_per_s"], 6),
+            "unit": "gates/s",
+            "n_gpus": 1,
+            "steps": args.steps,
+            "warmup": args.warmup,
+            "ms_per_step": _r(1e3 * wall / args.steps, 6),
+            "higher_is_better": True,
+            "scaling": "weak",
+            "vs_baseline": None,
+            "dtype": "f64",
+            "data": "synthetic",
+            "config": {"workload": f"single-gate sweep, {n} qubits complex128 (seeded Gaussian state), gate-specific "
+                                   f"and general kernels", "qubits": n, "cases_per_step": len(cases),
+                       "second_qubits": [0, n // 2, n - 1]},
+            "roofline": roof,
+            "effective_GBps": _r(tot["effective_GBps"]),
+            "effective_frac_of_8TBps": _r(tot["effective_frac_of_8TBps"]),
+            "line_GBps": _r(tot["line_GBps"]),
+            "general_gates_per_s": _r(tot["general_gates_per_s"]),
+            "ceiling_GBps": {k: _r(ceiling[f"{k}_GBps"]) for k in ("inplace", "copy", "read", "write")},
+            # per class: [gate-specific, general] as fractions of 8 TB/s
+            "classes_frac": {k: [_r(v["specific"]["frac_of_8TBps"], 3), _r(v["general"]["frac_of_8TBps"], 3)]
+                             for k, v in per_class.items()},
+            "partial_touch_lowest_qubit_ge3_frac": {k: _r(v["specific_lowest_qubit_ge_line_bits"]["frac_of_8TBps"], 3)
+                                                    for k, v in per_class.items()
+                                                    if "specific_lowest_qubit_ge_line_bits" in v},
+        }
+        del state, t
+        torch.cuda.empty_cache()
+    head["detail"] = os.path.relpath(args.detail, ROOT)
+    if want("c64", args.skip_c64_sweep):
         log(f"[bench] complex64 sweep, {n} qubits, one step after one warm-up")
         t = torch.randn(1 << n, dtype=torch.complex64, device="cuda", generator=gen)
         t /= torch.linalg.vector_norm(t)
@@ -887,7 +914,7 @@ def main():
                              "classes_frac": {k: _r(v["specific"]["frac_of_8TBps"], 3) for k, v in pc64.items()}}
         del st64, t
         torch.cuda.empty_cache()
-    if not args.skip_adjoint:
+    if want("adjoint", args.skip_adjoint):
         log(f"[bench] adjoint vs parameter shift at {args.adjoint_qubits} qubits")
         a = adjoint_compare(sv, torch, args.adjoint_qubits, args.adjoint_layers, args.ps_params, args.full_param_shift)
         detail["adjoint"] = a
@@ -895,31 +922,35 @@ def main():
             "adjoint_s_c128", "param_shift_s_c128", "speedup_c128", "adjoint_s_c64", "param_shift_s_c64",
             "speedup_c64", "max_abs_err_adjoint_c128_vs_oracle_ps", "max_abs_err_adjoint_c64_vs_oracle_ps",
             "max_abs_err_adjoint_c128_vs_oracle_fd")}
-    if not args.skip_fused:
+    if want("adjoint_fused", args.skip_fused):
         log("[bench] adjoint workload on the fused engine")
         a = adjoint_fused(sv, torch, args.adjoint_qubits, args.adjoint_layers, 128)
         detail["adjoint_fused"] = a
         head["adjoint_fused"] = {k: _r(a.get(k)) for k in ("adjoint_s_c128", "adjoint_s_c64", "speedup_c128",
                                                             "speedup_c64")}
+    if want("batch", args.skip_fused):
         log("[bench] 256 mixed circuits in one graph launch")
         bt = config5(sv, torch, 3, not args.no_sequential)
         detail["batch"] = bt
         head["batch"] = {dt: {"s": _r(bt[dt]["run_s"]), "speedup_vs_sequential": _r(bt[dt].get("speedup_vs_sequential"))}
                          for dt in ("c128", "c64")}
+    if want("circuits32", args.skip_fused):
         log(f"[bench] {args.config3_qubits}-qubit circuits")
-        c3 = config3(sv, torch, args.config3_qubits, 10, 3)
+        names = tuple(x for x in args.circuits.split(",") if x)
+        c3 = config3(sv, torch, args.config3_qubits, 10, 3, names, args.engine_only)
         detail["circuits32"] = c3
-        head["circuits32_s"] = {f"{nm}_{dt}": _r(c3[f"{nm}_{dt}"]["s"]) for nm in ("hea", "qft", "universal")
-                                for dt in ("c128", "c64")}
-        head["circuits32_s"]["qft_fused_diagonal_c128"] = _r(c3["qft_single_gate_kernels_c128"]["fused_diagonal_s"])
+        head["circuits32_s"] = {f"{nm}_{dt}": _r(c3[f"{nm}_{dt}"]["s"]) for nm in names for dt in ("c128", "c64")}
+        if "qft_single_gate_kernels_c128" in c3:
+            head["circuits32_s"]["qft_fused_diagonal_c128"] = _r(c3["qft_single_gate_kernels_c128"]["fused_diagonal_s"])
+    if want("circuits20", args.skip_fused):
         log("[bench] 20-qubit circuits against the oracle's stored results")
         c20 = circuits20(sv, torch)
         detail["circuits20"] = c20
         head["circuits20_err"] = {k: [_r(v["engine_amp_err"], 2), _r(v["op_by_op_amp_err"], 2)] for k, v in c20.items()}
-    if not args.skip_dense:
+    if want("dense", args.skip_dense):
         log(f"[bench] dense 4- to 6-qubit blocks on the matrix cores at {n} qubits")
         detail["dense_block"] = dense_block(sv, torch, W, n, gen)
-    if not args.skip_cpu_baseline:
+    if want("cpu", args.skip_cpu_baseline):
         log(f"[bench] oracle CPU baseline at {args.cpu_qubits} qubits")
         cb = cpu_baseline(args.cpu_qubits, n)
         cb["host"] = host_info()
@@ -931,7 +962,7 @@ def main():
         if r.returncode == 0:
             one = json.loads(r.stdout.strip().splitlines()[-1])
             cb["single_thread_gates_per_s"] = _r(one["value"])
-        if not args.skip_adjoint:
+        if want("adjoint", args.skip_adjoint) or only:
             cps = cpu_param_shift_estimate(args.adjoint_qubits, args.adjoint_layers)
             cb["oracle_param_shift_24q_s"] = _r(cps["param_shift_s_extrapolated"])
             detail["cpu_param_shift"] = cps

@@ -453,7 +453,9 @@ sv_status sv_plan_info(int n_qubits, int dtype, int gate, const int* controls, i
  * memory with 16-byte non-temporal accesses, the yardstick the gate kernels'
  * bandwidth is compared against.  mode 0 copies src to dst (bytes read and
  * bytes written), 1 only reads src (a sum that is never stored unless it
- * hits an impossible value keeps the loads alive), 2 only writes dst (zeros).
+ * hits an impossible value keeps the loads alive), 2 only writes dst (zeros),
+ * 3 reads dst and writes it back negated in place (the access pattern of a
+ * gate that touches every amplitude; src unused).
  * block: threads per workgroup (multiple of 64 in [64, 1024]); unroll: 16-byte
  * vectors per thread per workgroup tile (1, 2, 4 or 8).  bytes must be a
  * positive multiple of 16 and the used pointers 16-byte aligned.

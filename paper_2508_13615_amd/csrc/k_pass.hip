@@ -473,7 +473,7 @@ __device__ __forceinline__ void rswap(int ka, int kb, typename Vec2<T>::type* v,
 // compiler spill scalar registers across the whole op loop.
 template <typename T, int RB, bool CHK, bool SEL, bool TWO>
 __device__ __forceinline__ void reg_apply_c(typename Vec2<T>::type* v, const FOp& op, cptr<T> cf, bool dagger,
-                                            uint32_t tl, uint32_t cmk, bool ok)
+                                            uint32_t tl, uint32_t cmk, bool ok, T pzr, T pzi)
 {
     switch (op.kind) {
     case FK_PAIRX: {
@@ -530,8 +530,8 @@ __device__ __forceinline__ void reg_apply_c(typename Vec2<T>::type* v, const FOp
         }
         break;
     }
-    case FK_PHASE: {
-        T zr = (T)cf[0], zi = (T)(dagger ? -cf[1] : cf[1]);
+    case FK_PHASE: {  // the caller supplies the phase (a chain's product, or conjugated in reverse)
+        T zr = pzr, zi = pzi;
         if constexpr (SEL) {
             zr = ok ? zr : T(1);
             zi = ok ? zi : T(0);
@@ -549,18 +549,19 @@ __device__ __forceinline__ void reg_apply_c(typename Vec2<T>::type* v, const FOp
 // Every thread runs every op (no divergent branch around the registers, which
 // would make the compiler copy all of them at each join): a lane-bit control
 // turns the op into the identity for threads where it is 0.
+// (pzr, pzi): the phase of an FK_PHASE op, supplied by the caller.
 template <typename T, int RB, bool TWO = true>
 __device__ __forceinline__ void reg_apply(typename Vec2<T>::type* v, const FOp& op, cptr<T> cf, bool dagger,
-                                          uint32_t tl)
+                                          uint32_t tl, T pzr, T pzi)
 {
     const uint32_t cmk = op.cmk, cml = op.cml;
     const bool ok = (tl & cml) == cml;
     if (cml) {
-        if (cmk) reg_apply_c<T, RB, true, true, TWO>(v, op, cf, dagger, tl, cmk, ok);
-        else reg_apply_c<T, RB, false, true, TWO>(v, op, cf, dagger, tl, 0u, ok);
+        if (cmk) reg_apply_c<T, RB, true, true, TWO>(v, op, cf, dagger, tl, cmk, ok, pzr, pzi);
+        else reg_apply_c<T, RB, false, true, TWO>(v, op, cf, dagger, tl, 0u, ok, pzr, pzi);
     } else {
-        if (cmk) reg_apply_c<T, RB, true, false, TWO>(v, op, cf, dagger, tl, cmk, true);
-        else reg_apply_c<T, RB, false, false, TWO>(v, op, cf, dagger, tl, 0u, true);
+        if (cmk) reg_apply_c<T, RB, true, false, TWO>(v, op, cf, dagger, tl, cmk, true, pzr, pzi);
+        else reg_apply_c<T, RB, false, false, TWO>(v, op, cf, dagger, tl, 0u, true, pzr, pzi);
     }
 }
 
@@ -669,6 +670,13 @@ __device__ __forceinline__ uint64_t tile_base_of(uint64_t free_mask, uint64_t ti
     return b;
 }
 
+// Whether a subset phase acts on tile `tile`: the tile must hold every bit of
+// the op's mask that lies outside the tile (packed in b; a uniform test).
+__device__ __forceinline__ bool phase_on(const FOp& op, int tile)
+{
+    return ((uint32_t)tile & (uint32_t)op.b) == (uint32_t)op.b;
+}
+
 // The next op's descriptor is fetched one op ahead, so its load overlaps the
 // current op's arithmetic.
 struct OpPre {
@@ -739,6 +747,35 @@ __device__ __forceinline__ void item_reg_fwd(const PassTables& tb, const FCirc& 
         const OpPre p = nx;
         if (o + 1 < op_end) op_fetch(tb, o + 1, nx);
         const FOp& op = p.op;
+        T pzr = T(1), pzi = T(0);
+        if (op.kind == FK_PHASE) {
+            // A chained group of subset phases on one local mask: the product of
+            // the phases of the ops that act on this tile (those whose bits
+            // outside the tile the tile holds), applied once by the group's
+            // last op.  The product is uniform over the workgroup.
+            const cptr<double> cd = as_const(tb.coef);
+            double chr = 1.0, chi = 0.0;
+            bool any = false;
+            int e = o;
+            for (;; ++e) {
+                const FOp q = e == o ? op : ld_const(as_const(tb.ops) + e);
+                if (phase_on(q, tile)) {
+                    const double zr = cd[q.coef], zi = cd[q.coef + 1];
+                    const double r = chr * zr - chi * zi;
+                    chi = chr * zi + chi * zr;
+                    chr = r;
+                    any = true;
+                }
+                if (q.kb != 1) break;
+            }
+            if (e != o) {  // skip the group's other ops; refetch the next descriptor
+                o = e;
+                if (o + 1 < op_end) op_fetch(tb, o + 1, nx);
+            }
+            if (!any) continue;
+            pzr = (T)chr;
+            pzi = (T)chi;
+        }
         if (op.kind == FK_LAYOUT) {
             if (op.a == cur) continue;
             uint32_t off[R];
@@ -752,7 +789,7 @@ __device__ __forceinline__ void item_reg_fwd(const PassTables& tb, const FCirc& 
             continue;
         }
         if (op.kind == FK_QUAD) lds_op<T, RB>(v, lds, op, coef, false, tq, active, lays + cur);
-        else reg_apply<T, RB>(v, op, coef + op.coef, false, tl);
+        else reg_apply<T, RB>(v, op, coef + op.coef, false, tl, pzr, pzi);
     }
     if (active) {
         uint64_t g[R];
@@ -820,17 +857,22 @@ __device__ __forceinline__ void item_reg_rev(const PassTables& tb, const FCirc& 
             tl = tl2;
             continue;
         }
+        // a subset phase acts on this tile only if the tile holds its bits outside it
+        const bool on = op.kind != FK_PHASE || phase_on(op, tile);
         if (op.slot >= 0) {
-            const double c = wave_sum(active ? reg_gen_inner<T, RB>(v, w, op, tl) : 0.0);
+            const double c = wave_sum(active && on ? reg_gen_inner<T, RB>(v, w, op, tl) : 0.0);
             if ((threadIdx.x & 63) == 0) wpart[nslot * (blockDim.x >> 6) + (threadIdx.x >> 6)] = c;
             ++nslot;
         }
+        if (!on) continue;
         if (op.kind == FK_SWAP || op.kind == FK_QUAD) {
             lds_op<T, RB>(v, lds, op, coef, true, tq, active, lays + cur);
             lds_op<T, RB>(w, lds, op, coef, true, tq, active, lays + cur);
         } else {
-            reg_apply<T, RB, false>(v, op, coef + op.coef, true, tl);
-            reg_apply<T, RB, false>(w, op, coef + op.coef, true, tl);
+            const T pzr = op.kind == FK_PHASE ? (T)coef[op.coef] : T(1);
+            const T pzi = op.kind == FK_PHASE ? (T)-coef[op.coef + 1] : T(0);
+            reg_apply<T, RB, false>(v, op, coef + op.coef, true, tl, pzr, pzi);
+            reg_apply<T, RB, false>(w, op, coef + op.coef, true, tl, pzr, pzi);
         }
     }
     __syncthreads();  // every wave's partials are in LDS
@@ -919,7 +961,9 @@ __device__ __forceinline__ void item_lds(const PassTables& tb, const FCirc& cc, 
         }
         __syncthreads();
         for (int o = ps.op_begin; o < ps.op_end; ++o) {
-            lds_apply<T>(tileA, tb.ops[o], tb.coef, false, tq);
+            const FOp op = tb.ops[o];
+            if (op.kind == FK_PHASE && !phase_on(op, tile)) continue;  // uniform: not on this tile
+            lds_apply<T>(tileA, op, tb.coef, false, tq);
             __syncthreads();
         }
         for (uint32_t l = threadIdx.x; l < na; l += blockDim.x)
@@ -935,12 +979,14 @@ __device__ __forceinline__ void item_lds(const PassTables& tb, const FCirc& cc, 
     int nslot = 0;
     for (int o = ps.rop_end - 1; o >= ps.rop_begin; --o) {
         const FOp op = tb.ops[o];
+        const bool on = op.kind != FK_PHASE || phase_on(op, tile);  // uniform
         if (op.slot >= 0) {
-            const double c = wave_sum(lds_gen_inner<T>(tileA, tileB, op, tq));
+            const double c = on ? wave_sum(lds_gen_inner<T>(tileA, tileB, op, tq)) : 0.0;
             if ((threadIdx.x & 63) == 0) wpart[nslot * (blockDim.x >> 6) + (threadIdx.x >> 6)] = c;
             ++nslot;
             __syncthreads();  // every read of the tiles precedes the un-apply below
         }
+        if (!on) continue;
         lds_apply<T>(tileA, op, tb.coef, true, tq);
         lds_apply<T>(tileB, op, tb.coef, true, tq);
         __syncthreads();

@@ -1,5 +1,6 @@
 // k_stream.hip -- the measured HBM ceiling the gate kernels are compared
-// against: plain streaming kernels (copy, read-only, write-only) with 16-byte
+// against: plain streaming kernels (copy, read-only, write-only, in-place
+// read-and-write) with 16-byte
 // non-temporal accesses, in the same work layout as the gate kernels (each
 // workgroup owns one tile of block * unroll vectors, thread i handles
 // vectors i, i + block, ...: every load instruction of a wavefront covers
@@ -19,6 +20,8 @@ k_stream(const double2* __restrict__ src, double2* __restrict__ dst, uint64_t n,
     const uint64_t per_block = (uint64_t)blockDim.x * U;
     const uint64_t stride = (uint64_t)gridDim.x * per_block;
     double acc = 0.0;
+    // the in-place form reads and writes dst, like a gate on its state
+    const double2* __restrict__ in = MODE == 3 ? (const double2*)dst : src;
     for (uint64_t i0 = (uint64_t)blockIdx.x * per_block + threadIdx.x; i0 < n + threadIdx.x; i0 += stride) {
         double2 v[U];
         if constexpr (MODE != 2) {
@@ -26,8 +29,8 @@ k_stream(const double2* __restrict__ src, double2* __restrict__ dst, uint64_t n,
             for (int j = 0; j < U; ++j) {
                 const uint64_t i = i0 + (uint64_t)j * blockDim.x;
                 if (i < n) {
-                    v[j].x = __builtin_nontemporal_load(&src[i].x);
-                    v[j].y = __builtin_nontemporal_load(&src[i].y);
+                    v[j].x = __builtin_nontemporal_load(&in[i].x);
+                    v[j].y = __builtin_nontemporal_load(&in[i].y);
                 }
             }
         }
@@ -40,6 +43,10 @@ k_stream(const double2* __restrict__ src, double2* __restrict__ dst, uint64_t n,
                     __builtin_nontemporal_store(v[j].y, &dst[i].y);
                 } else if constexpr (MODE == 1) {
                     acc += v[j].x + v[j].y;
+                } else if constexpr (MODE == 3) {
+                    // negated, so the store cannot be dropped as a no-op
+                    __builtin_nontemporal_store(-v[j].x, &dst[i].x);
+                    __builtin_nontemporal_store(-v[j].y, &dst[i].y);
                 } else {
                     __builtin_nontemporal_store(0.0, &dst[i].x);
                     __builtin_nontemporal_store(0.0, &dst[i].y);
@@ -80,8 +87,10 @@ hipError_t launch_stream(int mode, void* dst, const void* src, uint64_t n16, int
         SV_STREAM_GO(0)
     } else if (mode == 1) {
         SV_STREAM_GO(1)
-    } else {
+    } else if (mode == 2) {
         SV_STREAM_GO(2)
+    } else {
+        SV_STREAM_GO(3)
     }
 #undef SV_STREAM_GO
     return hipGetLastError();
@@ -93,12 +102,13 @@ using namespace svk;
 
 sv_status sv_stream_bench(int mode, void* dst, const void* src, size_t bytes, int block, int unroll, void* stream)
 {
-    if (mode < 0 || mode > 2) return set_error(SV_ERR_ARG, "mode must be 0 (copy), 1 (read) or 2 (write)");
+    if (mode < 0 || mode > 3) return set_error(SV_ERR_ARG, "mode must be 0 (copy), 1 (read), 2 (write) or 3 (in place)");
     if (bytes == 0 || bytes % 16) return set_error(SV_ERR_ARG, "bytes must be a positive multiple of 16");
     if (block < 64 || block > 1024 || (block & 63)) return set_error(SV_ERR_ARG, "block must be a multiple of 64 in [64, 1024]");
     if (unroll != 1 && unroll != 2 && unroll != 4 && unroll != 8) return set_error(SV_ERR_ARG, "unroll must be 1, 2, 4 or 8");
-    if (mode != 2 && (!src || ((uintptr_t)src) % 16)) return set_error(SV_ERR_ARG, "src must be 16-byte aligned");
-    if (mode != 1 && (!dst || ((uintptr_t)dst) % 16)) return set_error(SV_ERR_ARG, "dst must be 16-byte aligned");
+    const bool reads_src = mode == 0 || mode == 1, writes_dst = mode != 1;
+    if (reads_src && (!src || ((uintptr_t)src) % 16)) return set_error(SV_ERR_ARG, "src must be 16-byte aligned");
+    if (writes_dst && (!dst || ((uintptr_t)dst) % 16)) return set_error(SV_ERR_ARG, "dst must be 16-byte aligned");
     // the read-only form may store one vector into dst when given one; without
     // a dst it stores nothing
     const hipError_t e = launch_stream(mode, dst, src, bytes / 16, block, unroll, (hipStream_t)stream);

@@ -9,7 +9,12 @@
 // lines) and greedily takes ready ops in program order while the union of
 // their qubits stays within tq qubits; it is then padded with the lowest
 // unused qubits to exactly tq.  Every op of a pass acts inside one tile, so
-// one HBM round trip of the state serves all of them.
+// one HBM round trip of the state serves all of them.  A subset phase (Z, S,
+// T, PHASE, any controls) is diagonal in every one of its qubits: its qubits
+// outside the tile are fixed over a tile and only decide whether it acts
+// there, so it joins a pass as soon as one of its qubits is in the tile (or
+// its target can still be added), without growing the tile further.  The
+// QFT's controlled phases then ride along with the Hadamard passes.
 //
 // Register tiling.  Inside a pass each thread holds 2^rb amplitudes of the
 // tile.  The ops of the pass are grouped again (same commutation rule) into
@@ -49,6 +54,9 @@ struct BOp {
 int popc(uint64_t x) { return __builtin_popcountll(x); }
 
 int targets_of(int gate) { return gate == SV_SWAP || gate == SV_U4 ? 2 : 1; }
+
+// Subset phases: a phase on the amplitudes holding every qubit of the op.
+bool subset_phase_gate(int gate) { return gate == SV_Z || gate == SV_S || gate == SV_T || gate == SV_PHASE; }
 
 bool is_rotation(int gate) { return gate == SV_RX || gate == SV_RY || gate == SV_RZ || gate == SV_PHASE; }
 
@@ -108,7 +116,9 @@ void schedule(int n, int tq, int cb, const std::vector<BOp>& ops, std::vector<st
                     ready = qops[q][front[q]] == i;
                 }
                 if (!ready) continue;
-                const uint64_t np = P | o.qmask();
+                uint64_t np = P | o.qmask();
+                if (subset_phase_gate(o.gate))  // joins on one qubit in the tile (its target, if none is)
+                    np = (o.qmask() & P) ? P : (P | (1ull << o.q[o.nc]));
                 if (popc(np) > tq) continue;
                 if (o.pidx >= 0 && nparam >= kMaxPassSlots) continue;
                 done[i] = 1;
@@ -256,7 +266,8 @@ void plan_layouts(std::vector<FOp>& pass_ops, int tq, int rb, int cb, const int3
             FOp f = pass_ops[i];
             const uint32_t S = r.first;
             f.ka = (int8_t)(((S >> f.a) & 1u) ? reg_index(S, f.a) : -1);
-            f.kb = (int8_t)(((S >> f.b) & 1u) && (f.kind == FK_SWAP || f.kind == FK_QUAD) ? reg_index(S, f.b) : -1);
+            const bool two = f.kind == FK_SWAP || f.kind == FK_QUAD;
+            f.kb = (int8_t)(two && ((S >> f.b) & 1u) ? reg_index(S, f.b) : -1);
             uint32_t cmk = 0;
             for (int q = 0; q < 32; ++q)
                 if (((f.cm & S) >> q) & 1u) cmk |= 1u << reg_index(S, q);
@@ -326,7 +337,8 @@ std::vector<FOp> fuse_forward(const std::vector<FOp>& ops, const std::vector<int
     for (int& x : last) x = -1;
     for (size_t i = 0; i < ops.size(); ++i) {
         const FOp& f = ops[i];
-        const bool fus = one_target_kind(f.kind);
+        // a subset phase with qubits outside the tile stays on its own (it may be chained)
+        const bool fus = one_target_kind(f.kind) && !(f.kind == FK_PHASE && f.b != 0);
         const uint32_t ctrl = f.kind == FK_PHASE ? (f.cm & ~(1u << f.a)) : f.cm;
         uint32_t touch = f.cm | (1u << f.a);
         if (f.kind == FK_SWAP || f.kind == FK_QUAD) touch |= 1u << f.b;
@@ -487,6 +499,27 @@ hipError_t enqueue_run(sv_batch b)
     return e;
 }
 
+// Consecutive subset phases commute.  Within each maximal run of them in a
+// planned forward list (no layout change inside, so one local mask means one
+// register / lane split), order them by local mask and chain each one to the
+// next of the same mask: the kernel multiplies a group's phases (those whose
+// out-of-tile bits the tile holds) into one and applies it once.
+void mark_phase_chains(std::vector<FOp>& ops)
+{
+    size_t i = 0;
+    while (i < ops.size()) {
+        if (ops[i].kind != FK_PHASE) {
+            ++i;
+            continue;
+        }
+        size_t j = i;
+        while (j < ops.size() && ops[j].kind == FK_PHASE) ++j;
+        std::stable_sort(ops.begin() + i, ops.begin() + j, [](const FOp& x, const FOp& y) { return x.cm < y.cm; });
+        for (size_t k = i; k < j; ++k) ops[k].kb = (k + 1 < j && ops[k + 1].cm == ops[k].cm) ? 1 : 0;
+        i = j;
+    }
+}
+
 }  // namespace
 
 static sv_status hip_fail(hipError_t e, const char* what)
@@ -630,6 +663,7 @@ static sv_status compile_batch(const sv_batch_circuit* circuits, int n_circuits,
             memset(&fp, 0, sizeof fp);
             int local[64];
             int k = 0;
+            for (int q = 0; q < 64; ++q) local[q] = -1;
             for (int q = 0; q < n; ++q)
                 if (pq[p] & (1ull << q)) {
                     local[q] = k;
@@ -644,11 +678,29 @@ static sv_status compile_batch(const sv_batch_circuit* circuits, int n_circuits,
                 memset(&f, 0, sizeof f);
                 f.slot = slot_of[i];
                 f.gen = (int8_t)(o.gate == SV_RX ? GEN_X : (o.gate == SV_RY ? GEN_Y : (o.gate == SV_RZ ? GEN_Z : GEN_P1)));
+                // controls (and a subset phase's target) inside the tile -> cm,
+                // a subset phase's qubits outside it -> gm
+                const bool sp = subset_phase_gate(o.gate);
                 uint32_t cm = 0;
-                for (int j = 0; j < o.nc; ++j) cm |= 1u << local[o.q[j]];
+                uint64_t gm = 0;
+                for (int j = 0; j < o.nc + (sp ? 1 : 0); ++j) {
+                    const int q = o.q[j];
+                    if (local[q] >= 0) cm |= 1u << local[q];
+                    else gm |= 1ull << q;
+                }
+                const int tl0 = local[o.q[o.nc]];
+                if ((!sp && (gm || tl0 < 0 || (o.nt > 1 && local[o.q[o.nc + 1]] < 0))) || (sp && !cm))
+                    return set_error(SV_ERR_UNSUPPORTED, "internal: an op of a pass lies outside its tile");
                 f.cm = cm;
-                f.a = local[o.q[o.nc]];
+                // a subset phase is symmetric in its qubits: any one inside the tile serves as its target
+                f.a = tl0 >= 0 ? tl0 : __builtin_ctz(cm);
                 f.b = o.nt > 1 ? local[o.q[o.nc + 1]] : 0;
+                if (sp) {  // b: the bits outside the tile, packed as in a tile index
+                    uint32_t packed = 0;
+                    for (int q = 0; q < n; ++q)
+                        if ((gm >> q) & 1ull) packed |= 1u << popc(fp.free_mask & ((1ull << q) - 1ull));
+                    f.b = (int32_t)packed;
+                }
                 FCoefSpec cs;
                 memset(&cs, 0, sizeof cs);
                 cs.gate = o.gate;
@@ -665,10 +717,10 @@ static sv_status compile_batch(const sv_batch_circuit* circuits, int n_circuits,
                 case SV_RX: f.kind = FK_PAIR; coef_total += 8; break;
                 case SV_RY: f.kind = FK_PAIRR; coef_total += 8; break;
                 case SV_RZ: f.kind = FK_DIAG; coef_total += 4; break;
-                case SV_Z: { f.kind = FK_PHASE; f.cm |= 1u << f.a; cs.fixed[0] = -1; cs.nfixed = 2; coef_total += 2; break; }
-                case SV_S: { f.kind = FK_PHASE; f.cm |= 1u << f.a; cs.fixed[1] = 1; cs.nfixed = 2; coef_total += 2; break; }
-                case SV_T: { f.kind = FK_PHASE; f.cm |= 1u << f.a; cs.fixed[0] = cos(M_PI / 4); cs.fixed[1] = sin(M_PI / 4); cs.nfixed = 2; coef_total += 2; break; }
-                case SV_PHASE: f.kind = FK_PHASE; f.cm |= 1u << f.a; coef_total += 2; break;
+                case SV_Z: { f.kind = FK_PHASE; cs.fixed[0] = -1; cs.nfixed = 2; coef_total += 2; break; }
+                case SV_S: { f.kind = FK_PHASE; cs.fixed[1] = 1; cs.nfixed = 2; coef_total += 2; break; }
+                case SV_T: { f.kind = FK_PHASE; cs.fixed[0] = cos(M_PI / 4); cs.fixed[1] = sin(M_PI / 4); cs.nfixed = 2; coef_total += 2; break; }
+                case SV_PHASE: f.kind = FK_PHASE; coef_total += 2; break;
                 case SV_SWAP: f.kind = FK_SWAP; break;
                 default: { f.kind = FK_QUAD; memcpy(cs.fixed, o.mat.data(), 32 * sizeof(double)); cs.nfixed = 32; coef_total += 32; break; }
                 }
@@ -678,7 +730,10 @@ static sv_status compile_batch(const sv_batch_circuit* circuits, int n_circuits,
             }
             std::vector<FOp> fwd_ops = fuse_forward(pass_ops, pass_src, ops, n_params, cspec, cfac, coef_total);
             const bool fused = fwd_ops.size() != pass_ops.size();
-            if (fc.reg) plan_layouts(fwd_ops, tq, reg_bits, cb, fp.q, lays, fp.lay_begin, fp.lay_end);
+            if (fc.reg) {
+                plan_layouts(fwd_ops, tq, reg_bits, cb, fp.q, lays, fp.lay_begin, fp.lay_end);
+                mark_phase_chains(fwd_ops);
+            }
             fp.op_begin = (int)fops.size();
             fops.insert(fops.end(), fwd_ops.begin(), fwd_ops.end());
             fp.op_end = (int)fops.size();

@@ -28,6 +28,18 @@ enum FusedKind : int32_t {
 // One op of a pass, in tile-local bit positions.  FK_LAYOUT (register-tiled
 // passes only) re-distributes the tile: a = index of the layout that holds
 // from here on, b = the layout that held before.
+//
+// A subset phase (FK_PHASE: Z, S, T, PHASE with any controls) multiplies the
+// amplitudes holding every bit of its mask, which makes it diagonal in all of
+// them: it need not have its qubits in the tile.  The mask bits inside the
+// tile are local bits in cm (a is one of them); the bits outside it are
+// constant over a tile, so the op acts on a tile only if the tile holds all of
+// them.  A tile's index is its bits outside the tile, packed (bit i = the i-th
+// lowest qubit outside the tile), so for FK_PHASE b holds the op's bits
+// outside the tile in that packed form (0: none) and the test is
+// (tile & b) == b.  In forward lists kb = 1 chains the op to the next one, a
+// subset phase on the same local mask whose phase the kernel multiplies in
+// before applying the group's product once (reverse sweeps ignore kb).
 struct FOp {
     int32_t kind;
     int32_t a, b;   // local target bits (b: second target of SWAP / QUAD)

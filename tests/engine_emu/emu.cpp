@@ -401,8 +401,48 @@ static void run_emu(Emu& E, const std::vector<double>& params)
                             for (int k = 0; k < tq; ++k) if ((l >> k) & 1) g |= 1ull << ps.q[k];
                             v[t * R + j] = p == 0 ? cd(g == 0 ? 1 : 0, 0) : psi[g];
                         }
+                    cd chain_acc = 1.0;
+                    bool ch_any = false;
+                    const uint64_t tile_bits = ~ps.free_mask & ((1ull << cc.n) - 1);
                     for (int o = ps.op_begin; o < ps.op_end; ++o) {
                         const FOp& op = H.fops[o];
+                        if (op.kind == FK_PHASE) {
+                            // subset phase: out-of-tile bits gate it per tile; chains multiply
+                            // b: the op's qubits outside the tile, packed as in a tile index
+                            uint64_t gm = 0;
+                            {
+                                int rank = 0;
+                                for (int q = 0; q < cc.n; ++q)
+                                    if ((ps.free_mask >> q) & 1ull) {
+                                        if (((uint32_t)op.b >> rank) & 1u) gm |= 1ull << q;
+                                        ++rank;
+                                    }
+                            }
+                            CHECK(((uint64_t)(uint32_t)op.b >> (cc.n - tq)) == 0, "packed mask beyond the tile index");
+                            CHECK((gm & tile_bits) == 0, "gm holds tile bits");
+                            // the kernel tests the packed mask against the tile index
+                            CHECK((((uint32_t)tile & (uint32_t)op.b) == (uint32_t)op.b) == ((tb & gm) == gm),
+                                  "packed test disagrees with the base-index test");
+                            CHECK(op.cm != 0 && ((op.cm >> op.a) & 1u), "phase without an in-tile bit");
+                            CHECK(op.kb == 0 || op.kb == 1, "chain flag %d", op.kb);
+                            if ((tb & gm) == gm) {
+                                chain_acc *= cd(E.coef[op.coef], E.coef[op.coef + 1]);
+                                ch_any = true;
+                            }
+                            if (op.kb == 1) {
+                                CHECK(o + 1 < ps.op_end && H.fops[o + 1].kind == FK_PHASE && H.fops[o + 1].cm == op.cm,
+                                      "chain not followed by a phase on the same mask");
+                                continue;
+                            }
+                            if (ch_any) {
+                                const double zz[2] = {chain_acc.real(), chain_acc.imag()};
+                                for (int t = 0; t < nthr; ++t)
+                                    reg_apply_h(&v[t * R], rb, op, zz, false, f.tl[t], f.off, H.lays[cur], tq);
+                            }
+                            chain_acc = 1.0;
+                            ch_any = false;
+                            continue;
+                        }
                         if (op.kind == FK_LAYOUT) {
                             if (op.a == cur) continue;
                             CHECK(op.b == cur, "marker from %d but current %d", op.b, cur);
@@ -485,12 +525,15 @@ static void run_emu(Emu& E, const std::vector<double>& params)
                         f = f2;
                         continue;
                     }
+                    const bool on = op.kind != FK_PHASE || ((uint32_t)tile & (uint32_t)op.b) == (uint32_t)op.b;
                     if (op.slot >= 0) {
                         double acc = 0;
-                        for (int t = 0; t < nthr; ++t)
-                            acc += gen_inner_h(&v[t * R], &w[t * R], rb, op, f.tl[t], f.off, H.lays[cur], tq);
+                        if (on)
+                            for (int t = 0; t < nthr; ++t)
+                                acc += gen_inner_h(&v[t * R], &w[t * R], rb, op, f.tl[t], f.off, H.lays[cur], tq);
                         E.gpart[cc.g_part_begin + (int64_t)op.slot * cc.n_tiles + tile] = acc;
                     }
+                    if (!on) continue;
                     if (op.kind == FK_QUAD || op.kind == FK_SWAP) {
                         quad_sweep_h(v, nthr, R, f, tq, op, E.coef.data() + op.coef, true);
                         quad_sweep_h(w, nthr, R, f, tq, op, E.coef.data() + op.coef, true);
@@ -617,6 +660,69 @@ static Circ hea(int n, int L)
     return C;
 }
 
+// QFT (Hadamards and controlled phases, no swaps), with every fourth phase
+// angle a parameter so the reverse sweep's subset-phase gradients are covered.
+static Circ qft(int n)
+{
+    Circ C;
+    C.n = n;
+    C.n_params = 0;
+    C.obs = 2;
+    int np = 0;
+    for (int j = n - 1; j >= 0; --j) {
+        C.ops.push_back(mk(SV_H, {}, {j}));
+        for (int c = j - 1; c >= 0; --c) {
+            if ((c + j) % 4 == 0) C.ops.push_back(mk(SV_PHASE, {c}, {j}, np++));
+            else C.ops.push_back(mk(SV_PHASE, {c}, {j}, -1, M_PI / (double)(1 << std::min(j - c, 30))));
+        }
+    }
+    C.n_params = np;
+    return C;
+}
+
+// Mostly subset phases (Z, S, T, PHASE with 0..3 controls) between a few
+// Hadamards and CNOTs: phases whose qubits fall outside the tile.
+static Circ phase_heavy(std::mt19937_64& rng, int n, int n_ops, int n_params)
+{
+    Circ C;
+    C.n = n;
+    C.n_params = n_params;
+    C.obs = 1 + (rng() & 1);
+    std::vector<int> qs;
+    auto pick = [&](int k) {
+        qs.clear();
+        while ((int)qs.size() < k) {
+            int q = rng() % n;
+            if (std::find(qs.begin(), qs.end(), q) == qs.end()) qs.push_back(q);
+        }
+    };
+    for (int q = 0; q < n; ++q) C.ops.push_back(mk(SV_H, {}, {q}));
+    const int ph[] = {SV_Z, SV_S, SV_T, SV_PHASE, SV_PHASE};
+    for (int i = 0; i < n_ops; ++i) {
+        const int r = rng() % 10;
+        if (r == 0) {
+            pick(1);
+            C.ops.push_back(mk(SV_H, {}, {qs[0]}));
+        } else if (r == 1) {
+            pick(2);
+            C.ops.push_back(mk(SV_X, {qs[0]}, {qs[1]}));
+        } else {
+            const int g = ph[rng() % 5];
+            const int nc = std::min((int)(rng() % 4), n - 1);
+            pick(nc + 1);
+            std::vector<int> ctl(qs.begin(), qs.begin() + nc);
+            int pidx = -1;
+            double val = 0;
+            if (g == SV_PHASE) {
+                if (rng() % 2 && n_params > 0) pidx = rng() % n_params;
+                else val = (rng() % 1000) * 0.00628;
+            }
+            C.ops.push_back(mk(g, ctl, {qs[nc]}, pidx, val));
+        }
+    }
+    return C;
+}
+
 static void test(const std::vector<Circ>& cs, int dtype, int tile, int apt, int with_grad, const char* name,
                  std::mt19937_64& rng)
 {
@@ -703,6 +809,11 @@ int main(int argc, char** argv)
                 }
                 snprintf(nm, sizeof nm, "random 13q default tile %s apt%d grad%d", dt == SV_C128 ? "c128" : "c64", apt, wg);
                 test({random_circ(rng, 13, 200, 12), random_circ(rng, 14, 150, 9)}, dt, 0, apt, wg, nm, rng);
+                for (int tile : {5, 7, 0}) {
+                    snprintf(nm, sizeof nm, "qft 11q + phases 12q tile%d %s apt%d grad%d", tile,
+                             dt == SV_C128 ? "c128" : "c64", apt, wg);
+                    test({qft(11), phase_heavy(rng, 12, 120, 6)}, dt, tile, apt, wg, nm, rng);
+                }
             }
     printf("%s (%d errors)\n", errors ? "FAILED" : "all ok", errors);
     return errors ? 1 : 0;

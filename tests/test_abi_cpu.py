@@ -189,7 +189,8 @@ def test_device_output_expval_validation():
 
 def test_stream_bench_validation():
     f = ctypes.c_void_p(FAKE)
-    assert lib.sv_stream_bench(3, f, f, 1024, 256, 4, None) == ARG  # mode
+    assert lib.sv_stream_bench(4, f, f, 1024, 256, 4, None) == ARG  # mode
+    assert lib.sv_stream_bench(3, None, f, 1024, 256, 4, None) == ARG  # in place needs dst
     assert lib.sv_stream_bench(0, f, f, 0, 256, 4, None) == ARG  # empty
     assert lib.sv_stream_bench(0, f, f, 1000, 256, 4, None) == ARG  # not a multiple of 16
     assert lib.sv_stream_bench(0, f, f, 1024, 100, 4, None) == ARG  # block
@@ -197,6 +198,7 @@ def test_stream_bench_validation():
     assert lib.sv_stream_bench(0, ctypes.c_void_p(FAKE + 8), f, 1024, 256, 4, None) == ARG  # alignment
     assert lib.sv_stream_bench(1, None, None, 1024, 256, 4, None) == ARG  # read needs src
     assert lib.sv_stream_bench(2, None, f, 1024, 256, 4, None) == ARG  # write needs dst
+    assert lib.sv_stream_bench(3, ctypes.c_void_p(FAKE + 8), None, 1024, 256, 4, None) == ARG  # in place: dst aligned
 
 
 def test_circuit_create_validation_is_host_side():

@@ -126,8 +126,9 @@ def test_expval_pauli_dev_is_ordered_between_gates():
 
 
 def test_stream_bench_kernels_move_exact_bytes():
-    # copy reproduces the source bit for bit, write leaves zeros, read
-    # changes nothing; a ragged length (not a multiple of a workgroup tile)
+    # copy reproduces the source bit for bit, the in-place form negates its
+    # buffer, write leaves zeros, read changes nothing; a ragged length (not a
+    # multiple of a workgroup tile)
     for nvec in (1 << 20, 1000003, 37):
         src = torch.randn(2 * nvec, dtype=torch.float64, device="cuda")
         keep = src.clone()
@@ -137,6 +138,9 @@ def test_stream_bench_kernels_move_exact_bytes():
             sv.stream_bench(0, dst, src, nvec * 16, block, unroll)
             torch.cuda.synchronize()
             assert torch.equal(dst, src)
+            sv.stream_bench(3, dst, None, nvec * 16, block, unroll)
+            torch.cuda.synchronize()
+            assert torch.equal(dst, -src)
             sv.stream_bench(1, None, src, nvec * 16, block, unroll)
             sv.stream_bench(2, dst, None, nvec * 16, block, unroll)
             torch.cuda.synchronize()
