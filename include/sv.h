@@ -410,8 +410,9 @@ sv_status sv_batch_free(sv_batch b);
  * the element size: 0 (< 64 B), 1 (< 1 KiB), 2 (larger).  block is a
  * multiple of 64 in [64, 1024]; unroll is 1, 2 or 4: groups per thread,
  * and for class 6 the chunk elements a thread of a 3-qubit gate loads (and
- * stores) per round trip between HBM and LDS (1- and 2-qubit gates move
- * one); nt = 1 makes the kernel's loads and stores non-temporal.  The table is
+ * stores) per round trip between HBM and LDS (2-qubit gates: two in
+ * complex64 when unroll >= 2, else one; sv_plan_info reports the depth a
+ * launch uses); nt = 1 makes the kernel's loads and stores non-temporal.  The table is
  * process-wide; set it from one thread before launching work.
  * Errors: SV_ERR_ARG for a bad key or shape.
  * ------------------------------------------------------------------------ */

@@ -586,9 +586,9 @@ static hipError_t launch_lds_k(typename Vec2<T>::type* p, const GroupSpec& tiles
     const dim3 grid((unsigned)grid_cap(tiles.n_groups, lc.block)), blk(lc.block);
     const size_t lds = sizeof(typename Vec2<T>::type) << (kLdsChunkBits + ls.h);
     if (op == 1 && K != 2) return hipErrorInvalidValue;
-    // the launch shape's unroll is the number of lines a thread stages per
-    // round trip in the 3-qubit form; the 1- and 2-qubit forms stage one
-    // (measured faster at 30 qubits: 5.62 against 5.76 ms per 2-qubit gate)
+    // lines a thread stages per round trip: lds_stage_depth (the 3-qubit form
+    // takes the launch shape's unroll; complex128 2-qubit forms stage one,
+    // measured faster at 30 qubits: 5.62 against 5.76 ms per gate)
     auto go = [&](auto nt_tag, auto b_tag) {
         constexpr bool NTv = decltype(nt_tag)::value;
         constexpr int Bv = decltype(b_tag)::value;
@@ -601,11 +601,14 @@ static hipError_t launch_lds_k(typename Vec2<T>::type* p, const GroupSpec& tiles
     using I1 = std::integral_constant<int, 1>;
     using I2 = std::integral_constant<int, 2>;
     using I4 = std::integral_constant<int, 4>;
-    const int b = lds_stage_depth(K, lc.unroll);
+    const int b = lds_stage_depth(K, lc.unroll, (int)sizeof(typename Vec2<T>::type));
     if (lc.nt) {
         if constexpr (K == 3) {
             if (b == 4) go(std::true_type{}, I4{});
             else if (b == 2) go(std::true_type{}, I2{});
+            else go(std::true_type{}, I1{});
+        } else if constexpr (K == 2 && sizeof(T) == 4) {
+            if (b == 2) go(std::true_type{}, I2{});
             else go(std::true_type{}, I1{});
         } else {
             go(std::true_type{}, I1{});
@@ -614,6 +617,9 @@ static hipError_t launch_lds_k(typename Vec2<T>::type* p, const GroupSpec& tiles
         if constexpr (K == 3) {
             if (b == 4) go(std::false_type{}, I4{});
             else if (b == 2) go(std::false_type{}, I2{});
+            else go(std::false_type{}, I1{});
+        } else if constexpr (K == 2 && sizeof(T) == 4) {
+            if (b == 2) go(std::false_type{}, I2{});
             else go(std::false_type{}, I1{});
         } else {
             go(std::false_type{}, I1{});

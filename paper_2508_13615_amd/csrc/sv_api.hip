@@ -1971,7 +1971,7 @@ sv_status sv_plan_info(int n_qubits, int dtype, int gate, const int* controls, i
     *tier = tier_of(dtype, low);
     *op = opv;
     *block = l.block;
-    *unroll = kc == KC_LDS ? lds_stage_depth(opv >> 4, l.unroll) : l.unroll;
+    *unroll = kc == KC_LDS ? lds_stage_depth(opv >> 4, l.unroll, (int)elem_bytes(dtype)) : l.unroll;
     *nt_flag = l.nt;
     return SV_OK;
 }

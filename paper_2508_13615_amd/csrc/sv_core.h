@@ -88,8 +88,16 @@ __device__ __forceinline__ uint64_t group_base(uint64_t g, const GroupSpec& gs)
 // the stage and streams the chunks back.
 constexpr int kLdsChunkBits = 8;
 // Lines a thread of the LDS-staged kernel moves per round trip between HBM
-// and LDS for a k-qubit gate under a launch shape's unroll.
-inline int lds_stage_depth(int k, int unroll) { return k == 3 ? unroll : 1; }
+// and LDS for a k-qubit gate under a launch shape's unroll: the 3-qubit form
+// stages `unroll`; the 2-qubit forms stage two in complex64 (8-byte
+// amplitudes: a thread's single line leaves too few bytes in flight) and one
+// in complex128, where more registers per thread cost more waves than the
+// extra line brings.
+inline int lds_stage_depth(int k, int unroll, int elem_bytes)
+{
+    if (k == 3) return unroll;
+    return k == 2 && elem_bytes == 8 && unroll >= 2 ? 2 : 1;
+}
 struct LdsSpec {
     int32_t k;        // gate qubits (1..3)
     int32_t h;        // gate qubits >= kLdsChunkBits
