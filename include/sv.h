@@ -419,6 +419,20 @@ sv_status sv_batch_free(sv_batch b);
 sv_status sv_tune_set(int kernel_class, int dtype, int tier, int block, int unroll, int nt);
 sv_status sv_tune_get(int kernel_class, int dtype, int tier, int* block, int* unroll, int* nt);
 
+/* Order in which a gate launch's workgroups walk the state.  The hardware
+ * deals consecutive workgroups to the 8 XCDs in turn; order 0 walks the
+ * groups in launch order, order 1 gives each XCD one contiguous eighth of
+ * them.  -1 (the default) picks per launch: order 1 for complex128 gates
+ * with a member offset (a target bit) of 32..128 MiB, which run slower in
+ * launch order (measured on MI355X), else order 0.  The environment variable
+ * SV_BLOCK_ORDER=0 or 1, read at the first launch, forces an order until
+ * this call changes it.  Results do not depend on the order: every group is
+ * still touched once with the same arithmetic.  Process-wide; set it from
+ * one thread before launching work.
+ * Errors: SV_ERR_ARG for an order outside {-1, 0, 1}. */
+sv_status sv_set_block_order(int order);
+sv_status sv_get_block_order(int* order);
+
 /* Engine tile shape (written by the autotuner, read by sv_batch_create and
  * sv_batch_plan where sv_batch_opts leaves tile_qubits or amps_per_thread at
  * 0), one per dtype and per stage mix: with_grad = 0 for forward-only

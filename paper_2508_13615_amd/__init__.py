@@ -24,7 +24,7 @@ from ._lib import (GATES, OP_MAX_QUBITS, SV_C64, SV_C128, SvBatchCircuit, SvBatc
                    check, lib)
 
 __all__ = ["State", "Circuit", "Batch", "Observable", "AdjointExpval", "SvError", "lib", "tune_set", "tune_get",
-           "plan_info", "batch_plan", "sv_version", "stream_bench"]
+           "plan_info", "batch_plan", "sv_version", "stream_bench", "set_block_order", "get_block_order"]
 
 _TORCH_DT = {"c128": torch.complex128, "c64": torch.complex64}
 _SV_DT = {"c128": SV_C128, "c64": SV_C64}
@@ -59,6 +59,18 @@ def tune_get(kernel_class: int, dtype: str, tier: int) -> Tuple[int, int, int]:
     b, u, t = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
     check(lib.sv_tune_get(kernel_class, _SV_DT[dtype], tier, ctypes.byref(b), ctypes.byref(u), ctypes.byref(t)))
     return b.value, u.value, t.value
+
+
+def set_block_order(order: int) -> None:
+    """Workgroup walk order of the gate kernels: -1 picks per launch, 0 is
+    launch order, 1 gives each XCD a contiguous eighth of the state."""
+    check(lib.sv_set_block_order(int(order)))
+
+
+def get_block_order() -> int:
+    o = ctypes.c_int()
+    check(lib.sv_get_block_order(ctypes.byref(o)))
+    return o.value
 
 
 def tune_engine_set(dtype: str, with_grad: bool, tile_qubits: int, amps_per_thread: int) -> None:

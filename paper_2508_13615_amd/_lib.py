@@ -30,8 +30,8 @@ EXPORTS = [
     "sv_circuit_apply_fused", "sv_circuit_apply_blocks", "sv_block_plan", "sv_adjoint_grad",
     "sv_batch_create", "sv_batch_plan", "sv_batch_run", "sv_batch_info", "sv_batch_state", "sv_batch_copy_state",
     "sv_batch_free", "sv_batch_set_stream",
-    "sv_tune_set", "sv_tune_get", "sv_tune_engine_set", "sv_tune_engine_get", "sv_plan_info", "sv_last_error",
-    "sv_status_string", "sv_version", "sv_stream_bench",
+    "sv_tune_set", "sv_tune_get", "sv_tune_engine_set", "sv_tune_engine_get", "sv_set_block_order",
+    "sv_get_block_order", "sv_plan_info", "sv_last_error", "sv_status_string", "sv_version", "sv_stream_bench",
 ]
 
 
@@ -109,6 +109,8 @@ def _load():
         "sv_batch_copy_state": [vp, i, vp, ctypes.c_size_t],
         "sv_tune_set": [i, i, i, i, i, i],
         "sv_tune_get": [i, i, i, ip, ip, ip],
+        "sv_set_block_order": [i],
+        "sv_get_block_order": [ip],
         "sv_tune_engine_set": [i, i, i, i],
         "sv_tune_engine_get": [i, i, ip, ip],
         "sv_plan_info": [i, i, i, ip, i, ip, i, ip, ip, ip, ip, ip, ip],

@@ -24,6 +24,7 @@
 #include <algorithm>
 
 #include "sv.h"
+#include "sv_core.h"
 #include "sv_dense.h"
 
 namespace svk {
@@ -118,18 +119,29 @@ __global__ void __launch_bounds__(512) k_dense(T* __restrict__ psi, const T* __r
             a[i] = valid ? row[dep[4 * j + (l >> 4)]] : V{T(0), T(0)};
         }
     };
-    int64_t blk = (int64_t)blockIdx.x * wpg + (threadIdx.x >> 6);
+    const int64_t wg = (int64_t)block_slot(blockIdx.x, gridDim.x, sp.order);
+    const int wave = threadIdx.x >> 6;
+    int64_t blk, end, step;
+    if (sp.walk) {
+        blk = wg * sp.per_wg + wave;
+        end = std::min<int64_t>(nblk, (wg + 1) * sp.per_wg);
+        step = wpg;
+    } else {
+        blk = wg * wpg + wave;
+        end = nblk;
+        step = stride;
+    }
     V a_cur[CH / 2], a_nxt[CH / 2];
     bool valid = false;
     const V* row = nullptr;
-    if (blk < nblk) {
+    if (blk < end) {
         row = row_of(blk, valid);
         load_chunk(row, valid, 0, a_cur);
     }
-    for (; blk < nblk; blk += stride) {
-        const int64_t nb = blk + stride;
+    for (; blk < end; blk += step) {
+        const int64_t nb = blk + step;
         bool nvalid = false;
-        const V* const nrow = nb < nblk ? row_of(nb, nvalid) : nullptr;
+        const V* const nrow = nb < end ? row_of(nb, nvalid) : nullptr;
         Acc acc[NT];
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) acc[nt] = Acc{0, 0, 0, 0};
@@ -138,7 +150,7 @@ __global__ void __launch_bounds__(512) k_dense(T* __restrict__ psi, const T* __r
             // in flight during this chunk's products: the next chunk, or the
             // first chunk of this wavefront's next block (other groups)
             if (kc + CH < KS) load_chunk(row, valid, kc + CH, a_nxt);
-            else if (nb < nblk) load_chunk(nrow, nvalid, 0, a_nxt);
+            else if (nb < end) load_chunk(nrow, nvalid, 0, a_nxt);
 #pragma unroll
             for (int i = 0; i < CH; ++i) {
                 const T* const brow = Bl + (4 * (kc + i) + (l >> 4)) * N2 + (l & 15);
@@ -209,7 +221,9 @@ static hipError_t launch_k(T* psi, const T* B, const DenseSpec& sp, hipStream_t 
     // take a larger grid, whose concurrent workgroups stream closer together
     const int64_t cap = K == 6 ? 256 * 16 : 256 * 256;
     const int64_t grid = std::min<int64_t>((nblk + wpg - 1) / wpg, cap);
-    hipLaunchKernelGGL((k_dense<T, K>), dim3((unsigned)grid), dim3(threads), lds, s, psi, B, sp);
+    DenseSpec spl = sp;
+    spl.per_wg = ((nblk + grid - 1) / grid + wpg - 1) / wpg * wpg;
+    hipLaunchKernelGGL((k_dense<T, K>), dim3((unsigned)grid), dim3(threads), lds, s, psi, B, spl);
     return hipGetLastError();
 }
 

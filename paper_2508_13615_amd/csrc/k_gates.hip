@@ -86,8 +86,8 @@ k_pair(typename Vec2<T>::type* __restrict__ psi, GroupSpec gs, uint64_t o0, uint
     using V = typename Vec2<T>::type;
     const uint64_t per_block = (uint64_t)blockDim.x * U;
     const uint64_t stride = (uint64_t)gridDim.x * per_block;
-    for (uint64_t g0 = (uint64_t)blockIdx.x * per_block + threadIdx.x; g0 < gs.n_groups + threadIdx.x;
-         g0 += stride) {
+    const uint64_t first = block_slot(blockIdx.x, gridDim.x, gs.order) * per_block;
+    for (uint64_t g0 = first + threadIdx.x; g0 < gs.n_groups + threadIdx.x; g0 += stride) {
         uint64_t b[U];
         V a0[U], a1[U];
 #pragma unroll
@@ -129,8 +129,8 @@ k_wpair(typename Vec2<T>::type* __restrict__ psi, GroupSpec gs, int t, Coef2<T> 
     const uint64_t per_block = (uint64_t)blockDim.x * U;
     const uint64_t stride = (uint64_t)gridDim.x * per_block;
     const int lm = 1 << t;
-    for (uint64_t g0 = (uint64_t)blockIdx.x * per_block + threadIdx.x; g0 < gs.n_groups + threadIdx.x;
-         g0 += stride) {
+    const uint64_t first = block_slot(blockIdx.x, gridDim.x, gs.order) * per_block;
+    for (uint64_t g0 = first + threadIdx.x; g0 < gs.n_groups + threadIdx.x; g0 += stride) {
         uint64_t x[U];
         V a[U];
 #pragma unroll
@@ -175,8 +175,8 @@ k_one(typename Vec2<T>::type* __restrict__ psi, GroupSpec gs, T zr, T zi)
     using V = typename Vec2<T>::type;
     const uint64_t per_block = (uint64_t)blockDim.x * U;
     const uint64_t stride = (uint64_t)gridDim.x * per_block;
-    for (uint64_t g0 = (uint64_t)blockIdx.x * per_block + threadIdx.x; g0 < gs.n_groups + threadIdx.x;
-         g0 += stride) {
+    const uint64_t first = block_slot(blockIdx.x, gridDim.x, gs.order) * per_block;
+    for (uint64_t g0 = first + threadIdx.x; g0 < gs.n_groups + threadIdx.x; g0 += stride) {
         uint64_t b[U];
         V a[U];
 #pragma unroll
@@ -217,8 +217,8 @@ k_quad(typename Vec2<T>::type* __restrict__ psi, GroupSpec gs, uint64_t o1, uint
     using V = typename Vec2<T>::type;
     const uint64_t per_block = (uint64_t)blockDim.x * U;
     const uint64_t stride = (uint64_t)gridDim.x * per_block;
-    for (uint64_t g0 = (uint64_t)blockIdx.x * per_block + threadIdx.x; g0 < gs.n_groups + threadIdx.x;
-         g0 += stride) {
+    const uint64_t first = block_slot(blockIdx.x, gridDim.x, gs.order) * per_block;
+    for (uint64_t g0 = first + threadIdx.x; g0 < gs.n_groups + threadIdx.x; g0 += stride) {
         uint64_t b[U];
         V a[U][4];
 #pragma unroll
@@ -270,8 +270,8 @@ k_general(typename Vec2<T>::type* __restrict__ psi, GroupSpec gs, GeneralSpec<T,
     constexpr int M = 1 << K;
     const uint64_t per_block = (uint64_t)blockDim.x * U;
     const uint64_t stride = (uint64_t)gridDim.x * per_block;
-    for (uint64_t g0 = (uint64_t)blockIdx.x * per_block + threadIdx.x; g0 < gs.n_groups + threadIdx.x;
-         g0 += stride) {
+    const uint64_t first = block_slot(blockIdx.x, gridDim.x, gs.order) * per_block;
+    for (uint64_t g0 = first + threadIdx.x; g0 < gs.n_groups + threadIdx.x; g0 += stride) {
         uint64_t b[U];
         V a[U][M];
 #pragma unroll
@@ -335,7 +335,7 @@ k_lds_gate(typename Vec2<T>::type* __restrict__ psi, GroupSpec tiles, LdsSpec ls
     // (the 3-qubit form); B = 1 keeps the registers, and with them the waves
     // in flight, at their lowest.
     const uint32_t step = blockDim.x * B;
-    for (uint64_t tile = blockIdx.x; tile < tiles.n_groups; tile += gridDim.x) {
+    for (uint64_t tile = block_slot(blockIdx.x, gridDim.x, tiles.order); tile < tiles.n_groups; tile += gridDim.x) {
         const uint64_t base = (group_base(tile, tiles) << C) | ls.cmask;
         if constexpr (B == 1) {
             for (uint32_t l = threadIdx.x; l < nl; l += blockDim.x) st[l] = ldg<NT>(psi + index_of(base, l));

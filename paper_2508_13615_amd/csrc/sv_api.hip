@@ -21,6 +21,7 @@
 
 #include <algorithm>
 #include <complex>
+#include <cstdlib>
 #include <cstdio>
 #include <mutex>
 #include <string>
@@ -216,6 +217,39 @@ static Launch tune_get(int kc, int dtype, int low_qubit)
 {
     if (!g_tune_init) tune_defaults();
     return g_tune[kc][dtype == SV_C128 ? 1 : 0][tier_of(dtype, low_qubit)];
+}
+
+// Workgroup walk order of the group kernels (GroupSpec::order, block_slot).
+// Measured on MI355X at 30 qubits (per-target medians of the gate sweep), a
+// complex128 gate whose member offset is 32..128 MiB (target 21..23) runs
+// 5-8% slower in launch order than at neighbouring targets, and the XCD
+// spread brings it back in line; at 256 MiB and beyond, and at every
+// complex64 target, the spread is 2-8% slower, so it is taken only in that
+// band.  (Target 20, 16 MiB, is 8% slow under both orders.)  SV_BLOCK_ORDER=0
+// or 1 in the environment (read at the first launch) or sv_set_block_order
+// forces one order for every launch.
+static int g_block_order = -2;  // -2: not yet read from the environment; -1: per launch
+
+static int block_order_override()
+{
+    if (g_block_order == -2) {
+        const char* e = getenv("SV_BLOCK_ORDER");
+        g_block_order = (!e || !*e) ? -1 : (atoi(e) ? 1 : 0);
+    }
+    return g_block_order;
+}
+
+static int block_order(int dtype, uint64_t offsets)
+{
+    const int forced = block_order_override();
+    if (forced >= 0) return forced;
+    if (dtype != SV_C128) return 0;
+    for (int t = 0; t < 64; ++t) {
+        if (!((offsets >> t) & 1ull)) continue;
+        const uint64_t bytes = elem_bytes(dtype) << t;
+        if (bytes >= (32ull << 20) && bytes <= (128ull << 20)) return 1;
+    }
+    return 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -546,33 +580,52 @@ static sv_status build_plan(int n, int dtype, int gate, const int* ctrl, int nc,
     return set_error(SV_ERR_ARG, "unknown gate");
 }
 
+// The member offsets of a plan's groups (bits between the streams a group
+// touches); the wavefront form's partners share a wavefront, the one-member
+// form has none.
+static uint64_t plan_offsets(const Plan& pl)
+{
+    switch (pl.kind) {
+    case PK_PAIR: return pl.off[1];
+    case PK_QUAD: return pl.off[3];
+    case PK_LDS: {
+        uint64_t m = 0;
+        for (int j = 0; j < pl.ls.h; ++j) m |= 1ull << pl.ls.hq[j];
+        return m;
+    }
+    default: return 0;
+    }
+}
+
 template <typename T>
 static hipError_t run_plan_t(const Plan& pl, void* psi, hipStream_t s, int dtype)
 {
     const Launch lc = tune_get(pl.kc, dtype, pl.low);
+    GroupSpec gs = pl.gs;
+    gs.order = block_order(dtype, plan_offsets(pl));
     switch (pl.kind) {
     case PK_NOP: return hipSuccess;
     case PK_PAIR: {
         Coef2<T> c;
         for (int i = 0; i < 8; ++i) c.m[i] = (T)pl.m[i];
-        return launch_pair<T>(psi, pl.gs, pl.off[0], pl.off[1], pl.op, c, s, lc);
+        return launch_pair<T>(psi, gs, pl.off[0], pl.off[1], pl.op, c, s, lc);
     }
     case PK_WPAIR: {
         Coef2<T> c;
         for (int i = 0; i < 8; ++i) c.m[i] = (T)pl.m[i];
-        return launch_wpair<T>(psi, pl.gs, pl.wt, pl.op, c, s, lc);
+        return launch_wpair<T>(psi, gs, pl.wt, pl.op, c, s, lc);
     }
     case PK_LDS: {
         T m[128];
         const int mm = 2 * (1 << pl.lk) * (1 << pl.lk);
         for (int i = 0; i < mm; ++i) m[i] = (T)pl.m[i];
-        return launch_lds_gate<T>(psi, pl.gs, pl.ls, pl.op, m, s, lc);
+        return launch_lds_gate<T>(psi, gs, pl.ls, pl.op, m, s, lc);
     }
-    case PK_ONE: return launch_one<T>(psi, pl.gs, pl.op, (T)pl.m[0], (T)pl.m[1], s, lc);
+    case PK_ONE: return launch_one<T>(psi, gs, pl.op, (T)pl.m[0], (T)pl.m[1], s, lc);
     case PK_QUAD: {
         Coef4<T> c;
         for (int i = 0; i < 32; ++i) c.m[i] = (T)pl.m[i];
-        return launch_quad<T>(psi, pl.gs, pl.off, c, s, lc);
+        return launch_quad<T>(psi, gs, pl.off, c, s, lc);
     }
     }
     return hipErrorInvalidValue;
@@ -779,6 +832,7 @@ sv_status sv_apply_general(sv_state st_h, const int* qubits, int k, const double
         off[r] = o;
     }
     for (int j = 0; j < k; ++j) low = std::min(low, qubits[j]);
+    gs.order = block_order(st->dtype, off[M - 1]);
     if (k == 1 && qubits[0] < 6) {
         // the same dense 2x2, with the partner amplitude fetched across lanes
         Plan pl;
@@ -827,6 +881,15 @@ static sv_status apply_dense(sv_state_s* st, const int* qubits, int k, const dou
         for (int j = 0; j < k; ++j)
             if ((c >> (k - 1 - j)) & 1) sp.dep[c] |= 1ull << qubits[j];
     sp.groups = (int64_t)1 << (st->n - k);
+    sp.order = block_order(st->dtype, sp.dep[(1 << k) - 1]);
+    // a group's 2^k amplitudes sit in up to 2^k pages when the targets are
+    // high, and the UTCL1 misses on a grid-stride walk, whose next block is
+    // far away (measured at 30 qubits: 13-18% of complex64 translations miss
+    // at the top placement against under 0.01% at the bottom); a contiguous
+    // run per workgroup keeps its pages for k <= 5 (4-10% faster off the
+    // bottom, equal on it), while at k = 6 its 64 pages per wavefront thrash
+    // more than the stride walk (1.3-1.8x slower at the top)
+    sp.walk = k <= 5;
     // one buffer of the largest real form (k = kDenseMaxK) serves every call
     const size_t cap = dense_lds_bytes(kDenseMaxK, SV_C128);
     if (!st->dense_dev) {
@@ -1916,6 +1979,20 @@ sv_status sv_tune_set(int kernel_class, int dtype, int tier, int block, int unro
     if (unroll != 1 && unroll != 2 && unroll != 4) return set_error(SV_ERR_ARG, "unroll must be 1, 2 or 4");
     if (nt != 0 && nt != 1) return set_error(SV_ERR_ARG, "nt must be 0 or 1");
     g_tune[kernel_class][dtype == SV_C128 ? 1 : 0][tier] = Launch{block, unroll, nt};
+    return SV_OK;
+}
+
+sv_status sv_set_block_order(int order)
+{
+    if (order < -1 || order > 1) return set_error(SV_ERR_ARG, "block order must be -1, 0 or 1");
+    g_block_order = order;
+    return SV_OK;
+}
+
+sv_status sv_get_block_order(int* order)
+{
+    if (!order) return set_error(SV_ERR_ARG, "null output");
+    *order = block_order_override();
     return SV_OK;
 }
 

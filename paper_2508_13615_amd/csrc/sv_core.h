@@ -28,6 +28,9 @@ struct GroupSpec {
     // that fail the predicate are written back unchanged.
     uint64_t pmask;
     int32_t nins;
+    // Order in which the workgroups walk the groups (block_slot): 0 = launch
+    // order, 1 = one contiguous eighth of the grid per XCD.
+    int32_t order;
     int32_t pos[kMaxIns];
 };
 
@@ -80,6 +83,22 @@ __device__ __forceinline__ uint64_t group_base(uint64_t g, const GroupSpec& gs)
         }
     }
     return g | gs.set_mask;
+}
+
+// The place of workgroup b (of G) in a walk over the groups.  The hardware
+// deals consecutive workgroups to the 8 XCDs in turn.  order 0 keeps launch
+// order, so at any moment the whole chip streams one narrow window of the
+// state (plus the windows of the gate's partner offsets); order 1 gives XCD x
+// (the workgroups b = x mod 8) the x-th contiguous eighth of the grid, so the
+// chip streams 8 windows an eighth of the state apart, which measured faster
+// on MI355X for complex128 gates with a member offset of 32-128 MiB (the host
+// picks the order per launch).  Any G: XCD x owns floor(G/8) slots, plus one
+// if x < G mod 8.
+__device__ __forceinline__ uint64_t block_slot(uint32_t b, uint32_t G, int order)
+{
+    if (!order) return b;
+    const uint32_t x = b & 7u, q = G >> 3, r = G & 7u;
+    return (uint64_t)x * q + (x < r ? x : r) + (b >> 3);
 }
 
 // LDS-staged single gate: a block stages 2^(kLdsChunkBits + h) amplitudes --

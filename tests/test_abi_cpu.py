@@ -231,6 +231,22 @@ def test_tuning_table_validation():
     assert lib.sv_tune_set(0, 2, 2, b.value, u.value, nt.value) == OK
 
 
+def test_block_order_setting_validation():
+    o = ctypes.c_int()
+    assert lib.sv_get_block_order(ctypes.byref(o)) == OK
+    saved = o.value
+    assert saved in (-1, 0, 1)
+    try:
+        for bad in (-2, 2, 7):
+            assert lib.sv_set_block_order(bad) == ARG
+        assert lib.sv_get_block_order(None) == ARG
+        for good in (-1, 0, 1):
+            assert lib.sv_set_block_order(good) == OK
+            assert sv.get_block_order() == good
+    finally:
+        sv.set_block_order(saved)
+
+
 def test_lds_staging_depth_reported_per_form():
     """The LDS-staged class's unroll sets the staging depth of 3-qubit gates
     only; sv_plan_info reports the depth each launch uses, which names the

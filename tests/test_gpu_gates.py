@@ -139,6 +139,62 @@ def test_lds_staged_gate_every_launch_shape(dtype):
             sv.tune_set(6, dtype, t, *shp)
 
 
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_block_orders_agree_and_match_oracle(dtype):
+    """Both workgroup walk orders (launch order; one contiguous eighth of the
+    grid per XCD) on every gate form at 7 and 12 qubits: the results must be
+    bit-identical to each other (each group is still touched once with the
+    same arithmetic) and within the bar of the oracle.  Launch shapes of 192
+    threads make grids that are not multiples of 8, and the 7-qubit state has
+    grids under 8 workgroups.  Settings are restored after."""
+    classes = (0, 1, 3, 4, 5, 6)
+    saved_order = sv.get_block_order()
+    saved = {(kc, t): sv.tune_get(kc, dtype, t) for kc in classes for t in range(3)}
+    rng = np.random.default_rng(2020)
+    try:
+        for n in (7, 12):
+            psi0 = W.gaussian_state(n, 2021 + n).astype(NP_DT[dtype])
+            base = sv.State(n, dtype).load(psi0)
+            work = sv.State(n, dtype)
+            # every case at 7 qubits; at 12, every seventh Toffoli
+            cases = [(c.gate, c.targets, c.controls, c.params, c.matrix)
+                     for i, c in enumerate(W.sweep_cases(n, 2030 + n))
+                     if n == 7 or len(c.controls) < 2 or i % 7 == 0]
+            for k in (1, 2, 3):
+                cases.append(("GENERAL", tuple(int(q) for q in rng.permutation(n)[:k]), (), (),
+                              W.haar_unitary(k, rng)))
+            for shape in ((64, 1, 1), (192, 2, 0)):
+                for kc in classes:
+                    for t in range(3):
+                        sv.tune_set(kc, dtype, t, *shape)
+                outs = {}
+                for order in (0, 1):
+                    sv.set_block_order(order)
+                    res = []
+                    for g, tg, ct, p, m in cases:
+                        work.copy_from(base)
+                        if g == "GENERAL":
+                            work.apply_general(tg, m)
+                        else:
+                            work.apply(g, tg, ct, p, m)
+                        res.append(work.numpy())
+                    outs[order] = res
+                for i, (g, tg, ct, p, m) in enumerate(cases):
+                    a, b = outs[0][i], outs[1][i]
+                    assert np.array_equal(a.view(np.uint8), b.view(np.uint8)), (n, shape, g, tg, ct)
+                    if g == "GENERAL":
+                        ref = oracle.apply_matrix(psi0.astype(np.complex128), tg, m)
+                    else:
+                        ref = _oracle_apply(psi0, W.GateCase(g, ct, tg, p, m))
+                    err = float(np.max(np.abs(b.astype(np.complex128) - ref.astype(np.complex128))))
+                    assert err <= TOL[dtype], (n, shape, g, tg, ct, err)
+                log(f"block orders {dtype} n={n} shape={shape}: {len(cases)} cases agree")
+    finally:
+        sv.set_block_order(saved_order)
+        for (kc, t), shp in saved.items():
+            sv.tune_set(kc, dtype, t, *shp)
+
+
 def test_general_kernel_equals_specific_for_permutations():
     # Sec. 3.1 "general approach": CNOT as a 4x4 and Toffoli as an 8x8 dense
     # matrix give the same state as the dedicated move kernels (products with
