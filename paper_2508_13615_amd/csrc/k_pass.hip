@@ -270,17 +270,34 @@ __device__ double block_sum_fixed(double v, double* red)
 
 // Lane bits of the thread and register offsets of a layout.  The layout
 // table holds the bit values, so nothing here waits on a dependent load.
+// The table words are read whole and unconditionally (uniform scalar loads);
+// each lane then keeps the values of its own set bits by a select.  (A load
+// under the lane's bit test becomes a per-lane vector load, and the chain of
+// them, one wait each, stalled every layout change.)  A workgroup has at most
+// kMaxPassThreads threads, so only the lowest kPassLaneBits lane bits occur.
+constexpr int kPassLaneBits = 9;
+static_assert((1 << kPassLaneBits) == kMaxPassThreads, "lane bits cover the largest pass workgroup");
+
 template <int RB>
 __device__ __forceinline__ void frame_of(cptr<FLayout> L, uint32_t tid, uint32_t& tl, uint32_t* off)
 {
+    const cptr<uint32_t> w = (cptr<uint32_t>)L->lane_l;  // two 16-bit entries per word
     uint32_t t = 0;
 #pragma unroll
-    for (int i = 0; i < 16; ++i)
-        if ((tid >> i) & 1u) t |= L->lane_l[i];
+    for (int i = 0; i < kPassLaneBits; ++i) {
+        const uint32_t b = (w[i >> 1] >> (16 * (i & 1))) & 0xffffu;
+        t |= ((tid >> i) & 1u) ? b : 0u;
+    }
     tl = t;
     off[0] = 0;
 #pragma unroll
     for (int j = 1; j < (1 << RB); ++j) off[j] = off[j & (j - 1)] | L->reg_l[__builtin_ctz(j)];
+    // The offsets are uniform.  The exchanges that use them sit under the
+    // active-thread test, and a table load moved into that branch becomes a
+    // per-lane vector load with a wait; pinning the offsets to scalar
+    // registers here keeps them scalar loads ahead of the branch.
+#pragma unroll
+    for (int j = 1; j < (1 << RB); ++j) asm volatile("" ::"s"(off[j]));
 }
 
 // Global element offsets of this thread's registers in a layout.
@@ -289,8 +306,10 @@ __device__ __forceinline__ void global_frame(cptr<FLayout> L, uint32_t tid, uint
 {
     uint64_t t = tile_base;
 #pragma unroll
-    for (int i = 0; i < 16; ++i)
-        if ((tid >> i) & 1u) t |= L->lane_g[i];
+    for (int i = 0; i < kPassLaneBits; ++i) {
+        const uint64_t b = L->lane_g[i];
+        t |= ((tid >> i) & 1u) ? b : 0ull;
+    }
     g[0] = t;
 #pragma unroll
     for (int j = 1; j < (1 << RB); ++j) g[j] = g[j & (j - 1)] | L->reg_g[__builtin_ctz(j)];
