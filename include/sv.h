@@ -451,10 +451,23 @@ sv_status sv_get_block_order(int* order);
 sv_status sv_tune_engine_set(int dtype, int with_grad, int tile_qubits, int amps_per_thread);
 sv_status sv_tune_engine_get(int dtype, int with_grad, int* tile_qubits, int* amps_per_thread);
 
+/* Environment read by the library (each once, at first use):
+ *   SV_BLOCK_ORDER=0|1  forces a workgroup walk order (sv_set_block_order);
+ *   SV_FORCE_TIER=0|1|2 gives every gate launch the launch shape of that
+ *                       tier (the kernel a gate runs is unchanged; other
+ *                       values are ignored);
+ * and by the Python binding at import: SV_TUNING_FILE=path loads that tuning
+ * table instead of the one shipped beside the library ("none" loads none).
+ * Determinism needs no switch: every reduction (norms, expectations,
+ * gradient sums, the engine's per-tile partials) runs in a fixed order with
+ * no floating-point atomics, so a call repeated on the same inputs with the
+ * same launch shapes returns bit-identical results. */
+
 /* Host-only report of how a gate would be launched on an n_qubits state of
  * `dtype`: kernel class, tier, operation code (the pair/subset operation;
  * for the general kernel, k; for class 6, 16 * k + (1 for SWAP, else 0)) and
- * the launch shape.  gate = -1 asks about the
+ * the launch shape (tier: the one whose shape the launch takes, which
+ * SV_FORCE_TIER overrides).  gate = -1 asks about the
  * general dense kernel on `targets` (nc must be 0).  No device work.
  * Errors: as sv_apply_controlled's validation; SV_ERR_ARG for SV_I. */
 sv_status sv_plan_info(int n_qubits, int dtype, int gate, const int* controls, int nc, const int* targets, int nt,

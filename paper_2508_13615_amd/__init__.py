@@ -14,6 +14,7 @@ in the most significant bit of their index.
 from __future__ import annotations
 
 import ctypes
+import os
 import sys
 from typing import Iterable, List, Optional, Sequence, Tuple
 
@@ -437,13 +438,63 @@ class Batch:
 
 class AdjointExpval(torch.autograd.Function):
     """E(params) = <psi|O|psi> with psi = U(params)|0...0>, differentiated by the
-    adjoint kernel.  The gradient is produced together with E (the adjoint sweep
-    needs the forward state) and returned by backward scaled by dL/dE."""
+    adjoint method: the autograd loop of the paper's Listing 1, with the
+    gradient from one backward sweep instead of per-parameter reruns.
+
+    Two forms:
+      * AdjointExpval.apply(params, circuit, psi, lam, obs): a Circuit run op
+        by op on the states psi and lam (any observable).  The C entry point
+        takes host parameters, so params are copied to the host.  When no
+        gradient is needed (params does not require one, or under
+        torch.no_grad) only the forward pass and the expectation run, outside
+        autograd;
+        otherwise the adjoint sweep computes E and the gradient together.
+      * AdjointExpval.apply(params, batch): a one-circuit Batch of the fused
+        engine (observable sum_z or sum_zz).  params stay in device memory
+        (float64 on the batch's GPU), E and the gradient are written there,
+        ordered on torch's current stream; without a needed gradient a batch
+        built with with_grad=False runs forward only.
+    backward returns dL/dE times the saved gradient."""
+
+    @classmethod
+    def apply(cls, params: torch.Tensor, circuit, psi: Optional[State] = None, lam: Optional[State] = None,
+              obs=None):
+        # whether a gradient is needed is known here, before autograd's
+        # forward (which always runs with gradients off)
+        if torch.is_grad_enabled() and params.requires_grad:
+            return super().apply(params, circuit, psi, lam, obs)
+        with torch.no_grad():
+            return cls._run(None, params, circuit, psi, lam, obs)
 
     @staticmethod
-    def forward(ctx, params: torch.Tensor, circuit: Circuit, psi: State, lam: State, obs):
+    def forward(ctx, params: torch.Tensor, circuit, psi: Optional[State] = None, lam: Optional[State] = None,
+                obs=None):
+        return AdjointExpval._run(ctx, params, circuit, psi, lam, obs)
+
+    @staticmethod
+    def _run(ctx, params, circuit, psi, lam, obs):
+        """E, and with ctx the gradient saved for backward; ctx None: forward only."""
+        need = ctx is not None
+        if isinstance(circuit, Batch):
+            if circuit.n_circuits != 1:
+                raise ValueError("AdjointExpval takes a Batch of one circuit")
+            if need and not circuit.with_grad:
+                raise ValueError("a gradient is needed but the batch was built with with_grad=False")
+            if not params.is_cuda:
+                raise ValueError("the engine form takes parameters in device memory")
+            p = params.detach().to(torch.float64).contiguous()
+            e = torch.empty(1, dtype=torch.float64, device=p.device)
+            g = torch.empty(max(1, circuit.n_params[0]), dtype=torch.float64, device=p.device)
+            circuit.run_device(p, e, g)
+            if need:
+                ctx.save_for_backward(g[: circuit.n_params[0]].to(params.dtype))
+            return e[0].to(params.dtype)
+        th = params.detach().cpu().double().numpy()
         psi.set_basis(0)
-        e, g = circuit.adjoint_grad(psi, lam, params.detach().cpu().double().numpy(), obs)
+        if not need:
+            circuit.apply(psi, th)
+            return torch.tensor(psi.expval(obs), dtype=params.dtype, device=params.device)
+        e, g = circuit.adjoint_grad(psi, lam, th, obs)
         ctx.save_for_backward(torch.from_numpy(g).to(params.device, params.dtype))
         return torch.tensor(e, dtype=params.dtype, device=params.device)
 
@@ -457,4 +508,19 @@ class AdjointExpval(torch.autograd.Function):
 # applied once at import when the table exists.
 from . import autotune as _autotune  # noqa: E402
 
-TUNED_ENTRIES = _autotune.apply_table(sys.modules[__name__])
+def _tuning_path() -> Optional[str]:
+    """The tuning table loaded at import: SV_TUNING_FILE names another file
+    ("none": load none and keep the built-in shapes); a named file that does
+    not exist is an error, not a silent fallback."""
+    p = os.environ.get("SV_TUNING_FILE", "")
+    if not p:
+        return _autotune.TABLE
+    if p.lower() == "none":
+        return None
+    if not os.path.exists(p):
+        raise FileNotFoundError(f"SV_TUNING_FILE={p!r} does not exist")
+    return p
+
+
+_TUNING_PATH = _tuning_path()
+TUNED_ENTRIES = _autotune.apply_table(sys.modules[__name__], _TUNING_PATH) if _TUNING_PATH else 0

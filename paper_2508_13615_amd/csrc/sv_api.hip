@@ -213,10 +213,24 @@ static int tier_of(int dtype, int low_qubit)
     return span < 64 ? 0 : (span < 1024 ? 1 : 2);
 }
 
+// Tier whose launch shape a gate takes: its own, or the one SV_FORCE_TIER
+// (0, 1 or 2 in the environment, read at the first launch) names for every
+// gate.  Forcing changes launch shapes only, never the kernel a gate runs.
+static int shape_tier(int dtype, int low_qubit)
+{
+    static const int forced = [] {
+        const char* e = getenv("SV_FORCE_TIER");
+        if (!e || !*e) return -1;
+        const int t = atoi(e);
+        return t >= 0 && t < kTiers ? t : -1;
+    }();
+    return forced >= 0 ? forced : tier_of(dtype, low_qubit);
+}
+
 static Launch tune_get(int kc, int dtype, int low_qubit)
 {
     if (!g_tune_init) tune_defaults();
-    return g_tune[kc][dtype == SV_C128 ? 1 : 0][tier_of(dtype, low_qubit)];
+    return g_tune[kc][dtype == SV_C128 ? 1 : 0][shape_tier(dtype, low_qubit)];
 }
 
 // Workgroup walk order of the group kernels (GroupSpec::order, block_slot).
@@ -2045,7 +2059,7 @@ sv_status sv_plan_info(int n_qubits, int dtype, int gate, const int* controls, i
     }
     const Launch l = tune_get(kc, dtype, low);
     *kernel_class = kc;
-    *tier = tier_of(dtype, low);
+    *tier = shape_tier(dtype, low);
     *op = opv;
     *block = l.block;
     *unroll = kc == KC_LDS ? lds_stage_depth(opv >> 4, l.unroll, (int)elem_bytes(dtype)) : l.unroll;

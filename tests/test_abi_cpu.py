@@ -5,8 +5,10 @@ No compute call is made: states are wrapped around a dummy, never
 dereferenced address, and every call below fails validation on the host.
 """
 import ctypes
+import json
 import os
 import re
+import sys
 
 import pytest
 
@@ -245,6 +247,45 @@ def test_block_order_setting_validation():
             assert sv.get_block_order() == good
     finally:
         sv.set_block_order(saved)
+
+
+def _run_with_env(env_extra, code):
+    import subprocess
+    env = dict(os.environ, **env_extra)
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    return subprocess.run([sys.executable, "-c", code], env=env, cwd=root, capture_output=True, text=True,
+                          timeout=120)
+
+
+def test_environment_settings_force_tier_tuning_file_and_order(tmp_path):
+    """SV_FORCE_TIER changes the launch-shape tier a gate reports (never its
+    kernel), SV_TUNING_FILE loads the named table ("none": built-in shapes
+    only; a missing file is an error) and SV_BLOCK_ORDER sets the walk
+    order; each in a fresh process, host-only calls."""
+    probe = ("import paper_2508_13615_amd as sv; i = sv.plan_info(20, 'c128', 'H', (12,)); "
+             "j = sv.plan_info(20, 'c128', 'U4', (19, 0)); "
+             "print(i['class'], i['tier'], j['class'], j['tier'], sv.TUNED_ENTRIES, sv.get_block_order(), "
+             "sv.tune_get(0, 'c128', 2))")
+    base = _run_with_env({}, probe)
+    assert base.returncode == 0, base.stderr
+    kc_h, tier_h, kc_u, tier_u, n_tuned, order, shape = base.stdout.split(None, 6)
+    assert (tier_h, tier_u) == ("2", "0") and int(n_tuned) > 0 and order == "-1"
+    forced = _run_with_env({"SV_FORCE_TIER": "1", "SV_BLOCK_ORDER": "1"}, probe)
+    assert forced.returncode == 0, forced.stderr
+    f = forced.stdout.split(None, 6)
+    assert (f[0], f[2]) == (kc_h, kc_u) and (f[1], f[3]) == ("1", "1") and f[5] == "1"
+    none = _run_with_env({"SV_TUNING_FILE": "none"}, probe)
+    assert none.returncode == 0, none.stderr
+    assert none.stdout.split(None, 6)[4] == "0"
+    tab = tmp_path / "tab.json"
+    tab.write_text(json.dumps({"entries": [{"class": 0, "dtype": "c128", "tier": 2, "block": 320, "unroll": 2,
+                                            "nt": 0}]}))
+    own = _run_with_env({"SV_TUNING_FILE": str(tab)}, probe)
+    assert own.returncode == 0, own.stderr
+    o = own.stdout.split(None, 6)
+    assert o[4] == "1" and o[6].strip() == "(320, 2, 0)"
+    missing = _run_with_env({"SV_TUNING_FILE": str(tmp_path / "nope.json")}, probe)
+    assert missing.returncode != 0 and "SV_TUNING_FILE" in missing.stderr
 
 
 def test_lds_staging_depth_reported_per_form():

@@ -83,3 +83,52 @@ def test_autograd_function():
     loss.backward()
     g_ref = oracle.param_shift_grad(n, ops, th, W.sum_zz(n))
     assert np.max(np.abs(params.grad.numpy() - 3.0 * g_ref)) <= 3e-10
+
+
+def test_autograd_function_forward_only_when_no_gradient_is_needed():
+    # under no_grad (or for parameters without requires_grad) only the forward
+    # pass runs: lam is never written, and E matches the oracle
+    import torch
+    n, layers = 6, 2
+    ops = W.hea_ops(n, layers)
+    npar = W.hea_n_params(n, layers)
+    th = W.uniform_angles(npar, 4003)
+    circ = sv.Circuit(n, ops, npar)
+    psi, lam = sv.State(n), sv.State(n)
+    lam.set_basis(5)
+    params = torch.tensor(th, dtype=torch.float64, requires_grad=True)
+    with torch.no_grad():
+        e = sv.AdjointExpval.apply(params, circ, psi, lam, W.sum_zz(n))
+    assert not e.requires_grad
+    assert abs(float(e) - oracle.energy(n, ops, th, W.sum_zz(n))) <= 1e-12
+    lam_host = lam.numpy()
+    assert lam_host[5] == 1 and np.count_nonzero(lam_host) == 1  # untouched
+    e2 = sv.AdjointExpval.apply(torch.tensor(th), circ, psi, lam, W.sum_zz(n))
+    assert float(e2) == float(e)
+
+
+@pytest.mark.parametrize("dtype,tol", [("c128", 1e-10), ("c64", 1e-4)])
+def test_autograd_function_engine_form_keeps_parameters_on_device(dtype, tol):
+    # a one-circuit Batch: params, E and the gradient stay in device memory
+    import torch
+    n, layers = 8, 3
+    ops = W.hea_ops(n, layers)
+    npar = W.hea_n_params(n, layers)
+    th = W.uniform_angles(npar, 4004)
+    b = sv.Batch([(n, ops, npar, "sum_zz")], dtype, with_grad=True)
+    params = torch.tensor(th, dtype=torch.float64, device="cuda", requires_grad=True)
+    loss = -2.0 * sv.AdjointExpval.apply(params, b)
+    assert loss.device.type == "cuda"
+    loss.backward()
+    g_ref = oracle.param_shift_grad(n, ops, th, W.sum_zz(n))
+    e_ref = oracle.energy(n, ops, th, W.sum_zz(n))
+    assert abs(float(loss.detach()) + 2.0 * e_ref) <= 2 * tol * (n - 1)
+    assert params.grad.device.type == "cuda"
+    assert np.max(np.abs(params.grad.cpu().numpy() + 2.0 * g_ref)) <= 2 * tol
+    # forward only: a batch without the sweep, and no gradient asked for
+    f = sv.Batch([(n, ops, npar, "sum_zz")], dtype, with_grad=False)
+    with torch.no_grad():
+        e = sv.AdjointExpval.apply(params, f)
+    assert abs(float(e) - e_ref) <= tol * (n - 1)
+    with pytest.raises(ValueError):
+        sv.AdjointExpval.apply(params, f)  # a gradient is needed, the batch has no sweep
