@@ -638,6 +638,19 @@ def config5(sv, torch, reps, sequential):
     return out
 
 
+def circuit_jobs(n, layers):
+    """(basis index of the QFT input, {name: (ops, params)}) of the circuits
+    benchmark: HEA (layers of RY+RZ and a CNOT ladder), the QFT of a seeded
+    basis state and the universal circuit after an H on every qubit."""
+    import numpy as np
+    import workloads as W
+    x = W.random_basis_index(n, 1004)
+    prep = [W.Op("X", (), (q,)) for q in range(n) if (x >> q) & 1]
+    return x, {"hea": (W.hea_ops(n, layers), W.uniform_angles(W.hea_n_params(n, layers), 1003)),
+               "qft": (prep + W.qft_ops(n), np.zeros(0)),
+               "universal": ([W.Op("H", (), (q,)) for q in range(n)] + W.universal_ops(n), np.zeros(0))}
+
+
 def config3(sv, torch, n, layers, reps, names=("hea", "qft", "universal"), engine_only=False):
     """32-qubit HEA (10 layers RY+RZ, CNOT ladder, from |0..0>), QFT of a
     random basis state and the universal circuit (2 n^2 gates after an H on
@@ -646,13 +659,8 @@ def config3(sv, torch, n, layers, reps, names=("hea", "qft", "universal"), engin
     single-gate kernels with and without fused diagonal runs.  The
     complex64 error is taken against the complex128 GPU result (itself
     checked against the fp64 oracle at 20 qubits by the GPU tests)."""
-    import numpy as np
     import workloads as W
-    x = W.random_basis_index(n, 1004)
-    prep = [W.Op("X", (), (q,)) for q in range(n) if (x >> q) & 1]
-    jobs = {"hea": (W.hea_ops(n, layers), W.uniform_angles(W.hea_n_params(n, layers), 1003)),
-            "qft": (prep + W.qft_ops(n), np.zeros(0)),
-            "universal": ([W.Op("H", (), (q,)) for q in range(n)] + W.universal_ops(n), np.zeros(0))}
+    x, jobs = circuit_jobs(n, layers)
     jobs = {k: v for k, v in jobs.items() if k in names}
     out = {"qubits": n, "hea_layers": layers, "qft_basis_index": x}
     for name, (ops, th) in jobs.items():

@@ -6,6 +6,7 @@
     python -m paper_2508_13615_amd.profsum sweep-pmc <fetch.json> <write.json> <source_sha256>
     python -m paper_2508_13615_amd.profsum counters <prefix_counter_collection.csv> [more.csv ...]
     python -m paper_2508_13615_amd.profsum sweep-lines <fetch.json> <write.json> [qubits]
+    python -m paper_2508_13615_amd.profsum engine-bounds <bench_line.json> <name>=<counters.csv> ... [--qubits N]
 
 ``stats`` tabulates the kernel statistics that ``rocprofv3 --stats`` writes.
 ``pmc`` folds a per-dispatch counter CSV (one counter per run) into
@@ -23,7 +24,15 @@ wavefront.  ``sweep-lines`` sets each sweep kernel's measured traffic (all
 its dispatches of one benchmark step) beside the algorithmic and the
 line-granular bytes of the gate cases the benchmark launches on it (the case
 list and kernel choice come from bench.py and the library's host-only
-sv_plan_info).
+sv_plan_info).  ``engine-bounds`` sets the circuits benchmark's engine runs
+(seconds per run from its bench line, one counter run per circuit holding
+SQ_INSTS_VALU, SQ_INSTS_SALU and SQ_WAVES) against their HBM floor (every
+forward pass reads and writes the state once, the observable pass reads it:
+(2 passes + 1) S at 8 TB/s) and their VALU issue floor (a wave64 VALU
+instruction takes 4 cycles of a 16-lane SIMD; 1024 SIMDs at 2.4 GHz); the
+benchmark runs each circuit 4 times (a warm-up and 3 timed runs), so counter
+totals are divided by 4.  Pass and layout counts come from the library's
+host-only batch planner with the shipped tuning table.
 """
 from __future__ import annotations
 
@@ -199,6 +208,40 @@ def sweep_lines(fetch_json: str, write_json: str, n: int = 30) -> str:
     return "\n".join(rows)
 
 
+def engine_bounds(bench_line: str, runs: dict, n: int = 30, layers: int = 10) -> str:
+    import os
+
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import bench
+    import paper_2508_13615_amd as sv
+    with open(bench_line) as f:
+        secs = json.loads(f.read().strip().splitlines()[-1])["circuits32_s"]
+    _, jobs = bench.circuit_jobs(n, layers)
+    kern = {"c128": "k_pass_fwd<double, 4>", "c64": "k_pass_fwd<float, 4>"}
+    ebytes = {"c128": 16, "c64": 8}
+    rows = ["| circuit | dtype | s per run (HIP events) | passes | gate ops (fused) | layout changes | "
+            "HBM floor at 8 TB/s | VALU issue floor | VALU / wave / pass | SALU / wave / pass | VALU busy |",
+            "|---|---|---|---|---|---|---|---|---|---|---|"]
+    for name, path in runs.items():
+        tot = {}
+        for r in csv.DictReader(open(path)):
+            k = short_name(r["Kernel_Name"])
+            tot.setdefault(k, {})
+            tot[k][r["Counter_Name"]] = tot[k].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+        ops, th = jobs[name]
+        for dt in ("c128", "c64"):
+            c = tot[kern[dt]]
+            plan = sv.batch_plan([(n, ops, len(th), "sum_z")], dt, with_grad=False)
+            t = secs[f"{name}_{dt}"]
+            hbm = (2 * plan["passes"] + 1) * (1 << n) * ebytes[dt] / 8e12
+            valu = c["SQ_INSTS_VALU"] / 4 * 4 / (1024 * 2.4e9)
+            rows.append(f"| {name} | {dt} | {t:.4f} | {plan['passes']} | {plan['fused_ops']} | "
+                        f"{plan['layout_changes']} | {hbm:.4f} s | {valu:.4f} s | "
+                        f"{c['SQ_INSTS_VALU'] / c['SQ_WAVES']:.0f} | {c['SQ_INSTS_SALU'] / c['SQ_WAVES']:.0f} | "
+                        f"{valu / t:.2f} |")
+    return "\n".join(rows)
+
+
 def main(argv):
     if len(argv) >= 2 and argv[0] == "stats":
         top = int(argv[argv.index("--top") + 1]) if "--top" in argv else 40
@@ -211,6 +254,10 @@ def main(argv):
         print(sweep_pmc(argv[1], argv[2], argv[3]))
     elif len(argv) >= 2 and argv[0] == "counters":
         print(counters_table(argv[1:]))
+    elif len(argv) >= 3 and argv[0] == "engine-bounds":
+        n = int(argv[argv.index("--qubits") + 1]) if "--qubits" in argv else 30
+        runs = dict(a.split("=", 1) for a in argv[2:] if "=" in a)
+        print(engine_bounds(argv[1], runs, n))
     elif len(argv) in (3, 4) and argv[0] == "sweep-lines":
         print(sweep_lines(argv[1], argv[2], int(argv[3]) if len(argv) == 4 else 30))
     else:
