@@ -451,3 +451,68 @@ def test_single_gates_on_32_qubits_sampled():
             assert np.max(np.abs(after[row] - ref)) <= 1e-5, (gate, tg, ct, row)
     del s, t
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("n,dtype,tol", [(33, "c128", 1e-12), (34, "c64", 1e-5)])
+def test_largest_states_sampled(n, dtype, tol):
+    """The largest states one MI355X holds for each dtype (128 GiB: 33 qubits
+    complex128, 34 qubits complex64): every kernel form once, at targets
+    that put members 2^32 and more apart, checked on 256 sampled groups per
+    gate against the oracle's dense apply, then the norm (a unitary keeps
+    it) through the two-stage reduction."""
+    import torch
+    log(f"{n}-qubit {dtype}: allocating {((1 << n) * (16 if dtype == 'c128' else 8)) >> 30} GiB")
+    tdt = torch.complex128 if dtype == "c128" else torch.complex64
+    g = torch.Generator(device="cuda")
+    g.manual_seed(1033 + n)
+    t = torch.randn(1 << n, dtype=tdt, device="cuda", generator=g)
+    t /= torch.linalg.vector_norm(t)
+    s = sv.State(n, dtype, tensor=t, basis=None)
+    rng = np.random.default_rng(3033 + n)
+    top = n - 1
+    cases = [("H", (0,), ()), ("RY", (top,), ()), ("RZ", (top - 1,), (2,)), ("U4", (top, 1), ()),
+             ("SWAP", (3, top), ()), ("X", (top,), (0, 17)), ("Z", (top,), (top - 2,)), ("U2", (5,), (top,)),
+             ("GENERAL", (top, 2, 0), ()), ("DENSE", (top, top - 1, 3, 0), ())]
+    for gate, tg, ct in cases:
+        log("  case", gate, tg, ct)
+        p = (float(rng.uniform(0, 2 * math.pi)),)
+        k = len(tg)
+        m = W.haar_unitary(k, rng) if gate in ("U4", "U2", "GENERAL", "DENSE") else None
+        free = rng.integers(0, 1 << n, size=256, dtype=np.int64)
+        for q in list(ct) + list(tg):
+            free &= ~(1 << q)
+        for q in ct:
+            free |= 1 << q
+        members = []
+        for r in range(1 << k):
+            off = 0
+            for j, q in enumerate(tg):
+                if (r >> (k - 1 - j)) & 1:
+                    off |= 1 << q
+            members.append(free | off)
+        idx = torch.from_numpy(np.stack(members, axis=1).reshape(-1)).cuda()
+        before = t[idx].cpu().numpy().astype(np.complex128).reshape(256, -1)
+        if gate == "GENERAL":
+            s.apply_general(tg, m)
+            u = m
+        elif gate == "DENSE":
+            s.apply_dense(tg, m)
+            u = m
+        else:
+            s.apply(gate, tg, ct, p, m)
+            u = oracle.gate_matrix(gate, p, m)
+        s.synchronize()
+        after = t[idx].cpu().numpy().astype(np.complex128).reshape(256, -1)
+        if gate in ("X", "SWAP"):
+            # moves: the sampled members are permuted bit for bit
+            perm = [1, 0] if gate == "X" else [0, 2, 1, 3]
+            assert np.array_equal(after, before[:, perm]), (gate, tg, ct)
+            continue
+        for row in range(256):
+            ref = oracle.apply_matrix(before[row].copy(), tuple(range(k - 1, -1, -1)), u)
+            assert np.max(np.abs(after[row] - ref)) <= tol, (gate, tg, ct, row)
+    nrm = s.norm2()
+    log(f"  norm^2 after the gates: {nrm!r}")
+    assert abs(nrm - 1.0) <= (1e-11 if dtype == "c128" else 1e-4)
+    del s, t
+    torch.cuda.empty_cache()
