@@ -103,7 +103,6 @@ __global__ void __launch_bounds__(512) k_dense(T* __restrict__ psi, const T* __r
     const int l = threadIdx.x & 63;
     const int wpg = blockDim.x >> 6;
     const int64_t nblk = (sp.groups + 15) >> 4;
-    const int64_t stride = (int64_t)gridDim.x * wpg;
     // this lane's group row of block b (the last block of a small state is
     // partial: rows past the groups read zeros and are not stored)
     auto row_of = [&](int64_t b, bool& valid) {
@@ -119,18 +118,14 @@ __global__ void __launch_bounds__(512) k_dense(T* __restrict__ psi, const T* __r
             a[i] = valid ? row[dep[4 * j + (l >> 4)]] : V{T(0), T(0)};
         }
     };
+    // Teams of sp.team consecutive workgroups each own a contiguous run of
+    // sp.per_team blocks and walk it with a stride of the team's wavefronts
+    // (team = 1: a run per workgroup; team = grid: one grid-stride walk).
     const int64_t wg = (int64_t)block_slot(blockIdx.x, gridDim.x, sp.order);
-    const int wave = threadIdx.x >> 6;
-    int64_t blk, end, step;
-    if (sp.walk) {
-        blk = wg * sp.per_wg + wave;
-        end = std::min<int64_t>(nblk, (wg + 1) * sp.per_wg);
-        step = wpg;
-    } else {
-        blk = wg * wpg + wave;
-        end = nblk;
-        step = stride;
-    }
+    const int64_t team = wg / sp.team, local = wg % sp.team;
+    int64_t blk = team * sp.per_team + local * wpg + (threadIdx.x >> 6);
+    const int64_t end = std::min<int64_t>(nblk, (team + 1) * sp.per_team);
+    const int64_t step = (int64_t)sp.team * wpg;
     V a_cur[CH / 2], a_nxt[CH / 2];
     bool valid = false;
     const V* row = nullptr;
@@ -220,9 +215,13 @@ static hipError_t launch_k(T* psi, const T* B, const DenseSpec& sp, hipStream_t 
     // complex128) amortises it over many blocks per workgroup; smaller forms
     // take a larger grid, whose concurrent workgroups stream closer together
     const int64_t cap = K == 6 ? 256 * 16 : 256 * 256;
-    const int64_t grid = std::min<int64_t>((nblk + wpg - 1) / wpg, cap);
+    int64_t grid = std::min<int64_t>((nblk + wpg - 1) / wpg, cap);
     DenseSpec spl = sp;
-    spl.per_wg = ((nblk + grid - 1) / grid + wpg - 1) / wpg * wpg;
+    // whole teams only: every residue of a team's stride needs its workgroup
+    spl.team = (int)std::min<int64_t>(std::max(sp.team, 1), grid);
+    grid = grid / spl.team * spl.team;
+    const int64_t teams = grid / spl.team;
+    spl.per_team = (nblk + teams - 1) / teams;
     hipLaunchKernelGGL((k_dense<T, K>), dim3((unsigned)grid), dim3(threads), lds, s, psi, B, spl);
     return hipGetLastError();
 }

@@ -896,14 +896,16 @@ static sv_status apply_dense(sv_state_s* st, const int* qubits, int k, const dou
             if ((c >> (k - 1 - j)) & 1) sp.dep[c] |= 1ull << qubits[j];
     sp.groups = (int64_t)1 << (st->n - k);
     sp.order = block_order(st->dtype, sp.dep[(1 << k) - 1]);
-    // a group's 2^k amplitudes sit in up to 2^k pages when the targets are
+    // A group's 2^k amplitudes sit in up to 2^k pages when the targets are
     // high, and the UTCL1 misses on a grid-stride walk, whose next block is
     // far away (measured at 30 qubits: 13-18% of complex64 translations miss
-    // at the top placement against under 0.01% at the bottom); a contiguous
-    // run per workgroup keeps its pages for k <= 5 (4-10% faster off the
-    // bottom, equal on it), while at k = 6 its 64 pages per wavefront thrash
-    // more than the stride walk (1.3-1.8x slower at the top)
-    sp.walk = k <= 5;
+    // at the top placement against under 0.01% at the bottom).  A contiguous
+    // run per workgroup (team of 1) keeps its pages for k <= 5 (4-10% faster
+    // off the bottom, equal on it); at k = 6 its 64 pages per wavefront
+    // thrash more than the grid-stride walk (a team as large as the grid),
+    // 1.3-1.8x slower at the top.  Teams of 8 to 2048 workgroups sharing a
+    // run measured no better for any placement.
+    sp.team = k <= 5 ? 1 : (1 << 30);
     // one buffer of the largest real form (k = kDenseMaxK) serves every call
     const size_t cap = dense_lds_bytes(kDenseMaxK, SV_C128);
     if (!st->dense_dev) {

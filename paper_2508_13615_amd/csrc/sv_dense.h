@@ -19,8 +19,8 @@ struct DenseSpec {
     uint64_t dep[1 << kDenseMaxK];
     int64_t groups;  // 2^(n-k)
     int order;       // workgroup walk order (block_slot in sv_core.h)
-    int walk;        // 0: grid-stride over 16-group blocks; 1: a contiguous run per workgroup
-    int64_t per_wg;  // walk 1: blocks per workgroup (set by the launcher)
+    int team;          // workgroups that walk one contiguous run of 16-group blocks together (capped at the grid)
+    int64_t per_team;  // blocks per team (set by the launcher)
 };
 
 // Real form of the 2^k x 2^k complex matrix U: 2^(k+1) x 2^(k+1), row-major,
