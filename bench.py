@@ -356,10 +356,12 @@ def cpu_baseline(qubits_cpu, qubits_gpu, min_seconds=10.0):
         if dt >= min_seconds:
             break
     rate = gates / dt * 2.0 ** (qubits_cpu - qubits_gpu)
+    scaled = ("" if qubits_cpu == qubits_gpu else
+              f"; rate scaled by 2^{qubits_cpu - qubits_gpu} to {qubits_gpu} qubits (the oracle's work is linear "
+              f"in the amplitude count)")
     return {"value": rate, "unit": "gates/s", "cores": oracle.num_threads(), "kind": "oracle",
             "sample": (f"X, H, RZ, CNOT, CZ, Toffoli at t in {ts} on a {qubits_cpu}-qubit complex128 Gaussian state, "
-                       f"{gates} gates in {dt:.1f} s; rate scaled by 2^{qubits_cpu - qubits_gpu} to {qubits_gpu} "
-                       f"qubits (the oracle's work is linear in the amplitude count)")}
+                       f"{gates} gates in {dt:.1f} s{scaled}")}
 
 
 def cpu_param_shift_estimate(n, layers):
@@ -790,7 +792,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--qubits", type=int, default=30)
-    ap.add_argument("--cpu-qubits", type=int, default=27)
+    ap.add_argument("--cpu-qubits", type=int, default=30)
     ap.add_argument("--skip-cpu-baseline", action="store_true")
     ap.add_argument("--skip-c64-sweep", action="store_true", help="skip the secondary complex64 sweep (one step)")
     ap.add_argument("--skip-adjoint", action="store_true")

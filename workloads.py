@@ -43,13 +43,16 @@ PERMUTATION = ("X", "SWAP")
 # random inputs
 # --------------------------------------------------------------------------
 def gaussian_state(n: int, seed: int) -> np.ndarray:
-    """i.i.d. complex Gaussian amplitudes (Re, Im ~ N(0,1)), normalised in fp64."""
+    """i.i.d. complex Gaussian amplitudes (Re, Im ~ N(0,1)), normalised in fp64.
+    The real parts are drawn first, then the imaginary parts, straight into
+    the result (a 30-qubit state peaks near 2.5x its own 16 GiB)."""
     rng = np.random.default_rng(seed)
-    re = rng.standard_normal(1 << n)
-    im = rng.standard_normal(1 << n)
-    psi = re + 1j * im
+    psi = np.empty(1 << n, dtype=np.complex128)
+    psi.real = rng.standard_normal(1 << n)
+    psi.imag = rng.standard_normal(1 << n)
+    re, im = psi.real, psi.imag
     psi /= math.sqrt(float(np.sum(re * re + im * im)))
-    return psi.astype(np.complex128)
+    return psi
 
 
 def haar_unitary(k: int, rng: np.random.Generator) -> np.ndarray:
