@@ -210,6 +210,28 @@ __device__ void lds_apply(typename Vec2<T>::type* A0, const FOp op, P coef, bool
     }
 }
 
+// FK_PAIRC on an LDS tile (forward passes of the LDS-sweep form): the 2x2
+// cf[0..7] where bit b is 0, cf[8..15] where it is 1.  Kept out of lds_apply,
+// which the register passes also inline with all their amplitudes live.
+template <typename T>
+__device__ void lds_pairc(typename Vec2<T>::type* A, const FOp op, const double* coef, int tq)
+{
+    using V = typename Vec2<T>::type;
+    const double* cf = coef + op.coef;
+    T u0[8], u1[8];
+    load2x2<T>(cf, false, u0);
+    load2x2<T>(cf + 8, false, u1);
+    const uint32_t np = 1u << (tq - 1);
+    for (uint32_t p = threadIdx.x; p < np; p += blockDim.x) {
+        const uint32_t i0 = ins0(p, op.a);
+        const uint32_t i1 = i0 | (1u << op.a);
+        const T* u = ((i0 >> op.b) & 1u) ? u1 : u0;
+        const V v0 = A[i0], v1 = A[i1];
+        A[i0] = cmul_add2<V, T>(u[0], u[1], v0, u[2], u[3], v1);
+        A[i1] = cmul_add2<V, T>(u[4], u[5], v0, u[6], u[7], v1);
+    }
+}
+
 // Per-thread Im <lambda|G|phi> over the tile for a one-target generator on
 // local bit a, restricted to the local control mask cm.
 template <typename T>
@@ -368,6 +390,22 @@ __device__ __forceinline__ void rpair_k(typename Vec2<T>::type* v, const T* u, u
         if (j & (1 << K)) continue;
         if (CHK && skip_reg(j, cmk)) continue;
         const int j1 = j | (1 << K);
+        const auto a = v[j], b = v[j1];
+        v[j] = cmul_add2<typename Vec2<T>::type, T>(u[0], u[1], a, u[2], u[3], b);
+        v[j1] = cmul_add2<typename Vec2<T>::type, T>(u[4], u[5], a, u[6], u[7], b);
+    }
+}
+
+// Complex 2x2 on register bit K chosen per register pair by register bit
+// KS (the selector of FK_PAIRC): u0 where bit KS is 0, u1 where it is 1.
+template <typename T, int RB, int K, int KS>
+__device__ __forceinline__ void rpairc_k(typename Vec2<T>::type* v, const T* u0, const T* u1)
+{
+#pragma unroll
+    for (int j = 0; j < (1 << RB); ++j) {
+        if (j & (1 << K)) continue;
+        const int j1 = j | (1 << K);
+        const T* u = (j & (1 << KS)) ? u1 : u0;
         const auto a = v[j], b = v[j1];
         v[j] = cmul_add2<typename Vec2<T>::type, T>(u[0], u[1], a, u[2], u[3], b);
         v[j1] = cmul_add2<typename Vec2<T>::type, T>(u[4], u[5], a, u[6], u[7], b);
@@ -562,6 +600,44 @@ __device__ __forceinline__ void reg_apply_c(typename Vec2<T>::type* v, const FOp
         if constexpr (TWO) rswap<T, RB, CHK, SEL>(op.ka, op.kb, v, ok, cmk);
         break;
     default: break;
+    }
+}
+
+// FK_PAIRC in a register layout: with the selector on a lane bit each thread
+// takes one of the two matrices (a select of its coefficients); with it on a
+// register bit the matrix is fixed per register pair.
+template <typename T, int RB>
+__device__ __forceinline__ void reg_pairc(typename Vec2<T>::type* v, const FOp& op, cptr<T> cf, uint32_t tl)
+{
+    T u0[8], u1[8];
+    load2x2<T>(cf, false, u0);
+    load2x2<T>(cf + 8, false, u1);
+    if (op.kb < 0) {
+        const bool s = (tl >> op.b) & 1u;
+        T u[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) u[k] = s ? u1[k] : u0[k];
+#define SV_CALL(K) rpair_k<T, RB, K, false>(v, u, 0u)
+        SV_K_SWITCH(op.ka, SV_CALL)
+#undef SV_CALL
+        return;
+    }
+    switch (op.ka * 4 + op.kb) {
+#define SV_CASE(A, B)                                                                                              \
+    case A * 4 + B: rpairc_k<T, RB, A, B>(v, u0, u1); break;
+        SV_RB_PAIRS(SV_CASE)
+#undef SV_CASE
+    default:
+        if constexpr (RB > 3) {
+            switch (op.ka * 4 + op.kb) {
+#define SV_CASE(A, B)                                                                                              \
+    case A * 4 + B: rpairc_k<T, RB, A, B>(v, u0, u1); break;
+                SV_RB4_PAIRS(SV_CASE)
+#undef SV_CASE
+            default: break;
+            }
+        }
+        break;
     }
 }
 
@@ -808,6 +884,7 @@ __device__ __forceinline__ void item_reg_fwd(const PassTables& tb, const FCirc& 
             continue;
         }
         if (op.kind == FK_QUAD) lds_op<T, RB>(v, lds, op, coef, false, tq, active, lays + cur);
+        else if (op.kind == FK_PAIRC) reg_pairc<T, RB>(v, op, coef + op.coef, tl);
         else reg_apply<T, RB>(v, op, coef + op.coef, false, tl, pzr, pzi);
     }
     if (active) {
@@ -982,7 +1059,8 @@ __device__ __forceinline__ void item_lds(const PassTables& tb, const FCirc& cc, 
         for (int o = ps.op_begin; o < ps.op_end; ++o) {
             const FOp op = tb.ops[o];
             if (op.kind == FK_PHASE && !phase_on(op, tile)) continue;  // uniform: not on this tile
-            lds_apply<T>(tileA, op, tb.coef, false, tq);
+            if (op.kind == FK_PAIRC) lds_pairc<T>(tileA, op, tb.coef, tq);
+            else lds_apply<T>(tileA, op, tb.coef, false, tq);
             __syncthreads();
         }
         for (uint32_t l = threadIdx.x; l < na; l += blockDim.x)
@@ -1140,31 +1218,43 @@ __global__ void k_pass_coef(const FCoefSpec* __restrict__ spec, int n, const FCo
     double* c = coef + s.coef;
     int cnt;
     if (s.nfactor > 0) {
-        // M = G_last ... G_first
-        double m[8] = {1, 0, 0, 0, 0, 0, 1, 0};
+        // M = G_last ... G_first; a two-branch product (out_diag 2) keeps M
+        // for the selector-0 branch and M1 for the selector-1 branch
+        double m[8] = {1, 0, 0, 0, 0, 0, 1, 0}, m1[8] = {1, 0, 0, 0, 0, 0, 1, 0};
         for (int k = 0; k < s.nfactor; ++k) {
-            double g[8], r[8];
-            gate2x2(factors[s.factor_begin + k], params, g);
+            const FCoefSpec& fk = factors[s.factor_begin + k];
+            double g[8];
+            gate2x2(fk, params, g);
+            const int br = s.out_diag == 2 ? fk.branch : 1;
+            for (int which = 0; which < 2; ++which) {
+                if (!((br >> which) & 1)) continue;
+                double* mm = which ? m1 : m;
+                double r[8];
 #pragma unroll
-            for (int row = 0; row < 2; ++row)
+                for (int row = 0; row < 2; ++row)
 #pragma unroll
-                for (int col = 0; col < 2; ++col) {
-                    // r[row][col] = sum_t g[row][t] * m[t][col]
-                    double re = 0, im = 0;
+                    for (int col = 0; col < 2; ++col) {
+                        // r[row][col] = sum_t g[row][t] * mm[t][col]
+                        double re = 0, im = 0;
 #pragma unroll
-                    for (int t = 0; t < 2; ++t) {
-                        const double gr = g[2 * (2 * row + t)], gi = g[2 * (2 * row + t) + 1];
-                        const double mr = m[2 * (2 * t + col)], mi = m[2 * (2 * t + col) + 1];
-                        re += gr * mr - gi * mi;
-                        im += gr * mi + gi * mr;
+                        for (int t = 0; t < 2; ++t) {
+                            const double gr = g[2 * (2 * row + t)], gi = g[2 * (2 * row + t) + 1];
+                            const double mr = mm[2 * (2 * t + col)], mi = mm[2 * (2 * t + col) + 1];
+                            re += gr * mr - gi * mi;
+                            im += gr * mi + gi * mr;
+                        }
+                        r[2 * (2 * row + col)] = re;
+                        r[2 * (2 * row + col) + 1] = im;
                     }
-                    r[2 * (2 * row + col)] = re;
-                    r[2 * (2 * row + col) + 1] = im;
-                }
 #pragma unroll
-            for (int k2 = 0; k2 < 8; ++k2) m[k2] = r[k2];
+                for (int k2 = 0; k2 < 8; ++k2) mm[k2] = r[k2];
+            }
         }
-        if (s.out_diag) {
+        if (s.out_diag == 2) {
+            for (int k = 0; k < 8; ++k) c[k] = m[k];
+            for (int k = 0; k < 8; ++k) c[8 + k] = m1[k];
+            cnt = 16;
+        } else if (s.out_diag) {
             c[0] = m[0]; c[1] = m[1]; c[2] = m[6]; c[3] = m[7];
             cnt = 4;
         } else {

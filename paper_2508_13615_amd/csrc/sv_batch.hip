@@ -144,7 +144,8 @@ uint32_t op_need(const FOp& f)
     switch (f.kind) {
     case FK_PAIR:
     case FK_PAIRR:
-    case FK_PAIRX: return 1u << f.a;
+    case FK_PAIRX:
+    case FK_PAIRC: return 1u << f.a;
     case FK_SWAP: return (1u << f.a) | (1u << f.b);
     default: return 0u;
     }
@@ -153,7 +154,7 @@ uint32_t op_need(const FOp& f)
 uint32_t op_touch(const FOp& f)
 {
     uint32_t m = f.cm | (1u << f.a);
-    if (f.kind == FK_SWAP || f.kind == FK_QUAD) m |= 1u << f.b;
+    if (f.kind == FK_SWAP || f.kind == FK_QUAD || f.kind == FK_PAIRC) m |= 1u << f.b;
     return m;
 }
 
@@ -266,7 +267,7 @@ void plan_layouts(std::vector<FOp>& pass_ops, int tq, int rb, int cb, const int3
             FOp f = pass_ops[i];
             const uint32_t S = r.first;
             f.ka = (int8_t)(((S >> f.a) & 1u) ? reg_index(S, f.a) : -1);
-            const bool two = f.kind == FK_SWAP || f.kind == FK_QUAD;
+            const bool two = f.kind == FK_SWAP || f.kind == FK_QUAD || f.kind == FK_PAIRC;
             f.kb = (int8_t)(two && ((S >> f.b) & 1u) ? reg_index(S, f.b) : -1);
             uint32_t cmk = 0;
             for (int q = 0; q < 32; ++q)
@@ -317,11 +318,22 @@ FCoefSpec factor_of(const BOp& o, int param_base)
 }
 
 // Forward-list gate fusion: a one-target op joins the previous op on the same
-// target with the same controls when no op in between touches any of their
-// qubits (ops on disjoint qubits commute).  A group of more than one op
-// becomes one op whose coefficients are the product of its gates (evaluated
-// on the device from the parameters).  Reverse passes keep the ops unfused:
-// each parameterised op needs its own gradient partial.
+// target when it may move back to that op (no op in between touches any of
+// its qubits: ops on disjoint qubits commute) and
+//   * it has the group's controls (a group without a selector), or
+//   * it has one control s and the group has none: the group becomes a
+//     two-branch group with selector s, and the op enters only the branch
+//     where s is 1 (a rotation followed by a CNOT from s becomes one op whose
+//     2x2 is U where s is 0 and X U where s is 1), or
+//   * the group has a selector s and the op is uncontrolled (both branches)
+//     or controlled by s alone (the second branch), or
+//   * the group's ops all have the one control s and the op is uncontrolled:
+//     the group becomes two-branch, its ops in the second branch and the op
+//     in both (a CNOT followed by a rotation of its target).
+// A group of more than one op becomes one op whose coefficients are the
+// product of its gates, per branch (evaluated on the device from the
+// parameters).  Reverse passes keep the ops unfused: each parameterised op
+// needs its own gradient partial.
 std::vector<FOp> fuse_forward(const std::vector<FOp>& ops, const std::vector<int>& src, const std::vector<BOp>& bops,
                               int param_base, std::vector<FCoefSpec>& cspec, std::vector<FCoefSpec>& cfac,
                               int& coef_total)
@@ -330,7 +342,9 @@ std::vector<FOp> fuse_forward(const std::vector<FOp>& ops, const std::vector<int
         FOp op;
         uint32_t ctrl;
         bool fusable;
+        int sel;                   // selector bit of a two-branch group, -1 if none
         std::vector<int> members;  // indices into bops
+        std::vector<int> branch;   // per member: 3 both branches, 2 the selector-1 branch
     };
     std::vector<Grp> g;
     int last[32];
@@ -344,15 +358,38 @@ std::vector<FOp> fuse_forward(const std::vector<FOp>& ops, const std::vector<int
         if (f.kind == FK_SWAP || f.kind == FK_QUAD) touch |= 1u << f.b;
         if (fus) {
             const int c = last[f.a];
-            bool ok = c >= 0 && g[c].fusable && g[c].op.a == f.a && g[c].ctrl == ctrl;
-            for (int q = 0; ok && q < 32; ++q)
-                if ((touch >> q) & 1u) ok = last[q] == c;
-            if (ok) {
-                g[c].members.push_back(src[i]);
-                continue;
+            if (c >= 0 && g[c].fusable && g[c].op.a == f.a) {
+                Grp& G = g[c];
+                bool later = false;  // a later group touched one of the op's qubits
+                for (int q = 0; q < 32; ++q)
+                    if ((touch >> q) & 1u) later = later || last[q] != c;
+                int tag = 0;
+                if (G.sel < 0 && G.ctrl == ctrl && !later) {
+                    tag = 3;
+                } else if (G.sel >= 0 && ctrl == 0) {
+                    tag = 3;  // touches only the target, whose latest group is G
+                } else if (G.sel >= 0 && ctrl == (1u << G.sel) && !later) {
+                    tag = 2;
+                } else if (G.sel < 0 && G.ctrl == 0 && popc(ctrl) == 1 && last[__builtin_ctz(ctrl)] <= c) {
+                    G.sel = __builtin_ctz(ctrl);  // no later group touched it: the op moves back to G
+                    last[G.sel] = c;
+                    tag = 2;
+                } else if (G.sel < 0 && popc(G.ctrl) == 1 && ctrl == 0) {
+                    // a group controlled by one qubit s, then an uncontrolled op:
+                    // the group's ops become the s = 1 branch
+                    G.sel = __builtin_ctz(G.ctrl);
+                    G.ctrl = 0;
+                    for (int& b : G.branch) b = 2;
+                    tag = 3;
+                }
+                if (tag) {
+                    G.members.push_back(src[i]);
+                    G.branch.push_back(tag);
+                    continue;
+                }
             }
         }
-        g.push_back({f, ctrl, fus, {src[i]}});
+        g.push_back({f, ctrl, fus, -1, {src[i]}, {3}});
         for (int q = 0; q < 32; ++q)
             if ((touch >> q) & 1u) last[q] = (int)g.size() - 1;
     }
@@ -367,9 +404,11 @@ std::vector<FOp> fuse_forward(const std::vector<FOp>& ops, const std::vector<int
             all_diag = all_diag && diag_gate(bops[m].gate);
             all_real = all_real && real_gate(bops[m].gate);
         }
+        const bool two = gr.sel >= 0;
         FOp f = gr.op;
-        f.kind = all_diag ? FK_DIAG : (all_real ? FK_PAIRR : FK_PAIR);
+        f.kind = two ? FK_PAIRC : (all_diag ? FK_DIAG : (all_real ? FK_PAIRR : FK_PAIR));
         f.cm = gr.ctrl;
+        if (two) f.b = gr.sel;
         f.slot = -1;
         f.coef = coef_total;
         FCoefSpec cs;
@@ -379,10 +418,14 @@ std::vector<FOp> fuse_forward(const std::vector<FOp>& ops, const std::vector<int
         cs.coef = coef_total;
         cs.nfactor = (int)gr.members.size();
         cs.factor_begin = (int)cfac.size();
-        cs.out_diag = all_diag ? 1 : 0;
-        for (int m : gr.members) cfac.push_back(factor_of(bops[m], param_base));
+        cs.out_diag = two ? 2 : (all_diag ? 1 : 0);
+        for (size_t k = 0; k < gr.members.size(); ++k) {
+            FCoefSpec fa = factor_of(bops[gr.members[k]], param_base);
+            fa.branch = gr.branch[k];
+            cfac.push_back(fa);
+        }
         cspec.push_back(cs);
-        coef_total += all_diag ? 4 : 8;
+        coef_total += two ? 16 : (all_diag ? 4 : 8);
         out.push_back(f);
     }
     return out;

@@ -20,9 +20,14 @@ constexpr int kSwzBits = 4;
 
 // FK_PAIR: complex 2x2 on a target; FK_PAIRR: real 2x2 (H, RY); FK_PAIRX: the
 // exchange of the pair (X).  All three keep the complex 2x2 in the coefficient
-// table, so the LDS-sweep form treats them alike.
+// table, so the LDS-sweep form treats them alike.  FK_PAIRC (forward lists
+// only): a complex 2x2 on target a that depends on one selector bit b, the
+// first matrix where bit b is 0 and the second where it is 1 (16 doubles): a
+// run of one-target gates on a in which some gates are controlled by b, such
+// as a rotation followed by a CNOT from b.
 enum FusedKind : int32_t {
-    FK_PAIR = 0, FK_DIAG = 1, FK_PHASE = 2, FK_SWAP = 3, FK_QUAD = 4, FK_LAYOUT = 5, FK_PAIRR = 6, FK_PAIRX = 7
+    FK_PAIR = 0, FK_DIAG = 1, FK_PHASE = 2, FK_SWAP = 3, FK_QUAD = 4, FK_LAYOUT = 5, FK_PAIRR = 6, FK_PAIRX = 7,
+    FK_PAIRC = 8
 };
 
 // One op of a pass, in tile-local bit positions.  FK_LAYOUT (register-tiled
@@ -42,13 +47,14 @@ enum FusedKind : int32_t {
 // before applying the group's product once (reverse sweeps ignore kb).
 struct FOp {
     int32_t kind;
-    int32_t a, b;   // local target bits (b: second target of SWAP / QUAD)
+    int32_t a, b;   // local target bits (b: second target of SWAP / QUAD, selector of FK_PAIRC)
     uint32_t cm;    // local bits that must all be 1 (controls; for FK_PHASE also the target)
     int32_t coef;   // offset of the op's coefficients in the coefficient table (doubles)
     int32_t slot;   // gradient slot within the circuit, -1 if not parameterised
     int8_t gen;     // generator (GenKind) of a parameterised op
     // Register-tiled passes, for the layout the op runs in: the register bits
-    // holding a and b (-1 where the bit is a lane bit), and cm split into its
+    // holding a and b (-1 where the bit is a lane bit; b for SWAP, QUAD and
+    // FK_PAIRC), and cm split into its
     // register bits (as register indices, cmk) and its lane bits (cml).
     int8_t ka, kb;
     uint8_t cmk;
@@ -113,7 +119,9 @@ struct FSeg {
 // product of the factor gates' 2x2 matrices, factors [factor_begin,
 // factor_begin + nfactor) of the factor table in the order applied; each
 // factor is an FCoefSpec whose fixed[0..7] holds the full 2x2 of a fixed gate.
-// out_diag = 1 writes the product's diagonal only (d0, d1), else all 8 values.
+// out_diag = 1 writes the product's diagonal only (d0, d1); 2 writes two
+// products (FK_PAIRC: 16 values), each factor entering the first, the second
+// or both as its `branch` says (1, 2, 3); 0 writes all 8 values.
 struct FCoefSpec {
     int32_t gate;
     int32_t pidx;    // global parameter index, -1 = fixed angle `value`
@@ -122,7 +130,8 @@ struct FCoefSpec {
     double value;
     double fixed[32];
     int32_t nfactor, factor_begin;
-    int32_t out_diag, pad_;
+    int32_t out_diag;
+    int32_t branch;  // factor entries of an out_diag = 2 product
 };
 
 struct PassTables {

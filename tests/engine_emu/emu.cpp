@@ -103,6 +103,7 @@ static double ref_energy(int n, const std::vector<sv_op>& ops, const std::vector
 
 // ---------------- emulation of the kernels -------------------------------
 static int errors = 0;
+static long pairc_lane = 0, pairc_reg = 0;  // two-branch ops replayed, by selector placement
 #define CHECK(c, ...) do { if (!(c)) { ++errors; if (errors < 20) { printf("FAIL %s:%d ", __FILE__, __LINE__); printf(__VA_ARGS__); printf("\n"); } } } while (0)
 
 static void gate2x2_h(const FCoefSpec& f, const double* params, cd u[4])
@@ -121,17 +122,29 @@ static void gate2x2_h(const FCoefSpec& f, const double* params, cd u[4])
 static void coef_eval(const FCoefSpec& s, const std::vector<FCoefSpec>& fac, const double* params, double* c)
 {
     if (s.nfactor > 0) {
-        cd m[4] = {1, 0, 0, 1};
+        cd mm[2][4] = {{1, 0, 0, 1}, {1, 0, 0, 1}};
         for (int k = 0; k < s.nfactor; ++k) {
-            cd g[4], r[4];
-            gate2x2_h(fac[s.factor_begin + k], params, g);
-            r[0] = g[0] * m[0] + g[1] * m[2];
-            r[1] = g[0] * m[1] + g[1] * m[3];
-            r[2] = g[2] * m[0] + g[3] * m[2];
-            r[3] = g[2] * m[1] + g[3] * m[3];
-            for (int q = 0; q < 4; ++q) m[q] = r[q];
+            const FCoefSpec& fk = fac[s.factor_begin + k];
+            const int br = s.out_diag == 2 ? fk.branch : 1;
+            CHECK(br >= 1 && br <= 3, "factor branch %d", br);
+            cd g[4];
+            gate2x2_h(fk, params, g);
+            for (int w = 0; w < 2; ++w) {
+                if (!((br >> w) & 1)) continue;
+                cd* m = mm[w];
+                cd r[4];
+                r[0] = g[0] * m[0] + g[1] * m[2];
+                r[1] = g[0] * m[1] + g[1] * m[3];
+                r[2] = g[2] * m[0] + g[3] * m[2];
+                r[3] = g[2] * m[1] + g[3] * m[3];
+                for (int q = 0; q < 4; ++q) m[q] = r[q];
+            }
         }
-        if (s.out_diag) {
+        const cd* m = mm[0];
+        if (s.out_diag == 2) {
+            for (int w = 0; w < 2; ++w)
+                for (int q = 0; q < 4; ++q) { c[8 * w + 2 * q] = mm[w][q].real(); c[8 * w + 2 * q + 1] = mm[w][q].imag(); }
+        } else if (s.out_diag) {
             CHECK(std::abs(m[1]) == 0 && std::abs(m[2]) == 0, "diagonal fusion has off-diagonal terms");
             c[0] = m[0].real(); c[1] = m[0].imag(); c[2] = m[3].real(); c[3] = m[3].imag();
         } else {
@@ -223,6 +236,26 @@ static void reg_apply_h(cd* v, int rb, const FOp& op, const double* cf, bool dag
             const cd a = v[j], b = v[j1];
             v[j] = u[0] * a + u[1] * b;
             v[j1] = u[2] * a + u[3] * b;
+        }
+        break;
+    }
+    case FK_PAIRC: {
+        // forward only: the 2x2 depends on selector bit b (cf[0..7] where it is 0, cf[8..15] where it is 1)
+        CHECK(!dagger, "two-branch op in a reverse list");
+        ++(op.kb >= 0 ? pairc_reg : pairc_lane);
+        CHECK(op.cm == 0, "two-branch op with controls");
+        CHECK(L.pos[nl + op.ka] == op.a, "two-branch target %d not at register bit %d", op.a, op.ka);
+        if (op.kb >= 0) CHECK(L.pos[nl + op.kb] == op.b, "selector kb %d does not hold %d", op.kb, op.b);
+        else for (int r = 0; r < rb; ++r) CHECK(L.pos[nl + r] != op.b, "selector in registers but kb = -1");
+        for (int j = 0; j < R; ++j) {
+            if (j & (1 << op.ka)) continue;
+            const int j1 = j | (1 << op.ka);
+            const bool s = ((tl | off[j]) >> op.b) & 1u;
+            const double* m = cf + (s ? 8 : 0);
+            const cd u0(m[0], m[1]), u1(m[2], m[3]), u2(m[4], m[5]), u3(m[6], m[7]);
+            const cd a = v[j], b = v[j1];
+            v[j] = u0 * a + u1 * b;
+            v[j1] = u2 * a + u3 * b;
         }
         break;
     }
@@ -815,6 +848,12 @@ int main(int argc, char** argv)
                     test({qft(11), phase_heavy(rng, 12, 120, 6)}, dt, tile, apt, wg, nm, rng);
                 }
             }
+    printf("two-branch ops replayed: %ld with the selector on a lane bit, %ld on a register bit\n", pairc_lane,
+           pairc_reg);
+    if (!pairc_lane || !pairc_reg) {
+        ++errors;
+        printf("FAIL: the circuits do not exercise both selector placements of the two-branch op\n");
+    }
     printf("%s (%d errors)\n", errors ? "FAILED" : "all ok", errors);
     return errors ? 1 : 0;
 }

@@ -67,6 +67,77 @@ def test_batch_forward_states_and_energies(dtype, tile, apt):
         assert abs(e[i] - e_ref) <= 4 * TOL[dtype] * n, (i, e[i], e_ref)
 
 
+def two_branch_circuit(n, rng, reps):
+    """Runs of one-target gates on a target t in which some gates are
+    controlled by one other qubit c: the forward passes fuse each run into one
+    2x2 chosen by bit c.  Four patterns: rotation, CNOT, rotation; CNOT then
+    uncontrolled gates; controlled diagonal and phase gates inside a run;
+    controlled U2 and Z between uncontrolled gates.  Each parameterised gate
+    has a parameter of its own (the two-term shift rule needs that); returns
+    (ops, number of parameters)."""
+    ops = []
+    n_params = 0
+    for _ in range(reps):
+        t, c = (int(x) for x in rng.permutation(n)[:2])
+        p = n_params
+        v = float(rng.uniform(0, 2 * math.pi))
+        pat = int(rng.integers(0, 4))
+        if pat == 0:
+            ops += [W.Op("U2", (), (t,), -1, 0.0, W.haar_unitary(1, rng)), W.Op("X", (c,), (t,)),
+                    W.Op("RY", (), (t,), p, v)]
+            n_params += 1
+        elif pat == 1:
+            ops += [W.Op("X", (c,), (t,)), W.Op("RZ", (), (t,), p, v), W.Op("H", (), (t,))]
+            n_params += 1
+        elif pat == 2:
+            ops += [W.Op("RX", (), (t,), p, v), W.Op("RZ", (c,), (t,), -1, v / 3),
+                    W.Op("PHASE", (c,), (t,), -1, v / 5), W.Op("Y", (), (t,))]
+            n_params += 1
+        else:
+            ops += [W.Op("H", (), (t,)), W.Op("U2", (c,), (t,), -1, 0.0, W.haar_unitary(1, rng)),
+                    W.Op("S", (), (t,)), W.Op("Z", (c,), (t,))]
+    return ops, n_params
+
+
+@pytest.mark.parametrize("apt", [16, 8])
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("tile", [4, 5, 0])
+def test_two_branch_fusion_states_and_energies(dtype, tile, apt):
+    # 3 qubits runs the LDS-sweep form; the others put selectors on lane and
+    # register bits across the layouts
+    rng = np.random.default_rng(5100 + tile)
+    circs, params, n_gates = [], [], 0
+    for n in (3, 6, 10):
+        ops, npar = two_branch_circuit(n, rng, 30)
+        n_gates += len(ops)
+        circs.append((n, ops, npar, "sum_zz"))
+        params.append(rng.uniform(0, 2 * math.pi, size=npar))
+    b = sv.Batch(circs, dtype, tile_qubits=tile, amps_per_thread=apt, with_grad=False)
+    e, _ = b.run(np.concatenate(params))
+    assert b.info()["fused_ops"] < n_gates // 2  # runs of 3-4 gates became one op each
+    for i, (n, ops, npar, obs) in enumerate(circs):
+        ref = oracle.run_circuit(oracle.zero_state(n), ops, params[i])
+        got = b.state(i).astype(np.complex128)
+        err = float(np.max(np.abs(got - ref)))
+        assert err <= 4 * TOL[dtype], (i, n, err)
+        e_ref = oracle.expval_obs(ref, obs_terms(obs, n))
+        assert abs(e[i] - e_ref) <= 4 * TOL[dtype] * n, (i, e[i], e_ref)
+
+
+@pytest.mark.parametrize("dtype,tol", [("c128", 1e-10), ("c64", 1e-4)])
+def test_two_branch_fusion_gradients_vs_oracle(dtype, tol):
+    # with the adjoint: forward passes fused, reverse passes gate by gate
+    rng = np.random.default_rng(5200)
+    n = 9
+    ops, npar = two_branch_circuit(n, rng, 25)
+    th = rng.uniform(0, 2 * math.pi, size=npar)
+    b = sv.Batch([(n, ops, npar, "sum_z")], dtype, tile_qubits=6, with_grad=True)
+    e, g = b.run(th)
+    g_ref = oracle.param_shift_grad(n, ops, th, W.sum_z(n))
+    assert abs(e[0] - oracle.energy(n, ops, th, W.sum_z(n))) <= tol * n
+    assert float(np.max(np.abs(g - g_ref))) <= tol
+
+
 @pytest.mark.parametrize("apt", [16, 8])
 @pytest.mark.parametrize("dtype,tol", [("c128", 1e-10), ("c64", 1e-4)])
 def test_batch_gradients_vs_oracle(dtype, tol, apt):
