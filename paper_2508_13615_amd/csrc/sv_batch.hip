@@ -88,8 +88,12 @@ sv_status validate(int n, const sv_op& s, int n_params, int index, BOp* out)
 }
 
 // Greedy commutation-aware grouping of ops into passes of at most tq qubits.
-void schedule(int n, int tq, int cb, const std::vector<BOp>& ops, std::vector<std::vector<int>>& pass_ops,
-              std::vector<uint64_t>& pass_q)
+// With `reserve`, a qubit that joins the tile brings the other qubits of the
+// next multi-qubit op on it (subset phases aside) when they still fit, so that
+// op can follow in the same pass: a rotation and the CNOT ladder step onto its
+// qubit land together (fewer passes for ladders, and the pair fuses).
+void schedule_greedy(int n, int tq, int cb, const std::vector<BOp>& ops, bool reserve,
+                     std::vector<std::vector<int>>& pass_ops, std::vector<uint64_t>& pass_q)
 {
     const int m = (int)ops.size();
     std::vector<std::vector<int>> qops(n);
@@ -124,15 +128,47 @@ void schedule(int n, int tq, int cb, const std::vector<BOp>& ops, std::vector<st
                 done[i] = 1;
                 --remaining;
                 po.push_back(i);
+                const uint64_t grown = np & ~P;
                 P = np;
                 nparam += o.pidx >= 0;
                 for (int j = 0; j < o.nc + o.nt; ++j) ++front[o.q[j]];
                 added = true;
+                if (reserve) {
+                    for (uint64_t gq = grown; gq; gq &= gq - 1) {
+                        const int q = __builtin_ctzll(gq);
+                        for (size_t k = front[q]; k < qops[q].size(); ++k) {
+                            const BOp& nx = ops[qops[q][k]];
+                            if (subset_phase_gate(nx.gate)) continue;
+                            if (nx.qmask() & ~(1ull << q)) {
+                                const uint64_t r = P | nx.qmask();
+                                if (popc(r) <= tq) P = r;
+                                break;
+                            }
+                        }
+                    }
+                }
             }
         }
         for (int q = 0; q < n && popc(P) < tq; ++q) P |= 1ull << q;
         pass_ops.push_back(po);
         pass_q.push_back(P);
+    }
+}
+
+// Both greedy forms, keeping the one with fewer passes (the plain one on a
+// tie): reserving helps ladders (the 32-qubit HEA: 26 passes instead of 35)
+// and costs circuits whose two-qubit gates jump about (the universal
+// circuit: 124 instead of 112).
+void schedule(int n, int tq, int cb, const std::vector<BOp>& ops, std::vector<std::vector<int>>& pass_ops,
+              std::vector<uint64_t>& pass_q)
+{
+    std::vector<std::vector<int>> po_r;
+    std::vector<uint64_t> pq_r;
+    schedule_greedy(n, tq, cb, ops, false, pass_ops, pass_q);
+    schedule_greedy(n, tq, cb, ops, true, po_r, pq_r);
+    if (po_r.size() < pass_ops.size()) {
+        pass_ops.swap(po_r);
+        pass_q.swap(pq_r);
     }
 }
 
