@@ -772,6 +772,16 @@ __device__ __forceinline__ bool phase_on(const FOp& op, int tile)
     return ((uint32_t)tile & (uint32_t)op.b) == (uint32_t)op.b;
 }
 
+// Whether an op acts on tile `tile` (uniform): one-target ops and subset
+// phases carry their bits outside the tile packed in b, and act only on the
+// tiles whose index holds them all; other kinds use b otherwise.
+__device__ __forceinline__ bool op_on(const FOp& op, int tile)
+{
+    const bool gated = op.kind == FK_PHASE || op.kind == FK_PAIR || op.kind == FK_PAIRR || op.kind == FK_PAIRX ||
+                       op.kind == FK_DIAG;
+    return !gated || phase_on(op, tile);
+}
+
 // The next op's descriptor is fetched one op ahead, so its load overlaps the
 // current op's arithmetic.
 struct OpPre {
@@ -799,7 +809,10 @@ __device__ __forceinline__ void lds_op(typename Vec2<T>::type* v, typename Vec2<
     __syncthreads();
 }
 
-template <typename T, int RB>
+// GATED: the pass holds one-target ops with controls outside the tile, which
+// act only on the tiles that hold those bits; passes without them take a
+// kernel that does not test for it.
+template <typename T, int RB, bool GATED>
 __device__ __forceinline__ void item_reg_fwd(const PassTables& tb, const FCirc& cc, int pidx, int tile,
                                              typename Vec2<T>::type* lds)
 {
@@ -809,6 +822,7 @@ __device__ __forceinline__ void item_reg_fwd(const PassTables& tb, const FCirc& 
     const cptr<FPass> pp = as_const(tb.passes) + cc.pass_begin + pidx;
     const cptr<FLayout> lays = as_const(tb.lays);
     const int op_begin = pp->op_begin, op_end = pp->op_end;
+    const bool gated = GATED && pp->gated != 0;
     const bool active = threadIdx.x < (1u << (tq - RB));
     const uint64_t tile_base = tile_base_of(pp->free_mask, (uint64_t)tile);
     V* const psi = (V*)cc.psi;
@@ -885,6 +899,7 @@ __device__ __forceinline__ void item_reg_fwd(const PassTables& tb, const FCirc& 
         }
         if (op.kind == FK_QUAD) lds_op<T, RB>(v, lds, op, coef, false, tq, active, lays + cur);
         else if (op.kind == FK_PAIRC) reg_pairc<T, RB>(v, op, coef + op.coef, tl);
+        else if (gated && op.kind != FK_PHASE && !op_on(op, tile)) continue;  // controls outside the tile not all 1 here
         else reg_apply<T, RB>(v, op, coef + op.coef, false, tl, pzr, pzi);
     }
     if (active) {
@@ -953,8 +968,8 @@ __device__ __forceinline__ void item_reg_rev(const PassTables& tb, const FCirc& 
             tl = tl2;
             continue;
         }
-        // a subset phase acts on this tile only if the tile holds its bits outside it
-        const bool on = op.kind != FK_PHASE || phase_on(op, tile);
+        // an op with bits outside the tile acts here only if the tile holds them all
+        const bool on = op_on(op, tile);
         if (op.slot >= 0) {
             const double c = wave_sum(active && on ? reg_gen_inner<T, RB>(v, w, op, tl) : 0.0);
             if ((threadIdx.x & 63) == 0) wpart[nslot * (blockDim.x >> 6) + (threadIdx.x >> 6)] = c;
@@ -1014,8 +1029,9 @@ __device__ __forceinline__ void item_observable(const PassTables& tb, const FCir
 }
 
 // A pass of a circuit whose tile is smaller than a workgroup's register tile:
-// the tile stays in LDS and every op sweeps it.
-template <typename T>
+// the tile stays in LDS and every op sweeps it.  GATED as in item_reg_fwd
+// (forward passes; reverse passes always test).
+template <typename T, bool GATED>
 __device__ __forceinline__ void item_lds(const PassTables& tb, const FCirc& cc, bool fwd, int pidx, int tile,
                                          typename Vec2<T>::type* tileA, typename Vec2<T>::type* tileB,
                                          uint64_t* hi_map, double* wpart)
@@ -1058,7 +1074,8 @@ __device__ __forceinline__ void item_lds(const PassTables& tb, const FCirc& cc, 
         __syncthreads();
         for (int o = ps.op_begin; o < ps.op_end; ++o) {
             const FOp op = tb.ops[o];
-            if (op.kind == FK_PHASE && !phase_on(op, tile)) continue;  // uniform: not on this tile
+            // uniform: not on this tile
+            if (GATED ? !op_on(op, tile) : op.kind == FK_PHASE && !phase_on(op, tile)) continue;
             if (op.kind == FK_PAIRC) lds_pairc<T>(tileA, op, tb.coef, tq);
             else lds_apply<T>(tileA, op, tb.coef, false, tq);
             __syncthreads();
@@ -1076,7 +1093,7 @@ __device__ __forceinline__ void item_lds(const PassTables& tb, const FCirc& cc, 
     int nslot = 0;
     for (int o = ps.rop_end - 1; o >= ps.rop_begin; --o) {
         const FOp op = tb.ops[o];
-        const bool on = op.kind != FK_PHASE || phase_on(op, tile);  // uniform
+        const bool on = op_on(op, tile);  // uniform
         if (op.slot >= 0) {
             const double c = on ? wave_sum(lds_gen_inner<T>(tileA, tileB, op, tq)) : 0.0;
             if ((threadIdx.x & 63) == 0) wpart[nslot * (blockDim.x >> 6) + (threadIdx.x >> 6)] = c;
@@ -1143,7 +1160,7 @@ constexpr int pass_waves_per_eu()
     else return !REV && RB == 3 ? 4 : 3;
 }
 
-template <typename T, int RB>
+template <typename T, int RB, bool GATED>
 __global__ void __launch_bounds__(kMaxPassThreads, (pass_waves_per_eu<T, RB, false>()))
 k_pass_fwd(PassTables tb, int64_t item_begin, int64_t item_end)
 {
@@ -1154,8 +1171,8 @@ k_pass_fwd(PassTables tb, int64_t item_begin, int64_t item_end)
         const FSeg sg = seg_of(tb, item);
         const int tile = (int)(item - sg.first);
         const FCirc cc = ld_const(as_const(tb.circs) + sg.circ);
-        if (cc.reg) item_reg_fwd<T, RB>(tb, cc, sg.stage, tile, (V*)L.tileA);
-        else item_lds<T>(tb, cc, true, sg.stage, tile, (V*)L.tileA, (V*)L.tileB, L.hi_map, L.wpart);
+        if (cc.reg) item_reg_fwd<T, RB, GATED>(tb, cc, sg.stage, tile, (V*)L.tileA);
+        else item_lds<T, GATED>(tb, cc, true, sg.stage, tile, (V*)L.tileA, (V*)L.tileB, L.hi_map, L.wpart);
         __syncthreads();  // LDS is reused by the next item of this workgroup
     }
 }
@@ -1185,7 +1202,7 @@ k_pass_rev(PassTables tb, int64_t item_begin, int64_t item_end)
         const FCirc cc = ld_const(as_const(tb.circs) + sg.circ);
         const int pidx = 2 * cc.n_pass - sg.stage;  // reverse stage n_pass+1+r -> pass n_pass-1-r
         if (cc.rreg) item_reg_rev<T, RB>(tb, cc, pidx, tile, (V*)L.tileA, L.wpart);
-        else item_lds<T>(tb, cc, false, pidx, tile, (V*)L.tileA, (V*)L.tileB, L.hi_map, L.wpart);
+        else item_lds<T, true>(tb, cc, false, pidx, tile, (V*)L.tileA, (V*)L.tileB, L.hi_map, L.wpart);
         __syncthreads();
     }
 }
@@ -1330,9 +1347,11 @@ hipError_t pass_engine_prepare(size_t lds_bytes)
 {
     static size_t limit = 0;
     if (lds_bytes <= limit) return hipSuccess;
-    const void* f[] = {(const void*)k_pass_fwd<double, 3>, (const void*)k_pass_fwd<double, 4>,
-                       (const void*)k_pass_rev<double, 3>, (const void*)k_pass_fwd<float, 3>,
-                       (const void*)k_pass_fwd<float, 4>,  (const void*)k_pass_rev<float, 3>,
+    const void* f[] = {(const void*)k_pass_fwd<double, 3, false>, (const void*)k_pass_fwd<double, 4, false>,
+                       (const void*)k_pass_fwd<double, 3, true>,  (const void*)k_pass_fwd<double, 4, true>,
+                       (const void*)k_pass_rev<double, 3>,        (const void*)k_pass_fwd<float, 3, false>,
+                       (const void*)k_pass_fwd<float, 4, false>,  (const void*)k_pass_fwd<float, 3, true>,
+                       (const void*)k_pass_fwd<float, 4, true>,   (const void*)k_pass_rev<float, 3>,
                        (const void*)k_pass_rev<float, 4>};
     for (const void* k : f) {
         const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
@@ -1343,14 +1362,19 @@ hipError_t pass_engine_prepare(size_t lds_bytes)
 }
 
 template <typename T>
-static void launch_items_t(const PassTables& tb, int mode, unsigned grid, int threads, size_t lds, hipStream_t s,
-                           int64_t b, int64_t e)
+static void launch_items_t(const PassTables& tb, int mode, bool gated, unsigned grid, int threads, size_t lds,
+                           hipStream_t s, int64_t b, int64_t e)
 {
     if (mode == PM_OBS) {
         hipLaunchKernelGGL((k_pass_obs<T>), dim3(grid), dim3(threads), 0, s, tb, b, e);
     } else if (mode == PM_FWD) {
-        if (tb.reg_bits == 3) hipLaunchKernelGGL((k_pass_fwd<T, 3>), dim3(grid), dim3(threads), lds, s, tb, b, e);
-        else hipLaunchKernelGGL((k_pass_fwd<T, 4>), dim3(grid), dim3(threads), lds, s, tb, b, e);
+        if (tb.reg_bits == 3) {
+            if (gated) hipLaunchKernelGGL((k_pass_fwd<T, 3, true>), dim3(grid), dim3(threads), lds, s, tb, b, e);
+            else hipLaunchKernelGGL((k_pass_fwd<T, 3, false>), dim3(grid), dim3(threads), lds, s, tb, b, e);
+        } else {
+            if (gated) hipLaunchKernelGGL((k_pass_fwd<T, 4, true>), dim3(grid), dim3(threads), lds, s, tb, b, e);
+            else hipLaunchKernelGGL((k_pass_fwd<T, 4, false>), dim3(grid), dim3(threads), lds, s, tb, b, e);
+        }
     } else if constexpr (sizeof(T) == 8) {
         hipLaunchKernelGGL((k_pass_rev<T, 3>), dim3(grid), dim3(threads), lds, s, tb, b, e);
     } else {
@@ -1360,7 +1384,7 @@ static void launch_items_t(const PassTables& tb, int mode, unsigned grid, int th
 }
 
 hipError_t launch_pass_items(const PassTables& tb, int dtype, int mode, int64_t item_begin, int64_t item_end,
-                             int threads, size_t lds_bytes, hipStream_t s)
+                             int threads, size_t lds_bytes, hipStream_t s, bool gated)
 {
     const int64_t n = item_end - item_begin;
     if (n <= 0) return hipSuccess;
@@ -1369,8 +1393,8 @@ hipError_t launch_pass_items(const PassTables& tb, int dtype, int mode, int64_t 
     // blocks x threads below 2^32); the kernels' item loops cover the rest
     const int64_t cap = std::min<int64_t>(1 << 30, 0xffffffffll / threads);
     const unsigned grid = (unsigned)(n < cap ? n : cap);
-    if (dtype == SV_C128) launch_items_t<double>(tb, mode, grid, threads, lds_bytes, s, item_begin, item_end);
-    else launch_items_t<float>(tb, mode, grid, threads, lds_bytes, s, item_begin, item_end);
+    if (dtype == SV_C128) launch_items_t<double>(tb, mode, gated, grid, threads, lds_bytes, s, item_begin, item_end);
+    else launch_items_t<float>(tb, mode, gated, grid, threads, lds_bytes, s, item_begin, item_end);
     return hipGetLastError();
 }
 

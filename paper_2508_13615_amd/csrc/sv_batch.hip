@@ -87,12 +87,26 @@ sv_status validate(int n, const sv_op& s, int n_params, int index, BOp* out)
     return SV_OK;
 }
 
+// The qubits an op needs inside a pass's tile (P: the tile so far).  A subset
+// phase joins on any one of its qubits (its target if none is in the tile).
+// A one-target op needs its target only: a control outside the tile is
+// constant over a tile, so it just selects the tiles the op acts on (the
+// kernels test the tile index), as a control on a non-local qubit selects the
+// processes that act in the paper's distributed scheme.  Two-target ops need
+// all their qubits.
+uint64_t tile_need(const BOp& o, uint64_t P, bool free_ctrl)
+{
+    if (subset_phase_gate(o.gate)) return (o.qmask() & P) ? 0ull : (1ull << o.q[o.nc]);
+    if (o.nt == 1 && free_ctrl) return 1ull << o.q[o.nc];
+    return o.qmask();
+}
+
 // Greedy commutation-aware grouping of ops into passes of at most tq qubits.
 // With `reserve`, a qubit that joins the tile brings the other qubits of the
 // next multi-qubit op on it (subset phases aside) when they still fit, so that
 // op can follow in the same pass: a rotation and the CNOT ladder step onto its
 // qubit land together (fewer passes for ladders, and the pair fuses).
-void schedule_greedy(int n, int tq, int cb, const std::vector<BOp>& ops, bool reserve,
+void schedule_greedy(int n, int tq, int cb, const std::vector<BOp>& ops, bool reserve, bool free_ctrl,
                      std::vector<std::vector<int>>& pass_ops, std::vector<uint64_t>& pass_q)
 {
     const int m = (int)ops.size();
@@ -120,9 +134,7 @@ void schedule_greedy(int n, int tq, int cb, const std::vector<BOp>& ops, bool re
                     ready = qops[q][front[q]] == i;
                 }
                 if (!ready) continue;
-                uint64_t np = P | o.qmask();
-                if (subset_phase_gate(o.gate))  // joins on one qubit in the tile (its target, if none is)
-                    np = (o.qmask() & P) ? P : (P | (1ull << o.q[o.nc]));
+                const uint64_t np = P | tile_need(o, P, free_ctrl);
                 if (popc(np) > tq) continue;
                 if (o.pidx >= 0 && nparam >= kMaxPassSlots) continue;
                 done[i] = 1;
@@ -140,7 +152,7 @@ void schedule_greedy(int n, int tq, int cb, const std::vector<BOp>& ops, bool re
                             const BOp& nx = ops[qops[q][k]];
                             if (subset_phase_gate(nx.gate)) continue;
                             if (nx.qmask() & ~(1ull << q)) {
-                                const uint64_t r = P | nx.qmask();
+                                const uint64_t r = P | tile_need(nx, P, free_ctrl);
                                 if (popc(r) <= tq) P = r;
                                 break;
                             }
@@ -155,20 +167,26 @@ void schedule_greedy(int n, int tq, int cb, const std::vector<BOp>& ops, bool re
     }
 }
 
-// Both greedy forms, keeping the one with fewer passes (the plain one on a
-// tie): reserving helps ladders (the 32-qubit HEA: 26 passes instead of 35)
-// and costs circuits whose two-qubit gates jump about (the universal
-// circuit: 124 instead of 112).
+// Four greedy forms, keeping the one with the fewest passes (the first of
+// them on a tie): with or without reserving room for the next multi-qubit op
+// of a joining qubit, and with controls of one-target ops inside the tile or
+// left outside.  Reserving helps ladders (the 32-qubit HEA: 26 passes instead
+// of 35); controls left outside help circuits whose controls range over the
+// whole register (the 32-qubit universal circuit: 7 passes instead of 112)
+// but leave the HEA's CNOTs unfused and take it to 32.
 void schedule(int n, int tq, int cb, const std::vector<BOp>& ops, std::vector<std::vector<int>>& pass_ops,
               std::vector<uint64_t>& pass_q)
 {
-    std::vector<std::vector<int>> po_r;
-    std::vector<uint64_t> pq_r;
-    schedule_greedy(n, tq, cb, ops, false, pass_ops, pass_q);
-    schedule_greedy(n, tq, cb, ops, true, po_r, pq_r);
-    if (po_r.size() < pass_ops.size()) {
-        pass_ops.swap(po_r);
-        pass_q.swap(pq_r);
+    bool have = false;
+    for (int form = 0; form < 4; ++form) {
+        std::vector<std::vector<int>> po;
+        std::vector<uint64_t> pq;
+        schedule_greedy(n, tq, cb, ops, (form & 1) != 0, (form & 2) != 0, po, pq);
+        if (!have || po.size() < pass_ops.size()) {
+            pass_ops.swap(po);
+            pass_q.swap(pq);
+            have = true;
+        }
     }
 }
 
@@ -387,8 +405,8 @@ std::vector<FOp> fuse_forward(const std::vector<FOp>& ops, const std::vector<int
     for (int& x : last) x = -1;
     for (size_t i = 0; i < ops.size(); ++i) {
         const FOp& f = ops[i];
-        // a subset phase with qubits outside the tile stays on its own (it may be chained)
-        const bool fus = one_target_kind(f.kind) && !(f.kind == FK_PHASE && f.b != 0);
+        // an op with qubits outside the tile stays on its own (a subset phase may be chained)
+        const bool fus = one_target_kind(f.kind) && f.b == 0;
         const uint32_t ctrl = f.kind == FK_PHASE ? (f.cm & ~(1u << f.a)) : f.cm;
         uint32_t touch = f.cm | (1u << f.a);
         if (f.kind == FK_SWAP || f.kind == FK_QUAD) touch |= 1u << f.b;
@@ -479,6 +497,7 @@ struct sv_batch_s {
     int reg_bits, rreg_bits;
     size_t lds_fwd, lds_rev;  // dynamic LDS of forward and reverse workgroups
     std::vector<int64_t> level_first;  // per level: forward, observable, reverse item ranges (4 bounds)
+    std::vector<uint8_t> level_gated;  // per level: 1 if a forward pass of the level has FPass.gated set
     int64_t n_items;
     int n_segs;
     int n_slots;
@@ -565,7 +584,8 @@ hipError_t enqueue_run(sv_batch b)
                                     b->dtype == SV_C64 ? b->d_coef_f : nullptr, s);
     const std::vector<int64_t>& lf = b->level_first;
     for (size_t l = 0; l + 3 < lf.size() && e == hipSuccess; l += 3) {
-        e = launch_pass_items(b->tb, b->dtype, PM_FWD, lf[l], lf[l + 1], b->threads, b->lds_fwd, s);
+        e = launch_pass_items(b->tb, b->dtype, PM_FWD, lf[l], lf[l + 1], b->threads, b->lds_fwd, s,
+                              b->level_gated[l / 3] != 0);
         if (e == hipSuccess) e = launch_pass_items(b->tb, b->dtype, PM_OBS, lf[l + 1], lf[l + 2], b->threads, 0, s);
         if (e == hipSuccess)
             e = launch_pass_items(b->tb, b->dtype, PM_REV, lf[l + 2], lf[l + 3], b->rthreads, b->lds_rev, s);
@@ -621,6 +641,7 @@ struct HostTables {
     std::vector<double> slot_scale;
     std::vector<int> slot_param;
     std::vector<int64_t> g_off, e_off, level_first;
+    std::vector<uint8_t> level_gated;
     std::vector<int> g_cnt, e_cnt, csr_ptr, csr_col;
     std::vector<FSeg> segs;
     std::vector<size_t> psi_off;
@@ -758,7 +779,7 @@ static sv_status compile_batch(const sv_batch_circuit* circuits, int n_circuits,
                 f.slot = slot_of[i];
                 f.gen = (int8_t)(o.gate == SV_RX ? GEN_X : (o.gate == SV_RY ? GEN_Y : (o.gate == SV_RZ ? GEN_Z : GEN_P1)));
                 // controls (and a subset phase's target) inside the tile -> cm,
-                // a subset phase's qubits outside it -> gm
+                // those outside it -> gm (a one-target op's tile gate)
                 const bool sp = subset_phase_gate(o.gate);
                 uint32_t cm = 0;
                 uint64_t gm = 0;
@@ -768,13 +789,13 @@ static sv_status compile_batch(const sv_batch_circuit* circuits, int n_circuits,
                     else gm |= 1ull << q;
                 }
                 const int tl0 = local[o.q[o.nc]];
-                if ((!sp && (gm || tl0 < 0 || (o.nt > 1 && local[o.q[o.nc + 1]] < 0))) || (sp && !cm))
+                if ((!sp && (tl0 < 0 || (o.nt > 1 && (gm || local[o.q[o.nc + 1]] < 0)))) || (sp && !cm))
                     return set_error(SV_ERR_UNSUPPORTED, "internal: an op of a pass lies outside its tile");
                 f.cm = cm;
                 // a subset phase is symmetric in its qubits: any one inside the tile serves as its target
                 f.a = tl0 >= 0 ? tl0 : __builtin_ctz(cm);
                 f.b = o.nt > 1 ? local[o.q[o.nc + 1]] : 0;
-                if (sp) {  // b: the bits outside the tile, packed as in a tile index
+                if (o.nt == 1) {  // b: the op's qubits outside the tile, packed as in a tile index (0: none)
                     uint32_t packed = 0;
                     for (int q = 0; q < n; ++q)
                         if ((gm >> q) & 1ull) packed |= 1u << popc(fp.free_mask & ((1ull << q) - 1ull));
@@ -816,6 +837,10 @@ static sv_status compile_batch(const sv_batch_circuit* circuits, int n_circuits,
             fp.op_begin = (int)fops.size();
             fops.insert(fops.end(), fwd_ops.begin(), fwd_ops.end());
             fp.op_end = (int)fops.size();
+            fp.gated = 0;
+            for (const FOp& f : fwd_ops)
+                if (f.b != 0 && (f.kind == FK_PAIR || f.kind == FK_PAIRR || f.kind == FK_PAIRX || f.kind == FK_DIAG))
+                    fp.gated = 1;
             fp.rop_begin = fp.op_begin;
             fp.rop_end = fp.op_end;
             fp.rlay_begin = fp.lay_begin;
@@ -855,6 +880,7 @@ static sv_status compile_batch(const sv_batch_circuit* circuits, int n_circuits,
         max_stages = std::max(max_stages, stages[c]);
     }
     std::vector<int64_t> level_first;
+    std::vector<uint8_t> level_gated(max_stages, 0);
     for (int s = 0; s < max_stages; ++s) {
         for (int kind = PM_FWD; kind <= PM_REV; ++kind) {
             level_first.push_back(n_items);
@@ -863,6 +889,7 @@ static sv_status compile_batch(const sv_batch_circuit* circuits, int n_circuits,
                 const int np = circs[c].n_pass;
                 const int k = s < np ? PM_FWD : (s == np ? PM_OBS : PM_REV);
                 if (k != kind) continue;
+                if (k == PM_FWD && passes[circs[c].pass_begin + s].gated) level_gated[s] = 1;
                 FSeg sg;
                 sg.first = n_items;
                 sg.circ = c;
@@ -917,6 +944,7 @@ static sv_status compile_batch(const sv_batch_circuit* circuits, int n_circuits,
     H.g_off = std::move(g_off);
     H.e_off = std::move(e_off);
     H.level_first = std::move(level_first);
+    H.level_gated = std::move(level_gated);
     H.g_cnt = std::move(g_cnt);
     H.e_cnt = std::move(e_cnt);
     H.csr_ptr = std::move(csr_ptr);
@@ -1053,6 +1081,7 @@ sv_status sv_batch_create(const sv_batch_circuit* circuits, int n_circuits, sv_d
     b->psi_off = psi_off;
     b->n_cspec = (int)cspec.size();
     b->level_first = level_first;
+    b->level_gated = H.level_gated;
     for (int c = 0; c < n_circuits; ++c) {
         b->nq.push_back(circs[c].n);
         b->max_passes = std::max(b->max_passes, circs[c].n_pass);

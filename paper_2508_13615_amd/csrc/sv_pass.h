@@ -34,17 +34,18 @@ enum FusedKind : int32_t {
 // passes only) re-distributes the tile: a = index of the layout that holds
 // from here on, b = the layout that held before.
 //
-// A subset phase (FK_PHASE: Z, S, T, PHASE with any controls) multiplies the
+// Bits outside the tile are constant over a tile, so an op whose controls lie
+// there acts on a tile only if the tile holds them all.  A one-target op
+// (FK_PAIR, FK_PAIRR, FK_PAIRX, FK_DIAG) needs only its target in the tile;
+// a subset phase (FK_PHASE: Z, S, T, PHASE with any controls) multiplies the
 // amplitudes holding every bit of its mask, which makes it diagonal in all of
-// them: it need not have its qubits in the tile.  The mask bits inside the
-// tile are local bits in cm (a is one of them); the bits outside it are
-// constant over a tile, so the op acts on a tile only if the tile holds all of
-// them.  A tile's index is its bits outside the tile, packed (bit i = the i-th
-// lowest qubit outside the tile), so for FK_PHASE b holds the op's bits
-// outside the tile in that packed form (0: none) and the test is
-// (tile & b) == b.  In forward lists kb = 1 chains the op to the next one, a
-// subset phase on the same local mask whose phase the kernel multiplies in
-// before applying the group's product once (reverse sweeps ignore kb).
+// them, so it needs just one of its bits in the tile (a).  Bits inside the
+// tile are local bits in cm; for these kinds b holds the op's bits outside
+// the tile, packed as a tile index is (bit i = the i-th lowest qubit outside
+// the tile; 0: none), and the kernels test (tile & b) == b.  In forward lists
+// an FK_PHASE's kb = 1 chains it to the next op, a subset phase on the same
+// local mask whose phase the kernel multiplies in before applying the
+// group's product once (reverse sweeps ignore kb).
 struct FOp {
     int32_t kind;
     int32_t a, b;   // local target bits (b: second target of SWAP / QUAD, selector of FK_PAIRC)
@@ -85,6 +86,8 @@ struct FPass {
     int32_t rop_begin, rop_end;
     int32_t rlay_begin, rlay_end;
     uint64_t free_mask;  // global bits outside the tile (the tile index is deposited into them)
+    int32_t gated;       // 1 if a one-target op of the forward list has controls outside the tile
+    int32_t pad_;
 };
 
 struct FCirc {
@@ -159,8 +162,9 @@ enum PassMode : int { PM_FWD = 0, PM_OBS = 1, PM_REV = 2 };
 // any graph capture).
 hipError_t pass_engine_prepare(size_t lds_bytes);
 // Items [item_begin, item_end), all of stage kind `mode`, one workgroup per tile.
+// gated: some forward pass among the items has FPass.gated set.
 hipError_t launch_pass_items(const PassTables& tb, int dtype, int mode, int64_t item_begin, int64_t item_end,
-                             int threads, size_t lds_bytes, hipStream_t s);
+                             int threads, size_t lds_bytes, hipStream_t s, bool gated = false);
 hipError_t launch_pass_coef(const FCoefSpec* spec, int n, const FCoefSpec* factors, const double* params,
                             double* coef, float* coef_f, hipStream_t s);
 hipError_t launch_pass_segsum(const double* part, const int64_t* off, const int* cnt, const double* scale, double* out,

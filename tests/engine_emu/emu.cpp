@@ -104,6 +104,7 @@ static double ref_energy(int n, const std::vector<sv_op>& ops, const std::vector
 // ---------------- emulation of the kernels -------------------------------
 static int errors = 0;
 static long pairc_lane = 0, pairc_reg = 0;  // two-branch ops replayed, by selector placement
+static long gated_ops = 0;                  // one-target ops with controls outside the tile, per tile
 #define CHECK(c, ...) do { if (!(c)) { ++errors; if (errors < 20) { printf("FAIL %s:%d ", __FILE__, __LINE__); printf(__VA_ARGS__); printf("\n"); } } } while (0)
 
 static void gate2x2_h(const FCoefSpec& f, const double* params, cd u[4])
@@ -489,6 +490,22 @@ static void run_emu(Emu& E, const std::vector<double>& params)
                                 for (int j = 0; j < R; ++j) v[t * R + j] = lds[swz_h(f.tl[t] | f.off[j])];
                             continue;
                         }
+                        if ((op.kind == FK_PAIR || op.kind == FK_PAIRR || op.kind == FK_PAIRX || op.kind == FK_DIAG) &&
+                            op.b != 0) {
+                            // controls outside the tile: the op acts on the tiles whose index holds them
+                            uint64_t gm = 0;
+                            int rank = 0;
+                            for (int q = 0; q < cc.n; ++q)
+                                if ((ps.free_mask >> q) & 1ull) {
+                                    if (((uint32_t)op.b >> rank) & 1u) gm |= 1ull << q;
+                                    ++rank;
+                                }
+                            CHECK((gm & tile_bits) == 0, "out-of-tile controls hold tile bits");
+                            CHECK((((uint32_t)tile & (uint32_t)op.b) == (uint32_t)op.b) == ((tb & gm) == gm),
+                                  "packed control test disagrees with the base-index test");
+                            ++gated_ops;
+                            if ((tb & gm) != gm) continue;
+                        }
                         if (op.kind == FK_QUAD) {
                             quad_sweep_h(v, nthr, R, f, tq, op, E.coef.data() + op.coef, false);
                             continue;
@@ -558,7 +575,9 @@ static void run_emu(Emu& E, const std::vector<double>& params)
                         f = f2;
                         continue;
                     }
-                    const bool on = op.kind != FK_PHASE || ((uint32_t)tile & (uint32_t)op.b) == (uint32_t)op.b;
+                    const bool gated = op.kind == FK_PHASE || op.kind == FK_PAIR || op.kind == FK_PAIRR ||
+                                       op.kind == FK_PAIRX || op.kind == FK_DIAG;
+                    const bool on = !gated || ((uint32_t)tile & (uint32_t)op.b) == (uint32_t)op.b;
                     if (op.slot >= 0) {
                         double acc = 0;
                         if (on)
@@ -850,6 +869,11 @@ int main(int argc, char** argv)
             }
     printf("two-branch ops replayed: %ld with the selector on a lane bit, %ld on a register bit\n", pairc_lane,
            pairc_reg);
+    printf("one-target ops with controls outside the tile replayed: %ld (tile x op)\n", gated_ops);
+    if (!gated_ops) {
+        ++errors;
+        printf("FAIL: the circuits do not exercise controls outside the tile\n");
+    }
     if (!pairc_lane || !pairc_reg) {
         ++errors;
         printf("FAIL: the circuits do not exercise both selector placements of the two-branch op\n");
