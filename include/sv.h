@@ -408,7 +408,10 @@ sv_status sv_batch_free(sv_batch b);
  * qubit has runs under 1 KiB).  Tier: bytes spanned by
  * one run of consecutive touched amplitudes, 2^(lowest touched qubit) times
  * the element size: 0 (< 64 B), 1 (< 1 KiB), 2 (larger).  block is a
- * multiple of 64 in [64, 1024]; unroll is 1, 2 or 4: groups per thread,
+ * multiple of 64 in [64, 1024] (for class 6 an upper bound: a launch takes
+ * one thread per 4 staged amplitudes for complex128 2-qubit matrices, per 2
+ * for the complex128 SWAP move and per 8 otherwise, at least 64 threads and
+ * at most block; sv_plan_info reports the block a launch takes); unroll is 1, 2 or 4: groups per thread,
  * and for class 6 the chunk elements a thread of a 3-qubit gate loads (and
  * stores) per round trip between HBM and LDS (2-qubit gates: two in
  * complex64 when unroll >= 2, else one; sv_plan_info reports the depth a

@@ -201,8 +201,8 @@ static void tune_defaults()
             g_tune[c][d][0] = Launch{128, u, nt0};
             g_tune[c][d][1] = Launch{128, u, 1};
             g_tune[c][d][2] = Launch{64, u, 1};
-            if (c == KC_LDS)  // staged chunks are whole lines in every tier
-                for (int t = 0; t < kTiers; ++t) g_tune[c][d][t] = Launch{128, 1, 1};
+            if (c == KC_LDS)  // staged chunks are whole lines in every tier; block caps lds_block
+                for (int t = 0; t < kTiers; ++t) g_tune[c][d][t] = Launch{512, 1, 1};
         }
     g_tune_init = true;
 }
@@ -2031,7 +2031,7 @@ sv_status sv_plan_info(int n_qubits, int dtype, int gate, const int* controls, i
     if (n_qubits < 1 || n_qubits > SV_MAX_QUBITS || (dtype != SV_C64 && dtype != SV_C128))
         return set_error(SV_ERR_ARG, "n_qubits or dtype out of range");
     if (!kernel_class || !tier || !op || !block || !unroll || !nt_flag) return set_error(SV_ERR_ARG, "null output");
-    int kc, low, opv = 0;
+    int kc, low, opv = 0, lds_h = 0;
     if (gate == -1) {  // the general dense kernel on `targets`
         if (nt < 1 || nt > SV_MAX_GENERAL_K || nc != 0) return set_error(SV_ERR_ARG, "general gate needs 1..3 targets");
         sv_status rc = check_qubits(n_qubits, nullptr, 0, targets, nt);
@@ -2047,6 +2047,7 @@ sv_status sv_plan_info(int n_qubits, int dtype, int gate, const int* controls, i
         } else if (lds_eligible(n_qubits, dtype, targets, nt)) {
             kc = KC_LDS;
             opv = nt << 4;
+            for (int j = 0; j < nt; ++j) lds_h += targets[j] >= kLdsChunkBits;
         }
     } else {
         Plan pl;
@@ -2058,12 +2059,13 @@ sv_status sv_plan_info(int n_qubits, int dtype, int gate, const int* controls, i
         kc = pl.kc;
         low = pl.low;
         opv = pl.kind == PK_LDS ? ((pl.lk << 4) | pl.op) : pl.op;
+        if (pl.kind == PK_LDS) lds_h = pl.ls.h;
     }
     const Launch l = tune_get(kc, dtype, low);
     *kernel_class = kc;
     *tier = shape_tier(dtype, low);
     *op = opv;
-    *block = l.block;
+    *block = kc == KC_LDS ? lds_block(opv >> 4, lds_h, opv & 15, (int)elem_bytes(dtype), l.block) : l.block;
     *unroll = kc == KC_LDS ? lds_stage_depth(opv >> 4, l.unroll, (int)elem_bytes(dtype)) : l.unroll;
     *nt_flag = l.nt;
     return SV_OK;

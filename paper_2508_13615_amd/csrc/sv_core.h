@@ -117,6 +117,20 @@ inline int lds_stage_depth(int k, int unroll, int elem_bytes)
     if (k == 3) return unroll;
     return k == 2 && elem_bytes == 8 && unroll >= 2 ? 2 : 1;
 }
+// Workgroup size of the LDS-staged kernel for a stage of 2^(kLdsChunkBits + h)
+// amplitudes: `a` amplitudes of the stage per thread -- 4 for complex128
+// 2-qubit matrices, 2 for the complex128 SWAP move, 8 otherwise, the fastest
+// counts measured on MI355X at 30 qubits over stages of 256 to 1024
+// amplitudes (a workgroup of one wavefront on a 256-amplitude stage of a
+// complex128 2-qubit matrix took 5.35 ms per gate against 5.82 with two) --
+// at least one wavefront and at most `cap`, the launch shape's block.
+inline int lds_block(int k, int h, int op, int elem_bytes, int cap)
+{
+    const int a = elem_bytes == 16 && k == 2 ? (op == 1 ? 2 : 4) : 8;
+    const int want = (1 << (kLdsChunkBits + h)) / a;
+    const int b = want < 64 ? 64 : want;
+    return b < cap ? b : (cap < 64 ? 64 : cap);
+}
 struct LdsSpec {
     int32_t k;        // gate qubits (1..3)
     int32_t h;        // gate qubits >= kLdsChunkBits
