@@ -782,6 +782,24 @@ __device__ __forceinline__ bool op_on(const FOp& op, int tile)
     return !gated || phase_on(op, tile);
 }
 
+// Entry of a tile-selected op (FK_PAIRT) for tile `tile`: the tile index's
+// bits under the packed mask, gathered in order (uniform).
+__device__ __forceinline__ uint32_t tile_select(uint32_t tile, uint32_t mask)
+{
+    uint32_t e = 0;
+    for (int k = 0; mask; mask &= mask - 1u, ++k) e |= ((tile >> __builtin_ctz(mask)) & 1u) << k;
+    return e;
+}
+
+// A tile-selected op becomes the plain 2x2 of its entry for this tile.
+__device__ __forceinline__ void tile_select_op(FOp& op, int tile)
+{
+    if (op.kind != FK_PAIRT) return;
+    op.coef += 8 * (int32_t)tile_select((uint32_t)tile, (uint32_t)op.b);
+    op.kind = FK_PAIR;
+    op.b = 0;
+}
+
 // The next op's descriptor is fetched one op ahead, so its load overlaps the
 // current op's arithmetic.
 struct OpPre {
@@ -853,8 +871,9 @@ __device__ __forceinline__ void item_reg_fwd(const PassTables& tb, const FCirc& 
     OpPre nx;
     if (op_begin < op_end) op_fetch(tb, op_begin, nx);
     for (int o = op_begin; o < op_end; ++o) {
-        const OpPre p = nx;
+        OpPre p = nx;
         if (o + 1 < op_end) op_fetch(tb, o + 1, nx);
+        if constexpr (GATED) tile_select_op(p.op, tile);
         const FOp& op = p.op;
         T pzr = T(1), pzi = T(0);
         if (op.kind == FK_PHASE) {
@@ -1073,7 +1092,8 @@ __device__ __forceinline__ void item_lds(const PassTables& tb, const FCirc& cc, 
         }
         __syncthreads();
         for (int o = ps.op_begin; o < ps.op_end; ++o) {
-            const FOp op = tb.ops[o];
+            FOp op = tb.ops[o];
+            if constexpr (GATED) tile_select_op(op, tile);
             // uniform: not on this tile
             if (GATED ? !op_on(op, tile) : op.kind == FK_PHASE && !phase_on(op, tile)) continue;
             if (op.kind == FK_PAIRC) lds_pairc<T>(tileA, op, tb.coef, tq);
@@ -1234,7 +1254,44 @@ __global__ void k_pass_coef(const FCoefSpec* __restrict__ spec, int n, const FCo
     const FCoefSpec s = spec[i];
     double* c = coef + s.coef;
     int cnt;
-    if (s.nfactor > 0) {
+    if (s.nfactor > 0 && s.out_diag == 3) {
+        // tile-selected product: entry e stands for the tiles whose bits under
+        // the mask read e; a factor enters if those bits hold all of its own
+        const uint32_t mask = (uint32_t)s.branch;
+        const int ne = 1 << __popc(mask);
+        for (int e = 0; e < ne; ++e) {
+            uint32_t bits = 0;  // e deposited onto the mask's bits
+            int k = 0;
+            for (uint32_t m = mask; m; m &= m - 1, ++k)
+                if ((e >> k) & 1) bits |= m & (~m + 1u);
+            double m0[8] = {1, 0, 0, 0, 0, 0, 1, 0};
+            for (int f = 0; f < s.nfactor; ++f) {
+                const FCoefSpec& fk = factors[s.factor_begin + f];
+                if (((uint32_t)fk.branch & ~bits) != 0u) continue;
+                double g[8], r[8];
+                gate2x2(fk, params, g);
+#pragma unroll
+                for (int row = 0; row < 2; ++row)
+#pragma unroll
+                    for (int col = 0; col < 2; ++col) {
+                        double re = 0, im = 0;
+#pragma unroll
+                        for (int t = 0; t < 2; ++t) {
+                            const double gr = g[2 * (2 * row + t)], gi = g[2 * (2 * row + t) + 1];
+                            const double mr = m0[2 * (2 * t + col)], mi = m0[2 * (2 * t + col) + 1];
+                            re += gr * mr - gi * mi;
+                            im += gr * mi + gi * mr;
+                        }
+                        r[2 * (2 * row + col)] = re;
+                        r[2 * (2 * row + col) + 1] = im;
+                    }
+#pragma unroll
+                for (int q = 0; q < 8; ++q) m0[q] = r[q];
+            }
+            for (int q = 0; q < 8; ++q) c[8 * e + q] = m0[q];
+        }
+        cnt = 8 * ne;
+    } else if (s.nfactor > 0) {
         // M = G_last ... G_first; a two-branch product (out_diag 2) keeps M
         // for the selector-0 branch and M1 for the selector-1 branch
         double m[8] = {1, 0, 0, 0, 0, 0, 1, 0}, m1[8] = {1, 0, 0, 0, 0, 0, 1, 0};

@@ -199,7 +199,8 @@ uint32_t op_need(const FOp& f)
     case FK_PAIR:
     case FK_PAIRR:
     case FK_PAIRX:
-    case FK_PAIRC: return 1u << f.a;
+    case FK_PAIRC:
+    case FK_PAIRT: return 1u << f.a;
     case FK_SWAP: return (1u << f.a) | (1u << f.b);
     default: return 0u;
     }
@@ -383,7 +384,13 @@ FCoefSpec factor_of(const BOp& o, int param_base)
 //     or controlled by s alone (the second branch), or
 //   * the group's ops all have the one control s and the op is uncontrolled:
 //     the group becomes two-branch, its ops in the second branch and the op
-//     in both (a CNOT followed by a rotation of its target).
+//     in both (a CNOT followed by a rotation of its target), or
+//   * neither the group nor the op has a control inside the tile, and the
+//     union of their controls outside it stays within kMaxTileSelBits: the
+//     group becomes tile-selected (FK_PAIRT), one product per combination of
+//     those bits, each gate entering the products whose combination holds
+//     all of its controls (a run of CNOTs from far qubits interleaved with
+//     rotations of their common target).
 // A group of more than one op becomes one op whose coefficients are the
 // product of its gates, per branch (evaluated on the device from the
 // parameters).  Reverse passes keep the ops unfused: each parameterised op
@@ -399,15 +406,19 @@ std::vector<FOp> fuse_forward(const std::vector<FOp>& ops, const std::vector<int
         int sel;                   // selector bit of a two-branch group, -1 if none
         std::vector<int> members;  // indices into bops
         std::vector<int> branch;   // per member: 3 both branches, 2 the selector-1 branch
+        std::vector<uint32_t> out; // per member: its controls outside the tile (packed)
+        uint32_t tmask;            // union of the members' controls outside the tile
     };
     std::vector<Grp> g;
     int last[32];
     for (int& x : last) x = -1;
     for (size_t i = 0; i < ops.size(); ++i) {
         const FOp& f = ops[i];
-        // an op with qubits outside the tile stays on its own (a subset phase may be chained)
-        const bool fus = one_target_kind(f.kind) && f.b == 0;
+        // a subset phase with qubits outside the tile stays on its own (it may be
+        // chained); a one-target gate with controls outside the tile may join a
+        // group whose controls also lie outside the tile
         const uint32_t ctrl = f.kind == FK_PHASE ? (f.cm & ~(1u << f.a)) : f.cm;
+        const bool fus = one_target_kind(f.kind) && (f.b == 0 || (f.kind != FK_PHASE && ctrl == 0));
         uint32_t touch = f.cm | (1u << f.a);
         if (f.kind == FK_SWAP || f.kind == FK_QUAD) touch |= 1u << f.b;
         if (fus) {
@@ -418,7 +429,16 @@ std::vector<FOp> fuse_forward(const std::vector<FOp>& ops, const std::vector<int
                 for (int q = 0; q < 32; ++q)
                     if ((touch >> q) & 1u) later = later || last[q] != c;
                 int tag = 0;
-                if (G.sel < 0 && G.ctrl == ctrl && !later) {
+                if (f.b != 0 || G.tmask != 0) {
+                    // tile-selected: no control inside the tile on either side
+                    if (G.sel < 0 && G.ctrl == 0 && ctrl == 0 && popc(G.tmask | (uint32_t)f.b) <= kMaxTileSelBits) {
+                        G.tmask |= (uint32_t)f.b;
+                        G.members.push_back(src[i]);
+                        G.branch.push_back(3);
+                        G.out.push_back((uint32_t)f.b);
+                        continue;
+                    }
+                } else if (G.sel < 0 && G.ctrl == ctrl && !later) {
                     tag = 3;
                 } else if (G.sel >= 0 && ctrl == 0) {
                     tag = 3;  // touches only the target, whose latest group is G
@@ -439,11 +459,13 @@ std::vector<FOp> fuse_forward(const std::vector<FOp>& ops, const std::vector<int
                 if (tag) {
                     G.members.push_back(src[i]);
                     G.branch.push_back(tag);
+                    G.out.push_back(0u);
                     continue;
                 }
             }
         }
-        g.push_back({f, ctrl, fus, -1, {src[i]}, {3}});
+        const uint32_t out_bits = fus ? (uint32_t)f.b : 0u;
+        g.push_back({f, ctrl, fus, -1, {src[i]}, {3}, {out_bits}, out_bits});
         for (int q = 0; q < 32; ++q)
             if ((touch >> q) & 1u) last[q] = (int)g.size() - 1;
     }
@@ -458,11 +480,12 @@ std::vector<FOp> fuse_forward(const std::vector<FOp>& ops, const std::vector<int
             all_diag = all_diag && diag_gate(bops[m].gate);
             all_real = all_real && real_gate(bops[m].gate);
         }
-        const bool two = gr.sel >= 0;
+        const bool two = gr.sel >= 0, tsel = gr.tmask != 0;
         FOp f = gr.op;
-        f.kind = two ? FK_PAIRC : (all_diag ? FK_DIAG : (all_real ? FK_PAIRR : FK_PAIR));
+        f.kind = tsel ? FK_PAIRT : two ? FK_PAIRC : (all_diag ? FK_DIAG : (all_real ? FK_PAIRR : FK_PAIR));
         f.cm = gr.ctrl;
         if (two) f.b = gr.sel;
+        if (tsel) f.b = (int32_t)gr.tmask;
         f.slot = -1;
         f.coef = coef_total;
         FCoefSpec cs;
@@ -472,14 +495,15 @@ std::vector<FOp> fuse_forward(const std::vector<FOp>& ops, const std::vector<int
         cs.coef = coef_total;
         cs.nfactor = (int)gr.members.size();
         cs.factor_begin = (int)cfac.size();
-        cs.out_diag = two ? 2 : (all_diag ? 1 : 0);
+        cs.out_diag = tsel ? 3 : two ? 2 : (all_diag ? 1 : 0);
+        if (tsel) cs.branch = (int32_t)gr.tmask;
         for (size_t k = 0; k < gr.members.size(); ++k) {
             FCoefSpec fa = factor_of(bops[gr.members[k]], param_base);
-            fa.branch = gr.branch[k];
+            fa.branch = tsel ? (int32_t)gr.out[k] : gr.branch[k];
             cfac.push_back(fa);
         }
         cspec.push_back(cs);
-        coef_total += two ? 16 : (all_diag ? 4 : 8);
+        coef_total += tsel ? 8 << popc(gr.tmask) : two ? 16 : (all_diag ? 4 : 8);
         out.push_back(f);
     }
     return out;
@@ -839,7 +863,8 @@ static sv_status compile_batch(const sv_batch_circuit* circuits, int n_circuits,
             fp.op_end = (int)fops.size();
             fp.gated = 0;
             for (const FOp& f : fwd_ops)
-                if (f.b != 0 && (f.kind == FK_PAIR || f.kind == FK_PAIRR || f.kind == FK_PAIRX || f.kind == FK_DIAG))
+                if ((f.b != 0 && (f.kind == FK_PAIR || f.kind == FK_PAIRR || f.kind == FK_PAIRX || f.kind == FK_DIAG)) ||
+                    f.kind == FK_PAIRT)
                     fp.gated = 1;
             fp.rop_begin = fp.op_begin;
             fp.rop_end = fp.op_end;

@@ -24,11 +24,19 @@ constexpr int kSwzBits = 4;
 // only): a complex 2x2 on target a that depends on one selector bit b, the
 // first matrix where bit b is 0 and the second where it is 1 (16 doubles): a
 // run of one-target gates on a in which some gates are controlled by b, such
-// as a rotation followed by a CNOT from b.
+// as a rotation followed by a CNOT from b.  FK_PAIRT (forward lists only): a
+// complex 2x2 on target a chosen per tile by the bits of b, a packed mask of
+// qubits outside the tile (as below): a run of one-target gates on a whose
+// controls all lie outside the tile, where each gate acts on the tiles holding
+// its controls.  Its coefficients are 2^popcount(b) matrices of 8 doubles,
+// entry e for the tiles whose bits under b, gathered in order, read e.
 enum FusedKind : int32_t {
     FK_PAIR = 0, FK_DIAG = 1, FK_PHASE = 2, FK_SWAP = 3, FK_QUAD = 4, FK_LAYOUT = 5, FK_PAIRR = 6, FK_PAIRX = 7,
-    FK_PAIRC = 8
+    FK_PAIRC = 8, FK_PAIRT = 9
 };
+// Largest packed mask of an FK_PAIRT (bits), so its table holds at most 32
+// matrices.
+constexpr int kMaxTileSelBits = 5;
 
 // One op of a pass, in tile-local bit positions.  FK_LAYOUT (register-tiled
 // passes only) re-distributes the tile: a = index of the layout that holds
@@ -48,7 +56,8 @@ enum FusedKind : int32_t {
 // group's product once (reverse sweeps ignore kb).
 struct FOp {
     int32_t kind;
-    int32_t a, b;   // local target bits (b: second target of SWAP / QUAD, selector of FK_PAIRC)
+    int32_t a, b;   // local target bits (b: second target of SWAP / QUAD, selector of FK_PAIRC, packed mask
+                    // of the out-of-tile bits of one-target kinds, FK_PHASE and FK_PAIRT)
     uint32_t cm;    // local bits that must all be 1 (controls; for FK_PHASE also the target)
     int32_t coef;   // offset of the op's coefficients in the coefficient table (doubles)
     int32_t slot;   // gradient slot within the circuit, -1 if not parameterised
@@ -124,7 +133,10 @@ struct FSeg {
 // factor is an FCoefSpec whose fixed[0..7] holds the full 2x2 of a fixed gate.
 // out_diag = 1 writes the product's diagonal only (d0, d1); 2 writes two
 // products (FK_PAIRC: 16 values), each factor entering the first, the second
-// or both as its `branch` says (1, 2, 3); 0 writes all 8 values.
+// or both as its `branch` says (1, 2, 3); 3 writes 2^popcount(branch)
+// products (FK_PAIRT: the spec's branch is the op's packed mask), product e
+// taking the factors whose own packed mask (their `branch`) lies within the
+// bits that e selects; 0 writes all 8 values.
 struct FCoefSpec {
     int32_t gate;
     int32_t pidx;    // global parameter index, -1 = fixed angle `value`
@@ -134,7 +146,7 @@ struct FCoefSpec {
     double fixed[32];
     int32_t nfactor, factor_begin;
     int32_t out_diag;
-    int32_t branch;  // factor entries of an out_diag = 2 product
+    int32_t branch;  // factor entries of an out_diag = 2 or 3 product; the op's mask of an out_diag = 3 spec
 };
 
 struct PassTables {

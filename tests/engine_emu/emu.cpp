@@ -105,6 +105,7 @@ static double ref_energy(int n, const std::vector<sv_op>& ops, const std::vector
 static int errors = 0;
 static long pairc_lane = 0, pairc_reg = 0;  // two-branch ops replayed, by selector placement
 static long gated_ops = 0;                  // one-target ops with controls outside the tile, per tile
+static long tsel_ops = 0;                   // tile-selected fused ops replayed, per tile
 #define CHECK(c, ...) do { if (!(c)) { ++errors; if (errors < 20) { printf("FAIL %s:%d ", __FILE__, __LINE__); printf(__VA_ARGS__); printf("\n"); } } } while (0)
 
 static void gate2x2_h(const FCoefSpec& f, const double* params, cd u[4])
@@ -122,6 +123,34 @@ static void gate2x2_h(const FCoefSpec& f, const double* params, cd u[4])
 
 static void coef_eval(const FCoefSpec& s, const std::vector<FCoefSpec>& fac, const double* params, double* c)
 {
+    if (s.nfactor > 0 && s.out_diag == 3) {
+        // one product per subset of the op's out-of-tile bits: the list of the
+        // mask's set bits, entry e taking bit list[k] when bit k of e is set
+        std::vector<int> bits;
+        for (int q = 0; q < 32; ++q)
+            if (((uint32_t)s.branch >> q) & 1u) bits.push_back(q);
+        CHECK(!bits.empty() && (int)bits.size() <= kMaxTileSelBits, "tile-selected mask of %zu bits", bits.size());
+        for (int e = 0; e < (1 << bits.size()); ++e) {
+            uint32_t held = 0;
+            for (size_t k = 0; k < bits.size(); ++k)
+                if ((e >> k) & 1) held |= 1u << bits[k];
+            cd m[4] = {1, 0, 0, 1};
+            for (int k = 0; k < s.nfactor; ++k) {
+                const FCoefSpec& fk = fac[s.factor_begin + k];
+                CHECK(((uint32_t)fk.branch & ~(uint32_t)s.branch) == 0, "factor bits outside the op's mask");
+                if (((uint32_t)fk.branch & held) != (uint32_t)fk.branch) continue;
+                cd g[4], r[4];
+                gate2x2_h(fk, params, g);
+                r[0] = g[0] * m[0] + g[1] * m[2];
+                r[1] = g[0] * m[1] + g[1] * m[3];
+                r[2] = g[2] * m[0] + g[3] * m[2];
+                r[3] = g[2] * m[1] + g[3] * m[3];
+                for (int q = 0; q < 4; ++q) m[q] = r[q];
+            }
+            for (int q = 0; q < 4; ++q) { c[8 * e + 2 * q] = m[q].real(); c[8 * e + 2 * q + 1] = m[q].imag(); }
+        }
+        return;
+    }
     if (s.nfactor > 0) {
         cd mm[2][4] = {{1, 0, 0, 1}, {1, 0, 0, 1}};
         for (int k = 0; k < s.nfactor; ++k) {
@@ -510,6 +539,28 @@ static void run_emu(Emu& E, const std::vector<double>& params)
                             quad_sweep_h(v, nthr, R, f, tq, op, E.coef.data() + op.coef, false);
                             continue;
                         }
+                        if (op.kind == FK_PAIRT) {
+                            // the entry whose bits are the tile's values of the out-of-tile qubits under b
+                            CHECK(op.cm == 0 && op.b != 0, "tile-selected op with in-tile controls or no mask");
+                            int rank = 0, k = 0, e = 0;
+                            for (int q = 0; q < cc.n; ++q)
+                                if ((ps.free_mask >> q) & 1ull) {
+                                    if (((uint32_t)op.b >> rank) & 1u) {
+                                        if ((tb >> q) & 1ull) e |= 1 << k;
+                                        ++k;
+                                    }
+                                    ++rank;
+                                }
+                            CHECK(k == __builtin_popcount((uint32_t)op.b), "mask bits beyond the free qubits");
+                            FOp q2 = op;
+                            q2.kind = FK_PAIR;
+                            q2.b = 0;
+                            ++tsel_ops;
+                            for (int t = 0; t < nthr; ++t)
+                                reg_apply_h(&v[t * R], rb, q2, E.coef.data() + op.coef + 8 * e, false, f.tl[t], f.off,
+                                            H.lays[cur], tq);
+                            continue;
+                        }
                         for (int t = 0; t < nthr; ++t)
                             reg_apply_h(&v[t * R], rb, op, E.coef.data() + op.coef, false, f.tl[t], f.off, H.lays[cur], tq);
                     }
@@ -734,6 +785,27 @@ static Circ qft(int n)
 
 // Mostly subset phases (Z, S, T, PHASE with 0..3 controls) between a few
 // Hadamards and CNOTs: phases whose qubits fall outside the tile.
+// Runs of CNOTs from every other qubit onto one target, each followed by a
+// rotation of the target (parameterised every third), target by target.
+static Circ cnot_runs(int n)
+{
+    Circ C;
+    C.n = n;
+    C.obs = 1;
+    int np = 0;
+    for (int t = 0; t < n; ++t) {
+        C.ops.push_back(mk(SV_RY, {}, {t}, np++));
+        for (int c = 0; c < n; ++c) {
+            if (c == t) continue;
+            C.ops.push_back(mk(SV_X, {c}, {t}));
+            if (c % 3 == 0) C.ops.push_back(mk(SV_RZ, {}, {t}, np++));
+            else C.ops.push_back(mk(c % 3 == 1 ? SV_RZ : SV_RX, {}, {t}, -1, 0.1 * (c + 1) + 0.01 * t));
+        }
+    }
+    C.n_params = np;
+    return C;
+}
+
 static Circ phase_heavy(std::mt19937_64& rng, int n, int n_ops, int n_params)
 {
     Circ C;
@@ -861,6 +933,11 @@ int main(int argc, char** argv)
                 }
                 snprintf(nm, sizeof nm, "random 13q default tile %s apt%d grad%d", dt == SV_C128 ? "c128" : "c64", apt, wg);
                 test({random_circ(rng, 13, 200, 12), random_circ(rng, 14, 150, 9)}, dt, 0, apt, wg, nm, rng);
+                for (int tile : {4, 6}) {
+                    snprintf(nm, sizeof nm, "cnot runs 11q tile%d %s apt%d grad%d", tile, dt == SV_C128 ? "c128" : "c64",
+                             apt, wg);
+                    test({cnot_runs(11), cnot_runs(9)}, dt, tile, apt, wg, nm, rng);
+                }
                 for (int tile : {5, 7, 0}) {
                     snprintf(nm, sizeof nm, "qft 11q + phases 12q tile%d %s apt%d grad%d", tile,
                              dt == SV_C128 ? "c128" : "c64", apt, wg);
@@ -870,6 +947,11 @@ int main(int argc, char** argv)
     printf("two-branch ops replayed: %ld with the selector on a lane bit, %ld on a register bit\n", pairc_lane,
            pairc_reg);
     printf("one-target ops with controls outside the tile replayed: %ld (tile x op)\n", gated_ops);
+    printf("tile-selected ops replayed: %ld (tile x op)\n", tsel_ops);
+    if (!tsel_ops) {
+        ++errors;
+        printf("FAIL: the circuits do not exercise tile-selected ops\n");
+    }
     if (!gated_ops) {
         ++errors;
         printf("FAIL: the circuits do not exercise controls outside the tile\n");

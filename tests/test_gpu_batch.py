@@ -268,6 +268,77 @@ def test_config3_circuits_at_20_qubits_vs_oracle():
             assert abs(e[0] - oracle.expval_obs(ref, W.sum_z(n))) <= tol * n
 
 
+def far_control_runs(n, rng, reps):
+    """Runs of one-target gates on a target t whose controls are qubits far
+    from it (at or above n - 4, outside a tile of the low qubits), mixed with
+    uncontrolled gates: with a small tile the forward passes fuse each run into
+    one 2x2 per tile, chosen by the tile's values of those qubits.  CNOTs with
+    one or two far controls, controlled rotations and phases, uncontrolled
+    rotations, H and U2; each parameterised gate has a parameter of its own.
+    Returns (ops, number of parameters)."""
+    ops = []
+    n_params = 0
+    far = list(range(n - 4, n))
+    for _ in range(reps):
+        t = int(rng.integers(0, n - 4))
+        for _ in range(int(rng.integers(3, 9))):
+            k = int(rng.integers(0, 7))
+            ctl = tuple(int(x) for x in rng.choice(far, size=1 + (k == 1), replace=False))
+            v = float(rng.uniform(0, 2 * math.pi))
+            if k <= 1:
+                ops.append(W.Op("X", ctl, (t,)))
+            elif k == 2:
+                ops.append(W.Op("RY", ctl, (t,), -1, v))
+            elif k == 3:
+                ops.append(W.Op("PHASE" if v < math.pi else "RZ", ctl, (t,), -1, v))
+            elif k == 4:
+                ops.append(W.Op("RZ", (), (t,), n_params, v))
+                n_params += 1
+            elif k == 5:
+                ops.append(W.Op("H", (), (t,)))
+            else:
+                ops.append(W.Op("U2", (), (t,), -1, 0.0, W.haar_unitary(1, rng)))
+    return ops, n_params
+
+
+@pytest.mark.parametrize("apt", [16, 8])
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("tile", [3, 4, 6])
+def test_tile_selected_fusion_states_and_energies(dtype, tile, apt):
+    # tile 3 with 16 amplitudes per thread runs the LDS-sweep form
+    rng = np.random.default_rng(5400 + tile)
+    circs, params, n_gates = [], [], 0
+    for n in (8, 11):
+        ops, npar = far_control_runs(n, rng, 12)
+        n_gates += len(ops)
+        circs.append((n, ops, npar, "sum_zz"))
+        params.append(rng.uniform(0, 2 * math.pi, size=npar))
+    b = sv.Batch(circs, dtype, tile_qubits=tile, amps_per_thread=apt, with_grad=False)
+    e, _ = b.run(np.concatenate(params))
+    assert b.info()["fused_ops"] < n_gates // 2  # runs of 3-8 gates became one op each
+    for i, (n, ops, npar, obs) in enumerate(circs):
+        ref = oracle.run_circuit(oracle.zero_state(n), ops, params[i])
+        got = b.state(i).astype(np.complex128)
+        err = float(np.max(np.abs(got - ref)))
+        assert err <= 4 * TOL[dtype], (i, n, err)
+        e_ref = oracle.expval_obs(ref, obs_terms(obs, n))
+        assert abs(e[i] - e_ref) <= 4 * TOL[dtype] * n, (i, e[i], e_ref)
+
+
+@pytest.mark.parametrize("dtype,tol", [("c128", 1e-10), ("c64", 1e-4)])
+def test_tile_selected_fusion_gradients_vs_oracle(dtype, tol):
+    # with the adjoint: forward passes fused per tile, reverse passes gate by gate
+    rng = np.random.default_rng(5500)
+    n = 10
+    ops, npar = far_control_runs(n, rng, 10)
+    th = rng.uniform(0, 2 * math.pi, size=npar)
+    b = sv.Batch([(n, ops, npar, "sum_z")], dtype, tile_qubits=5, with_grad=True)
+    e, g = b.run(th)
+    g_ref = oracle.param_shift_grad(n, ops, th, W.sum_z(n))
+    assert abs(e[0] - oracle.energy(n, ops, th, W.sum_z(n))) <= tol * n
+    assert float(np.max(np.abs(g - g_ref))) <= tol
+
+
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 def test_universal_circuit_fused_and_op_by_op_vs_oracle(dtype):
     """The universal circuit (2 n^2 gates: CNOTs and Z rotations) after an H on
