@@ -217,7 +217,9 @@ def engine_bounds(bench_line: str, runs: dict, n: int = 30, layers: int = 10) ->
     with open(bench_line) as f:
         secs = json.loads(f.read().strip().splitlines()[-1])["circuits32_s"]
     _, jobs = bench.circuit_jobs(n, layers)
-    kern = {"c128": "k_pass_fwd<double, 4>", "c64": "k_pass_fwd<float, 4>"}
+    # forward pass kernels of 16 amplitudes per thread, both instances (with and
+    # without the out-of-tile control test), summed
+    kern = {"c128": "k_pass_fwd<double, 4", "c64": "k_pass_fwd<float, 4"}
     ebytes = {"c128": 16, "c64": 8}
     rows = ["| circuit | dtype | s per run (HIP events) | passes | gate ops (fused) | layout changes | "
             "HBM floor at 8 TB/s | VALU issue floor | VALU / wave / pass | SALU / wave / pass | VALU busy |",
@@ -230,7 +232,11 @@ def engine_bounds(bench_line: str, runs: dict, n: int = 30, layers: int = 10) ->
             tot[k][r["Counter_Name"]] = tot[k].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
         ops, th = jobs[name]
         for dt in ("c128", "c64"):
-            c = tot[kern[dt]]
+            c = {}
+            for k, v in tot.items():
+                if k.startswith(kern[dt]):
+                    for cn, cv in v.items():
+                        c[cn] = c.get(cn, 0.0) + cv
             plan = sv.batch_plan([(n, ops, len(th), "sum_z")], dt, with_grad=False)
             t = secs[f"{name}_{dt}"]
             hbm = (2 * plan["passes"] + 1) * (1 << n) * ebytes[dt] / 8e12
