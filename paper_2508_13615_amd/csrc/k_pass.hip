@@ -258,11 +258,34 @@ __device__ double lds_gen_inner(const typename Vec2<T>::type* P, const typename 
     return acc;
 }
 
+// v plus the value DPP control CTRL routes to each lane (rows outside ROWS add
+// zero); a double moves as its two 32-bit halves.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_plus(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWS, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWS, 0xf, false);
+    return v + __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes of a wavefront in a fixed order, returned to every
+// lane (every lane must call it).  Within each row of 16 lanes: pairs
+// (quad_perm 1,0,3,2), quads (2,3,0,1), half rows (row_half_mirror), rows
+// (row_mirror); then row 0's sum into row 1 and row 2's into row 3
+// (row_bcast:15), and lane 31's into rows 2 and 3 (row_bcast:31): lane 63
+// holds the total.  Cross-lane moves through DPP take a few cycles each, where
+// a shuffle through the LDS crossbar waits on a memory-like round trip.
 __device__ __forceinline__ double wave_sum(double v)
 {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-    return v;
+    v = dpp_plus<0xB1, 0xf>(v);
+    v = dpp_plus<0x4E, 0xf>(v);
+    v = dpp_plus<0x141, 0xf>(v);
+    v = dpp_plus<0x140, 0xf>(v);
+    v = dpp_plus<0x142, 0xa>(v);
+    v = dpp_plus<0x143, 0xc>(v);
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+    return __hiloint2double(hi, lo);
 }
 
 // Sum over the block of one value per thread, order fixed; result on thread 0.
