@@ -551,13 +551,15 @@ __device__ __forceinline__ void rswap(int ka, int kb, typename Vec2<T>::type* v,
 // LDS sweep (lds_op).  4x4 ops always take the LDS sweep: their 32 complex
 // coefficients would claim 64 scalar registers in this switch and make the
 // compiler spill scalar registers across the whole op loop.
-template <typename T, int RB, bool CHK, bool SEL, bool TWO>
-__device__ __forceinline__ void reg_apply_c(typename Vec2<T>::type* v, const FOp& op, cptr<T> cf, bool dagger,
-                                            uint32_t tl, uint32_t cmk, bool ok, T pzr, T pzi)
+// DUAL: the op acts on w as well (a reverse pass un-applies it on phi and
+// lambda): one dispatch, the coefficients read once.
+template <typename T, int RB, bool CHK, bool SEL, bool TWO, bool DUAL = false>
+__device__ __forceinline__ void reg_apply_c(typename Vec2<T>::type* v, typename Vec2<T>::type* w, const FOp& op,
+                                            cptr<T> cf, bool dagger, uint32_t tl, uint32_t cmk, bool ok, T pzr, T pzi)
 {
     switch (op.kind) {
     case FK_PAIRX: {
-#define SV_CALL(K) rpairx_k<T, RB, K, CHK, SEL>(v, ok, cmk)
+#define SV_CALL(K) { rpairx_k<T, RB, K, CHK, SEL>(v, ok, cmk); if constexpr (DUAL) rpairx_k<T, RB, K, CHK, SEL>(w, ok, cmk); }
         SV_K_SWITCH(op.ka, SV_CALL)
 #undef SV_CALL
         break;
@@ -575,7 +577,7 @@ __device__ __forceinline__ void reg_apply_c(typename Vec2<T>::type* v, const FOp
             r[2] = ok ? r[2] : T(0);
             r[3] = ok ? r[3] : T(1);
         }
-#define SV_CALL(K) rpairr_k<T, RB, K, CHK>(v, r, cmk)
+#define SV_CALL(K) { rpairr_k<T, RB, K, CHK>(v, r, cmk); if constexpr (DUAL) rpairr_k<T, RB, K, CHK>(w, r, cmk); }
         SV_K_SWITCH(op.ka, SV_CALL)
 #undef SV_CALL
         break;
@@ -587,7 +589,7 @@ __device__ __forceinline__ void reg_apply_c(typename Vec2<T>::type* v, const FOp
 #pragma unroll
             for (int k = 0; k < 8; ++k) u[k] = ok ? u[k] : ((k == 0 || k == 6) ? T(1) : T(0));
         }
-#define SV_CALL(K) rpair_k<T, RB, K, CHK>(v, u, cmk)
+#define SV_CALL(K) { rpair_k<T, RB, K, CHK>(v, u, cmk); if constexpr (DUAL) rpair_k<T, RB, K, CHK>(w, u, cmk); }
         SV_K_SWITCH(op.ka, SV_CALL)
 #undef SV_CALL
         break;
@@ -601,12 +603,13 @@ __device__ __forceinline__ void reg_apply_c(typename Vec2<T>::type* v, const FOp
             d[3] = ok ? d[3] : T(0);
         }
         if (op.ka >= 0) {
-#define SV_CALL(K) rdiag_k<T, RB, K, CHK>(v, d, cmk)
+#define SV_CALL(K) { rdiag_k<T, RB, K, CHK>(v, d, cmk); if constexpr (DUAL) rdiag_k<T, RB, K, CHK>(w, d, cmk); }
             SV_K_SWITCH(op.ka, SV_CALL)
 #undef SV_CALL
         } else {  // target on a lane bit: one phase for all of this thread's registers
             const bool b = (tl >> op.a) & 1u;
             rphase<T, RB, CHK>(v, b ? d[2] : d[0], b ? d[3] : d[1], cmk);
+            if constexpr (DUAL) rphase<T, RB, CHK>(w, b ? d[2] : d[0], b ? d[3] : d[1], cmk);
         }
         break;
     }
@@ -617,10 +620,14 @@ __device__ __forceinline__ void reg_apply_c(typename Vec2<T>::type* v, const FOp
             zi = ok ? zi : T(0);
         }
         rphase<T, RB, CHK>(v, zr, zi, cmk);
+        if constexpr (DUAL) rphase<T, RB, CHK>(w, zr, zi, cmk);
         break;
     }
     case FK_SWAP:
-        if constexpr (TWO) rswap<T, RB, CHK, SEL>(op.ka, op.kb, v, ok, cmk);
+        if constexpr (TWO) {
+            rswap<T, RB, CHK, SEL>(op.ka, op.kb, v, ok, cmk);
+            if constexpr (DUAL) rswap<T, RB, CHK, SEL>(op.ka, op.kb, w, ok, cmk);
+        }
         break;
     default: break;
     }
@@ -668,18 +675,18 @@ __device__ __forceinline__ void reg_pairc(typename Vec2<T>::type* v, const FOp& 
 // would make the compiler copy all of them at each join): a lane-bit control
 // turns the op into the identity for threads where it is 0.
 // (pzr, pzi): the phase of an FK_PHASE op, supplied by the caller.
-template <typename T, int RB, bool TWO = true>
+template <typename T, int RB, bool TWO = true, bool DUAL = false>
 __device__ __forceinline__ void reg_apply(typename Vec2<T>::type* v, const FOp& op, cptr<T> cf, bool dagger,
-                                          uint32_t tl, T pzr, T pzi)
+                                          uint32_t tl, T pzr, T pzi, typename Vec2<T>::type* w = nullptr)
 {
     const uint32_t cmk = op.cmk, cml = op.cml;
     const bool ok = (tl & cml) == cml;
     if (cml) {
-        if (cmk) reg_apply_c<T, RB, true, true, TWO>(v, op, cf, dagger, tl, cmk, ok, pzr, pzi);
-        else reg_apply_c<T, RB, false, true, TWO>(v, op, cf, dagger, tl, 0u, ok, pzr, pzi);
+        if (cmk) reg_apply_c<T, RB, true, true, TWO, DUAL>(v, w, op, cf, dagger, tl, cmk, ok, pzr, pzi);
+        else reg_apply_c<T, RB, false, true, TWO, DUAL>(v, w, op, cf, dagger, tl, 0u, ok, pzr, pzi);
     } else {
-        if (cmk) reg_apply_c<T, RB, true, false, TWO>(v, op, cf, dagger, tl, cmk, true, pzr, pzi);
-        else reg_apply_c<T, RB, false, false, TWO>(v, op, cf, dagger, tl, 0u, true, pzr, pzi);
+        if (cmk) reg_apply_c<T, RB, true, false, TWO, DUAL>(v, w, op, cf, dagger, tl, cmk, true, pzr, pzi);
+        else reg_apply_c<T, RB, false, false, TWO, DUAL>(v, w, op, cf, dagger, tl, 0u, true, pzr, pzi);
     }
 }
 
@@ -1024,8 +1031,7 @@ __device__ __forceinline__ void item_reg_rev(const PassTables& tb, const FCirc& 
         } else {
             const T pzr = op.kind == FK_PHASE ? (T)coef[op.coef] : T(1);
             const T pzi = op.kind == FK_PHASE ? (T)-coef[op.coef + 1] : T(0);
-            reg_apply<T, RB, false>(v, op, coef + op.coef, true, tl, pzr, pzi);
-            reg_apply<T, RB, false>(w, op, coef + op.coef, true, tl, pzr, pzi);
+            reg_apply<T, RB, false, true>(v, op, coef + op.coef, true, tl, pzr, pzi, w);
         }
     }
     __syncthreads();  // every wave's partials are in LDS
