@@ -907,10 +907,13 @@ __device__ __forceinline__ void item_reg_fwd(const PassTables& tb, const FCirc& 
         const FOp& op = p.op;
         T pzr = T(1), pzi = T(0);
         if (op.kind == FK_PHASE) {
-            // A chained group of subset phases on one local mask: the product of
-            // the phases of the ops that act on this tile (those whose bits
-            // outside the tile the tile holds), applied once by the group's
-            // last op.  The product is uniform over the workgroup.
+            // A chained group of subset phases on one local mask (kb 1): the
+            // product of the phases of the ops that act on this tile (those whose
+            // bits outside the tile the tile holds), applied once by the group's
+            // last op.  A run on target a (kb 2, the last 3): members whose
+            // other in-tile bit is a lane bit count only on the lanes holding
+            // it, so the product is per lane; it is applied once to the
+            // amplitudes holding a.
             const cptr<double> cd = as_const(tb.coef);
             double chr = 1.0, chi = 0.0;
             bool any = false;
@@ -918,19 +921,25 @@ __device__ __forceinline__ void item_reg_fwd(const PassTables& tb, const FCirc& 
             for (;; ++e) {
                 const FOp q = e == o ? op : ld_const(as_const(tb.ops) + e);
                 if (phase_on(q, tile)) {
+                    const uint32_t lc = q.kb >= 2 ? q.cml & ~(1u << q.a) : 0u;
+                    const bool in = (tl & lc) == lc;
                     const double zr = cd[q.coef], zi = cd[q.coef + 1];
-                    const double r = chr * zr - chi * zi;
-                    chi = chr * zi + chi * zr;
-                    chr = r;
+                    const double r = chr * zr - chi * zi, im = chr * zi + chi * zr;
+                    chr = in ? r : chr;
+                    chi = in ? im : chi;
                     any = true;
                 }
-                if (q.kb != 1) break;
+                if (q.kb != 1 && q.kb != 2) break;
             }
             if (e != o) {  // skip the group's other ops; refetch the next descriptor
                 o = e;
                 if (o + 1 < op_end) op_fetch(tb, o + 1, nx);
             }
             if (!any) continue;
+            if (p.op.kb >= 2) {  // a run acts on the amplitudes holding its target only
+                p.op.cmk = p.op.ka >= 0 ? (uint8_t)(1u << p.op.ka) : (uint8_t)0;
+                p.op.cml = p.op.ka >= 0 ? 0u : 1u << p.op.a;
+            }
             pzr = (T)chr;
             pzi = (T)chi;
         }

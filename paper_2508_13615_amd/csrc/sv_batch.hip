@@ -624,11 +624,27 @@ hipError_t enqueue_run(sv_batch b)
 
 // Consecutive subset phases commute.  Within each maximal run of them in a
 // planned forward list (no layout change inside, so one local mask means one
-// register / lane split), order them by local mask and chain each one to the
-// next of the same mask: the kernel multiplies a group's phases (those whose
-// out-of-tile bits the tile holds) into one and applies it once.
+// register / lane split) the host groups them:
+//   * a phase whose in-tile mask is one bit t, or t and one lane bit c, joins
+//     the group of run target t (for a mask of one register bit and one lane
+//     bit, t is the register bit): the kernel multiplies the group's phases
+//     into one factor per lane (a member with c counts on the lanes holding
+//     c) and applies it once to the amplitudes holding t.  Members carry
+//     a = t (ka to match) and kb = 2, the last one kb = 3;
+//   * other phases are ordered by local mask and each is chained to the next
+//     of the same mask (kb = 1): the kernel multiplies a chain's phases (those
+//     whose out-of-tile bits the tile holds) into one and applies it once.
+// Changing a phase's named target changes nothing: a subset phase is
+// symmetric in the qubits of its mask.
 void mark_phase_chains(std::vector<FOp>& ops)
 {
+    auto run_target = [](const FOp& f) -> int {
+        const uint32_t reg = f.cm & ~f.cml;  // in-tile bits on registers (cml: those on lanes)
+        const int n = popc(f.cm);
+        if (n == 1) return f.a;
+        if (n != 2 || popc(reg) == 2) return -1;
+        return popc(reg) == 1 ? __builtin_ctz(reg) : f.a;
+    };
     size_t i = 0;
     while (i < ops.size()) {
         if (ops[i].kind != FK_PHASE) {
@@ -637,8 +653,29 @@ void mark_phase_chains(std::vector<FOp>& ops)
         }
         size_t j = i;
         while (j < ops.size() && ops[j].kind == FK_PHASE) ++j;
-        std::stable_sort(ops.begin() + i, ops.begin() + j, [](const FOp& x, const FOp& y) { return x.cm < y.cm; });
-        for (size_t k = i; k < j; ++k) ops[k].kb = (k + 1 < j && ops[k + 1].cm == ops[k].cm) ? 1 : 0;
+        // run groups first, by target; then the others by mask
+        auto key = [&](const FOp& f) {
+            const int t = run_target(f);
+            return t >= 0 ? (int64_t)t : (int64_t)64 + (int64_t)f.cm;
+        };
+        std::stable_sort(ops.begin() + i, ops.begin() + j, [&](const FOp& x, const FOp& y) { return key(x) < key(y); });
+        for (size_t k = i; k < j;) {
+            size_t e = k;
+            while (e < j && key(ops[e]) == key(ops[k])) ++e;
+            const int t = run_target(ops[k]);
+            if (t >= 0 && e - k >= 2) {
+                for (size_t m = k; m < e; ++m) {
+                    FOp& f = ops[m];
+                    const bool treg = ((f.cm & ~f.cml) >> t) & 1u;
+                    f.a = t;
+                    f.ka = (int8_t)(treg ? __builtin_ctz(f.cmk) : -1);
+                    f.kb = m + 1 < e ? 2 : 3;
+                }
+            } else {
+                for (size_t m = k; m < e; ++m) ops[m].kb = (t < 0 && m + 1 < e) ? 1 : 0;
+            }
+            k = e;
+        }
         i = j;
     }
 }

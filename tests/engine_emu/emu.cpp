@@ -106,6 +106,7 @@ static int errors = 0;
 static long pairc_lane = 0, pairc_reg = 0;  // two-branch ops replayed, by selector placement
 static long gated_ops = 0;                  // one-target ops with controls outside the tile, per tile
 static long tsel_ops = 0;                   // tile-selected fused ops replayed, per tile
+static long run_members = 0;                // subset phases replayed as members of a per-target run
 #define CHECK(c, ...) do { if (!(c)) { ++errors; if (errors < 20) { printf("FAIL %s:%d ", __FILE__, __LINE__); printf(__VA_ARGS__); printf("\n"); } } } while (0)
 
 static void gate2x2_h(const FCoefSpec& f, const double* params, cd u[4])
@@ -466,6 +467,7 @@ static void run_emu(Emu& E, const std::vector<double>& params)
                         }
                     cd chain_acc = 1.0;
                     bool ch_any = false;
+                    std::vector<cd> run_acc(nthr, cd(1.0));  // per-thread product of a phase run
                     const uint64_t tile_bits = ~ps.free_mask & ((1ull << cc.n) - 1);
                     for (int o = ps.op_begin; o < ps.op_end; ++o) {
                         const FOp& op = H.fops[o];
@@ -487,7 +489,33 @@ static void run_emu(Emu& E, const std::vector<double>& params)
                             CHECK((((uint32_t)tile & (uint32_t)op.b) == (uint32_t)op.b) == ((tb & gm) == gm),
                                   "packed test disagrees with the base-index test");
                             CHECK(op.cm != 0 && ((op.cm >> op.a) & 1u), "phase without an in-tile bit");
-                            CHECK(op.kb == 0 || op.kb == 1, "chain flag %d", op.kb);
+                            CHECK(op.kb >= 0 && op.kb <= 3, "chain flag %d", op.kb);
+                            if (op.kb >= 2) {
+                                // run on target a: the other in-tile bit, if any, must be a lane bit
+                                const uint32_t other = op.cm & ~(1u << op.a);
+                                uint32_t lanes = 0;
+                                for (int i = 0; i < tq - rb; ++i) lanes |= 1u << H.lays[cur].pos[i];
+                                CHECK(__builtin_popcount(other) <= 1 && (other & ~lanes) == 0,
+                                      "run member with mask %x on target %d", op.cm, op.a);
+                                CHECK(op.ka == -1 || H.lays[cur].pos[tq - rb + op.ka] == op.a, "run ka does not hold a");
+                                CHECK(op.ka != -1 || ((lanes >> op.a) & 1u), "run target on a register but ka = -1");
+                                if (op.kb == 2)
+                                    CHECK(o + 1 < ps.op_end && H.fops[o + 1].kind == FK_PHASE && H.fops[o + 1].a == op.a &&
+                                              H.fops[o + 1].kb >= 2, "run not followed by a member on the same target");
+                                if ((tb & gm) == gm) {
+                                    const cd z(E.coef[op.coef], E.coef[op.coef + 1]);
+                                    for (int t = 0; t < nthr; ++t)
+                                        if ((f.tl[t] & other) == other) run_acc[t] *= z;
+                                }
+                                ++run_members;
+                                if (op.kb == 2) continue;
+                                for (int t = 0; t < nthr; ++t) {
+                                    for (int j = 0; j < R; ++j)
+                                        if ((((f.tl[t] | f.off[j]) >> op.a) & 1u)) v[t * R + j] *= run_acc[t];
+                                    run_acc[t] = 1.0;
+                                }
+                                continue;
+                            }
                             if ((tb & gm) == gm) {
                                 chain_acc *= cd(E.coef[op.coef], E.coef[op.coef + 1]);
                                 ch_any = true;
@@ -948,6 +976,11 @@ int main(int argc, char** argv)
            pairc_reg);
     printf("one-target ops with controls outside the tile replayed: %ld (tile x op)\n", gated_ops);
     printf("tile-selected ops replayed: %ld (tile x op)\n", tsel_ops);
+    printf("subset phases replayed in per-target runs: %ld (tile x op)\n", run_members);
+    if (!run_members) {
+        ++errors;
+        printf("FAIL: the circuits do not exercise phase runs\n");
+    }
     if (!tsel_ops) {
         ++errors;
         printf("FAIL: the circuits do not exercise tile-selected ops\n");
