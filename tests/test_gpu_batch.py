@@ -249,6 +249,45 @@ def test_every_tunable_engine_shape_vs_oracle(dtype, tol):
                 assert err <= (1e-12 if dtype == "c128" else 1e-5), (tq, apt, err)
 
 
+def phase_run_circuit(n, rng):
+    """QFT-shaped circuit whose controlled phases each carry a parameter of
+    their own, with RZ and H between targets and a few doubly controlled
+    phases (three-qubit masks, applied as per-mask chains): the forward passes
+    multiply the phases on one target (and one lane bit besides) into a
+    factor per lane, the reverse passes differentiate each of them.  Returns
+    (ops, number of parameters)."""
+    ops, np_ = [], 0
+    for j in range(n - 1, -1, -1):
+        ops.append(W.Op("H", (), (j,)))
+        for c in range(j - 1, -1, -1):
+            ops.append(W.Op("PHASE", (c,), (j,), np_, float(rng.uniform(0, 2 * math.pi))))
+            np_ += 1
+        if j >= 2:
+            ops.append(W.Op("T", (j - 1, j - 2), (j,)))
+        ops.append(W.Op("RZ", (), (j,), np_, float(rng.uniform(0, 2 * math.pi))))
+        np_ += 1
+    return ops, np_
+
+
+@pytest.mark.parametrize("dtype,tol", [("c128", 1e-10), ("c64", 1e-4)])
+@pytest.mark.parametrize("tile", [4, 6, 0])
+def test_phase_run_gradients_vs_oracle(dtype, tol, tile):
+    rng = np.random.default_rng(5600 + tile)
+    n = 9
+    ops, npar = phase_run_circuit(n, rng)
+    th = rng.uniform(0, 2 * math.pi, size=npar)
+    ref = oracle.run_circuit(oracle.zero_state(n), ops, th)
+    b = sv.Batch([(n, ops, npar, "sum_zz")], dtype, tile_qubits=tile, with_grad=False)
+    b.run(th)
+    err = float(np.max(np.abs(b.state(0).astype(np.complex128) - ref)))
+    assert err <= 4 * TOL[dtype], err
+    b = sv.Batch([(n, ops, npar, "sum_zz")], dtype, tile_qubits=tile, with_grad=True)
+    e, g = b.run(th)
+    g_ref = oracle.param_shift_grad(n, ops, th, W.sum_zz(n))
+    assert abs(e[0] - oracle.expval_obs(ref, W.sum_zz(n))) <= tol * n
+    assert float(np.max(np.abs(g - g_ref))) <= tol
+
+
 def test_config3_circuits_at_20_qubits_vs_oracle():
     """HEA (10 layers) and QFT of a random basis state at 20 qubits on the
     fused engine: complex128 within 1e-12, complex64 within 1e-5 of the fp64
