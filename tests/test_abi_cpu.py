@@ -337,6 +337,21 @@ def test_batch_create_validation_is_host_side():
     assert lib.sv_batch_run(ctypes.c_void_p(0x1234), None, 0, None, None, 0) == HANDLE
 
 
+def test_batch_plan_far_controls_host_only():
+    # The universal circuit's CNOTs reach across the register: with their
+    # controls left outside the tile, each target needs one pass, and each
+    # run of CNOTs from qubits outside the tile with the rotations between
+    # them becomes one op per tile (a table of at most 32 products), so the
+    # 2080 gates leave far fewer fused ops than the per-gate count.
+    import workloads as W
+    n = 32
+    ops = W.universal_ops(n)
+    for tq in (10, 12):
+        p = sv.batch_plan([(n, ops, 0, "sum_z")], "c128", with_grad=False, tile_qubits=tq, amps_per_thread=16)
+        assert p["passes"] <= 12, (tq, p["passes"])
+        assert p["fused_ops"] < len(ops) // 3, (tq, p["fused_ops"])
+
+
 def test_batch_plan_fuses_gates_host_only():
     # The pass scheduler runs on the host: a 32-qubit, 10-layer hardware-efficient
     # ansatz (950 gates) needs far fewer state passes than gates, every pass
