@@ -53,7 +53,11 @@ constexpr int kMaxTileSelBits = 5;
 // the tile; 0: none), and the kernels test (tile & b) == b.  In forward lists
 // an FK_PHASE's kb = 1 chains it to the next op, a subset phase on the same
 // local mask whose phase the kernel multiplies in before applying the
-// group's product once (reverse sweeps ignore kb).
+// group's product once; kb = 2 makes it a member of a run on target a whose
+// next op is a member too, kb = 3 the run's last member: each member's
+// in-tile mask is a, or a and one lane bit, and the run's product (per lane:
+// a member with a lane bit counts on the lanes holding it) is applied once
+// to the amplitudes holding a (reverse sweeps ignore kb).
 struct FOp {
     int32_t kind;
     int32_t a, b;   // local target bits (b: second target of SWAP / QUAD, selector of FK_PAIRC, packed mask
