@@ -729,6 +729,52 @@ __device__ __forceinline__ double rgen_elem(const typename Vec2<T>::type* P, con
     return acc;
 }
 
+// Per-thread Im <lambda|M|phi> over this thread's register pairs on bit K
+// for a 2x2 complex M (row-major, interleaved; uniform).
+template <typename T, int RB, int K, bool CHK>
+__device__ __forceinline__ double rgen_m_k(const typename Vec2<T>::type* P, const typename Vec2<T>::type* L,
+                                           cptr<T> m, uint32_t cmk)
+{
+    const double m0r = m[0], m0i = m[1], m1r = m[2], m1i = m[3], m2r = m[4], m2i = m[5], m3r = m[6], m3i = m[7];
+    double acc = 0.0;
+#pragma unroll
+    for (int j = 0; j < (1 << RB); ++j) {
+        if (j & (1 << K)) continue;
+        if (CHK && skip_reg(j, cmk)) continue;
+        const int j1 = j | (1 << K);
+        const double a0r = P[j].x, a0i = P[j].y, a1r = P[j1].x, a1i = P[j1].y;
+        const double l0r = L[j].x, l0i = L[j].y, l1r = L[j1].x, l1i = L[j1].y;
+        // t = M phi on the pair
+        const double t0r = m0r * a0r - m0i * a0i + m1r * a1r - m1i * a1i;
+        const double t0i = m0r * a0i + m0i * a0r + m1r * a1i + m1i * a1r;
+        const double t1r = m2r * a0r - m2i * a0i + m3r * a1r - m3i * a1i;
+        const double t1i = m2r * a0i + m2i * a0r + m3r * a1i + m3i * a1r;
+        acc += l0r * t0i - l0i * t0r + l1r * t1i - l1i * t1r;
+    }
+    return acc;
+}
+
+// Im <lambda|M|phi> of a reverse pair's first gate (FK_RFUSE): M from the
+// coefficient table, the op's controls as for its generator.
+template <typename T, int RB>
+__device__ __forceinline__ double reg_gen_inner_m(const typename Vec2<T>::type* P, const typename Vec2<T>::type* L,
+                                                  const FOp& op, cptr<T> m, uint32_t tl)
+{
+    const uint32_t cmk = op.cmk & ~(1u << op.ka), cml = op.cml;
+    if ((tl & cml) != cml) return 0.0;
+    double r = 0.0;
+    if (cmk) {
+#define SV_CALL(K) r = rgen_m_k<T, RB, K, true>(P, L, m, cmk)
+        SV_K_SWITCH(op.ka, SV_CALL)
+#undef SV_CALL
+    } else {
+#define SV_CALL(K) r = rgen_m_k<T, RB, K, false>(P, L, m, 0u)
+        SV_K_SWITCH(op.ka, SV_CALL)
+#undef SV_CALL
+    }
+    return r;
+}
+
 template <typename T, int RB>
 __device__ __forceinline__ double reg_gen_inner(const typename Vec2<T>::type* P, const typename Vec2<T>::type* L,
                                                 const FOp& op, uint32_t tl)
@@ -769,11 +815,16 @@ __device__ __forceinline__ void flush_slots(const PassTables& tb, const FCirc& c
     int k = 0;
     for (int o = op_end - 1; o >= op_begin; --o) {
         const FOp op = ld_const(as_const(tb.ops) + o);
-        if (op.kind == FK_LAYOUT || op.slot < 0) continue;
-        double s = 0.0;
-        for (int w = 0; w < nwaves; ++w) s += wpart[k * nwaves + w];
-        tb.g_part[cc.g_part_begin + (int64_t)op.slot * cc.n_tiles + tile] = s;
-        ++k;
+        if (op.kind == FK_LAYOUT) continue;
+        // slots in the order the kernel filled them: the op's, then (FK_RFUSE) its first gate's
+        const int sl[2] = {op.slot, op.kind == FK_RFUSE ? op.b : -1};
+        for (int x = 0; x < 2; ++x) {
+            if (sl[x] < 0) continue;
+            double s = 0.0;
+            for (int w = 0; w < nwaves; ++w) s += wpart[k * nwaves + w];
+            tb.g_part[cc.g_part_begin + (int64_t)sl[x] * cc.n_tiles + tile] = s;
+            ++k;
+        }
     }
 }
 
@@ -1006,7 +1057,7 @@ __device__ __forceinline__ void item_reg_rev(const PassTables& tb, const FCirc& 
     OpPre nx;
     if (rop_begin < rop_end) op_fetch(tb, rop_end - 1, nx);
     for (int o = rop_end - 1; o >= rop_begin; --o) {
-        const OpPre p = nx;
+        OpPre p = nx;
         if (o - 1 >= rop_begin) op_fetch(tb, o - 1, nx);
         const FOp& op = p.op;
         if (op.kind == FK_LAYOUT) {
@@ -1032,6 +1083,15 @@ __device__ __forceinline__ void item_reg_rev(const PassTables& tb, const FCirc& 
             const double c = wave_sum(active && on ? reg_gen_inner<T, RB>(v, w, op, tl) : 0.0);
             if ((threadIdx.x & 63) == 0) wpart[nslot * (blockDim.x >> 6) + (threadIdx.x >> 6)] = c;
             ++nslot;
+        }
+        if (op.kind == FK_RFUSE) {
+            // the pair's first gate: its partial with B G_A B^dagger; then one un-apply of B A
+            if (op.b >= 0) {
+                const double c = wave_sum(active ? reg_gen_inner_m<T, RB>(v, w, op, coef + op.coef + 8, tl) : 0.0);
+                if ((threadIdx.x & 63) == 0) wpart[nslot * (blockDim.x >> 6) + (threadIdx.x >> 6)] = c;
+                ++nslot;
+            }
+            p.op.kind = FK_PAIR;
         }
         if (!on) continue;
         if (op.kind == FK_SWAP || op.kind == FK_QUAD) {
@@ -1282,6 +1342,23 @@ __device__ void gate2x2(const FCoefSpec& f, const double* __restrict__ params, d
     }
 }
 
+// r = a b for 2x2 complex matrices (row-major, interleaved); r may not alias.
+__device__ void mul2x2(const double* a, const double* b, double* r)
+{
+    for (int row = 0; row < 2; ++row)
+        for (int col = 0; col < 2; ++col) {
+            double re = 0, im = 0;
+            for (int t = 0; t < 2; ++t) {
+                const double ar = a[2 * (2 * row + t)], ai = a[2 * (2 * row + t) + 1];
+                const double br = b[2 * (2 * t + col)], bi = b[2 * (2 * t + col) + 1];
+                re += ar * br - ai * bi;
+                im += ar * bi + ai * br;
+            }
+            r[2 * (2 * row + col)] = re;
+            r[2 * (2 * row + col) + 1] = im;
+        }
+}
+
 // One thread per op: gate coefficients from the parameters, in double and
 // (if coef_f is set) rounded once to float for complex64 runs.
 __global__ void k_pass_coef(const FCoefSpec* __restrict__ spec, int n, const FCoefSpec* __restrict__ factors,
@@ -1292,7 +1369,30 @@ __global__ void k_pass_coef(const FCoefSpec* __restrict__ spec, int n, const FCo
     const FCoefSpec s = spec[i];
     double* c = coef + s.coef;
     int cnt;
-    if (s.nfactor > 0 && s.out_diag == 3) {
+    if (s.nfactor == 2 && s.out_diag == 4) {
+        // reverse pair A then B: the product B A, and B G_A B^dagger
+        double ua[8], ub[8];
+        gate2x2(factors[s.factor_begin], params, ua);
+        gate2x2(factors[s.factor_begin + 1], params, ub);
+        mul2x2(ub, ua, c);
+        if (s.branch > 0) {
+            double gm[8] = {0, 0, 0, 0, 0, 0, 0, 0}, t[8], ubd[8];
+            switch (s.branch - 1) {
+            case GEN_X: gm[2] = 1; gm[4] = 1; break;
+            case GEN_Y: gm[3] = -1; gm[5] = 1; break;
+            case GEN_Z: gm[0] = 1; gm[6] = -1; break;
+            default: gm[6] = 1; break;  // GEN_P1: the projector on |1>
+            }
+            // B^dagger: conjugate transpose
+            ubd[0] = ub[0]; ubd[1] = -ub[1]; ubd[2] = ub[4]; ubd[3] = -ub[5];
+            ubd[4] = ub[2]; ubd[5] = -ub[3]; ubd[6] = ub[6]; ubd[7] = -ub[7];
+            mul2x2(gm, ubd, t);
+            mul2x2(ub, t, c + 8);
+        } else {
+            for (int k = 8; k < 16; ++k) c[k] = 0.0;
+        }
+        cnt = 16;
+    } else if (s.nfactor > 0 && s.out_diag == 3) {
         // tile-selected product: entry e stands for the tiles whose bits under
         // the mask read e; a factor enters if those bits hold all of its own
         const uint32_t mask = (uint32_t)s.branch;

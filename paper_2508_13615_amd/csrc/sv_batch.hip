@@ -200,7 +200,8 @@ uint32_t op_need(const FOp& f)
     case FK_PAIRR:
     case FK_PAIRX:
     case FK_PAIRC:
-    case FK_PAIRT: return 1u << f.a;
+    case FK_PAIRT:
+    case FK_RFUSE: return 1u << f.a;
     case FK_SWAP: return (1u << f.a) | (1u << f.b);
     default: return 0u;
     }
@@ -622,6 +623,78 @@ hipError_t enqueue_run(sv_batch b)
     return e;
 }
 
+// Reverse-list fusion: a one-target gate B joins the earlier gate A on the
+// same target with the same in-tile controls (and none outside the tile)
+// when no op in between touches their qubits, so B may move back to A (ops
+// on disjoint qubits commute, and so do their gradient terms).  The pair
+// becomes one FK_RFUSE op: one un-apply of B A on phi and lambda, B's
+// gradient partial with its own generator and A's with B G_A B^dagger, both
+// taken before the un-apply.  Subset phases, gated and two-target ops stay
+// as they are.
+std::vector<FOp> fuse_reverse(const std::vector<FOp>& ops, const std::vector<int>& src, const std::vector<BOp>& bops,
+                              int param_base, std::vector<FCoefSpec>& cspec, std::vector<FCoefSpec>& cfac,
+                              int& coef_total)
+{
+    struct Grp {
+        int first, second;
+        bool fusable;
+    };
+    std::vector<Grp> g;
+    int last[32];
+    for (int& x : last) x = -1;
+    auto eligible = [](const FOp& f) {
+        return (f.kind == FK_PAIR || f.kind == FK_PAIRR || f.kind == FK_PAIRX || f.kind == FK_DIAG) && f.b == 0;
+    };
+    for (size_t i = 0; i < ops.size(); ++i) {
+        const FOp& f = ops[i];
+        uint32_t touch = f.cm | (1u << f.a);
+        if (f.kind == FK_SWAP || f.kind == FK_QUAD || f.kind == FK_PAIRC) touch |= 1u << f.b;
+        if (eligible(f)) {
+            const int c = last[f.a];
+            if (c >= 0 && g[c].fusable && g[c].second < 0 && ops[g[c].first].a == f.a && ops[g[c].first].cm == f.cm) {
+                bool later = false;
+                for (int q = 0; q < 32; ++q)
+                    if ((touch >> q) & 1u) later = later || last[q] != c;
+                if (!later) {
+                    g[c].second = (int)i;
+                    continue;
+                }
+            }
+        }
+        g.push_back({(int)i, -1, eligible(f)});
+        for (int q = 0; q < 32; ++q)
+            if ((touch >> q) & 1u) last[q] = (int)g.size() - 1;
+    }
+    std::vector<FOp> out;
+    for (const Grp& gr : g) {
+        if (gr.second < 0) {
+            out.push_back(ops[gr.first]);
+            continue;
+        }
+        const FOp& A = ops[gr.first];
+        const FOp& B = ops[gr.second];
+        FOp f = B;
+        f.kind = FK_RFUSE;
+        f.b = A.slot;
+        f.coef = coef_total;
+        FCoefSpec cs;
+        memset(&cs, 0, sizeof cs);
+        cs.gate = SV_I;
+        cs.pidx = -1;
+        cs.coef = coef_total;
+        cs.nfactor = 2;
+        cs.factor_begin = (int)cfac.size();
+        cs.out_diag = 4;
+        cs.branch = A.slot >= 0 ? 1 + A.gen : 0;
+        cfac.push_back(factor_of(bops[src[gr.first]], param_base));
+        cfac.push_back(factor_of(bops[src[gr.second]], param_base));
+        cspec.push_back(cs);
+        coef_total += 16;
+        out.push_back(f);
+    }
+    return out;
+}
+
 // Consecutive subset phases commute.  Within each maximal run of them in a
 // planned forward list (no layout change inside, so one local mask means one
 // register / lane split) the host groups them:
@@ -907,8 +980,11 @@ static sv_status compile_batch(const sv_batch_circuit* circuits, int n_circuits,
             fp.rop_end = fp.op_end;
             fp.rlay_begin = fp.lay_begin;
             fp.rlay_end = fp.lay_end;
-            if (with_grad && (fused || fc.reg != fc.rreg || (fc.rreg && rreg_bits != reg_bits))) {
-                std::vector<FOp> rev_ops = pass_ops;
+            std::vector<FOp> rev_ops;
+            if (with_grad && fc.rreg) rev_ops = fuse_reverse(pass_ops, pass_src, ops, n_params, cspec, cfac, coef_total);
+            const bool rfused = with_grad && fc.rreg && rev_ops.size() != pass_ops.size();
+            if (with_grad && (fused || rfused || fc.reg != fc.rreg || (fc.rreg && rreg_bits != reg_bits))) {
+                if (!rfused) rev_ops = pass_ops;
                 if (fc.rreg) plan_layouts(rev_ops, tq, rreg_bits, cb, fp.q, lays, fp.rlay_begin, fp.rlay_end);
                 fp.rop_begin = (int)fops.size();
                 fops.insert(fops.end(), rev_ops.begin(), rev_ops.end());

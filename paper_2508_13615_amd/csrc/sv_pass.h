@@ -30,9 +30,15 @@ constexpr int kSwzBits = 4;
 // controls all lie outside the tile, where each gate acts on the tiles holding
 // its controls.  Its coefficients are 2^popcount(b) matrices of 8 doubles,
 // entry e for the tiles whose bits under b, gathered in order, read e.
+// FK_RFUSE (reverse lists only): two one-target gates A then B on one target
+// with the same controls, un-applied as one complex 2x2 (coefficients: the
+// product B A, then M = B G_A B^dagger for A's generator G_A); slot and gen
+// are B's, b is A's slot (-1: none): the kernel takes B's gradient partial
+// with B's generator and A's with M, both before the un-apply, which is the
+// same as taking A's after un-applying B.
 enum FusedKind : int32_t {
     FK_PAIR = 0, FK_DIAG = 1, FK_PHASE = 2, FK_SWAP = 3, FK_QUAD = 4, FK_LAYOUT = 5, FK_PAIRR = 6, FK_PAIRX = 7,
-    FK_PAIRC = 8, FK_PAIRT = 9
+    FK_PAIRC = 8, FK_PAIRT = 9, FK_RFUSE = 10
 };
 // Largest packed mask of an FK_PAIRT (bits), so its table holds at most 32
 // matrices.
@@ -140,7 +146,9 @@ struct FSeg {
 // or both as its `branch` says (1, 2, 3); 3 writes 2^popcount(branch)
 // products (FK_PAIRT: the spec's branch is the op's packed mask), product e
 // taking the factors whose own packed mask (their `branch`) lies within the
-// bits that e selects; 0 writes all 8 values.
+// bits that e selects; 4 (FK_RFUSE, two factors A then B) writes B A and,
+// if the spec's branch is 1 + A's generator kind, B G_A B^dagger (16 values);
+// 0 writes all 8 values.
 struct FCoefSpec {
     int32_t gate;
     int32_t pidx;    // global parameter index, -1 = fixed angle `value`

@@ -122,8 +122,42 @@ static void gate2x2_h(const FCoefSpec& f, const double* params, cd u[4])
     }
 }
 
+static long rfuse_ops = 0;  // reverse pairs replayed, per tile
+
 static void coef_eval(const FCoefSpec& s, const std::vector<FCoefSpec>& fac, const double* params, double* c)
 {
+    if (s.out_diag == 4) {
+        // reverse pair A then B: B A, then B G B^dagger for A's generator G
+        CHECK(s.nfactor == 2, "reverse pair with %d factors", s.nfactor);
+        cd a[4], b[4];
+        gate2x2_h(fac[s.factor_begin], params, a);
+        gate2x2_h(fac[s.factor_begin + 1], params, b);
+        auto mul = [](const cd* x, const cd* y, cd* r) {
+            r[0] = x[0] * y[0] + x[1] * y[2];
+            r[1] = x[0] * y[1] + x[1] * y[3];
+            r[2] = x[2] * y[0] + x[3] * y[2];
+            r[3] = x[2] * y[1] + x[3] * y[3];
+        };
+        cd ba[4];
+        mul(b, a, ba);
+        for (int q = 0; q < 4; ++q) { c[2 * q] = ba[q].real(); c[2 * q + 1] = ba[q].imag(); }
+        for (int q = 8; q < 16; ++q) c[q] = 0;
+        if (s.branch > 0) {
+            cd g[4] = {0, 0, 0, 0};
+            switch (s.branch - 1) {
+            case GEN_X: g[1] = 1; g[2] = 1; break;
+            case GEN_Y: g[1] = cd(0, -1); g[2] = cd(0, 1); break;
+            case GEN_Z: g[0] = 1; g[3] = -1; break;
+            default: g[3] = 1; break;
+            }
+            const cd bd[4] = {std::conj(b[0]), std::conj(b[2]), std::conj(b[1]), std::conj(b[3])};
+            cd t[4], m[4];
+            mul(g, bd, t);
+            mul(b, t, m);
+            for (int q = 0; q < 4; ++q) { c[8 + 2 * q] = m[q].real(); c[8 + 2 * q + 1] = m[q].imag(); }
+        }
+        return;
+    }
     if (s.nfactor > 0 && s.out_diag == 3) {
         // one product per subset of the op's out-of-tile bits: the list of the
         // mask's set bits, entry e taking bit list[k] when bit k of e is set
@@ -664,6 +698,36 @@ static void run_emu(Emu& E, const std::vector<double>& params)
                                 acc += gen_inner_h(&v[t * R], &w[t * R], rb, op, f.tl[t], f.off, H.lays[cur], tq);
                         E.gpart[cc.g_part_begin + (int64_t)op.slot * cc.n_tiles + tile] = acc;
                     }
+                    if (op.kind == FK_RFUSE) {
+                        // first gate's partial: Im <lambda| M |phi> with M = B G_A B^dagger, over the controlled pairs
+                        const int nl = tq - rb;
+                        CHECK(op.ka >= 0 && H.lays[cur].pos[nl + op.ka] == op.a, "reverse pair target not in registers");
+                        const double* mc = E.coef.data() + op.coef + 8;
+                        const cd M[4] = {cd(mc[0], mc[1]), cd(mc[2], mc[3]), cd(mc[4], mc[5]), cd(mc[6], mc[7])};
+                        if (op.b >= 0) {
+                            double acc = 0;
+                            const uint32_t cm = op.cm & ~(1u << op.a);
+                            for (int t = 0; t < nthr; ++t)
+                                for (int j = 0; j < R; ++j) {
+                                    if (j & (1 << op.ka)) continue;
+                                    if (((f.tl[t] | f.off[j]) & cm) != cm) continue;
+                                    const int j1 = j | (1 << op.ka);
+                                    const cd p0 = v[t * R + j], p1 = v[t * R + j1];
+                                    const cd t0 = M[0] * p0 + M[1] * p1, t1 = M[2] * p0 + M[3] * p1;
+                                    acc += (std::conj(w[t * R + j]) * t0 + std::conj(w[t * R + j1]) * t1).imag();
+                                }
+                            E.gpart[cc.g_part_begin + (int64_t)op.b * cc.n_tiles + tile] = acc;
+                        }
+                        FOp q2 = op;
+                        q2.kind = FK_PAIR;
+                        q2.b = 0;
+                        ++rfuse_ops;
+                        for (int t = 0; t < nthr; ++t) {
+                            reg_apply_h(&v[t * R], rb, q2, E.coef.data() + op.coef, true, f.tl[t], f.off, H.lays[cur], tq);
+                            reg_apply_h(&w[t * R], rb, q2, E.coef.data() + op.coef, true, f.tl[t], f.off, H.lays[cur], tq);
+                        }
+                        continue;
+                    }
                     if (!on) continue;
                     if (op.kind == FK_QUAD || op.kind == FK_SWAP) {
                         quad_sweep_h(v, nthr, R, f, tq, op, E.coef.data() + op.coef, true);
@@ -977,6 +1041,11 @@ int main(int argc, char** argv)
     printf("one-target ops with controls outside the tile replayed: %ld (tile x op)\n", gated_ops);
     printf("tile-selected ops replayed: %ld (tile x op)\n", tsel_ops);
     printf("subset phases replayed in per-target runs: %ld (tile x op)\n", run_members);
+    printf("reverse pairs replayed: %ld (tile x op)\n", rfuse_ops);
+    if (!rfuse_ops) {
+        ++errors;
+        printf("FAIL: the circuits do not exercise reverse pairs\n");
+    }
     if (!run_members) {
         ++errors;
         printf("FAIL: the circuits do not exercise phase runs\n");
