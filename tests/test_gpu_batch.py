@@ -288,6 +288,40 @@ def test_phase_run_gradients_vs_oracle(dtype, tol, tile):
     assert float(np.max(np.abs(g - g_ref))) <= tol
 
 
+def rotation_pairs_circuit(n, rng, reps):
+    """Pairs of parameterised rotations on one target with the same controls
+    (none, one or two), the reverse passes' fusable form, between H layers and
+    CNOTs; every rotation has a parameter of its own.  Returns (ops, number of
+    parameters)."""
+    ops = [W.Op("H", (), (q,)) for q in range(n)]
+    np_ = 0
+    for _ in range(reps):
+        qs = [int(q) for q in rng.permutation(n)]
+        t, ctl = qs[0], tuple(qs[1:1 + int(rng.integers(0, 3))])
+        g1, g2 = (str(x) for x in rng.choice(["RX", "RY", "RZ"], size=2))
+        ops.append(W.Op(g1, ctl, (t,), np_, 0.0))
+        ops.append(W.Op(g2, ctl, (t,), np_ + 1, 0.0))
+        np_ += 2
+        ops.append(W.Op("X", (qs[-1],), (qs[-2],)))
+    return ops, np_
+
+
+@pytest.mark.parametrize("dtype,tol", [("c128", 1e-7), ("c64", 1e-4)])
+@pytest.mark.parametrize("tile", [4, 6, 0])
+def test_reverse_pair_gradients_vs_oracle(dtype, tol, tile):
+    # controlled rotations: central differences (the two-term shift rule does not hold for them)
+    rng = np.random.default_rng(5700 + tile)
+    n = 8
+    ops, npar = rotation_pairs_circuit(n, rng, 14)
+    th = rng.uniform(0, 2 * math.pi, size=npar)
+    b = sv.Batch([(n, ops, npar, "sum_zz")], dtype, tile_qubits=tile, with_grad=True)
+    e, g = b.run(th)
+    g_ref = oracle.fd_grad(n, ops, th, W.sum_zz(n), h=1e-6)
+    e_tol = (1e-10 if dtype == "c128" else 1e-4) * n
+    assert abs(e[0] - oracle.energy(n, ops, th, W.sum_zz(n))) <= e_tol
+    assert float(np.max(np.abs(g - g_ref))) <= tol
+
+
 def test_config3_circuits_at_20_qubits_vs_oracle():
     """HEA (10 layers) and QFT of a random basis state at 20 qubits on the
     fused engine: complex128 within 1e-12, complex64 within 1e-5 of the fp64
